@@ -337,10 +337,12 @@ int orc_banded(const uint8_t *text, uint64_t L, const uint8_t *x, uint32_t n, in
             cur[b] = v;
             if (v < rowmin) rowmin = v;
         }
-        /* every path from row 0 to row n crosses row i and costs never
-         * decrease along a path: once the whole row exceeds k, so does every
-         * cell of the last row (Ukkonen's cut-off) */
-        if (rowmin > k) return 0;
+        /* costs never decrease along a path, and a path into the last row
+         * either crosses row i or starts at a boundary cell E[i'][0] = i'
+         * with i' > i.  Once i >= k those boundary cells already exceed k,
+         * so a whole row above k ends the band (Ukkonen's cut-off); before
+         * that, a band lying left of column 0 may still meet column 0. */
+        if (rowmin > k && (int)i >= k) return 0;
         memcpy(prev, cur, sizeof(int) * W);
     }
     int m = 0;

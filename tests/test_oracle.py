@@ -308,3 +308,42 @@ def test_best_stratum_is_min_error_subset():
     assert set(as_tuples(best)) <= s_all
     for rid in np.unique(allh["read_id"]):
         assert best["errors"][best["read_id"] == rid].max() == allh["errors"][allh["read_id"] == rid].min()
+
+
+def band_brute(text: bytes, x: bytes, d: int, k: int):
+    """The band-restricted recurrence written out over the whole matrix:
+    cells off the diagonals [d-k, d+k] or outside columns [0, L] do not exist,
+    E[0][j] = 0, E[i][0] = i (no early termination)."""
+    INF = 10 ** 9
+    L, n = len(text), len(x)
+    E = [[INF] * (L + 1) for _ in range(n + 1)]
+    for j in range(L + 1):
+        if d - k <= j <= d + k:
+            E[0][j] = 0
+    for i in range(1, n + 1):
+        for j in range(L + 1):
+            if not (d - k <= j - i <= d + k):
+                continue
+            if j == 0:
+                E[i][j] = i
+                continue
+            v = E[i - 1][j - 1] + (x[i - 1] != text[j - 1])
+            v = min(v, E[i - 1][j] + 1, E[i][j - 1] + 1)
+            E[i][j] = v
+    return sorted((j - 1, E[n][j]) for j in range(1, L + 1) if E[n][j] <= k)
+
+
+def test_banded_equals_brute_band_including_overhangs():
+    """Bands that start entirely left of column 0 (d < -k) meet the boundary
+    column E[i][0] = i only at a later row."""
+    rng = np.random.default_rng(77)
+    for trial in range(300):
+        L = int(rng.integers(10, 60))
+        text = rand_dna(rng, L)
+        n = int(rng.integers(3, 25))
+        k = int(rng.integers(0, 9))
+        x = rand_dna(rng, n) if rng.random() < 0.5 else \
+            (rand_dna(rng, int(rng.integers(0, 6))) + text[:n])[:n]
+        d = int(rng.integers(-n - k, L + 2))
+        got = oracle.banded(oracle.encode(text), oracle.encode(x), d, k)
+        assert sorted(got) == band_brute(text, x, d, k), (text, x, d, k)

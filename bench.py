@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the mapping hot path on one MI355X.
+
+A step maps one batch of reads that is already resident in HBM: ASCII reads
+are packed to two bits, the q-group index is built over them
+(Algorithm 1), both strands of the resident reference are filtered through
+it (Algorithm 2), candidates are verified with the banded bit-parallel edit
+distance, and the sorted hit list is written to a device buffer.  The
+reference is loaded once, outside the timed region.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel, CPU
+oracle baseline).  Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# 32-bit integer operations of one band row of the verification recurrence:
+# match word (4), bit-vector step (13), band shift (3), right-edge value (2)
+OPS_PER_ROW = 22
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_BPS = 8.0e12
+
+WORKLOADS = {
+    "repeat": "100 Mbp reference with 5% segmental copies and 0.5% homopolymer runs, "
+              "1 M reads x 100 bp at 4% error, both strands, q=12, k=5",
+    "tiny": "1 Mbp i.i.d. reference, 10,000 reads x 100 bp at 2% error, q=10, k=5",
+    "mixed": "100 Mbp repeat reference, 2 M reads of 50-250 bp at 3% error, k=ceil(5% n), q=12",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="repeat", choices=sorted(WORKLOADS))
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--mode", default="all", choices=["all", "best"])
+    ap.add_argument("--w", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+            "(the path shards by reads with no exchange, see DESIGN.md)")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1403_1706_amd import peanut as pn
+    from paper_1403_1706_amd import synth
+
+    t0 = time.time()
+    w = synth.make(args.workload, scale=args.scale)
+    log(f"workload {args.workload}: L={len(w.ref)} reads={w.n_reads} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    uniform_k = len(set(w.k_per_read.tolist())) == 1
+    d_k = None if uniform_k else torch.from_numpy(w.k_per_read.copy()).to(dev)
+    k = int(w.k_per_read[0]) if uniform_k else -1
+    mode = pn.PN_ALL_HITS if args.mode == "all" else pn.PN_BEST_STRATUM
+    torch.cuda.synchronize()
+
+    ctx = pn.pn_ctx_create(0)
+    ref = pn.pn_ref_load(ctx, w.ref)
+    out = torch.empty(12 * max(1 << 20, 64 * w.n_reads), dtype=torch.uint8, device=dev)
+    pn.pn_ctx_set_timing(ctx, True)
+    n_hits = 0
+
+    def step():
+        nonlocal n_hits
+        idx = pn.pn_index_build_dev(ctx, d_reads, d_offs, w.q, args.w)
+        try:
+            n_hits = pn.pn_map_dev(ctx, ref, idx, k, out, mode, d_k=d_k)
+        finally:
+            pn.pn_index_free(idx)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    pn.pn_ctx_get_stats(ctx, reset=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    st = pn.pn_ctx_get_stats(ctx)
+    ms_per_step = (t_end - t_start) * 1000.0 / args.steps
+    reads_per_s = w.n_reads / (ms_per_step / 1000.0)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:.3e} reads/s, hits {n_hits}")
+
+    hits = np.frombuffer(out[:12 * n_hits].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
+    mapped = len(np.unique(hits["read_id"])) / max(1, w.n_reads)
+
+    K = args.steps
+    stage_ms = {s: st["ms"][s] / K for s in pn.STAGES}
+    launches = {s: st["launches"][s] / K for s in pn.STAGES}
+    dominant = max(stage_ms, key=stage_ms.get)
+    n_pos = max(0, len(w.ref) - w.q + 1)
+    probe_bytes = 2 * (args.w / 8 + 4 + 8) + 0.25  # per forward position, both strands
+    if dominant == "verify":
+        work = st["verify_rows"] / K * OPS_PER_ROW
+        per_launch_ms = stage_ms["verify"] / max(1.0, launches["verify"])
+        achieved = work / max(1.0, launches["verify"]) / (per_launch_ms / 1000.0)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                "kernel": "k_verify", "avg_launch_ms": per_launch_ms}
+    else:
+        if dominant in ("filter_count", "filter_emit"):
+            nbytes = n_pos * probe_bytes
+            if dominant == "filter_emit":
+                nbytes += st["n_candidates"] / K * 12
+        elif dominant == "index":
+            T = int(np.maximum(w.lengths - w.q + 1, 0).sum())
+            nbytes = len(w.reads) / 4 + 4 ** w.q / 8 + 4 * (4 ** w.q / args.w) + 4 * min(4 ** w.q, T) + 4 * T
+        else:
+            nbytes = st["n_records"] / K * 16 * 8
+        per_launch_ms = stage_ms[dominant] / max(1.0, launches[dominant])
+        achieved = nbytes / max(1.0, launches[dominant]) / (per_launch_ms / 1000.0)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BPS / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_BPS, "traffic": None,
+                "kernel": dominant, "avg_launch_ms": per_launch_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(2024)
+        m = min(args.cpu_sample, w.n_reads)
+        sample = np.sort(rng.choice(w.n_reads, m, replace=False))
+        sub = w.subset(sample)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"cpu baseline: oracle on {m} reads with {threads} threads")
+        c0 = time.perf_counter()
+        oracle.map_filtered(sub.ref, sub.reads, sub.offsets, w.q, sub.k_per_read,
+                            best=(mode == pn.PN_BEST_STRATUM), nthreads=threads)
+        c1 = time.perf_counter()
+        cpu = {"value": m / (c1 - c0), "unit": "reads/s", "cores": threads, "kind": "oracle",
+               "sample": f"{m} of {w.n_reads} reads (seeded), whole reference, both strands",
+               "seconds": c1 - c0}
+        log(f"cpu baseline: {cpu['value']:.1f} reads/s")
+
+    pn.pn_ref_free(ref)
+    pn.pn_ctx_destroy(ctx)
+
+    line = {
+        "metric": "mapped reads/sec (all hits <=k errors) on 1 MI355X; p50/p99 request latency",
+        "value": reads_per_s,
+        "unit": "reads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload] + (f" (scale {args.scale})" if args.scale != 1 else ""),
+                   "mode": args.mode, "q": w.q, "w": args.w, "n_reads": w.n_reads,
+                   "ref_len": len(w.ref)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms": None,
+        "hits": n_hits,
+        "mapped_fraction": mapped,
+        "stage_ms": stage_ms,
+        "counters_per_step": {c: st[c] / K for c in ("n_seeds", "n_candidates", "verify_rows",
+                                                        "n_records", "n_hits")},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * peanut.h — C ABI of the MI355X (gfx950) read-mapping hot path after
+ * PEANUT (Koester & Rahmann, "Massively parallel read mapping on GPUs with
+ * PEANUT", arXiv 1403.1706).
+ *
+ * The library maps a batch of DNA reads against a reference and both of its
+ * strands.  It builds a q-group index over the reads on the device
+ * (Section 2.2, Algorithm 1), streams every reference q-gram through it to
+ * produce (read, diagonal) candidates (Section 3.2, Algorithm 2) and
+ * verifies each candidate with a banded bit-parallel semiglobal edit
+ * distance (Section 3.3).  It reports every hit with at most k errors, or
+ * only the best stratum (Section 3.4), as (read_id, strand, end_pos, errors).
+ *
+ * The result is defined without reference to the filter.  For read x of
+ * length n and text T (strand 0: the reference R; strand 1: its reverse
+ * complement, T[i] = complement(R[L-1-i])), let E be the semiglobal edit
+ * matrix with unit costs: E[0][j] = 0, E[i][0] = i,
+ * E[i][j] = min(E[i-1][j-1] + [x[i-1] != T[j-1]], E[i-1][j] + 1, E[i][j-1] + 1)
+ * (Section 3.3: E_ij is the smallest edit distance between the read prefix of
+ * length i and any substring of the reference ending at j).  A hit is
+ * (r, s, e = j-1, E[n][j]) with E[n][j] <= k_r.  In best-stratum mode only
+ * hits whose error count equals the read's minimum over both strands are
+ * kept.  The filter loses nothing when every read satisfies
+ * (k_r + 1) * q <= n_r (q-gram lemma, Section 2.2); calls check this.
+ *
+ * Conventions
+ *  - Every call returns a status (PN_OK = 0 or a negative PN_E* code).  On
+ *    error, out-parameters are left untouched and nothing leaks.  The
+ *    library never aborts and never prints.
+ *  - Input host pointers are borrowed for the duration of the call.  Handles
+ *    are owned by the caller and released with the matching _free/_destroy;
+ *    passing NULL to those is a no-op.  Host hit arrays returned by the
+ *    library are released with pn_hits_free.
+ *  - Device ("_dev") variants take device pointers and a hipStream_t passed
+ *    as void*; all device work of such a call is ordered on that stream.
+ *    The caller keeps device inputs alive until the call returns.
+ *  - A handle is not thread-safe; distinct contexts are.
+ *  - Sequences are ASCII A, C, G, T in either case; anything else is
+ *    PN_EALPHABET.  Base codes are A=0, C=1, G=2, T=3 (Section 2.2).
+ *  - Limits: reference length L < 2^32 - 2^16; reads per index < 2^21;
+ *    read length <= 256; 1 <= q <= 15; w in {32, 64}; 0 <= k_r <= 15.
+ */
+#ifndef PEANUT_H
+#define PEANUT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PN_OK 0
+#define PN_EINVAL (-1)     /* bad argument or limit exceeded */
+#define PN_EALPHABET (-2)  /* a letter other than A/C/G/T */
+#define PN_ENOMEM (-3)     /* device or host allocation failed */
+#define PN_EDEVICE (-4)    /* HIP runtime error or no device */
+#define PN_ELEMMA (-5)     /* some read has (k_r + 1) * q > n_r */
+#define PN_ETRUNC (-6)     /* output capacity too small; required count returned */
+#define PN_EBUDGET (-7)    /* request does not fit the memory budget */
+
+typedef struct pn_ctx pn_ctx;
+typedef struct pn_ref pn_ref;
+typedef struct pn_index pn_index;
+
+typedef enum { PN_ALL_HITS = 0, PN_BEST_STRATUM = 1 } pn_mode;
+
+/* One reported hit, 12 bytes.  read_id: 0-based position of the read in the
+ * batch.  strand: 0 = reference, 1 = reverse complement.  end_pos: 0-based
+ * last aligned text position in that strand's own coordinates (a strand-1
+ * end e corresponds to forward position L-1-e, where the reverse-complemented
+ * read starts).  errors: the exact edit distance E[n][end_pos+1]. */
+typedef struct {
+    uint32_t read_id;
+    uint32_t end_pos;
+    uint8_t strand;
+    uint8_t errors;
+    uint16_t reserved;
+} pn_hit;
+
+/* A filtration hit (Algorithm 2): read, strand and hit diagonal
+ * d = p - o, the text position where the read would start if the q-gram at
+ * read offset o matched text position p without indels. */
+typedef struct {
+    uint32_t read_id;
+    uint8_t strand;
+    uint8_t reserved[3];
+    int64_t diagonal;
+} pn_candidate;
+
+/* Sizes of a built q-group index (Section 2.2): |I| = n_groups words of w
+ * bits, S has n_groups + 1 entries, S' has n_distinct + 1 entries (D = the
+ * number of distinct q-grams present), O has n_qgrams = |T| entries. */
+typedef struct {
+    uint64_t n_reads;
+    uint64_t n_bases;
+    uint64_t n_qgrams;
+    uint64_t n_distinct;
+    uint64_t n_groups;
+    int32_t q;
+    int32_t w;
+    int32_t max_len;
+    int32_t reserved;
+} pn_index_info;
+
+/* Human-readable name of a status code; never NULL. */
+const char *pn_strerror(int status);
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Bind HIP device `device`, create the context's stream (default priority)
+ * and its workspace pool.  PN_EDEVICE if the device does not exist. */
+int pn_ctx_create(int device, pn_ctx **out);
+void pn_ctx_destroy(pn_ctx *ctx);
+/* The context's own hipStream_t (as void*), used by the host-pointer calls. */
+int pn_ctx_stream(pn_ctx *ctx, void **stream);
+
+/* Stage timing and work counters of a context.  While timing is enabled,
+ * every stage of the path is bracketed by hipEvents on the stream it runs on
+ * and its device time is accumulated (ms) with its kernel-launch count.
+ * Counters accumulate always: occurrence pairs seen by filtration (n_seeds),
+ * candidates verified, band rows computed by verification, records emitted
+ * and hits reported.  pn_ctx_get_stats copies them out and optionally
+ * resets them. */
+enum {
+    PN_STAGE_INGEST = 0,       /* ASCII -> 2-bit codes, read metadata, read planes */
+    PN_STAGE_INDEX = 1,        /* Algorithm 1 */
+    PN_STAGE_FILTER_COUNT = 2, /* Algorithm 2, counting pass */
+    PN_STAGE_FILTER_EMIT = 3,  /* Algorithm 2, emitting pass */
+    PN_STAGE_VERIFY = 4,       /* banded bit-parallel validation */
+    PN_STAGE_SORT = 5,         /* radix sort of hit records */
+    PN_STAGE_FINISH = 6,       /* duplicate removal, strata, output */
+    PN_N_STAGES = 8
+};
+typedef struct {
+    double ms[PN_N_STAGES];
+    uint64_t launches[PN_N_STAGES];
+    uint64_t n_seeds;
+    uint64_t n_candidates;
+    uint64_t verify_rows;
+    uint64_t n_records;
+    uint64_t n_hits;
+} pn_stats;
+int pn_ctx_set_timing(pn_ctx *ctx, int enable);
+int pn_ctx_get_stats(pn_ctx *ctx, pn_stats *out, int reset);
+
+/* ---- reference (resident in HBM) -------------------------------------- */
+
+/* Pack an ASCII reference of `len` letters to two bits per base on the
+ * device and derive both strands' verification bit planes (Section 3.2: the
+ * reference and its reverse complement are scanned; strand 1's q-grams are
+ * computed from strand 0's packed words, only its bit planes are stored).
+ * `seq` is host memory (pn_ref_load) or device memory (pn_ref_load_dev). */
+int pn_ref_load(pn_ctx *ctx, const char *seq, uint64_t len, pn_ref **out);
+int pn_ref_load_dev(pn_ctx *ctx, const char *d_seq, uint64_t len, void *stream, pn_ref **out);
+void pn_ref_free(pn_ref *ref);
+uint64_t pn_ref_length(const pn_ref *ref);
+
+/* ---- q-group index over a read batch (Algorithm 1) --------------------- */
+
+/* Build the q-group index (I, S, S', O) of all q-grams of the reads
+ * (Section 2.2 and Algorithm 1: presence bitmap I, S = exclusive prefix sum
+ * of popcount(I[i]), S' = exclusive prefix sum of per-q-gram counts, O =
+ * occurrence positions in q-gram order).  Read r is
+ * reads[offsets[r] .. offsets[r+1]); a read shorter than q contributes no
+ * q-gram.  The index keeps its own copy of everything it needs.
+ * The _dev variant takes device `d_reads`/`d_offsets` (offsets u64[n+1],
+ * n_bases = offsets[n]) and orders its work on `stream`; it synchronises
+ * once to validate the batch. */
+int pn_index_build(pn_ctx *ctx, const char *reads, const uint64_t *offsets, uint32_t n_reads,
+                   int q, int w, pn_index **out);
+int pn_index_build_dev(pn_ctx *ctx, const char *d_reads, const uint64_t *d_offsets,
+                       uint32_t n_reads, uint64_t n_bases, int q, int w, void *stream,
+                       pn_index **out);
+void pn_index_free(pn_index *idx);
+int pn_index_get_info(const pn_index *idx, pn_index_info *out);
+
+/* Copy the index arrays to host buffers sized from pn_index_get_info:
+ * I: n_groups words of w bits (uint32 for w = 32, uint64 for w = 64);
+ * S: n_groups + 1 uint32; S': n_distinct + 1 uint32; O: n_qgrams uint32.
+ * An O entry packs a position as (cls << 29) | (read << 8) | offset, where
+ * cls is the base code of the letter before the q-gram in its read (4 when
+ * offset == 0).  Inside each q-gram's slice of O entries are ascending.
+ * Any pointer may be NULL to skip that array. */
+int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint32_t *O);
+
+/* ---- mapping ----------------------------------------------------------- */
+
+/* Map the indexed reads against both strands of `ref`.  k >= 0 applies to
+ * every read; k < 0 takes k_per_read[r] (host array for pn_map, device
+ * array for pn_map_dev).  Hits are sorted by (read_id, strand, end_pos).
+ * PN_ELEMMA if some read has (k_r + 1) * q > n_r; PN_EINVAL if k_r > 15.
+ * pn_map returns a library-allocated host array (free with pn_hits_free).
+ * pn_map_dev writes at most `capacity` hits to device `d_hits`, stores the
+ * total in *n_hits (host) and returns PN_ETRUNC if it exceeded capacity. */
+int pn_map(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, int k,
+           const uint8_t *k_per_read, pn_mode mode, pn_hit **hits, uint64_t *n_hits);
+int pn_map_dev(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, int k,
+               const uint8_t *d_k_per_read, pn_mode mode, pn_hit *d_hits, uint64_t capacity,
+               uint64_t *n_hits, void *stream);
+void pn_hits_free(pn_hit *hits);
+
+/* ---- the two steps on their own (for inspection) ----------------------- */
+
+/* Filtration only (Algorithm 2, both strands).  Returns the candidates the
+ * mapper verifies: for every reference q-gram occurrence pair (p, o) whose
+ * left neighbours differ (or p == 0 or o == 0) — an exact match that
+ * extends to the left yields the same diagonal from position p-1 — one
+ * (read, strand, d = p - o), sorted by (read, strand, diagonal), duplicates
+ * kept.  *n_seeds receives the number of occurrence pairs before that
+ * pruning (sum over positions of k_end - k_start).  Free with pn_hits_free. */
+int pn_filter(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, pn_candidate **cands,
+              uint64_t *n_cands, uint64_t *n_seeds);
+
+/* Validation only (Section 3.3): banded bit-parallel edit distance over
+ * diagonals [d - k_r, d + k_r] for each given candidate; returns every
+ * (read, strand, end, value) with value <= k_r, one record per candidate
+ * and end (duplicates across candidates kept), sorted.  Free with
+ * pn_hits_free. */
+int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_candidate *cands,
+                uint64_t n_cands, int k, const uint8_t *k_per_read, pn_hit **records,
+                uint64_t *n_records);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEANUT_H */

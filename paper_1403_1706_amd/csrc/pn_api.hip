@@ -1,0 +1,911 @@
+// Host runtime of libpeanut: the C ABI of include/peanut.h, a per-context
+// caching device allocator, and the ordering of the kernels of the mapping
+// path on one stream.  No call aborts or prints; HIP failures become status
+// codes.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/peanut.h"
+#include "pn_internal.h"
+
+// ---------------------------------------------------------------------------
+// context, allocator, workspace
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+enum MiscSlot {  // 64-bit words of the context's device scratch block
+    kStatus = 0,
+    kStatMaxLen = 1,
+    kStatT = 2,
+    kStatBad = 3,
+    kSeeds = 4,
+    kRecCount = 5,
+    kOutCount = 6,
+    kBigCount = 7,
+    kVerifyRows = 8,
+    kMiscWords = 10
+};
+
+struct PendingStage {
+    int stage;
+    hipEvent_t a, b;
+    int launches;
+};
+
+}  // namespace
+
+struct pn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::multimap<size_t, void *> cache;  // free device blocks by size
+    std::map<void *, size_t> live;        // allocated device blocks
+    uint64_t *misc = nullptr;             // device scratch words (MiscSlot)
+    uint64_t *hmisc = nullptr;            // pinned host mirror
+    // grow-only workspace of the mapping path
+    Buf cands, keys, keys_tmp, sort_temp, flags, pos, partials, minv, block_counts,
+        block_offsets, out_hits;
+    uint64_t cand_chunk = 1ull << 27;  // candidates verified per launch (at most)
+    // stage timing and counters
+    bool timing = false;
+    pn_stats stats{};
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<PendingStage> pending;
+};
+
+struct pn_ref {
+    pn_ctx *ctx;
+    uint64_t L;
+    uint32_t *packed_base;  // one front word, then the text, then 4 words
+    uint4 *planes0, *planes1;
+    uint64_t n_blocks;
+};
+
+struct pn_index {
+    pn_ctx *ctx;
+    uint32_t n_reads;
+    uint64_t n_bases, n_qgrams, n_distinct, n_groups, n_slots;
+    int q, w, max_len;
+    uint32_t *packed;
+    uint64_t *offsets;
+    uint2 *rplanes;
+    void *I;
+    uint32_t *S, *Sp, *O;
+};
+
+namespace {
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return PN_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return PN_ENOMEM;
+    return PN_EDEVICE;
+}
+
+#define PN_TRY(expr)                          \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) return map_err(e_); \
+    } while (0)
+
+#define PN_CHECK(st)                  \
+    do {                              \
+        int s_ = (st);                \
+        if (s_ != PN_OK) return s_;   \
+    } while (0)
+
+size_t round_size(size_t n) {
+    if (n < 256) return 256;
+    if (n < (1u << 20)) return (n + 255) & ~(size_t)255;
+    return (n + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
+}
+
+int dalloc(pn_ctx *c, size_t bytes, void **out) {
+    size_t n = round_size(bytes);
+    auto it = c->cache.lower_bound(n);
+    if (it != c->cache.end() && it->first <= 2 * n) {
+        void *p = it->second;
+        c->live[p] = it->first;
+        c->cache.erase(it);
+        *out = p;
+        return PN_OK;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached blocks back to the driver and try once more
+        PN_TRY(hipStreamSynchronize(c->stream));
+        for (auto &kv : c->cache) (void)hipFree(kv.second);
+        c->cache.clear();
+        e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return PN_ENOMEM;
+        }
+    }
+    c->live[p] = n;
+    *out = p;
+    return PN_OK;
+}
+
+void dfree(pn_ctx *c, void *p) {
+    if (!p) return;
+    auto it = c->live.find(p);
+    if (it == c->live.end()) return;
+    c->cache.emplace(it->second, p);
+    c->live.erase(it);
+}
+
+template <typename T>
+int dalloc_t(pn_ctx *c, size_t count, T **out) {
+    void *p = nullptr;
+    PN_CHECK(dalloc(c, count * sizeof(T) ? count * sizeof(T) : 1, &p));
+    *out = (T *)p;
+    return PN_OK;
+}
+
+// grow-only workspace buffer (contents are not preserved)
+int ensure(pn_ctx *c, Buf &b, size_t bytes) {
+    if (b.cap >= bytes && b.p) return PN_OK;
+    dfree(c, b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    size_t want = std::max(bytes + bytes / 4, (size_t)4096);
+    PN_CHECK(dalloc(c, want, &b.p));
+    b.cap = want;
+    return PN_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int bitlen(uint64_t x) {
+    int b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+hipStream_t pick_stream(pn_ctx *c, void *s) { return s ? (hipStream_t)s : c->stream; }
+
+// ---- stage timing: hipEvents on the stream the stage runs on ----
+
+hipEvent_t take_event(pn_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+int stage_begin(pn_ctx *c, hipStream_t st, int stage) {
+    if (!c->timing) return -1;
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return -1;
+    (void)hipEventRecord(a, st);
+    c->pending.push_back({stage, a, b, 0});
+    return (int)c->pending.size() - 1;
+}
+
+void stage_end(pn_ctx *c, hipStream_t st, int tok, int launches) {
+    if (tok < 0) return;
+    (void)hipEventRecord(c->pending[tok].b, st);
+    c->pending[tok].launches = launches;
+}
+
+// after a synchronisation: fold finished stage events into the statistics
+void collect_stages(pn_ctx *c) {
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->stats.ms[p.stage] += ms;
+            c->stats.launches[p.stage] += (uint64_t)p.launches;
+        } else {
+            (void)hipGetLastError();
+        }
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+// read the misc words back to the host (synchronises the stream)
+int read_misc(pn_ctx *c, hipStream_t st) {
+    PN_TRY(hipMemcpyAsync(c->hmisc, c->misc, kMiscWords * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                          st));
+    PN_TRY(hipStreamSynchronize(st));
+    collect_stages(c);
+    return PN_OK;
+}
+
+void zero_misc(pn_ctx *c, hipStream_t st) {
+    pn::launch_fill_u32((uint32_t *)c->misc, 2 * kMiscWords, 0u, st);
+}
+
+PnRefDev ref_desc(const pn_ref *r) {
+    PnRefDev d;
+    d.packed = r->packed_base + 1;
+    d.planes[0] = r->planes0;
+    d.planes[1] = r->planes1;
+    d.L = r->L;
+    d.n_plane_blocks = r->n_blocks;
+    return d;
+}
+
+PnIndexDev index_desc(const pn_index *x) {
+    PnIndexDev d;
+    d.packed = x->packed;
+    d.offsets = x->offsets;
+    d.rplanes = x->rplanes;
+    d.I = x->I;
+    d.S = x->S;
+    d.Sp = x->Sp;
+    d.O = x->O;
+    d.n_reads = x->n_reads;
+    d.max_len = (uint32_t)x->max_len;
+    d.q = x->q;
+    d.log2w = x->w == 64 ? 6 : 5;
+    d.n_groups = x->n_groups;
+    return d;
+}
+
+void free_index_arrays(pn_index *x) {
+    pn_ctx *c = x->ctx;
+    dfree(c, x->packed);
+    dfree(c, x->offsets);
+    dfree(c, x->rplanes);
+    dfree(c, x->I);
+    dfree(c, x->S);
+    dfree(c, x->Sp);
+    dfree(c, x->O);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *pn_strerror(int status) {
+    switch (status) {
+        case PN_OK: return "ok";
+        case PN_EINVAL: return "invalid argument or limit exceeded";
+        case PN_EALPHABET: return "letter other than A/C/G/T";
+        case PN_ENOMEM: return "out of memory";
+        case PN_EDEVICE: return "HIP device error";
+        case PN_ELEMMA: return "q-gram lemma violated: (k+1)*q > read length";
+        case PN_ETRUNC: return "output capacity too small";
+        case PN_EBUDGET: return "request exceeds the memory budget";
+        default: return "unknown status";
+    }
+}
+
+int pn_ctx_create(int device, pn_ctx **out) {
+    if (!out) return PN_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return PN_EDEVICE;
+    }
+    DeviceGuard g(device);
+    pn_ctx *c = new (std::nothrow) pn_ctx();
+    if (!c) return PN_ENOMEM;
+    c->device = device;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->misc, kMiscWords * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmisc, kMiscWords * sizeof(uint64_t), 0);
+    if (e != hipSuccess) {
+        if (c->misc) (void)hipFree(c->misc);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return map_err(e);
+    }
+    *out = c;
+    return PN_OK;
+}
+
+void pn_ctx_destroy(pn_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->cache) (void)hipFree(kv.second);
+    for (auto &kv : c->live) (void)hipFree(kv.first);
+    collect_stages(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    (void)hipFree(c->misc);
+    (void)hipHostFree(c->hmisc);
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int pn_ctx_stream(pn_ctx *c, void **stream) {
+    if (!c || !stream) return PN_EINVAL;
+    *stream = (void *)c->stream;
+    return PN_OK;
+}
+
+int pn_ctx_set_timing(pn_ctx *c, int enable) {
+    if (!c) return PN_EINVAL;
+    c->timing = enable != 0;
+    return PN_OK;
+}
+
+int pn_ctx_get_stats(pn_ctx *c, pn_stats *out, int reset) {
+    if (!c || !out) return PN_EINVAL;
+    *out = c->stats;
+    if (reset) c->stats = pn_stats{};
+    return PN_OK;
+}
+
+// ---- reference --------------------------------------------------------------
+
+int pn_ref_load_dev(pn_ctx *c, const char *d_seq, uint64_t len, void *stream, pn_ref **out) {
+    if (!c || !out || !d_seq || len == 0 || len >= (1ull << 32) - (1ull << 16)) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = pick_stream(c, stream);
+    pn_ref *r = new (std::nothrow) pn_ref();
+    if (!r) return PN_ENOMEM;
+    r->ctx = c;
+    r->L = len;
+    const uint64_t words = (len + 15) / 16;
+    r->n_blocks = (len + 31) / 32 + 2 * PN_PAD_BLOCKS + 16;
+    int s = dalloc_t(c, words + 5, &r->packed_base);
+    if (!s) s = dalloc_t(c, r->n_blocks, &r->planes0);
+    if (!s) s = dalloc_t(c, r->n_blocks, &r->planes1);
+    if (s) {
+        dfree(c, r->packed_base);
+        dfree(c, r->planes0);
+        dfree(c, r->planes1);
+        delete r;
+        return s;
+    }
+    zero_misc(c, st);
+    pn::launch_fill_u32(r->packed_base, 1, 0u, st);
+    pn::launch_fill_u32(r->packed_base + 1 + words, 4, 0u, st);
+    pn::launch_pack2(d_seq, len, r->packed_base + 1, (uint32_t *)&c->misc[kStatus], st);
+    pn::launch_ref_planes(r->packed_base + 1, len, r->planes0, r->planes1, r->n_blocks, st);
+    s = read_misc(c, st);
+    if (!s && (c->hmisc[kStatus] & 1)) s = PN_EALPHABET;
+    if (s) {
+        pn_ref_free(r);
+        return s;
+    }
+    *out = r;
+    return PN_OK;
+}
+
+int pn_ref_load(pn_ctx *c, const char *seq, uint64_t len, pn_ref **out) {
+    if (!c || !out || !seq || len == 0 || len >= (1ull << 32) - (1ull << 16)) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    char *d = nullptr;
+    PN_CHECK(dalloc_t(c, len, &d));
+    hipError_t e = hipMemcpyAsync(d, seq, len, hipMemcpyHostToDevice, c->stream);
+    int s = e == hipSuccess ? pn_ref_load_dev(c, d, len, c->stream, out) : map_err(e);
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, d);
+    return s;
+}
+
+void pn_ref_free(pn_ref *r) {
+    if (!r) return;
+    pn_ctx *c = r->ctx;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, r->packed_base);
+    dfree(c, r->planes0);
+    dfree(c, r->planes1);
+    delete r;
+}
+
+uint64_t pn_ref_length(const pn_ref *r) { return r ? r->L : 0; }
+
+// ---- index (Algorithm 1) ------------------------------------------------------
+
+int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets,
+                       uint32_t n_reads, uint64_t n_bases, int q, int w, void *stream,
+                       pn_index **out) {
+    if (!c || !out || (n_reads && !d_offsets) || (n_bases && !d_reads)) return PN_EINVAL;
+    if (q < 1 || q > 15 || (w != 32 && w != 64) || n_reads > PN_MAX_READS ||
+        n_bases >= (1ull << 32))
+        return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = pick_stream(c, stream);
+    pn_index *x = new (std::nothrow) pn_index();
+    if (!x) return PN_ENOMEM;
+    x->ctx = c;
+    x->n_reads = n_reads;
+    x->n_bases = n_bases;
+    x->q = q;
+    x->w = w;
+    const uint64_t G = 1ull << (2 * q);
+    x->n_groups = (G + w - 1) / w;
+    const uint64_t words = (n_bases + 15) / 16;
+    int s = dalloc_t(c, words + 4, &x->packed);
+    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &x->offsets);
+    if (s) {
+        free_index_arrays(x);
+        delete x;
+        return s;
+    }
+    zero_misc(c, st);
+    int tok = stage_begin(c, st, PN_STAGE_INGEST);
+    pn::launch_fill_u32(x->packed + words, 4, 0u, st);
+    pn::launch_pack2(d_reads, n_bases, x->packed, (uint32_t *)&c->misc[kStatus], st);
+    hipError_t e = n_reads ? hipMemcpyAsync(x->offsets, d_offsets, ((uint64_t)n_reads + 1) * 8,
+                                            hipMemcpyDeviceToDevice, st)
+                           : hipSuccess;
+    if (!n_reads) pn::launch_fill_u32((uint32_t *)x->offsets, 2, 0u, st);
+    pn::launch_read_meta(x->offsets, n_reads, q, n_bases, &c->misc[kStatMaxLen], st);
+    stage_end(c, st, tok, 3);
+    if (e == hipSuccess) s = read_misc(c, st);
+    else s = map_err(e);
+    if (!s && (c->hmisc[kStatus] & 1)) s = PN_EALPHABET;
+    if (!s && c->hmisc[kStatBad]) s = PN_EINVAL;
+    if (s) {
+        free_index_arrays(x);
+        delete x;
+        return s;
+    }
+    x->max_len = (int)c->hmisc[kStatMaxLen];
+    x->n_qgrams = c->hmisc[kStatT];
+    x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
+    const uint64_t T = x->n_qgrams, U = x->n_slots;
+    uint32_t *cnt = nullptr, *big = nullptr, *tmp = nullptr, *partials = nullptr;
+    const uint64_t n_big_max = T / 33 + 1;
+    s = dalloc_t(c, (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
+    if (!s) s = dalloc(c, x->n_groups * (w / 8), &x->I);
+    if (!s) s = dalloc_t(c, x->n_groups + 1, &x->S);
+    if (!s) s = dalloc_t(c, U + 1, &x->Sp);
+    if (!s) s = dalloc_t(c, T + 1, &x->O);
+    if (!s) s = dalloc_t(c, U + 1, &cnt);
+    if (!s) s = dalloc_t(c, n_big_max, &big);
+    if (!s) s = dalloc_t(c, T + 1, &tmp);
+    if (!s)
+        s = dalloc_t(c, pn::scan_partials_size(std::max<uint64_t>(x->n_groups, U + 1)), &partials);
+    if (!s) {
+        PnIndexDev ix = index_desc(x);
+        tok = stage_begin(c, st, PN_STAGE_INGEST);
+        pn::launch_read_planes(x->packed, x->offsets, n_reads, x->rplanes, st);
+        stage_end(c, st, tok, 1);
+        tok = stage_begin(c, st, PN_STAGE_INDEX);
+        pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
+        pn::launch_qgram_bitmap(ix, x->I, st);                                // step 1
+        pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
+        pn::launch_fill_u32(cnt, U + 1, 0u, st);
+        pn::launch_qgram_count(ix, cnt, st);                    // step 4
+        pn::launch_scan_u32(cnt, x->Sp, U, partials, st);      // step 5
+        pn::launch_fill_u32(cnt, U + 1, 0u, st);
+        pn::launch_qgram_scatter(ix, cnt, x->O, st);           // step 6
+        pn::launch_bucket_sort(x->Sp, U, x->S + x->n_groups, x->O, big,
+                               (uint32_t *)&c->misc[kBigCount], st);
+        stage_end(c, st, tok, 14);
+        uint32_t n_distinct = 0;
+        e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) s = read_misc(c, st);
+        else s = map_err(e);
+        if (!s) {
+            x->n_distinct = n_distinct;
+            const uint32_t n_big = (uint32_t)c->hmisc[kBigCount];
+            tok = stage_begin(c, st, PN_STAGE_INDEX);
+            pn::launch_bucket_sort_big(x->Sp, x->O, tmp, big, n_big, st);
+            stage_end(c, st, tok, n_big ? 1 : 0);
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) s = map_err(e);
+            collect_stages(c);
+        }
+    }
+    dfree(c, cnt);
+    dfree(c, big);
+    dfree(c, tmp);
+    dfree(c, partials);
+    if (s) {
+        free_index_arrays(x);
+        delete x;
+        return s;
+    }
+    *out = x;
+    return PN_OK;
+}
+
+int pn_index_build(pn_ctx *c, const char *reads, const uint64_t *offsets, uint32_t n_reads, int q,
+                   int w, pn_index **out) {
+    if (!c || !out || (n_reads && (!offsets || !reads))) return PN_EINVAL;
+    uint64_t n_bases = n_reads ? offsets[n_reads] : 0;
+    for (uint32_t r = 0; r < n_reads; r++)
+        if (offsets[r + 1] < offsets[r]) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    char *dr = nullptr;
+    uint64_t *doff = nullptr;
+    int s = dalloc_t(c, n_bases + 1, &dr);
+    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &doff);
+    if (!s && n_bases)
+        s = map_err(hipMemcpyAsync(dr, reads, n_bases, hipMemcpyHostToDevice, c->stream));
+    if (!s && n_reads)
+        s = map_err(hipMemcpyAsync(doff, offsets, ((uint64_t)n_reads + 1) * 8,
+                                   hipMemcpyHostToDevice, c->stream));
+    if (!s) s = pn_index_build_dev(c, dr, doff, n_reads, n_bases, q, w, c->stream, out);
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, dr);
+    dfree(c, doff);
+    return s;
+}
+
+void pn_index_free(pn_index *x) {
+    if (!x) return;
+    DeviceGuard g(x->ctx->device);
+    (void)hipStreamSynchronize(x->ctx->stream);
+    free_index_arrays(x);
+    delete x;
+}
+
+int pn_index_get_info(const pn_index *x, pn_index_info *out) {
+    if (!x || !out) return PN_EINVAL;
+    pn_index_info i{};
+    i.n_reads = x->n_reads;
+    i.n_bases = x->n_bases;
+    i.n_qgrams = x->n_qgrams;
+    i.n_distinct = x->n_distinct;
+    i.n_groups = x->n_groups;
+    i.q = x->q;
+    i.w = x->w;
+    i.max_len = x->max_len;
+    *out = i;
+    return PN_OK;
+}
+
+int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint32_t *O) {
+    if (!x) return PN_EINVAL;
+    pn_ctx *c = x->ctx;
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    if (I) PN_TRY(hipMemcpyAsync(I, x->I, x->n_groups * (x->w / 8), hipMemcpyDeviceToHost, st));
+    if (S) PN_TRY(hipMemcpyAsync(S, x->S, (x->n_groups + 1) * 4, hipMemcpyDeviceToHost, st));
+    if (Sp) PN_TRY(hipMemcpyAsync(Sp, x->Sp, (x->n_distinct + 1) * 4, hipMemcpyDeviceToHost, st));
+    if (O && x->n_qgrams)
+        PN_TRY(hipMemcpyAsync(O, x->O, x->n_qgrams * 4, hipMemcpyDeviceToHost, st));
+    PN_TRY(hipStreamSynchronize(st));
+    return PN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// mapping path
+
+namespace {
+
+struct FilterPlan {
+    uint64_t n_blocks = 0;
+    std::vector<uint64_t> offs;  // exclusive prefix of block counts, n_blocks + 1
+    uint64_t n_seeds = 0;
+};
+
+// count pass of Algorithm 2 (plus the k / lemma check) and the host-side
+// cumulative sum over block totals
+int filter_plan(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
+                hipStream_t st, FilterPlan &plan, bool check_k) {
+    const uint64_t L = ref->L;
+    const uint64_t npos = L >= (uint64_t)x->q ? L - x->q + 1 : 0;
+    plan.n_blocks = (npos + pn::kFilterBlockPos - 1) / pn::kFilterBlockPos;
+    PN_CHECK(ensure(c, c->block_counts, (plan.n_blocks + 1) * 4));
+    zero_misc(c, st);
+    if (check_k)
+        pn::launch_check_k(x->offsets, x->n_reads, x->q, kglob, d_k, (uint32_t *)&c->misc[kStatus],
+                           st);
+    PnRefDev rd = ref_desc(ref);
+    PnIndexDev ix = index_desc(x);
+    int tok = stage_begin(c, st, PN_STAGE_FILTER_COUNT);
+    if (x->n_qgrams)
+        pn::launch_filter_count(rd, ix, plan.n_blocks, (uint32_t *)c->block_counts.p,
+                                (unsigned long long *)&c->misc[kSeeds], st);
+    stage_end(c, st, tok, 1);
+    std::vector<uint32_t> counts(plan.n_blocks);
+    if (plan.n_blocks && x->n_qgrams)
+        PN_TRY(hipMemcpyAsync(counts.data(), c->block_counts.p, plan.n_blocks * 4,
+                              hipMemcpyDeviceToHost, st));
+    PN_CHECK(read_misc(c, st));
+    const uint32_t status = (uint32_t)c->hmisc[kStatus];
+    if (status & 2u) return PN_EINVAL;
+    if (status & 4u) return PN_ELEMMA;
+    plan.n_seeds = c->hmisc[kSeeds];
+    plan.offs.assign(plan.n_blocks + 1, 0);
+    for (uint64_t b = 0; b < plan.n_blocks; b++) plan.offs[b + 1] = plan.offs[b] + counts[b];
+    PN_CHECK(ensure(c, c->block_offsets, (plan.n_blocks + 1) * 8));
+    PN_TRY(hipMemcpyAsync(c->block_offsets.p, plan.offs.data(), (plan.n_blocks + 1) * 8,
+                          hipMemcpyHostToDevice, st));
+    return PN_OK;
+}
+
+// consecutive block ranges whose candidates fit one verification launch
+std::vector<std::pair<uint64_t, uint64_t>> chunk_blocks(const FilterPlan &p, uint64_t cap) {
+    std::vector<std::pair<uint64_t, uint64_t>> out;
+    uint64_t b0 = 0;
+    while (b0 < p.n_blocks) {
+        uint64_t b1 = b0 + 1;
+        while (b1 < p.n_blocks && p.offs[b1 + 1] - p.offs[b0] <= cap) b1++;
+        out.emplace_back(b0, b1);
+        b0 = b1;
+    }
+    return out;
+}
+
+int key_ebits(uint64_t L) { return std::max(1, bitlen(L - 1)); }
+int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
+
+// filtration + validation; leaves the sorted record keys in c->keys and
+// their count in *n_rec
+int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
+                hipStream_t st, uint64_t *n_rec) {
+    FilterPlan plan;
+    PN_CHECK(filter_plan(c, ref, x, kglob, d_k, st, plan, true));
+    const int ebits = key_ebits(ref->L);
+    const auto chunks = chunk_blocks(plan, c->cand_chunk);
+    uint64_t biggest = 0;
+    for (auto &ch : chunks) biggest = std::max(biggest, plan.offs[ch.second] - plan.offs[ch.first]);
+    PN_CHECK(ensure(c, c->cands, std::max<uint64_t>(biggest, 1) * sizeof(uint2)));
+    uint64_t rec_cap = std::max<uint64_t>(c->keys.cap / 8, std::max<uint64_t>(1u << 20, 16ull * x->n_reads));
+    PnRefDev rd = ref_desc(ref);
+    PnIndexDev ix = index_desc(x);
+    for (int attempt = 0; attempt < 8; attempt++) {
+        PN_CHECK(ensure(c, c->keys, rec_cap * 8));
+        rec_cap = c->keys.cap / 8;
+        pn::launch_fill_u32((uint32_t *)&c->misc[kRecCount], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 2, 0u, st);
+        pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
+                         (unsigned long long *)&c->misc[kVerifyRows], rec_cap, ebits};
+        for (auto &ch : chunks) {
+            const uint64_t n = plan.offs[ch.second] - plan.offs[ch.first];
+            if (!n) continue;
+            int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
+            pn::launch_filter_emit(rd, ix, ch.first, ch.second,
+                                   (const uint64_t *)c->block_offsets.p, (uint2 *)c->cands.p, st);
+            stage_end(c, st, tok, 1);
+            tok = stage_begin(c, st, PN_STAGE_VERIFY);
+            pn::launch_verify(rd, ix, (const uint2 *)c->cands.p, n, kglob, d_k, vo, st);
+            stage_end(c, st, tok, 1);
+        }
+        PN_CHECK(read_misc(c, st));
+        const uint64_t got = c->hmisc[kRecCount];
+        if (got <= rec_cap) {
+            *n_rec = got;
+            c->stats.n_seeds += plan.n_seeds;
+            c->stats.n_candidates += plan.offs.empty() ? 0 : plan.offs.back();
+            c->stats.verify_rows += c->hmisc[kVerifyRows];
+            c->stats.n_records += got;
+            const int bits = 6 + ebits + key_rbits(x->n_reads);
+            PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(got, 1) * 8));
+            PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(got)));
+            int tok = stage_begin(c, st, PN_STAGE_SORT);
+            pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
+                               got, bits, c->sort_temp.p, st);
+            stage_end(c, st, tok, 3 * ((bits + 7) / 8));
+            return PN_OK;
+        }
+        rec_cap = got + got / 4;  // records overflowed: grow and verify again
+    }
+    return PN_ENOMEM;
+}
+
+// duplicate removal + strata + output of the sorted records
+int finish(pn_ctx *c, const pn_ref *ref, const pn_index *x, uint64_t n_rec, int best, void *d_out,
+           uint64_t cap, hipStream_t st, uint64_t *n_out) {
+    const int ebits = key_ebits(ref->L);
+    PN_CHECK(ensure(c, c->flags, (n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->pos, (n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->partials, pn::scan_partials_size(n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->minv, ((uint64_t)x->n_reads + 1) * 4));
+    int tok = stage_begin(c, st, PN_STAGE_FINISH);
+    pn::launch_finish_hits((const unsigned long long *)c->keys.p, n_rec, ebits, best, x->n_reads,
+                           (uint32_t *)c->minv.p, (uint32_t *)c->flags.p, (uint32_t *)c->pos.p,
+                           (uint32_t *)c->partials.p, d_out, cap,
+                           (unsigned long long *)&c->misc[kOutCount], st);
+    stage_end(c, st, tok, best ? 7 : 5);
+    PN_CHECK(read_misc(c, st));
+    *n_out = c->hmisc[kOutCount];
+    c->stats.n_hits += *n_out;
+    return PN_OK;
+}
+
+int check_map_args(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *kpr,
+                   pn_mode mode) {
+    if (!c || !ref || !x || ref->ctx != c || x->ctx != c) return PN_EINVAL;
+    if (mode != PN_ALL_HITS && mode != PN_BEST_STRATUM) return PN_EINVAL;
+    if (k > PN_MAX_K) return PN_EINVAL;
+    if (k < 0 && !kpr && x->n_reads) return PN_EINVAL;
+    return PN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pn_map_dev(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *d_kpr,
+               pn_mode mode, pn_hit *d_hits, uint64_t capacity, uint64_t *n_hits, void *stream) {
+    PN_CHECK(check_map_args(c, ref, x, k, d_kpr, mode));
+    if (!n_hits || (capacity && !d_hits)) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = pick_stream(c, stream);
+    uint64_t n_rec = 0, n_out = 0;
+    PN_CHECK(map_records(c, ref, x, k < 0 ? -1 : k, d_kpr, st, &n_rec));
+    PN_CHECK(finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, d_hits, capacity, st, &n_out));
+    *n_hits = n_out;
+    return n_out > capacity ? PN_ETRUNC : PN_OK;
+}
+
+int pn_map(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *kpr,
+           pn_mode mode, pn_hit **hits, uint64_t *n_hits) {
+    PN_CHECK(check_map_args(c, ref, x, k, kpr, mode));
+    if (!hits || !n_hits) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    uint8_t *dk = nullptr;
+    if (k < 0 && x->n_reads) {
+        PN_CHECK(dalloc_t(c, x->n_reads, &dk));
+        hipError_t e = hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            dfree(c, dk);
+            return map_err(e);
+        }
+    }
+    uint64_t n_rec = 0, n_out = 0;
+    int s = map_records(c, ref, x, k < 0 ? -1 : k, dk, st, &n_rec);
+    // the output can hold at most one hit per record
+    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
+    if (!s)
+        s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->out_hits.p,
+                   c->out_hits.cap / sizeof(pn_hit), st, &n_out);
+    pn_hit *h = nullptr;
+    if (!s) {
+        h = (pn_hit *)std::malloc(std::max<uint64_t>(n_out, 1) * sizeof(pn_hit));
+        if (!h) s = PN_ENOMEM;
+    }
+    if (!s && n_out) {
+        hipError_t e = hipMemcpyAsync(h, c->out_hits.p, n_out * sizeof(pn_hit),
+                                      hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        s = map_err(e);
+    }
+    (void)hipStreamSynchronize(st);
+    dfree(c, dk);
+    if (s) {
+        std::free(h);
+        return s;
+    }
+    *hits = h;
+    *n_hits = n_out;
+    return PN_OK;
+}
+
+void pn_hits_free(pn_hit *h) { std::free(h); }
+
+int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, pn_candidate **cands,
+              uint64_t *n_cands, uint64_t *n_seeds) {
+    if (!c || !ref || !x || !cands || !n_cands || ref->ctx != c || x->ctx != c) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    FilterPlan plan;
+    PN_CHECK(filter_plan(c, ref, x, 0, nullptr, st, plan, false));
+    const uint64_t n = plan.offs.empty() ? 0 : plan.offs.back();
+    PN_CHECK(ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2)));
+    PN_CHECK(ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8));
+    PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8));
+    PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(n)));
+    PN_CHECK(ensure(c, c->out_hits, std::max<uint64_t>(n, 1) * sizeof(pn_candidate)));
+    if (n) {
+        pn::launch_filter_emit(ref_desc(ref), index_desc(x), 0, plan.n_blocks,
+                               (const uint64_t *)c->block_offsets.p, (uint2 *)c->cands.p, st);
+        pn::launch_cand_keys((const uint2 *)c->cands.p, n, (unsigned long long *)c->keys.p, st);
+        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, n,
+                           33 + key_rbits(x->n_reads), c->sort_temp.p, st);
+        pn::launch_keys_to_cands((const unsigned long long *)c->keys.p, n, c->out_hits.p, st);
+    }
+    pn_candidate *h = (pn_candidate *)std::malloc(std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
+    if (!h) return PN_ENOMEM;
+    hipError_t e = n ? hipMemcpyAsync(h, c->out_hits.p, n * sizeof(pn_candidate),
+                                      hipMemcpyDeviceToHost, st)
+                     : hipSuccess;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        std::free(h);
+        return map_err(e);
+    }
+    *cands = h;
+    *n_cands = n;
+    if (n_seeds) *n_seeds = plan.n_seeds;
+    return PN_OK;
+}
+
+int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candidate *cands,
+                uint64_t n, int k, const uint8_t *kpr, pn_hit **records, uint64_t *n_records) {
+    PN_CHECK(check_map_args(c, ref, x, k, kpr, PN_ALL_HITS));
+    if (!records || !n_records || (n && !cands)) return PN_EINVAL;
+    std::vector<uint2> host(n);
+    for (uint64_t i = 0; i < n; i++) {
+        const pn_candidate &cd = cands[i];
+        if (cd.read_id >= x->n_reads || cd.strand > 1 || cd.diagonal < -(int64_t)PN_MAX_READ_LEN ||
+            cd.diagonal > (int64_t)ref->L)
+            return PN_EINVAL;
+        host[i] = make_uint2(cd.read_id | ((uint32_t)cd.strand << 31),
+                             (uint32_t)(cd.diagonal + (int64_t)PN_DBIAS));
+    }
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    uint8_t *dk = nullptr;
+    if (k < 0 && x->n_reads) {
+        PN_CHECK(dalloc_t(c, x->n_reads, &dk));
+        PN_TRY(hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st));
+    }
+    int s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
+    const uint64_t cap = std::max<uint64_t>(n * (2 * PN_MAX_K + 1), 1);
+    if (!s) s = ensure(c, c->keys, cap * 8);
+    if (!s) s = ensure(c, c->keys_tmp, cap * 8);
+    if (!s && n)
+        s = map_err(hipMemcpyAsync(c->cands.p, host.data(), n * sizeof(uint2),
+                                   hipMemcpyHostToDevice, st));
+    uint64_t got = 0;
+    const int ebits = key_ebits(ref->L);
+    if (!s) {
+        zero_misc(c, st);
+        pn::launch_check_k(x->offsets, x->n_reads, x->q, k < 0 ? -1 : k, dk,
+                           (uint32_t *)&c->misc[kStatus], st);
+        pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
+                         (unsigned long long *)&c->misc[kVerifyRows], cap, ebits};
+        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p, n,
+                          k < 0 ? -1 : k, dk, vo, st);
+        s = read_misc(c, st);
+        if (!s && (c->hmisc[kStatus] & 2u)) s = PN_EINVAL;
+        if (!s && (c->hmisc[kStatus] & 4u)) s = PN_ELEMMA;
+        got = s ? 0 : c->hmisc[kRecCount];
+    }
+    if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(got));
+    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(got, 1) * sizeof(pn_hit));
+    pn_hit *h = nullptr;
+    if (!s) {
+        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, got,
+                           6 + ebits + key_rbits(x->n_reads), c->sort_temp.p, st);
+        pn::launch_records_to_hits((const unsigned long long *)c->keys.p, got, ebits, c->out_hits.p,
+                                   st);
+        h = (pn_hit *)std::malloc(std::max<uint64_t>(got, 1) * sizeof(pn_hit));
+        if (!h) s = PN_ENOMEM;
+    }
+    if (!s && got)
+        s = map_err(hipMemcpyAsync(h, c->out_hits.p, got * sizeof(pn_hit), hipMemcpyDeviceToHost,
+                                   st));
+    if (!s) s = map_err(hipStreamSynchronize(st));
+    dfree(c, dk);
+    if (s) {
+        std::free(h);
+        return s;
+    }
+    *records = h;
+    *n_records = got;
+    return PN_OK;
+}
+
+}  // extern "C"

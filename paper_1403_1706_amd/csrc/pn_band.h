@@ -1,0 +1,79 @@
+// Per-candidate banded bit-parallel semiglobal edit distance (Section 3.3),
+// shared by the verification kernel and by a host-side check of the same
+// code.  See pn_verify.hip for the recurrence and its band conventions.
+#pragma once
+
+#include "pn_internal.h"
+
+// bits [sh, sh+32) of the 64-bit value hi:lo
+__host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+}
+
+// Verify one candidate.  `pl`: the strand's padded bit planes; `rp`: the
+// read's PN_READ_WORDS plane words; the band covers diagonals [lo, lo + 2k]
+// (lo = d - k); 1 <= len <= PN_MAX_READ_LEN; 0 <= k <= PN_MAX_K.  Calls
+// emit(end, value) for every end column of the last row with value <= k,
+// and returns the number of rows computed.
+template <typename Emit>
+__host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__ pl,
+                                                       const uint2 *__restrict__ rp, int len, int k,
+                                                       int64_t lo, uint64_t L, Emit &&emit) {
+    const int W = 2 * k + 1;
+    const uint32_t M = (1u << W) - 1u;
+    const uint32_t M2 = M & ~1u;
+    const uint32_t TOP = 1u << (W - 1);
+    // the candidate's own stream of plane words: stream word m covers
+    // reference positions [lo + 32m, lo + 32m + 32)
+    const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
+    const uint64_t blk = tp >> 5;
+    const uint32_t ph = (uint32_t)(tp & 31);
+    const uint4 A = pl[blk], B = pl[blk + 1];
+    uint4 C = pl[blk + 2], Dn = pl[blk + 3];
+    uint32_t h0 = pn_funnel(B.x, A.x, ph), l0 = pn_funnel(B.y, A.y, ph), v0 = pn_funnel(B.z, A.z, ph);
+    uint32_t h1 = pn_funnel(C.x, B.x, ph), l1 = pn_funnel(C.y, B.y, ph), v1 = pn_funnel(C.z, B.z, ph);
+    uint32_t VP = 0, VN = 0;  // row 0: every band cell is 0 (free start)
+    int R = 0;                // value of the right-most band cell
+    for (int m = 0;; m++) {
+        const uint2 rw = rp[m];
+#pragma unroll
+        for (int t = 0; t < 32; t++) {
+            const int i = 32 * m + t + 1;  // row i compares read letter i-1
+            const uint32_t H = pn_funnel(h1, h0, t), Lw = pn_funnel(l1, l0, t),
+                           V = pn_funnel(v1, v0, t);
+            const uint32_t xh = 0u - ((rw.x >> t) & 1u), xl = 0u - ((rw.y >> t) & 1u);
+            const uint32_t Eq = ~((H ^ xh) | (Lw ^ xl)) & V & M;
+            VP = (VP >> 1) | TOP;  // previous row's differences, moved into this row's frame
+            VN >>= 1;
+            const uint32_t Xv = Eq | VN;
+            const uint32_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
+            uint32_t HP = VN | ~(Xh | VP);
+            uint32_t HN = VP & Xh;
+            R += 1 - (int)((HN >> (W - 1)) & 1u);
+            HP = (HP << 1) | 1u;
+            HN <<= 1;
+            VP = HN | ~(Xv | HP);
+            VN = HP & Xv;
+            if (i == len) {
+                // last row: cell b holds R minus the differences to its right
+                int v = R;
+                for (int b = W - 1; b >= 0; b--) {
+                    const int64_t c = (int64_t)len + lo + b;
+                    if (c >= 1 && c <= (int64_t)L && v <= k) emit((uint32_t)(c - 1), v);
+                    v -= (int)((VP >> b) & 1u) - (int)((VN >> b) & 1u);
+                }
+                return i;
+            }
+            if (R - __builtin_popcount(VP & M2) > k) return i;  // whole row above k
+        }
+        // advance the stream by 32 positions
+        h0 = h1;
+        l0 = l1;
+        v0 = v1;
+        h1 = pn_funnel(Dn.x, C.x, ph);
+        l1 = pn_funnel(Dn.y, C.y, ph);
+        v1 = pn_funnel(Dn.z, C.z, ph);
+        C = Dn;
+        Dn = pl[blk + m + 4];
+    }
+}

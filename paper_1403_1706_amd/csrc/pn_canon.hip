@@ -1,0 +1,229 @@
+// Canonical hit list (Section 3.4, postprocessing): records (read, strand,
+// end, errors) packed into 64-bit keys are sorted, duplicates of the same
+// (read, strand, end) found through several candidates keep the smallest
+// error count, and best-stratum mode keeps the hits whose error count is the
+// read's minimum.  The sort is a stable LSD radix sort with 8-bit digits:
+// per-tile digit histograms, one exclusive scan over (digit, tile), and a
+// stable scatter that ranks equal digits inside each wave with ballots.
+#include "pn_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;
+
+inline unsigned grid_for(uint64_t n, unsigned threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long long *keys,
+                                                         uint64_t n, int shift, uint32_t *hist,
+                                                         uint64_t n_tiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int j = 0; j < kItems; j++) {
+        uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
+                                                            unsigned long long *out, uint64_t n,
+                                                            int shift, const uint32_t *offs,
+                                                            uint64_t n_tiles) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    run[threadIdx.x] = offs[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    for (int j = 0; j < kItems; j++) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+        const bool valid = i < n;
+        const unsigned long long key = valid ? keys[i] : 0ull;
+        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (dg >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dg] + rank;
+            for (int w = 0; w < wave; w++) pos += wcnt[w][dg];
+            out[pos] = key;
+        }
+        __syncthreads();
+        run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
+                            wcnt[3][threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// smallest error count per read (over all records; duplicates do not matter)
+__global__ void k_read_min(const unsigned long long *keys, uint64_t n, int ebits,
+                           uint32_t *minv) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long k = keys[i];
+    uint32_t r = (uint32_t)(k >> (6 + ebits));
+    atomicMin(&minv[r], (uint32_t)(k & 31u));
+}
+
+// 1 for the first record of each (read, strand, end) run (smallest errors,
+// keys being sorted) that also passes the stratum filter
+__global__ void k_keep_flags(const unsigned long long *keys, uint64_t n, int ebits, int best,
+                             const uint32_t *minv, uint32_t *flags) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long k = keys[i];
+    uint32_t f = (i == 0) || ((keys[i - 1] >> 5) != (k >> 5));
+    if (best && f) f = (uint32_t)(k & 31u) == minv[(uint32_t)(k >> (6 + ebits))];
+    flags[i] = f;
+}
+
+__device__ __forceinline__ uint4 key_to_hit(unsigned long long k, int ebits) {
+    uint32_t v = (uint32_t)(k & 31u);
+    uint32_t e = (uint32_t)((k >> 5) & ((1ull << ebits) - 1ull));
+    uint32_t s = (uint32_t)((k >> (5 + ebits)) & 1u);
+    uint32_t r = (uint32_t)(k >> (6 + ebits));
+    return make_uint4(r, e, s | (v << 8), 0u);
+}
+
+__global__ void k_write_hits(const unsigned long long *keys, uint64_t n, int ebits,
+                             const uint32_t *flags, const uint32_t *pos, uint32_t *out,
+                             uint64_t capacity) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flags[i]) return;
+    uint64_t p = pos[i];
+    if (p >= capacity) return;
+    uint4 h = key_to_hit(keys[i], ebits);
+    out[3 * p + 0] = h.x;
+    out[3 * p + 1] = h.y;
+    out[3 * p + 2] = h.z;
+}
+
+__global__ void k_total(const uint32_t *pos, uint64_t n, unsigned long long *n_out) {
+    *n_out = pos[n];
+}
+
+__global__ void k_records_to_hits(const unsigned long long *keys, uint64_t n, int ebits,
+                                  uint32_t *out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 h = key_to_hit(keys[i], ebits);
+    out[3 * i + 0] = h.x;
+    out[3 * i + 1] = h.y;
+    out[3 * i + 2] = h.z;
+}
+
+// candidate (read | strand << 31, diagonal + bias) -> sortable key
+__global__ void k_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint2 v = c[i];
+    keys[i] = ((unsigned long long)(v.x & 0x7fffffffu) << 33) |
+              ((unsigned long long)(v.x >> 31) << 32) | v.y;
+}
+
+// sorted candidate key -> pn_candidate {u32 read, u8 strand, pad[3], i64 diag}
+__global__ void k_keys_to_cands(const unsigned long long *keys, uint64_t n, uint32_t *out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long k = keys[i];
+    long long d = (long long)(k & 0xffffffffull) - (long long)PN_DBIAS;
+    out[4 * i + 0] = (uint32_t)(k >> 33);
+    out[4 * i + 1] = (uint32_t)((k >> 32) & 1u);
+    out[4 * i + 2] = (uint32_t)((unsigned long long)d & 0xffffffffull);
+    out[4 * i + 3] = (uint32_t)((unsigned long long)d >> 32);
+}
+
+}  // namespace
+
+namespace pn {
+
+static uint64_t tiles_for(uint64_t n) { return (n + kTile - 1) / kTile; }
+
+uint64_t radix_temp_size(uint64_t n) {
+    uint64_t nt = tiles_for(n) ? tiles_for(n) : 1;
+    uint64_t hist = 256 * nt + 1;
+    return (2 * hist + scan_partials_size(256 * nt)) * sizeof(uint32_t) + 256;
+}
+
+void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
+                    void *temp, hipStream_t st) {
+    if (n <= 1 || bits <= 0) return;
+    const uint64_t nt = tiles_for(n);
+    uint32_t *hist = (uint32_t *)temp;
+    uint32_t *offs = hist + 256 * nt + 1;
+    uint32_t *partials = offs + 256 * nt + 1;
+    unsigned long long *src = keys, *dst = tmp;
+    const int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kThreads), 0, st, src, n, shift,
+                           hist, nt);
+        launch_scan_u32(hist, offs, 256 * nt, partials, st);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,
+                           shift, offs, nt);
+        unsigned long long *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != keys) (void)hipMemcpyAsync(keys, src, n * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToDevice, st);
+}
+
+void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,
+                        uint32_t n_reads, uint32_t *minv, uint32_t *flags, uint32_t *pos,
+                        uint32_t *partials, void *out_hits, uint64_t capacity,
+                        unsigned long long *n_out, hipStream_t st) {
+    if (best) {
+        launch_fill_u32(minv, n_reads, 0xffffffffu, st);
+        if (n)
+            hipLaunchKernelGGL(k_read_min, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+                               ebits, minv);
+    }
+    if (n)
+        hipLaunchKernelGGL(k_keep_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+                           ebits, best, (const uint32_t *)minv, flags);
+    launch_scan_u32(flags, pos, n, partials, st);
+    if (n)
+        hipLaunchKernelGGL(k_write_hits, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+                           ebits, (const uint32_t *)flags, (const uint32_t *)pos,
+                           (uint32_t *)out_hits, capacity);
+    hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, st, (const uint32_t *)pos, n, n_out);
+}
+
+void launch_records_to_hits(const unsigned long long *sorted, uint64_t n, int ebits, void *out,
+                            hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_records_to_hits, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+                       ebits, (uint32_t *)out);
+}
+
+void launch_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_cand_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, c, n, keys);
+}
+
+void launch_keys_to_cands(const unsigned long long *keys, uint64_t n, void *out, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_keys_to_cands, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, n,
+                       (uint32_t *)out);
+}
+
+}  // namespace pn

@@ -1,0 +1,184 @@
+// Internal declarations shared by the HIP translation units of libpeanut.
+// Device layouts:
+//  * packed text: 2 bits per base, 16 bases per uint32, first base in the
+//    most significant bits (base t lives in word t/16 at bits 30-2(t%16)),
+//    so a q-gram code with its first base most significant is a funnel
+//    shift of two words.
+//  * bit planes (verification): per 32 positions one uint4 {H, L, V, 0}
+//    with bit b of H / L = high / low bit of the base code at position
+//    32*blk + b and V = 1 where the position lies inside [0, L).  Arrays are
+//    padded by PN_PAD_BLOCKS blocks on each side so that band windows that
+//    hang over either end of the reference read "no base here".
+//  * read planes: per read, PN_READ_WORDS uint2 {H, L} words (LSB-first).
+//  * O entry: (cls << 29) | (read << 8) | offset, cls = code of the letter
+//    before the q-gram in its read or 4 at offset 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PN_MAX_READ_LEN 256
+#define PN_READ_WORDS (PN_MAX_READ_LEN / 32)
+#define PN_MAX_READS (1u << 21)
+#define PN_MAX_K 15
+#define PN_PAD_BLOCKS 16
+#define PN_PAD_POS (32 * PN_PAD_BLOCKS)
+#define PN_DBIAS 65536u
+#define PN_CLS_NONE 4u
+
+// ---------------------------------------------------------------------------
+// descriptors passed by value to kernels
+
+struct PnRefDev {
+    const uint32_t *packed;  // 2-bit text, ceil(L/16) + 4 words
+    const uint4 *planes[2];  // strand 0 and strand 1 bit planes (padded)
+    uint64_t L;
+    uint64_t n_plane_blocks;
+};
+
+struct PnIndexDev {
+    const uint32_t *packed;   // 2-bit concatenated reads
+    const uint64_t *offsets;  // n_reads + 1
+    const uint2 *rplanes;     // n_reads * PN_READ_WORDS
+    const void *I;            // n_groups words of w bits
+    const uint32_t *S;        // n_groups + 1
+    const uint32_t *Sp;       // n_distinct + 1
+    const uint32_t *O;        // n_qgrams
+    uint32_t n_reads;
+    uint32_t max_len;
+    int q;
+    int log2w;
+    uint64_t n_groups;
+};
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ __forceinline__ uint32_t pn_base_at(const uint32_t *packed, uint64_t t) {
+    return (packed[t >> 4] >> (30 - 2 * (uint32_t)(t & 15))) & 3u;
+}
+
+// 32 bits of packed text starting at base t: bases t..t+15, first base in
+// the top two bits.
+__device__ __forceinline__ uint32_t pn_window16(const uint32_t *packed, uint64_t t) {
+    uint64_t wi = t >> 4;
+    uint32_t sh = 2 * (uint32_t)(t & 15);
+    uint32_t hi = packed[wi];
+    uint32_t lo = packed[wi + 1];
+    return sh ? (hi << sh) | (lo >> (32 - sh)) : hi;
+}
+
+// reverse complement of a q-gram code (first base most significant):
+// complement every base (code xor 3) and reverse the order of the 2-bit
+// groups.
+__device__ __forceinline__ uint32_t pn_revcomp_code(uint32_t g, int q) {
+    uint32_t x = ~g;
+    x = __builtin_bitreverse32(x);                       // reverses bits
+    x = ((x >> 1) & 0x55555555u) | ((x & 0x55555555u) << 1);  // restore bit order inside each base
+    return x >> (32 - 2 * q);
+}
+
+template <typename TW>
+__device__ __forceinline__ int pn_popc(TW x);
+template <>
+__device__ __forceinline__ int pn_popc<uint32_t>(uint32_t x) { return __popc(x); }
+template <>
+__device__ __forceinline__ int pn_popc<uint64_t>(uint64_t x) { return __popcll(x); }
+template <>
+__device__ __forceinline__ int pn_popc<unsigned long long>(unsigned long long x) {
+    return __popcll(x);
+}
+
+// exclusive scan of one uint32 per thread over a 256-thread block (four
+// waves of 64); returns the thread's exclusive prefix, *total = block sum.
+// Every thread of the block must call it (it synchronises).
+__device__ __forceinline__ uint32_t pn_block_excl_scan(uint32_t x, uint32_t *total) {
+    __shared__ uint32_t ws[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        before += w < wave ? ws[w] : 0u;
+        all += ws[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (all asynchronous on `st`)
+
+namespace pn {
+
+// pn_pack.hip
+void launch_pack2(const char *ascii, uint64_t n, uint32_t *packed, uint32_t *status,
+                  hipStream_t st);
+void launch_ref_planes(const uint32_t *packed, uint64_t L, uint4 *planes0, uint4 *planes1,
+                       uint64_t n_blocks, hipStream_t st);
+void launch_read_meta(const uint64_t *offsets, uint32_t n_reads, int q, uint64_t n_bases,
+                      uint64_t *stats, hipStream_t st);
+void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_t n_reads,
+                        uint2 *rplanes, hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+void launch_check_k(const uint64_t *offsets, uint32_t n_reads, int q, int kglob,
+                    const uint8_t *kpr, uint32_t *status, hipStream_t st);
+
+// pn_scan.hip: exclusive prefix sums; out has n + 1 entries (out[n] = total)
+void launch_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
+                     hipStream_t st);
+void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint32_t *partials,
+                      hipStream_t st);
+uint64_t scan_partials_size(uint64_t n);
+
+// pn_index.hip (Algorithm 1)
+void launch_qgram_bitmap(const PnIndexDev &ix, void *I, hipStream_t st);
+void launch_qgram_count(const PnIndexDev &ix, uint32_t *cnt, hipStream_t st);
+void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, uint32_t *O, hipStream_t st);
+void launch_bucket_sort(const uint32_t *Sp, uint64_t n_slots, const uint32_t *n_distinct,
+                        uint32_t *O, uint32_t *big_list, uint32_t *big_count, hipStream_t st);
+void launch_bucket_sort_big(const uint32_t *Sp, uint32_t *O, uint32_t *tmp,
+                            const uint32_t *big_list, uint32_t n_big, hipStream_t st);
+
+// pn_filter.hip (Algorithm 2)
+constexpr int kFilterThreads = 256;
+constexpr int kFilterPPT = 8;  // forward positions per thread
+constexpr int kFilterBlockPos = kFilterThreads * kFilterPPT;
+void launch_filter_count(const PnRefDev &ref, const PnIndexDev &ix, uint64_t n_blocks,
+                         uint32_t *block_counts, unsigned long long *n_seeds, hipStream_t st);
+void launch_filter_emit(const PnRefDev &ref, const PnIndexDev &ix, uint64_t blk0, uint64_t blk1,
+                        const uint64_t *block_offsets, uint2 *cands, hipStream_t st);
+
+// pn_verify.hip (Section 3.3)
+struct VerifyOut {
+    unsigned long long *records;  // packed hit keys
+    unsigned long long *count;
+    unsigned long long *rows;     // band rows computed (work counter)
+    uint64_t capacity;
+    int ebits;  // bits for end positions in a key
+};
+void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands, uint64_t n,
+                   int kglob, const uint8_t *kpr, VerifyOut out, hipStream_t st);
+
+// pn_canon.hip: sort + duplicate removal + strata + output
+uint64_t radix_temp_size(uint64_t n);  // bytes
+void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
+                    void *temp, hipStream_t st);
+void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,
+                        uint32_t n_reads, uint32_t *minv, uint32_t *flags, uint32_t *pos,
+                        uint32_t *partials, void *out_hits, uint64_t capacity,
+                        unsigned long long *n_out, hipStream_t st);
+void launch_records_to_hits(const unsigned long long *sorted, uint64_t n, int ebits, void *out,
+                            hipStream_t st);
+void launch_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys, hipStream_t st);
+void launch_keys_to_cands(const unsigned long long *keys, uint64_t n, void *out, hipStream_t st);
+
+}  // namespace pn

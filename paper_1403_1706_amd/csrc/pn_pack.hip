@@ -1,0 +1,197 @@
+// Ingest: ASCII -> 2-bit codes, reference bit planes for both strands, read
+// metadata and read bit planes.  Base codes follow Section 2.2
+// (A=00, C=01, G=10, T=11).
+#include "pn_internal.h"
+
+namespace {
+
+// code of an ASCII letter (either case) and whether it is A/C/G/T.
+// A 0x41 -> 0, C 0x43 -> 1, G 0x47 -> 2, T 0x54 -> 3 (same for lower case).
+__device__ __forceinline__ uint32_t ascii_code(uint32_t c, bool &ok) {
+    uint32_t l = c | 0x20u;
+    ok = (l == 'a') | (l == 'c') | (l == 'g') | (l == 't');
+    return ((c >> 1) ^ (c >> 2)) & 3u;
+}
+
+__global__ void k_pack2(const char *__restrict__ ascii, uint64_t n, uint32_t *__restrict__ packed,
+                        uint32_t *status, int aligned16) {
+    uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t t0 = w * 16;
+    if (t0 >= n) return;
+    uint32_t bytes[16];
+    if (aligned16 && t0 + 16 <= n) {
+        uint4 v = *reinterpret_cast<const uint4 *>(ascii + t0);
+        uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 16; i++) bytes[i] = (u[i >> 2] >> (8 * (i & 3))) & 0xffu;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; i++) bytes[i] = (t0 + i < n) ? (uint32_t)(uint8_t)ascii[t0 + i] : 'A';
+    }
+    uint32_t word = 0;
+    bool all_ok = true;
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        bool ok;
+        uint32_t c = ascii_code(bytes[i], ok);
+        all_ok &= ok;
+        word |= c << (30 - 2 * i);
+    }
+    packed[w] = word;
+    if (!all_ok) atomicOr(status, 1u);
+}
+
+__global__ void k_ref_planes(const uint32_t *__restrict__ packed, uint64_t L,
+                             uint4 *__restrict__ planes0, uint4 *__restrict__ planes1,
+                             uint64_t n_blocks) {
+    uint64_t B = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= n_blocks) return;
+    int64_t t0 = 32 * ((int64_t)B - PN_PAD_BLOCKS);
+    uint32_t h0 = 0, l0 = 0, h1 = 0, l1 = 0, v = 0;
+    for (int b = 0; b < 32; b++) {
+        int64_t t = t0 + b;
+        if (t < 0 || t >= (int64_t)L) continue;
+        uint32_t c0 = pn_base_at(packed, (uint64_t)t);
+        // strand 1 at t is the complement of strand 0 at L-1-t
+        uint32_t c1 = 3u - pn_base_at(packed, L - 1 - (uint64_t)t);
+        h0 |= (c0 >> 1) << b;
+        l0 |= (c0 & 1u) << b;
+        h1 |= (c1 >> 1) << b;
+        l1 |= (c1 & 1u) << b;
+        v |= 1u << b;
+    }
+    planes0[B] = make_uint4(h0, l0, v, 0u);
+    planes1[B] = make_uint4(h1, l1, v, 0u);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// stats[0] = max read length, stats[1] = |T| = sum max(0, n_r - q + 1),
+// stats[2] = number of malformed reads (decreasing offsets, past n_bases,
+// or longer than PN_MAX_READ_LEN)
+__global__ void k_read_meta(const uint64_t *__restrict__ offsets, uint32_t n_reads, int q,
+                            uint64_t n_bases, unsigned long long *stats) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long len = 0, tq = 0, bad = 0;
+    if (r < n_reads) {
+        uint64_t a = offsets[r], b = offsets[r + 1];
+        if (b < a || b > n_bases) {
+            bad = 1;
+        } else {
+            len = b - a;
+            tq = len >= (unsigned long long)q ? len - q + 1 : 0;
+            bad = len > PN_MAX_READ_LEN;
+        }
+    }
+    unsigned long long mx = wave_max_u64(len);
+    tq = wave_sum_u64(tq);
+    bad = wave_sum_u64(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&stats[0], mx);
+        if (tq) atomicAdd(&stats[1], tq);
+        if (bad) atomicAdd(&stats[2], bad);
+    }
+}
+
+__global__ void k_read_planes(const uint32_t *__restrict__ packed,
+                              const uint64_t *__restrict__ offsets, uint32_t n_reads,
+                              uint2 *__restrict__ rplanes) {
+    uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t r = (uint32_t)(gid / PN_READ_WORDS);
+    uint32_t m = (uint32_t)(gid % PN_READ_WORDS);
+    if (r >= n_reads) return;
+    uint64_t start = offsets[r];
+    uint64_t len = offsets[r + 1] - start;
+    uint32_t h = 0, l = 0;
+    for (uint32_t b = 0; b < 32; b++) {
+        uint64_t o = 32ull * m + b;
+        if (o >= len) break;
+        uint32_t c = pn_base_at(packed, start + o);
+        h |= (c >> 1) << b;
+        l |= (c & 1u) << b;
+    }
+    rplanes[gid] = make_uint2(h, l);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
+__global__ void k_check_k(const uint64_t *__restrict__ offsets, uint32_t n_reads, int q, int kglob,
+                          const uint8_t *__restrict__ kpr, uint32_t *status) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_reads) return;
+    uint64_t len = offsets[r + 1] - offsets[r];
+    uint32_t k = kglob >= 0 ? (uint32_t)kglob : kpr[r];
+    uint32_t bad = 0;
+    if (k > PN_MAX_K) bad |= 2u;
+    if ((uint64_t)(k + 1) * (uint64_t)q > len) bad |= 4u;
+    if (bad) atomicOr(status, bad);
+}
+
+inline unsigned grid_for(uint64_t n, unsigned threads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+namespace pn {
+
+void launch_pack2(const char *ascii, uint64_t n, uint32_t *packed, uint32_t *status,
+                  hipStream_t st) {
+    uint64_t words = (n + 15) / 16;
+    if (!words) return;
+    int aligned = ((uintptr_t)ascii % 16) == 0;
+    hipLaunchKernelGGL(k_pack2, dim3(grid_for(words, 256)), dim3(256), 0, st, ascii, n, packed,
+                       status, aligned);
+}
+
+void launch_ref_planes(const uint32_t *packed, uint64_t L, uint4 *planes0, uint4 *planes1,
+                       uint64_t n_blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_ref_planes, dim3(grid_for(n_blocks, 256)), dim3(256), 0, st, packed, L,
+                       planes0, planes1, n_blocks);
+}
+
+void launch_read_meta(const uint64_t *offsets, uint32_t n_reads, int q, uint64_t n_bases,
+                      uint64_t *stats, hipStream_t st) {
+    if (!n_reads) return;
+    hipLaunchKernelGGL(k_read_meta, dim3(grid_for(n_reads, 256)), dim3(256), 0, st, offsets,
+                       n_reads, q, n_bases, (unsigned long long *)stats);
+}
+
+void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_t n_reads,
+                        uint2 *rplanes, hipStream_t st) {
+    uint64_t n = (uint64_t)n_reads * PN_READ_WORDS;
+    if (!n) return;
+    hipLaunchKernelGGL(k_read_planes, dim3(grid_for(n, 256)), dim3(256), 0, st, packed, offsets,
+                       n_reads, rplanes);
+}
+
+void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = grid_for(n, 256);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
+}
+
+void launch_check_k(const uint64_t *offsets, uint32_t n_reads, int q, int kglob,
+                    const uint8_t *kpr, uint32_t *status, hipStream_t st) {
+    if (!n_reads) return;
+    hipLaunchKernelGGL(k_check_k, dim3(grid_for(n_reads, 256)), dim3(256), 0, st, offsets,
+                       n_reads, q, kglob, kpr, status);
+}
+
+}  // namespace pn

@@ -1,0 +1,151 @@
+// Exclusive prefix sums (the cumulative sums of Algorithm 1, steps 3 and 5;
+// the parallel prefix scans of Section 2.1).  Reduce-then-scan in three
+// launches: per-tile sums, one block scanning the tile sums, per-tile scan
+// plus carry.  Tiles are 4096 elements (256 lanes x 16); values are uint32.
+#include "pn_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;
+
+__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 5); }
+
+struct LoadU32 {
+    const uint32_t *p;
+    __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
+};
+template <typename TW>
+struct LoadPopc {
+    const TW *I;
+    __device__ uint32_t operator()(uint64_t i) const { return (uint32_t)pn_popc<TW>(I[i]); }
+};
+
+// inclusive scan across the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// exclusive block scan of one value per thread; returns the thread's
+// exclusive prefix and writes the block total to *total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *total) {
+    __shared__ uint32_t wsum[kThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; w++) {
+        uint32_t s = wsum[w];
+        before += (w < wave) ? s : 0u;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+template <typename Load>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(Load load, uint64_t n,
+                                                          uint32_t *partials) {
+    uint64_t base = (uint64_t)blockIdx.x * kTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+        if (i < n) s += load(i);
+    }
+    uint32_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// one block: exclusive scan of partials[0..nb) in place, total to partials[nb]
+__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t *partials, uint64_t nb) {
+    uint32_t carry = 0;
+    for (uint64_t base = 0; base < nb; base += kThreads) {
+        uint64_t i = base + threadIdx.x;
+        uint32_t x = i < nb ? partials[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_excl_scan(x, &total);
+        if (i < nb) partials[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) partials[nb] = carry;
+}
+
+template <typename Load>
+__global__ __launch_bounds__(kThreads) void k_scan_down(Load load, uint32_t *out, uint64_t n,
+                                                        const uint32_t *partials, uint64_t nb) {
+    __shared__ uint32_t tile[kTile + kTile / 32];
+    uint64_t base = (uint64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        int li = j * kThreads + threadIdx.x;
+        uint64_t i = base + li;
+        tile[lds_idx(li)] = i < n ? load(i) : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        v[j] = tile[lds_idx(threadIdx.x * kItems + j)];
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(s, &total) + partials[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        tile[lds_idx(threadIdx.x * kItems + j)] = run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        int li = j * kThreads + threadIdx.x;
+        uint64_t i = base + li;
+        if (i < n) out[i] = tile[lds_idx(li)];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[nb];
+}
+
+template <typename Load>
+void scan_impl(Load load, uint32_t *out, uint64_t n, uint32_t *partials, hipStream_t st) {
+    uint64_t nb = (n + kTile - 1) / kTile;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce<Load>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, n,
+                       partials);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, partials, nb);
+    hipLaunchKernelGGL(k_scan_down<Load>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, out, n,
+                       (const uint32_t *)partials, nb);
+}
+
+}  // namespace
+
+namespace pn {
+
+uint64_t scan_partials_size(uint64_t n) { return (n + kTile - 1) / kTile + 2; }
+
+void launch_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
+                     hipStream_t st) {
+    scan_impl(LoadU32{in}, out, n, partials, st);
+}
+
+void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint32_t *partials,
+                      hipStream_t st) {
+    if (log2w == 6)
+        scan_impl(LoadPopc<uint64_t>{(const uint64_t *)I}, out, n, partials, st);
+    else
+        scan_impl(LoadPopc<uint32_t>{(const uint32_t *)I}, out, n, partials, st);
+}
+
+}  // namespace pn

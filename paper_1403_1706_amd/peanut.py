@@ -1,0 +1,328 @@
+"""Python binding of libpeanut (include/peanut.h) — argument marshalling only.
+
+Every function keeps the C name and forwards to the shared library; all
+mapping work happens in the HIP kernels behind it.  Host arrays are numpy;
+device buffers are torch tensors on the GPU (PyTorch supplies device memory
+and streams, nothing else).  The library must have been built
+(``paper_1403_1706_amd.build.build()``); importing this module without it
+raises immediately — there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpeanut.so")
+
+PN_OK = 0
+PN_EINVAL = -1
+PN_EALPHABET = -2
+PN_ENOMEM = -3
+PN_EDEVICE = -4
+PN_ELEMMA = -5
+PN_ETRUNC = -6
+PN_EBUDGET = -7
+
+PN_ALL_HITS = 0
+PN_BEST_STRATUM = 1
+
+HIT_DTYPE = np.dtype([("read_id", "<u4"), ("end_pos", "<u4"), ("strand", "u1"),
+                      ("errors", "u1"), ("reserved", "<u2")])
+CAND_DTYPE = np.dtype([("read_id", "<u4"), ("strand", "u1"), ("reserved", "u1", (3,)),
+                       ("diagonal", "<i8")])
+
+
+class _IndexInfo(ctypes.Structure):
+    _fields_ = [("n_reads", ctypes.c_uint64), ("n_bases", ctypes.c_uint64),
+                ("n_qgrams", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
+                ("n_groups", ctypes.c_uint64), ("q", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("max_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+STAGES = ["ingest", "index", "filter_count", "filter_emit", "verify", "sort", "finish"]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
+                ("n_seeds", ctypes.c_uint64), ("n_candidates", ctypes.c_uint64),
+                ("verify_rows", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
+                ("n_hits", ctypes.c_uint64)]
+
+
+class PnError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.pn_strerror(status).decode()} ({status})")
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libpeanut.so is not built ({LIB_PATH}); run paper_1403_1706_amd.build.build()")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_int = ctypes.c_int
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("pn_strerror", ctypes.c_char_p, [_int])
+_sig("pn_ctx_create", _int, [_int, _PP])
+_sig("pn_ctx_destroy", None, [_P])
+_sig("pn_ctx_stream", _int, [_P, _PP])
+_sig("pn_ctx_set_timing", _int, [_P, _int])
+_sig("pn_ctx_get_stats", _int, [_P, ctypes.POINTER(_Stats), _int])
+_sig("pn_ref_load", _int, [_P, ctypes.c_char_p, _u64, _PP])
+_sig("pn_ref_load_dev", _int, [_P, _P, _u64, _P, _PP])
+_sig("pn_ref_free", None, [_P])
+_sig("pn_ref_length", _u64, [_P])
+_sig("pn_index_build", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _int, _PP])
+_sig("pn_index_build_dev", _int, [_P, _P, _P, _u32, _u64, _int, _int, _P, _PP])
+_sig("pn_index_free", None, [_P])
+_sig("pn_index_get_info", _int, [_P, ctypes.POINTER(_IndexInfo)])
+_sig("pn_index_export", _int, [_P, _P, _P, _P, _P])
+_sig("pn_map", _int, [_P, _P, _P, _int, _P, _int, _PP, ctypes.POINTER(_u64)])
+_sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_u64), _P])
+_sig("pn_hits_free", None, [_P])
+_sig("pn_filter", _int, [_P, _P, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
+_sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
+
+EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
+            "pn_ctx_set_timing", "pn_ctx_get_stats", "pn_ref_load",
+            "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_index_build",
+            "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
+            "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate"]
+
+
+def _check(st: int, where: str):
+    if st != PN_OK:
+        raise PnError(st, where)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def _take_hits(ptr, n: int, dtype) -> np.ndarray:
+    try:
+        if n == 0:
+            return np.zeros(0, dtype=dtype)
+        return np.frombuffer(ctypes.string_at(ptr, n * dtype.itemsize), dtype=dtype).copy()
+    finally:
+        _lib.pn_hits_free(ptr)
+
+
+def pn_strerror(status: int) -> str:
+    return _lib.pn_strerror(status).decode()
+
+
+def pn_ctx_create(device: int = 0):
+    h = ctypes.c_void_p()
+    _check(_lib.pn_ctx_create(device, ctypes.byref(h)), "pn_ctx_create")
+    return h
+
+
+def pn_ctx_destroy(ctx) -> None:
+    _lib.pn_ctx_destroy(ctx)
+
+
+def pn_ctx_stream(ctx) -> int:
+    s = ctypes.c_void_p()
+    _check(_lib.pn_ctx_stream(ctx, ctypes.byref(s)), "pn_ctx_stream")
+    return s.value or 0
+
+
+def pn_ctx_set_timing(ctx, enable: bool) -> None:
+    _check(_lib.pn_ctx_set_timing(ctx, int(bool(enable))), "pn_ctx_set_timing")
+
+
+def pn_ctx_get_stats(ctx, reset: bool = False) -> dict:
+    st = _Stats()
+    _check(_lib.pn_ctx_get_stats(ctx, ctypes.byref(st), int(bool(reset))), "pn_ctx_get_stats")
+    out = {"ms": {n: st.ms[i] for i, n in enumerate(STAGES)},
+           "launches": {n: int(st.launches[i]) for i, n in enumerate(STAGES)}}
+    for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits"):
+        out[f] = int(getattr(st, f))
+    return out
+
+
+def pn_ref_load(ctx, seq: bytes):
+    h = ctypes.c_void_p()
+    _check(_lib.pn_ref_load(ctx, seq, len(seq), ctypes.byref(h)), "pn_ref_load")
+    return h
+
+
+def pn_ref_load_dev(ctx, d_seq, stream=None):
+    """d_seq: uint8 torch tensor on the GPU holding ASCII letters."""
+    h = ctypes.c_void_p()
+    _check(_lib.pn_ref_load_dev(ctx, ctypes.c_void_p(d_seq.data_ptr()), d_seq.numel(),
+                                _stream_ptr(stream), ctypes.byref(h)), "pn_ref_load_dev")
+    return h
+
+
+def pn_ref_free(ref) -> None:
+    _lib.pn_ref_free(ref)
+
+
+def pn_ref_length(ref) -> int:
+    return int(_lib.pn_ref_length(ref))
+
+
+def pn_index_build(ctx, reads: bytes, offsets: np.ndarray, q: int, w: int = 64):
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    h = ctypes.c_void_p()
+    _check(_lib.pn_index_build(ctx, reads, _ptr(offsets), len(offsets) - 1, q, w, ctypes.byref(h)),
+           "pn_index_build")
+    return h
+
+
+def pn_index_build_dev(ctx, d_reads, d_offsets, q: int, w: int = 64, stream=None, n_bases=None):
+    """d_reads: uint8 ASCII tensor; d_offsets: int64/uint64 tensor of n+1 offsets."""
+    n_reads = d_offsets.numel() - 1
+    if n_bases is None:
+        n_bases = d_reads.numel()
+    h = ctypes.c_void_p()
+    _check(_lib.pn_index_build_dev(ctx, ctypes.c_void_p(d_reads.data_ptr()),
+                                   ctypes.c_void_p(d_offsets.data_ptr()), n_reads, n_bases, q, w,
+                                   _stream_ptr(stream), ctypes.byref(h)), "pn_index_build_dev")
+    return h
+
+
+def pn_index_free(idx) -> None:
+    _lib.pn_index_free(idx)
+
+
+def pn_index_get_info(idx) -> dict:
+    info = _IndexInfo()
+    _check(_lib.pn_index_get_info(idx, ctypes.byref(info)), "pn_index_get_info")
+    return {f: getattr(info, f) for f, _ in _IndexInfo._fields_ if f != "reserved"}
+
+
+def pn_index_export(idx):
+    """(I, S, S', O) as numpy arrays."""
+    info = pn_index_get_info(idx)
+    I = np.empty(info["n_groups"], dtype=np.uint64 if info["w"] == 64 else np.uint32)
+    S = np.empty(info["n_groups"] + 1, dtype=np.uint32)
+    Sp = np.empty(info["n_distinct"] + 1, dtype=np.uint32)
+    O = np.empty(max(info["n_qgrams"], 1), dtype=np.uint32)
+    _check(_lib.pn_index_export(idx, _ptr(I), _ptr(S), _ptr(Sp), _ptr(O)), "pn_index_export")
+    return I, S, Sp, O[:info["n_qgrams"]]
+
+
+def _k_args(k, n_reads):
+    if k is None or not np.isscalar(k):
+        arr = np.ascontiguousarray(k, dtype=np.uint8)
+        assert len(arr) == n_reads
+        return -1, arr
+    return int(k), None
+
+
+def pn_map(ctx, ref, idx, k, mode: int = PN_ALL_HITS) -> np.ndarray:
+    """k: int for all reads, or a uint8 array of per-read k."""
+    n_reads = pn_index_get_info(idx)["n_reads"]
+    kg, karr = _k_args(k, n_reads)
+    hp = ctypes.c_void_p()
+    n = _u64()
+    _check(_lib.pn_map(ctx, ref, idx, kg, None if karr is None else _ptr(karr), mode,
+                       ctypes.byref(hp), ctypes.byref(n)), "pn_map")
+    return _take_hits(hp, n.value, HIT_DTYPE)
+
+
+def pn_map_dev(ctx, ref, idx, k, d_out, mode: int = PN_ALL_HITS, stream=None, d_k=None) -> int:
+    """Writes hits into d_out (uint8/int32 torch tensor of >= 12*capacity
+    bytes); returns the hit count.  Raises PnError(PN_ETRUNC) if it
+    overflowed (the required count is in .required)."""
+    cap = d_out.numel() * d_out.element_size() // HIT_DTYPE.itemsize
+    n = _u64()
+    kg = -1 if d_k is not None else int(k)
+    st = _lib.pn_map_dev(ctx, ref, idx, kg, None if d_k is None else ctypes.c_void_p(d_k.data_ptr()),
+                         mode, ctypes.c_void_p(d_out.data_ptr()), cap, ctypes.byref(n),
+                         _stream_ptr(stream))
+    if st == PN_ETRUNC:
+        e = PnError(st, "pn_map_dev")
+        e.required = n.value
+        raise e
+    _check(st, "pn_map_dev")
+    return n.value
+
+
+def pn_filter(ctx, ref, idx):
+    """(candidates structured array, number of occurrence pairs before pruning)."""
+    cp = ctypes.c_void_p()
+    n = _u64()
+    seeds = _u64()
+    _check(_lib.pn_filter(ctx, ref, idx, ctypes.byref(cp), ctypes.byref(n), ctypes.byref(seeds)),
+           "pn_filter")
+    return _take_hits(cp, n.value, CAND_DTYPE), seeds.value
+
+
+def pn_validate(ctx, ref, idx, cands: np.ndarray, k) -> np.ndarray:
+    cands = np.ascontiguousarray(cands, dtype=CAND_DTYPE)
+    n_reads = pn_index_get_info(idx)["n_reads"]
+    kg, karr = _k_args(k, n_reads)
+    hp = ctypes.c_void_p()
+    n = _u64()
+    _check(_lib.pn_validate(ctx, ref, idx, _ptr(cands), len(cands), kg,
+                            None if karr is None else _ptr(karr), ctypes.byref(hp),
+                            ctypes.byref(n)), "pn_validate")
+    return _take_hits(hp, n.value, HIT_DTYPE)
+
+
+def make_candidates(read_id, strand, diagonal) -> np.ndarray:
+    c = np.zeros(len(read_id), dtype=CAND_DTYPE)
+    c["read_id"] = read_id
+    c["strand"] = strand
+    c["diagonal"] = diagonal
+    return c
+
+
+class Session:
+    """Owns a context and frees handles in order (convenience for tests)."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = pn_ctx_create(device)
+        self._refs, self._idx = [], []
+
+    def ref(self, seq: bytes):
+        r = pn_ref_load(self.ctx, seq)
+        self._refs.append(r)
+        return r
+
+    def index(self, reads: bytes, offsets, q: int, w: int = 64):
+        x = pn_index_build(self.ctx, reads, offsets, q, w)
+        self._idx.append(x)
+        return x
+
+    def close(self):
+        for x in self._idx:
+            pn_index_free(x)
+        for r in self._refs:
+            pn_ref_free(r)
+        self._idx, self._refs = [], []
+        if self.ctx is not None:
+            pn_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,366 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Integer work throughout, so every comparison is exact: index arrays,
+candidate sets, per-candidate band values and final hit lists must be
+identical.  Where several orders are correct (entries inside one q-gram's
+slice of O, the order of candidates) the unique content is compared and the
+rest is checked for validity.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_1706_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pn():
+    from paper_1403_1706_amd import peanut
+    return peanut
+
+
+@pytest.fixture(scope="module")
+def sess(pn):
+    s = pn.Session(0)
+    yield s
+    s.close()
+
+
+def fields(h):
+    return np.stack([h["read_id"].astype(np.int64), h["strand"].astype(np.int64),
+                     h["end_pos"].astype(np.int64), h["errors"].astype(np.int64)], axis=1)
+
+
+def assert_hits_equal(gpu, orc):
+    a, b = fields(gpu), fields(orc)
+    assert a.shape == b.shape, f"{len(a)} GPU hits vs {len(b)} oracle hits"
+    if len(a):
+        bad = np.nonzero((a != b).any(axis=1))[0]
+        assert len(bad) == 0, f"first mismatch at {bad[0]}: gpu {a[bad[0]]} oracle {b[bad[0]]}"
+
+
+def map_both(pn, sess, w, k=None, q=None, modes=(0, 1), wbits=64):
+    q = q or w.q
+    k = w.k_per_read if k is None else k
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, q, wbits)
+    for mode in modes:
+        say(f"map {w.name} n_reads={w.n_reads} L={len(w.ref)} q={q} mode={mode}")
+        g = pn.pn_map(sess.ctx, ref, idx, k, mode)
+        o = oracle.map_filtered(w.ref, w.reads, w.offsets, q, k, best=bool(mode))
+        assert_hits_equal(g, o)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: the q-group index equals the conventional index's content
+
+
+def decode_O(O):
+    return (O >> 29).astype(np.int64), ((O >> 8) & ((1 << 21) - 1)).astype(np.int64), \
+        (O & 0xff).astype(np.int64)
+
+
+@pytest.mark.parametrize("wbits", [32, 64])
+@pytest.mark.parametrize("case", ["tiny", "mixed"])
+def test_index_arrays_match_definition(pn, sess, wbits, case):
+    if case == "tiny":
+        w = synth.make("tiny", n_reads=3000)
+        q = 10
+    else:
+        w = synth.make("mixed", scale=0.001)
+        q = 12
+    say(f"index {case} w={wbits} q={q} reads={w.n_reads}")
+    idx = sess.index(w.reads, w.offsets, q, wbits)
+    I, S, Sp, O = pn.pn_index_export(idx)
+    A, Pr, Po = oracle.qgram_index(w.reads, w.offsets, q)
+    I0, S0, Sp0 = oracle.qgroup_from_conventional(A, q, wbits)
+    assert np.array_equal(I.astype(np.uint64), I0)
+    assert np.array_equal(S.astype(np.int64), S0)
+    assert np.array_equal(Sp.astype(np.int64), Sp0)
+    info = pn.pn_index_get_info(idx)
+    assert info["n_qgrams"] == len(Pr) == int(A[-1]) and info["n_distinct"] == len(Sp0) - 1
+    # O slice by slice equals P bucket by bucket as multisets of (read, offset)
+    cls, r, o = decode_O(O)
+    bucket = np.repeat(np.arange(len(Sp) - 1), np.diff(Sp.astype(np.int64)))
+    present = np.nonzero(A[1:] > A[:-1])[0]
+    bucket0 = np.repeat(np.arange(len(present)), (A[present + 1] - A[present]).astype(np.int64))
+    g = np.lexsort((o, r, bucket))
+    g0 = np.lexsort((Po, Pr, bucket0))
+    assert np.array_equal(bucket[g], bucket0[g0])
+    assert np.array_equal(r[g], Pr[g0].astype(np.int64))
+    assert np.array_equal(o[g], Po[g0].astype(np.int64))
+    # the class field is the letter before the q-gram (4 at offset 0)
+    codes = oracle.encode(w.reads)
+    prev = np.where(o == 0, 4, codes[np.maximum(w.offsets[r].astype(np.int64) + o - 1, 0)])
+    assert np.array_equal(cls, prev)
+    # inside a slice entries are grouped by class; short slices fully ascending
+    same = bucket[1:] == bucket[:-1]
+    assert np.all(cls[1:][same] >= cls[:-1][same])
+    sizes = np.diff(Sp.astype(np.int64))
+    short = same & (sizes[bucket[1:]] <= 32)
+    assert np.all(O[1:][short] > O[:-1][short])
+
+
+def test_index_w32_equals_w64(pn, sess):
+    w = synth.make("tiny", n_reads=2000)
+    a = pn.pn_index_export(sess.index(w.reads, w.offsets, 10, 32))
+    b = pn.pn_index_export(sess.index(w.reads, w.offsets, 10, 64))
+    assert np.array_equal(a[2], b[2])  # S' does not depend on w
+    for Sp, O in ((a[2], a[3]), (b[2], b[3])):
+        bucket = np.repeat(np.arange(len(Sp) - 1), np.diff(Sp.astype(np.int64)))
+        assert np.all(np.diff(bucket) >= 0)
+    assert np.array_equal(np.sort(a[3]), np.sort(b[3]))
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 and validation on their own
+
+
+def cand_set(r, s, d):
+    key = (np.asarray(r, np.int64) << 40) | (np.asarray(s, np.int64) << 39) | (np.asarray(d, np.int64) + (1 << 20))
+    return np.unique(key)
+
+
+@pytest.mark.parametrize("case", ["tiny", "repeat"])
+def test_filter_candidates_match_oracle(pn, sess, case):
+    if case == "tiny":
+        w = synth.make("tiny", scale=0.1)
+    else:
+        w = synth.make("repeat", scale=0.002)
+    say(f"filter {case} L={len(w.ref)} reads={w.n_reads}")
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, w.q)
+    c, n_seeds = pn.pn_filter(sess.ctx, ref, idx)
+    r0, s0, d0 = oracle.candidates(w.ref, w.reads, w.offsets, w.q)
+    # every occurrence pair is seen; the candidates keep every (read, strand, diagonal)
+    assert n_seeds == len(r0)
+    assert np.array_equal(cand_set(c["read_id"], c["strand"], c["diagonal"]), cand_set(r0, s0, d0))
+    assert len(c) <= len(r0)
+    key = (c["read_id"].astype(np.int64) << 40) | (c["strand"].astype(np.int64) << 39) | \
+        (c["diagonal"] + (1 << 20))
+    assert np.all(np.diff(key) >= 0)  # sorted as documented
+
+
+def test_validate_matches_scalar_band(pn, sess):
+    w = synth.make("mixed", scale=0.0005)
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, w.q)
+    r0, s0, d0 = oracle.candidates(w.ref, w.reads, w.offsets, w.q)
+    # one candidate per read (first), so records map back to their candidate
+    _, first = np.unique(r0, return_index=True)
+    rng = np.random.default_rng(0)
+    pick = rng.choice(first, size=min(400, len(first)), replace=False)
+    # include diagonals hanging over both ends of the reference
+    cands = pn.make_candidates(r0[pick], s0[pick], d0[pick])
+    extra_r = np.setdiff1d(np.arange(w.n_reads), r0[pick])[:4]
+    L = len(w.ref)
+    extra = pn.make_candidates(extra_r, [0, 1, 0, 1][:len(extra_r)],
+                               [-7, -3, L - 60, L - 2][:len(extra_r)])
+    cands = np.concatenate([cands, extra])
+    got = pn.pn_validate(sess.ctx, ref, idx, cands, w.k_per_read)
+    texts = [oracle.encode(w.ref), oracle.reverse_complement(oracle.encode(w.ref))]
+    codes = oracle.encode(w.reads)
+    expect = []
+    for c in cands:
+        r, s, d = int(c["read_id"]), int(c["strand"]), int(c["diagonal"])
+        x = codes[int(w.offsets[r]):int(w.offsets[r + 1])]
+        for e, v in oracle.banded(texts[s], x, d, int(w.k_per_read[r])):
+            expect.append((r, s, e, v))
+    expect.sort()
+    assert [tuple(t) for t in fields(got).tolist()] == expect
+
+
+# ---------------------------------------------------------------------------
+# whole path
+
+
+def test_map_brute_subset_equals_definition(pn, sess):
+    w = synth.tiny_brute_subset()
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, 10)
+    for mode in (0, 1):
+        g = pn.pn_map(sess.ctx, ref, idx, 5, mode)
+        assert_hits_equal(g, oracle.map_sellers(w.ref, w.reads, w.offsets, 5, best=bool(mode)))
+
+
+def test_map_tiny_full(pn, sess):
+    """1 Mbp i.i.d. reference, 10,000 reads x 100, q = 10, k = 5."""
+    map_both(pn, sess, synth.make("tiny"), k=5)
+
+
+def test_map_tiny_w32_and_q_invariance(pn, sess):
+    w = synth.make("tiny", scale=0.2)
+    base = map_both(pn, sess, w, k=5, q=10, modes=(0,), wbits=32)
+    for q in (8, 9, 11):
+        idx = sess.index(w.reads, w.offsets, q)
+        ref = sess.ref(w.ref)
+        assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, 5, 0), base)
+
+
+def test_map_repeat_small(pn, sess):
+    map_both(pn, sess, synth.make("repeat", scale=0.01))
+
+
+def test_map_mixed_lengths(pn, sess):
+    map_both(pn, sess, synth.make("mixed", scale=0.002))
+
+
+def test_edge_cases(pn, sess):
+    rng = np.random.default_rng(42)
+    L = 6000
+    refc = rng.integers(0, 4, L).astype(np.uint8)
+    refc[3000:3040] = 0  # homopolymer run
+    ref = synth.ALPHABET[refc].tobytes()
+    comp = bytes.maketrans(b"ACGT", b"TGCA")
+
+    def rc(x):
+        return x.translate(comp)[::-1]
+    reads = [
+        rng.choice(list(b"ACGT"), 3).astype(np.uint8).tobytes() + ref[:97],   # hangs off the start
+        ref[-95:] + b"GATTA",                                                    # hangs off the end
+        ref[:100],                                                               # reference start
+        ref[-100:],                                                              # reference end
+        b"A" * 100,                                                              # homopolymer read
+        ref[2980:3080],                                                          # covers the run
+        ref[1000:1030] + rc(ref[1000:1030]),                                     # own reverse complement
+        ref[500:600], ref[500:600],                                              # duplicates
+        ref[4000:4060],                                                          # n = q (k + 1)
+        ref[4500:4600].lower(),                                                  # lower case
+        rc(ref[5200:5300]),                                                      # strand 1
+    ]
+    buf = b"".join(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    np.cumsum([len(x) for x in reads], out=offs[1:])
+    q, k = 10, 5
+    refh = sess.ref(ref)
+    idx = sess.index(buf, offs, q)
+    for mode in (0, 1):
+        g = pn.pn_map(sess.ctx, refh, idx, k, mode)
+        assert_hits_equal(g, oracle.map_sellers(ref, buf, offs, k, best=bool(mode)))
+        assert_hits_equal(g, oracle.map_filtered(ref, buf, offs, q, k, best=bool(mode)))
+    # the whole reference upper-cased and mixed-case give the same hits
+    refl = sess.ref(ref[:3000].lower() + ref[3000:])
+    assert_hits_equal(pn.pn_map(sess.ctx, refl, idx, k, 0), pn.pn_map(sess.ctx, refh, idx, k, 0))
+
+
+def test_empty_and_tiny_batches(pn, sess):
+    w = synth.make("tiny", scale=0.01)
+    ref = sess.ref(w.ref)
+    idx = sess.index(b"", np.zeros(1, np.uint64), 10)
+    assert len(pn.pn_map(sess.ctx, ref, idx, 5, 0)) == 0
+    one = w.subset([0])
+    idx = sess.index(one.reads, one.offsets, 10)
+    assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, 5, 0),
+                      oracle.map_filtered(w.ref, one.reads, one.offsets, 10, 5))
+
+
+def test_error_statuses(pn, sess):
+    w = synth.make("tiny", scale=0.01)
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, 10)
+    with pytest.raises(pn.PnError) as e:
+        pn.pn_map(sess.ctx, ref, idx, 9, 0)  # (9+1)*10 > 100
+    assert e.value.status == pn.PN_ELEMMA
+    with pytest.raises(pn.PnError) as e:
+        pn.pn_map(sess.ctx, ref, idx, 16, 0)
+    assert e.value.status == pn.PN_EINVAL
+    bad = bytearray(w.reads)
+    bad[50] = ord("N")
+    with pytest.raises(pn.PnError) as e:
+        sess.index(bytes(bad), w.offsets, 10)
+    assert e.value.status == pn.PN_EALPHABET
+    with pytest.raises(pn.PnError) as e:
+        sess.ref(b"ACGTNACGT")
+    assert e.value.status == pn.PN_EALPHABET
+    with pytest.raises(pn.PnError) as e:
+        sess.index(b"A" * 300, np.array([0, 300], np.uint64), 10)
+    assert e.value.status == pn.PN_EINVAL
+    with pytest.raises(pn.PnError) as e:
+        sess.index(w.reads, w.offsets, 16)
+    assert e.value.status == pn.PN_EINVAL
+    # the context still works after errors
+    assert len(pn.pn_map(sess.ctx, ref, idx, 5, 0)) > 0
+
+
+def test_device_entry_points_and_truncation(pn, sess):
+    import torch
+    w = synth.make("tiny", scale=0.05)
+    ref = sess.ref(w.ref)
+    host = pn.pn_map(sess.ctx, ref, sess.index(w.reads, w.offsets, 10), 5, 0)
+    dev = torch.device("cuda:0")
+    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    d_k = torch.full((w.n_reads,), 5, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    idx = pn.pn_index_build_dev(sess.ctx, d_reads, d_offs, 10, 64)
+    try:
+        out = torch.zeros(len(host) * 12 + 64, dtype=torch.uint8, device=dev)
+        n = pn.pn_map_dev(sess.ctx, ref, idx, 5, out, 0)
+        got = np.frombuffer(out.cpu().numpy().tobytes()[:n * 12], dtype=pn.HIT_DTYPE)
+        assert_hits_equal(got, host)
+        n2 = pn.pn_map_dev(sess.ctx, ref, idx, -1, out, 0, d_k=d_k)
+        assert n2 == n
+        small = torch.zeros(12 * 10, dtype=torch.uint8, device=dev)
+        with pytest.raises(pn.PnError) as e:
+            pn.pn_map_dev(sess.ctx, ref, idx, 5, small, 0)
+        assert e.value.status == pn.PN_ETRUNC and e.value.required == n
+        got10 = np.frombuffer(small.cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
+        assert_hits_equal(got10, host[:10])
+    finally:
+        pn.pn_index_free(idx)
+
+
+def test_repeat_runs_are_identical(pn, sess):
+    w = synth.make("repeat", scale=0.003)
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, 12)
+    a = pn.pn_map(sess.ctx, ref, idx, 5, 0)
+    b = pn.pn_map(sess.ctx, ref, idx, 5, 0)
+    assert a.tobytes() == b.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# full size: 100 Mbp repeat reference, 1 M reads, the benchmark's launch path
+
+
+def test_full_size_repeat_sampled(pn, sess):
+    import torch
+    say("generating the 100 Mbp / 1 M read workload")
+    w = synth.make("repeat")
+    ref = sess.ref(w.ref)
+    dev = torch.device("cuda:0")
+    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12345)
+    sample = np.sort(rng.choice(w.n_reads, 1000, replace=False))
+    sub = w.subset(sample)
+    idx = pn.pn_index_build_dev(sess.ctx, d_reads, d_offs, 12, 64)
+    try:
+        out = torch.zeros(12 * 40_000_000, dtype=torch.uint8, device=dev)
+        for mode in (0, 1):
+            say(f"full-size map mode={mode}")
+            n = pn.pn_map_dev(sess.ctx, ref, idx, 5, out, mode)
+            got = np.frombuffer(out[:n * 12].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
+            keep = np.isin(got["read_id"], sample)
+            mine = got[keep].copy()
+            mine["read_id"] = np.searchsorted(sample, mine["read_id"])
+            say(f"oracle on {len(sample)} sampled reads")
+            orc = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, 5, best=bool(mode))
+            assert_hits_equal(mine, orc)
+            # properties at full size: sorted, unique, errors within budget
+            key = (got["read_id"].astype(np.int64) << 33) | (got["strand"].astype(np.int64) << 32) | \
+                got["end_pos"].astype(np.int64)
+            assert np.all(np.diff(key) > 0) and got["errors"].max() <= 5
+            say(f"mode={mode}: {n} hits, {len(np.unique(got['read_id']))} reads mapped")
+    finally:
+        pn.pn_index_free(idx)

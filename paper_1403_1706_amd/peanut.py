@@ -13,6 +13,10 @@ import ctypes
 import os
 
 import numpy as np
+# PyTorch bundles its own HIP runtime (same soname as /opt/rocm's).  Loading
+# it first makes libpeanut bind to that one, so torch tensors and this
+# library share a single HIP runtime in the process.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpeanut.so")

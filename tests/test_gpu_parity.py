@@ -268,7 +268,7 @@ def test_error_statuses(pn, sess):
     ref = sess.ref(w.ref)
     idx = sess.index(w.reads, w.offsets, 10)
     with pytest.raises(pn.PnError) as e:
-        pn.pn_map(sess.ctx, ref, idx, 9, 0)  # (9+1)*10 > 100
+        pn.pn_map(sess.ctx, ref, idx, 10, 0)  # (10+1)*10 > 100
     assert e.value.status == pn.PN_ELEMMA
     with pytest.raises(pn.PnError) as e:
         pn.pn_map(sess.ctx, ref, idx, 16, 0)

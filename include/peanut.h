@@ -177,12 +177,16 @@ int pn_index_get_info(const pn_index *idx, pn_index_info *out);
 
 /* Copy the index arrays to host buffers sized from pn_index_get_info:
  * I: n_groups words of w bits (uint32 for w = 32, uint64 for w = 64);
- * S: n_groups + 1 uint32; S': n_distinct + 1 uint32; O: n_qgrams uint32.
- * An O entry packs a position as (cls << 29) | (read << 8) | offset, where
- * cls is the base code of the letter before the q-gram in its read (4 when
- * offset == 0).  Inside each q-gram's slice of O entries are ascending.
- * Any pointer may be NULL to skip that array. */
-int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint32_t *O);
+ * S: n_groups + 1 uint32; S': n_distinct + 1 uint32; O: n_qgrams uint64.
+ * An O entry holds one occurrence (read r, offset o) of its q-gram: the high
+ * 32 bits are (cls << 29) | (r << 8) | o, where cls is the code of the
+ * letter before the q-gram in its read (4 when o == 0); the low 32 bits are
+ * (next4 << 24) | (nav << 21): the nav = min(4, n_r - o - q) letters after
+ * the q-gram, first letter in the top bits (unused letters 0).  Inside each
+ * q-gram's slice of O, entries are ordered by value when the slice has at
+ * most 32 entries and grouped by cls otherwise.  Any pointer may be NULL to
+ * skip that array. */
+int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint64_t *O);
 
 /* ---- mapping ----------------------------------------------------------- */
 
@@ -202,15 +206,23 @@ void pn_hits_free(pn_hit *hits);
 
 /* ---- the two steps on their own (for inspection) ----------------------- */
 
-/* Filtration only (Algorithm 2, both strands).  Returns the candidates the
- * mapper verifies: for every reference q-gram occurrence pair (p, o) whose
- * left neighbours differ (or p == 0 or o == 0) — an exact match that
- * extends to the left yields the same diagonal from position p-1 — one
- * (read, strand, d = p - o), sorted by (read, strand, diagonal), duplicates
- * kept.  *n_seeds receives the number of occurrence pairs before that
- * pruning (sum over positions of k_end - k_start).  Free with pn_hits_free. */
-int pn_filter(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, pn_candidate **cands,
-              uint64_t *n_cands, uint64_t *n_seeds);
+/* Filtration only (Algorithm 2, both strands), with the error budget the
+ * mapping would use (k >= 0 for all reads, or k < 0 and host k_per_read).
+ * Returns the candidates pn_map verifies, each (read, strand, diagonal
+ * d = p - o) for an occurrence pair (reference position p, read offset o)
+ * of a q-gram, sorted by (read, strand, diagonal), duplicates kept.  Pairs
+ * are left out only when the mapping provably does not need them, so the
+ * hit list is unchanged (Section 2.2, q-gram lemma): a pair whose left
+ * neighbours agree (the pair one step up-left is on the same diagonal), the
+ * low-complexity q-grams (period <= 2) of a read with more than k_r q other
+ * q-grams, and a pair whose exact run along its diagonal is shorter than the
+ * run every alignment with <= k_r errors must contain.  *n_seeds (if not
+ * NULL) receives the number of all occurrence pairs (sum over positions of
+ * k_end - k_start).  PN_ELEMMA / PN_EINVAL as for pn_map.  Free with
+ * pn_hits_free. */
+int pn_filter(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, int k,
+              const uint8_t *k_per_read, pn_candidate **cands, uint64_t *n_cands,
+              uint64_t *n_seeds);
 
 /* Validation only (Section 3.3): banded bit-parallel edit distance over
  * diagonals [d - k_r, d + k_r] for each given candidate; returns every

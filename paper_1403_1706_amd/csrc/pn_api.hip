@@ -32,7 +32,8 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kOutCount = 6,
     kBigCount = 7,
     kVerifyRows = 8,
-    kMiscWords = 10
+    kCandCount = 9,
+    kMiscWords = 12
 };
 
 struct PendingStage {
@@ -51,9 +52,9 @@ struct pn_ctx {
     uint64_t *misc = nullptr;             // device scratch words (MiscSlot)
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
-    Buf cands, keys, keys_tmp, sort_temp, flags, pos, partials, minv, block_counts,
-        block_offsets, out_hits;
-    uint64_t cand_chunk = 1ull << 27;  // candidates verified per launch (at most)
+    Buf cands, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
+        out_hits;
+    uint64_t cand_cap = 1ull << 24;  // candidate buffer capacity (grows on demand)
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -78,7 +79,11 @@ struct pn_index {
     uint64_t *offsets;
     uint2 *rplanes;
     void *I;
-    uint32_t *S, *Sp, *O;
+    uint32_t *S, *Sp;
+    unsigned long long *O;
+    uint32_t *lcinfo;
+    uint32_t lc_size[pn::kLcPatterns];  // slice sizes of the low-complexity q-grams
+    uint64_t lc_total;
 };
 
 namespace {
@@ -266,6 +271,7 @@ PnIndexDev index_desc(const pn_index *x) {
     d.S = x->S;
     d.Sp = x->Sp;
     d.O = x->O;
+    d.lcinfo = x->lcinfo;
     d.n_reads = x->n_reads;
     d.max_len = (uint32_t)x->max_len;
     d.q = x->q;
@@ -283,6 +289,7 @@ void free_index_arrays(pn_index *x) {
     dfree(c, x->S);
     dfree(c, x->Sp);
     dfree(c, x->O);
+    dfree(c, x->lcinfo);
 }
 
 }  // namespace
@@ -476,13 +483,16 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_qgrams = c->hmisc[kStatT];
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
-    uint32_t *cnt = nullptr, *big = nullptr, *tmp = nullptr, *partials = nullptr;
+    uint32_t *cnt = nullptr, *big = nullptr, *partials = nullptr, *lcs = nullptr;
+    unsigned long long *tmp = nullptr;
     const uint64_t n_big_max = T / 33 + 1;
     s = dalloc_t(c, (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
     if (!s) s = dalloc(c, x->n_groups * (w / 8), &x->I);
     if (!s) s = dalloc_t(c, x->n_groups + 1, &x->S);
     if (!s) s = dalloc_t(c, U + 1, &x->Sp);
     if (!s) s = dalloc_t(c, T + 1, &x->O);
+    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &x->lcinfo);
+    if (!s) s = dalloc_t(c, pn::kLcPatterns, &lcs);
     if (!s) s = dalloc_t(c, U + 1, &cnt);
     if (!s) s = dalloc_t(c, n_big_max, &big);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
@@ -492,7 +502,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         PnIndexDev ix = index_desc(x);
         tok = stage_begin(c, st, PN_STAGE_INGEST);
         pn::launch_read_planes(x->packed, x->offsets, n_reads, x->rplanes, st);
-        stage_end(c, st, tok, 1);
+        pn::launch_read_lc(ix, x->lcinfo, st);
+        stage_end(c, st, tok, 2);
         tok = stage_begin(c, st, PN_STAGE_INDEX);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
         pn::launch_qgram_bitmap(ix, x->I, st);                                // step 1
@@ -505,12 +516,17 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         pn::launch_bucket_sort(x->Sp, U, x->S + x->n_groups, x->O, big,
                                (uint32_t *)&c->misc[kBigCount], st);
         stage_end(c, st, tok, 14);
+        pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
         e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(x->lc_size, lcs, sizeof(x->lc_size), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) s = read_misc(c, st);
         else s = map_err(e);
         if (!s) {
             x->n_distinct = n_distinct;
+            x->lc_total = 0;
+            for (int i = 0; i < pn::kLcPatterns; i++) x->lc_total += x->lc_size[i];
             const uint32_t n_big = (uint32_t)c->hmisc[kBigCount];
             tok = stage_begin(c, st, PN_STAGE_INDEX);
             pn::launch_bucket_sort_big(x->Sp, x->O, tmp, big, n_big, st);
@@ -524,6 +540,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     dfree(c, big);
     dfree(c, tmp);
     dfree(c, partials);
+    dfree(c, lcs);
     if (s) {
         free_index_arrays(x);
         delete x;
@@ -579,7 +596,7 @@ int pn_index_get_info(const pn_index *x, pn_index_info *out) {
     return PN_OK;
 }
 
-int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint32_t *O) {
+int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint64_t *O) {
     if (!x) return PN_EINVAL;
     pn_ctx *c = x->ctx;
     DeviceGuard g(c->device);
@@ -588,7 +605,7 @@ int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint3
     if (S) PN_TRY(hipMemcpyAsync(S, x->S, (x->n_groups + 1) * 4, hipMemcpyDeviceToHost, st));
     if (Sp) PN_TRY(hipMemcpyAsync(Sp, x->Sp, (x->n_distinct + 1) * 4, hipMemcpyDeviceToHost, st));
     if (O && x->n_qgrams)
-        PN_TRY(hipMemcpyAsync(O, x->O, x->n_qgrams * 4, hipMemcpyDeviceToHost, st));
+        PN_TRY(hipMemcpyAsync(O, x->O, x->n_qgrams * 8, hipMemcpyDeviceToHost, st));
     PN_TRY(hipStreamSynchronize(st));
     return PN_OK;
 }
@@ -600,114 +617,96 @@ int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint3
 
 namespace {
 
-struct FilterPlan {
-    uint64_t n_blocks = 0;
-    std::vector<uint64_t> offs;  // exclusive prefix of block counts, n_blocks + 1
-    uint64_t n_seeds = 0;
-};
+int key_ebits(uint64_t L) { return std::max(1, bitlen(L - 1)); }
+int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 
-// count pass of Algorithm 2 (plus the k / lemma check) and the host-side
-// cumulative sum over block totals
-int filter_plan(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
-                hipStream_t st, FilterPlan &plan, bool check_k) {
-    const uint64_t L = ref->L;
-    const uint64_t npos = L >= (uint64_t)x->q ? L - x->q + 1 : 0;
-    plan.n_blocks = (npos + pn::kFilterBlockPos - 1) / pn::kFilterBlockPos;
-    PN_CHECK(ensure(c, c->block_counts, (plan.n_blocks + 1) * 4));
+// per-read seed rules (with the k / lemma check) and the low-complexity side
+// lists; synchronises once to report a bad k or a lemma violation
+int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, hipStream_t st) {
+    PN_CHECK(ensure(c, c->rinfo, (uint64_t)x->n_reads + 1));
+    PN_CHECK(ensure(c, c->side, std::max<uint64_t>(x->lc_total, 1) * 8));
+    PN_CHECK(ensure(c, c->side_meta, 2 * pn::kLcPatterns * 4));
+    uint32_t starts[pn::kLcPatterns];
+    uint64_t at = 0;
+    for (int i = 0; i < pn::kLcPatterns; i++) {
+        starts[i] = (uint32_t)at;
+        at += x->lc_size[i];
+    }
     zero_misc(c, st);
-    if (check_k)
-        pn::launch_check_k(x->offsets, x->n_reads, x->q, kglob, d_k, (uint32_t *)&c->misc[kStatus],
-                           st);
-    PnRefDev rd = ref_desc(ref);
+    PN_TRY(hipMemcpyAsync(c->side_meta.p, starts, sizeof(starts), hipMemcpyHostToDevice, st));
     PnIndexDev ix = index_desc(x);
-    int tok = stage_begin(c, st, PN_STAGE_FILTER_COUNT);
-    if (x->n_qgrams)
-        pn::launch_filter_count(rd, ix, plan.n_blocks, (uint32_t *)c->block_counts.p,
-                                (unsigned long long *)&c->misc[kSeeds], st);
-    stage_end(c, st, tok, 1);
-    std::vector<uint32_t> counts(plan.n_blocks);
-    if (plan.n_blocks && x->n_qgrams)
-        PN_TRY(hipMemcpyAsync(counts.data(), c->block_counts.p, plan.n_blocks * 4,
-                              hipMemcpyDeviceToHost, st));
+    pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->rinfo.p, (uint32_t *)&c->misc[kStatus],
+                          st);
+    uint32_t *meta = (uint32_t *)c->side_meta.p;
+    if (x->n_reads)
+        pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
+                           meta + pn::kLcPatterns, st);
     PN_CHECK(read_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];
     if (status & 2u) return PN_EINVAL;
     if (status & 4u) return PN_ELEMMA;
-    plan.n_seeds = c->hmisc[kSeeds];
-    plan.offs.assign(plan.n_blocks + 1, 0);
-    for (uint64_t b = 0; b < plan.n_blocks; b++) plan.offs[b + 1] = plan.offs[b] + counts[b];
-    PN_CHECK(ensure(c, c->block_offsets, (plan.n_blocks + 1) * 8));
-    PN_TRY(hipMemcpyAsync(c->block_offsets.p, plan.offs.data(), (plan.n_blocks + 1) * 8,
-                          hipMemcpyHostToDevice, st));
     return PN_OK;
 }
 
-// consecutive block ranges whose candidates fit one verification launch
-std::vector<std::pair<uint64_t, uint64_t>> chunk_blocks(const FilterPlan &p, uint64_t cap) {
-    std::vector<std::pair<uint64_t, uint64_t>> out;
-    uint64_t b0 = 0;
-    while (b0 < p.n_blocks) {
-        uint64_t b1 = b0 + 1;
-        while (b1 < p.n_blocks && p.offs[b1 + 1] - p.offs[b0] <= cap) b1++;
-        out.emplace_back(b0, b1);
-        b0 = b1;
-    }
-    return out;
+void launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
+    const uint32_t *meta = (const uint32_t *)c->side_meta.p;
+    pn::FilterOut fo{(uint2 *)c->cands.p, (unsigned long long *)&c->misc[kCandCount],
+                     c->cand_cap, (unsigned long long *)&c->misc[kSeeds]};
+    int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
+    pn::launch_filter(ref_desc(ref), index_desc(x), (const uint8_t *)c->rinfo.p,
+                      (const unsigned long long *)c->side.p, meta, meta + pn::kLcPatterns, fo, st);
+    stage_end(c, st, tok, 1);
 }
 
-int key_ebits(uint64_t L) { return std::max(1, bitlen(L - 1)); }
-int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
-
 // filtration + validation; leaves the sorted record keys in c->keys and
-// their count in *n_rec
+// their count in *n_rec.  Capacities of the candidate and record buffers
+// grow (and the pass is repeated) when a run overflowed them.
 int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
                 hipStream_t st, uint64_t *n_rec) {
-    FilterPlan plan;
-    PN_CHECK(filter_plan(c, ref, x, kglob, d_k, st, plan, true));
+    PN_CHECK(prepare_rules(c, x, kglob, d_k, st));
     const int ebits = key_ebits(ref->L);
-    const auto chunks = chunk_blocks(plan, c->cand_chunk);
-    uint64_t biggest = 0;
-    for (auto &ch : chunks) biggest = std::max(biggest, plan.offs[ch.second] - plan.offs[ch.first]);
-    PN_CHECK(ensure(c, c->cands, std::max<uint64_t>(biggest, 1) * sizeof(uint2)));
-    uint64_t rec_cap = std::max<uint64_t>(c->keys.cap / 8, std::max<uint64_t>(1u << 20, 16ull * x->n_reads));
-    PnRefDev rd = ref_desc(ref);
-    PnIndexDev ix = index_desc(x);
+    uint64_t rec_cap =
+        std::max<uint64_t>(c->keys.cap / 8, std::max<uint64_t>(1u << 20, 16ull * x->n_reads));
     for (int attempt = 0; attempt < 8; attempt++) {
+        PN_CHECK(ensure(c, c->cands, c->cand_cap * sizeof(uint2)));
+        c->cand_cap = c->cands.cap / sizeof(uint2);
         PN_CHECK(ensure(c, c->keys, rec_cap * 8));
         rec_cap = c->keys.cap / 8;
+        pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
         pn::launch_fill_u32((uint32_t *)&c->misc[kRecCount], 2, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);  // rows + candidates
+        launch_filter_into(c, ref, x, st);
         pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
                          (unsigned long long *)&c->misc[kVerifyRows], rec_cap, ebits};
-        for (auto &ch : chunks) {
-            const uint64_t n = plan.offs[ch.second] - plan.offs[ch.first];
-            if (!n) continue;
-            int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
-            pn::launch_filter_emit(rd, ix, ch.first, ch.second,
-                                   (const uint64_t *)c->block_offsets.p, (uint2 *)c->cands.p, st);
-            stage_end(c, st, tok, 1);
-            tok = stage_begin(c, st, PN_STAGE_VERIFY);
-            pn::launch_verify(rd, ix, (const uint2 *)c->cands.p, n, kglob, d_k, vo, st);
-            stage_end(c, st, tok, 1);
-        }
+        int tok = stage_begin(c, st, PN_STAGE_VERIFY);
+        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p,
+                          (const unsigned long long *)&c->misc[kCandCount], c->cand_cap, kglob, d_k,
+                          vo, st);
+        stage_end(c, st, tok, 1);
         PN_CHECK(read_misc(c, st));
+        const uint64_t n_cand = c->hmisc[kCandCount];
         const uint64_t got = c->hmisc[kRecCount];
-        if (got <= rec_cap) {
-            *n_rec = got;
-            c->stats.n_seeds += plan.n_seeds;
-            c->stats.n_candidates += plan.offs.empty() ? 0 : plan.offs.back();
-            c->stats.verify_rows += c->hmisc[kVerifyRows];
-            c->stats.n_records += got;
-            const int bits = 6 + ebits + key_rbits(x->n_reads);
-            PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(got, 1) * 8));
-            PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(got)));
-            int tok = stage_begin(c, st, PN_STAGE_SORT);
-            pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
-                               got, bits, c->sort_temp.p, st);
-            stage_end(c, st, tok, 3 * ((bits + 7) / 8));
-            return PN_OK;
+        if (n_cand > c->cand_cap) {  // candidates overflowed: grow and run again
+            c->cand_cap = n_cand + n_cand / 4;
+            continue;
         }
-        rec_cap = got + got / 4;  // records overflowed: grow and verify again
+        if (got > rec_cap) {
+            rec_cap = got + got / 4;
+            continue;
+        }
+        *n_rec = got;
+        c->stats.n_seeds += c->hmisc[kSeeds];
+        c->stats.n_candidates += n_cand;
+        c->stats.verify_rows += c->hmisc[kVerifyRows];
+        c->stats.n_records += got;
+        const int bits = 6 + ebits + key_rbits(x->n_reads);
+        PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(got, 1) * 8));
+        PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(got)));
+        tok = stage_begin(c, st, PN_STAGE_SORT);
+        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
+                           got, bits, c->sort_temp.p, st);
+        stage_end(c, st, tok, 3 * ((bits + 7) / 8));
+        return PN_OK;
     }
     return PN_ENOMEM;
 }
@@ -804,47 +803,72 @@ int pn_map(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t
 
 void pn_hits_free(pn_hit *h) { std::free(h); }
 
-int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, pn_candidate **cands,
-              uint64_t *n_cands, uint64_t *n_seeds) {
-    if (!c || !ref || !x || !cands || !n_cands || ref->ctx != c || x->ctx != c) return PN_EINVAL;
+int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *kpr,
+              pn_candidate **cands, uint64_t *n_cands, uint64_t *n_seeds) {
+    PN_CHECK(check_map_args(c, ref, x, k, kpr, PN_ALL_HITS));
+    if (!cands || !n_cands) return PN_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t st = c->stream;
-    FilterPlan plan;
-    PN_CHECK(filter_plan(c, ref, x, 0, nullptr, st, plan, false));
-    const uint64_t n = plan.offs.empty() ? 0 : plan.offs.back();
-    PN_CHECK(ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2)));
-    PN_CHECK(ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8));
-    PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8));
-    PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(n)));
-    PN_CHECK(ensure(c, c->out_hits, std::max<uint64_t>(n, 1) * sizeof(pn_candidate)));
-    if (n) {
-        pn::launch_filter_emit(ref_desc(ref), index_desc(x), 0, plan.n_blocks,
-                               (const uint64_t *)c->block_offsets.p, (uint2 *)c->cands.p, st);
-        pn::launch_cand_keys((const uint2 *)c->cands.p, n, (unsigned long long *)c->keys.p, st);
-        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, n,
-                           33 + key_rbits(x->n_reads), c->sort_temp.p, st);
-        pn::launch_keys_to_cands((const unsigned long long *)c->keys.p, n, c->out_hits.p, st);
+    uint8_t *dk = nullptr;
+    if (k < 0 && x->n_reads) {
+        PN_CHECK(dalloc_t(c, x->n_reads, &dk));
+        hipError_t e = hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            dfree(c, dk);
+            return map_err(e);
+        }
     }
-    pn_candidate *h = (pn_candidate *)std::malloc(std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
-    if (!h) return PN_ENOMEM;
-    hipError_t e = n ? hipMemcpyAsync(h, c->out_hits.p, n * sizeof(pn_candidate),
-                                      hipMemcpyDeviceToHost, st)
-                     : hipSuccess;
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
+    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
+    uint64_t n = 0;
+    for (int attempt = 0; !s && attempt < 8; attempt++) {
+        s = ensure(c, c->cands, c->cand_cap * sizeof(uint2));
+        if (s) break;
+        c->cand_cap = c->cands.cap / sizeof(uint2);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kCandCount], 2, 0u, st);
+        launch_filter_into(c, ref, x, st);
+        s = read_misc(c, st);
+        if (s) break;
+        n = c->hmisc[kCandCount];
+        if (n <= c->cand_cap) break;
+        c->cand_cap = n + n / 4;
+        n = 0;
+    }
+    const uint64_t seeds = s ? 0 : c->hmisc[kSeeds];
+    if (!s) s = ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8);
+    if (!s) s = ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8);
+    if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(n));
+    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
+    pn_candidate *h = nullptr;
+    if (!s) {
+        if (n) {
+            pn::launch_cand_keys((const uint2 *)c->cands.p, n, (unsigned long long *)c->keys.p, st);
+            pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
+                               n, 33 + key_rbits(x->n_reads), c->sort_temp.p, st);
+            pn::launch_keys_to_cands((const unsigned long long *)c->keys.p, n, c->out_hits.p, st);
+        }
+        h = (pn_candidate *)std::malloc(std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
+        if (!h) s = PN_ENOMEM;
+    }
+    if (!s && n)
+        s = map_err(hipMemcpyAsync(h, c->out_hits.p, n * sizeof(pn_candidate),
+                                   hipMemcpyDeviceToHost, st));
+    if (!s) s = map_err(hipStreamSynchronize(st));
+    dfree(c, dk);
+    if (s) {
         std::free(h);
-        return map_err(e);
+        return s;
     }
     *cands = h;
     *n_cands = n;
-    if (n_seeds) *n_seeds = plan.n_seeds;
+    if (n_seeds) *n_seeds = seeds;
     return PN_OK;
 }
 
 int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candidate *cands,
                 uint64_t n, int k, const uint8_t *kpr, pn_hit **records, uint64_t *n_records) {
     PN_CHECK(check_map_args(c, ref, x, k, kpr, PN_ALL_HITS));
-    if (!records || !n_records || (n && !cands)) return PN_EINVAL;
+    if (!records || !n_records || (n && !cands) || n >= (1ull << 32)) return PN_EINVAL;
     std::vector<uint2> host(n);
     for (uint64_t i = 0; i < n; i++) {
         const pn_candidate &cd = cands[i];
@@ -861,8 +885,9 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
         PN_CHECK(dalloc_t(c, x->n_reads, &dk));
         PN_TRY(hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st));
     }
-    int s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
+    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
     const uint64_t cap = std::max<uint64_t>(n * (2 * PN_MAX_K + 1), 1);
+    if (!s) s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
     if (!s) s = ensure(c, c->keys, cap * 8);
     if (!s) s = ensure(c, c->keys_tmp, cap * 8);
     if (!s && n)
@@ -871,16 +896,15 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
     uint64_t got = 0;
     const int ebits = key_ebits(ref->L);
     if (!s) {
-        zero_misc(c, st);
-        pn::launch_check_k(x->offsets, x->n_reads, x->q, k < 0 ? -1 : k, dk,
-                           (uint32_t *)&c->misc[kStatus], st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kRecCount], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kCandCount], 1, (uint32_t)n, st);
         pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
                          (unsigned long long *)&c->misc[kVerifyRows], cap, ebits};
-        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p, n,
+        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p,
+                          (const unsigned long long *)&c->misc[kCandCount], std::max<uint64_t>(n, 1),
                           k < 0 ? -1 : k, dk, vo, st);
         s = read_misc(c, st);
-        if (!s && (c->hmisc[kStatus] & 2u)) s = PN_EINVAL;
-        if (!s && (c->hmisc[kStatus] & 4u)) s = PN_ELEMMA;
         got = s ? 0 : c->hmisc[kRecCount];
     }
     if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(got));

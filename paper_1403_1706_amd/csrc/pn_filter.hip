@@ -1,26 +1,53 @@
 // Algorithm 2: filtration of reference positions through the q-group index
 // (Section 3.2).  Both strands come from one pass over the forward 2-bit
-// text: the q-gram of strand 1 at position L-q-u is the reverse complement
-// of the forward q-gram at u.  For each (position, strand) the occurrences
-// of its q-gram are O[k_start .. k_end) (INDEXPAIR), each giving a candidate
-// (read r, diagonal d = p - o).
+// text: the q-gram of strand 1 at position p = L-q-u is the reverse
+// complement of the forward q-gram at u.  For every (position, strand) the
+// occurrences of its q-gram are O[k_start .. k_end) (INDEXPAIR); each
+// occurrence (read r, offset o) that passes the rules below becomes a
+// candidate (r, strand, diagonal d = p - o).
 //
-// An occurrence pair (p, o) whose left neighbours are equal,
-// T[p-1] == read[o-1], is not emitted: the pair (p-1, o-1) lies on the same
-// diagonal and is found from position p-1, so the candidate set (read,
-// strand, diagonal) is unchanged.  O slices are ordered by the class of the
-// letter before each q-gram occurrence, so the skipped pairs form one
-// contiguous sub-range [cl, ch) found by a short search.
+// Every rule below drops a candidate only if another one is guaranteed to
+// hold every alignment of the read with at most k_r errors, so the hits do
+// not change.  They rest on the counting argument of the q-gram lemma
+// (Section 2.2): an alignment with at most k edits leaves every read q-gram
+// that no edit touches matched exactly on its diagonal, and one edit
+// touches at most q of the read's q-grams.
 //
-// Two launches share the probe code: a count pass (per-block totals, the
-// cumulative sum C of Algorithm 2) and an emit pass writing each block's
-// candidates at its exclusive offset, so compaction needs no atomics.
+//  1. Left extension.  If the letters before the q-gram agree in read and
+//     text, the pair (p-1, o-1) is on the same diagonal and is itself a
+//     candidate unless rule 2 drops it; (p, o) is dropped only when
+//     (p-1, o-1) stays.
+//  2. Low-complexity q-grams (period <= 2: homopolymers, dinucleotide
+//     repeats) have huge occurrence lists.  A read with Q_r offsets whose
+//     q-gram is not low-complexity keeps, under at most k_r edits, at least
+//     Q_r - k_r q of them untouched; if that is >= 1 the read needs none of
+//     its low-complexity seeds.  Only reads with Q_r <= k_r q keep them
+//     (the per-read flag "keep"), and their occurrences of the 16 such
+//     q-grams are collected in side lists so that the long original lists
+//     are never walked.
+//  3. Exact run length.  The untouched offsets fall into at most
+//     k_r + 1 + h_r blocks (h_r = maximal runs of low-complexity offsets),
+//     so some block of consecutive untouched offsets has at least
+//     ceil((Q_r - k_r q) / (k_r + 1 + h_r)) members: an exact match of length
+//     L_r >= q - 1 + that many letters.  (A read that keeps its
+//     low-complexity seeds uses ceil((n_r - k_r) / (k_r + 1)), the plain
+//     pigeonhole bound.)  The candidate that rule 1 keeps for that run
+//     starts at or before the block, so every needed candidate has a forward
+//     exact run of at least L_r letters; up to four letters past the q-gram
+//     are compared (stored in the O entry and read from the reference
+//     window).
+//
+// Candidates are staged per wave in LDS and appended to the output with one
+// atomic add per wave; the total is counted even past the capacity so that
+// the host can grow the buffer and run again.
 #include "pn_internal.h"
 
 namespace {
 
 constexpr int kT = pn::kFilterThreads;
 constexpr int kPPT = pn::kFilterPPT;
+constexpr int kWaves = kT / 64;
+constexpr int kWBuf = 256;  // staged candidates per wave
 
 // 64 bits of packed reference starting at signed base position B (base B+t
 // in bits 63-2t .. 62-2t); packed[-1] and 3 words past the end are readable
@@ -32,172 +59,267 @@ __device__ __forceinline__ uint64_t window32(const uint32_t *packed, int64_t B) 
     return (hi << (2 * sh)) | (packed[wi + 2] >> (32 - 2 * sh));
 }
 
-struct Probe {
-    uint32_t ks, cl, ch, ke;  // survivors: [ks, cl) and [ch, ke)
-};
-
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *O, uint32_t lo, uint32_t hi,
-                                                    uint32_t key) {
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (O[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
+__device__ __forceinline__ uint32_t base_rel(uint64_t X, int t) {
+    return (uint32_t)(X >> (62 - 2 * t)) & 3u;
 }
 
-// INDEXPAIR(g) and the sub-range of occurrences preceded by letter `prev`
+struct Stage {
+    uint2 *buf;      // this wave's LDS buffer
+    uint32_t *cnt;   // this wave's LDS counter
+    pn::FilterOut out;
+};
+
+__device__ __forceinline__ void push(const Stage &sg, uint2 c) {
+    uint32_t i = atomicAdd(sg.cnt, 1u);
+    if (i < kWBuf) {
+        sg.buf[i] = c;
+    } else {
+        unsigned long long at = atomicAdd(sg.out.count, 1ull);
+        if (at < sg.out.capacity) sg.out.cands[at] = c;
+    }
+}
+
+// one (position, strand): INDEXPAIR and the rules of the header comment
 template <typename TW>
-__device__ __forceinline__ Probe probe(const PnIndexDev &ix, uint32_t g, bool has_prev,
-                                       uint32_t prev) {
-    Probe pr{0, 0, 0, 0};
+__device__ __forceinline__ unsigned long long probe(const PnIndexDev &ix, const uint8_t *rinfo,
+                                                    const unsigned long long *side,
+                                                    const uint32_t *side_start,
+                                                    const uint32_t *side_count, uint32_t g,
+                                                    int64_t p, uint32_t s, bool has_prev,
+                                                    uint32_t prev, bool lh, uint32_t N,
+                                                    uint32_t avail, const Stage &sg) {
     const TW *I = (const TW *)ix.I;
     const uint32_t wmask = (1u << ix.log2w) - 1;
-    uint32_t i = g >> ix.log2w, j = g & wmask;
-    TW word = I[i];
-    if (!((word >> j) & 1)) return pr;
-    uint32_t jp = (uint32_t)pn_popc<TW>(word & (((TW)1 << j) - 1));  // GROUPRANK
-    uint32_t x = ix.S[i] + jp;
-    pr.ks = ix.Sp[x];
-    pr.ke = ix.Sp[x + 1];
-    pr.cl = pr.ch = pr.ke;
-    if (!has_prev) return pr;
-    const uint32_t key0 = prev << 29, key1 = (prev + 1) << 29;
-    uint32_t m = pr.ke - pr.ks;
-    if (m <= 8) {
-        uint32_t below0 = 0, below1 = 0;
-        for (uint32_t t = 0; t < m; t++) {
-            uint32_t v = ix.O[pr.ks + t];
-            below0 += v < key0;
-            below1 += v < key1;
-        }
-        pr.cl = pr.ks + below0;
-        pr.ch = pr.ks + below1;
-    } else {
-        pr.cl = lower_bound_u32(ix.O, pr.ks, pr.ke, key0);
-        pr.ch = lower_bound_u32(ix.O, pr.cl, pr.ke, key1);
+    const uint32_t i = g >> ix.log2w, j = g & wmask;
+    const TW word = I[i];
+    if (!((word >> j) & 1)) return 0;
+    const uint32_t jp = (uint32_t)pn_popc<TW>(word & (((TW)1 << j) - 1));  // GROUPRANK
+    const uint32_t x = ix.S[i] + jp;
+    const uint32_t ks = ix.Sp[x], ke = ix.Sp[x + 1];
+    const unsigned long long *src = ix.O + ks;
+    uint32_t m = ke - ks;
+    if (pn_low_complexity(g, ix.q)) {  // rule 2: only reads that keep these seeds
+        const uint32_t id = g >> (2 * ix.q - 4);
+        src = side + side_start[id];
+        m = side_count[id];
     }
-    return pr;
-}
-
-// the two probes of forward position u (strand 0 at p = u, strand 1 at
-// p = L-q-u); returns false past the last q-gram
-struct PosQ {
-    uint32_t g0, g1, prev0, prev1;
-    bool has0, has1;
-};
-
-__device__ __forceinline__ bool pos_qgrams(const PnRefDev &ref, int q, uint64_t X, uint64_t u,
-                                           int j, PosQ &pq) {
-    if (u + q > ref.L) return false;
-    pq.g0 = (uint32_t)((X << (2 * (j + 1))) >> (64 - 2 * q));
-    pq.prev0 = (uint32_t)(X >> (62 - 2 * j)) & 3u;            // R[u-1]
-    uint32_t nxt = (uint32_t)(X >> (62 - 2 * (j + 1 + q))) & 3u;  // R[u+q]
-    pq.has0 = u >= 1;
-    pq.g1 = pn_revcomp_code(pq.g0, q);
-    pq.prev1 = 3u - nxt;  // T1[p-1] = complement of R[u+q]
-    pq.has1 = u + q < ref.L;
-    return true;
+    for (uint32_t t = 0; t < m; t++) {
+        const unsigned long long v = src[t];
+        const uint32_t hi = (uint32_t)(v >> 32);
+        const uint32_t cls = hi >> 29;
+        const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
+        const uint32_t o = hi & 0xffu;
+        const uint32_t info = rinfo[r];
+        const bool keep = (info >> 7) & 1u;
+        if (has_prev && cls == prev && (keep || !lh)) continue;  // rule 1
+        const uint32_t need = info & 7u;                           // rule 3
+        if (need) {
+            const uint32_t nav = (uint32_t)(v >> 21) & 7u;
+            const uint32_t next4 = (uint32_t)(v >> 24) & 0xffu;
+            if (nav < need || avail < need || ((next4 ^ N) >> (8 - 2 * need)) != 0u) continue;
+        }
+        push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+    }
+    return (unsigned long long)(ke - ks);
 }
 
 template <typename TW>
-__global__ __launch_bounds__(kT) void k_filter_count(PnRefDev ref, PnIndexDev ix,
-                                                     uint32_t *block_counts,
-                                                     unsigned long long *n_seeds) {
+__global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
+                                               const uint8_t *__restrict__ rinfo,
+                                               const unsigned long long *__restrict__ side,
+                                               const uint32_t *__restrict__ side_start,
+                                               const uint32_t *__restrict__ side_count,
+                                               pn::FilterOut out) {
+    __shared__ uint2 wbuf[kWaves][kWBuf];
+    __shared__ uint32_t wcnt[kWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
+    __syncthreads();
+    const Stage sg{wbuf[wave], &wcnt[wave], out};
+    const int q = ix.q;
+    const uint64_t L = ref.L;
     const uint64_t u0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kPPT;
-    uint32_t cnt = 0;
     unsigned long long seeds = 0;
-    if (u0 + ix.q <= ref.L) {
-        const uint64_t X = window32(ref.packed, (int64_t)u0 - 1);
-#pragma unroll
-        for (int j = 0; j < kPPT; j++) {
-            PosQ pq;
-            if (!pos_qgrams(ref, ix.q, X, u0 + j, j, pq)) break;
-            Probe a = probe<TW>(ix, pq.g0, pq.has0, pq.prev0);
-            Probe b = probe<TW>(ix, pq.g1, pq.has1, pq.prev1);
-            cnt += (a.cl - a.ks) + (a.ke - a.ch) + (b.cl - b.ks) + (b.ke - b.ch);
-            seeds += (a.ke - a.ks) + (b.ke - b.ks);
+    if (u0 + q <= L) {
+        // bases u0-5 .. u0+26: one letter before, q letters, four after on
+        // strand 0, and four before on the forward strand for strand 1
+        const uint64_t X = window32(ref.packed, (int64_t)u0 - 5);
+        for (int jj = 0; jj < kPPT; jj++) {
+            const uint64_t u = u0 + jj;
+            if (u + q > L) break;
+            const int t0 = jj + 5;  // window index of base u
+            const uint32_t g0 = (uint32_t)((X << (2 * t0)) >> (64 - 2 * q));
+            const uint32_t g1 = pn_revcomp_code(g0, q);
+            // strand 0 at p = u
+            const bool has0 = u >= 1;
+            const uint32_t prev0 = base_rel(X, t0 - 1);
+            const uint32_t N0 = (uint32_t)((X << (2 * (t0 + q))) >> 56);
+            const uint64_t after0 = L - u - q;
+            const uint32_t avail0 = after0 < 4 ? (uint32_t)after0 : 4u;
+            const bool lh0 = has0 && pn_low_complexity((prev0 << (2 * (q - 1))) | (g0 >> 2), q);
+            // strand 1 at p = L-q-u: T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
+            const bool has1 = after0 >= 1;
+            const uint32_t prev1 = 3u - base_rel(X, t0 + q);
+            const uint32_t F = (uint32_t)(X >> (62 - 2 * (t0 - 1))) & 0xffu;  // R[u-4..u-1]
+            const uint32_t N1 = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) |
+                                 (F >> 6)) ^ 0xffu;
+            const uint32_t avail1 = u < 4 ? (uint32_t)u : 4u;
+            const bool lh1 = has1 && pn_low_complexity((prev1 << (2 * (q - 1))) | (g1 >> 2), q);
+            seeds += probe<TW>(ix, rinfo, side, side_start, side_count, g0, (int64_t)u, 0u, has0,
+                               prev0, lh0, N0, avail0, sg);
+            seeds += probe<TW>(ix, rinfo, side, side_start, side_count, g1,
+                               (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, sg);
         }
     }
-    uint32_t total;
-    pn_block_excl_scan(cnt, &total);
     for (int o = 32; o > 0; o >>= 1) seeds += __shfl_xor(seeds, o);
-    if ((threadIdx.x & 63) == 0 && seeds) atomicAdd(n_seeds, seeds);
-    if (threadIdx.x == 0) block_counts[blockIdx.x] = total;
+    if (lane == 0 && seeds) atomicAdd(out.n_seeds, seeds);
+    __syncthreads();
+    // flush this wave's staged candidates with one atomic add
+    const uint32_t n = min(wcnt[wave], (uint32_t)kWBuf);
+    unsigned long long base = 0;
+    if (lane == 0 && n) base = atomicAdd(out.count, (unsigned long long)n);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane; i < n; i += 64)
+        if (base + i < out.capacity) out.cands[base + i] = wbuf[wave][i];
 }
 
-__device__ __forceinline__ void emit_range(const PnIndexDev &ix, uint32_t a, uint32_t b,
-                                           int64_t p, uint32_t s, uint2 *out, uint64_t &at) {
-    for (uint32_t k = a; k < b; k++) {
-        uint32_t e = ix.O[k];
-        uint32_t r = (e >> 8) & (PN_MAX_READS - 1);
-        int64_t d = p - (int64_t)(e & 0xffu);
-        out[at++] = make_uint2(r | (s << 31), (uint32_t)(d + PN_DBIAS));
+// ---------------------------------------------------------------------------
+// map-time per-read rules
+
+__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+// status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
+__global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict__ kpr,
+                             uint8_t *__restrict__ rinfo, uint32_t *status) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ix.n_reads) return;
+    const uint32_t n = (uint32_t)(ix.offsets[r + 1] - ix.offsets[r]);
+    const uint32_t k = kglob >= 0 ? (uint32_t)kglob : kpr[r];
+    const uint32_t q = (uint32_t)ix.q;
+    uint32_t bad = 0;
+    if (k > PN_MAX_K) bad |= 2u;
+    if ((k + 1) * q > n) bad |= 4u;
+    if (bad) {
+        atomicOr(status, bad);
+        rinfo[r] = 0;
+        return;
     }
+    const uint32_t nq = n - q + 1;
+    const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = ix.lcinfo[r] >> 16;
+    const uint32_t Q = nq - lc;  // offsets whose q-gram is not low-complexity
+    uint32_t keep, run;
+    if (Q >= k * q + 1) {
+        keep = 0;
+        run = q - 1 + ceil_div(Q - k * q, k + 1 + runs);
+    } else {
+        keep = 1;
+        run = ceil_div(n - k, k + 1);
+    }
+    const uint32_t need = run > q ? min(run - q, 4u) : 0u;
+    rinfo[r] = (uint8_t)((keep << 7) | need);
 }
 
+// side lists: for each of the 16 low-complexity q-grams (first two letters
+// x, y; then x y x y ...), the occurrences from reads that keep them.  One
+// block per q-gram; `cap_start` are the host-computed list starts.
 template <typename TW>
-__global__ __launch_bounds__(kT) void k_filter_emit(PnRefDev ref, PnIndexDev ix, uint64_t blk0,
-                                                    const uint64_t *block_offsets, uint2 *cands) {
-    const uint64_t blk = blk0 + blockIdx.x;
-    const uint64_t u0 = (blk * kT + threadIdx.x) * kPPT;
-    const bool any = u0 + ix.q <= ref.L;
-    const uint64_t X = any ? window32(ref.packed, (int64_t)u0 - 1) : 0;
-    uint32_t cnt = 0;
-    if (any) {
-#pragma unroll
-        for (int j = 0; j < kPPT; j++) {
-            PosQ pq;
-            if (!pos_qgrams(ref, ix.q, X, u0 + j, j, pq)) break;
-            Probe a = probe<TW>(ix, pq.g0, pq.has0, pq.prev0);
-            Probe b = probe<TW>(ix, pq.g1, pq.has1, pq.prev1);
-            cnt += (a.cl - a.ks) + (a.ke - a.ch) + (b.cl - b.ks) + (b.ke - b.ch);
+__global__ __launch_bounds__(256) void k_lc_side(PnIndexDev ix, const uint8_t *__restrict__ rinfo,
+                                                 unsigned long long *side,
+                                                 const uint32_t *side_start,
+                                                 uint32_t *side_count) {
+    const uint32_t id = blockIdx.x;
+    const uint32_t x = id >> 2, y = id & 3u;
+    uint32_t g = 0;
+    for (int t = 0; t < ix.q; t++) g = (g << 2) | ((t & 1) ? y : x);
+    const TW *I = (const TW *)ix.I;
+    const uint32_t wmask = (1u << ix.log2w) - 1;
+    const uint32_t gi = g >> ix.log2w, gj = g & wmask;
+    const TW word = I[gi];
+    uint32_t ks = 0, ke = 0;
+    if ((word >> gj) & 1) {
+        const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
+        ks = ix.Sp[slot];
+        ke = ix.Sp[slot + 1];
+    }
+    uint32_t at = side_start[id];
+    for (uint32_t base = ks; base < ke; base += 256) {
+        const uint32_t i = base + threadIdx.x;
+        unsigned long long v = 0;
+        uint32_t f = 0;
+        if (i < ke) {
+            v = ix.O[i];
+            const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
+            f = (rinfo[r] >> 7) & 1u;
         }
+        uint32_t tot;
+        const uint32_t ex = pn_block_excl_scan(f, &tot);
+        if (f) side[at + ex] = v;
+        at += tot;
     }
-    uint32_t total;
-    uint32_t ex = pn_block_excl_scan(cnt, &total);
-    if (!any || cnt == 0) return;
-    uint64_t at = block_offsets[blk] - block_offsets[blk0] + ex;
-    for (int j = 0; j < kPPT; j++) {
-        PosQ pq;
-        const uint64_t u = u0 + j;
-        if (!pos_qgrams(ref, ix.q, X, u, j, pq)) break;
-        Probe a = probe<TW>(ix, pq.g0, pq.has0, pq.prev0);
-        emit_range(ix, a.ks, a.cl, (int64_t)u, 0, cands, at);
-        emit_range(ix, a.ch, a.ke, (int64_t)u, 0, cands, at);
-        Probe b = probe<TW>(ix, pq.g1, pq.has1, pq.prev1);
-        const int64_t p1 = (int64_t)(ref.L - ix.q - u);
-        emit_range(ix, b.ks, b.cl, p1, 1, cands, at);
-        emit_range(ix, b.ch, b.ke, p1, 1, cands, at);
+    if (threadIdx.x == 0) side_count[id] = at - side_start[id];
+}
+
+// occurrence counts of the 16 low-complexity q-grams (sizes of their O slices)
+template <typename TW>
+__global__ void k_lc_sizes(PnIndexDev ix, uint32_t *sizes) {
+    const uint32_t id = threadIdx.x;
+    if (id >= pn::kLcPatterns) return;
+    const uint32_t x = id >> 2, y = id & 3u;
+    uint32_t g = 0;
+    for (int t = 0; t < ix.q; t++) g = (g << 2) | ((t & 1) ? y : x);
+    const TW *I = (const TW *)ix.I;
+    const uint32_t wmask = (1u << ix.log2w) - 1;
+    const uint32_t gi = g >> ix.log2w, gj = g & wmask;
+    const TW word = I[gi];
+    uint32_t m = 0;
+    if ((word >> gj) & 1) {
+        const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
+        m = ix.Sp[slot + 1] - ix.Sp[slot];
     }
+    sizes[id] = m;
 }
 
 }  // namespace
 
 namespace pn {
 
-void launch_filter_count(const PnRefDev &ref, const PnIndexDev &ix, uint64_t n_blocks,
-                         uint32_t *block_counts, unsigned long long *n_seeds, hipStream_t st) {
-    if (!n_blocks) return;
+void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st) {
     if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_filter_count<unsigned long long>, dim3((unsigned)n_blocks), dim3(kT),
-                           0, st, ref, ix, block_counts, n_seeds);
+        hipLaunchKernelGGL(k_lc_sizes<unsigned long long>, dim3(1), dim3(64), 0, st, ix, sizes);
     else
-        hipLaunchKernelGGL(k_filter_count<uint32_t>, dim3((unsigned)n_blocks), dim3(kT), 0, st,
-                           ref, ix, block_counts, n_seeds);
+        hipLaunchKernelGGL(k_lc_sizes<uint32_t>, dim3(1), dim3(64), 0, st, ix, sizes);
 }
 
-void launch_filter_emit(const PnRefDev &ref, const PnIndexDev &ix, uint64_t blk0, uint64_t blk1,
-                        const uint64_t *block_offsets, uint2 *cands, hipStream_t st) {
-    if (blk1 <= blk0) return;
+
+void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
+                       uint32_t *status, hipStream_t st) {
+    if (!ix.n_reads) return;
+    hipLaunchKernelGGL(k_read_rules, dim3((ix.n_reads + 255) / 256), dim3(256), 0, st, ix, kglob,
+                       kpr, rinfo, status);
+}
+
+void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
+                    uint32_t *side_start, uint32_t *side_count, hipStream_t st) {
     if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_filter_emit<unsigned long long>, dim3((unsigned)(blk1 - blk0)),
-                           dim3(kT), 0, st, ref, ix, blk0, block_offsets, cands);
+        hipLaunchKernelGGL(k_lc_side<unsigned long long>, dim3(kLcPatterns), dim3(256), 0, st, ix,
+                           rinfo, side, side_start, side_count);
     else
-        hipLaunchKernelGGL(k_filter_emit<uint32_t>, dim3((unsigned)(blk1 - blk0)), dim3(kT), 0, st,
-                           ref, ix, blk0, block_offsets, cands);
+        hipLaunchKernelGGL(k_lc_side<uint32_t>, dim3(kLcPatterns), dim3(256), 0, st, ix, rinfo,
+                           side, side_start, side_count);
+}
+
+void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const uint8_t *rinfo,
+                   const unsigned long long *side, const uint32_t *side_start,
+                   const uint32_t *side_count, FilterOut out, hipStream_t st) {
+    const uint64_t npos = ref.L >= (uint64_t)ix.q ? ref.L - ix.q + 1 : 0;
+    const uint64_t nb = (npos + kFilterBlockPos - 1) / kFilterBlockPos;
+    if (!nb || !ix.n_reads) return;
+    if (ix.log2w == 6)
+        hipLaunchKernelGGL(k_filter<unsigned long long>, dim3((unsigned)nb), dim3(kT), 0, st, ref,
+                           ix, rinfo, side, side_start, side_count, out);
+    else
+        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, ix, rinfo,
+                           side, side_start, side_count, out);
 }
 
 }  // namespace pn

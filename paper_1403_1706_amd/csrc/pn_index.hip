@@ -6,9 +6,10 @@
 //   4. count[S[i] + j'] += 1, j' = GROUPRANK   (k_qgram_count)
 //   5. S' = exclusive scan of count            (pn_scan.hip)
 //   6. O[S'[x] + next free] = position         (k_qgram_scatter)
-// followed by ordering each q-gram's slice of O by entry value, which puts
-// entries with equal preceding letter next to each other (the filter uses
-// that to skip occurrence pairs that extend to the left).
+// followed by ordering each q-gram's slice of O by entry value (small slices
+// fully, long slices by preceding letter).  Each O entry also carries the
+// letter before its q-gram and the (up to) four letters after it, which the
+// filter compares with the reference without touching the reads.
 #include "pn_internal.h"
 
 namespace {
@@ -18,6 +19,7 @@ constexpr int kChunk = 32;  // q-gram starts per thread
 struct QgramIter {
     uint32_t r;
     uint64_t off;
+    uint32_t n;       // read length
     uint32_t o0, o1;  // q-gram starts [o0, o1)
 };
 
@@ -28,6 +30,7 @@ __device__ __forceinline__ bool qgram_iter(const PnIndexDev &ix, uint32_t nch, Q
     if (it.r >= ix.n_reads) return false;
     it.off = ix.offsets[it.r];
     uint64_t n = ix.offsets[it.r + 1] - it.off;
+    it.n = (uint32_t)n;
     if (n < (uint64_t)ix.q) return false;
     uint32_t nq = (uint32_t)(n - ix.q + 1);
     it.o0 = c * kChunk;
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(256) void k_qgram_count(PnIndexDev ix, uint32_t nch
 
 template <typename TW>
 __global__ __launch_bounds__(256) void k_qgram_scatter(PnIndexDev ix, uint32_t nch,
-                                                       uint32_t *cursor, uint32_t *O) {
+                                                       uint32_t *cursor, unsigned long long *O) {
     QgramIter it;
     if (!qgram_iter(ix, nch, it)) return;
     const TW *I = (const TW *)ix.I;
@@ -94,14 +97,41 @@ __global__ __launch_bounds__(256) void k_qgram_scatter(PnIndexDev ix, uint32_t n
         uint32_t g = qgram_at(ix, it.off, o, cls);
         uint32_t x = group_rank_slot<TW>(ix, I, g);
         uint32_t k = ix.Sp[x] + atomicAdd(&cursor[x], 1u);
-        O[k] = (cls << 29) | (it.r << 8) | o;
+        // the letters after the q-gram inside the read (at most four)
+        const uint32_t after = it.n - o - (uint32_t)ix.q;
+        const uint32_t nav = after < 4u ? after : 4u;
+        uint32_t next4 = pn_window16(ix.packed, it.off + o + ix.q) >> 24;
+        next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
+        const uint32_t hi = (cls << 29) | (it.r << 8) | o;
+        const uint32_t lo = (next4 << 24) | (nav << 21);
+        O[k] = ((unsigned long long)hi << 32) | lo;
     }
+}
+
+// per read: number of low-complexity q-gram offsets and of maximal runs of
+// such offsets (both used by the map-time seed rules)
+__global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ix.n_reads) return;
+    const uint64_t off = ix.offsets[r];
+    const uint64_t n = ix.offsets[r + 1] - off;
+    uint32_t cnt = 0, runs = 0;
+    bool prev_lc = false;
+    for (uint64_t o = 0; o + (uint64_t)ix.q <= n; o++) {
+        const uint32_t g = pn_window16(ix.packed, off + o) >> (32 - 2 * ix.q);
+        const bool lc = pn_low_complexity(g, ix.q);
+        cnt += lc;
+        runs += lc && !prev_lc;
+        prev_lc = lc;
+    }
+    lcinfo[r] = cnt | (runs << 16);
 }
 
 // order small slices of O in place; slices longer than 32 go to a list
 __global__ __launch_bounds__(256) void k_bucket_sort(const uint32_t *Sp, uint64_t n_slots,
-                                                     const uint32_t *n_distinct, uint32_t *O,
-                                                     uint32_t *big_list, uint32_t *big_count) {
+                                                     const uint32_t *n_distinct,
+                                                     unsigned long long *O, uint32_t *big_list,
+                                                     uint32_t *big_count) {
     uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_slots || x >= *n_distinct) return;
     uint32_t s = Sp[x], e = Sp[x + 1];
@@ -112,7 +142,7 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const uint32_t *Sp, uint64_
         return;
     }
     for (uint32_t i = s + 1; i < e; i++) {
-        uint32_t v = O[i];
+        unsigned long long v = O[i];
         uint32_t j = i;
         while (j > s && O[j - 1] > v) {
             O[j] = O[j - 1];
@@ -124,16 +154,18 @@ __global__ __launch_bounds__(256) void k_bucket_sort(const uint32_t *Sp, uint64_
 
 // one block per long slice: stable partition by preceding-letter class
 // (the top three bits of an entry) through a scratch copy
-__global__ __launch_bounds__(256) void k_bucket_sort_big(const uint32_t *Sp, uint32_t *O,
-                                                         uint32_t *tmp, const uint32_t *big_list) {
+__global__ __launch_bounds__(256) void k_bucket_sort_big(const uint32_t *Sp,
+                                                         unsigned long long *O,
+                                                         unsigned long long *tmp,
+                                                         const uint32_t *big_list) {
     uint32_t x = big_list[blockIdx.x];
     uint32_t s = Sp[x], e = Sp[x + 1];
     uint32_t at = s;
     for (uint32_t cls = 0; cls <= PN_CLS_NONE; cls++) {
         for (uint32_t base = s; base < e; base += 256) {
             uint32_t i = base + threadIdx.x;
-            uint32_t v = i < e ? O[i] : 0u;
-            uint32_t f = (i < e) && ((v >> 29) == cls);
+            unsigned long long v = i < e ? O[i] : 0ull;
+            uint32_t f = (i < e) && ((uint32_t)(v >> 61) == cls);
             uint32_t tot;
             uint32_t ex = pn_block_excl_scan(f, &tot);
             if (f) tmp[at + ex] = v;
@@ -182,7 +214,8 @@ void launch_qgram_count(const PnIndexDev &ix, uint32_t *cnt, hipStream_t st) {
                            nch, cnt);
 }
 
-void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, uint32_t *O, hipStream_t st) {
+void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, unsigned long long *O,
+                          hipStream_t st) {
     const uint32_t nch = nch_for(ix);
     uint64_t n = (uint64_t)ix.n_reads * nch;
     if (!n) return;
@@ -195,16 +228,22 @@ void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, uint32_t *O, h
 }
 
 void launch_bucket_sort(const uint32_t *Sp, uint64_t n_slots, const uint32_t *n_distinct,
-                        uint32_t *O, uint32_t *big_list, uint32_t *big_count, hipStream_t st) {
+                        unsigned long long *O, uint32_t *big_list, uint32_t *big_count,
+                        hipStream_t st) {
     if (!n_slots) return;
     hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, Sp, n_slots,
                        n_distinct, O, big_list, big_count);
 }
 
-void launch_bucket_sort_big(const uint32_t *Sp, uint32_t *O, uint32_t *tmp,
+void launch_bucket_sort_big(const uint32_t *Sp, unsigned long long *O, unsigned long long *tmp,
                             const uint32_t *big_list, uint32_t n_big, hipStream_t st) {
     if (!n_big) return;
     hipLaunchKernelGGL(k_bucket_sort_big, dim3(n_big), dim3(256), 0, st, Sp, O, tmp, big_list);
+}
+
+void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st) {
+    if (!ix.n_reads) return;
+    hipLaunchKernelGGL(k_read_lc, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, lcinfo);
 }
 
 }  // namespace pn

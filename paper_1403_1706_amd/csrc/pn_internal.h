@@ -10,8 +10,12 @@
 //    padded by PN_PAD_BLOCKS blocks on each side so that band windows that
 //    hang over either end of the reference read "no base here".
 //  * read planes: per read, PN_READ_WORDS uint2 {H, L} words (LSB-first).
-//  * O entry: (cls << 29) | (read << 8) | offset, cls = code of the letter
-//    before the q-gram in its read or 4 at offset 0.
+//  * O entry (64 bits): high word (cls << 29) | (read << 8) | offset, cls =
+//    code of the letter before the q-gram in its read or 4 at offset 0; low
+//    word (next4 << 24) | (nav << 21): the (up to) four read letters after
+//    the q-gram, first letter in the top bits, and how many exist (0..4).
+//  * low-complexity q-grams: period <= 2 (homopolymers and dinucleotide
+//    repeats), see pn_low_complexity.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,7 +47,8 @@ struct PnIndexDev {
     const void *I;            // n_groups words of w bits
     const uint32_t *S;        // n_groups + 1
     const uint32_t *Sp;       // n_distinct + 1
-    const uint32_t *O;        // n_qgrams
+    const unsigned long long *O;  // n_qgrams 64-bit entries
+    const uint32_t *lcinfo;   // per read: low-complexity offsets | (intervals << 16)
     uint32_t n_reads;
     uint32_t max_len;
     int q;
@@ -76,6 +81,17 @@ __device__ __forceinline__ uint32_t pn_revcomp_code(uint32_t g, int q) {
     x = __builtin_bitreverse32(x);                       // reverses bits
     x = ((x >> 1) & 0x55555555u) | ((x & 0x55555555u) << 1);  // restore bit order inside each base
     return x >> (32 - 2 * q);
+}
+
+// q-gram of q letters (2q bits) with period 1 or 2: letter t equals letter
+// t+2 throughout.  Such q-grams (homopolymers, dinucleotide repeats) are the
+// ones whose occurrence lists explode; reads that do not need them to be
+// found skip them (see pn_filter.hip).
+// (For q < 3 no q-gram is treated this way.)
+__device__ __forceinline__ bool pn_low_complexity(uint32_t g, int q) {
+    if (q < 3) return false;
+    const uint32_t mask = (1u << (2 * (q - 2))) - 1u;
+    return ((g ^ (g >> 4)) & mask) == 0u;
 }
 
 template <typename TW>
@@ -129,8 +145,6 @@ void launch_read_meta(const uint64_t *offsets, uint32_t n_reads, int q, uint64_t
 void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_t n_reads,
                         uint2 *rplanes, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
-void launch_check_k(const uint64_t *offsets, uint32_t n_reads, int q, int kglob,
-                    const uint8_t *kpr, uint32_t *status, hipStream_t st);
 
 // pn_scan.hip: exclusive prefix sums; out has n + 1 entries (out[n] = total)
 void launch_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
@@ -142,20 +156,38 @@ uint64_t scan_partials_size(uint64_t n);
 // pn_index.hip (Algorithm 1)
 void launch_qgram_bitmap(const PnIndexDev &ix, void *I, hipStream_t st);
 void launch_qgram_count(const PnIndexDev &ix, uint32_t *cnt, hipStream_t st);
-void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, uint32_t *O, hipStream_t st);
+void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, unsigned long long *O,
+                          hipStream_t st);
 void launch_bucket_sort(const uint32_t *Sp, uint64_t n_slots, const uint32_t *n_distinct,
-                        uint32_t *O, uint32_t *big_list, uint32_t *big_count, hipStream_t st);
-void launch_bucket_sort_big(const uint32_t *Sp, uint32_t *O, uint32_t *tmp,
+                        unsigned long long *O, uint32_t *big_list, uint32_t *big_count,
+                        hipStream_t st);
+void launch_bucket_sort_big(const uint32_t *Sp, unsigned long long *O, unsigned long long *tmp,
                             const uint32_t *big_list, uint32_t n_big, hipStream_t st);
+void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
 
 // pn_filter.hip (Algorithm 2)
 constexpr int kFilterThreads = 256;
 constexpr int kFilterPPT = 8;  // forward positions per thread
 constexpr int kFilterBlockPos = kFilterThreads * kFilterPPT;
-void launch_filter_count(const PnRefDev &ref, const PnIndexDev &ix, uint64_t n_blocks,
-                         uint32_t *block_counts, unsigned long long *n_seeds, hipStream_t st);
-void launch_filter_emit(const PnRefDev &ref, const PnIndexDev &ix, uint64_t blk0, uint64_t blk1,
-                        const uint64_t *block_offsets, uint2 *cands, hipStream_t st);
+constexpr int kLcPatterns = 16;  // period <= 2 q-grams: first two letters
+struct FilterOut {
+    uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS)
+    unsigned long long *count;    // candidates produced (may exceed capacity)
+    uint64_t capacity;
+    unsigned long long *n_seeds;  // occurrence pairs seen (sum of k_end - k_start)
+};
+// per read: bit 7 = keeps its low-complexity seeds, bits 0-2 = extra letters
+// of exact run required beyond q (0..4)
+void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
+                       uint32_t *status, hipStream_t st);
+// sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)
+void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st);
+// low-complexity occurrence lists restricted to reads that keep them
+void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
+                    uint32_t *side_start, uint32_t *side_count, hipStream_t st);
+void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const uint8_t *rinfo,
+                   const unsigned long long *side, const uint32_t *side_start,
+                   const uint32_t *side_count, FilterOut out, hipStream_t st);
 
 // pn_verify.hip (Section 3.3)
 struct VerifyOut {
@@ -165,8 +197,10 @@ struct VerifyOut {
     uint64_t capacity;
     int ebits;  // bits for end positions in a key
 };
-void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands, uint64_t n,
-                   int kglob, const uint8_t *kpr, VerifyOut out, hipStream_t st);
+// verifies min(*n_dev, cap) candidates (count read on the device)
+void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands,
+                   const unsigned long long *n_dev, uint64_t cap, int kglob, const uint8_t *kpr,
+                   VerifyOut out, hipStream_t st);
 
 // pn_canon.hip: sort + duplicate removal + strata + output
 uint64_t radix_temp_size(uint64_t n);  // bytes

@@ -129,19 +129,6 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
         p[i] = v;
 }
 
-// status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
-__global__ void k_check_k(const uint64_t *__restrict__ offsets, uint32_t n_reads, int q, int kglob,
-                          const uint8_t *__restrict__ kpr, uint32_t *status) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_reads) return;
-    uint64_t len = offsets[r + 1] - offsets[r];
-    uint32_t k = kglob >= 0 ? (uint32_t)kglob : kpr[r];
-    uint32_t bad = 0;
-    if (k > PN_MAX_K) bad |= 2u;
-    if ((uint64_t)(k + 1) * (uint64_t)q > len) bad |= 4u;
-    if (bad) atomicOr(status, bad);
-}
-
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -185,13 +172,6 @@ void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
     uint64_t g = grid_for(n, 256);
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
-}
-
-void launch_check_k(const uint64_t *offsets, uint32_t n_reads, int q, int kglob,
-                    const uint8_t *kpr, uint32_t *status, hipStream_t st) {
-    if (!n_reads) return;
-    hipLaunchKernelGGL(k_check_k, dim3(grid_for(n_reads, 256)), dim3(256), 0, st, offsets,
-                       n_reads, q, kglob, kpr, status);
 }
 
 }  // namespace pn

@@ -28,20 +28,24 @@
 namespace {
 
 __global__ __launch_bounds__(256) void k_verify(PnRefDev ref, PnIndexDev ix,
-                                                const uint2 *__restrict__ cands, uint64_t n,
-                                                int kglob, const uint8_t *__restrict__ kpr,
+                                                const uint2 *__restrict__ cands,
+                                                const unsigned long long *__restrict__ n_dev,
+                                                uint64_t cap, int kglob,
+                                                const uint8_t *__restrict__ kpr,
                                                 pn::VerifyOut out) {
-    const uint64_t ci = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = min((uint64_t)*n_dev, cap);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long rows = 0;
-    if (ci < n) {
+    for (uint64_t ci = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < n; ci += stride) {
         const uint2 c = cands[ci];
         const uint32_t r = c.x & 0x7fffffffu;
         const uint32_t s = c.x >> 31;
         const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
         const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
         const int k = kglob >= 0 ? kglob : (int)kpr[r];
+        if (k > PN_MAX_K || len < 1 || len > PN_MAX_READ_LEN) continue;
         const unsigned long long head = (((unsigned long long)r << 1) | s) << out.ebits;
-        rows = (unsigned long long)pn_band_verify(
+        rows += (unsigned long long)pn_band_verify(
             s ? ref.planes[1] : ref.planes[0], ix.rplanes + (uint64_t)r * PN_READ_WORDS, len, k,
             d - k, ref.L, [&](uint32_t e, int v) {
                 unsigned long long at = atomicAdd(out.count, 1ull);
@@ -57,11 +61,15 @@ __global__ __launch_bounds__(256) void k_verify(PnRefDev ref, PnIndexDev ix,
 
 namespace pn {
 
-void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands, uint64_t n,
-                   int kglob, const uint8_t *kpr, VerifyOut out, hipStream_t st) {
-    if (!n) return;
-    hipLaunchKernelGGL(k_verify, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ref, ix,
-                       cands, n, kglob, kpr, out);
+void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands,
+                   const unsigned long long *n_dev, uint64_t cap, int kglob, const uint8_t *kpr,
+                   VerifyOut out, hipStream_t st) {
+    if (!cap) return;
+    // enough resident waves to fill the chip; each thread strides over candidates
+    uint64_t blocks = (cap + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_verify, dim3((unsigned)blocks), dim3(256), 0, st, ref, ix, cands, n_dev,
+                       cap, kglob, kpr, out);
 }
 
 }  // namespace pn

@@ -98,7 +98,7 @@ _sig("pn_index_export", _int, [_P, _P, _P, _P, _P])
 _sig("pn_map", _int, [_P, _P, _P, _int, _P, _int, _PP, ctypes.POINTER(_u64)])
 _sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_u64), _P])
 _sig("pn_hits_free", None, [_P])
-_sig("pn_filter", _int, [_P, _P, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
+_sig("pn_filter", _int, [_P, _P, _P, _int, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
 _sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
 
 EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
@@ -226,7 +226,7 @@ def pn_index_export(idx):
     I = np.empty(info["n_groups"], dtype=np.uint64 if info["w"] == 64 else np.uint32)
     S = np.empty(info["n_groups"] + 1, dtype=np.uint32)
     Sp = np.empty(info["n_distinct"] + 1, dtype=np.uint32)
-    O = np.empty(max(info["n_qgrams"], 1), dtype=np.uint32)
+    O = np.empty(max(info["n_qgrams"], 1), dtype=np.uint64)
     _check(_lib.pn_index_export(idx, _ptr(I), _ptr(S), _ptr(Sp), _ptr(O)), "pn_index_export")
     return I, S, Sp, O[:info["n_qgrams"]]
 
@@ -268,13 +268,15 @@ def pn_map_dev(ctx, ref, idx, k, d_out, mode: int = PN_ALL_HITS, stream=None, d_
     return n.value
 
 
-def pn_filter(ctx, ref, idx):
-    """(candidates structured array, number of occurrence pairs before pruning)."""
+def pn_filter(ctx, ref, idx, k):
+    """(candidates structured array, number of all occurrence pairs)."""
+    n_reads = pn_index_get_info(idx)["n_reads"]
+    kg, karr = _k_args(k, n_reads)
     cp = ctypes.c_void_p()
     n = _u64()
     seeds = _u64()
-    _check(_lib.pn_filter(ctx, ref, idx, ctypes.byref(cp), ctypes.byref(n), ctypes.byref(seeds)),
-           "pn_filter")
+    _check(_lib.pn_filter(ctx, ref, idx, kg, None if karr is None else _ptr(karr), ctypes.byref(cp),
+                          ctypes.byref(n), ctypes.byref(seeds)), "pn_filter")
     return _take_hits(cp, n.value, CAND_DTYPE), seeds.value
 
 

@@ -625,7 +625,7 @@ int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, hipStream_t st) {
     PN_CHECK(ensure(c, c->rinfo, (uint64_t)x->n_reads + 1));
     PN_CHECK(ensure(c, c->side, std::max<uint64_t>(x->lc_total, 1) * 8));
-    PN_CHECK(ensure(c, c->side_meta, 2 * pn::kLcPatterns * 4));
+    PN_CHECK(ensure(c, c->side_meta, 7 * pn::kLcPatterns * 4));
     uint32_t starts[pn::kLcPatterns];
     uint64_t at = 0;
     for (int i = 0; i < pn::kLcPatterns; i++) {
@@ -637,7 +637,9 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     PnIndexDev ix = index_desc(x);
     pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->rinfo.p, (uint32_t *)&c->misc[kStatus],
                           st);
-    uint32_t *meta = (uint32_t *)c->side_meta.p;
+    pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->rinfo.p, st);
+    uint32_t *meta = (uint32_t *)c->side_meta.p;  // 16 region starts, then 16 x 6 class bounds
+    pn::launch_fill_u32(meta + pn::kLcPatterns, 6 * pn::kLcPatterns, 0u, st);
     if (x->n_reads)
         pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
                            meta + pn::kLcPatterns, st);
@@ -653,8 +655,8 @@ void launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStre
     pn::FilterOut fo{(uint2 *)c->cands.p, (unsigned long long *)&c->misc[kCandCount],
                      c->cand_cap, (unsigned long long *)&c->misc[kSeeds]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
-    pn::launch_filter(ref_desc(ref), index_desc(x), (const uint8_t *)c->rinfo.p,
-                      (const unsigned long long *)c->side.p, meta, meta + pn::kLcPatterns, fo, st);
+    pn::launch_filter(ref_desc(ref), index_desc(x), (const unsigned long long *)c->side.p,
+                      meta + pn::kLcPatterns, fo, st);
     stage_end(c, st, tok, 1);
 }
 
@@ -859,6 +861,8 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         std::free(h);
         return s;
     }
+    // padding slots (read id all ones) sort last
+    while (n && h[n - 1].read_id == 0x7fffffffu) n--;
     *cands = h;
     *n_cands = n;
     if (n_seeds) *n_seeds = seeds;

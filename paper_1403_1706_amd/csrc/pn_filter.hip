@@ -38,8 +38,10 @@
 //     window).
 //
 // Candidates are staged per wave in LDS and appended to the output with one
-// atomic add per wave; the total is counted even past the capacity so that
-// the host can grow the buffer and run again.
+// atomic add per wave.  A lane that finds the wave's buffer full reserves
+// output slots 64 at a time; slots it does not use are filled with
+// PN_CAND_NONE, which verification skips.  The slot total is counted even
+// past the capacity so that the host can grow the buffer and run again.
 #include "pn_internal.h"
 
 namespace {
@@ -63,31 +65,70 @@ __device__ __forceinline__ uint32_t base_rel(uint64_t X, int t) {
     return (uint32_t)(X >> (62 - 2 * t)) & 3u;
 }
 
+constexpr uint32_t kLaneChunk = 64;  // slots a lane reserves at a time
+
 struct Stage {
     uint2 *buf;      // this wave's LDS buffer
     uint32_t *cnt;   // this wave's LDS counter
     pn::FilterOut out;
+    unsigned long long lane_base;  // this lane's reserved slots
+    uint32_t lane_left;
 };
 
-__device__ __forceinline__ void push(const Stage &sg, uint2 c) {
+__device__ __forceinline__ void push(Stage &sg, uint2 c) {
     uint32_t i = atomicAdd(sg.cnt, 1u);
     if (i < kWBuf) {
         sg.buf[i] = c;
-    } else {
-        unsigned long long at = atomicAdd(sg.out.count, 1ull);
-        if (at < sg.out.capacity) sg.out.cands[at] = c;
+        return;
     }
+    if (sg.lane_left == 0) {
+        sg.lane_base = atomicAdd(sg.out.count, (unsigned long long)kLaneChunk);
+        sg.lane_left = kLaneChunk;
+    }
+    const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left);
+    sg.lane_left--;
+    if (at < sg.out.capacity) sg.out.cands[at] = c;
 }
 
 // one (position, strand): INDEXPAIR and the rules of the header comment
+// One occurrence.  The read's rule bits (keep flag, required extra run) were
+// stamped into the entry's low byte for this mapping call (k_stamp_rules).
+__device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uint32_t s,
+                                      bool has_prev, uint32_t prev, bool lh, uint32_t N,
+                                      uint32_t avail, Stage &sg) {
+    const uint32_t hi = (uint32_t)(v >> 32);
+    const uint32_t cls = hi >> 29;
+    const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
+    const uint32_t o = hi & 0xffu;
+    const uint32_t info = (uint32_t)v & 0xffu;
+    const bool keep = (info >> 7) & 1u;
+    if (has_prev && cls == prev && (keep || !lh)) return;  // rule 1
+    const uint32_t need = info & 7u;                         // rule 3
+    if (need) {
+        const uint32_t nav = (uint32_t)(v >> 21) & 7u;
+        const uint32_t next4 = (uint32_t)(v >> 24) & 0xffu;
+        if (nav < need || avail < need || ((next4 ^ N) >> (8 - 2 * need)) != 0u) return;
+    }
+    push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+}
+
+// Slices longer than this are walked by the whole wave together.
+constexpr uint32_t kBigSlice = 64;
+
+// INDEXPAIR(g) and the occurrence ranges to visit for one (position,
+// strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
+// the low-complexity side lists).  Returns k_end - k_start.
+struct Ranges {
+    const unsigned long long *src;
+    uint32_t a0, a1, b0, b1;
+};
+
 template <typename TW>
-__device__ __forceinline__ unsigned long long probe(const PnIndexDev &ix, const uint8_t *rinfo,
-                                                    const unsigned long long *side,
-                                                    const uint32_t *side_start,
-                                                    const uint32_t *side_count, uint32_t g,
-                                                    int64_t p, uint32_t s, bool has_prev,
-                                                    uint32_t prev, bool lh, uint32_t N,
-                                                    uint32_t avail, const Stage &sg) {
+__device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned long long *side,
+                                          const uint32_t *side_cls, uint32_t g, bool has_prev,
+                                          uint32_t prev, Ranges &rg) {
+    rg.src = ix.O;
+    rg.a0 = rg.a1 = rg.b0 = rg.b1 = 0;
     const TW *I = (const TW *)ix.I;
     const uint32_t wmask = (1u << ix.log2w) - 1;
     const uint32_t i = g >> ix.log2w, j = g & wmask;
@@ -96,83 +137,113 @@ __device__ __forceinline__ unsigned long long probe(const PnIndexDev &ix, const 
     const uint32_t jp = (uint32_t)pn_popc<TW>(word & (((TW)1 << j) - 1));  // GROUPRANK
     const uint32_t x = ix.S[i] + jp;
     const uint32_t ks = ix.Sp[x], ke = ix.Sp[x + 1];
-    const unsigned long long *src = ix.O + ks;
-    uint32_t m = ke - ks;
-    if (pn_low_complexity(g, ix.q)) {  // rule 2: only reads that keep these seeds
-        const uint32_t id = g >> (2 * ix.q - 4);
-        src = side + side_start[id];
-        m = side_count[id];
+    if (pn_low_complexity(g, ix.q)) {
+        // rule 2: only reads that keep these seeds, listed by preceding
+        // letter; for those reads rule 1 drops the class equal to `prev`
+        const uint32_t *cb = side_cls + (g >> (2 * ix.q - 4)) * 6;
+        rg.src = side;
+        rg.a0 = cb[0];
+        rg.b1 = cb[5];
+        rg.a1 = has_prev ? cb[prev] : rg.b1;
+        rg.b0 = has_prev ? cb[prev + 1] : rg.b1;
+    } else {
+        rg.a0 = ks;
+        rg.a1 = ke;
+        rg.b0 = rg.b1 = ke;
     }
-    for (uint32_t t = 0; t < m; t++) {
-        const unsigned long long v = src[t];
-        const uint32_t hi = (uint32_t)(v >> 32);
-        const uint32_t cls = hi >> 29;
-        const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
-        const uint32_t o = hi & 0xffu;
-        const uint32_t info = rinfo[r];
-        const bool keep = (info >> 7) & 1u;
-        if (has_prev && cls == prev && (keep || !lh)) continue;  // rule 1
-        const uint32_t need = info & 7u;                           // rule 3
-        if (need) {
-            const uint32_t nav = (uint32_t)(v >> 21) & 7u;
-            const uint32_t next4 = (uint32_t)(v >> 24) & 0xffu;
-            if (nav < need || avail < need || ((next4 ^ N) >> (8 - 2 * need)) != 0u) continue;
-        }
-        push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+    return ke - ks;
+}
+
+// visit one (position, strand): short ranges by this lane, long ones by
+// the whole wave (every lane of the wave must call this together)
+__device__ __forceinline__ void visit_all(const Ranges &rg, int64_t p, uint32_t s, bool has_prev,
+                                          uint32_t prev, bool lh, uint32_t N, uint32_t avail,
+                                          bool valid, Stage &sg) {
+    const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
+    const bool big = valid && len > kBigSlice;
+    if (valid && !big) {
+        for (uint32_t t = rg.a0; t < rg.a1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
+        for (uint32_t t = rg.b0; t < rg.b1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
     }
-    return (unsigned long long)(ke - ks);
+    unsigned long long mask = __ballot(big);
+    const int lane = threadIdx.x & 63;
+    while (mask) {
+        const int leader = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const unsigned long long *src = (const unsigned long long *)__shfl((long long)rg.src, leader);
+        const uint32_t a0 = __shfl(rg.a0, leader), a1 = __shfl(rg.a1, leader);
+        const uint32_t b0 = __shfl(rg.b0, leader), b1 = __shfl(rg.b1, leader);
+        const int64_t lp = __shfl((long long)p, leader);
+        const uint32_t flags = __shfl((has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
+                                          (avail << 4) | (N << 8),
+                                      leader);
+        const bool lhp = flags & 1u, llh = (flags >> 1) & 1u;
+        const uint32_t lprev = (flags >> 2) & 3u, lavail = (flags >> 4) & 7u, lN = (flags >> 8) & 0xffu;
+        for (uint32_t t = a0 + lane; t < a1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
+        for (uint32_t t = b0 + lane; t < b1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
+    }
 }
 
 template <typename TW>
 __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
-                                               const uint8_t *__restrict__ rinfo,
                                                const unsigned long long *__restrict__ side,
-                                               const uint32_t *__restrict__ side_start,
-                                               const uint32_t *__restrict__ side_count,
+                                               const uint32_t *__restrict__ side_cls,
                                                pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBuf];
     __shared__ uint32_t wcnt[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
-    const Stage sg{wbuf[wave], &wcnt[wave], out};
+    Stage sg{wbuf[wave], &wcnt[wave], out, 0ull, 0u};
     const int q = ix.q;
     const uint64_t L = ref.L;
     const uint64_t u0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kPPT;
     unsigned long long seeds = 0;
-    if (u0 + q <= L) {
+    // every lane runs the same 8 positions so that long slices can be
+    // shared by the wave; lanes past the end carry valid = false
+    const bool any = u0 + q <= L;
+    const uint64_t X = any ? window32(ref.packed, (int64_t)u0 - 5) : 0ull;
+    for (int jj = 0; jj < kPPT; jj++) {
+        const uint64_t u = u0 + jj;
+        const bool valid = any && u + q <= L;
         // bases u0-5 .. u0+26: one letter before, q letters, four after on
         // strand 0, and four before on the forward strand for strand 1
-        const uint64_t X = window32(ref.packed, (int64_t)u0 - 5);
-        for (int jj = 0; jj < kPPT; jj++) {
-            const uint64_t u = u0 + jj;
-            if (u + q > L) break;
-            const int t0 = jj + 5;  // window index of base u
-            const uint32_t g0 = (uint32_t)((X << (2 * t0)) >> (64 - 2 * q));
-            const uint32_t g1 = pn_revcomp_code(g0, q);
-            // strand 0 at p = u
-            const bool has0 = u >= 1;
-            const uint32_t prev0 = base_rel(X, t0 - 1);
-            const uint32_t N0 = (uint32_t)((X << (2 * (t0 + q))) >> 56);
-            const uint64_t after0 = L - u - q;
-            const uint32_t avail0 = after0 < 4 ? (uint32_t)after0 : 4u;
-            const bool lh0 = has0 && pn_low_complexity((prev0 << (2 * (q - 1))) | (g0 >> 2), q);
-            // strand 1 at p = L-q-u: T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
-            const bool has1 = after0 >= 1;
-            const uint32_t prev1 = 3u - base_rel(X, t0 + q);
-            const uint32_t F = (uint32_t)(X >> (62 - 2 * (t0 - 1))) & 0xffu;  // R[u-4..u-1]
-            const uint32_t N1 = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) |
-                                 (F >> 6)) ^ 0xffu;
-            const uint32_t avail1 = u < 4 ? (uint32_t)u : 4u;
-            const bool lh1 = has1 && pn_low_complexity((prev1 << (2 * (q - 1))) | (g1 >> 2), q);
-            seeds += probe<TW>(ix, rinfo, side, side_start, side_count, g0, (int64_t)u, 0u, has0,
-                               prev0, lh0, N0, avail0, sg);
-            seeds += probe<TW>(ix, rinfo, side, side_start, side_count, g1,
-                               (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, sg);
+        const int t0 = jj + 5;  // window index of base u
+        const uint32_t g0 = (uint32_t)((X << (2 * t0)) >> (64 - 2 * q));
+        const uint32_t g1 = pn_revcomp_code(g0, q);
+        // strand 0 at p = u
+        const bool has0 = u >= 1;
+        const uint32_t prev0 = base_rel(X, t0 - 1);
+        const uint32_t N0 = (uint32_t)((X << (2 * (t0 + q))) >> 56);
+        const uint64_t after0 = valid ? L - u - q : 0;
+        const uint32_t avail0 = after0 < 4 ? (uint32_t)after0 : 4u;
+        const bool lh0 = has0 && pn_low_complexity((prev0 << (2 * (q - 1))) | (g0 >> 2), q);
+        // strand 1 at p = L-q-u: T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
+        const bool has1 = after0 >= 1;
+        const uint32_t prev1 = 3u - base_rel(X, t0 + q);
+        const uint32_t F = (uint32_t)(X >> (62 - 2 * (t0 - 1))) & 0xffu;  // R[u-4..u-1]
+        const uint32_t N1 = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) |
+                             (F >> 6)) ^ 0xffu;
+        const uint32_t avail1 = u < 4 ? (uint32_t)u : 4u;
+        const bool lh1 = has1 && pn_low_complexity((prev1 << (2 * (q - 1))) | (g1 >> 2), q);
+        Ranges r0, r1;
+        if (valid) {
+            seeds += probe<TW>(ix, side, side_cls, g0, has0, prev0, r0);
+            seeds += probe<TW>(ix, side, side_cls, g1, has1, prev1, r1);
+        } else {
+            r0.src = r1.src = ix.O;
+            r0.a0 = r0.a1 = r0.b0 = r0.b1 = r1.a0 = r1.a1 = r1.b0 = r1.b1 = 0;
         }
+        visit_all(r0, (int64_t)u, 0u, has0, prev0, lh0, N0, avail0, valid, sg);
+        visit_all(r1, (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, valid, sg);
     }
     for (int o = 32; o > 0; o >>= 1) seeds += __shfl_xor(seeds, o);
     if (lane == 0 && seeds) atomicAdd(out.n_seeds, seeds);
+    // pad the unused part of this lane's reserved slots
+    for (uint32_t i = 0; i < sg.lane_left; i++) {
+        const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;
+        if (at < out.capacity) out.cands[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    }
     __syncthreads();
     // flush this wave's staged candidates with one atomic add
     const uint32_t n = min(wcnt[wave], (uint32_t)kWBuf);
@@ -220,13 +291,14 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
 }
 
 // side lists: for each of the 16 low-complexity q-grams (first two letters
-// x, y; then x y x y ...), the occurrences from reads that keep them.  One
-// block per q-gram; `cap_start` are the host-computed list starts.
+// x, y; then x y x y ...), the occurrences from reads that keep them, grouped
+// by the letter before the q-gram (class 0..4).  One block per q-gram;
+// `region` holds the host-computed list starts; side_cls[id*6 + c] receives
+// the start of class c and side_cls[id*6 + 5] the end.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_lc_side(PnIndexDev ix, const uint8_t *__restrict__ rinfo,
-                                                 unsigned long long *side,
-                                                 const uint32_t *side_start,
-                                                 uint32_t *side_count) {
+                                                 unsigned long long *side, const uint32_t *region,
+                                                 uint32_t *side_cls) {
     const uint32_t id = blockIdx.x;
     const uint32_t x = id >> 2, y = id & 3u;
     uint32_t g = 0;
@@ -241,22 +313,36 @@ __global__ __launch_bounds__(256) void k_lc_side(PnIndexDev ix, const uint8_t *_
         ks = ix.Sp[slot];
         ke = ix.Sp[slot + 1];
     }
-    uint32_t at = side_start[id];
-    for (uint32_t base = ks; base < ke; base += 256) {
-        const uint32_t i = base + threadIdx.x;
-        unsigned long long v = 0;
-        uint32_t f = 0;
-        if (i < ke) {
-            v = ix.O[i];
-            const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
-            f = (rinfo[r] >> 7) & 1u;
+    uint32_t at = region[id];
+    for (uint32_t cls = 0; cls <= PN_CLS_NONE; cls++) {
+        if (threadIdx.x == 0) side_cls[id * 6 + cls] = at;
+        for (uint32_t base = ks; base < ke; base += 256) {
+            const uint32_t i = base + threadIdx.x;
+            unsigned long long v = 0;
+            uint32_t f = 0;
+            if (i < ke) {
+                v = ix.O[i];
+                const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
+                f = ((rinfo[r] >> 7) & 1u) && (uint32_t)(v >> 61) == cls;
+            }
+            uint32_t tot;
+            const uint32_t ex = pn_block_excl_scan(f, &tot);
+            if (f) side[at + ex] = v;
+            at += tot;
         }
-        uint32_t tot;
-        const uint32_t ex = pn_block_excl_scan(f, &tot);
-        if (f) side[at + ex] = v;
-        at += tot;
     }
-    if (threadIdx.x == 0) side_count[id] = at - side_start[id];
+    if (threadIdx.x == 0) side_cls[id * 6 + 5] = at;
+}
+
+// copy each read's rule bits (keep flag << 7 | required extra run) into the
+// low byte of its O entries, so that the filter reads them with the entry
+__global__ void k_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *__restrict__ rinfo) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long v = O[i];
+        const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
+        O[i] = (v & ~0xffull) | rinfo[r];
+    }
 }
 
 // occurrence counts of the 16 low-complexity q-grams (sizes of their O slices)
@@ -299,27 +385,33 @@ void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint
 }
 
 void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
-                    uint32_t *side_start, uint32_t *side_count, hipStream_t st) {
+                    const uint32_t *region, uint32_t *side_cls, hipStream_t st) {
     if (ix.log2w == 6)
         hipLaunchKernelGGL(k_lc_side<unsigned long long>, dim3(kLcPatterns), dim3(256), 0, st, ix,
-                           rinfo, side, side_start, side_count);
+                           rinfo, side, region, side_cls);
     else
         hipLaunchKernelGGL(k_lc_side<uint32_t>, dim3(kLcPatterns), dim3(256), 0, st, ix, rinfo,
-                           side, side_start, side_count);
+                           side, region, side_cls);
 }
 
-void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const uint8_t *rinfo,
-                   const unsigned long long *side, const uint32_t *side_start,
-                   const uint32_t *side_count, FilterOut out, hipStream_t st) {
+void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st) {
+    if (!n) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_stamp_rules, dim3((unsigned)blocks), dim3(256), 0, st, O, n, rinfo);
+}
+
+void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const unsigned long long *side,
+                   const uint32_t *side_cls, FilterOut out, hipStream_t st) {
     const uint64_t npos = ref.L >= (uint64_t)ix.q ? ref.L - ix.q + 1 : 0;
     const uint64_t nb = (npos + kFilterBlockPos - 1) / kFilterBlockPos;
     if (!nb || !ix.n_reads) return;
     if (ix.log2w == 6)
         hipLaunchKernelGGL(k_filter<unsigned long long>, dim3((unsigned)nb), dim3(kT), 0, st, ref,
-                           ix, rinfo, side, side_start, side_count, out);
+                           ix, side, side_cls, out);
     else
-        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, ix, rinfo,
-                           side, side_start, side_count, out);
+        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, ix, side,
+                           side_cls, out);
 }
 
 }  // namespace pn

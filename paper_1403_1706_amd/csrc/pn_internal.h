@@ -12,8 +12,10 @@
 //  * read planes: per read, PN_READ_WORDS uint2 {H, L} words (LSB-first).
 //  * O entry (64 bits): high word (cls << 29) | (read << 8) | offset, cls =
 //    code of the letter before the q-gram in its read or 4 at offset 0; low
-//    word (next4 << 24) | (nav << 21): the (up to) four read letters after
-//    the q-gram, first letter in the top bits, and how many exist (0..4).
+//    word (next4 << 24) | (nav << 21) | rule byte: the (up to) four read
+//    letters after the q-gram, first letter in the top bits, how many exist
+//    (0..4), and in the low byte the read's seed-rule bits of the current
+//    mapping call (written by launch_stamp_rules).
 //  * low-complexity q-grams: period <= 2 (homopolymers and dinucleotide
 //    repeats), see pn_low_complexity.
 #pragma once
@@ -29,6 +31,7 @@
 #define PN_PAD_POS (32 * PN_PAD_BLOCKS)
 #define PN_DBIAS 65536u
 #define PN_CLS_NONE 4u
+#define PN_CAND_NONE 0xffffffffu  // padding slot in the candidate array
 
 // ---------------------------------------------------------------------------
 // descriptors passed by value to kernels
@@ -183,11 +186,13 @@ void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint
 // sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)
 void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st);
 // low-complexity occurrence lists restricted to reads that keep them
+// (grouped by preceding letter; side_cls: 6 bounds per q-gram)
 void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
-                    uint32_t *side_start, uint32_t *side_count, hipStream_t st);
-void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const uint8_t *rinfo,
-                   const unsigned long long *side, const uint32_t *side_start,
-                   const uint32_t *side_count, FilterOut out, hipStream_t st);
+                    const uint32_t *region, uint32_t *side_cls, hipStream_t st);
+// write each read's rule byte into the low byte of its O entries
+void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st);
+void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const unsigned long long *side,
+                   const uint32_t *side_cls, FilterOut out, hipStream_t st);
 
 // pn_verify.hip (Section 3.3)
 struct VerifyOut {

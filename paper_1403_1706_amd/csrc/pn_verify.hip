@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_verify(PnRefDev ref, PnIndexDev ix,
     unsigned long long rows = 0;
     for (uint64_t ci = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < n; ci += stride) {
         const uint2 c = cands[ci];
+        if (c.x == PN_CAND_NONE) continue;  // padding slot
         const uint32_t r = c.x & 0x7fffffffu;
         const uint32_t s = c.x >> 31;
         const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;

@@ -19,7 +19,8 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpeanut.so")
+# PEANUT_LIB may name another build of the same library
+LIB_PATH = os.environ.get("PEANUT_LIB", os.path.join(_HERE, "libpeanut.so"))
 
 PN_OK = 0
 PN_EINVAL = -1

@@ -28,12 +28,13 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kStatT = 2,
     kStatBad = 3,
     kSeeds = 4,
-    kRecCount = 5,
     kOutCount = 6,
     kBigCount = 7,
     kVerifyRows = 8,
-    kCandCount = 9,
-    kMiscWords = 12
+    kCandCounts = 16,                        // pn::kShards words each
+    kRecCounts = kCandCounts + pn::kShards,
+    kLongCounts = kRecCounts + pn::kShards,
+    kMiscWords = kLongCounts + pn::kShards
 };
 
 struct PendingStage {
@@ -52,9 +53,11 @@ struct pn_ctx {
     uint64_t *misc = nullptr;             // device scratch words (MiscSlot)
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
-    Buf cands, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
+    Buf cands, longc, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
         out_hits;
-    uint64_t cand_cap = 1ull << 24;  // candidate buffer capacity (grows on demand)
+    // capacities per output region (pn::kShards regions; grow on demand)
+    uint64_t cand_rcap = 1ull << 18;
+    uint64_t rec_rcap = 1ull << 14;
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -652,65 +655,103 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
 
 void launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
     const uint32_t *meta = (const uint32_t *)c->side_meta.p;
-    pn::FilterOut fo{(uint2 *)c->cands.p, (unsigned long long *)&c->misc[kCandCount],
-                     c->cand_cap, (unsigned long long *)&c->misc[kSeeds]};
+    pn::FilterOut fo{(uint2 *)c->cands.p,
+                     {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
+                     (unsigned long long *)&c->misc[kSeeds]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
     pn::launch_filter(ref_desc(ref), index_desc(x), (const unsigned long long *)c->side.p,
                       meta + pn::kLcPatterns, fo, st);
     stage_end(c, st, tok, 1);
 }
 
-// filtration + validation; leaves the sorted record keys in c->keys and
-// their count in *n_rec.  Capacities of the candidate and record buffers
-// grow (and the pass is repeated) when a run overflowed them.
-int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
-                hipStream_t st, uint64_t *n_rec) {
-    PN_CHECK(prepare_rules(c, x, kglob, d_k, st));
+// largest and total count of a sharded list (host mirror)
+void region_counts(const pn_ctx *c, int slot, uint32_t regions, uint64_t *mx, uint64_t *total) {
+    *mx = *total = 0;
+    for (uint32_t g = 0; g < regions; g++) {
+        *mx = std::max<uint64_t>(*mx, c->hmisc[slot + g]);
+        *total += c->hmisc[slot + g];
+    }
+}
+
+void zero_counts(pn_ctx *c, int slot, hipStream_t st) {
+    pn::launch_fill_u32((uint32_t *)&c->misc[slot], 2 * pn::kShards, 0u, st);
+}
+
+// validation of the candidates `in` (both passes), records into the
+// sharded c->keys_tmp; grows the record regions and runs again on overflow.
+// Leaves the records, gathered and sorted, in c->keys and their count in
+// *n_rec.  With `filter`, each attempt also runs filtration first (its
+// candidate regions may overflow too).
+int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
+                    bool filter, uint64_t n_in, hipStream_t st, uint64_t *n_rec) {
     const int ebits = key_ebits(ref->L);
-    uint64_t rec_cap =
-        std::max<uint64_t>(c->keys.cap / 8, std::max<uint64_t>(1u << 20, 16ull * x->n_reads));
+    c->rec_rcap = std::max<uint64_t>(c->rec_rcap, (16ull * x->n_reads) / pn::kShards + 4096);
     for (int attempt = 0; attempt < 8; attempt++) {
-        PN_CHECK(ensure(c, c->cands, c->cand_cap * sizeof(uint2)));
-        c->cand_cap = c->cands.cap / sizeof(uint2);
-        PN_CHECK(ensure(c, c->keys, rec_cap * 8));
-        rec_cap = c->keys.cap / 8;
+        const uint32_t regions = filter ? pn::kShards : 1;
+        const uint64_t in_rcap = filter ? c->cand_rcap : std::max<uint64_t>(n_in, 1);
+        PN_CHECK(ensure(c, c->cands, regions * in_rcap * sizeof(uint2)));
+        PN_CHECK(ensure(c, c->longc, regions * in_rcap * sizeof(uint2)));
+        PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
         pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kRecCount], 2, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);  // rows + candidates
-        launch_filter_into(c, ref, x, st);
-        pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
-                         (unsigned long long *)&c->misc[kVerifyRows], rec_cap, ebits};
+        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 2, 0u, st);
+        zero_counts(c, kRecCounts, st);
+        zero_counts(c, kLongCounts, st);
+        if (filter) {
+            zero_counts(c, kCandCounts, st);
+            launch_filter_into(c, ref, x, st);
+        } else {
+            zero_counts(c, kCandCounts, st);
+            pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n_in, st);
+        }
+        pn::VerifyIn in{(const uint2 *)c->cands.p, (const unsigned long long *)&c->misc[kCandCounts],
+                        regions, in_rcap};
+        pn::VerifyOut vo{(unsigned long long *)c->keys_tmp.p,
+                         {(unsigned long long *)&c->misc[kRecCounts], c->rec_rcap},
+                         (unsigned long long *)&c->misc[kVerifyRows], ebits};
         int tok = stage_begin(c, st, PN_STAGE_VERIFY);
-        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p,
-                          (const unsigned long long *)&c->misc[kCandCount], c->cand_cap, kglob, d_k,
-                          vo, st);
-        stage_end(c, st, tok, 1);
+        pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, (uint2 *)c->longc.p,
+                          (unsigned long long *)&c->misc[kLongCounts], st);
+        stage_end(c, st, tok, 2);
         PN_CHECK(read_misc(c, st));
-        const uint64_t n_cand = c->hmisc[kCandCount];
-        const uint64_t got = c->hmisc[kRecCount];
-        if (n_cand > c->cand_cap) {  // candidates overflowed: grow and run again
-            c->cand_cap = n_cand + n_cand / 4;
+        uint64_t cand_max, cand_total, rec_max, got;
+        region_counts(c, kCandCounts, regions, &cand_max, &cand_total);
+        region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
+        if (filter && cand_max > c->cand_rcap) {  // candidates overflowed: grow, run again
+            c->cand_rcap = cand_max + cand_max / 4;
             continue;
         }
-        if (got > rec_cap) {
-            rec_cap = got + got / 4;
+        if (rec_max > c->rec_rcap) {
+            c->rec_rcap = rec_max + rec_max / 4;
             continue;
         }
         *n_rec = got;
-        c->stats.n_seeds += c->hmisc[kSeeds];
-        c->stats.n_candidates += n_cand;
+        if (filter) {
+            c->stats.n_seeds += c->hmisc[kSeeds];
+            c->stats.n_candidates += cand_total;
+        }
         c->stats.verify_rows += c->hmisc[kVerifyRows];
         c->stats.n_records += got;
         const int bits = 6 + ebits + key_rbits(x->n_reads);
-        PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(got, 1) * 8));
+        PN_CHECK(ensure(c, c->keys, std::max<uint64_t>(got, 1) * 8));
         PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(got)));
         tok = stage_begin(c, st, PN_STAGE_SORT);
+        pn::launch_gather_shards((const unsigned long long *)c->keys_tmp.p,
+                                 (const unsigned long long *)&c->misc[kRecCounts], pn::kShards,
+                                 c->rec_rcap, (unsigned long long *)c->keys.p, st);
         pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
                            got, bits, c->sort_temp.p, st);
-        stage_end(c, st, tok, 3 * ((bits + 7) / 8));
+        stage_end(c, st, tok, 1 + 3 * ((bits + 7) / 8));
         return PN_OK;
     }
     return PN_ENOMEM;
+}
+
+// filtration + validation; leaves the sorted record keys in c->keys and
+// their count in *n_rec
+int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
+                hipStream_t st, uint64_t *n_rec) {
+    PN_CHECK(prepare_rules(c, x, kglob, d_k, st));
+    return validate_sorted(c, ref, x, kglob, d_k, true, 0, st, n_rec);
 }
 
 // duplicate removal + strata + output of the sorted records
@@ -823,17 +864,17 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
     int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
     uint64_t n = 0;
     for (int attempt = 0; !s && attempt < 8; attempt++) {
-        s = ensure(c, c->cands, c->cand_cap * sizeof(uint2));
+        s = ensure(c, c->cands, pn::kShards * c->cand_rcap * sizeof(uint2));
         if (s) break;
-        c->cand_cap = c->cands.cap / sizeof(uint2);
         pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kCandCount], 2, 0u, st);
+        zero_counts(c, kCandCounts, st);
         launch_filter_into(c, ref, x, st);
         s = read_misc(c, st);
         if (s) break;
-        n = c->hmisc[kCandCount];
-        if (n <= c->cand_cap) break;
-        c->cand_cap = n + n / 4;
+        uint64_t mx;
+        region_counts(c, kCandCounts, pn::kShards, &mx, &n);
+        if (mx <= c->cand_rcap) break;
+        c->cand_rcap = mx + mx / 4;
         n = 0;
     }
     const uint64_t seeds = s ? 0 : c->hmisc[kSeeds];
@@ -844,7 +885,12 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
     pn_candidate *h = nullptr;
     if (!s) {
         if (n) {
-            pn::launch_cand_keys((const uint2 *)c->cands.p, n, (unsigned long long *)c->keys.p, st);
+            pn::launch_gather_shards((const unsigned long long *)c->cands.p,
+                                     (const unsigned long long *)&c->misc[kCandCounts],
+                                     pn::kShards, c->cand_rcap,
+                                     (unsigned long long *)c->keys_tmp.p, st);
+            pn::launch_cand_keys((const uint2 *)c->keys_tmp.p, n, (unsigned long long *)c->keys.p,
+                                 st);
             pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
                                n, 33 + key_rbits(x->n_reads), c->sort_temp.p, st);
             pn::launch_keys_to_cands((const unsigned long long *)c->keys.p, n, c->out_hits.p, st);
@@ -890,33 +936,16 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
         PN_TRY(hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st));
     }
     int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
-    const uint64_t cap = std::max<uint64_t>(n * (2 * PN_MAX_K + 1), 1);
     if (!s) s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
-    if (!s) s = ensure(c, c->keys, cap * 8);
-    if (!s) s = ensure(c, c->keys_tmp, cap * 8);
     if (!s && n)
         s = map_err(hipMemcpyAsync(c->cands.p, host.data(), n * sizeof(uint2),
                                    hipMemcpyHostToDevice, st));
     uint64_t got = 0;
     const int ebits = key_ebits(ref->L);
-    if (!s) {
-        pn::launch_fill_u32((uint32_t *)&c->misc[kRecCount], 2, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kCandCount], 1, (uint32_t)n, st);
-        pn::VerifyOut vo{(unsigned long long *)c->keys.p, (unsigned long long *)&c->misc[kRecCount],
-                         (unsigned long long *)&c->misc[kVerifyRows], cap, ebits};
-        pn::launch_verify(ref_desc(ref), index_desc(x), (const uint2 *)c->cands.p,
-                          (const unsigned long long *)&c->misc[kCandCount], std::max<uint64_t>(n, 1),
-                          k < 0 ? -1 : k, dk, vo, st);
-        s = read_misc(c, st);
-        got = s ? 0 : c->hmisc[kRecCount];
-    }
-    if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(got));
+    if (!s) s = validate_sorted(c, ref, x, k < 0 ? -1 : k, dk, false, n, st, &got);
     if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(got, 1) * sizeof(pn_hit));
     pn_hit *h = nullptr;
     if (!s) {
-        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, got,
-                           6 + ebits + key_rbits(x->n_reads), c->sort_temp.p, st);
         pn::launch_records_to_hits((const unsigned long long *)c->keys.p, got, ebits, c->out_hits.p,
                                    st);
         h = (pn_hit *)std::malloc(std::max<uint64_t>(got, 1) * sizeof(pn_hit));

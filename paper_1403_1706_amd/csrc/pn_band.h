@@ -14,11 +14,14 @@ __host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo,
 // read's PN_READ_WORDS plane words; the band covers diagonals [lo, lo + 2k]
 // (lo = d - k); 1 <= len <= PN_MAX_READ_LEN; 0 <= k <= PN_MAX_K.  Calls
 // emit(end, value) for every end column of the last row with value <= k,
-// and returns the number of rows computed.
+// and returns the number of rows computed.  A candidate still alive after
+// row_cap rows (a multiple of 32, below len) stops there without emitting
+// and -row_cap is returned; the caller runs it again from row 0 without cap.
 template <typename Emit>
 __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__ pl,
                                                        const uint2 *__restrict__ rp, int len, int k,
-                                                       int64_t lo, uint64_t L, Emit &&emit) {
+                                                       int64_t lo, uint64_t L, int row_cap,
+                                                       Emit &&emit) {
     const int W = 2 * k + 1;
     const uint32_t M = (1u << W) - 1u;
     const uint32_t M2 = M & ~1u;
@@ -66,6 +69,7 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
             }
             if (R - __builtin_popcount(VP & M2) > k) return i;  // whole row above k
         }
+        if (32 * (m + 1) >= row_cap) return -32 * (m + 1);
         // advance the stream by 32 positions
         h0 = h1;
         l0 = l1;

@@ -37,11 +37,12 @@
 //     are compared (stored in the O entry and read from the reference
 //     window).
 //
-// Candidates are staged per wave in LDS and appended to the output with one
-// atomic add per wave.  A lane that finds the wave's buffer full reserves
-// output slots 64 at a time; slots it does not use are filled with
-// PN_CAND_NONE, which verification skips.  The slot total is counted even
-// past the capacity so that the host can grow the buffer and run again.
+// Candidates are staged per wave in LDS and appended to the block's output
+// region (one of kShards, each with its own counter) with one atomic add
+// per wave.  A lane that finds the wave's buffer full reserves output slots
+// 64 at a time; slots it does not use are filled with PN_CAND_NONE, which
+// verification skips.  Slots are counted even past a region's capacity so
+// that the host can grow the buffer and run again.
 #include "pn_internal.h"
 
 namespace {
@@ -70,7 +71,9 @@ constexpr uint32_t kLaneChunk = 64;  // slots a lane reserves at a time
 struct Stage {
     uint2 *buf;      // this wave's LDS buffer
     uint32_t *cnt;   // this wave's LDS counter
-    pn::FilterOut out;
+    uint2 *region;   // this block's output region
+    unsigned long long *count;  // its counter
+    uint64_t region_cap;
     unsigned long long lane_base;  // this lane's reserved slots
     uint32_t lane_left;
 };
@@ -82,12 +85,12 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
         return;
     }
     if (sg.lane_left == 0) {
-        sg.lane_base = atomicAdd(sg.out.count, (unsigned long long)kLaneChunk);
+        sg.lane_base = atomicAdd(sg.count, (unsigned long long)kLaneChunk);
         sg.lane_left = kLaneChunk;
     }
     const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left);
     sg.lane_left--;
-    if (at < sg.out.capacity) sg.out.cands[at] = c;
+    if (at < sg.region_cap) sg.region[at] = c;
 }
 
 // one (position, strand): INDEXPAIR and the rules of the header comment
@@ -194,7 +197,9 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
-    Stage sg{wbuf[wave], &wcnt[wave], out, 0ull, 0u};
+    const uint32_t shard = blockIdx.x % pn::kShards;
+    Stage sg{wbuf[wave], &wcnt[wave], out.cands + (uint64_t)shard * out.sh.region_cap,
+             out.sh.counts + shard, out.sh.region_cap, 0ull, 0u};
     const int q = ix.q;
     const uint64_t L = ref.L;
     const uint64_t u0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kPPT;
@@ -242,16 +247,16 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
     // pad the unused part of this lane's reserved slots
     for (uint32_t i = 0; i < sg.lane_left; i++) {
         const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;
-        if (at < out.capacity) out.cands[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+        if (at < sg.region_cap) sg.region[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
     }
     __syncthreads();
     // flush this wave's staged candidates with one atomic add
     const uint32_t n = min(wcnt[wave], (uint32_t)kWBuf);
     unsigned long long base = 0;
-    if (lane == 0 && n) base = atomicAdd(out.count, (unsigned long long)n);
+    if (lane == 0 && n) base = atomicAdd(sg.count, (unsigned long long)n);
     base = __shfl(base, 0);
     for (uint32_t i = lane; i < n; i += 64)
-        if (base + i < out.capacity) out.cands[base + i] = wbuf[wave][i];
+        if (base + i < sg.region_cap) sg.region[base + i] = wbuf[wave][i];
 }
 
 // ---------------------------------------------------------------------------

@@ -168,15 +168,24 @@ void launch_bucket_sort_big(const uint32_t *Sp, unsigned long long *O, unsigned 
                             const uint32_t *big_list, uint32_t n_big, hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
 
+// Append-only output split into kShards regions of `region_cap` entries,
+// each with its own counter: a thread block appends to region
+// blockIdx.x % kShards.  One counter taken by every wave of the chip
+// serialises at a single memory channel; 64 of them spread over channels.
+constexpr uint32_t kShards = 64;
+struct Shards {
+    unsigned long long *counts;  // kShards counters (may exceed region_cap)
+    uint64_t region_cap;
+};
+
 // pn_filter.hip (Algorithm 2)
 constexpr int kFilterThreads = 256;
 constexpr int kFilterPPT = 8;  // forward positions per thread
 constexpr int kFilterBlockPos = kFilterThreads * kFilterPPT;
 constexpr int kLcPatterns = 16;  // period <= 2 q-grams: first two letters
 struct FilterOut {
-    uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS)
-    unsigned long long *count;    // candidates produced (may exceed capacity)
-    uint64_t capacity;
+    uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS), kShards regions
+    Shards sh;                    // per-region append counters
     unsigned long long *n_seeds;  // occurrence pairs seen (sum of k_end - k_start)
 };
 // per read: bit 7 = keeps its low-complexity seeds, bits 0-2 = extra letters
@@ -195,17 +204,31 @@ void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const unsigned lon
                    const uint32_t *side_cls, FilterOut out, hipStream_t st);
 
 // pn_verify.hip (Section 3.3)
-struct VerifyOut {
-    unsigned long long *records;  // packed hit keys
-    unsigned long long *count;
-    unsigned long long *rows;     // band rows computed (work counter)
-    uint64_t capacity;
-    int ebits;  // bits for end positions in a key
+struct VerifyIn {
+    const uint2 *cands;
+    const unsigned long long *counts;  // candidates per region (may exceed region_cap)
+    uint32_t regions;                  // 1 or kShards
+    uint64_t region_cap;
 };
-// verifies min(*n_dev, cap) candidates (count read on the device)
-void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands,
-                   const unsigned long long *n_dev, uint64_t cap, int kglob, const uint8_t *kpr,
-                   VerifyOut out, hipStream_t st);
+struct VerifyOut {
+    unsigned long long *records;  // packed hit keys, kShards regions
+    Shards sh;
+    unsigned long long *rows;     // band rows computed (work counter)
+    int ebits;                    // bits for end positions in a key
+};
+// Two passes: every candidate for at most 32 rows, then the candidates still
+// alive from row 0 to the end.  `longc` (in.regions regions of
+// in.region_cap entries) and its counters `n_long` (in.regions words, zeroed
+// by the caller) hold the second pass's candidates.
+void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                   const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
+                   hipStream_t st);
+
+// pn_scan.hip: concatenate the regions of a sharded list (8-byte entries)
+// into dst; counts past region_cap are clipped
+void launch_gather_shards(const unsigned long long *src, const unsigned long long *counts,
+                          uint32_t regions, uint64_t region_cap, unsigned long long *dst,
+                          hipStream_t st);
 
 // pn_canon.hip: sort + duplicate removal + strata + output
 uint64_t radix_temp_size(uint64_t n);  // bytes

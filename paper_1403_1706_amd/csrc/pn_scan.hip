@@ -129,6 +129,22 @@ void scan_impl(Load load, uint32_t *out, uint64_t n, uint32_t *partials, hipStre
                        (const uint32_t *)partials, nb);
 }
 
+// Concatenation of a sharded list: block b copies part b / regions of
+// region b % regions to dst at the region's exclusive prefix of counts.
+__global__ __launch_bounds__(256) void k_gather_shards(const unsigned long long *__restrict__ src,
+                                                       const unsigned long long *__restrict__ counts,
+                                                       uint32_t regions, uint64_t region_cap,
+                                                       unsigned long long *__restrict__ dst) {
+    const uint32_t g = blockIdx.x % regions;
+    uint64_t start = 0;
+    for (uint32_t t = 0; t < g; t++) start += min((uint64_t)counts[t], region_cap);
+    const uint64_t n = min((uint64_t)counts[g], region_cap);
+    const uint64_t per = gridDim.x / regions;
+    const unsigned long long *s = src + (uint64_t)g * region_cap;
+    for (uint64_t i = (blockIdx.x / regions) * 256 + threadIdx.x; i < n; i += per * 256)
+        dst[start + i] = s[i];
+}
+
 }  // namespace
 
 namespace pn {
@@ -146,6 +162,16 @@ void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint3
         scan_impl(LoadPopc<uint64_t>{(const uint64_t *)I}, out, n, partials, st);
     else
         scan_impl(LoadPopc<uint32_t>{(const uint32_t *)I}, out, n, partials, st);
+}
+
+void launch_gather_shards(const unsigned long long *src, const unsigned long long *counts,
+                          uint32_t regions, uint64_t region_cap, unsigned long long *dst,
+                          hipStream_t st) {
+    if (!regions || !region_cap) return;
+    uint64_t per = (region_cap + 255) / 256;
+    if (per > 64) per = 64;
+    hipLaunchKernelGGL(k_gather_shards, dim3((unsigned)(per * regions)), dim3(256), 0, st, src,
+                       counts, regions, region_cap, dst);
 }
 
 }  // namespace pn

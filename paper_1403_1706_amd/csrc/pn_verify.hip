@@ -23,54 +23,142 @@
 // its row exceeds k (the row minimum never decreases from one row to the
 // next; bounded below by R - #(+1 steps)), or after row n, where it reports
 // each end column with value <= k.
+//
+// Lanes of a wave run in lockstep, so a wave costs as many rows as its
+// longest candidate.  Most candidates end within a few rows while true hits
+// run the full read, so verification takes two passes: every candidate for
+// at most 32 rows, then only the survivors, packed densely, to the end.
+// Records and survivors are staged per wave in LDS and appended with one
+// atomic per flush to one of kShards output regions.
+#include <algorithm>
+
 #include "pn_band.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_verify(PnRefDev ref, PnIndexDev ix,
-                                                const uint2 *__restrict__ cands,
-                                                const unsigned long long *__restrict__ n_dev,
-                                                uint64_t cap, int kglob,
-                                                const uint8_t *__restrict__ kpr,
-                                                pn::VerifyOut out) {
-    const uint64_t n = min((uint64_t)*n_dev, cap);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    unsigned long long rows = 0;
-    for (uint64_t ci = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < n; ci += stride) {
-        const uint2 c = cands[ci];
-        if (c.x == PN_CAND_NONE) continue;  // padding slot
-        const uint32_t r = c.x & 0x7fffffffu;
-        const uint32_t s = c.x >> 31;
-        const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
-        const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
-        const int k = kglob >= 0 ? kglob : (int)kpr[r];
-        if (k > PN_MAX_K || len < 1 || len > PN_MAX_READ_LEN) continue;
-        const unsigned long long head = (((unsigned long long)r << 1) | s) << out.ebits;
-        rows += (unsigned long long)pn_band_verify(
-            s ? ref.planes[1] : ref.planes[0], ix.rplanes + (uint64_t)r * PN_READ_WORDS, len, k,
-            d - k, ref.L, [&](uint32_t e, int v) {
-                unsigned long long at = atomicAdd(out.count, 1ull);
-                if (at < out.capacity)
-                    out.records[at] = ((head | (unsigned long long)e) << 5) | (unsigned long long)v;
-            });
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr uint32_t kStage = 512;  // staged entries per wave
+constexpr int kShortRows = 32;    // row cap of the first pass
+
+// Entries (8 bytes) staged per wave in LDS and appended to one output region
+// with one global atomic per flush.  A lane that finds the stage full takes
+// a global slot of its own.
+struct Stage {
+    unsigned long long *buf;    // this wave's LDS stage
+    uint32_t *cnt;              // this wave's LDS counter
+    unsigned long long *region; // output region
+    unsigned long long *count;  // its counter
+    uint64_t cap;               // its capacity
+
+    __device__ __forceinline__ void push(unsigned long long v) {
+        const uint32_t i = atomicAdd(cnt, 1u);
+        if (i < kStage) {
+            buf[i] = v;
+            return;
+        }
+        const unsigned long long at = atomicAdd(count, 1ull);
+        if (at < cap) region[at] = v;
     }
+
+    // whole wave, converged
+    __device__ __forceinline__ void flush(int lane) {
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t n = min(*cnt, kStage);
+        if (n == 0) return;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)n);
+        base = __shfl(base, 0);
+        for (uint32_t i = lane; i < n; i += 64)
+            if (base + i < cap) region[base + i] = buf[i];
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) *cnt = 0;
+        __builtin_amdgcn_wave_barrier();
+    }
+};
+
+// Block b reads input region b % in.regions; its records go to output
+// region b % kShards and (first pass) its survivors to long region
+// b % in.regions, which can hold every candidate of that input region.
+template <bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_verify(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
+                                                     int kglob, const uint8_t *__restrict__ kpr,
+                                                     pn::VerifyOut out, uint2 *longc,
+                                                     unsigned long long *n_long) {
+    __shared__ unsigned long long s_rec[kWaves][kStage];
+    __shared__ unsigned long long s_long[kFirst ? kWaves : 1][kFirst ? kStage : 1];
+    __shared__ uint32_t s_cnt[kWaves][2];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) s_cnt[wv][0] = s_cnt[wv][1] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t rin = blockIdx.x % in.regions;
+    const uint32_t rout = blockIdx.x % pn::kShards;
+    Stage rec{s_rec[wv], &s_cnt[wv][0], out.records + (uint64_t)rout * out.sh.region_cap,
+              out.sh.counts + rout, out.sh.region_cap};
+    Stage lng{s_long[kFirst ? wv : 0], &s_cnt[wv][1],
+              (unsigned long long *)longc + (uint64_t)rin * in.region_cap, n_long + rin,
+              in.region_cap};
+
+    const uint2 *cands = in.cands + (uint64_t)rin * in.region_cap;
+    const uint64_t n = min((uint64_t)in.counts[rin], in.region_cap);
+    const uint64_t per = gridDim.x / in.regions;  // blocks per input region
+    const uint64_t stride = per * kThreads;
+    unsigned long long rows = 0;
+    // the loop bound is wave-uniform, so the wave is converged at the flushes
+    for (uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64; base < n;
+         base += stride) {
+        const uint64_t ci = base + lane;
+        if (ci < n) {
+            const uint2 c = cands[ci];
+            if (c.x != PN_CAND_NONE) {  // else a padding slot
+                const uint32_t r = c.x & 0x7fffffffu;
+                const uint32_t s = c.x >> 31;
+                const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
+                const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
+                const int k = kglob >= 0 ? kglob : (int)kpr[r];
+                if (k <= PN_MAX_K && len >= 1 && len <= PN_MAX_READ_LEN) {
+                    const unsigned long long head = (((unsigned long long)r << 1) | s)
+                                                    << out.ebits;
+                    const int rw = pn_band_verify(
+                        s ? ref.planes[1] : ref.planes[0],
+                        ix.rplanes + (uint64_t)r * PN_READ_WORDS, len, k, d - k, ref.L,
+                        kFirst ? kShortRows : PN_MAX_READ_LEN, [&](uint32_t e, int v) {
+                            rec.push(((head | (unsigned long long)e) << 5) |
+                                     (unsigned long long)v);
+                        });
+                    if (kFirst && rw < 0) lng.push(((unsigned long long)c.y << 32) | c.x);
+                    rows += (unsigned long long)(rw < 0 ? -rw : rw);
+                }
+            }
+        }
+        if (*rec.cnt >= kStage / 2) rec.flush(lane);
+        if (kFirst && *lng.cnt >= kStage / 2) lng.flush(lane);
+    }
+    rec.flush(lane);
+    if (kFirst) lng.flush(lane);
     for (int o = 32; o > 0; o >>= 1) rows += __shfl_xor(rows, o);
-    if ((threadIdx.x & 63) == 0 && rows) atomicAdd(out.rows, rows);
+    if (lane == 0 && rows) atomicAdd(out.rows, rows);
 }
 
 }  // namespace
 
 namespace pn {
 
-void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, const uint2 *cands,
-                   const unsigned long long *n_dev, uint64_t cap, int kglob, const uint8_t *kpr,
-                   VerifyOut out, hipStream_t st) {
-    if (!cap) return;
-    // enough resident waves to fill the chip; each thread strides over candidates
-    uint64_t blocks = (cap + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_verify, dim3((unsigned)blocks), dim3(256), 0, st, ref, ix, cands, n_dev,
-                       cap, kglob, kpr, out);
+void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                   const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
+                   hipStream_t st) {
+    if (!in.region_cap || !in.regions) return;
+    // blocks: a multiple of the input regions, enough to fill the chip
+    uint64_t per = (in.region_cap + kThreads - 1) / kThreads;
+    const uint64_t max_per = std::max<uint64_t>(8192 / in.regions, 1);
+    if (per > max_per) per = max_per;
+    const dim3 grid((unsigned)(per * in.regions));
+    hipLaunchKernelGGL(k_verify<true>, grid, dim3(kThreads), 0, st, ref, ix, in, kglob, kpr, out,
+                       longc, n_long);
+    VerifyIn in2{longc, n_long, in.regions, in.region_cap};
+    hipLaunchKernelGGL(k_verify<false>, grid, dim3(kThreads), 0, st, ref, ix, in2, kglob, kpr, out,
+                       longc, n_long);
 }
 
 }  // namespace pn

@@ -39,6 +39,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none
+    for this workload or the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_traffic.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("workload_key") != workload:
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["sources_sha256"]:
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,8 +68,10 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--mode", default="all", choices=["all", "best"])
     ap.add_argument("--w", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-kernel", action="store_true",
+                    help="only copy 1 GiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -58,6 +80,15 @@ def main():
 
     import numpy as np
     import torch
+    if args.copy_kernel:
+        n = 1 << 30
+        a = torch.full((n,), 1, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes")
+        return
     from paper_1403_1706_amd import peanut as pn
     from paper_1403_1706_amd import synth
 
@@ -110,7 +141,9 @@ def main():
     launches = {s: st["launches"][s] / K for s in pn.STAGES}
     dominant = max(stage_ms, key=stage_ms.get)
     n_pos = max(0, len(w.ref) - w.q + 1)
-    probe_bytes = 2 * (args.w / 8 + 4 + 8) + 0.25  # per forward position, both strands
+    # filtration, per forward position (both strands): 2 bits of reference,
+    # then per strand the I word, S entry and S' pair of INDEXPAIR
+    probe_bytes = 2 * (args.w / 8 + 4 + 8) + 0.25
     if dominant == "verify":
         work = st["verify_rows"] / K * OPS_PER_ROW
         per_launch_ms = stage_ms["verify"] / max(1.0, launches["verify"])
@@ -120,9 +153,8 @@ def main():
                 "kernel": "k_verify", "avg_launch_ms": per_launch_ms}
     else:
         if dominant in ("filter_count", "filter_emit"):
-            nbytes = n_pos * probe_bytes
-            if dominant == "filter_emit":
-                nbytes += st["n_candidates"] / K * 12
+            # + every 8-byte index entry read and every 8-byte candidate written
+            nbytes = n_pos * probe_bytes + st["n_visited"] / K * 8 + st["n_candidates"] / K * 8
         elif dominant == "index":
             T = int(np.maximum(w.lengths - w.q + 1, 0).sum())
             nbytes = len(w.reads) / 4 + 4 ** w.q / 8 + 4 * (4 ** w.q / args.w) + 4 * min(4 ** w.q, T) + 4 * T
@@ -130,9 +162,16 @@ def main():
             nbytes = st["n_records"] / K * 16 * 8
         per_launch_ms = stage_ms[dominant] / max(1.0, launches[dominant])
         achieved = nbytes / max(1.0, launches[dominant]) / (per_launch_ms / 1000.0)
+        kernel = {"filter_emit": "k_filter"}.get(dominant, dominant)
+        wkey = f"{args.workload}:{args.scale}:{args.w}"
+        tb = counter_traffic(kernel, wkey)
+        # traffic: counter bytes of one launch over the same launch time (GB/s)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BPS / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_BPS, "traffic": None,
-                "kernel": dominant, "avg_launch_ms": per_launch_ms}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_BPS,
+                "traffic": None if tb is None else tb / (per_launch_ms / 1000.0) / 1e9,
+                "traffic_gb_per_launch": None if tb is None else tb / 1e9,
+                "algorithmic_gb_per_launch": nbytes / max(1.0, launches[dominant]) / 1e9,
+                "kernel": kernel, "avg_launch_ms": per_launch_ms}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -177,8 +216,8 @@ def main():
         "hits": n_hits,
         "mapped_fraction": mapped,
         "stage_ms": stage_ms,
-        "counters_per_step": {c: st[c] / K for c in ("n_seeds", "n_candidates", "verify_rows",
-                                                        "n_records", "n_hits")},
+        "counters_per_step": {c: st[c] / K for c in ("n_seeds", "n_visited", "n_candidates",
+                                                        "verify_rows", "n_records", "n_hits")},
     }
     print(json.dumps(line), flush=True)
 

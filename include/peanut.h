@@ -119,14 +119,15 @@ int pn_ctx_stream(pn_ctx *ctx, void **stream);
  * every stage of the path is bracketed by hipEvents on the stream it runs on
  * and its device time is accumulated (ms) with its kernel-launch count.
  * Counters accumulate always: occurrence pairs seen by filtration (n_seeds),
- * candidates verified, band rows computed by verification, records emitted
- * and hits reported.  pn_ctx_get_stats copies them out and optionally
+ * candidates verified, band rows computed by verification, records emitted,
+ * hits reported, and index entries filtration actually read (n_visited:
+ * the seed rules skip the rest).  pn_ctx_get_stats copies them out and optionally
  * resets them. */
 enum {
     PN_STAGE_INGEST = 0,       /* ASCII -> 2-bit codes, read metadata, read planes */
     PN_STAGE_INDEX = 1,        /* Algorithm 1 */
-    PN_STAGE_FILTER_COUNT = 2, /* Algorithm 2, counting pass */
-    PN_STAGE_FILTER_EMIT = 3,  /* Algorithm 2, emitting pass */
+    PN_STAGE_FILTER_COUNT = 2, /* reserved (filtration is one pass: FILTER_EMIT) */
+    PN_STAGE_FILTER_EMIT = 3,  /* Algorithm 2 */
     PN_STAGE_VERIFY = 4,       /* banded bit-parallel validation */
     PN_STAGE_SORT = 5,         /* radix sort of hit records */
     PN_STAGE_FINISH = 6,       /* duplicate removal, strata, output */
@@ -140,6 +141,7 @@ typedef struct {
     uint64_t verify_rows;
     uint64_t n_records;
     uint64_t n_hits;
+    uint64_t n_visited;
 } pn_stats;
 int pn_ctx_set_timing(pn_ctx *ctx, int enable);
 int pn_ctx_get_stats(pn_ctx *ctx, pn_stats *out, int reset);

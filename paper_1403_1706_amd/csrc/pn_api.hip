@@ -27,14 +27,14 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kStatMaxLen = 1,
     kStatT = 2,
     kStatBad = 3,
-    kSeeds = 4,
     kOutCount = 6,
     kBigCount = 7,
     kVerifyRows = 8,
     kCandCounts = 16,                        // pn::kShards words each
     kRecCounts = kCandCounts + pn::kShards,
     kLongCounts = kRecCounts + pn::kShards,
-    kMiscWords = kLongCounts + pn::kShards
+    kFilterStats = kLongCounts + pn::kShards,  // 2 x pn::kShards words
+    kMiscWords = kFilterStats + 2 * pn::kShards
 };
 
 struct PendingStage {
@@ -657,7 +657,7 @@ void launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStre
     const uint32_t *meta = (const uint32_t *)c->side_meta.p;
     pn::FilterOut fo{(uint2 *)c->cands.p,
                      {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
-                     (unsigned long long *)&c->misc[kSeeds]};
+                     (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
     pn::launch_filter(ref_desc(ref), index_desc(x), (const unsigned long long *)c->side.p,
                       meta + pn::kLcPatterns, fo, st);
@@ -670,6 +670,15 @@ void region_counts(const pn_ctx *c, int slot, uint32_t regions, uint64_t *mx, ui
     for (uint32_t g = 0; g < regions; g++) {
         *mx = std::max<uint64_t>(*mx, c->hmisc[slot + g]);
         *total += c->hmisc[slot + g];
+    }
+}
+
+// occurrence pairs seen and index entries read by the last filtration
+void filter_stats(const pn_ctx *c, uint64_t *seeds, uint64_t *visited) {
+    *seeds = *visited = 0;
+    for (uint32_t g = 0; g < pn::kShards; g++) {
+        *seeds += c->hmisc[kFilterStats + 2 * g];
+        *visited += c->hmisc[kFilterStats + 2 * g + 1];
     }
 }
 
@@ -692,7 +701,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         PN_CHECK(ensure(c, c->cands, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->longc, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
-        pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 4 * pn::kShards, 0u, st);
         pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 2, 0u, st);
         zero_counts(c, kRecCounts, st);
         zero_counts(c, kLongCounts, st);
@@ -726,7 +735,10 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         }
         *n_rec = got;
         if (filter) {
-            c->stats.n_seeds += c->hmisc[kSeeds];
+            uint64_t seeds, visited;
+            filter_stats(c, &seeds, &visited);
+            c->stats.n_seeds += seeds;
+            c->stats.n_visited += visited;
             c->stats.n_candidates += cand_total;
         }
         c->stats.verify_rows += c->hmisc[kVerifyRows];
@@ -866,7 +878,7 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
     for (int attempt = 0; !s && attempt < 8; attempt++) {
         s = ensure(c, c->cands, pn::kShards * c->cand_rcap * sizeof(uint2));
         if (s) break;
-        pn::launch_fill_u32((uint32_t *)&c->misc[kSeeds], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 4 * pn::kShards, 0u, st);
         zero_counts(c, kCandCounts, st);
         launch_filter_into(c, ref, x, st);
         s = read_misc(c, st);
@@ -877,7 +889,8 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         c->cand_rcap = mx + mx / 4;
         n = 0;
     }
-    const uint64_t seeds = s ? 0 : c->hmisc[kSeeds];
+    uint64_t seeds = 0, visited = 0;
+    if (!s) filter_stats(c, &seeds, &visited);
     if (!s) s = ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8);
     if (!s) s = ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8);
     if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(n));

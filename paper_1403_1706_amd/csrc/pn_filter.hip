@@ -159,9 +159,9 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
 
 // visit one (position, strand): short ranges by this lane, long ones by
 // the whole wave (every lane of the wave must call this together)
-__device__ __forceinline__ void visit_all(const Ranges &rg, int64_t p, uint32_t s, bool has_prev,
-                                          uint32_t prev, bool lh, uint32_t N, uint32_t avail,
-                                          bool valid, Stage &sg) {
+__device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint32_t s,
+                                              bool has_prev, uint32_t prev, bool lh, uint32_t N,
+                                              uint32_t avail, bool valid, Stage &sg) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     const bool big = valid && len > kBigSlice;
     if (valid && !big) {
@@ -185,6 +185,7 @@ __device__ __forceinline__ void visit_all(const Ranges &rg, int64_t p, uint32_t 
         for (uint32_t t = a0 + lane; t < a1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
         for (uint32_t t = b0 + lane; t < b1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
     }
+    return valid ? len : 0u;  // entries read for this lane's (position, strand)
 }
 
 template <typename TW>
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
     const int q = ix.q;
     const uint64_t L = ref.L;
     const uint64_t u0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kPPT;
-    unsigned long long seeds = 0;
+    unsigned long long seeds = 0, visited = 0;
     // every lane runs the same 8 positions so that long slices can be
     // shared by the wave; lanes past the end carry valid = false
     const bool any = u0 + q <= L;
@@ -239,11 +240,15 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
             r0.src = r1.src = ix.O;
             r0.a0 = r0.a1 = r0.b0 = r0.b1 = r1.a0 = r1.a1 = r1.b0 = r1.b1 = 0;
         }
-        visit_all(r0, (int64_t)u, 0u, has0, prev0, lh0, N0, avail0, valid, sg);
-        visit_all(r1, (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, valid, sg);
+        visited += visit_all(r0, (int64_t)u, 0u, has0, prev0, lh0, N0, avail0, valid, sg);
+        visited += visit_all(r1, (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, valid, sg);
     }
-    for (int o = 32; o > 0; o >>= 1) seeds += __shfl_xor(seeds, o);
-    if (lane == 0 && seeds) atomicAdd(out.n_seeds, seeds);
+    for (int o = 32; o > 0; o >>= 1) {
+        seeds += __shfl_xor(seeds, o);
+        visited += __shfl_xor(visited, o);
+    }
+    if (lane == 0 && seeds) atomicAdd(&out.stats[2 * shard], seeds);
+    if (lane == 0 && visited) atomicAdd(&out.stats[2 * shard + 1], visited);
     // pad the unused part of this lane's reserved slots
     for (uint32_t i = 0; i < sg.lane_left; i++) {
         const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;

@@ -186,7 +186,9 @@ constexpr int kLcPatterns = 16;  // period <= 2 q-grams: first two letters
 struct FilterOut {
     uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS), kShards regions
     Shards sh;                    // per-region append counters
-    unsigned long long *n_seeds;  // occurrence pairs seen (sum of k_end - k_start)
+    // per region g: stats[2g] = occurrence pairs seen (sum of k_end - k_start),
+    // stats[2g+1] = index entries read
+    unsigned long long *stats;
 };
 // per read: bit 7 = keeps its low-complexity seeds, bits 0-2 = extra letters
 // of exact run required beyond q (0..4)

@@ -54,7 +54,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
                 ("n_seeds", ctypes.c_uint64), ("n_candidates", ctypes.c_uint64),
                 ("verify_rows", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
-                ("n_hits", ctypes.c_uint64)]
+                ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64)]
 
 
 class PnError(RuntimeError):
@@ -164,7 +164,7 @@ def pn_ctx_get_stats(ctx, reset: bool = False) -> dict:
     _check(_lib.pn_ctx_get_stats(ctx, ctypes.byref(st), int(bool(reset))), "pn_ctx_get_stats")
     out = {"ms": {n: st.ms[i] for i, n in enumerate(STAGES)},
            "launches": {n: int(st.launches[i]) for i, n in enumerate(STAGES)}}
-    for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits"):
+    for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits", "n_visited"):
         out[f] = int(getattr(st, f))
     return out
 

@@ -59,6 +59,193 @@ def counter_traffic(kernel, workload):
     return None
 
 
+def serving_run(pn, ref, ref_ascii, q, args):
+    """Requests shaped like the serving workload (1k-200k reads log-uniform,
+    75-250 bp, 2-5 % error, all hits or best stratum, Poisson arrivals)
+    against the resident reference.  Serial capacity first (one request per
+    batch, one slot); then the continuous-batching server at twice that
+    arrival rate (sustained reads/s) and both forms at 0.8x (latency)."""
+    import threading
+    import numpy as np
+    from paper_1403_1706_amd import synth
+
+    rng = np.random.Generator(np.random.PCG64(5002))
+    t0 = time.time()
+    reqs = synth.serving_requests(rng, synth.letters_to_index(ref_ascii), args.serve_requests)
+    n_reads = sum(len(r["offsets"]) - 1 for r in reqs)
+    log(f"serving: {len(reqs)} requests, {n_reads} reads ({time.time() - t0:.1f}s to generate)")
+    unit_arrivals = np.array([r["arrival"] for r in reqs])
+
+    def run(srv, rate):
+        before = pn.pn_server_get_stats(srv)
+        tickets = [None] * len(reqs)
+        t_sub = [0.0] * len(reqs)
+        start = time.perf_counter()
+
+        def feed():
+            for i, r in enumerate(reqs):
+                if rate:
+                    delay = start + unit_arrivals[i] / rate - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                t_sub[i] = time.perf_counter()
+                tickets[i] = pn.pn_server_submit(srv, r["reads"], r["offsets"], r["k_per_read"],
+                                                 int(r["best"]))
+
+        th = threading.Thread(target=feed)
+        th.start()
+        lat, done, hits = [], [], 0
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                if not th.is_alive() and tickets[i] is None:
+                    raise RuntimeError(f"request {i} was not submitted")
+                time.sleep(0.0005)
+            h, ms = pn.pn_server_wait(srv, tickets[i])
+            hits += len(h)
+            lat.append(ms)
+            done.append(t_sub[i] + ms / 1000.0)
+        th.join()
+        after = pn.pn_server_get_stats(srv)
+        wall = max(done) - start
+        return {"reads_per_s": n_reads / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "hits": hits,
+                "batches": after["batches"] - before["batches"]}
+
+    batched = dict(slots=2, max_batch_reads=1 << 20, hbm_budget=16 << 30)
+    serial_cfg = dict(slots=1, max_batch_reads=1, hbm_budget=16 << 30)
+    srv_b = pn.pn_server_create(ref, q, **batched)
+    srv_s = pn.pn_server_create(ref, q, **serial_cfg)
+    try:
+        run(srv_b, None)  # warm-up: workspaces grow to their working size
+        run(srv_s, None)
+        serial = run(srv_s, None)
+        cap = len(reqs) / serial["wall_s"]  # requests/s, one at a time
+        log(f"serving: serial {serial['reads_per_s']:.3e} reads/s ({cap:.1f} requests/s)")
+        sat = run(srv_b, 2.0 * cap)
+        log(f"serving: batched at 2x serial rate {sat['reads_per_s']:.3e} reads/s "
+            f"in {sat['batches']} batches")
+        lat_b = run(srv_b, 0.8 * cap)
+        lat_s = run(srv_s, 0.8 * cap)
+        log(f"serving: p50/p99 batched {lat_b['p50_ms']:.1f}/{lat_b['p99_ms']:.1f} ms, "
+            f"serial {lat_s['p50_ms']:.1f}/{lat_s['p99_ms']:.1f} ms")
+        max_batch = pn.pn_server_get_stats(srv_b)["max_batch_reads"]
+    finally:
+        pn.pn_server_destroy(srv_b)
+        pn.pn_server_destroy(srv_s)
+    assert sat["hits"] == serial["hits"] == lat_b["hits"] == lat_s["hits"]
+    return {
+        "workload": f"{len(reqs)} requests, {n_reads} reads of 75-250 bp (1k-200k per request, "
+                    "log-uniform), 2-5 % error, k=ceil(5% n), all hits or best stratum, q=%d, "
+                    "against the resident reference" % q,
+        "slots": batched["slots"], "max_batch_reads": batched["max_batch_reads"],
+        "serial_requests_per_s": cap,
+        "serial_reads_per_s": serial["reads_per_s"],
+        "sustained_reads_per_s": sat["reads_per_s"], "sustained_rate_per_s": 2.0 * cap,
+        "sustained_batches": sat["batches"], "max_batch_reads_seen": max_batch,
+        "latency_rate_per_s": 0.8 * cap,
+        "p50_ms": lat_b["p50_ms"], "p99_ms": lat_b["p99_ms"],
+        "serial_p50_ms": lat_s["p50_ms"], "serial_p99_ms": lat_s["p99_ms"],
+        "hits": sat["hits"],
+    }
+
+
+def batching_run(args):
+    """Mixed-length batch (2 M reads of 50-250 bp, k = ceil(5% n)) mapped as
+    one batch with autotuned q and w, against plain per-length launches (one
+    index and one mapping per distinct read length).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1403_1706_amd import peanut as pn
+    from paper_1403_1706_amd import synth
+
+    t0 = time.time()
+    w = synth.make("mixed", scale=args.scale)
+    log(f"workload mixed: L={len(w.ref)} reads={w.n_reads} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    lengths = w.lengths
+    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    d_k = torch.from_numpy(w.k_per_read.copy()).to(dev)
+    mode = pn.PN_ALL_HITS if args.mode == "all" else pn.PN_BEST_STRATUM
+    ctx = pn.pn_ctx_create(0)
+    ref = pn.pn_ref_load(ctx, w.ref)
+    q, wbits, tune = pn.pn_autotune(ctx, ref, d_reads, d_offs, None, mode,
+                                    sample_reads=min(w.n_reads, 250_000), d_k=d_k)
+    log(f"autotune: q={q} w={wbits} " + ", ".join(
+        f"(q={r['q']},w={r['w']}): " + (f"{r['ms']:.1f} ms" if r['status'] == 0 else "lemma")
+        for r in tune))
+    out = torch.empty(12 * 64 * w.n_reads, dtype=torch.uint8, device=dev)
+
+    def batched():
+        idx = pn.pn_index_build_dev(ctx, d_reads, d_offs, q, wbits)
+        try:
+            return pn.pn_map_dev(ctx, ref, idx, -1, out, mode, d_k=d_k)
+        finally:
+            pn.pn_index_free(idx)
+
+    # per-length groups, staged on the device before timing
+    groups = []
+    for n in np.unique(lengths):
+        ids = np.nonzero(lengths == n)[0]
+        sub = w.subset(ids)
+        groups.append((ids, torch.frombuffer(bytearray(sub.reads), dtype=torch.uint8).to(dev),
+                       torch.from_numpy(sub.offsets.astype(np.int64)).to(dev),
+                       torch.from_numpy(sub.k_per_read.copy()).to(dev),
+                       torch.empty(12 * 64 * len(ids), dtype=torch.uint8, device=dev)))
+
+    def per_length():
+        counts = []
+        for ids, gr, go, gk, gout in groups:
+            idx = pn.pn_index_build_dev(ctx, gr, go, q, wbits)
+            try:
+                counts.append(pn.pn_map_dev(ctx, ref, idx, -1, gout, mode, d_k=gk))
+            finally:
+                pn.pn_index_free(idx)
+        return counts
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1000.0 / steps, r
+
+    ms_b, n_b = timed(batched, args.steps)
+    log(f"batched: {ms_b:.1f} ms/step, {n_b} hits")
+    ms_p, counts = timed(per_length, 1)
+    log(f"per-length ({len(groups)} lengths): {ms_p:.1f} ms/step, {sum(counts)} hits")
+    # equal output: the per-length hits, renumbered to batch read ids
+    hb = np.frombuffer(out[:12 * n_b].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE).copy()
+    parts = []
+    for (ids, _, _, _, gout), c in zip(groups, counts):
+        h = np.frombuffer(gout[:12 * c].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE).copy()
+        h["read_id"] = ids[h["read_id"]]
+        parts.append(h)
+    hp = np.concatenate(parts)
+    hp = hp[np.lexsort((hp["end_pos"], hp["strand"], hp["read_id"]))]
+    equal = len(hp) == len(hb) and all((hp[f] == hb[f]).all() for f in hp.dtype.names)
+    log(f"equal output: {equal}")
+    pn.pn_ref_free(ref)
+    pn.pn_ctx_destroy(ctx)
+    line = {
+        "metric": "mapped reads/sec (all hits <=k errors) on 1 MI355X; mixed-length batch",
+        "value": w.n_reads / (ms_b / 1000.0), "unit": "reads/s", "n_gpus": 1,
+        "steps": args.steps, "ms_per_step": ms_b, "higher_is_better": True,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["mixed"] + (f" (scale {args.scale})" if args.scale != 1 else ""),
+                   "mode": args.mode, "n_reads": w.n_reads, "ref_len": len(w.ref)},
+        "batching": {"q": q, "w": wbits, "autotune": tune, "batched_ms": ms_b,
+                     "per_length_ms": ms_p, "n_lengths": len(groups),
+                     "per_length_reads_per_s": w.n_reads / (ms_p / 1000.0),
+                     "speedup": ms_p / ms_b, "hits": int(n_b), "equal_output": bool(equal)},
+    }
+    print(json.dumps(line), flush=True)
+    if not equal:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +257,10 @@ def main():
     ap.add_argument("--w", type=int, default=64)
     ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batching", action="store_true",
+                    help="mixed-length batch with autotuned q/w vs per-length launches")
     ap.add_argument("--copy-kernel", action="store_true",
                     help="only copy 1 GiB device to device (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -78,6 +269,9 @@ def main():
             "(the path shards by reads with no exchange, see DESIGN.md)")
         sys.exit(2)
 
+    if args.batching:
+        batching_run(args)
+        return
     import numpy as np
     import torch
     if args.copy_kernel:
@@ -191,6 +385,10 @@ def main():
                "seconds": c1 - c0}
         log(f"cpu baseline: {cpu['value']:.1f} reads/s")
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_run(pn, ref, w.ref, w.q, args)
+
     pn.pn_ref_free(ref)
     pn.pn_ctx_destroy(ctx)
 
@@ -212,7 +410,9 @@ def main():
                    "ref_len": len(w.ref)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "latency_ms": None,
+        "latency_ms": None if serving is None else {"p50": serving["p50_ms"],
+                                                     "p99": serving["p99_ms"]},
+        "serving": serving,
         "hits": n_hits,
         "mapped_fraction": mapped,
         "stage_ms": stage_ms,

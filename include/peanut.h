@@ -235,6 +235,84 @@ int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_ca
                 uint64_t n_cands, int k, const uint8_t *k_per_read, pn_hit **records,
                 uint64_t *n_records);
 
+/* ---- batching: parameter choice ----------------------------------------- */
+
+/* Pick q in {10, 11, 12} and group width w in {32, 64} for a read batch
+ * (device arrays as for pn_index_build_dev; k >= 0 for all reads, or
+ * k < 0 and device k_per_read).  q must satisfy the q-gram lemma
+ * (k_r + 1) q <= n_r for every read of the batch (Section 2.2); each such
+ * (q, w) is timed on the batch's first sample_reads reads (index build +
+ * pn_map_dev, best of two runs after a warm-up) and the fastest is returned
+ * in *best_q, *best_w.  results[] (room for 6) receives every candidate
+ * with its time (ms) or status (PN_ELEMMA when the lemma excludes it);
+ * *n_results their count.  The hits do not depend on the choice: the
+ * filter is lossless for every admitted q.  PN_ELEMMA if no q is
+ * admitted. */
+typedef struct {
+    int q, w;
+    double ms;
+    int status;
+} pn_tune_result;
+int pn_autotune(pn_ctx *ctx, const pn_ref *ref, const char *d_reads, const uint64_t *d_offsets,
+                uint32_t n_reads, uint64_t n_bases, int k, const uint8_t *d_k_per_read,
+                pn_mode mode, uint32_t sample_reads, pn_tune_result *results, int *n_results,
+                int *best_q, int *best_w);
+
+/* ---- serving: continuous batching over a resident reference ------------ */
+
+/* A request loop around the mapping path (the paper's layered pipeline of
+ * Fig. 2 with queues between the stages, and its buffering of reads into
+ * batches for one index, Section 3.1).  Submitted requests wait in a FIFO
+ * queue; each of `slots` workers, with its own context and HIP stream on
+ * the reference's device, takes as many queued requests as fit one batch
+ * (at most max_batch_reads reads, and the batch's estimated working set
+ * within what is left of hbm_budget), builds one q-group index over their
+ * concatenated reads, maps them against both strands of the resident
+ * reference, and hands each request its own hits.  Requests that arrive
+ * while batches run are admitted when a slot and budget free up; the slots'
+ * work overlaps on the device.  A request's hits do not depend on what it
+ * was batched with: per read they are exactly pn_map's (read ids relative
+ * to the request, sorted by (read_id, strand, end_pos)).
+ *
+ * Working-set estimate of a batch (bytes): 12 per base + 4096 per read +
+ * 16 MiB.  A request whose own estimate exceeds hbm_budget, or with more
+ * than 2^21 reads (one index), is refused with PN_EBUDGET at submit.  A
+ * batch always takes at least one request, however many reads it has, so
+ * serial one-request-at-a-time mapping is slots = 1, max_batch_reads = 1. */
+typedef struct pn_server pn_server;
+typedef struct {
+    int q;                    /* q-gram length of every batch index, 1..15 */
+    int w;                    /* group width, 32 or 64 */
+    uint64_t hbm_budget;      /* bytes of estimated working sets in flight */
+    uint32_t max_batch_reads; /* reads merged into one batch, 1..2^21 */
+    int slots;                /* batches in flight, 1..8 */
+} pn_server_config;
+typedef struct {
+    uint64_t requests;        /* completed */
+    uint64_t batches;         /* run */
+    uint64_t reads;           /* mapped */
+    uint64_t hits;            /* delivered */
+    uint64_t max_batch_reads; /* largest batch run */
+} pn_server_stats;
+/* `ref` stays owned by the caller and must outlive the server. */
+int pn_server_create(const pn_ref *ref, const pn_server_config *cfg, pn_server **out);
+/* Queue a request: reads[offsets[i] .. offsets[i+1]) for i < n_reads
+ * (host memory, copied before return), error budget k >= 0 for all reads
+ * or k < 0 and k_per_read[i] (host).  Checked here: letters ACGT (either
+ * case), 1 <= n_r <= 256, k_r <= 15, (k_r + 1) q <= n_r; PN_EALPHABET /
+ * PN_EINVAL / PN_ELEMMA / PN_EBUDGET.  *ticket identifies the request. */
+int pn_server_submit(pn_server *srv, const char *reads, const uint64_t *offsets, uint32_t n_reads,
+                     int k, const uint8_t *k_per_read, pn_mode mode, uint64_t *ticket);
+/* Block until the request is done; returns its status.  On PN_OK, *hits
+ * (free with pn_hits_free) and *n_hits receive its hits; *latency_ms (if
+ * not NULL) the time from submit to completion.  A ticket is redeemed
+ * once. */
+int pn_server_wait(pn_server *srv, uint64_t ticket, pn_hit **hits, uint64_t *n_hits,
+                   double *latency_ms);
+int pn_server_get_stats(pn_server *srv, pn_server_stats *out);
+/* Finishes every queued request, then stops the workers. */
+void pn_server_destroy(pn_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/peanut.h"
+#include "pn_runtime.h"
 #include "pn_internal.h"
 
 // ---------------------------------------------------------------------------
@@ -28,7 +28,6 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kStatT = 2,
     kStatBad = 3,
     kOutCount = 6,
-    kBigCount = 7,
     kVerifyRows = 8,
     kCandCounts = 16,                        // pn::kShards words each
     kRecCounts = kCandCounts + pn::kShards,
@@ -54,7 +53,7 @@ struct pn_ctx {
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
     Buf cands, longc, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
-        out_hits;
+        out_hits, out_best;
     // capacities per output region (pn::kShards regions; grow on demand)
     uint64_t cand_rcap = 1ull << 18;
     uint64_t rec_rcap = 1ull << 14;
@@ -486,9 +485,9 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_qgrams = c->hmisc[kStatT];
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
-    uint32_t *cnt = nullptr, *big = nullptr, *partials = nullptr, *lcs = nullptr;
-    unsigned long long *tmp = nullptr;
-    const uint64_t n_big_max = T / 33 + 1;
+    uint32_t *nq = nullptr, *flags = nullptr, *pos = nullptr, *partials = nullptr, *lcs = nullptr;
+    unsigned long long *keys = nullptr, *tmp = nullptr;
+    void *sort_temp = nullptr;
     s = dalloc_t(c, (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
     if (!s) s = dalloc(c, x->n_groups * (w / 8), &x->I);
     if (!s) s = dalloc_t(c, x->n_groups + 1, &x->S);
@@ -496,11 +495,17 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     if (!s) s = dalloc_t(c, T + 1, &x->O);
     if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &x->lcinfo);
     if (!s) s = dalloc_t(c, pn::kLcPatterns, &lcs);
-    if (!s) s = dalloc_t(c, U + 1, &cnt);
-    if (!s) s = dalloc_t(c, n_big_max, &big);
+    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &nq);
+    if (!s) s = dalloc_t(c, T + 1, &keys);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
+    if (!s) s = dalloc_t(c, T + 1, &flags);
+    if (!s) s = dalloc_t(c, T + 1, &pos);
+    if (!s) s = dalloc(c, pn::radix_temp_size(T), &sort_temp);
     if (!s)
-        s = dalloc_t(c, pn::scan_partials_size(std::max<uint64_t>(x->n_groups, U + 1)), &partials);
+        s = dalloc_t(c,
+                     pn::scan_partials_size(
+                         std::max<uint64_t>(std::max<uint64_t>(x->n_groups, T + 1), n_reads + 1)),
+                     &partials);
     if (!s) {
         PnIndexDev ix = index_desc(x);
         tok = stage_begin(c, st, PN_STAGE_INGEST);
@@ -508,40 +513,38 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         pn::launch_read_lc(ix, x->lcinfo, st);
         stage_end(c, st, tok, 2);
         tok = stage_begin(c, st, PN_STAGE_INDEX);
+        // q-gram occurrences -> keys at their read's offset in O
+        pn::launch_read_nq(ix, nq, st);
+        pn::launch_scan_u32(nq, nq, n_reads, partials, st);
+        pn::launch_qgram_keys(ix, nq, keys, st);
+        const unsigned long long *sorted =
+            pn::radix_sort_u64_any(keys, tmp, T, 2 * q + 3, sort_temp, st);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
-        pn::launch_qgram_bitmap(ix, x->I, st);                                // step 1
+        pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);  // step 1 and O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
-        pn::launch_fill_u32(cnt, U + 1, 0u, st);
-        pn::launch_qgram_count(ix, cnt, st);                    // step 4
-        pn::launch_scan_u32(cnt, x->Sp, U, partials, st);      // step 5
-        pn::launch_fill_u32(cnt, U + 1, 0u, st);
-        pn::launch_qgram_scatter(ix, cnt, x->O, st);           // step 6
-        pn::launch_bucket_sort(x->Sp, U, x->S + x->n_groups, x->O, big,
-                               (uint32_t *)&c->misc[kBigCount], st);
-        stage_end(c, st, tok, 14);
+        pn::launch_scan_u32(flags, pos, T, partials, st);
+        pn::launch_sp_fill(flags, pos, T, x->Sp, st);  // steps 4-6
+        stage_end(c, st, tok, 5 + 3 * ((2 * q + 3 + 7) / 8) + 3 + 3 + 1);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
         e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(x->lc_size, lcs, sizeof(x->lc_size), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) s = read_misc(c, st);
-        else s = map_err(e);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = map_err(e);
         if (!s) {
             x->n_distinct = n_distinct;
             x->lc_total = 0;
             for (int i = 0; i < pn::kLcPatterns; i++) x->lc_total += x->lc_size[i];
-            const uint32_t n_big = (uint32_t)c->hmisc[kBigCount];
-            tok = stage_begin(c, st, PN_STAGE_INDEX);
-            pn::launch_bucket_sort_big(x->Sp, x->O, tmp, big, n_big, st);
-            stage_end(c, st, tok, n_big ? 1 : 0);
-            e = hipStreamSynchronize(st);
-            if (e != hipSuccess) s = map_err(e);
             collect_stages(c);
         }
     }
-    dfree(c, cnt);
-    dfree(c, big);
+    dfree(c, nq);
+    dfree(c, keys);
     dfree(c, tmp);
+    dfree(c, flags);
+    dfree(c, pos);
+    dfree(c, sort_temp);
     dfree(c, partials);
     dfree(c, lcs);
     if (s) {
@@ -788,7 +791,8 @@ int finish(pn_ctx *c, const pn_ref *ref, const pn_index *x, uint64_t n_rec, int 
 
 int check_map_args(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *kpr,
                    pn_mode mode) {
-    if (!c || !ref || !x || ref->ctx != c || x->ctx != c) return PN_EINVAL;
+    // the reference may come from any context on the same device
+    if (!c || !ref || !x || ref->ctx->device != c->device || x->ctx != c) return PN_EINVAL;
     if (mode != PN_ALL_HITS && mode != PN_BEST_STRATUM) return PN_EINVAL;
     if (k > PN_MAX_K) return PN_EINVAL;
     if (k < 0 && !kpr && x->n_reads) return PN_EINVAL;
@@ -796,6 +800,36 @@ int check_map_args(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const
 }
 
 }  // namespace
+
+namespace pnrt {
+
+int ctx_device(const pn_ctx *c) { return c->device; }
+int ref_device(const pn_ref *r) { return r->ctx->device; }
+
+int map_to_workspace(pn_ctx *c, const pn_ref *ref, const pn_index *x, const uint8_t *d_k,
+                     bool want_all, bool want_best, const pn_hit **d_all, uint64_t *n_all,
+                     const pn_hit **d_best, uint64_t *n_best, hipStream_t st) {
+    PN_CHECK(check_map_args(c, ref, x, -1, d_k, PN_ALL_HITS));
+    DeviceGuard g(c->device);
+    uint64_t n_rec = 0;
+    PN_CHECK(map_records(c, ref, x, -1, d_k, st, &n_rec));
+    // each output holds at most one hit per record
+    const uint64_t cap = std::max<uint64_t>(n_rec, 1);
+    *n_all = *n_best = 0;
+    if (want_all) {
+        PN_CHECK(ensure(c, c->out_hits, cap * sizeof(pn_hit)));
+        PN_CHECK(finish(c, ref, x, n_rec, 0, c->out_hits.p, cap, st, n_all));
+        *d_all = (const pn_hit *)c->out_hits.p;
+    }
+    if (want_best) {
+        PN_CHECK(ensure(c, c->out_best, cap * sizeof(pn_hit)));
+        PN_CHECK(finish(c, ref, x, n_rec, 1, c->out_best.p, cap, st, n_best));
+        *d_best = (const pn_hit *)c->out_best.p;
+    }
+    return PN_OK;
+}
+
+}  // namespace pnrt
 
 extern "C" {
 

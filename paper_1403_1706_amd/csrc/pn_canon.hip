@@ -163,9 +163,9 @@ uint64_t radix_temp_size(uint64_t n) {
     return (2 * hist + scan_partials_size(256 * nt)) * sizeof(uint32_t) + 256;
 }
 
-void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
-                    void *temp, hipStream_t st) {
-    if (n <= 1 || bits <= 0) return;
+unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
+                                       uint64_t n, int bits, void *temp, hipStream_t st) {
+    if (n <= 1 || bits <= 0) return keys;
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
     uint32_t *offs = hist + 256 * nt + 1;
@@ -183,8 +183,15 @@ void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t 
         src = dst;
         dst = t;
     }
-    if (src != keys) (void)hipMemcpyAsync(keys, src, n * sizeof(unsigned long long),
-                                    hipMemcpyDeviceToDevice, st);
+    return src;
+}
+
+void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
+                    void *temp, hipStream_t st) {
+    unsigned long long *src = radix_sort_u64_any(keys, tmp, n, bits, temp, st);
+    if (src != keys)
+        (void)hipMemcpyAsync(keys, src, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                             st);
 }
 
 void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,

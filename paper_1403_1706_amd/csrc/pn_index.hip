@@ -1,15 +1,20 @@
 // Algorithm 1: building the q-group index (I, S, S', O) of the read batch
-// on the device (Section 2.2).  One thread handles up to 32 consecutive
-// q-gram starts of one read; reads are independent, so the six steps are
-//   1. I[g / w] |= bit (g mod w)              (k_qgram_bitmap)
-//   2-3. S = exclusive scan of popcount(I[i])  (pn_scan.hip)
-//   4. count[S[i] + j'] += 1, j' = GROUPRANK   (k_qgram_count)
-//   5. S' = exclusive scan of count            (pn_scan.hip)
-//   6. O[S'[x] + next free] = position         (k_qgram_scatter)
-// followed by ordering each q-gram's slice of O by entry value (small slices
-// fully, long slices by preceding letter).  Each O entry also carries the
-// letter before its q-gram and the (up to) four letters after it, which the
-// filter compares with the reference without touching the reads.
+// on the device (Section 2.2).  The paper fills O through per-q-gram
+// counters and "next free entry" cursors; here the same arrays come from
+// one sort, which needs no atomic per occurrence and leaves every slice of
+// O ordered:
+//   a. one 64-bit key per q-gram occurrence (read r, offset o):
+//      (r, o) above (q-gram g, class of the letter before it)   (k_qgram_keys)
+//   b. stable LSD radix sort on the low 2q+3 bits: occurrences grouped by
+//      g, inside a group by (class, r, o)                         (pn_canon.hip)
+//   c. O[i] from the i-th key; the first key of each g sets bit g of I
+//      (Algorithm 1 step 1) and marks a group start               (k_index_from_sorted)
+//   d. S = exclusive scan of popcount(I[i]) (steps 2-3); the rank of each
+//      group start among the starts is its slot x = S[g/w] + GROUPRANK, so
+//      S'[x] = its position in O (steps 4-6)                     (pn_scan.hip, k_sp_fill)
+// Each O entry also carries the letter before its q-gram and the (up to)
+// four letters after it, which the filter compares with the reference
+// without touching the reads.
 #include "pn_internal.h"
 
 namespace {
@@ -51,61 +56,69 @@ __device__ __forceinline__ uint32_t qgram_at(const PnIndexDev &ix, uint64_t off,
     return (w << 2) >> (32 - 2 * ix.q);
 }
 
-template <typename TW>
-__global__ __launch_bounds__(256) void k_qgram_bitmap(PnIndexDev ix, uint32_t nch, TW *I) {
+// q-gram starts per read (n_r - q + 1, or 0)
+__global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ix.n_reads) return;
+    const uint64_t n = ix.offsets[r + 1] - ix.offsets[r];
+    nq[r] = n >= (uint64_t)ix.q ? (uint32_t)(n - ix.q + 1) : 0u;
+}
+
+// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class
+__global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix, uint32_t nch,
+                                                    const uint32_t *__restrict__ qoff,
+                                                    unsigned long long *__restrict__ keys) {
     QgramIter it;
     if (!qgram_iter(ix, nch, it)) return;
-    const uint32_t wmask = (1u << ix.log2w) - 1;
+    const int sh = 2 * ix.q + 3;
+    const uint64_t base = qoff[it.r];
     for (uint32_t o = it.o0; o < it.o1; o++) {
         uint32_t cls;
-        uint32_t g = qgram_at(ix, it.off, o, cls);
-        TW bit = (TW)1 << (g & wmask);
-        TW *p = &I[g >> ix.log2w];
-        if (!(*p & bit)) atomicOr(p, bit);
+        const uint32_t g = qgram_at(ix, it.off, o, cls);
+        keys[base + o] = ((unsigned long long)((it.r << 8) | o) << sh) |
+                         ((unsigned long long)g << 3) | cls;
     }
 }
 
+// O entries from the sorted keys, group starts, and the presence bitmap I
 template <typename TW>
-__device__ __forceinline__ uint32_t group_rank_slot(const PnIndexDev &ix, const TW *I, uint32_t g) {
-    const uint32_t wmask = (1u << ix.log2w) - 1;
-    uint32_t i = g >> ix.log2w, j = g & wmask;
-    TW word = I[i];
-    uint32_t jp = (uint32_t)pn_popc<TW>(word & (((TW)1 << j) - 1));  // GROUPRANK
-    return ix.S[i] + jp;
+__global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
+                                                           const unsigned long long *__restrict__ keys,
+                                                           uint64_t T, unsigned long long *O,
+                                                           uint32_t *flags, TW *I) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= T) return;
+    const int sh = 2 * ix.q + 3;
+    const unsigned long long lowm = (1ull << sh) - 1ull;
+    const unsigned long long k = keys[i];
+    const uint32_t g = (uint32_t)((k & lowm) >> 3);
+    const uint32_t cls = (uint32_t)(k & 7ull);
+    const uint32_t ro = (uint32_t)(k >> sh);
+    const uint32_t r = ro >> 8, o = ro & 0xffu;
+    const bool start = i == 0 || (uint32_t)((keys[i - 1] & lowm) >> 3) != g;
+    flags[i] = start;
+    if (start) {
+        const uint32_t wmask = (1u << ix.log2w) - 1;
+        atomicOr(&I[g >> ix.log2w], (TW)1 << (g & wmask));
+    }
+    // the letters after the q-gram inside the read (at most four)
+    const uint64_t off = ix.offsets[r];
+    const uint32_t n = (uint32_t)(ix.offsets[r + 1] - off);
+    const uint32_t after = n - o - (uint32_t)ix.q;
+    const uint32_t nav = after < 4u ? after : 4u;
+    uint32_t next4 = pn_window16(ix.packed, off + o + ix.q) >> 24;
+    next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
+    const uint32_t hi = (cls << 29) | (r << 8) | o;
+    const uint32_t lo = (next4 << 24) | (nav << 21);
+    O[i] = ((unsigned long long)hi << 32) | lo;
 }
 
-template <typename TW>
-__global__ __launch_bounds__(256) void k_qgram_count(PnIndexDev ix, uint32_t nch, uint32_t *cnt) {
-    QgramIter it;
-    if (!qgram_iter(ix, nch, it)) return;
-    const TW *I = (const TW *)ix.I;
-    for (uint32_t o = it.o0; o < it.o1; o++) {
-        uint32_t cls;
-        uint32_t g = qgram_at(ix, it.off, o, cls);
-        atomicAdd(&cnt[group_rank_slot<TW>(ix, I, g)], 1u);
-    }
-}
-
-template <typename TW>
-__global__ __launch_bounds__(256) void k_qgram_scatter(PnIndexDev ix, uint32_t nch,
-                                                       uint32_t *cursor, unsigned long long *O) {
-    QgramIter it;
-    if (!qgram_iter(ix, nch, it)) return;
-    const TW *I = (const TW *)ix.I;
-    for (uint32_t o = it.o0; o < it.o1; o++) {
-        uint32_t cls;
-        uint32_t g = qgram_at(ix, it.off, o, cls);
-        uint32_t x = group_rank_slot<TW>(ix, I, g);
-        uint32_t k = ix.Sp[x] + atomicAdd(&cursor[x], 1u);
-        // the letters after the q-gram inside the read (at most four)
-        const uint32_t after = it.n - o - (uint32_t)ix.q;
-        const uint32_t nav = after < 4u ? after : 4u;
-        uint32_t next4 = pn_window16(ix.packed, it.off + o + ix.q) >> 24;
-        next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
-        const uint32_t hi = (cls << 29) | (it.r << 8) | o;
-        const uint32_t lo = (next4 << 24) | (nav << 21);
-        O[k] = ((unsigned long long)hi << 32) | lo;
-    }
+// S'[x] = position of the x-th group start; S'[D] = T
+__global__ void k_sp_fill(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
+                          uint64_t T, uint32_t *Sp) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < T && flags[i]) Sp[pos[i]] = (uint32_t)i;
+    if (i == T) Sp[pos[T]] = (uint32_t)T;
 }
 
 // per read: number of low-complexity q-gram offsets and of maximal runs of
@@ -127,55 +140,6 @@ __global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo
     lcinfo[r] = cnt | (runs << 16);
 }
 
-// order small slices of O in place; slices longer than 32 go to a list
-__global__ __launch_bounds__(256) void k_bucket_sort(const uint32_t *Sp, uint64_t n_slots,
-                                                     const uint32_t *n_distinct,
-                                                     unsigned long long *O, uint32_t *big_list,
-                                                     uint32_t *big_count) {
-    uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n_slots || x >= *n_distinct) return;
-    uint32_t s = Sp[x], e = Sp[x + 1];
-    uint32_t m = e - s;
-    if (m <= 1) return;
-    if (m > 32) {
-        big_list[atomicAdd(big_count, 1u)] = (uint32_t)x;
-        return;
-    }
-    for (uint32_t i = s + 1; i < e; i++) {
-        unsigned long long v = O[i];
-        uint32_t j = i;
-        while (j > s && O[j - 1] > v) {
-            O[j] = O[j - 1];
-            j--;
-        }
-        O[j] = v;
-    }
-}
-
-// one block per long slice: stable partition by preceding-letter class
-// (the top three bits of an entry) through a scratch copy
-__global__ __launch_bounds__(256) void k_bucket_sort_big(const uint32_t *Sp,
-                                                         unsigned long long *O,
-                                                         unsigned long long *tmp,
-                                                         const uint32_t *big_list) {
-    uint32_t x = big_list[blockIdx.x];
-    uint32_t s = Sp[x], e = Sp[x + 1];
-    uint32_t at = s;
-    for (uint32_t cls = 0; cls <= PN_CLS_NONE; cls++) {
-        for (uint32_t base = s; base < e; base += 256) {
-            uint32_t i = base + threadIdx.x;
-            unsigned long long v = i < e ? O[i] : 0ull;
-            uint32_t f = (i < e) && ((uint32_t)(v >> 61) == cls);
-            uint32_t tot;
-            uint32_t ex = pn_block_excl_scan(f, &tot);
-            if (f) tmp[at + ex] = v;
-            at += tot;
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = s + threadIdx.x; i < e; i += 256) O[i] = tmp[i];
-}
-
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -190,55 +154,33 @@ uint32_t nch_for(const PnIndexDev &ix) {
 
 namespace pn {
 
-void launch_qgram_bitmap(const PnIndexDev &ix, void *I, hipStream_t st) {
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st) {
+    if (!ix.n_reads) return;
+    hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq);
+}
+
+void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
+                       hipStream_t st) {
     const uint32_t nch = nch_for(ix);
     uint64_t n = (uint64_t)ix.n_reads * nch;
     if (!n) return;
+    hipLaunchKernelGGL(k_qgram_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, ix, nch, qoff, keys);
+}
+
+void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
+                              unsigned long long *O, uint32_t *flags, void *I, hipStream_t st) {
+    if (!T) return;
     if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_qgram_bitmap<unsigned long long>, dim3(grid_for(n, 256)), dim3(256),
-                           0, st, ix, nch, (unsigned long long *)I);
+        hipLaunchKernelGGL(k_index_from_sorted<unsigned long long>, dim3(grid_for(T, 256)),
+                           dim3(256), 0, st, ix, keys, T, O, flags, (unsigned long long *)I);
     else
-        hipLaunchKernelGGL(k_qgram_bitmap<uint32_t>, dim3(grid_for(n, 256)), dim3(256), 0, st, ix,
-                           nch, (uint32_t *)I);
+        hipLaunchKernelGGL(k_index_from_sorted<uint32_t>, dim3(grid_for(T, 256)), dim3(256), 0, st,
+                           ix, keys, T, O, flags, (uint32_t *)I);
 }
 
-void launch_qgram_count(const PnIndexDev &ix, uint32_t *cnt, hipStream_t st) {
-    const uint32_t nch = nch_for(ix);
-    uint64_t n = (uint64_t)ix.n_reads * nch;
-    if (!n) return;
-    if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_qgram_count<unsigned long long>, dim3(grid_for(n, 256)), dim3(256), 0,
-                           st, ix, nch, cnt);
-    else
-        hipLaunchKernelGGL(k_qgram_count<uint32_t>, dim3(grid_for(n, 256)), dim3(256), 0, st, ix,
-                           nch, cnt);
-}
-
-void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, unsigned long long *O,
-                          hipStream_t st) {
-    const uint32_t nch = nch_for(ix);
-    uint64_t n = (uint64_t)ix.n_reads * nch;
-    if (!n) return;
-    if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_qgram_scatter<unsigned long long>, dim3(grid_for(n, 256)), dim3(256),
-                           0, st, ix, nch, cursor, O);
-    else
-        hipLaunchKernelGGL(k_qgram_scatter<uint32_t>, dim3(grid_for(n, 256)), dim3(256), 0, st, ix,
-                           nch, cursor, O);
-}
-
-void launch_bucket_sort(const uint32_t *Sp, uint64_t n_slots, const uint32_t *n_distinct,
-                        unsigned long long *O, uint32_t *big_list, uint32_t *big_count,
-                        hipStream_t st) {
-    if (!n_slots) return;
-    hipLaunchKernelGGL(k_bucket_sort, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, Sp, n_slots,
-                       n_distinct, O, big_list, big_count);
-}
-
-void launch_bucket_sort_big(const uint32_t *Sp, unsigned long long *O, unsigned long long *tmp,
-                            const uint32_t *big_list, uint32_t n_big, hipStream_t st) {
-    if (!n_big) return;
-    hipLaunchKernelGGL(k_bucket_sort_big, dim3(n_big), dim3(256), 0, st, Sp, O, tmp, big_list);
+void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_sp_fill, dim3(grid_for(T + 1, 256)), dim3(256), 0, st, flags, pos, T, Sp);
 }
 
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st) {

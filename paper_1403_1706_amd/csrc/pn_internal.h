@@ -157,15 +157,16 @@ void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint3
 uint64_t scan_partials_size(uint64_t n);
 
 // pn_index.hip (Algorithm 1)
-void launch_qgram_bitmap(const PnIndexDev &ix, void *I, hipStream_t st);
-void launch_qgram_count(const PnIndexDev &ix, uint32_t *cnt, hipStream_t st);
-void launch_qgram_scatter(const PnIndexDev &ix, uint32_t *cursor, unsigned long long *O,
-                          hipStream_t st);
-void launch_bucket_sort(const uint32_t *Sp, uint64_t n_slots, const uint32_t *n_distinct,
-                        unsigned long long *O, uint32_t *big_list, uint32_t *big_count,
-                        hipStream_t st);
-void launch_bucket_sort_big(const uint32_t *Sp, unsigned long long *O, unsigned long long *tmp,
-                            const uint32_t *big_list, uint32_t n_big, hipStream_t st);
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st);
+void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
+                       hipStream_t st);
+// O, group-start flags and I (zeroed by the caller) from keys sorted by
+// their low 2q+3 bits
+void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
+                              unsigned long long *O, uint32_t *flags, void *I, hipStream_t st);
+// pos = exclusive scan of flags (pos[T] = D)
+void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,
+                    hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
 
 // Append-only output split into kShards regions of `region_cap` entries,
@@ -234,6 +235,10 @@ void launch_gather_shards(const unsigned long long *src, const unsigned long lon
 
 // pn_canon.hip: sort + duplicate removal + strata + output
 uint64_t radix_temp_size(uint64_t n);  // bytes
+// stable sort by the low `bits` bits; the result is in the returned buffer
+// (keys or tmp)
+unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
+                                       uint64_t n, int bits, void *temp, hipStream_t st);
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
                     void *temp, hipStream_t st);
 void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,

@@ -57,6 +57,22 @@ class _Stats(ctypes.Structure):
                 ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("w", ctypes.c_int), ("hbm_budget", ctypes.c_uint64),
+                ("max_batch_reads", ctypes.c_uint32), ("slots", ctypes.c_int)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("reads", ctypes.c_uint64), ("hits", ctypes.c_uint64),
+                ("max_batch_reads", ctypes.c_uint64)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("w", ctypes.c_int), ("ms", ctypes.c_double),
+                ("status", ctypes.c_int)]
+
+
 class PnError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -101,12 +117,24 @@ _sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_
 _sig("pn_hits_free", None, [_P])
 _sig("pn_filter", _int, [_P, _P, _P, _int, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
 _sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
+_sig("pn_server_create", _int, [_P, ctypes.POINTER(_ServerConfig), _PP])
+_sig("pn_server_submit", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _P, _int,
+                                ctypes.POINTER(_u64)])
+_sig("pn_server_wait", _int, [_P, _u64, _PP, ctypes.POINTER(_u64),
+                              ctypes.POINTER(ctypes.c_double)])
+_sig("pn_server_get_stats", _int, [_P, ctypes.POINTER(_ServerStats)])
+_sig("pn_server_destroy", None, [_P])
+_sig("pn_autotune", _int, [_P, _P, _P, _P, _u32, _u64, _int, _P, _int, _u32,
+                           ctypes.POINTER(_TuneResult), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                           ctypes.POINTER(_int)])
 
 EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ctx_set_timing", "pn_ctx_get_stats", "pn_ref_load",
             "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
-            "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate"]
+            "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
+            "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_server_get_stats",
+            "pn_server_destroy", "pn_autotune"]
 
 
 def _check(st: int, where: str):
@@ -333,3 +361,57 @@ class Session:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def pn_server_create(ref, q: int, w: int = 64, hbm_budget: int = 16 << 30,
+                     max_batch_reads: int = 1 << 20, slots: int = 2):
+    cfg = _ServerConfig(q, w, hbm_budget, max_batch_reads, slots)
+    h = ctypes.c_void_p()
+    _check(_lib.pn_server_create(ref, ctypes.byref(cfg), ctypes.byref(h)), "pn_server_create")
+    return h
+
+
+def pn_server_submit(srv, reads: bytes, offsets, k, mode: int = PN_ALL_HITS) -> int:
+    """k: int for all reads, or a uint8 array of per-read k.  Returns a ticket."""
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n_reads = len(offs) - 1
+    kg, karr = _k_args(k, n_reads)
+    t = _u64()
+    _check(_lib.pn_server_submit(srv, reads, _ptr(offs), n_reads, kg,
+                                 None if karr is None else _ptr(karr), mode, ctypes.byref(t)),
+           "pn_server_submit")
+    return t.value
+
+
+def pn_server_wait(srv, ticket: int):
+    """Returns (hits, latency_ms) of a submitted request."""
+    hp = ctypes.c_void_p()
+    n = _u64()
+    lat = ctypes.c_double()
+    _check(_lib.pn_server_wait(srv, ticket, ctypes.byref(hp), ctypes.byref(n), ctypes.byref(lat)),
+           "pn_server_wait")
+    return _take_hits(hp, n.value, HIT_DTYPE), lat.value
+
+
+def pn_server_get_stats(srv) -> dict:
+    st = _ServerStats()
+    _check(_lib.pn_server_get_stats(srv, ctypes.byref(st)), "pn_server_get_stats")
+    return {f: int(getattr(st, f)) for f, _ in _ServerStats._fields_}
+
+
+def pn_server_destroy(srv) -> None:
+    _lib.pn_server_destroy(srv)
+
+
+def pn_autotune(ctx, ref, d_reads, d_offsets, k, mode: int = PN_ALL_HITS, sample_reads: int = 0,
+                d_k=None):
+    """Device tensors as for pn_index_build_dev.  Returns (q, w, [results])."""
+    n_reads = int(d_offsets.numel()) - 1
+    res = (_TuneResult * 6)()
+    nres, bq, bw = _int(), _int(), _int()
+    _check(_lib.pn_autotune(ctx, ref, d_reads.data_ptr(), d_offsets.data_ptr(), n_reads,
+                            int(d_reads.numel()), -1 if d_k is not None else int(k),
+                            None if d_k is None else d_k.data_ptr(), mode, sample_reads, res,
+                            ctypes.byref(nres), ctypes.byref(bq), ctypes.byref(bw)), "pn_autotune")
+    out = [{"q": r.q, "w": r.w, "ms": r.ms, "status": r.status} for r in res[:nres.value]]
+    return bq.value, bw.value, out

@@ -353,6 +353,14 @@ def random_case(rng: np.random.Generator, L: int, n_reads: int, len_lo: int, len
                     strands, starts)
 
 
+def letters_to_index(seq: bytes) -> np.ndarray:
+    """ASCII ACGT -> 0..3, the inverse of ALPHABET (for drawing reads from a
+    preset's ASCII reference)."""
+    lut = np.zeros(256, dtype=np.uint8)
+    lut[ALPHABET] = np.arange(4, dtype=np.uint8)
+    return lut[np.frombuffer(seq, dtype=np.uint8)]
+
+
 def serving_requests(rng: np.random.Generator, ref: np.ndarray, n_requests: int,
                      min_reads: int = 1000, max_reads: int = 200_000):
     """Request stream: reads per request log-uniform in [min_reads, max_reads],

@@ -124,6 +124,9 @@ def serving_run(pn, ref, ref_ascii, q, args):
         sat = run(srv_b, 2.0 * cap)
         log(f"serving: batched at 2x serial rate {sat['reads_per_s']:.3e} reads/s "
             f"in {sat['batches']} batches")
+        burst = run(srv_b, None)  # every request queued at once: the server's capacity
+        log(f"serving: batched, all requests at once {burst['reads_per_s']:.3e} reads/s "
+            f"in {burst['batches']} batches")
         lat_b = run(srv_b, 0.8 * cap)
         lat_s = run(srv_s, 0.8 * cap)
         log(f"serving: p50/p99 batched {lat_b['p50_ms']:.1f}/{lat_b['p99_ms']:.1f} ms, "
@@ -132,16 +135,17 @@ def serving_run(pn, ref, ref_ascii, q, args):
     finally:
         pn.pn_server_destroy(srv_b)
         pn.pn_server_destroy(srv_s)
-    assert sat["hits"] == serial["hits"] == lat_b["hits"] == lat_s["hits"]
+    assert sat["hits"] == serial["hits"] == burst["hits"] == lat_b["hits"] == lat_s["hits"]
     return {
         "workload": f"{len(reqs)} requests, {n_reads} reads of 75-250 bp (1k-200k per request, "
-                    "log-uniform), 2-5 % error, k=ceil(5% n), all hits or best stratum, q=%d, "
-                    "against the resident reference" % q,
+                    f"log-uniform), 2-5 % error, k=ceil(5% n), all hits or best stratum, q={q}, "
+                    "against the resident reference",
         "slots": batched["slots"], "max_batch_reads": batched["max_batch_reads"],
         "serial_requests_per_s": cap,
         "serial_reads_per_s": serial["reads_per_s"],
         "sustained_reads_per_s": sat["reads_per_s"], "sustained_rate_per_s": 2.0 * cap,
         "sustained_batches": sat["batches"], "max_batch_reads_seen": max_batch,
+        "burst_reads_per_s": burst["reads_per_s"], "burst_batches": burst["batches"],
         "latency_rate_per_s": 0.8 * cap,
         "p50_ms": lat_b["p50_ms"], "p99_ms": lat_b["p99_ms"],
         "serial_p50_ms": lat_s["p50_ms"], "serial_p99_ms": lat_s["p99_ms"],

@@ -18,8 +18,8 @@ inline unsigned grid_for(uint64_t n, unsigned threads) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long long *keys,
-                                                         uint64_t n, int shift, uint32_t *hist,
-                                                         uint64_t n_tiles) {
+                                                         uint64_t n, int shift, uint32_t dmask,
+                                                         uint32_t *hist, uint64_t n_tiles) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long lon
 #pragma unroll 4
     for (int j = 0; j < kItems; j++) {
         uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & dmask], 1u);
     }
     __syncthreads();
     hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long lon
 
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
                                                             unsigned long long *out, uint64_t n,
-                                                            int shift, const uint32_t *offs,
-                                                            uint64_t n_tiles) {
+                                                            int shift, uint32_t dmask,
+                                                            const uint32_t *offs, uint64_t n_tiles) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[4][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
         const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
         const bool valid = i < n;
         const unsigned long long key = valid ? keys[i] : 0ull;
-        const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+        const uint32_t dg = (uint32_t)(key >> shift) & dmask;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -174,11 +174,13 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     const int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
+        // the last digit may be narrower: bits above `bits` do not take part
+        const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kThreads), 0, st, src, n, shift,
-                           hist, nt);
+                           dmask, hist, nt);
         launch_scan_u32(hist, offs, 256 * nt, partials, st);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,
-                           shift, offs, nt);
+                           shift, dmask, offs, nt);
         unsigned long long *t = src;
         src = dst;
         dst = t;

@@ -158,6 +158,17 @@ int pn_ref_load_dev(pn_ctx *ctx, const char *d_seq, uint64_t len, void *stream, 
 void pn_ref_free(pn_ref *ref);
 uint64_t pn_ref_length(const pn_ref *ref);
 
+/* Precompute the reference's position set for q-gram length q: every
+ * position of both strands, sorted by its q-gram (Section 3.2, where the
+ * paper takes P sorted from its precomputed reference index so that
+ * neighbouring threads probe neighbouring parts of the q-group index),
+ * with the letters around each q-gram.  Mapping with an index of this q
+ * builds it on first use anyway; calling this moves that one-time cost out
+ * of the first mapping.  It stays resident until pn_ref_free: 10 bytes per
+ * position and strand (2 GB for 100 Mbp) for each q used.  Safe to call
+ * from several threads. */
+int pn_ref_prepare(pn_ref *ref, int q);
+
 /* ---- q-group index over a read batch (Algorithm 1) --------------------- */
 
 /* Build the q-group index (I, S, S', O) of all q-grams of the reads

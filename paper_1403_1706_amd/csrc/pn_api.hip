@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -70,6 +71,12 @@ struct pn_ref {
     uint32_t *packed_base;  // one front word, then the text, then 4 words
     uint4 *planes0, *planes1;
     uint64_t n_blocks;
+    // position sets sorted by q-gram, built on first use per q (any context
+    // on the device may map against the reference: guarded by prep_mu)
+    std::mutex prep_mu;
+    unsigned long long *pkeys[16] = {};
+    uint16_t *pctx[16] = {};
+    uint64_t pn[16] = {};
 };
 
 struct pn_index {
@@ -264,6 +271,45 @@ PnRefDev ref_desc(const pn_ref *r) {
     return d;
 }
 
+// the q-gram-sorted position set of `r` for q (Section 3.2), built on first
+// use: keys of both strands, a stable radix sort by q-gram, then each
+// entry's context.  Owned by the reference (plain device allocations).
+int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
+    std::lock_guard<std::mutex> lk(r->prep_mu);
+    const uint64_t n = r->L >= (uint64_t)q ? 2 * (r->L - q + 1) : 0;
+    if (r->pkeys[q] || n == 0) {
+        *out = pn::RefQDev{r->pkeys[q], r->pctx[q], r->pkeys[q] ? r->pn[q] : 0};
+        return PN_OK;
+    }
+    unsigned long long *keys = nullptr, *tmp = nullptr;
+    uint16_t *ctx = nullptr;
+    void *temp = nullptr;
+    hipError_t e = hipMalloc((void **)&keys, n * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&tmp, n * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx, n * 2);
+    if (e == hipSuccess) e = hipMalloc(&temp, pn::radix_temp_size(n));
+    if (e == hipSuccess) {
+        const PnRefDev rd = ref_desc(r);
+        pn::launch_refq_keys(rd, q, keys, st);
+        unsigned long long *sorted = pn::radix_sort_u64_any(keys, tmp, n, 2 * q, temp, st);
+        if (sorted != keys) std::swap(keys, tmp);
+        pn::launch_refq_ctx(rd, q, keys, n, ctx, st);
+        e = hipStreamSynchronize(st);
+    }
+    if (tmp) (void)hipFree(tmp);
+    if (temp) (void)hipFree(temp);
+    if (e != hipSuccess) {
+        if (keys) (void)hipFree(keys);
+        if (ctx) (void)hipFree(ctx);
+        return map_err(e);
+    }
+    r->pkeys[q] = keys;
+    r->pctx[q] = ctx;
+    r->pn[q] = n;
+    *out = pn::RefQDev{keys, ctx, n};
+    return PN_OK;
+}
+
 PnIndexDev index_desc(const pn_index *x) {
     PnIndexDev d;
     d.packed = x->packed;
@@ -425,11 +471,22 @@ void pn_ref_free(pn_ref *r) {
     if (!r) return;
     pn_ctx *c = r->ctx;
     DeviceGuard g(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
     dfree(c, r->packed_base);
     dfree(c, r->planes0);
     dfree(c, r->planes1);
+    for (int q = 0; q < 16; q++) {
+        if (r->pkeys[q]) (void)hipFree(r->pkeys[q]);
+        if (r->pctx[q]) (void)hipFree(r->pctx[q]);
+    }
     delete r;
+}
+
+int pn_ref_prepare(pn_ref *r, int q) {
+    if (!r || q < 1 || q > 15) return PN_EINVAL;
+    DeviceGuard g(r->ctx->device);
+    pn::RefQDev P;
+    return ref_prepare(r, q, r->ctx->stream, &P);
 }
 
 uint64_t pn_ref_length(const pn_ref *r) { return r ? r->L : 0; }
@@ -656,15 +713,18 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     return PN_OK;
 }
 
-void launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
+int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
+    pn::RefQDev P;
+    PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
     const uint32_t *meta = (const uint32_t *)c->side_meta.p;
     pn::FilterOut fo{(uint2 *)c->cands.p,
                      {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
                      (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
-    pn::launch_filter(ref_desc(ref), index_desc(x), (const unsigned long long *)c->side.p,
+    pn::launch_filter(ref_desc(ref), P, index_desc(x), (const unsigned long long *)c->side.p,
                       meta + pn::kLcPatterns, fo, st);
     stage_end(c, st, tok, 1);
+    return PN_OK;
 }
 
 // largest and total count of a sharded list (host mirror)
@@ -710,7 +770,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         zero_counts(c, kLongCounts, st);
         if (filter) {
             zero_counts(c, kCandCounts, st);
-            launch_filter_into(c, ref, x, st);
+            PN_CHECK(launch_filter_into(c, ref, x, st));
         } else {
             zero_counts(c, kCandCounts, st);
             pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n_in, st);
@@ -914,8 +974,8 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         if (s) break;
         pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 4 * pn::kShards, 0u, st);
         zero_counts(c, kCandCounts, st);
-        launch_filter_into(c, ref, x, st);
-        s = read_misc(c, st);
+        s = launch_filter_into(c, ref, x, st);
+        if (!s) s = read_misc(c, st);
         if (s) break;
         uint64_t mx;
         region_counts(c, kCandCounts, pn::kShards, &mx, &n);

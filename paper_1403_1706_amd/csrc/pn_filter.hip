@@ -1,9 +1,13 @@
 // Algorithm 2: filtration of reference positions through the q-group index
-// (Section 3.2).  Both strands come from one pass over the forward 2-bit
-// text: the q-gram of strand 1 at position p = L-q-u is the reverse
-// complement of the forward q-gram at u.  For every (position, strand) the
-// occurrences of its q-gram are O[k_start .. k_end) (INDEXPAIR); each
-// occurrence (read r, offset o) that passes the rules below becomes a
+// (Section 3.2).  The position set P holds every (position, strand) of both
+// strands (the q-gram of strand 1 at p = L-q-u is the reverse complement of
+// the forward q-gram at u) and is sorted by q-gram, as the paper prepares
+// it with its reference index: neighbouring lanes then probe the same
+// parts of I, S, S' and O.  P is built once per reference and q
+// (k_refq_keys, a radix sort, k_refq_ctx), with a 16-bit context per entry:
+// the letter before the q-gram and up to four letters after it.  For every
+// entry the occurrences of its q-gram are O[k_start .. k_end) (INDEXPAIR);
+// each occurrence (read r, offset o) that passes the rules below becomes a
 // candidate (r, strand, diagonal d = p - o).
 //
 // Every rule below drops a candidate only if another one is guaranteed to
@@ -177,19 +181,75 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
         const uint32_t a0 = __shfl(rg.a0, leader), a1 = __shfl(rg.a1, leader);
         const uint32_t b0 = __shfl(rg.b0, leader), b1 = __shfl(rg.b1, leader);
         const int64_t lp = __shfl((long long)p, leader);
+        // everything about the leader's (position, strand), its strand included:
+        // neighbouring lanes need not be on the same strand
         const uint32_t flags = __shfl((has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
-                                          (avail << 4) | (N << 8),
+                                          (avail << 4) | (N << 8) | (s << 16),
                                       leader);
         const bool lhp = flags & 1u, llh = (flags >> 1) & 1u;
         const uint32_t lprev = (flags >> 2) & 3u, lavail = (flags >> 4) & 7u, lN = (flags >> 8) & 0xffu;
-        for (uint32_t t = a0 + lane; t < a1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
-        for (uint32_t t = b0 + lane; t < b1; t += 64) visit(src[t], lp, s, lhp, lprev, llh, lN, lavail, sg);
+        const uint32_t ls = (flags >> 16) & 1u;
+        for (uint32_t t = a0 + lane; t < a1; t += 64) visit(src[t], lp, ls, lhp, lprev, llh, lN, lavail, sg);
+        for (uint32_t t = b0 + lane; t < b1; t += 64) visit(src[t], lp, ls, lhp, lprev, llh, lN, lavail, sg);
     }
     return valid ? len : 0u;  // entries read for this lane's (position, strand)
 }
 
+// P's keys, one per forward position u: strand 0 at u, strand 1 at L-q-u;
+// key = ((p << 1 | strand) << 2q) | q-gram
+__global__ __launch_bounds__(256) void k_refq_keys(PnRefDev ref, int q,
+                                                   unsigned long long *__restrict__ keys) {
+    const uint64_t L = ref.L;
+    const uint64_t npos = L - q + 1;
+    const uint64_t u0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPPT;
+    if (u0 >= npos) return;
+    const uint64_t X = window32(ref.packed, (int64_t)u0 - 5);
+    const int sh = 2 * q;
+    for (int jj = 0; jj < kPPT && u0 + jj < npos; jj++) {
+        const uint64_t u = u0 + jj;
+        const uint32_t g0 = (uint32_t)((X << (2 * (jj + 5))) >> (64 - 2 * q));
+        keys[u] = ((unsigned long long)(u << 1) << sh) | g0;
+        keys[npos + u] = ((unsigned long long)(((L - q - u) << 1) | 1u) << sh) |
+                         pn_revcomp_code(g0, q);
+    }
+}
+
+// context of a sorted entry: letter before the q-gram (bits 0-1), whether
+// there is one (bit 2), letters after it that exist, up to 4 (bits 3-5),
+// and those letters (bits 6-13, first letter highest)
+__global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q,
+                                                  const unsigned long long *__restrict__ keys,
+                                                  uint64_t n, uint16_t *__restrict__ ctx) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t L = ref.L;
+    const unsigned long long ps = keys[i] >> (2 * q);
+    const uint64_t p = ps >> 1;
+    const uint32_t s = (uint32_t)(ps & 1u);
+    const uint64_t u = s ? L - q - p : p;  // forward position of the q-gram
+    const uint64_t X = window32(ref.packed, (int64_t)u - 5);
+    const uint64_t after = L - u - q;  // forward letters after the q-gram
+    uint32_t has, prev, N, avail;
+    if (!s) {
+        has = u >= 1;
+        prev = base_rel(X, 4);
+        N = (uint32_t)((X << (2 * (5 + q))) >> 56);
+        avail = after < 4 ? (uint32_t)after : 4u;
+    } else {
+        // T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
+        has = after >= 1;
+        prev = 3u - base_rel(X, 5 + q);
+        const uint32_t F = (uint32_t)(X >> 54) & 0xffu;  // R[u-4..u-1]
+        N = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) | (F >> 6)) ^ 0xffu;
+        avail = u < 4 ? (uint32_t)u : 4u;
+    }
+    if (!has) prev = 0;
+    N &= (0xffu << (8 - 2 * avail)) & 0xffu;
+    ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
+}
+
 template <typename TW>
-__global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
+__global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIndexDev ix,
                                                const unsigned long long *__restrict__ side,
                                                const uint32_t *__restrict__ side_cls,
                                                pn::FilterOut out) {
@@ -202,46 +262,32 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, PnIndexDev ix,
     Stage sg{wbuf[wave], &wcnt[wave], out.cands + (uint64_t)shard * out.sh.region_cap,
              out.sh.counts + shard, out.sh.region_cap, 0ull, 0u};
     const int q = ix.q;
-    const uint64_t L = ref.L;
-    const uint64_t u0 = ((uint64_t)blockIdx.x * kT + threadIdx.x) * kPPT;
+    const uint32_t gmask = (1u << (2 * q)) - 1u;
     unsigned long long seeds = 0, visited = 0;
-    // every lane runs the same 8 positions so that long slices can be
-    // shared by the wave; lanes past the end carry valid = false
-    const bool any = u0 + q <= L;
-    const uint64_t X = any ? window32(ref.packed, (int64_t)u0 - 5) : 0ull;
+    // the block takes kT * kPPT consecutive entries of P, a wave 64
+    // consecutive ones per round; every lane runs the same rounds so that
+    // long slices can be shared by the wave
+    const uint64_t i0 = (uint64_t)blockIdx.x * (kT * kPPT) + threadIdx.x;
     for (int jj = 0; jj < kPPT; jj++) {
-        const uint64_t u = u0 + jj;
-        const bool valid = any && u + q <= L;
-        // bases u0-5 .. u0+26: one letter before, q letters, four after on
-        // strand 0, and four before on the forward strand for strand 1
-        const int t0 = jj + 5;  // window index of base u
-        const uint32_t g0 = (uint32_t)((X << (2 * t0)) >> (64 - 2 * q));
-        const uint32_t g1 = pn_revcomp_code(g0, q);
-        // strand 0 at p = u
-        const bool has0 = u >= 1;
-        const uint32_t prev0 = base_rel(X, t0 - 1);
-        const uint32_t N0 = (uint32_t)((X << (2 * (t0 + q))) >> 56);
-        const uint64_t after0 = valid ? L - u - q : 0;
-        const uint32_t avail0 = after0 < 4 ? (uint32_t)after0 : 4u;
-        const bool lh0 = has0 && pn_low_complexity((prev0 << (2 * (q - 1))) | (g0 >> 2), q);
-        // strand 1 at p = L-q-u: T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
-        const bool has1 = after0 >= 1;
-        const uint32_t prev1 = 3u - base_rel(X, t0 + q);
-        const uint32_t F = (uint32_t)(X >> (62 - 2 * (t0 - 1))) & 0xffu;  // R[u-4..u-1]
-        const uint32_t N1 = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) |
-                             (F >> 6)) ^ 0xffu;
-        const uint32_t avail1 = u < 4 ? (uint32_t)u : 4u;
-        const bool lh1 = has1 && pn_low_complexity((prev1 << (2 * (q - 1))) | (g1 >> 2), q);
-        Ranges r0, r1;
+        const uint64_t i = i0 + (uint64_t)jj * kT;
+        const bool valid = i < P.n;
+        const unsigned long long key = valid ? P.keys[i] : 0ull;
+        const uint32_t c = valid ? P.ctx[i] : 0u;
+        const uint32_t g = (uint32_t)key & gmask;
+        const unsigned long long ps = key >> (2 * q);
+        const int64_t p = (int64_t)(ps >> 1);
+        const uint32_t s = (uint32_t)(ps & 1u);
+        const bool has = (c >> 2) & 1u;
+        const uint32_t prev = c & 3u, avail = (c >> 3) & 7u, N = (c >> 6) & 0xffu;
+        const bool lh = has && pn_low_complexity((prev << (2 * (q - 1))) | (g >> 2), q);
+        Ranges r;
         if (valid) {
-            seeds += probe<TW>(ix, side, side_cls, g0, has0, prev0, r0);
-            seeds += probe<TW>(ix, side, side_cls, g1, has1, prev1, r1);
+            seeds += probe<TW>(ix, side, side_cls, g, has, prev, r);
         } else {
-            r0.src = r1.src = ix.O;
-            r0.a0 = r0.a1 = r0.b0 = r0.b1 = r1.a0 = r1.a1 = r1.b0 = r1.b1 = 0;
+            r.src = ix.O;
+            r.a0 = r.a1 = r.b0 = r.b1 = 0;
         }
-        visited += visit_all(r0, (int64_t)u, 0u, has0, prev0, lh0, N0, avail0, valid, sg);
-        visited += visit_all(r1, (int64_t)(L - q - u), 1u, has1, prev1, lh1, N1, avail1, valid, sg);
+        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg);
     }
     for (int o = 32; o > 0; o >>= 1) {
         seeds += __shfl_xor(seeds, o);
@@ -411,17 +457,32 @@ void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo,
     hipLaunchKernelGGL(k_stamp_rules, dim3((unsigned)blocks), dim3(256), 0, st, O, n, rinfo);
 }
 
-void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const unsigned long long *side,
-                   const uint32_t *side_cls, FilterOut out, hipStream_t st) {
-    const uint64_t npos = ref.L >= (uint64_t)ix.q ? ref.L - ix.q + 1 : 0;
-    const uint64_t nb = (npos + kFilterBlockPos - 1) / kFilterBlockPos;
+void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipStream_t st) {
+    if (ref.L < (uint64_t)q) return;
+    const uint64_t npos = ref.L - q + 1;
+    const uint64_t threads = (npos + kPPT - 1) / kPPT;
+    hipLaunchKernelGGL(k_refq_keys, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ref,
+                       q, keys);
+}
+
+void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys, uint64_t n,
+                     uint16_t *ctx, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_refq_ctx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ref, q,
+                       keys, n, ctx);
+}
+
+void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
+                   const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
+                   hipStream_t st) {
+    const uint64_t nb = (P.n + kFilterBlockPos - 1) / kFilterBlockPos;
     if (!nb || !ix.n_reads) return;
     if (ix.log2w == 6)
         hipLaunchKernelGGL(k_filter<unsigned long long>, dim3((unsigned)nb), dim3(kT), 0, st, ref,
-                           ix, side, side_cls, out);
+                           P, ix, side, side_cls, out);
     else
-        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, ix, side,
-                           side_cls, out);
+        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, P, ix,
+                           side, side_cls, out);
 }
 
 }  // namespace pn

@@ -203,8 +203,18 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
                     const uint32_t *region, uint32_t *side_cls, hipStream_t st);
 // write each read's rule byte into the low byte of its O entries
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st);
-void launch_filter(const PnRefDev &ref, const PnIndexDev &ix, const unsigned long long *side,
-                   const uint32_t *side_cls, FilterOut out, hipStream_t st);
+// the position set P of a reference for one q, sorted by q-gram
+struct RefQDev {
+    const unsigned long long *keys;  // ((p << 1 | strand) << 2q) | q-gram
+    const uint16_t *ctx;             // letters around each entry's q-gram
+    uint64_t n;                      // 2 (L - q + 1)
+};
+void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipStream_t st);
+void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys, uint64_t n,
+                     uint16_t *ctx, hipStream_t st);
+void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
+                   const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
+                   hipStream_t st);
 
 // pn_verify.hip (Section 3.3)
 struct VerifyIn {

@@ -264,6 +264,9 @@ int pn_server_create(const pn_ref *ref, const pn_server_config *cfg, pn_server *
         cfg->slots > 8 || cfg->max_batch_reads < 1 || cfg->max_batch_reads > PN_MAX_READS ||
         cfg->hbm_budget == 0)
         return PN_EINVAL;
+    // the reference's q-gram-sorted position set, before the first request
+    const int prc = pn_ref_prepare(const_cast<pn_ref *>(ref), cfg->q);
+    if (prc) return prc;
     pn_server *s = new (std::nothrow) pn_server();
     if (!s) return PN_ENOMEM;
     s->device = pnrt::ref_device(ref);

@@ -427,3 +427,23 @@ def test_low_complexity_reads_equal_definition(pn, sess):
             say(f"low-complexity q={q} mode={mode}")
             g = pn.pn_map(sess.ctx, refh, idx, kr, mode)
             assert_hits_equal(g, oracle.map_sellers(ref, buf, offs, kr, best=bool(mode)))
+
+
+def test_repeat_family_in_both_orientations(pn, sess):
+    # A 400 bp family copied 30 times forward and 30 times reverse-complemented:
+    # each of its q-grams has well over 64 read occurrences (walked by a whole
+    # wave) and, in q-gram order, reference entries of both strands side by side.
+    rng = np.random.Generator(np.random.PCG64(7001))
+    ref = synth.iid_reference(200_000, rng)
+    fam = ref[1000:1400].copy()
+    starts = rng.choice(np.arange(5000, 195_000, 3000), 60, replace=False)
+    for i, st in enumerate(starts):
+        ref[st:st + 400] = fam if i % 2 == 0 else 3 - fam[::-1]
+    # 600 reads around the family's source (each family q-gram in ~80 of
+    # them, both strands), 100 from anywhere
+    r1, o1, _, _ = synth.simulate_reads(ref[800:1600], np.full(600, 100, dtype=np.int64), 0.02, rng)
+    r2, o2, _, _ = synth.simulate_reads(ref, np.full(100, 100, dtype=np.int64), 0.02, rng)
+    offsets = np.concatenate([o1, o2[1:] + o1[-1]]).astype(np.uint64)
+    w = synth.Workload("family", synth.ALPHABET[ref].tobytes(), r1 + r2, offsets, 12,
+                       np.full(700, 5, dtype=np.uint8))
+    map_both(pn, sess, w)

@@ -72,8 +72,19 @@ __device__ __forceinline__ uint32_t base_rel(uint64_t X, int t) {
 
 constexpr uint32_t kLaneChunk = 64;  // slots a lane reserves at a time
 
+// Pointers with their address space spelled out: a plain pointer kept in a
+// struct or chosen between two arrays is generic, and the compiler then
+// uses flat loads and stores, which wait on both the vector-memory and the
+// LDS counters.
+typedef __attribute__((address_space(1))) const unsigned long long gu64;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+
+__device__ __forceinline__ unsigned long long pack_cand(uint2 c) {
+    return ((unsigned long long)c.y << 32) | c.x;
+}
+
 struct Stage {
-    uint2 *buf;      // this wave's LDS buffer
+    lds_u64 *buf;    // this wave's LDS buffer (candidates packed as y:x)
     uint32_t *cnt;   // this wave's LDS counter
     uint2 *region;   // this block's output region
     unsigned long long *count;  // its counter
@@ -85,7 +96,7 @@ struct Stage {
 __device__ __forceinline__ void push(Stage &sg, uint2 c) {
     uint32_t i = atomicAdd(sg.cnt, 1u);
     if (i < kWBuf) {
-        sg.buf[i] = c;
+        sg.buf[i] = pack_cand(c);
         return;
     }
     if (sg.lane_left == 0) {
@@ -126,7 +137,7 @@ constexpr uint32_t kBigSlice = 64;
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
 // the low-complexity side lists).  Returns k_end - k_start.
 struct Ranges {
-    const unsigned long long *src;
+    gu64 *src;
     uint32_t a0, a1, b0, b1;
 };
 
@@ -134,7 +145,7 @@ template <typename TW>
 __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned long long *side,
                                           const uint32_t *side_cls, uint32_t g, bool has_prev,
                                           uint32_t prev, Ranges &rg) {
-    rg.src = ix.O;
+    rg.src = (gu64 *)ix.O;
     rg.a0 = rg.a1 = rg.b0 = rg.b1 = 0;
     const TW *I = (const TW *)ix.I;
     const uint32_t wmask = (1u << ix.log2w) - 1;
@@ -148,7 +159,7 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
         // rule 2: only reads that keep these seeds, listed by preceding
         // letter; for those reads rule 1 drops the class equal to `prev`
         const uint32_t *cb = side_cls + (g >> (2 * ix.q - 4)) * 6;
-        rg.src = side;
+        rg.src = (gu64 *)side;
         rg.a0 = cb[0];
         rg.b1 = cb[5];
         rg.a1 = has_prev ? cb[prev] : rg.b1;
@@ -169,7 +180,16 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     const bool big = valid && len > kBigSlice;
     if (valid && !big) {
-        for (uint32_t t = rg.a0; t < rg.a1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
+        // the next entry is loaded while this one is checked
+        if (rg.a0 < rg.a1) {
+            unsigned long long v = rg.src[rg.a0];
+            for (uint32_t t = rg.a0 + 1; t < rg.a1; t++) {
+                const unsigned long long nv = rg.src[t];
+                visit(v, p, s, has_prev, prev, lh, N, avail, sg);
+                v = nv;
+            }
+            visit(v, p, s, has_prev, prev, lh, N, avail, sg);
+        }
         for (uint32_t t = rg.b0; t < rg.b1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
     }
     unsigned long long mask = __ballot(big);
@@ -177,7 +197,7 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     while (mask) {
         const int leader = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
-        const unsigned long long *src = (const unsigned long long *)__shfl((long long)rg.src, leader);
+        gu64 *src = (gu64 *)__shfl((long long)rg.src, leader);
         const uint32_t a0 = __shfl(rg.a0, leader), a1 = __shfl(rg.a1, leader);
         const uint32_t b0 = __shfl(rg.b0, leader), b1 = __shfl(rg.b1, leader);
         const int64_t lp = __shfl((long long)p, leader);
@@ -259,7 +279,8 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t shard = blockIdx.x % pn::kShards;
-    Stage sg{wbuf[wave], &wcnt[wave], out.cands + (uint64_t)shard * out.sh.region_cap,
+    Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave],
+             out.cands + (uint64_t)shard * out.sh.region_cap,
              out.sh.counts + shard, out.sh.region_cap, 0ull, 0u};
     const int q = ix.q;
     const uint32_t gmask = (1u << (2 * q)) - 1u;
@@ -284,7 +305,7 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
         if (valid) {
             seeds += probe<TW>(ix, side, side_cls, g, has, prev, r);
         } else {
-            r.src = ix.O;
+            r.src = (gu64 *)ix.O;
             r.a0 = r.a1 = r.b0 = r.b1 = 0;
         }
         visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg);

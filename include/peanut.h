@@ -252,11 +252,13 @@ int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_ca
  * (device arrays as for pn_index_build_dev; k >= 0 for all reads, or
  * k < 0 and device k_per_read).  q must satisfy the q-gram lemma
  * (k_r + 1) q <= n_r for every read of the batch (Section 2.2); each such
- * (q, w) is timed on the batch's first sample_reads reads (index build +
- * pn_map_dev, best of two runs after a warm-up) and the fastest is returned
- * in *best_q, *best_w.  results[] (room for 6) receives every candidate
- * with its time (ms) or status (PN_ELEMMA when the lemma excludes it);
- * *n_results their count.  The hits do not depend on the choice: the
+ * (q, w) is timed (index build + pn_map_dev, best of two runs after a
+ * warm-up) on the batch's first sample_reads reads and on half as many; the
+ * line through the two times is evaluated at the whole batch (a fixed part,
+ * the reference scan, plus a part per read) and the fastest prediction is
+ * returned in *best_q, *best_w.  results[] (room for 6) receives every
+ * candidate with its predicted time (ms) or status (PN_ELEMMA when the
+ * lemma excludes it); *n_results their count.  The hits do not depend on the choice: the
  * filter is lossless for every admitted q.  PN_ELEMMA if no q is
  * admitted. */
 typedef struct {

@@ -1,10 +1,13 @@
 // Autotuning of the index parameters for a read batch: q (Section 2.2; a
 // larger q gives fewer random q-gram hits but a weaker lemma) and the group
 // width w of I (Section 2.2, GROUPBIT/GROUPRANK).  Every candidate that the
-// q-gram lemma admits for every read of the batch is timed on a sample of
-// the batch (build + map, best of a few runs) and the fastest is returned.
-// The hit list does not depend on the choice (the filter is lossless for
-// every admitted q), so the tuner only changes time.
+// q-gram lemma admits for every read of the batch is timed (build + map,
+// best of a few runs) on the batch's first m and first m/2 reads.  A mapping
+// costs a part that does not depend on the reads (the scan of the
+// reference) plus a part per read (index, candidates, verification), so the
+// two times give a line that is evaluated at the whole batch; the fastest
+// prediction wins.  The hit list does not depend on the choice (the filter
+// is lossless for every admitted q), so the tuner only changes time.
 #include <algorithm>
 #include <chrono>
 #include <vector>
@@ -76,6 +79,11 @@ int pn_autotune(pn_ctx *ctx, const pn_ref *ref, const char *d_reads, const uint6
     uint64_t sample_bases = 0;
     e = hipMemcpyAsync(&sample_bases, d_offsets + m, 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    uint64_t half_bases = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&half_bases, d_offsets + std::max<uint32_t>(1, m / 2), 8,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess || sample_bases > n_bases) return e != hipSuccess ? PN_EDEVICE : PN_EINVAL;
     // device output for the sample's hits (sized after a first run)
     pn_hit *d_hits = nullptr;
@@ -96,34 +104,43 @@ int pn_autotune(pn_ctx *ctx, const pn_ref *ref, const char *d_reads, const uint6
                 res.status = PN_ELEMMA;
                 continue;
             }
-            double t_best = 1e300;
-            for (int rep = 0; rep < 3 && res.status == PN_OK; rep++) {
-                const double t0 = now_ms();
-                pn_index *x = nullptr;
-                int s = pn_index_build_dev(ctx, d_reads, d_offsets, m, sample_bases, q, w, st, &x);
-                uint64_t n_hits = 0;
-                if (!s) {
-                    s = pn_map_dev(ctx, ref, x, k, d_k_per_read, mode, d_hits, cap, &n_hits, st);
-                    if (s == PN_ETRUNC) {  // size the output once, then time again
-                        if (d_hits) (void)hipFree(d_hits);
-                        cap = n_hits + n_hits / 4 + 1;
-                        d_hits = nullptr;
-                        s = hipMalloc((void **)&d_hits, cap * sizeof(pn_hit)) == hipSuccess
-                                ? PN_OK
-                                : PN_ENOMEM;
-                        if (!s) s = pn_map_dev(ctx, ref, x, k, d_k_per_read, mode, d_hits, cap,
+            double t_at[2] = {1e300, 1e300};
+            for (int half = 0; half < 2 && res.status == PN_OK; half++) {
+                const uint32_t mm = half ? std::max<uint32_t>(1, m / 2) : m;
+                const uint64_t bb = half ? half_bases : sample_bases;
+                for (int rep = 0; rep < 3 && res.status == PN_OK; rep++) {
+                    const double t0 = now_ms();
+                    pn_index *x = nullptr;
+                    int s = pn_index_build_dev(ctx, d_reads, d_offsets, mm, bb, q, w, st, &x);
+                    uint64_t n_hits = 0;
+                    if (!s) {
+                        s = pn_map_dev(ctx, ref, x, k, d_k_per_read, mode, d_hits, cap, &n_hits, st);
+                        if (s == PN_ETRUNC) {  // size the output once, then time again
+                            if (d_hits) (void)hipFree(d_hits);
+                            cap = n_hits + n_hits / 4 + 1;
+                            d_hits = nullptr;
+                            s = hipMalloc((void **)&d_hits, cap * sizeof(pn_hit)) == hipSuccess
+                                    ? PN_OK
+                                    : PN_ENOMEM;
+                            if (!s)
+                                s = pn_map_dev(ctx, ref, x, k, d_k_per_read, mode, d_hits, cap,
                                                &n_hits, st);
-                        rep = -1;  // this run paid for sizing: not timed
+                            rep = -1;  // this run paid for sizing: not timed
+                        }
+                        pn_index_free(x);
                     }
-                    pn_index_free(x);
+                    if (s == PN_OK && hipStreamSynchronize(st) != hipSuccess) s = PN_EDEVICE;
+                    if (s) {
+                        res.status = s;
+                        break;
+                    }
+                    if (rep >= 1) t_at[half] = std::min(t_at[half], now_ms() - t0);  // after a warm-up
                 }
-                if (s == PN_OK && hipStreamSynchronize(st) != hipSuccess) s = PN_EDEVICE;
-                if (s) {
-                    res.status = s;
-                    break;
-                }
-                if (rep >= 1) t_best = std::min(t_best, now_ms() - t0);  // first run warms up
             }
+            // the line through (m/2, t_half) and (m, t_m), at n_reads
+            const double mh = std::max<uint32_t>(1, m / 2);
+            const double slope = m > mh ? std::max(0.0, (t_at[0] - t_at[1]) / (m - mh)) : 0.0;
+            const double t_best = t_at[0] + slope * ((double)n_reads - m);
             if (res.status == PN_OK) {
                 res.ms = t_best;
                 if (t_best < best) {

@@ -17,11 +17,31 @@ __host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo,
 // and returns the number of rows computed.  A candidate still alive after
 // row_cap rows (a multiple of 32, below len) stops there without emitting
 // and -row_cap is returned; the caller runs it again from row 0 without cap.
+// The first memory words a candidate needs: plane blocks blk .. blk+3 of
+// its stream and the read's first plane word.  Loading them is separate so
+// that a kernel can issue one candidate's loads while it computes another.
+struct PnBandHead {
+    uint4 A, B, C, Dn;
+    uint2 rw0;
+};
+
+__host__ __device__ __forceinline__ void pn_band_load(const uint4 *__restrict__ pl,
+                                                      const uint2 *__restrict__ rp, int64_t lo,
+                                                      PnBandHead &h) {
+    const uint64_t blk = (uint64_t)(lo + PN_PAD_POS) >> 5;
+    h.A = pl[blk];
+    h.B = pl[blk + 1];
+    h.C = pl[blk + 2];
+    h.Dn = pl[blk + 3];
+    h.rw0 = rp[0];
+}
+
 template <typename Emit>
-__host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__ pl,
-                                                       const uint2 *__restrict__ rp, int len, int k,
-                                                       int64_t lo, uint64_t L, int row_cap,
-                                                       Emit &&emit) {
+__host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
+                                                    const uint4 *__restrict__ pl,
+                                                    const uint2 *__restrict__ rp, int len, int k,
+                                                    int64_t lo, uint64_t L, int row_cap,
+                                                    Emit &&emit) {
     const int W = 2 * k + 1;
     const uint32_t M = (1u << W) - 1u;
     const uint32_t M2 = M & ~1u;
@@ -31,14 +51,14 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
     const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
     const uint64_t blk = tp >> 5;
     const uint32_t ph = (uint32_t)(tp & 31);
-    const uint4 A = pl[blk], B = pl[blk + 1];
-    uint4 C = pl[blk + 2], Dn = pl[blk + 3];
+    const uint4 A = hd.A, B = hd.B;
+    uint4 C = hd.C, Dn = hd.Dn;
     uint32_t h0 = pn_funnel(B.x, A.x, ph), l0 = pn_funnel(B.y, A.y, ph), v0 = pn_funnel(B.z, A.z, ph);
     uint32_t h1 = pn_funnel(C.x, B.x, ph), l1 = pn_funnel(C.y, B.y, ph), v1 = pn_funnel(C.z, B.z, ph);
     uint32_t VP = 0, VN = 0;  // row 0: every band cell is 0 (free start)
     int R = 0;                // value of the right-most band cell
     for (int m = 0;; m++) {
-        const uint2 rw = rp[m];
+        const uint2 rw = m == 0 ? hd.rw0 : rp[m];
 #pragma unroll
         for (int t = 0; t < 32; t++) {
             const int i = 32 * m + t + 1;  // row i compares read letter i-1
@@ -80,4 +100,15 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
         C = Dn;
         Dn = pl[blk + m + 4];
     }
+}
+
+// one candidate start to finish (loads, then rows)
+template <typename Emit>
+__host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__ pl,
+                                                       const uint2 *__restrict__ rp, int len, int k,
+                                                       int64_t lo, uint64_t L, int row_cap,
+                                                       Emit &&emit) {
+    PnBandHead hd;
+    pn_band_load(pl, rp, lo, hd);
+    return pn_band_run(hd, pl, rp, len, k, lo, L, row_cap, emit);
 }

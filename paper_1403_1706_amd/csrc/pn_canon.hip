@@ -33,23 +33,40 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long lon
     hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile: the tile's keys are first put in digit order
+// in LDS (rank among equal digits from ballots, wave by wave), then written
+// out so that consecutive threads write consecutive addresses of one
+// digit's run.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
                                                             unsigned long long *out, uint64_t n,
                                                             int shift, uint32_t dmask,
-                                                            const uint32_t *offs, uint64_t n_tiles) {
-    __shared__ uint32_t run[256];
+                                                            const uint32_t *offs,
+                                                            const uint32_t *hist,
+                                                            uint64_t n_tiles) {
+    __shared__ unsigned long long tile[kTile];
+    __shared__ uint32_t local[256];  // start of each digit inside the tile
+    __shared__ uint32_t run[256];    // next free slot of each digit inside the tile
     __shared__ uint32_t wcnt[4][256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    run[threadIdx.x] = offs[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    const uint32_t tile_n = (uint32_t)min((uint64_t)kTile, n - base);
+    // exclusive scan of this tile's digit counts
+    {
+        const uint32_t c = hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
+        uint32_t tot;
+        const uint32_t ex = pn_block_excl_scan(c, &tot);
+        local[threadIdx.x] = ex;
+        run[threadIdx.x] = ex;
+    }
+    __syncthreads();
     for (int j = 0; j < kItems; j++) {
 #pragma unroll
         for (int w = 0; w < 4; w++) wcnt[w][threadIdx.x] = 0;
         __syncthreads();
-        const uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
-        const bool valid = i < n;
-        const unsigned long long key = valid ? keys[i] : 0ull;
+        const uint32_t li = (uint32_t)j * kThreads + threadIdx.x;
+        const bool valid = li < tile_n;
+        const unsigned long long key = valid ? keys[base + li] : 0ull;
         const uint32_t dg = (uint32_t)(key >> shift) & dmask;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -64,12 +81,19 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
         if (valid) {
             uint32_t pos = run[dg] + rank;
             for (int w = 0; w < wave; w++) pos += wcnt[w][dg];
-            out[pos] = key;
+            tile[pos] = key;
         }
         __syncthreads();
         run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
                             wcnt[3][threadIdx.x];
         __syncthreads();
+    }
+    // the tile in digit order: slot i belongs to digit d with local[d] <= i,
+    // and goes to offs[d] + (i - local[d])
+    for (uint32_t i = threadIdx.x; i < tile_n; i += kThreads) {
+        const unsigned long long key = tile[i];
+        const uint32_t dg = (uint32_t)(key >> shift) & dmask;
+        out[offs[(uint64_t)dg * n_tiles + blockIdx.x] + (i - local[dg])] = key;
     }
 }
 
@@ -180,7 +204,7 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
                            dmask, hist, nt);
         launch_scan_u32(hist, offs, 256 * nt, partials, st);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,
-                           shift, dmask, offs, nt);
+                           shift, dmask, offs, hist, nt);
         unsigned long long *t = src;
         src = dst;
         dst = t;

@@ -93,8 +93,17 @@ struct Stage {
     uint32_t lane_left;
 };
 
+// The lanes that reach this together append one candidate each: one of
+// them reserves stage slots for all (per-lane atomics on the one LDS
+// counter would serialise), the others take consecutive slots in lane order.
 __device__ __forceinline__ void push(Stage &sg, uint2 c) {
-    uint32_t i = atomicAdd(sg.cnt, 1u);
+    const unsigned long long mask = __ballot(1);  // the lanes appending now
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t first = 0;
+    if (lane == leader) first = atomicAdd(sg.cnt, (uint32_t)__popcll(mask));
+    first = __shfl(first, leader);
+    const uint32_t i = first + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     if (i < kWBuf) {
         sg.buf[i] = pack_cand(c);
         return;

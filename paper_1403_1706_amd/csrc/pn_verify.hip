@@ -77,6 +77,38 @@ struct Stage {
     }
 };
 
+// A candidate ready to run: its parameters and first memory words.
+struct Cand {
+    uint2 c;
+    bool ok;
+    int len, k;
+    int64_t lo;  // reference position of the band's first diagonal
+    const uint4 *pl;
+    const uint2 *rp;
+    unsigned long long head;  // record key prefix (read, strand)
+    PnBandHead hd;
+};
+
+// issue a candidate's loads (slot value c; padding and bad reads give !ok)
+__device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix, int kglob,
+                                      const uint8_t *__restrict__ kpr, int ebits, uint2 c,
+                                      Cand &x) {
+    x.c = c;
+    x.ok = false;
+    if (c.x == PN_CAND_NONE) return;  // padding slot
+    const uint32_t r = c.x & 0x7fffffffu;
+    const uint32_t s = c.x >> 31;
+    x.len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
+    x.k = kglob >= 0 ? kglob : (int)kpr[r];
+    if (x.k > PN_MAX_K || x.len < 1 || x.len > PN_MAX_READ_LEN) return;
+    x.ok = true;
+    x.lo = (int64_t)c.y - (int64_t)PN_DBIAS - x.k;
+    x.pl = s ? ref.planes[1] : ref.planes[0];
+    x.rp = ix.rplanes + (uint64_t)r * PN_READ_WORDS;
+    x.head = (((unsigned long long)r << 1) | s) << ebits;
+    pn_band_load(x.pl, x.rp, x.lo, x.hd);
+}
+
 // Block b reads input region b % in.regions; its records go to output
 // region b % kShards and (first pass) its survivors to long region
 // b % in.regions, which can hold every candidate of that input region.
@@ -104,34 +136,33 @@ __global__ __launch_bounds__(kThreads) void k_verify(PnRefDev ref, PnIndexDev ix
     const uint64_t n = min((uint64_t)in.counts[rin], in.region_cap);
     const uint64_t per = gridDim.x / in.regions;  // blocks per input region
     const uint64_t stride = per * kThreads;
+    const uint2 none = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
     unsigned long long rows = 0;
+    // Software pipeline over this lane's candidates: while one candidate's
+    // rows run, the next one's read length, k and first plane words are in
+    // flight, and the one after that is being read from the list.
+    uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64;
+    uint2 c_next = base + lane < n ? cands[base + lane] : none;
+    uint2 c_after = base + stride + lane < n ? cands[base + stride + lane] : none;
+    Cand cur;
+    start(ref, ix, kglob, kpr, out.ebits, c_next, cur);
     // the loop bound is wave-uniform, so the wave is converged at the flushes
-    for (uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64; base < n;
-         base += stride) {
-        const uint64_t ci = base + lane;
-        if (ci < n) {
-            const uint2 c = cands[ci];
-            if (c.x != PN_CAND_NONE) {  // else a padding slot
-                const uint32_t r = c.x & 0x7fffffffu;
-                const uint32_t s = c.x >> 31;
-                const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
-                const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
-                const int k = kglob >= 0 ? kglob : (int)kpr[r];
-                if (k <= PN_MAX_K && len >= 1 && len <= PN_MAX_READ_LEN) {
-                    const unsigned long long head = (((unsigned long long)r << 1) | s)
-                                                    << out.ebits;
-                    const int rw = pn_band_verify(
-                        s ? ref.planes[1] : ref.planes[0],
-                        ix.rplanes + (uint64_t)r * PN_READ_WORDS, len, k, d - k, ref.L,
-                        kFirst ? kShortRows : PN_MAX_READ_LEN, [&](uint32_t e, int v) {
-                            rec.push(((head | (unsigned long long)e) << 5) |
-                                     (unsigned long long)v);
-                        });
-                    if (kFirst && rw < 0) lng.push(((unsigned long long)c.y << 32) | c.x);
-                    rows += (unsigned long long)(rw < 0 ? -rw : rw);
-                }
-            }
+    for (; base < n; base += stride) {
+        Cand nxt;
+        start(ref, ix, kglob, kpr, out.ebits, c_after, nxt);
+        const uint64_t ci2 = base + 2 * stride + lane;
+        c_after = ci2 < n ? cands[ci2] : none;
+        if (cur.ok) {
+            const unsigned long long head = cur.head;
+            const int rw = pn_band_run(
+                cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
+                kFirst ? kShortRows : PN_MAX_READ_LEN, [&](uint32_t e, int v) {
+                    rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
+                });
+            if (kFirst && rw < 0) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
+            rows += (unsigned long long)(rw < 0 ? -rw : rw);
         }
+        cur = nxt;
         if (*rec.cnt >= kStage / 2) rec.flush(lane);
         if (kFirst && *lng.cnt >= kStage / 2) lng.flush(lane);
     }

@@ -34,7 +34,8 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kRecCounts = kCandCounts + pn::kShards,
     kLongCounts = kRecCounts + pn::kShards,
     kFilterStats = kLongCounts + pn::kShards,  // 2 x pn::kShards words
-    kMiscWords = kFilterStats + 2 * pn::kShards
+    kHeavyCounts = kFilterStats + 2 * pn::kShards,
+    kMiscWords = kHeavyCounts + pn::kShards
 };
 
 struct PendingStage {
@@ -53,11 +54,12 @@ struct pn_ctx {
     uint64_t *misc = nullptr;             // device scratch words (MiscSlot)
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
-    Buf cands, longc, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
+    Buf cands, longc, heavy, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
         out_hits, out_best;
     // capacities per output region (pn::kShards regions; grow on demand)
     uint64_t cand_rcap = 1ull << 18;
     uint64_t rec_rcap = 1ull << 14;
+    uint64_t heavy_rcap = 1ull << 12;  // filter entries set aside for a block each
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -716,9 +718,13 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
 int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
     pn::RefQDev P;
     PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
+    PN_CHECK(ensure(c, c->heavy, pn::kShards * c->heavy_rcap * 2 * sizeof(uint4)));
+    pn::launch_fill_u32((uint32_t *)&c->misc[kHeavyCounts], 2 * pn::kShards, 0u, st);
     const uint32_t *meta = (const uint32_t *)c->side_meta.p;
     pn::FilterOut fo{(uint2 *)c->cands.p,
                      {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
+                     (uint4 *)c->heavy.p,
+                     {(unsigned long long *)&c->misc[kHeavyCounts], c->heavy_rcap},
                      (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
     pn::launch_filter(ref_desc(ref), P, index_desc(x), (const unsigned long long *)c->side.p,
@@ -734,6 +740,16 @@ void region_counts(const pn_ctx *c, int slot, uint32_t regions, uint64_t *mx, ui
         *mx = std::max<uint64_t>(*mx, c->hmisc[slot + g]);
         *total += c->hmisc[slot + g];
     }
+}
+
+// after a filtration: did a heavy-item region overflow?  (then its capacity
+// grows and the caller runs the filtration again)
+bool heavy_overflow(pn_ctx *c) {
+    uint64_t mx, tot;
+    region_counts(c, kHeavyCounts, pn::kShards, &mx, &tot);
+    if (mx <= c->heavy_rcap) return false;
+    c->heavy_rcap = mx + mx / 4;
+    return true;
 }
 
 // occurrence pairs seen and index entries read by the last filtration
@@ -792,6 +808,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
             c->cand_rcap = cand_max + cand_max / 4;
             continue;
         }
+        if (filter && heavy_overflow(c)) continue;
         if (rec_max > c->rec_rcap) {
             c->rec_rcap = rec_max + rec_max / 4;
             continue;
@@ -979,8 +996,9 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         if (s) break;
         uint64_t mx;
         region_counts(c, kCandCounts, pn::kShards, &mx, &n);
-        if (mx <= c->cand_rcap) break;
-        c->cand_rcap = mx + mx / 4;
+        const bool hov = heavy_overflow(c);
+        if (mx <= c->cand_rcap && !hov) break;
+        if (mx > c->cand_rcap) c->cand_rcap = mx + mx / 4;
         n = 0;
     }
     uint64_t seeds = 0, visited = 0;

@@ -86,9 +86,11 @@ __device__ __forceinline__ unsigned long long pack_cand(uint2 c) {
 struct Stage {
     lds_u64 *buf;    // this wave's LDS buffer (candidates packed as y:x)
     uint32_t *cnt;   // this wave's LDS counter
-    uint2 *region;   // this block's output region
-    unsigned long long *count;  // its counter
+    uint2 *cands;    // all output regions
+    unsigned long long *counts;  // their counters
     uint64_t region_cap;
+    uint32_t shard;  // region the next flush goes to (the same in every lane)
+    uint2 *lane_region;            // region of this lane's reserved slots
     unsigned long long lane_base;  // this lane's reserved slots
     uint32_t lane_left;
 };
@@ -109,12 +111,46 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
         return;
     }
     if (sg.lane_left == 0) {
-        sg.lane_base = atomicAdd(sg.count, (unsigned long long)kLaneChunk);
+        sg.lane_region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
+        sg.lane_base = atomicAdd(sg.counts + sg.shard, (unsigned long long)kLaneChunk);
         sg.lane_left = kLaneChunk;
     }
     const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left);
     sg.lane_left--;
-    if (at < sg.region_cap) sg.region[at] = c;
+    if (at < sg.region_cap) sg.lane_region[at] = c;
+}
+
+// Copy the wave's staged candidates out with one atomic add (whole wave,
+// converged) and empty the stage.  Successive flushes of a wave go to
+// successive regions, so the regions fill evenly however unevenly the work
+// falls on the blocks.
+__device__ __forceinline__ void flush(Stage &sg, int lane) {
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n = min(*sg.cnt, (uint32_t)kWBuf);
+    if (n) {
+        uint2 *region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(sg.counts + sg.shard, (unsigned long long)n);
+        base = __shfl(base, 0);
+        for (uint32_t i = lane; i < n; i += 64) {
+            const unsigned long long v = sg.buf[i];
+            if (base + i < sg.region_cap)
+                region[base + i] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+        }
+        sg.shard = (sg.shard + 1) % pn::kShards;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) *sg.cnt = 0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// pad the unused part of this lane's reserved slots
+__device__ __forceinline__ void pad_lane(Stage &sg) {
+    for (uint32_t i = 0; i < sg.lane_left; i++) {
+        const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;
+        if (at < sg.region_cap) sg.lane_region[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    }
+    sg.lane_left = 0;
 }
 
 // one (position, strand): INDEXPAIR and the rules of the header comment
@@ -139,8 +175,10 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
     push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
 }
 
-// Slices longer than this are walked by the whole wave together.
+// Slices longer than this are walked by the whole wave together; longer
+// than kHeavy they are set aside for a block of their own.
 constexpr uint32_t kBigSlice = 64;
+constexpr uint32_t kHeavy = 1024;
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
@@ -185,10 +223,38 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
 // the whole wave (every lane of the wave must call this together)
 __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint32_t s,
                                               bool has_prev, uint32_t prev, bool lh, uint32_t N,
-                                              uint32_t avail, bool valid, Stage &sg) {
+                                              uint32_t avail, bool valid, Stage &sg,
+                                              const unsigned long long *side,
+                                              const pn::FilterOut &out) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
-    const bool big = valid && len > kBigSlice;
-    if (valid && !big) {
+    // the longest ranges wait for k_filter_heavy (a block each)
+    const bool heavy = valid && len > kHeavy;
+    const bool big = valid && len > kBigSlice && !heavy;
+    const unsigned long long hm = __ballot(heavy);
+    if (hm) {
+        const int hl = threadIdx.x & 63;
+        const int leader = __ffsll((long long)hm) - 1;
+        const uint32_t region = (blockIdx.x * kWaves + (threadIdx.x >> 6)) % pn::kShards;
+        unsigned long long first = 0;
+        if (hl == leader)
+            first = atomicAdd(out.hsh.counts + region, (unsigned long long)__popcll(hm));
+        first = __shfl(first, leader);
+        if (heavy) {
+            const unsigned long long at = first + __popcll(hm & ((1ull << hl) - 1ull));
+            if (at < out.hsh.region_cap) {
+                // position (33 bits), strand, letters and which list: 2 uint4
+                const uint32_t fl = (has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
+                                    (avail << 4) | (N << 8) | (s << 16) |
+                                    ((gu64 *)side == rg.src ? 1u << 17 : 0u) |
+                                    ((uint32_t)((uint64_t)p >> 32) << 18);
+                uint4 *h = out.heavy + 2 * ((uint64_t)region * out.hsh.region_cap + at);
+                h[0] = make_uint4((uint32_t)p, fl, rg.a0, rg.a1);
+                h[1] = make_uint4(rg.b0, rg.b1, 0u, 0u);
+            }
+        }
+    }
+
+    if (valid && len <= kBigSlice) {
         // the next entry is loaded while this one is checked
         if (rg.a0 < rg.a1) {
             unsigned long long v = rg.src[rg.a0];
@@ -288,9 +354,8 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t shard = blockIdx.x % pn::kShards;
-    Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave],
-             out.cands + (uint64_t)shard * out.sh.region_cap,
-             out.sh.counts + shard, out.sh.region_cap, 0ull, 0u};
+    Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
+             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u};
     const int q = ix.q;
     const uint32_t gmask = (1u << (2 * q)) - 1u;
     unsigned long long seeds = 0, visited = 0;
@@ -317,7 +382,9 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
             r.src = (gu64 *)ix.O;
             r.a0 = r.a1 = r.b0 = r.b1 = 0;
         }
-        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg);
+        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg, side, out);
+        // the wave is converged here: empty the stage before it can overflow
+        if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
     }
     for (int o = 32; o > 0; o >>= 1) {
         seeds += __shfl_xor(seeds, o);
@@ -325,19 +392,49 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     }
     if (lane == 0 && seeds) atomicAdd(&out.stats[2 * shard], seeds);
     if (lane == 0 && visited) atomicAdd(&out.stats[2 * shard + 1], visited);
-    // pad the unused part of this lane's reserved slots
-    for (uint32_t i = 0; i < sg.lane_left; i++) {
-        const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;
-        if (at < sg.region_cap) sg.region[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
-    }
+    pad_lane(sg);
+    flush(sg, lane);
+}
+
+// The ranges set aside by k_filter, one per block at a time: block b takes
+// items of heavy region b % kShards; every lane visits a share of the
+// item's entries (the same rules, the same staging).
+__global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
+                                                     const unsigned long long *__restrict__ side,
+                                                     pn::FilterOut out) {
+    __shared__ uint2 wbuf[kWaves][kWBuf];
+    __shared__ uint32_t wcnt[kWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
-    // flush this wave's staged candidates with one atomic add
-    const uint32_t n = min(wcnt[wave], (uint32_t)kWBuf);
-    unsigned long long base = 0;
-    if (lane == 0 && n) base = atomicAdd(sg.count, (unsigned long long)n);
-    base = __shfl(base, 0);
-    for (uint32_t i = lane; i < n; i += 64)
-        if (base + i < sg.region_cap) sg.region[base + i] = wbuf[wave][i];
+    Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
+             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u};
+    const uint32_t region = blockIdx.x % pn::kShards;
+    const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
+    const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
+    for (uint64_t it = blockIdx.x / pn::kShards; it < n; it += gridDim.x / pn::kShards) {
+        const uint4 h0 = items[2 * it], h1 = items[2 * it + 1];
+        const uint32_t fl = h0.y;
+        const int64_t p = (int64_t)(((uint64_t)(fl >> 18) << 32) | h0.x);
+        gu64 *src = (fl >> 17) & 1u ? (gu64 *)side : (gu64 *)ix.O;
+        const bool has = fl & 1u, lh = (fl >> 1) & 1u;
+        const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
+        const uint32_t s = (fl >> 16) & 1u;
+        // steps of kT entries with a wave-uniform bound: a step adds at most 64
+        // candidates per wave, so flushing at half full keeps the stage from
+        // overflowing
+        const uint32_t la = h0.w - h0.z, total = la + (h1.y - h1.x);
+        for (uint32_t base = 0; base < total; base += kT) {
+            const uint32_t k = base + threadIdx.x;
+            if (k < total) {
+                const uint32_t t = k < la ? h0.z + k : h1.x + (k - la);
+                visit(src[t], p, s, has, prev, lh, N, avail, sg);
+            }
+            if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
+        }
+    }
+    pad_lane(sg);
+    flush(sg, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,6 +610,7 @@ void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
     else
         hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, P, ix,
                            side, side_cls, out);
+    hipLaunchKernelGGL(k_filter_heavy, dim3(64 * pn::kShards), dim3(kT), 0, st, ix, side, out);
 }
 
 }  // namespace pn

@@ -187,6 +187,10 @@ constexpr int kLcPatterns = 16;  // period <= 2 q-grams: first two letters
 struct FilterOut {
     uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS), kShards regions
     Shards sh;                    // per-region append counters
+    // entries whose occurrence ranges are too long for one wave, set aside
+    // for a block each: 2 uint4 per item, kShards regions
+    uint4 *heavy;
+    Shards hsh;
     // per region g: stats[2g] = occurrence pairs seen (sum of k_end - k_start),
     // stats[2g+1] = index entries read
     unsigned long long *stats;

@@ -175,10 +175,9 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
     push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
 }
 
-// Slices longer than this are walked by the whole wave together; longer
-// than kHeavy they are set aside for a block of their own.
-constexpr uint32_t kBigSlice = 64;
-constexpr uint32_t kHeavy = 1024;
+// Occurrence ranges longer than this are set aside for a block of their own
+// (k_filter_heavy); shorter ones are walked by their lane.
+constexpr uint32_t kHeavy = 64;
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
@@ -219,8 +218,8 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
     return ke - ks;
 }
 
-// visit one (position, strand): short ranges by this lane, long ones by
-// the whole wave (every lane of the wave must call this together)
+// visit one (position, strand): short ranges by this lane, long ones set
+// aside for k_filter_heavy (every lane of the wave calls this together)
 __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint32_t s,
                                               bool has_prev, uint32_t prev, bool lh, uint32_t N,
                                               uint32_t avail, bool valid, Stage &sg,
@@ -229,7 +228,6 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     // the longest ranges wait for k_filter_heavy (a block each)
     const bool heavy = valid && len > kHeavy;
-    const bool big = valid && len > kBigSlice && !heavy;
     const unsigned long long hm = __ballot(heavy);
     if (hm) {
         const int hl = threadIdx.x & 63;
@@ -254,7 +252,7 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
         }
     }
 
-    if (valid && len <= kBigSlice) {
+    if (valid && !heavy) {
         // the next entry is loaded while this one is checked
         if (rg.a0 < rg.a1) {
             unsigned long long v = rg.src[rg.a0];
@@ -266,26 +264,6 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
             visit(v, p, s, has_prev, prev, lh, N, avail, sg);
         }
         for (uint32_t t = rg.b0; t < rg.b1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
-    }
-    unsigned long long mask = __ballot(big);
-    const int lane = threadIdx.x & 63;
-    while (mask) {
-        const int leader = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        gu64 *src = (gu64 *)__shfl((long long)rg.src, leader);
-        const uint32_t a0 = __shfl(rg.a0, leader), a1 = __shfl(rg.a1, leader);
-        const uint32_t b0 = __shfl(rg.b0, leader), b1 = __shfl(rg.b1, leader);
-        const int64_t lp = __shfl((long long)p, leader);
-        // everything about the leader's (position, strand), its strand included:
-        // neighbouring lanes need not be on the same strand
-        const uint32_t flags = __shfl((has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
-                                          (avail << 4) | (N << 8) | (s << 16),
-                                      leader);
-        const bool lhp = flags & 1u, llh = (flags >> 1) & 1u;
-        const uint32_t lprev = (flags >> 2) & 3u, lavail = (flags >> 4) & 7u, lN = (flags >> 8) & 0xffu;
-        const uint32_t ls = (flags >> 16) & 1u;
-        for (uint32_t t = a0 + lane; t < a1; t += 64) visit(src[t], lp, ls, lhp, lprev, llh, lN, lavail, sg);
-        for (uint32_t t = b0 + lane; t < b1; t += 64) visit(src[t], lp, ls, lhp, lprev, llh, lN, lavail, sg);
     }
     return valid ? len : 0u;  // entries read for this lane's (position, strand)
 }

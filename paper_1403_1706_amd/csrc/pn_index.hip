@@ -19,30 +19,6 @@
 
 namespace {
 
-constexpr int kChunk = 32;  // q-gram starts per thread
-
-struct QgramIter {
-    uint32_t r;
-    uint64_t off;
-    uint32_t n;       // read length
-    uint32_t o0, o1;  // q-gram starts [o0, o1)
-};
-
-__device__ __forceinline__ bool qgram_iter(const PnIndexDev &ix, uint32_t nch, QgramIter &it) {
-    uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    it.r = (uint32_t)(gid / nch);
-    uint32_t c = (uint32_t)(gid % nch);
-    if (it.r >= ix.n_reads) return false;
-    it.off = ix.offsets[it.r];
-    uint64_t n = ix.offsets[it.r + 1] - it.off;
-    it.n = (uint32_t)n;
-    if (n < (uint64_t)ix.q) return false;
-    uint32_t nq = (uint32_t)(n - ix.q + 1);
-    it.o0 = c * kChunk;
-    it.o1 = min(it.o0 + kChunk, nq);
-    return it.o0 < it.o1;
-}
-
 // q-gram code at read offset o (first base most significant) and the class
 // of the letter before it (its code, or PN_CLS_NONE at o == 0)
 __device__ __forceinline__ uint32_t qgram_at(const PnIndexDev &ix, uint64_t off, uint32_t o,
@@ -64,53 +40,88 @@ __global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
     nq[r] = n >= (uint64_t)ix.q ? (uint32_t)(n - ix.q + 1) : 0u;
 }
 
-// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class
-__global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix, uint32_t nch,
+// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class.
+// One wave per read: lane l takes offsets l, l + 64, ..., so a wave reads
+// one stretch of the packed reads and writes one stretch of keys.
+__global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                                                     const uint32_t *__restrict__ qoff,
                                                     unsigned long long *__restrict__ keys) {
-    QgramIter it;
-    if (!qgram_iter(ix, nch, it)) return;
+    const uint32_t r = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (r >= ix.n_reads) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t off = ix.offsets[r];
+    const uint64_t n = ix.offsets[r + 1] - off;
+    if (n < (uint64_t)ix.q) return;
+    const uint32_t nq = (uint32_t)(n - ix.q + 1);
     const int sh = 2 * ix.q + 3;
-    const uint64_t base = qoff[it.r];
-    for (uint32_t o = it.o0; o < it.o1; o++) {
+    const uint64_t base = qoff[r];
+    for (uint32_t o = lane; o < nq; o += 64) {
         uint32_t cls;
-        const uint32_t g = qgram_at(ix, it.off, o, cls);
-        keys[base + o] = ((unsigned long long)((it.r << 8) | o) << sh) |
+        const uint32_t g = qgram_at(ix, off, o, cls);
+        keys[base + o] = ((unsigned long long)((r << 8) | o) << sh) |
                          ((unsigned long long)g << 3) | cls;
     }
 }
 
-// O entries from the sorted keys, group starts, and the presence bitmap I
+// O entries from the sorted keys, group starts, and the presence bitmap I.
+// Each thread takes kPer entries, 256 apart, and issues the gathers of all
+// of them (read bounds, then the letters after each q-gram) before using
+// any, so that their latencies overlap.
+constexpr int kPer = 4;
+
 template <typename TW>
 __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            const unsigned long long *__restrict__ keys,
                                                            uint64_t T, unsigned long long *O,
                                                            uint32_t *flags, TW *I) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= T) return;
     const int sh = 2 * ix.q + 3;
     const unsigned long long lowm = (1ull << sh) - 1ull;
-    const unsigned long long k = keys[i];
-    const uint32_t g = (uint32_t)((k & lowm) >> 3);
-    const uint32_t cls = (uint32_t)(k & 7ull);
-    const uint32_t ro = (uint32_t)(k >> sh);
-    const uint32_t r = ro >> 8, o = ro & 0xffu;
-    const bool start = i == 0 || (uint32_t)((keys[i - 1] & lowm) >> 3) != g;
-    flags[i] = start;
-    if (start) {
-        const uint32_t wmask = (1u << ix.log2w) - 1;
-        atomicOr(&I[g >> ix.log2w], (TW)1 << (g & wmask));
+    const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
+    unsigned long long k[kPer];
+    uint64_t off[kPer], end[kPer];
+    uint32_t w[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint64_t i = i0 + (uint64_t)j * 256;
+        k[j] = i < T ? keys[i] : 0ull;
     }
-    // the letters after the q-gram inside the read (at most four)
-    const uint64_t off = ix.offsets[r];
-    const uint32_t n = (uint32_t)(ix.offsets[r + 1] - off);
-    const uint32_t after = n - o - (uint32_t)ix.q;
-    const uint32_t nav = after < 4u ? after : 4u;
-    uint32_t next4 = pn_window16(ix.packed, off + o + ix.q) >> 24;
-    next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
-    const uint32_t hi = (cls << 29) | (r << 8) | o;
-    const uint32_t lo = (next4 << 24) | (nav << 21);
-    O[i] = ((unsigned long long)hi << 32) | lo;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint32_t r = (uint32_t)(k[j] >> sh) >> 8;
+        const bool ok = i0 + (uint64_t)j * 256 < T;
+        off[j] = ok ? ix.offsets[r] : 0;
+        end[j] = ok ? ix.offsets[r + 1] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint32_t o = (uint32_t)(k[j] >> sh) & 0xffu;
+        const bool ok = i0 + (uint64_t)j * 256 < T;
+        w[j] = ok ? pn_window16(ix.packed, off[j] + o + ix.q) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint64_t i = i0 + (uint64_t)j * 256;
+        if (i >= T) break;
+        const uint32_t g = (uint32_t)((k[j] & lowm) >> 3);
+        const uint32_t cls = (uint32_t)(k[j] & 7ull);
+        const uint32_t ro = (uint32_t)(k[j] >> sh);
+        const uint32_t r = ro >> 8, o = ro & 0xffu;
+        const bool start = i == 0 || (uint32_t)((keys[i - 1] & lowm) >> 3) != g;
+        flags[i] = start;
+        if (start) {
+            const uint32_t wmask = (1u << ix.log2w) - 1;
+            atomicOr(&I[g >> ix.log2w], (TW)1 << (g & wmask));
+        }
+        // the letters after the q-gram inside the read (at most four)
+        const uint32_t n = (uint32_t)(end[j] - off[j]);
+        const uint32_t after = n - o - (uint32_t)ix.q;
+        const uint32_t nav = after < 4u ? after : 4u;
+        uint32_t next4 = w[j] >> 24;
+        next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
+        const uint32_t hi = (cls << 29) | (r << 8) | o;
+        const uint32_t lo = (next4 << 24) | (nav << 21);
+        O[i] = ((unsigned long long)hi << 32) | lo;
+    }
 }
 
 // S'[x] = position of the x-th group start; S'[D] = T
@@ -144,12 +155,6 @@ inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
-// chunks of kChunk q-gram starts per read, from the longest read
-uint32_t nch_for(const PnIndexDev &ix) {
-    uint32_t nq = ix.max_len >= (uint32_t)ix.q ? ix.max_len - ix.q + 1 : 1;
-    return (nq + kChunk - 1) / kChunk;
-}
-
 }  // namespace
 
 namespace pn {
@@ -161,21 +166,22 @@ void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st) {
 
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
                        hipStream_t st) {
-    const uint32_t nch = nch_for(ix);
-    uint64_t n = (uint64_t)ix.n_reads * nch;
-    if (!n) return;
-    hipLaunchKernelGGL(k_qgram_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, ix, nch, qoff, keys);
+    if (!ix.n_reads) return;
+    const uint64_t threads = (uint64_t)ix.n_reads * 64;  // a wave per read
+    hipLaunchKernelGGL(k_qgram_keys, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix, qoff,
+                       keys);
 }
 
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
                               unsigned long long *O, uint32_t *flags, void *I, hipStream_t st) {
     if (!T) return;
+    const unsigned blocks = grid_for(T, 256 * kPer);
     if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_index_from_sorted<unsigned long long>, dim3(grid_for(T, 256)),
-                           dim3(256), 0, st, ix, keys, T, O, flags, (unsigned long long *)I);
+        hipLaunchKernelGGL(k_index_from_sorted<unsigned long long>, dim3(blocks), dim3(256), 0, st,
+                           ix, keys, T, O, flags, (unsigned long long *)I);
     else
-        hipLaunchKernelGGL(k_index_from_sorted<uint32_t>, dim3(grid_for(T, 256)), dim3(256), 0, st,
-                           ix, keys, T, O, flags, (uint32_t *)I);
+        hipLaunchKernelGGL(k_index_from_sorted<uint32_t>, dim3(blocks), dim3(256), 0, st, ix, keys,
+                           T, O, flags, (uint32_t *)I);
 }
 
 void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,

@@ -545,6 +545,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
     uint32_t *nq = nullptr, *flags = nullptr, *pos = nullptr, *partials = nullptr, *lcs = nullptr;
+    uint16_t *rlen = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;
     s = dalloc_t(c, (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
@@ -555,6 +556,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &x->lcinfo);
     if (!s) s = dalloc_t(c, pn::kLcPatterns, &lcs);
     if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &nq);
+    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &rlen);
     if (!s) s = dalloc_t(c, T + 1, &keys);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
     if (!s) s = dalloc_t(c, T + 1, &flags);
@@ -573,13 +575,13 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         stage_end(c, st, tok, 2);
         tok = stage_begin(c, st, PN_STAGE_INDEX);
         // q-gram occurrences -> keys at their read's offset in O
-        pn::launch_read_nq(ix, nq, st);
+        pn::launch_read_nq(ix, nq, rlen, st);
         pn::launch_scan_u32(nq, nq, n_reads, partials, st);
         pn::launch_qgram_keys(ix, nq, keys, st);
         const unsigned long long *sorted =
             pn::radix_sort_u64_any(keys, tmp, T, 2 * q + 3, sort_temp, st);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
-        pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);  // step 1 and O
+        pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, rlen, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
         pn::launch_scan_u32(flags, pos, T, partials, st);
         pn::launch_sp_fill(flags, pos, T, x->Sp, st);  // steps 4-6
@@ -599,6 +601,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         }
     }
     dfree(c, nq);
+    dfree(c, rlen);
     dfree(c, keys);
     dfree(c, tmp);
     dfree(c, flags);

@@ -32,17 +32,22 @@ __device__ __forceinline__ uint32_t qgram_at(const PnIndexDev &ix, uint64_t off,
     return (w << 2) >> (32 - 2 * ix.q);
 }
 
-// q-gram starts per read (n_r - q + 1, or 0)
-__global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
+// q-gram starts per read (n_r - q + 1, or 0) and read lengths (<= 256)
+__global__ void k_read_nq(PnIndexDev ix, uint32_t *nq, uint16_t *len) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ix.n_reads) return;
     const uint64_t n = ix.offsets[r + 1] - ix.offsets[r];
     nq[r] = n >= (uint64_t)ix.q ? (uint32_t)(n - ix.q + 1) : 0u;
+    len[r] = (uint16_t)n;
 }
 
-// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class.
-// One wave per read: lane l takes offsets l, l + 64, ..., so a wave reads
-// one stretch of the packed reads and writes one stretch of keys.
+// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class;
+// with kCarry (q <= 12, where 8 bits are left) the four letters after the
+// q-gram sit between the two parts: ((r << 8 | o) << (2q + 11)) |
+// (next4 << (2q + 3)) | (g << 3) | class.  Sorting looks at the low 2q + 3
+// bits only.  One wave per read: lane l takes offsets l, l + 64, ..., so a
+// wave reads one stretch of the packed reads and writes one stretch of keys.
+template <bool kCarry>
 __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                                                     const uint32_t *__restrict__ qoff,
                                                     unsigned long long *__restrict__ keys) {
@@ -58,8 +63,15 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
     for (uint32_t o = lane; o < nq; o += 64) {
         uint32_t cls;
         const uint32_t g = qgram_at(ix, off, o, cls);
-        keys[base + o] = ((unsigned long long)((r << 8) | o) << sh) |
-                         ((unsigned long long)g << 3) | cls;
+        unsigned long long key = ((unsigned long long)g << 3) | cls;
+        if (kCarry) {
+            const uint32_t next4 = pn_window16(ix.packed, off + o + ix.q) >> 24;
+            key |= ((unsigned long long)((r << 8) | o) << (sh + 8)) |
+                   ((unsigned long long)next4 << sh);
+        } else {
+            key |= (unsigned long long)((r << 8) | o) << sh;
+        }
+        keys[base + o] = key;
     }
 }
 
@@ -69,12 +81,14 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
 // any, so that their latencies overlap.
 constexpr int kPer = 4;
 
-template <typename TW>
+template <typename TW, bool kCarry>
 __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            const unsigned long long *__restrict__ keys,
                                                            uint64_t T, unsigned long long *O,
-                                                           uint32_t *flags, TW *I) {
+                                                           uint32_t *flags, TW *I,
+                                                           const uint16_t *__restrict__ len) {
     const int sh = 2 * ix.q + 3;
+    const int rsh = kCarry ? sh + 8 : sh;  // where (r << 8 | o) starts
     const unsigned long long lowm = (1ull << sh) - 1ull;
     const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
     unsigned long long k[kPer];
@@ -85,33 +99,62 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         const uint64_t i = i0 + (uint64_t)j * 256;
         k[j] = i < T ? keys[i] : 0ull;
     }
+    if (kCarry) {
+        // the letters are in the key; only the read's length is looked up
 #pragma unroll
-    for (int j = 0; j < kPer; j++) {
-        const uint32_t r = (uint32_t)(k[j] >> sh) >> 8;
-        const bool ok = i0 + (uint64_t)j * 256 < T;
-        off[j] = ok ? ix.offsets[r] : 0;
-        end[j] = ok ? ix.offsets[r + 1] : 0;
-    }
+        for (int j = 0; j < kPer; j++) {
+            const uint32_t r = (uint32_t)(k[j] >> rsh) >> 8;
+            const bool ok = i0 + (uint64_t)j * 256 < T;
+            off[j] = 0;
+            end[j] = ok ? len[r] : 0;
+            w[j] = (uint32_t)((k[j] >> sh) & 0xffu) << 24;
+        }
+    } else {
 #pragma unroll
-    for (int j = 0; j < kPer; j++) {
-        const uint32_t o = (uint32_t)(k[j] >> sh) & 0xffu;
-        const bool ok = i0 + (uint64_t)j * 256 < T;
-        w[j] = ok ? pn_window16(ix.packed, off[j] + o + ix.q) : 0u;
+        for (int j = 0; j < kPer; j++) {
+            const uint32_t r = (uint32_t)(k[j] >> rsh) >> 8;
+            const bool ok = i0 + (uint64_t)j * 256 < T;
+            off[j] = ok ? ix.offsets[r] : 0;
+            end[j] = ok ? ix.offsets[r + 1] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; j++) {
+            const uint32_t o = (uint32_t)(k[j] >> rsh) & 0xffu;
+            const bool ok = i0 + (uint64_t)j * 256 < T;
+            w[j] = ok ? pn_window16(ix.packed, off[j] + o + ix.q) : 0u;
+        }
     }
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
         const uint64_t i = i0 + (uint64_t)j * 256;
-        if (i >= T) break;
+        if (i0 + (uint64_t)j * 256 - (threadIdx.x & 63) >= T) break;  // the whole wave is past T
+        const bool live = i < T;
         const uint32_t g = (uint32_t)((k[j] & lowm) >> 3);
         const uint32_t cls = (uint32_t)(k[j] & 7ull);
-        const uint32_t ro = (uint32_t)(k[j] >> sh);
+        const uint32_t ro = (uint32_t)(k[j] >> rsh);
         const uint32_t r = ro >> 8, o = ro & 0xffu;
-        const bool start = i == 0 || (uint32_t)((keys[i - 1] & lowm) >> 3) != g;
-        flags[i] = start;
-        if (start) {
-            const uint32_t wmask = (1u << ix.log2w) - 1;
-            atomicOr(&I[g >> ix.log2w], (TW)1 << (g & wmask));
+        // the previous entry's key: the lane before, or memory for lane 0
+        unsigned long long kp = __shfl_up(k[j], 1);
+        if ((threadIdx.x & 63) == 0) kp = i ? keys[i - 1] : ~0ull;
+        const bool start = i == 0 || (uint32_t)((kp & lowm) >> 3) != g;
+        if (live) flags[i] = start;
+        // I: lanes holding one word of I are contiguous (keys are sorted);
+        // their bits are ORed across the run and the run's last lane alone
+        // writes them (one atomic per word and wave, not one per q-gram)
+        const uint32_t wmask = (1u << ix.log2w) - 1;
+        const uint32_t word = g >> ix.log2w;
+        TW bits = live && start ? (TW)1 << (g & wmask) : (TW)0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ow = __shfl_up(word, d);
+            const TW ob = (TW)__shfl_up((unsigned long long)bits, d);
+            if ((int)(threadIdx.x & 63) >= d && ow == word) bits |= ob;
         }
+        const uint32_t nw = __shfl_down(word, 1);
+        const bool last = (threadIdx.x & 63) == 63 || nw != word ||
+                          i + 1 >= T;  // lanes past T do not take part
+        if (last && bits) atomicOr(&I[word], bits);
+        if (!live) continue;
         // the letters after the q-gram inside the read (at most four)
         const uint32_t n = (uint32_t)(end[j] - off[j]);
         const uint32_t after = n - o - (uint32_t)ix.q;
@@ -159,29 +202,41 @@ inline unsigned grid_for(uint64_t n, unsigned threads) {
 
 namespace pn {
 
-void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st) {
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream_t st) {
     if (!ix.n_reads) return;
-    hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq);
+    hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq, len);
 }
 
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
                        hipStream_t st) {
     if (!ix.n_reads) return;
     const uint64_t threads = (uint64_t)ix.n_reads * 64;  // a wave per read
-    hipLaunchKernelGGL(k_qgram_keys, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix, qoff,
-                       keys);
+    if (index_key_carries(ix.q))
+        hipLaunchKernelGGL(k_qgram_keys<true>, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix,
+                           qoff, keys);
+    else
+        hipLaunchKernelGGL(k_qgram_keys<false>, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix,
+                           qoff, keys);
 }
 
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint32_t *flags, void *I, hipStream_t st) {
+                              unsigned long long *O, uint32_t *flags, void *I, const uint16_t *len,
+                              hipStream_t st) {
     if (!T) return;
     const unsigned blocks = grid_for(T, 256 * kPer);
-    if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_index_from_sorted<unsigned long long>, dim3(blocks), dim3(256), 0, st,
-                           ix, keys, T, O, flags, (unsigned long long *)I);
+    const bool c = index_key_carries(ix.q);
+    if (ix.log2w == 6 && c)
+        hipLaunchKernelGGL((k_index_from_sorted<unsigned long long, true>), dim3(blocks), dim3(256),
+                           0, st, ix, keys, T, O, flags, (unsigned long long *)I, len);
+    else if (ix.log2w == 6)
+        hipLaunchKernelGGL((k_index_from_sorted<unsigned long long, false>), dim3(blocks),
+                           dim3(256), 0, st, ix, keys, T, O, flags, (unsigned long long *)I, len);
+    else if (c)
+        hipLaunchKernelGGL((k_index_from_sorted<uint32_t, true>), dim3(blocks), dim3(256), 0, st, ix,
+                           keys, T, O, flags, (uint32_t *)I, len);
     else
-        hipLaunchKernelGGL(k_index_from_sorted<uint32_t>, dim3(blocks), dim3(256), 0, st, ix, keys,
-                           T, O, flags, (uint32_t *)I);
+        hipLaunchKernelGGL((k_index_from_sorted<uint32_t, false>), dim3(blocks), dim3(256), 0, st,
+                           ix, keys, T, O, flags, (uint32_t *)I, len);
 }
 
 void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,

@@ -157,13 +157,17 @@ void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint3
 uint64_t scan_partials_size(uint64_t n);
 
 // pn_index.hip (Algorithm 1)
-void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st);
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream_t st);
+// index keys hold the four letters after each q-gram when there is room
+// (2q + 3 sort bits + 8 letter bits + 29 bits of read and offset <= 64)
+inline bool index_key_carries(int q) { return 2 * q + 3 + 8 + 29 <= 64; }
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
                        hipStream_t st);
 // O, group-start flags and I (zeroed by the caller) from keys sorted by
 // their low 2q+3 bits
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint32_t *flags, void *I, hipStream_t st);
+                              unsigned long long *O, uint32_t *flags, void *I, const uint16_t *len,
+                              hipStream_t st);
 // pos = exclusive scan of flags (pos[T] = D)
 void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,
                     hipStream_t st);

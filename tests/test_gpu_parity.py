@@ -70,11 +70,16 @@ def decode_O(O):
 
 
 @pytest.mark.parametrize("wbits", [32, 64])
-@pytest.mark.parametrize("case", ["tiny", "mixed"])
+@pytest.mark.parametrize("case", ["tiny", "mixed", "tiny-q13"])
 def test_index_arrays_match_definition(pn, sess, wbits, case):
+    # q <= 12 keeps the letters after each q-gram in the sort key; q = 13
+    # builds the same entries by looking them up in the packed reads
     if case == "tiny":
         w = synth.make("tiny", n_reads=3000)
         q = 10
+    elif case == "tiny-q13":
+        w = synth.make("tiny", n_reads=3000)
+        q = 13
     else:
         w = synth.make("mixed", scale=0.001)
         q = 12
@@ -218,7 +223,7 @@ def test_map_tiny_full(pn, sess):
 def test_map_tiny_w32_and_q_invariance(pn, sess):
     w = synth.make("tiny", scale=0.2)
     base = map_both(pn, sess, w, k=5, q=10, modes=(0,), wbits=32)
-    for q in (8, 9, 11):
+    for q in (8, 9, 11, 13, 15):
         idx = sess.index(w.reads, w.offsets, q)
         ref = sess.ref(w.ref)
         assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, 5, 0), base)

@@ -196,9 +196,8 @@ int pn_index_get_info(const pn_index *idx, pn_index_info *out);
  * letter before the q-gram in its read (4 when o == 0); the low 32 bits are
  * (next4 << 24) | (nav << 21): the nav = min(4, n_r - o - q) letters after
  * the q-gram, first letter in the top bits (unused letters 0).  Inside each
- * q-gram's slice of O, entries are ordered by value when the slice has at
- * most 32 entries and grouped by cls otherwise.  Any pointer may be NULL to
- * skip that array. */
+ * q-gram's slice of O, entries are in the order (r, o).  Any pointer may be
+ * NULL to skip that array. */
 int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint64_t *O);
 
 /* ---- mapping ----------------------------------------------------------- */

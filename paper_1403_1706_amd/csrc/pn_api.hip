@@ -579,13 +579,13 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         pn::launch_scan_u32(nq, nq, n_reads, partials, st);
         pn::launch_qgram_keys(ix, nq, keys, st);
         const unsigned long long *sorted =
-            pn::radix_sort_u64_any(keys, tmp, T, 2 * q + 3, sort_temp, st);
+            pn::radix_sort_u64_any(keys, tmp, T, 2 * q, sort_temp, st);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
         pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, rlen, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
         pn::launch_scan_u32(flags, pos, T, partials, st);
         pn::launch_sp_fill(flags, pos, T, x->Sp, st);  // steps 4-6
-        stage_end(c, st, tok, 5 + 3 * ((2 * q + 3 + 7) / 8) + 3 + 3 + 1);
+        stage_end(c, st, tok, 5 + 3 * ((2 * q + 7) / 8) + 3 + 3 + 1);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
         e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);

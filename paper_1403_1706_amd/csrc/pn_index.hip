@@ -3,10 +3,10 @@
 // counters and "next free entry" cursors; here the same arrays come from
 // one sort, which needs no atomic per occurrence and leaves every slice of
 // O ordered:
-//   a. one 64-bit key per q-gram occurrence (read r, offset o):
-//      (r, o) above (q-gram g, class of the letter before it)   (k_qgram_keys)
-//   b. stable LSD radix sort on the low 2q+3 bits: occurrences grouped by
-//      g, inside a group by (class, r, o)                         (pn_canon.hip)
+//   a. one 64-bit key per q-gram occurrence (read r, offset o): (r, o),
+//      the class of the letter before the q-gram and the q-gram g (k_qgram_keys)
+//   b. stable LSD radix sort on the 2q bits of g: occurrences grouped by g,
+//      inside a group in the order (r, o)                          (pn_canon.hip)
 //   c. O[i] from the i-th key; the first key of each g sets bit g of I
 //      (Algorithm 1 step 1) and marks a group start               (k_index_from_sorted)
 //   d. S = exclusive scan of popcount(I[i]) (steps 2-3); the rank of each
@@ -41,11 +41,11 @@ __global__ void k_read_nq(PnIndexDev ix, uint32_t *nq, uint16_t *len) {
     len[r] = (uint16_t)n;
 }
 
-// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (g << 3) | class;
+// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (class << 2q) | g;
 // with kCarry (q <= 12, where 8 bits are left) the four letters after the
-// q-gram sit between the two parts: ((r << 8 | o) << (2q + 11)) |
-// (next4 << (2q + 3)) | (g << 3) | class.  Sorting looks at the low 2q + 3
-// bits only.  One wave per read: lane l takes offsets l, l + 64, ..., so a
+// q-gram sit between (r, o) and the class: ((r << 8 | o) << (2q + 11)) |
+// (next4 << (2q + 3)) | (class << 2q) | g.  Sorting looks at the low 2q
+// bits (the q-gram) only, so each slice keeps the order (read, offset).  One wave per read: lane l takes offsets l, l + 64, ..., so a
 // wave reads one stretch of the packed reads and writes one stretch of keys.
 template <bool kCarry>
 __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
     for (uint32_t o = lane; o < nq; o += 64) {
         uint32_t cls;
         const uint32_t g = qgram_at(ix, off, o, cls);
-        unsigned long long key = ((unsigned long long)g << 3) | cls;
+        unsigned long long key = ((unsigned long long)cls << (2 * ix.q)) | g;
         if (kCarry) {
             const uint32_t next4 = pn_window16(ix.packed, off + o + ix.q) >> 24;
             key |= ((unsigned long long)((r << 8) | o) << (sh + 8)) |
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            const uint16_t *__restrict__ len) {
     const int sh = 2 * ix.q + 3;
     const int rsh = kCarry ? sh + 8 : sh;  // where (r << 8 | o) starts
-    const unsigned long long lowm = (1ull << sh) - 1ull;
+    const unsigned long long gmask = (1ull << (2 * ix.q)) - 1ull;
     const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
     unsigned long long k[kPer];
     uint64_t off[kPer], end[kPer];
@@ -129,14 +129,14 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         const uint64_t i = i0 + (uint64_t)j * 256;
         if (i0 + (uint64_t)j * 256 - (threadIdx.x & 63) >= T) break;  // the whole wave is past T
         const bool live = i < T;
-        const uint32_t g = (uint32_t)((k[j] & lowm) >> 3);
-        const uint32_t cls = (uint32_t)(k[j] & 7ull);
+        const uint32_t g = (uint32_t)(k[j] & gmask);
+        const uint32_t cls = (uint32_t)(k[j] >> (2 * ix.q)) & 7u;
         const uint32_t ro = (uint32_t)(k[j] >> rsh);
         const uint32_t r = ro >> 8, o = ro & 0xffu;
         // the previous entry's key: the lane before, or memory for lane 0
         unsigned long long kp = __shfl_up(k[j], 1);
         if ((threadIdx.x & 63) == 0) kp = i ? keys[i - 1] : ~0ull;
-        const bool start = i == 0 || (uint32_t)((kp & lowm) >> 3) != g;
+        const bool start = i == 0 || (uint32_t)(kp & gmask) != g;
         if (live) flags[i] = start;
         // I: lanes holding one word of I are contiguous (keys are sorted);
         // their bits are ORed across the run and the run's last lane alone

@@ -119,12 +119,10 @@ def test_index_arrays_match_definition(pn, sess, wbits, case):
         next4 |= letter.astype(np.int64) << (6 - 2 * t)
     assert np.array_equal((lo >> 24) & 0xff, next4)
     assert np.all((lo & ((1 << 21) - 1)) == 0)
-    # inside a slice entries are grouped by class; short slices fully ascending
+    # inside a slice entries are in the order (read, offset)
     same = bucket[1:] == bucket[:-1]
-    assert np.all(cls[1:][same] >= cls[:-1][same])
-    sizes = np.diff(Sp.astype(np.int64))
-    short = same & (sizes[bucket[1:]] <= 32)
-    assert np.all(O[1:][short] > O[:-1][short])
+    ro = r * 256 + o
+    assert np.all(ro[1:][same] > ro[:-1][same])
 
 
 def test_index_w32_equals_w64(pn, sess):

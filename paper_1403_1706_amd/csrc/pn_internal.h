@@ -237,7 +237,7 @@ struct VerifyOut {
     unsigned long long *rows;     // band rows computed (work counter)
     int ebits;                    // bits for end positions in a key
 };
-// Two passes: every candidate for at most 32 rows, then the candidates still
+// Two passes: every candidate for at most 16 rows, then the candidates still
 // alive from row 0 to the end.  `longc` (in.regions regions of
 // in.region_cap entries) and its counters `n_long` (in.regions words, zeroed
 // by the caller) hold the second pass's candidates.

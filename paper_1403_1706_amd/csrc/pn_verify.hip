@@ -27,7 +27,7 @@
 // Lanes of a wave run in lockstep, so a wave costs as many rows as its
 // longest candidate.  Most candidates end within a few rows while true hits
 // run the full read, so verification takes two passes: every candidate for
-// at most 32 rows, then only the survivors, packed densely, to the end.
+// at most 16 rows, then only the survivors, packed densely, to the end.
 // Records and survivors are staged per wave in LDS and appended with one
 // atomic per flush to one of kShards output regions.
 #include <algorithm>
@@ -39,7 +39,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kStage = 512;  // staged entries per wave
-constexpr int kShortRows = 32;    // row cap of the first pass
+constexpr int kShortRows = 16;    // row cap of the first pass
 
 // Entries (8 bytes) staged per wave in LDS and appended to one output region
 // with one global atomic per flush.  A lane that finds the stage full takes

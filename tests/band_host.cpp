@@ -24,7 +24,7 @@ extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, i
         rp[o / 32].x |= (uint32_t)(read[o] >> 1) << (o % 32);
         rp[o / 32].y |= (uint32_t)(read[o] & 1) << (o % 32);
     }
-    // the kernel's two passes: at most 32 rows first, then (if the candidate
+    // the kernel's two passes: at most 16 rows first, then (if the candidate
     // is still alive there) from row 0 without a cap
     int m = 0;
     auto emit = [&](uint32_t e, int v) {
@@ -32,7 +32,7 @@ extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, i
         out_v[m] = v;
         m++;
     };
-    if (pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, 32, emit) < 0) {
+    if (pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, 16, emit) < 0) {
         if (m != 0) return -2;  // a capped run must not have emitted
         pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, PN_MAX_READ_LEN, emit);
     }

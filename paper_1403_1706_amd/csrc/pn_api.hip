@@ -693,7 +693,7 @@ int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, hipStream_t st) {
     PN_CHECK(ensure(c, c->rinfo, (uint64_t)x->n_reads + 1));
     PN_CHECK(ensure(c, c->side, std::max<uint64_t>(x->lc_total, 1) * 8));
-    PN_CHECK(ensure(c, c->side_meta, 7 * pn::kLcPatterns * 4));
+    PN_CHECK(ensure(c, c->side_meta, 17 * pn::kLcPatterns * 4));
     uint32_t starts[pn::kLcPatterns];
     uint64_t at = 0;
     for (int i = 0; i < pn::kLcPatterns; i++) {
@@ -706,11 +706,12 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->rinfo.p, (uint32_t *)&c->misc[kStatus],
                           st);
     pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->rinfo.p, st);
-    uint32_t *meta = (uint32_t *)c->side_meta.p;  // 16 region starts, then 16 x 6 class bounds
+    // 16 region starts, 16 x 6 class bounds, then scratch for the side lists
+    uint32_t *meta = (uint32_t *)c->side_meta.p;
     pn::launch_fill_u32(meta + pn::kLcPatterns, 6 * pn::kLcPatterns, 0u, st);
     if (x->n_reads)
         pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
-                           meta + pn::kLcPatterns, st);
+                           meta + pn::kLcPatterns, meta + 7 * pn::kLcPatterns, st);
     PN_CHECK(read_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];
     if (status & 2u) return PN_EINVAL;

@@ -175,9 +175,10 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
     push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
 }
 
-// Occurrence ranges longer than this are set aside for a block of their own
-// (k_filter_heavy); shorter ones are walked by their lane.
+// Occurrence ranges longer than this are set aside for k_filter_heavy, in
+// items of at most kItem occurrences; shorter ones are walked by their lane.
 constexpr uint32_t kHeavy = 64;
+constexpr uint32_t kItem = 1024;
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
@@ -228,26 +229,40 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     // the longest ranges wait for k_filter_heavy (a block each)
     const bool heavy = valid && len > kHeavy;
-    const unsigned long long hm = __ballot(heavy);
-    if (hm) {
-        const int hl = threadIdx.x & 63;
-        const int leader = __ffsll((long long)hm) - 1;
+    // a set-aside entry becomes one item per kItem occurrences (a wave walks
+    // an item), so that no single item is long
+    const uint32_t nitems = heavy ? (len + kItem - 1) / kItem : 0u;
+    uint32_t incl = nitems;  // inclusive prefix over the wave
+    const int hl = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d);
+        if (hl >= d) incl += y;
+    }
+    const uint32_t wtotal = __shfl(incl, 63);
+    if (wtotal) {
         const uint32_t region = (blockIdx.x * kWaves + (threadIdx.x >> 6)) % pn::kShards;
         unsigned long long first = 0;
-        if (hl == leader)
-            first = atomicAdd(out.hsh.counts + region, (unsigned long long)__popcll(hm));
-        first = __shfl(first, leader);
+        if (hl == 0) first = atomicAdd(out.hsh.counts + region, (unsigned long long)wtotal);
+        first = __shfl(first, 0);
         if (heavy) {
-            const unsigned long long at = first + __popcll(hm & ((1ull << hl) - 1ull));
-            if (at < out.hsh.region_cap) {
-                // position (33 bits), strand, letters and which list: 2 uint4
-                const uint32_t fl = (has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
-                                    (avail << 4) | (N << 8) | (s << 16) |
-                                    ((gu64 *)side == rg.src ? 1u << 17 : 0u) |
-                                    ((uint32_t)((uint64_t)p >> 32) << 18);
+            // position (33 bits), strand, letters and which list
+            const uint32_t fl = (has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
+                                (avail << 4) | (N << 8) | (s << 16) |
+                                ((gu64 *)side == rg.src ? 1u << 17 : 0u) |
+                                ((uint32_t)((uint64_t)p >> 32) << 18);
+            const uint32_t la = rg.a1 - rg.a0;
+            unsigned long long at = first + (incl - nitems);
+            for (uint32_t c = 0; c < nitems; c++, at++) {
+                if (at >= out.hsh.region_cap) break;
+                // the part [c * kItem, (c + 1) * kItem) of the two ranges laid end to end
+                const uint32_t k0 = c * kItem, k1 = min(len, k0 + kItem);
+                const uint32_t a0 = rg.a0 + min(k0, la), a1 = rg.a0 + min(k1, la);
+                const uint32_t b0 = rg.b0 + (k0 > la ? k0 - la : 0u);
+                const uint32_t b1 = rg.b0 + (k1 > la ? k1 - la : 0u);
                 uint4 *h = out.heavy + 2 * ((uint64_t)region * out.hsh.region_cap + at);
-                h[0] = make_uint4((uint32_t)p, fl, rg.a0, rg.a1);
-                h[1] = make_uint4(rg.b0, rg.b1, 0u, 0u);
+                h[0] = make_uint4((uint32_t)p, fl, a0, a1);
+                h[1] = make_uint4(b0, b1, 0u, 0u);
             }
         }
     }
@@ -374,9 +389,11 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     flush(sg, lane);
 }
 
-// The ranges set aside by k_filter, one per block at a time: block b takes
-// items of heavy region b % kShards; every lane visits a share of the
-// item's entries (the same rules, the same staging).
+// The ranges set aside by k_filter, a wave per item: wave v of the grid
+// takes items v, v + (waves per region), ... of heavy region v % kShards and
+// walks each in wave-uniform steps of 64 occurrences (the same rules, the
+// same staging; a step adds at most 64 candidates, so flushing at half full
+// keeps the stage from overflowing).
 __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
                                                      const unsigned long long *__restrict__ side,
                                                      pn::FilterOut out) {
@@ -385,12 +402,14 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
+    const uint32_t gw = blockIdx.x * kWaves + wave;  // this wave in the grid
+    const uint32_t nw = gridDim.x * kWaves;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u};
-    const uint32_t region = blockIdx.x % pn::kShards;
+             gw % pn::kShards, nullptr, 0ull, 0u};
+    const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
-    for (uint64_t it = blockIdx.x / pn::kShards; it < n; it += gridDim.x / pn::kShards) {
+    for (uint64_t it = gw / pn::kShards; it < n; it += nw / pn::kShards) {
         const uint4 h0 = items[2 * it], h1 = items[2 * it + 1];
         const uint32_t fl = h0.y;
         const int64_t p = (int64_t)(((uint64_t)(fl >> 18) << 32) | h0.x);
@@ -398,12 +417,9 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
         const bool has = fl & 1u, lh = (fl >> 1) & 1u;
         const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
         const uint32_t s = (fl >> 16) & 1u;
-        // steps of kT entries with a wave-uniform bound: a step adds at most 64
-        // candidates per wave, so flushing at half full keeps the stage from
-        // overflowing
         const uint32_t la = h0.w - h0.z, total = la + (h1.y - h1.x);
-        for (uint32_t base = 0; base < total; base += kT) {
-            const uint32_t k = base + threadIdx.x;
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t k = base + (uint32_t)lane;
             if (k < total) {
                 const uint32_t t = k < la ? h0.z + k : h1.x + (k - la);
                 visit(src[t], p, s, has, prev, lh, N, avail, sg);
@@ -453,46 +469,128 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
 
 // side lists: for each of the 16 low-complexity q-grams (first two letters
 // x, y; then x y x y ...), the occurrences from reads that keep them, grouped
-// by the letter before the q-gram (class 0..4).  One block per q-gram;
-// `region` holds the host-computed list starts; side_cls[id*6 + c] receives
-// the start of class c and side_cls[id*6 + 5] the end.
+// by the letter before the q-gram (class 0..4).  Three kernels over all 16
+// slices of O laid end to end: counts per (q-gram, class), the class bounds
+// (side_cls[id*6 + c] = start of class c, side_cls[id*6 + 5] = end, inside
+// the host-computed region of q-gram id), then the entries, each block
+// reserving its slots once per (q-gram, class).  Order inside a class group
+// is free.
+
+// the 16 slices [ks, ks + len) and their prefix, in LDS
 template <typename TW>
-__global__ __launch_bounds__(256) void k_lc_side(PnIndexDev ix, const uint8_t *__restrict__ rinfo,
-                                                 unsigned long long *side, const uint32_t *region,
-                                                 uint32_t *side_cls) {
-    const uint32_t id = blockIdx.x;
-    const uint32_t x = id >> 2, y = id & 3u;
-    uint32_t g = 0;
-    for (int t = 0; t < ix.q; t++) g = (g << 2) | ((t & 1) ? y : x);
-    const TW *I = (const TW *)ix.I;
-    const uint32_t wmask = (1u << ix.log2w) - 1;
-    const uint32_t gi = g >> ix.log2w, gj = g & wmask;
-    const TW word = I[gi];
-    uint32_t ks = 0, ke = 0;
-    if ((word >> gj) & 1) {
-        const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
-        ks = ix.Sp[slot];
-        ke = ix.Sp[slot + 1];
+__device__ __forceinline__ void lc_slices(const PnIndexDev &ix, uint32_t *s_ks, uint32_t *s_pre) {
+    __shared__ uint32_t s_len[pn::kLcPatterns];
+    if (threadIdx.x < pn::kLcPatterns) {
+        const uint32_t id = threadIdx.x;
+        const uint32_t x = id >> 2, y = id & 3u;
+        uint32_t g = 0;
+        for (int t = 0; t < ix.q; t++) g = (g << 2) | ((t & 1) ? y : x);
+        const TW *I = (const TW *)ix.I;
+        const uint32_t wmask = (1u << ix.log2w) - 1;
+        const uint32_t gi = g >> ix.log2w, gj = g & wmask;
+        const TW word = I[gi];
+        uint32_t ks = 0, ke = 0;
+        if ((word >> gj) & 1) {
+            const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
+            ks = ix.Sp[slot];
+            ke = ix.Sp[slot + 1];
+        }
+        s_ks[id] = ks;
+        s_len[id] = ke - ks;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0;
+        for (int id = 0; id < pn::kLcPatterns; id++) {
+            s_pre[id] = a;
+            a += s_len[id];
+        }
+        s_pre[pn::kLcPatterns] = a;
+    }
+    __syncthreads();
+}
+
+// item t of the slices laid end to end: (q-gram id, O entry); cls = 8 when
+// the entry's read does not keep its low-complexity seeds
+__device__ __forceinline__ uint32_t lc_item(const PnIndexDev &ix, const uint8_t *rinfo,
+                                            const uint32_t *s_ks, const uint32_t *s_pre,
+                                            uint32_t t, unsigned long long &v, uint32_t &cls) {
+    uint32_t id = 0;
+    while (id + 1 < pn::kLcPatterns && s_pre[id + 1] <= t) id++;
+    v = ix.O[s_ks[id] + (t - s_pre[id])];
+    const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
+    cls = ((rinfo[r] >> 7) & 1u) ? (uint32_t)(v >> 61) : 8u;
+    return id;
+}
+
+template <typename TW>
+__global__ __launch_bounds__(256) void k_lc_count(PnIndexDev ix, const uint8_t *__restrict__ rinfo,
+                                                  uint32_t *counts) {
+    __shared__ uint32_t s_ks[pn::kLcPatterns], s_pre[pn::kLcPatterns + 1];
+    __shared__ uint32_t h[5 * pn::kLcPatterns];
+    lc_slices<TW>(ix, s_ks, s_pre);
+    if (threadIdx.x < 5 * pn::kLcPatterns) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t total = s_pre[pn::kLcPatterns];
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        unsigned long long v;
+        uint32_t cls;
+        const uint32_t id = lc_item(ix, rinfo, s_ks, s_pre, t, v, cls);
+        if (cls <= PN_CLS_NONE) atomicAdd(&h[id * 5 + cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 5 * pn::kLcPatterns && h[threadIdx.x])
+        atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_lc_bounds(const uint32_t *region, const uint32_t *counts, uint32_t *side_cls,
+                            uint32_t *cursors) {
+    const uint32_t id = threadIdx.x;
+    if (id >= pn::kLcPatterns) return;
     uint32_t at = region[id];
-    for (uint32_t cls = 0; cls <= PN_CLS_NONE; cls++) {
-        if (threadIdx.x == 0) side_cls[id * 6 + cls] = at;
-        for (uint32_t base = ks; base < ke; base += 256) {
-            const uint32_t i = base + threadIdx.x;
-            unsigned long long v = 0;
-            uint32_t f = 0;
-            if (i < ke) {
-                v = ix.O[i];
-                const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
-                f = ((rinfo[r] >> 7) & 1u) && (uint32_t)(v >> 61) == cls;
-            }
-            uint32_t tot;
-            const uint32_t ex = pn_block_excl_scan(f, &tot);
-            if (f) side[at + ex] = v;
-            at += tot;
+    for (uint32_t c = 0; c <= PN_CLS_NONE; c++) {
+        side_cls[id * 6 + c] = at;
+        cursors[id * 5 + c] = at;
+        at += counts[id * 5 + c];
+    }
+    side_cls[id * 6 + 5] = at;
+}
+
+// each block takes one contiguous chunk of items: counts them, reserves
+// its slots once per (q-gram, class), then places them
+template <typename TW>
+__global__ __launch_bounds__(256) void k_lc_scatter(PnIndexDev ix, const uint8_t *__restrict__ rinfo,
+                                                    unsigned long long *side, uint32_t *cursors) {
+    __shared__ uint32_t s_ks[pn::kLcPatterns], s_pre[pn::kLcPatterns + 1];
+    __shared__ uint32_t h[5 * pn::kLcPatterns], base[5 * pn::kLcPatterns];
+    lc_slices<TW>(ix, s_ks, s_pre);
+    if (threadIdx.x < 5 * pn::kLcPatterns) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t total = s_pre[pn::kLcPatterns];
+    const uint32_t chunk = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = min(total, blockIdx.x * chunk), t1 = min(total, t0 + chunk);
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        unsigned long long v;
+        uint32_t cls;
+        const uint32_t id = lc_item(ix, rinfo, s_ks, s_pre, t, v, cls);
+        if (cls <= PN_CLS_NONE) atomicAdd(&h[id * 5 + cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 5 * pn::kLcPatterns) {
+        const uint32_t n = h[threadIdx.x];
+        base[threadIdx.x] = n ? atomicAdd(&cursors[threadIdx.x], n) : 0u;
+        h[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        unsigned long long v;
+        uint32_t cls;
+        const uint32_t id = lc_item(ix, rinfo, s_ks, s_pre, t, v, cls);
+        if (cls <= PN_CLS_NONE) {
+            const uint32_t k = id * 5 + cls;
+            side[base[k] + atomicAdd(&h[k], 1u)] = v;
         }
     }
-    if (threadIdx.x == 0) side_cls[id * 6 + 5] = at;
 }
 
 // copy each read's rule bits (keep flag << 7 | required extra run) into the
@@ -546,13 +644,22 @@ void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint
 }
 
 void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
-                    const uint32_t *region, uint32_t *side_cls, hipStream_t st) {
+                    const uint32_t *region, uint32_t *side_cls, uint32_t *scratch,
+                    hipStream_t st) {
+    uint32_t *counts = scratch, *cursors = scratch + 5 * kLcPatterns;
+    launch_fill_u32(counts, 5 * kLcPatterns, 0u, st);
+    const dim3 grid(1024), block(256);
     if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_lc_side<unsigned long long>, dim3(kLcPatterns), dim3(256), 0, st, ix,
-                           rinfo, side, region, side_cls);
+        hipLaunchKernelGGL(k_lc_count<unsigned long long>, grid, block, 0, st, ix, rinfo, counts);
     else
-        hipLaunchKernelGGL(k_lc_side<uint32_t>, dim3(kLcPatterns), dim3(256), 0, st, ix, rinfo,
-                           side, region, side_cls);
+        hipLaunchKernelGGL(k_lc_count<uint32_t>, grid, block, 0, st, ix, rinfo, counts);
+    hipLaunchKernelGGL(k_lc_bounds, dim3(1), dim3(64), 0, st, region, (const uint32_t *)counts,
+                       side_cls, cursors);
+    if (ix.log2w == 6)
+        hipLaunchKernelGGL(k_lc_scatter<unsigned long long>, grid, block, 0, st, ix, rinfo, side,
+                           cursors);
+    else
+        hipLaunchKernelGGL(k_lc_scatter<uint32_t>, grid, block, 0, st, ix, rinfo, side, cursors);
 }
 
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st) {
@@ -588,7 +695,7 @@ void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
     else
         hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, P, ix,
                            side, side_cls, out);
-    hipLaunchKernelGGL(k_filter_heavy, dim3(64 * pn::kShards), dim3(kT), 0, st, ix, side, out);
+    hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), 0, st, ix, side, out);
 }
 
 }  // namespace pn

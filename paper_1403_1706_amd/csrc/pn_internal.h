@@ -207,8 +207,10 @@ void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint
 void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st);
 // low-complexity occurrence lists restricted to reads that keep them
 // (grouped by preceding letter; side_cls: 6 bounds per q-gram)
+// (scratch: 10 x kLcPatterns words)
 void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,
-                    const uint32_t *region, uint32_t *side_cls, hipStream_t st);
+                    const uint32_t *region, uint32_t *side_cls, uint32_t *scratch,
+                    hipStream_t st);
 // write each read's rule byte into the low byte of its O entries
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st);
 // the position set P of a reference for one q, sorted by q-gram

@@ -121,17 +121,22 @@ int pn_ctx_stream(pn_ctx *ctx, void **stream);
  * Counters accumulate always: occurrence pairs seen by filtration (n_seeds),
  * candidates verified, band rows computed by verification, records emitted,
  * hits reported, and index entries filtration actually read (n_visited:
- * the seed rules skip the rest).  pn_ctx_get_stats copies them out and optionally
+ * the seed rules skip the rest); verify_rows_long is the second pass's share
+ * of verify_rows.  pn_ctx_get_stats copies them out and optionally
  * resets them. */
 enum {
     PN_STAGE_INGEST = 0,       /* ASCII -> 2-bit codes, read metadata, read planes */
     PN_STAGE_INDEX = 1,        /* Algorithm 1 */
-    PN_STAGE_FILTER_COUNT = 2, /* reserved (filtration is one pass: FILTER_EMIT) */
-    PN_STAGE_FILTER_EMIT = 3,  /* Algorithm 2 */
-    PN_STAGE_VERIFY = 4,       /* banded bit-parallel validation */
+    PN_STAGE_FILTER_HEAVY = 2, /* Algorithm 2: occurrence lists set aside as too long
+                                  for one lane, a wave per slice of them */
+    PN_STAGE_FILTER_EMIT = 3,  /* Algorithm 2: the scan of the reference (one kernel) */
+    PN_STAGE_VERIFY = 4,       /* banded bit-parallel validation, first pass (one kernel) */
     PN_STAGE_SORT = 5,         /* radix sort of hit records */
     PN_STAGE_FINISH = 6,       /* duplicate removal, strata, output */
-    PN_N_STAGES = 8
+    PN_STAGE_RULES = 7,        /* per-read seed rules, low-complexity side lists */
+    PN_STAGE_VERIFY_LONG = 8,  /* validation, second pass: the candidates still open
+                                  after the first pass's rows (one kernel) */
+    PN_N_STAGES = 10           /* stage 9 is reserved */
 };
 typedef struct {
     double ms[PN_N_STAGES];
@@ -142,6 +147,10 @@ typedef struct {
     uint64_t n_records;
     uint64_t n_hits;
     uint64_t n_visited;
+    uint64_t verify_rows_long;   /* the part of verify_rows computed by the second pass */
+    uint64_t n_visited_heavy;    /* the part of n_visited read by FILTER_HEAVY */
+    uint64_t n_heavy_items;      /* work items (32 bytes each) handed to FILTER_HEAVY */
+    uint64_t n_candidates_heavy; /* the part of n_candidates written by FILTER_HEAVY */
 } pn_stats;
 int pn_ctx_set_timing(pn_ctx *ctx, int enable);
 int pn_ctx_get_stats(pn_ctx *ctx, pn_stats *out, int reset);

@@ -30,11 +30,12 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kStatBad = 3,
     kOutCount = 6,
     kVerifyRows = 8,
+    kVerifyRowsLong = 9,
     kCandCounts = 16,                        // pn::kShards words each
     kRecCounts = kCandCounts + pn::kShards,
     kLongCounts = kRecCounts + pn::kShards,
-    kFilterStats = kLongCounts + pn::kShards,  // 2 x pn::kShards words
-    kHeavyCounts = kFilterStats + 2 * pn::kShards,
+    kFilterStats = kLongCounts + pn::kShards,  // 4 x pn::kShards words
+    kHeavyCounts = kFilterStats + 4 * pn::kShards,
     kMiscWords = kHeavyCounts + pn::kShards
 };
 
@@ -703,6 +704,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     zero_misc(c, st);
     PN_TRY(hipMemcpyAsync(c->side_meta.p, starts, sizeof(starts), hipMemcpyHostToDevice, st));
     PnIndexDev ix = index_desc(x);
+    const int tok = stage_begin(c, st, PN_STAGE_RULES);
     pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->rinfo.p, (uint32_t *)&c->misc[kStatus],
                           st);
     pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->rinfo.p, st);
@@ -712,6 +714,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     if (x->n_reads)
         pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
                            meta + pn::kLcPatterns, meta + 7 * pn::kLcPatterns, st);
+    stage_end(c, st, tok, x->n_reads ? 7 : 3);
     PN_CHECK(read_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];
     if (status & 2u) return PN_EINVAL;
@@ -733,6 +736,9 @@ int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStrea
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
     pn::launch_filter(ref_desc(ref), P, index_desc(x), (const unsigned long long *)c->side.p,
                       meta + pn::kLcPatterns, fo, st);
+    stage_end(c, st, tok, 1);
+    tok = stage_begin(c, st, PN_STAGE_FILTER_HEAVY);
+    pn::launch_filter_heavy(index_desc(x), (const unsigned long long *)c->side.p, fo, st);
     stage_end(c, st, tok, 1);
     return PN_OK;
 }
@@ -757,12 +763,20 @@ bool heavy_overflow(pn_ctx *c) {
 }
 
 // occurrence pairs seen and index entries read by the last filtration
-void filter_stats(const pn_ctx *c, uint64_t *seeds, uint64_t *visited) {
-    *seeds = *visited = 0;
+struct FilterWork {
+    uint64_t seeds = 0, visited = 0, set_aside = 0, written = 0, items = 0;
+};
+
+FilterWork filter_stats(const pn_ctx *c) {
+    FilterWork f;
     for (uint32_t g = 0; g < pn::kShards; g++) {
-        *seeds += c->hmisc[kFilterStats + 2 * g];
-        *visited += c->hmisc[kFilterStats + 2 * g + 1];
+        f.seeds += c->hmisc[kFilterStats + 4 * g];
+        f.visited += c->hmisc[kFilterStats + 4 * g + 1];
+        f.set_aside += c->hmisc[kFilterStats + 4 * g + 2];
+        f.written += c->hmisc[kFilterStats + 4 * g + 3];
+        f.items += c->hmisc[kHeavyCounts + g];
     }
+    return f;
 }
 
 void zero_counts(pn_ctx *c, int slot, hipStream_t st) {
@@ -784,8 +798,8 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         PN_CHECK(ensure(c, c->cands, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->longc, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
-        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 4 * pn::kShards, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 2, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
         zero_counts(c, kRecCounts, st);
         zero_counts(c, kLongCounts, st);
         if (filter) {
@@ -802,30 +816,42 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
                          (unsigned long long *)&c->misc[kVerifyRows], ebits};
         int tok = stage_begin(c, st, PN_STAGE_VERIFY);
         pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, (uint2 *)c->longc.p,
-                          (unsigned long long *)&c->misc[kLongCounts], st);
-        stage_end(c, st, tok, 2);
+                          (unsigned long long *)&c->misc[kLongCounts], true, st);
+        stage_end(c, st, tok, 1);
+        vo.rows = (unsigned long long *)&c->misc[kVerifyRowsLong];
+        tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
+        pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, (uint2 *)c->longc.p,
+                          (unsigned long long *)&c->misc[kLongCounts], false, st);
+        stage_end(c, st, tok, 1);
         PN_CHECK(read_misc(c, st));
         uint64_t cand_max, cand_total, rec_max, got;
         region_counts(c, kCandCounts, regions, &cand_max, &cand_total);
         region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
-        if (filter && cand_max > c->cand_rcap) {  // candidates overflowed: grow, run again
+        // an output that overflowed is grown (every one at once) and the
+        // attempt runs again
+        bool again = false;
+        if (filter && cand_max > c->cand_rcap) {
             c->cand_rcap = cand_max + cand_max / 4;
-            continue;
+            again = true;
         }
-        if (filter && heavy_overflow(c)) continue;
+        if (filter && heavy_overflow(c)) again = true;
         if (rec_max > c->rec_rcap) {
             c->rec_rcap = rec_max + rec_max / 4;
-            continue;
+            again = true;
         }
+        if (again) continue;
         *n_rec = got;
         if (filter) {
-            uint64_t seeds, visited;
-            filter_stats(c, &seeds, &visited);
-            c->stats.n_seeds += seeds;
-            c->stats.n_visited += visited;
+            const FilterWork f = filter_stats(c);
+            c->stats.n_seeds += f.seeds;
+            c->stats.n_visited += f.visited;
             c->stats.n_candidates += cand_total;
+            c->stats.n_visited_heavy += f.set_aside;
+            c->stats.n_heavy_items += f.items;
+            c->stats.n_candidates_heavy += cand_total - std::min(cand_total, f.written);
         }
-        c->stats.verify_rows += c->hmisc[kVerifyRows];
+        c->stats.verify_rows += c->hmisc[kVerifyRows] + c->hmisc[kVerifyRowsLong];
+        c->stats.verify_rows_long += c->hmisc[kVerifyRowsLong];
         c->stats.n_records += got;
         const int bits = 6 + ebits + key_rbits(x->n_reads);
         PN_CHECK(ensure(c, c->keys, std::max<uint64_t>(got, 1) * 8));
@@ -993,7 +1019,7 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
     for (int attempt = 0; !s && attempt < 8; attempt++) {
         s = ensure(c, c->cands, pn::kShards * c->cand_rcap * sizeof(uint2));
         if (s) break;
-        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 4 * pn::kShards, 0u, st);
+        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
         zero_counts(c, kCandCounts, st);
         s = launch_filter_into(c, ref, x, st);
         if (!s) s = read_misc(c, st);
@@ -1005,8 +1031,8 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         if (mx > c->cand_rcap) c->cand_rcap = mx + mx / 4;
         n = 0;
     }
-    uint64_t seeds = 0, visited = 0;
-    if (!s) filter_stats(c, &seeds, &visited);
+    uint64_t seeds = 0;
+    if (!s) seeds = filter_stats(c).seeds;
     if (!s) s = ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8);
     if (!s) s = ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8);
     if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(n));

@@ -93,6 +93,7 @@ struct Stage {
     uint2 *lane_region;            // region of this lane's reserved slots
     unsigned long long lane_base;  // this lane's reserved slots
     uint32_t lane_left;
+    uint32_t written;  // output slots this lane accounts for (work counter)
 };
 
 // The lanes that reach this together append one candidate each: one of
@@ -114,6 +115,7 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
         sg.lane_region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
         sg.lane_base = atomicAdd(sg.counts + sg.shard, (unsigned long long)kLaneChunk);
         sg.lane_left = kLaneChunk;
+        sg.written += kLaneChunk;
     }
     const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left);
     sg.lane_left--;
@@ -130,7 +132,10 @@ __device__ __forceinline__ void flush(Stage &sg, int lane) {
     if (n) {
         uint2 *region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(sg.counts + sg.shard, (unsigned long long)n);
+        if (lane == 0) {
+            base = atomicAdd(sg.counts + sg.shard, (unsigned long long)n);
+            sg.written += n;
+        }
         base = __shfl(base, 0);
         for (uint32_t i = lane; i < n; i += 64) {
             const unsigned long long v = sg.buf[i];
@@ -225,7 +230,8 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
                                               bool has_prev, uint32_t prev, bool lh, uint32_t N,
                                               uint32_t avail, bool valid, Stage &sg,
                                               const unsigned long long *side,
-                                              const pn::FilterOut &out) {
+                                              const pn::FilterOut &out,
+                                              unsigned long long &set_aside) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     // the longest ranges wait for k_filter_heavy (a block each)
     const bool heavy = valid && len > kHeavy;
@@ -246,6 +252,7 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
         if (hl == 0) first = atomicAdd(out.hsh.counts + region, (unsigned long long)wtotal);
         first = __shfl(first, 0);
         if (heavy) {
+            set_aside += len;
             // position (33 bits), strand, letters and which list
             const uint32_t fl = (has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
                                 (avail << 4) | (N << 8) | (s << 16) |
@@ -348,10 +355,10 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     __syncthreads();
     const uint32_t shard = blockIdx.x % pn::kShards;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u};
+             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u, 0u};
     const int q = ix.q;
     const uint32_t gmask = (1u << (2 * q)) - 1u;
-    unsigned long long seeds = 0, visited = 0;
+    unsigned long long seeds = 0, visited = 0, set_aside = 0;
     // the block takes kT * kPPT consecutive entries of P, a wave 64
     // consecutive ones per round; every lane runs the same rounds so that
     // long slices can be shared by the wave
@@ -375,18 +382,24 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
             r.src = (gu64 *)ix.O;
             r.a0 = r.a1 = r.b0 = r.b1 = 0;
         }
-        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg, side, out);
+        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg, side, out, set_aside);
         // the wave is converged here: empty the stage before it can overflow
         if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
     }
+    pad_lane(sg);
+    flush(sg, lane);
+    unsigned long long written = sg.written;
     for (int o = 32; o > 0; o >>= 1) {
         seeds += __shfl_xor(seeds, o);
         visited += __shfl_xor(visited, o);
+        set_aside += __shfl_xor(set_aside, o);
+        written += __shfl_xor(written, o);
     }
-    if (lane == 0 && seeds) atomicAdd(&out.stats[2 * shard], seeds);
-    if (lane == 0 && visited) atomicAdd(&out.stats[2 * shard + 1], visited);
-    pad_lane(sg);
-    flush(sg, lane);
+    unsigned long long *stats = out.stats + 4 * shard;
+    if (lane == 0 && seeds) atomicAdd(stats, seeds);
+    if (lane == 0 && visited) atomicAdd(stats + 1, visited);
+    if (lane == 0 && set_aside) atomicAdd(stats + 2, set_aside);
+    if (lane == 0 && written) atomicAdd(stats + 3, written);
 }
 
 // The ranges set aside by k_filter, a wave per item: wave v of the grid
@@ -405,7 +418,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
     const uint32_t gw = blockIdx.x * kWaves + wave;  // this wave in the grid
     const uint32_t nw = gridDim.x * kWaves;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             gw % pn::kShards, nullptr, 0ull, 0u};
+             gw % pn::kShards, nullptr, 0ull, 0u, 0u};
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
@@ -695,6 +708,11 @@ void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
     else
         hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, P, ix,
                            side, side_cls, out);
+}
+
+void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,
+                         hipStream_t st) {
+    if (!ix.n_reads) return;
     hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), 0, st, ix, side, out);
 }
 

@@ -195,8 +195,10 @@ struct FilterOut {
     // for a block each: 2 uint4 per item, kShards regions
     uint4 *heavy;
     Shards hsh;
-    // per region g: stats[2g] = occurrence pairs seen (sum of k_end - k_start),
-    // stats[2g+1] = index entries read
+    // per region g (work counters of k_filter): stats[4g] = occurrence pairs
+    // seen (sum of k_end - k_start), stats[4g+1] = index entries read (by
+    // either kernel), stats[4g+2] = the part of those set aside for
+    // k_filter_heavy, stats[4g+3] = candidate slots k_filter wrote
     unsigned long long *stats;
 };
 // per read: bit 7 = keeps its low-complexity seeds, bits 0-2 = extra letters
@@ -222,6 +224,9 @@ struct RefQDev {
 void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipStream_t st);
 void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st);
+// the occurrence lists k_filter set aside (FilterOut::heavy)
+void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,
+                         hipStream_t st);
 void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
                    const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
                    hipStream_t st);
@@ -242,10 +247,11 @@ struct VerifyOut {
 // Two passes: every candidate for at most 16 rows, then the candidates still
 // alive from row 0 to the end.  `longc` (in.regions regions of
 // in.region_cap entries) and its counters `n_long` (in.regions words, zeroed
-// by the caller) hold the second pass's candidates.
+// by the caller) hold the second pass's candidates.  `first` picks the pass;
+// the second pass reads `longc` and ignores in.cands.
 void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
                    const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
-                   hipStream_t st);
+                   bool first, hipStream_t st);
 
 // pn_scan.hip: concatenate the regions of a sharded list (8-byte entries)
 // into dst; counts past region_cap are clipped

@@ -178,18 +178,21 @@ namespace pn {
 
 void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
                    const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
-                   hipStream_t st) {
+                   bool first, hipStream_t st) {
     if (!in.region_cap || !in.regions) return;
     // blocks: a multiple of the input regions, enough to fill the chip
     uint64_t per = (in.region_cap + kThreads - 1) / kThreads;
     const uint64_t max_per = std::max<uint64_t>(8192 / in.regions, 1);
     if (per > max_per) per = max_per;
     const dim3 grid((unsigned)(per * in.regions));
-    hipLaunchKernelGGL(k_verify<true>, grid, dim3(kThreads), 0, st, ref, ix, in, kglob, kpr, out,
-                       longc, n_long);
-    VerifyIn in2{longc, n_long, in.regions, in.region_cap};
-    hipLaunchKernelGGL(k_verify<false>, grid, dim3(kThreads), 0, st, ref, ix, in2, kglob, kpr, out,
-                       longc, n_long);
+    if (first) {
+        hipLaunchKernelGGL(k_verify<true>, grid, dim3(kThreads), 0, st, ref, ix, in, kglob, kpr,
+                           out, longc, n_long);
+    } else {
+        VerifyIn in2{longc, n_long, in.regions, in.region_cap};
+        hipLaunchKernelGGL(k_verify<false>, grid, dim3(kThreads), 0, st, ref, ix, in2, kglob, kpr,
+                           out, longc, n_long);
+    }
 }
 
 }  // namespace pn

@@ -47,14 +47,17 @@ class _IndexInfo(ctypes.Structure):
                 ("max_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-STAGES = ["ingest", "index", "filter_count", "filter_emit", "verify", "sort", "finish"]
+STAGES = ["ingest", "index", "filter_heavy", "filter_emit", "verify", "sort", "finish", "rules",
+          "verify_long"]
 
 
 class _Stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8),
+    _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_uint64 * 10),
                 ("n_seeds", ctypes.c_uint64), ("n_candidates", ctypes.c_uint64),
                 ("verify_rows", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
-                ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64)]
+                ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64),
+                ("verify_rows_long", ctypes.c_uint64), ("n_visited_heavy", ctypes.c_uint64),
+                ("n_heavy_items", ctypes.c_uint64), ("n_candidates_heavy", ctypes.c_uint64)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -193,7 +196,8 @@ def pn_ctx_get_stats(ctx, reset: bool = False) -> dict:
     _check(_lib.pn_ctx_get_stats(ctx, ctypes.byref(st), int(bool(reset))), "pn_ctx_get_stats")
     out = {"ms": {n: st.ms[i] for i, n in enumerate(STAGES)},
            "launches": {n: int(st.launches[i]) for i, n in enumerate(STAGES)}}
-    for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits", "n_visited"):
+    for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits", "n_visited",
+              "verify_rows_long", "n_visited_heavy", "n_heavy_items", "n_candidates_heavy"):
         out[f] = int(getattr(st, f))
     return out
 

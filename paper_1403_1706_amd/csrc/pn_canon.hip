@@ -33,41 +33,48 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long lon
     hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile: the tile's keys are first put in digit order
-// in LDS (rank among equal digits from ballots, wave by wave), then written
-// out so that consecutive threads write consecutive addresses of one
-// digit's run.
+// Stable scatter of one tile.  Wave w owns the tile's keys
+// [w * kTile/4, (w + 1) * kTile/4), all loaded up front; each key's rank
+// among the equal digits before it in its wave comes from ballots and a
+// per-wave digit counter in LDS (no block barrier per step).  One prefix
+// over the waves then places every key in digit order in LDS, and the tile
+// is written out so that consecutive threads write consecutive addresses of
+// one digit's run.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
                                                             unsigned long long *out, uint64_t n,
                                                             int shift, uint32_t dmask,
                                                             const uint32_t *offs,
                                                             const uint32_t *hist,
                                                             uint64_t n_tiles) {
+    constexpr int kWaves = kThreads / 64;
+    constexpr int kPerWave = kTile / kWaves;
     __shared__ unsigned long long tile[kTile];
-    __shared__ uint32_t local[256];  // start of each digit inside the tile
-    __shared__ uint32_t run[256];    // next free slot of each digit inside the tile
-    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t local[256];        // start of each digit inside the tile
+    __shared__ uint32_t wcnt[kWaves][256];  // per wave: keys of each digit (then: before it)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
     const uint32_t tile_n = (uint32_t)min((uint64_t)kTile, n - base);
-    // exclusive scan of this tile's digit counts
+    const uint32_t w0 = (uint32_t)wave * kPerWave;
+    unsigned long long key[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const uint32_t li = w0 + (uint32_t)j * 64 + lane;
+        key[j] = li < tile_n ? keys[base + li] : 0ull;
+    }
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) wcnt[w][threadIdx.x] = 0;
     {
         const uint32_t c = hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
         uint32_t tot;
-        const uint32_t ex = pn_block_excl_scan(c, &tot);
-        local[threadIdx.x] = ex;
-        run[threadIdx.x] = ex;
+        local[threadIdx.x] = pn_block_excl_scan(c, &tot);  // (synchronises the block)
     }
-    __syncthreads();
-    for (int j = 0; j < kItems; j++) {
+    uint32_t slot[kItems];  // digit | rank inside the wave's run of that digit << 8
 #pragma unroll
-        for (int w = 0; w < 4; w++) wcnt[w][threadIdx.x] = 0;
-        __syncthreads();
-        const uint32_t li = (uint32_t)j * kThreads + threadIdx.x;
+    for (int j = 0; j < kItems; j++) {
+        const uint32_t li = w0 + (uint32_t)j * 64 + lane;
         const bool valid = li < tile_n;
-        const unsigned long long key = valid ? keys[base + li] : 0ull;
-        const uint32_t dg = (uint32_t)(key >> shift) & dmask;
+        const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -76,24 +83,36 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
             peers &= bit ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[dg] + rank;
-            for (int w = 0; w < wave; w++) pos += wcnt[w][dg];
-            tile[pos] = key;
-        }
-        __syncthreads();
-        run[threadIdx.x] += wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] + wcnt[2][threadIdx.x] +
-                            wcnt[3][threadIdx.x];
-        __syncthreads();
+        const uint32_t before = wcnt[wave][dg];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wcnt[wave][dg] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        slot[j] = dg | ((before + rank) << 8);
     }
+    __syncthreads();
+    // per digit: the keys of the waves before each wave
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) {
+            const uint32_t c = wcnt[w][threadIdx.x];
+            wcnt[w][threadIdx.x] = acc + local[threadIdx.x];
+            acc += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const uint32_t li = w0 + (uint32_t)j * 64 + lane;
+        if (li < tile_n) tile[wcnt[wave][slot[j] & 255u] + (slot[j] >> 8)] = key[j];
+    }
+    __syncthreads();
     // the tile in digit order: slot i belongs to digit d with local[d] <= i,
     // and goes to offs[d] + (i - local[d])
     for (uint32_t i = threadIdx.x; i < tile_n; i += kThreads) {
-        const unsigned long long key = tile[i];
-        const uint32_t dg = (uint32_t)(key >> shift) & dmask;
-        out[offs[(uint64_t)dg * n_tiles + blockIdx.x] + (i - local[dg])] = key;
+        const unsigned long long k = tile[i];
+        const uint32_t dg = (uint32_t)(k >> shift) & dmask;
+        out[offs[(uint64_t)dg * n_tiles + blockIdx.x] + (i - local[dg])] = k;
     }
 }
 

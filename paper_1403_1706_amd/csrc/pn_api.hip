@@ -318,6 +318,7 @@ PnIndexDev index_desc(const pn_index *x) {
     d.packed = x->packed;
     d.offsets = x->offsets;
     d.rplanes = x->rplanes;
+    d.rplanes_rc = x->rplanes + (uint64_t)x->n_reads * PN_READ_WORDS;
     d.I = x->I;
     d.S = x->S;
     d.Sp = x->Sp;
@@ -549,7 +550,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     uint16_t *rlen = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;
-    s = dalloc_t(c, (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
+    s = dalloc_t(c, 2 * (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
     if (!s) s = dalloc(c, x->n_groups * (w / 8), &x->I);
     if (!s) s = dalloc_t(c, x->n_groups + 1, &x->S);
     if (!s) s = dalloc_t(c, U + 1, &x->Sp);

@@ -178,8 +178,8 @@ __global__ void k_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint2 v = c[i];
-    keys[i] = ((unsigned long long)(v.x & 0x7fffffffu) << 33) |
-              ((unsigned long long)(v.x >> 31) << 32) | v.y;
+    const uint32_t r = v.x == PN_CAND_NONE ? 0x7fffffffu : v.x & PN_CAND_READ;
+    keys[i] = ((unsigned long long)r << 33) | ((unsigned long long)(v.x >> 31) << 32) | v.y;
 }
 
 // sorted candidate key -> pn_candidate {u32 read, u8 strand, pad[3], i64 diag}

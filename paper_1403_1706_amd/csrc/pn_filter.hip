@@ -177,13 +177,16 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
         const uint32_t next4 = (uint32_t)(v >> 24) & 0xffu;
         if (nav < need || avail < need || ((next4 ^ N) >> (8 - 2 * need)) != 0u) return;
     }
-    push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+    const uint32_t tail = (info >> 6) & 1u;  // the read's first rows are mostly a repeat run
+    push(sg, make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
+                        (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
 }
 
 // Occurrence ranges longer than this are set aside for k_filter_heavy, in
 // items of at most kItem occurrences; shorter ones are walked by their lane.
 constexpr uint32_t kHeavy = 64;
 constexpr uint32_t kItem = 1024;
+constexpr uint32_t kWalk = 8;  // entries a lane loads at a time
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
@@ -275,15 +278,15 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     }
 
     if (valid && !heavy) {
-        // the next entry is loaded while this one is checked
-        if (rg.a0 < rg.a1) {
-            unsigned long long v = rg.src[rg.a0];
-            for (uint32_t t = rg.a0 + 1; t < rg.a1; t++) {
-                const unsigned long long nv = rg.src[t];
-                visit(v, p, s, has_prev, prev, lh, N, avail, sg);
-                v = nv;
-            }
-            visit(v, p, s, has_prev, prev, lh, N, avail, sg);
+        // eight entries loaded at a time: the walk waits on memory once per
+        // eight entries, not once per entry
+        for (uint32_t t = rg.a0; t < rg.a1; t += kWalk) {
+            unsigned long long w[kWalk];
+#pragma unroll
+            for (uint32_t u = 0; u < kWalk; u++) w[u] = t + u < rg.a1 ? rg.src[t + u] : 0ull;
+#pragma unroll
+            for (uint32_t u = 0; u < kWalk; u++)
+                if (t + u < rg.a1) visit(w[u], p, s, has_prev, prev, lh, N, avail, sg);
         }
         for (uint32_t t = rg.b0; t < rg.b1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
     }
@@ -422,8 +425,19 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
-    for (uint64_t it = gw / pn::kShards; it < n; it += nw / pn::kShards) {
-        const uint4 h0 = items[2 * it], h1 = items[2 * it + 1];
+    const uint64_t step = nw / pn::kShards;
+    uint64_t it = gw / pn::kShards;
+    uint4 n0 = make_uint4(0u, 0u, 0u, 0u), n1 = n0;  // the next item, loaded ahead
+    if (it < n) {
+        n0 = items[2 * it];
+        n1 = items[2 * it + 1];
+    }
+    for (; it < n; it += step) {
+        const uint4 h0 = n0, h1 = n1;
+        if (it + step < n) {
+            n0 = items[2 * (it + step)];
+            n1 = items[2 * (it + step) + 1];
+        }
         const uint32_t fl = h0.y;
         const int64_t p = (int64_t)(((uint64_t)(fl >> 18) << 32) | h0.x);
         gu64 *src = (fl >> 17) & 1u ? (gu64 *)side : (gu64 *)ix.O;
@@ -431,13 +445,21 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
         const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
         const uint32_t s = (fl >> 16) & 1u;
         const uint32_t la = h0.w - h0.z, total = la + (h1.y - h1.x);
-        for (uint32_t base = 0; base < total; base += 64) {
-            const uint32_t k = base + (uint32_t)lane;
-            if (k < total) {
+        // four steps of 64 occurrences: every load first, then the visits
+        for (uint32_t base = 0; base < total; base += 256) {
+            unsigned long long v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t k = base + 64 * u + (uint32_t)lane;
                 const uint32_t t = k < la ? h0.z + k : h1.x + (k - la);
-                visit(src[t], p, s, has, prev, lh, N, avail, sg);
+                v[u] = k < total ? src[t] : 0ull;
             }
-            if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (base + 64 * u + (uint32_t)lane < total)
+                    visit(v[u], p, s, has, prev, lh, N, avail, sg);
+                if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
+            }
         }
     }
     pad_lane(sg);
@@ -466,7 +488,8 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
         return;
     }
     const uint32_t nq = n - q + 1;
-    const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = ix.lcinfo[r] >> 16;
+    const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = (ix.lcinfo[r] >> 16) & 0x7fffu;
+    const uint32_t front = ix.lcinfo[r] >> 31;
     const uint32_t Q = nq - lc;  // offsets whose q-gram is not low-complexity
     uint32_t keep, run;
     if (Q >= k * q + 1) {
@@ -477,7 +500,7 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
         run = ceil_div(n - k, k + 1);
     }
     const uint32_t need = run > q ? min(run - q, 4u) : 0u;
-    rinfo[r] = (uint8_t)((keep << 7) | need);
+    rinfo[r] = (uint8_t)((keep << 7) | (front << 6) | need);
 }
 
 // side lists: for each of the 16 low-complexity q-grams (first two letters
@@ -608,13 +631,29 @@ __global__ __launch_bounds__(256) void k_lc_scatter(PnIndexDev ix, const uint8_t
 
 // copy each read's rule bits (keep flag << 7 | required extra run) into the
 // low byte of its O entries, so that the filter reads them with the entry
-__global__ void k_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *__restrict__ rinfo) {
+__device__ __forceinline__ unsigned long long stamp(unsigned long long v,
+                                                    const uint8_t *__restrict__ rinfo) {
+    return (v & ~0xffull) | rinfo[(uint32_t)(v >> 40) & (PN_MAX_READS - 1)];
+}
+
+// four entries per thread and step, in two 16-byte loads and stores (O is
+// 16-byte aligned), so that each thread has four gathers in flight
+__global__ __launch_bounds__(256) void k_stamp_rules(unsigned long long *O, uint64_t n,
+                                                     const uint8_t *__restrict__ rinfo) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const unsigned long long v = O[i];
-        const uint32_t r = (uint32_t)(v >> 40) & (PN_MAX_READS - 1);
-        O[i] = (v & ~0xffull) | rinfo[r];
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    ulonglong2 *O2 = (ulonglong2 *)O;
+    const uint64_t n4 = n / 4;
+    for (uint64_t i = tid; i < n4; i += stride) {
+        ulonglong2 a = O2[2 * i], b = O2[2 * i + 1];
+        a.x = stamp(a.x, rinfo);
+        a.y = stamp(a.y, rinfo);
+        b.x = stamp(b.x, rinfo);
+        b.y = stamp(b.y, rinfo);
+        O2[2 * i] = a;
+        O2[2 * i + 1] = b;
     }
+    if (tid < n - 4 * n4) O[4 * n4 + tid] = stamp(O[4 * n4 + tid], rinfo);
 }
 
 // occurrence counts of the 16 low-complexity q-grams (sizes of their O slices)
@@ -677,8 +716,8 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
 
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st) {
     if (!n) return;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
+    uint64_t blocks = (n / 4 + 255) / 256 + 1;
+    if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_stamp_rules, dim3((unsigned)blocks), dim3(256), 0, st, O, n, rinfo);
 }
 

@@ -176,22 +176,26 @@ __global__ void k_sp_fill(const uint32_t *__restrict__ flags, const uint32_t *__
 }
 
 // per read: number of low-complexity q-gram offsets and of maximal runs of
-// such offsets (both used by the map-time seed rules)
+// such offsets (both used by the map-time seed rules), and whether more of
+// them lie in the first half of the offsets than in the second (bit 31: a
+// hint for the direction of verification's first pass)
 __global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ix.n_reads) return;
     const uint64_t off = ix.offsets[r];
     const uint64_t n = ix.offsets[r + 1] - off;
-    uint32_t cnt = 0, runs = 0;
+    const uint64_t nq = n >= (uint64_t)ix.q ? n - ix.q + 1 : 0;
+    uint32_t cnt = 0, runs = 0, front = 0;
     bool prev_lc = false;
-    for (uint64_t o = 0; o + (uint64_t)ix.q <= n; o++) {
+    for (uint64_t o = 0; o < nq; o++) {
         const uint32_t g = pn_window16(ix.packed, off + o) >> (32 - 2 * ix.q);
         const bool lc = pn_low_complexity(g, ix.q);
         cnt += lc;
+        front += lc && 2 * o < nq;
         runs += lc && !prev_lc;
         prev_lc = lc;
     }
-    lcinfo[r] = cnt | (runs << 16);
+    lcinfo[r] = cnt | (runs << 16) | ((2 * front > cnt ? 1u : 0u) << 31);
 }
 
 inline unsigned grid_for(uint64_t n, unsigned threads) {

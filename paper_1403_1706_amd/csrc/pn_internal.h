@@ -32,6 +32,13 @@
 #define PN_DBIAS 65536u
 #define PN_CLS_NONE 4u
 #define PN_CAND_NONE 0xffffffffu  // padding slot in the candidate array
+// Candidate word x: read id (bits 0-20) | PN_CAND_TAIL | strand << 31.
+// PN_CAND_TAIL asks verification's first pass to check the read's last rows
+// instead of its first ones (set for reads whose low-complexity q-grams lie
+// mostly in their first half, whose first rows would match along a repeat
+// run); either check only drops a candidate without a hit.
+#define PN_CAND_TAIL 0x40000000u
+#define PN_CAND_READ 0x3fffffffu
 
 // ---------------------------------------------------------------------------
 // descriptors passed by value to kernels
@@ -47,6 +54,7 @@ struct PnIndexDev {
     const uint32_t *packed;   // 2-bit concatenated reads
     const uint64_t *offsets;  // n_reads + 1
     const uint2 *rplanes;     // n_reads * PN_READ_WORDS
+    const uint2 *rplanes_rc;  // the same for each read's reverse complement
     const void *I;            // n_groups words of w bits
     const uint32_t *S;        // n_groups + 1
     const uint32_t *Sp;       // n_distinct + 1
@@ -146,7 +154,7 @@ void launch_ref_planes(const uint32_t *packed, uint64_t L, uint4 *planes0, uint4
 void launch_read_meta(const uint64_t *offsets, uint32_t n_reads, int q, uint64_t n_bases,
                       uint64_t *stats, hipStream_t st);
 void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_t n_reads,
-                        uint2 *rplanes, hipStream_t st);
+                        uint2 *rplanes, hipStream_t st);  // rplanes: 2 * n_reads * PN_READ_WORDS (forward, then reverse complements)
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // pn_scan.hip: exclusive prefix sums; out has n + 1 entries (out[n] = total)
@@ -201,8 +209,9 @@ struct FilterOut {
     // k_filter_heavy, stats[4g+3] = candidate slots k_filter wrote
     unsigned long long *stats;
 };
-// per read: bit 7 = keeps its low-complexity seeds, bits 0-2 = extra letters
-// of exact run required beyond q (0..4)
+// per read: bit 7 = keeps its low-complexity seeds, bit 6 = its
+// low-complexity offsets lie mostly in its first half (candidates get
+// PN_CAND_TAIL), bits 0-2 = extra letters of exact run required beyond q (0..4)
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
                        uint32_t *status, hipStream_t st);
 // sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)

@@ -79,48 +79,71 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 // stats[0] = max read length, stats[1] = |T| = sum max(0, n_r - q + 1),
 // stats[2] = number of malformed reads (decreasing offsets, past n_bases,
 // or longer than PN_MAX_READ_LEN)
-__global__ void k_read_meta(const uint64_t *__restrict__ offsets, uint32_t n_reads, int q,
-                            uint64_t n_bases, unsigned long long *stats) {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long len = 0, tq = 0, bad = 0;
-    if (r < n_reads) {
-        uint64_t a = offsets[r], b = offsets[r + 1];
+__global__ __launch_bounds__(256) void k_read_meta(const uint64_t *__restrict__ offsets,
+                                                   uint32_t n_reads, int q, uint64_t n_bases,
+                                                   unsigned long long *stats) {
+    // a grid-stride loop and one atomic per block and figure: the three
+    // figures live at three addresses, whose atomics serialise
+    unsigned long long mx = 0, tq = 0, bad = 0;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < n_reads;
+         r += gridDim.x * blockDim.x) {
+        const uint64_t a = offsets[r], b = offsets[r + 1];
         if (b < a || b > n_bases) {
-            bad = 1;
+            bad++;
         } else {
-            len = b - a;
-            tq = len >= (unsigned long long)q ? len - q + 1 : 0;
-            bad = len > PN_MAX_READ_LEN;
+            const unsigned long long len = b - a;
+            mx = len > mx ? len : mx;
+            tq += len >= (unsigned long long)q ? len - q + 1 : 0;
+            bad += len > PN_MAX_READ_LEN;
         }
     }
-    unsigned long long mx = wave_max_u64(len);
+    mx = wave_max_u64(mx);
     tq = wave_sum_u64(tq);
     bad = wave_sum_u64(bad);
+    __shared__ unsigned long long red[3][4];
+    const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = mx;
+        red[1][wave] = tq;
+        red[2][wave] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) {
+            mx = red[0][w] > mx ? red[0][w] : mx;
+            tq += red[1][w];
+            bad += red[2][w];
+        }
         atomicMax(&stats[0], mx);
         if (tq) atomicAdd(&stats[1], tq);
         if (bad) atomicAdd(&stats[2], bad);
     }
 }
 
+// plane word m of read r and of its reverse complement (letter j of the
+// reverse complement is the complement, code ^ 3, of letter len-1-j)
 __global__ void k_read_planes(const uint32_t *__restrict__ packed,
                               const uint64_t *__restrict__ offsets, uint32_t n_reads,
-                              uint2 *__restrict__ rplanes) {
+                              uint2 *__restrict__ rplanes, uint2 *__restrict__ rplanes_rc) {
     uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t r = (uint32_t)(gid / PN_READ_WORDS);
     uint32_t m = (uint32_t)(gid % PN_READ_WORDS);
     if (r >= n_reads) return;
     uint64_t start = offsets[r];
     uint64_t len = offsets[r + 1] - start;
-    uint32_t h = 0, l = 0;
+    uint32_t h = 0, l = 0, hr = 0, lr = 0;
     for (uint32_t b = 0; b < 32; b++) {
         uint64_t o = 32ull * m + b;
         if (o >= len) break;
-        uint32_t c = pn_base_at(packed, start + o);
+        const uint32_t c = pn_base_at(packed, start + o);
         h |= (c >> 1) << b;
         l |= (c & 1u) << b;
+        const uint32_t cr = pn_base_at(packed, start + len - 1 - o) ^ 3u;
+        hr |= (cr >> 1) << b;
+        lr |= (cr & 1u) << b;
     }
     rplanes[gid] = make_uint2(h, l);
+    rplanes_rc[gid] = make_uint2(hr, lr);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -155,8 +178,10 @@ void launch_ref_planes(const uint32_t *packed, uint64_t L, uint4 *planes0, uint4
 void launch_read_meta(const uint64_t *offsets, uint32_t n_reads, int q, uint64_t n_bases,
                       uint64_t *stats, hipStream_t st) {
     if (!n_reads) return;
-    hipLaunchKernelGGL(k_read_meta, dim3(grid_for(n_reads, 256)), dim3(256), 0, st, offsets,
-                       n_reads, q, n_bases, (unsigned long long *)stats);
+    uint64_t g = grid_for(n_reads, 256 * 8);
+    if (g > 1024) g = 1024;
+    hipLaunchKernelGGL(k_read_meta, dim3((unsigned)g), dim3(256), 0, st, offsets, n_reads, q,
+                       n_bases, (unsigned long long *)stats);
 }
 
 void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_t n_reads,
@@ -164,7 +189,7 @@ void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_
     uint64_t n = (uint64_t)n_reads * PN_READ_WORDS;
     if (!n) return;
     hipLaunchKernelGGL(k_read_planes, dim3(grid_for(n, 256)), dim3(256), 0, st, packed, offsets,
-                       n_reads, rplanes);
+                       n_reads, rplanes, rplanes + n);
 }
 
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {

@@ -81,6 +81,7 @@ struct Stage {
 struct Cand {
     uint2 c;
     bool ok;
+    bool tail;  // first pass: check the read's last rows (reverse complement band)
     int len, k;
     int64_t lo;  // reference position of the band's first diagonal
     const uint4 *pl;
@@ -89,22 +90,34 @@ struct Cand {
     PnBandHead hd;
 };
 
-// issue a candidate's loads (slot value c; padding and bad reads give !ok)
+// issue a candidate's loads (slot value c; padding and bad reads give !ok).
+// With `tail` (first pass, PN_CAND_TAIL) the band is set up for the read's
+// reverse complement against the other strand: read letter i on diagonal
+// d is reverse-complement letter len-1-i on diagonal L-len-d, so the first
+// rows of that band are the last rows of the read's own.
 __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix, int kglob,
                                       const uint8_t *__restrict__ kpr, int ebits, uint2 c,
-                                      Cand &x) {
+                                      bool first, Cand &x) {
     x.c = c;
     x.ok = false;
     if (c.x == PN_CAND_NONE) return;  // padding slot
-    const uint32_t r = c.x & 0x7fffffffu;
+    const uint32_t r = c.x & PN_CAND_READ;
     const uint32_t s = c.x >> 31;
+    x.tail = first && (c.x & PN_CAND_TAIL);
     x.len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
     x.k = kglob >= 0 ? kglob : (int)kpr[r];
     if (x.k > PN_MAX_K || x.len < 1 || x.len > PN_MAX_READ_LEN) return;
     x.ok = true;
-    x.lo = (int64_t)c.y - (int64_t)PN_DBIAS - x.k;
-    x.pl = s ? ref.planes[1] : ref.planes[0];
-    x.rp = ix.rplanes + (uint64_t)r * PN_READ_WORDS;
+    const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
+    if (x.tail) {
+        x.lo = (int64_t)ref.L - x.len - d - x.k;
+        x.pl = s ? ref.planes[0] : ref.planes[1];
+        x.rp = ix.rplanes_rc + (uint64_t)r * PN_READ_WORDS;
+    } else {
+        x.lo = d - x.k;
+        x.pl = s ? ref.planes[1] : ref.planes[0];
+        x.rp = ix.rplanes + (uint64_t)r * PN_READ_WORDS;
+    }
     x.head = (((unsigned long long)r << 1) | s) << ebits;
     pn_band_load(x.pl, x.rp, x.lo, x.hd);
 }
@@ -145,21 +158,26 @@ __global__ __launch_bounds__(kThreads) void k_verify(PnRefDev ref, PnIndexDev ix
     uint2 c_next = base + lane < n ? cands[base + lane] : none;
     uint2 c_after = base + stride + lane < n ? cands[base + stride + lane] : none;
     Cand cur;
-    start(ref, ix, kglob, kpr, out.ebits, c_next, cur);
+    start(ref, ix, kglob, kpr, out.ebits, c_next, kFirst, cur);
     // the loop bound is wave-uniform, so the wave is converged at the flushes
     for (; base < n; base += stride) {
         Cand nxt;
-        start(ref, ix, kglob, kpr, out.ebits, c_after, nxt);
+        start(ref, ix, kglob, kpr, out.ebits, c_after, kFirst, nxt);
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
         if (cur.ok) {
             const unsigned long long head = cur.head;
+            const bool tail = kFirst && cur.tail;
             const int rw = pn_band_run(
                 cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
                 kFirst ? kShortRows : PN_MAX_READ_LEN, [&](uint32_t e, int v) {
-                    rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
+                    if (!tail)
+                        rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
                 });
-            if (kFirst && rw < 0) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
+            // survivors (and tail checks that reached the read's first
+            // letter) run again, forward, from row 0
+            if (kFirst && (rw < 0 || (tail && rw == cur.len)))
+                lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
             rows += (unsigned long long)(rw < 0 ? -rw : rw);
         }
         cur = nxt;

@@ -7,31 +7,63 @@
 
 #include "../paper_1403_1706_amd/csrc/pn_band.h"
 
-extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, int n, int64_t d,
-                         int k, int32_t *out_e, int32_t *out_v) {
-    if (n < 1 || n > PN_MAX_READ_LEN || k < 0 || k > PN_MAX_K) return -1;
+namespace {
+
+// padded bit planes of a text; with rc, of its reverse complement
+std::vector<uint4> text_planes(const uint8_t *text, uint64_t L, bool rc) {
     const uint64_t nb = (L + 31) / 32 + 2 * PN_PAD_BLOCKS + 16;
     std::vector<uint4> pl(nb, make_uint4(0, 0, 0, 0));
     for (uint64_t t = 0; t < L; t++) {
+        const uint32_t c = rc ? 3u - text[L - 1 - t] : text[t];
         uint64_t B = t / 32 + PN_PAD_BLOCKS;
         uint32_t b = (uint32_t)(t % 32);
-        pl[B].x |= (uint32_t)(text[t] >> 1) << b;
-        pl[B].y |= (uint32_t)(text[t] & 1) << b;
+        pl[B].x |= (c >> 1) << b;
+        pl[B].y |= (c & 1u) << b;
         pl[B].z |= 1u << b;
     }
+    return pl;
+}
+
+std::vector<uint2> read_planes(const uint8_t *read, int n, bool rc) {
     std::vector<uint2> rp(PN_READ_WORDS, make_uint2(0, 0));
     for (int o = 0; o < n; o++) {
-        rp[o / 32].x |= (uint32_t)(read[o] >> 1) << (o % 32);
-        rp[o / 32].y |= (uint32_t)(read[o] & 1) << (o % 32);
+        const uint32_t c = rc ? 3u - read[n - 1 - o] : read[o];
+        rp[o / 32].x |= (c >> 1) << (o % 32);
+        rp[o / 32].y |= (c & 1u) << (o % 32);
     }
-    // the kernel's two passes: at most 16 rows first, then (if the candidate
-    // is still alive there) from row 0 without a cap
+    return rp;
+}
+
+}  // namespace
+
+// The kernel's protocol for one candidate: a first pass of at most 16 rows,
+// then (if the candidate is still alive there) from row 0 without a cap.
+// With tail != 0 the first pass is the tail check instead: 16 rows of the
+// read's reverse complement against the text's reverse complement on the
+// mirrored diagonal L - n - d; the forward run follows if it survives.
+// Returns the number of hits written, or -3 when the tail check dropped
+// the candidate.
+extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, int n, int64_t d,
+                         int k, int tail, int32_t *out_e, int32_t *out_v) {
+    if (n < 1 || n > PN_MAX_READ_LEN || k < 0 || k > PN_MAX_K) return -1;
+    const std::vector<uint4> pl = text_planes(text, L, false);
+    const std::vector<uint2> rp = read_planes(read, n, false);
     int m = 0;
     auto emit = [&](uint32_t e, int v) {
         out_e[m] = (int32_t)e;
         out_v[m] = v;
         m++;
     };
+    if (tail) {
+        const std::vector<uint4> plr = text_planes(text, L, true);
+        const std::vector<uint2> rpr = read_planes(read, n, true);
+        auto none = [&](uint32_t, int) {};
+        const int64_t lo = (int64_t)L - n - d - k;
+        const int rw = pn_band_verify(plr.data(), rpr.data(), n, k, lo, L, 16, none);
+        if (rw > 0 && rw < n) return -3;
+        pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, PN_MAX_READ_LEN, emit);
+        return m;
+    }
     if (pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, 16, emit) < 0) {
         if (m != 0) return -2;  // a capped run must not have emitted
         pn_band_verify(pl.data(), rp.data(), n, k, d - k, L, PN_MAX_READ_LEN, emit);

@@ -23,15 +23,18 @@ def band():
     lib = ctypes.CDLL(LIB)
     lib.band_host.restype = ctypes.c_int
     lib.band_host.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
-                              ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+                              ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p]
 
-    def run(text, read, d, k):
+    def run(text, read, d, k, tail=False):
         text = np.ascontiguousarray(text, np.uint8)
         read = np.ascontiguousarray(read, np.uint8)
         oe = np.zeros(64, np.int32)
         ov = np.zeros(64, np.int32)
         m = lib.band_host(text.ctypes.data, len(text), read.ctypes.data, len(read), int(d), int(k),
-                          oe.ctypes.data, ov.ctypes.data)
+                          int(tail), oe.ctypes.data, ov.ctypes.data)
+        if m == -3:
+            return None  # dropped by the tail check
         assert m >= 0
         return sorted(zip(oe[:m].tolist(), ov[:m].tolist()))
     return run
@@ -62,3 +65,48 @@ def test_band_code_equals_scalar_band_dp(band, seed):
         got = band(text, x, d, k)
         exp = sorted(oracle.banded(text, x, d, k))
         assert got == exp, (L, n, k, d)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tail_check_is_lossless(band, seed):
+    """The first pass may check a candidate's last 16 rows instead of its
+    first ones (the read's reverse complement against the text's, on the
+    mirrored diagonal L - n - d).  A candidate it drops must have no hit in
+    its band, and one it keeps must give the band's own hits.  Texts with
+    homopolymer runs make the first rows match while the last ones decide."""
+    rng = np.random.default_rng(100 + seed)
+    dropped = kept_with_hits = 0
+    for trial in range(400):
+        L = int(rng.integers(150, 600))
+        text = rng.integers(0, 4, L).astype(np.uint8)
+        for _ in range(int(rng.integers(0, 4))):  # homopolymer runs
+            a = int(rng.integers(0, L - 40))
+            text[a:a + int(rng.integers(10, 40))] = rng.integers(0, 4)
+        n = int(rng.integers(40, 150))
+        k = int(rng.integers(0, 9))
+        if rng.random() < 0.5:  # a read from the text, with a few errors
+            p = int(rng.integers(-10, L - n + 10))
+            x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
+                         np.uint8)
+            for _ in range(int(rng.integers(0, k + 2))):
+                x[rng.integers(0, n)] = rng.integers(0, 4)
+            d = p + int(rng.integers(-2, 3))
+        else:  # a run of the read placed on a run of the text, the rest random
+            x = rng.integers(0, 4, n).astype(np.uint8)
+            runs = [a for a in range(L - 20) if (text[a:a + 12] == text[a]).all()]
+            if not runs:
+                continue
+            a = runs[int(rng.integers(0, len(runs)))]
+            m = int(rng.integers(12, 30))
+            x[:m] = text[a]
+            d = a + int(rng.integers(0, 5))
+        d = max(d, -256)
+        exp = sorted(oracle.banded(text, x, d, k))
+        got = band(text, x, d, k, tail=True)
+        if got is None:
+            assert exp == [], (L, n, k, d)
+            dropped += 1
+        else:
+            assert got == exp, (L, n, k, d)
+            kept_with_hits += bool(exp)
+    assert dropped > 50 and kept_with_hits > 50

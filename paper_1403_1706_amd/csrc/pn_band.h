@@ -56,7 +56,10 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
     uint32_t h0 = pn_funnel(B.x, A.x, ph), l0 = pn_funnel(B.y, A.y, ph), v0 = pn_funnel(B.z, A.z, ph);
     uint32_t h1 = pn_funnel(C.x, B.x, ph), l1 = pn_funnel(C.y, B.y, ph), v1 = pn_funnel(C.z, B.z, ph);
     uint32_t VP = 0, VN = 0;  // row 0: every band cell is 0 (free start)
-    int R = 0;                // value of the right-most band cell
+    // The right-most band cell of row i holds R = i - (number of rows whose
+    // step left it unchanged, i.e. moved a -1 difference out of the band's
+    // top bit); Ck counts those rows plus k, so that R = i + k - Ck.
+    int Ck = k;
     for (int m = 0;; m++) {
         const uint2 rw = m == 0 ? hd.rw0 : rp[m];
 #pragma unroll
@@ -64,7 +67,9 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
             const int i = 32 * m + t + 1;  // row i compares read letter i-1
             const uint32_t H = pn_funnel(h1, h0, t), Lw = pn_funnel(l1, l0, t),
                            V = pn_funnel(v1, v0, t);
-            const uint32_t xh = 0u - ((rw.x >> t) & 1u), xl = 0u - ((rw.y >> t) & 1u);
+            // all ones where read letter i-1 has a 1 bit (a sign-extended bit field)
+            const uint32_t xh = (uint32_t)((int32_t)(rw.x << (31 - t)) >> 31),
+                           xl = (uint32_t)((int32_t)(rw.y << (31 - t)) >> 31);
             const uint32_t Eq = ~((H ^ xh) | (Lw ^ xl)) & V & M;
             VP = (VP >> 1) | TOP;  // previous row's differences, moved into this row's frame
             VN >>= 1;
@@ -72,14 +77,14 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
             const uint32_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
             uint32_t HP = VN | ~(Xh | VP);
             uint32_t HN = VP & Xh;
-            R += 1 - (int)((HN >> (W - 1)) & 1u);
+            Ck += (int)((HN >> (W - 1)) & 1u);
             HP = (HP << 1) | 1u;
             HN <<= 1;
             VP = HN | ~(Xv | HP);
             VN = HP & Xv;
             if (i == len) {
                 // last row: cell b holds R minus the differences to its right
-                int v = R;
+                int v = i + k - Ck;
                 for (int b = W - 1; b >= 0; b--) {
                     const int64_t c = (int64_t)len + lo + b;
                     if (c >= 1 && c <= (int64_t)L && v <= k) emit((uint32_t)(c - 1), v);
@@ -87,7 +92,10 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
                 }
                 return i;
             }
-            if (R - __builtin_popcount(VP & M2) > k) return i;  // whole row above k
+            // stop when the whole row is above k: R minus the +1 steps bounds
+            // the row minimum from below (R - popcount > k), written as one
+            // accumulating bit count and a compare
+            if (__builtin_popcount(VP & M2) + Ck < i) return i;
             if (t == 15 && i == row_cap) return -i;  // a cap half way through a word
         }
         if (32 * (m + 1) >= row_cap) return -32 * (m + 1);

@@ -38,8 +38,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr uint32_t kStage = 512;  // staged entries per wave
+constexpr uint32_t kStage = 256;  // staged entries per wave
 constexpr int kShortRows = 16;    // row cap of the first pass
+// waves per SIMD the first pass is compiled for (its registers allow 6 without
+// spilling; the second pass keeps the compiler's choice)
+constexpr int kFirstWaves = 6;
 
 // Entries (8 bytes) staged per wave in LDS and appended to one output region
 // with one global atomic per flush.  A lane that finds the stage full takes
@@ -126,7 +129,7 @@ __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix,
 // region b % kShards and (first pass) its survivors to long region
 // b % in.regions, which can hold every candidate of that input region.
 template <bool kFirst>
-__global__ __launch_bounds__(kThreads) void k_verify(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst ? kFirstWaves : 1))) void k_verify(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
                                                      int kglob, const uint8_t *__restrict__ kpr,
                                                      pn::VerifyOut out, uint2 *longc,
                                                      unsigned long long *n_long) {

@@ -54,7 +54,10 @@ namespace {
 constexpr int kT = pn::kFilterThreads;
 constexpr int kPPT = pn::kFilterPPT;
 constexpr int kWaves = kT / 64;
-constexpr int kWBuf = 256;  // staged candidates per wave
+constexpr int kWBuf = 256;        // staged candidates per wave (k_filter)
+constexpr int kWBufHeavy = 512;   // the same in k_filter_heavy, which flushes at
+                                  // kWBufHeavy - 64: fewer, longer flushes (each
+                                  // one's stores hold up the wave's next loads)
 
 // 64 bits of packed reference starting at signed base position B (base B+t
 // in bits 63-2t .. 62-2t); packed[-1] and 3 words past the end are readable
@@ -94,6 +97,7 @@ struct Stage {
     unsigned long long lane_base;  // this lane's reserved slots
     uint32_t lane_left;
     uint32_t written;  // output slots this lane accounts for (work counter)
+    uint32_t cap;      // slots of the LDS buffer
 };
 
 // The lanes that reach this together append one candidate each: one of
@@ -107,7 +111,7 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
     if (lane == leader) first = atomicAdd(sg.cnt, (uint32_t)__popcll(mask));
     first = __shfl(first, leader);
     const uint32_t i = first + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    if (i < kWBuf) {
+    if (i < sg.cap) {
         sg.buf[i] = pack_cand(c);
         return;
     }
@@ -128,7 +132,7 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
 // falls on the blocks.
 __device__ __forceinline__ void flush(Stage &sg, int lane) {
     __builtin_amdgcn_wave_barrier();
-    const uint32_t n = min(*sg.cnt, (uint32_t)kWBuf);
+    const uint32_t n = min(*sg.cnt, sg.cap);
     if (n) {
         uint2 *region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
         unsigned long long base = 0;
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     __syncthreads();
     const uint32_t shard = blockIdx.x % pn::kShards;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u, 0u};
+             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u, 0u, (uint32_t)kWBuf};
     const int q = ix.q;
     const uint32_t gmask = (1u << (2 * q)) - 1u;
     unsigned long long seeds = 0, visited = 0, set_aside = 0;
@@ -408,12 +412,12 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
 // The ranges set aside by k_filter, a wave per item: wave v of the grid
 // takes items v, v + (waves per region), ... of heavy region v % kShards and
 // walks each in wave-uniform steps of 64 occurrences (the same rules, the
-// same staging; a step adds at most 64 candidates, so flushing at half full
-// keeps the stage from overflowing).
+// same staging; a step adds at most 64 candidates, so flushing once 64 or
+// fewer slots are free keeps the stage from overflowing).
 __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
                                                      const unsigned long long *__restrict__ side,
                                                      pn::FilterOut out) {
-    __shared__ uint2 wbuf[kWaves][kWBuf];
+    __shared__ uint2 wbuf[kWaves][kWBufHeavy];
     __shared__ uint32_t wcnt[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
     const uint32_t gw = blockIdx.x * kWaves + wave;  // this wave in the grid
     const uint32_t nw = gridDim.x * kWaves;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             gw % pn::kShards, nullptr, 0ull, 0u, 0u};
+             gw % pn::kShards, nullptr, 0ull, 0u, 0u, (uint32_t)kWBufHeavy};
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
@@ -458,7 +462,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
             for (int u = 0; u < 4; u++) {
                 if (base + 64 * u + (uint32_t)lane < total)
                     visit(v[u], p, s, has, prev, lh, N, avail, sg);
-                if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
+                if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
             }
         }
     }

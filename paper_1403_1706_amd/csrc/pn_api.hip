@@ -546,7 +546,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_qgrams = c->hmisc[kStatT];
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
-    uint32_t *nq = nullptr, *flags = nullptr, *pos = nullptr, *partials = nullptr, *lcs = nullptr;
+    uint32_t *nq = nullptr, *flags = nullptr, *partials = nullptr, *lcs = nullptr;
     uint16_t *rlen = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;
@@ -562,7 +562,6 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     if (!s) s = dalloc_t(c, T + 1, &keys);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
     if (!s) s = dalloc_t(c, T + 1, &flags);
-    if (!s) s = dalloc_t(c, T + 1, &pos);
     if (!s) s = dalloc(c, pn::radix_temp_size(T), &sort_temp);
     if (!s)
         s = dalloc_t(c,
@@ -585,9 +584,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
         pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, rlen, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
-        pn::launch_scan_u32(flags, pos, T, partials, st);
-        pn::launch_sp_fill(flags, pos, T, x->Sp, st);  // steps 4-6
-        stage_end(c, st, tok, 5 + 3 * ((2 * q + 7) / 8) + 3 + 3 + 1);
+        pn::launch_starts_to_sp(flags, T, partials, x->Sp, st);  // steps 4-6
+        stage_end(c, st, tok, 5 + 3 * ((2 * q + 7) / 8) + 3 + 3);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
         e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);
@@ -607,7 +605,6 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     dfree(c, keys);
     dfree(c, tmp);
     dfree(c, flags);
-    dfree(c, pos);
     dfree(c, sort_temp);
     dfree(c, partials);
     dfree(c, lcs);

@@ -3,8 +3,9 @@
 // (read, strand, end) found through several candidates keep the smallest
 // error count, and best-stratum mode keeps the hits whose error count is the
 // read's minimum.  The sort is a stable LSD radix sort with 8-bit digits:
-// per-tile digit histograms, one exclusive scan over (digit, tile), and a
-// stable scatter that ranks equal digits inside each wave with ballots.
+// per-tile digit histograms (stored tile by tile, 256 counts each), an
+// exclusive scan in (digit, tile) order done column by column, and a stable
+// scatter that ranks equal digits inside each wave with ballots.
 #include "pn_internal.h"
 
 namespace {
@@ -30,7 +31,60 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long lon
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & dmask], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+    hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of the tile-major counts hist[b][d] in (digit, tile) order:
+// offs[b][d] = sum of all counts of digits below d + counts of digit d in
+// tiles below b.  Three launches: column sums per group of tiles, one block
+// scanning those per digit (and the digit totals), then each group's
+// columns again with its carries.
+constexpr int kScanGroups = 256;
+
+__global__ __launch_bounds__(256) void k_col_sums(const uint32_t *__restrict__ hist,
+                                                  uint64_t n_tiles, uint64_t per,
+                                                  uint32_t *colsum) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min(n_tiles, b0 + per);
+    uint32_t acc = 0;
+#pragma unroll 8
+    for (uint64_t b = b0; b < b1; b++) acc += hist[b * 256 + threadIdx.x];
+    colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// one block: colsum[g][d] -> digit base + groups below g
+__global__ __launch_bounds__(256) void k_col_top(uint32_t *colsum, uint32_t groups) {
+    // this digit's column, held in registers (groups <= kScanGroups)
+    constexpr int kPerThread = kScanGroups;
+    uint32_t col[kPerThread];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int g = 0; g < kPerThread; g++) {
+        col[g] = g < (int)groups ? colsum[(uint64_t)g * 256 + threadIdx.x] : 0u;
+    }
+#pragma unroll
+    for (int g = 0; g < kPerThread; g++) {
+        const uint32_t c = col[g];
+        col[g] = acc;
+        acc += c;
+    }
+    uint32_t tot;
+    const uint32_t base = pn_block_excl_scan(acc, &tot);  // digits below this one
+#pragma unroll
+    for (int g = 0; g < kPerThread; g++)
+        if (g < (int)groups) colsum[(uint64_t)g * 256 + threadIdx.x] = col[g] + base;
+}
+
+__global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ hist,
+                                                  uint64_t n_tiles, uint64_t per,
+                                                  const uint32_t *__restrict__ colsum,
+                                                  uint32_t *offs) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min(n_tiles, b0 + per);
+    uint32_t run = colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x];
+#pragma unroll 8
+    for (uint64_t b = b0; b < b1; b++) {
+        offs[b * 256 + threadIdx.x] = run;
+        run += hist[b * 256 + threadIdx.x];
+    }
 }
 
 // Stable scatter of one tile.  Wave w owns the tile's keys
@@ -50,6 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
     constexpr int kPerWave = kTile / kWaves;
     __shared__ unsigned long long tile[kTile];
     __shared__ uint32_t local[256];        // start of each digit inside the tile
+    __shared__ uint32_t goff[256];         // start of each digit's run in the output
     __shared__ uint32_t wcnt[kWaves][256];  // per wave: keys of each digit (then: before it)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -65,7 +120,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
 #pragma unroll
     for (int w = 0; w < kWaves; w++) wcnt[w][threadIdx.x] = 0;
     {
-        const uint32_t c = hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
+        const uint32_t c = hist[(uint64_t)blockIdx.x * 256 + threadIdx.x];
+        goff[threadIdx.x] = offs[(uint64_t)blockIdx.x * 256 + threadIdx.x];
         uint32_t tot;
         local[threadIdx.x] = pn_block_excl_scan(c, &tot);  // (synchronises the block)
     }
@@ -112,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
     for (uint32_t i = threadIdx.x; i < tile_n; i += kThreads) {
         const unsigned long long k = tile[i];
         const uint32_t dg = (uint32_t)(k >> shift) & dmask;
-        out[offs[(uint64_t)dg * n_tiles + blockIdx.x] + (i - local[dg])] = k;
+        out[goff[dg] + (i - local[dg])] = k;
     }
 }
 
@@ -203,7 +259,7 @@ static uint64_t tiles_for(uint64_t n) { return (n + kTile - 1) / kTile; }
 uint64_t radix_temp_size(uint64_t n) {
     uint64_t nt = tiles_for(n) ? tiles_for(n) : 1;
     uint64_t hist = 256 * nt + 1;
-    return (2 * hist + scan_partials_size(256 * nt)) * sizeof(uint32_t) + 256;
+    return (2 * hist + 256 * (uint64_t)kScanGroups) * sizeof(uint32_t) + 256;
 }
 
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
@@ -212,7 +268,9 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
     uint32_t *offs = hist + 256 * nt + 1;
-    uint32_t *partials = offs + 256 * nt + 1;
+    uint32_t *colsum = offs + 256 * nt + 1;
+    const uint64_t per = (nt + kScanGroups - 1) / kScanGroups;  // tiles per group
+    const uint32_t groups = (uint32_t)((nt + per - 1) / per);
     unsigned long long *src = keys, *dst = tmp;
     const int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; p++) {
@@ -221,7 +279,11 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kThreads), 0, st, src, n, shift,
                            dmask, hist, nt);
-        launch_scan_u32(hist, offs, 256 * nt, partials, st);
+        hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
+                           per, colsum);
+        hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256), 0, st, colsum, groups);
+        hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
+                           per, (const uint32_t *)colsum, offs);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,
                            shift, dmask, offs, hist, nt);
         unsigned long long *t = src;

@@ -11,7 +11,7 @@
 //      (Algorithm 1 step 1) and marks a group start               (k_index_from_sorted)
 //   d. S = exclusive scan of popcount(I[i]) (steps 2-3); the rank of each
 //      group start among the starts is its slot x = S[g/w] + GROUPRANK, so
-//      S'[x] = its position in O (steps 4-6)                     (pn_scan.hip, k_sp_fill)
+//      S'[x] = its position in O (steps 4-6)                (pn_scan.hip, k_scan_down_sp)
 // Each O entry also carries the letter before its q-gram and the (up to)
 // four letters after it, which the filter compares with the reference
 // without touching the reads.
@@ -91,13 +91,16 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
     const int rsh = kCarry ? sh + 8 : sh;  // where (r << 8 | o) starts
     const unsigned long long gmask = (1ull << (2 * ix.q)) - 1ull;
     const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
-    unsigned long long k[kPer];
+    unsigned long long k[kPer], kl[kPer];
     uint64_t off[kPer], end[kPer];
     uint32_t w[kPer];
+    // every load before the first store (a wave's loads wait for its earlier
+    // stores): the keys, and for lane 0 the key before its own
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
         const uint64_t i = i0 + (uint64_t)j * 256;
         k[j] = i < T ? keys[i] : 0ull;
+        kl[j] = (threadIdx.x & 63) == 0 && i && i <= T ? keys[i - 1] : ~0ull;
     }
     if (kCarry) {
         // the letters are in the key; only the read's length is looked up
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         const uint32_t r = ro >> 8, o = ro & 0xffu;
         // the previous entry's key: the lane before, or memory for lane 0
         unsigned long long kp = __shfl_up(k[j], 1);
-        if ((threadIdx.x & 63) == 0) kp = i ? keys[i - 1] : ~0ull;
+        if ((threadIdx.x & 63) == 0) kp = kl[j];
         const bool start = i == 0 || (uint32_t)(kp & gmask) != g;
         if (live) flags[i] = start;
         // I: lanes holding one word of I are contiguous (keys are sorted);
@@ -168,12 +171,6 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
 }
 
 // S'[x] = position of the x-th group start; S'[D] = T
-__global__ void k_sp_fill(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
-                          uint64_t T, uint32_t *Sp) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < T && flags[i]) Sp[pos[i]] = (uint32_t)i;
-    if (i == T) Sp[pos[T]] = (uint32_t)T;
-}
 
 // per read: number of low-complexity q-gram offsets and of maximal runs of
 // such offsets (both used by the map-time seed rules), and whether more of
@@ -243,10 +240,6 @@ void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *ke
                            ix, keys, T, O, flags, (uint32_t *)I, len);
 }
 
-void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_sp_fill, dim3(grid_for(T + 1, 256)), dim3(256), 0, st, flags, pos, T, Sp);
-}
 
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st) {
     if (!ix.n_reads) return;

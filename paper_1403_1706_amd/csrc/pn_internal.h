@@ -176,9 +176,10 @@ void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
                               unsigned long long *O, uint32_t *flags, void *I, const uint16_t *len,
                               hipStream_t st);
-// pos = exclusive scan of flags (pos[T] = D)
-void launch_sp_fill(const uint32_t *flags, const uint32_t *pos, uint64_t T, uint32_t *Sp,
-                    hipStream_t st);
+// S' from the group-start flags of the sorted occurrences: Sp[x] = position
+// of the x-th start, Sp[D] = T (partials: scan_partials_size(T) words)
+void launch_starts_to_sp(const uint32_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,
+                         hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
 
 // Append-only output split into kShards regions of `region_cap` entries,

@@ -118,6 +118,41 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Load load, uint32_t *out
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[nb];
 }
 
+// The group starts of a sorted q-gram list (Algorithm 1 steps 4-6): for
+// every i with flags[i] = 1, Sp[number of flags before i] = i, and
+// Sp[number of flags] = n.  The scan's own down-sweep places them, so the
+// prefix sums are never stored.
+__global__ __launch_bounds__(kThreads) void k_scan_down_sp(const uint32_t *__restrict__ flags,
+                                                           uint64_t n,
+                                                           const uint32_t *partials, uint64_t nb,
+                                                           uint32_t *Sp) {
+    __shared__ uint32_t tile[kTile + kTile / 32];
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        const int li = j * kThreads + threadIdx.x;
+        const uint64_t i = base + li;
+        tile[lds_idx(li)] = i < n ? flags[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        v[j] = tile[lds_idx(threadIdx.x * kItems + j)];
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(s, &total) + partials[blockIdx.x];
+    const uint64_t first = base + (uint64_t)threadIdx.x * kItems;
+#pragma unroll
+    for (int j = 0; j < kItems; j++) {
+        if (v[j]) Sp[run] = (uint32_t)(first + j);
+        run += v[j];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) Sp[partials[nb]] = (uint32_t)n;
+}
+
 template <typename Load>
 void scan_impl(Load load, uint32_t *out, uint64_t n, uint32_t *partials, hipStream_t st) {
     uint64_t nb = (n + kTile - 1) / kTile;
@@ -154,6 +189,18 @@ uint64_t scan_partials_size(uint64_t n) { return (n + kTile - 1) / kTile + 2; }
 void launch_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
                      hipStream_t st) {
     scan_impl(LoadU32{in}, out, n, partials, st);
+}
+
+void launch_starts_to_sp(const uint32_t *flags, uint64_t n, uint32_t *partials, uint32_t *Sp,
+                         hipStream_t st) {
+    uint64_t nb = (n + kTile - 1) / kTile;
+    if (nb == 0) nb = 1;
+    const LoadU32 load{flags};
+    hipLaunchKernelGGL(k_scan_reduce<LoadU32>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, n,
+                       partials);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, partials, nb);
+    hipLaunchKernelGGL(k_scan_down_sp, dim3((unsigned)nb), dim3(kThreads), 0, st, flags, n,
+                       (const uint32_t *)partials, nb, Sp);
 }
 
 void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint32_t *partials,

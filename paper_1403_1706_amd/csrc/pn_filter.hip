@@ -93,7 +93,7 @@ struct Stage {
     unsigned long long *counts;  // their counters
     uint64_t region_cap;
     uint32_t shard;  // region the next flush goes to (the same in every lane)
-    uint2 *lane_region;            // region of this lane's reserved slots
+    uint32_t lane_shard;           // region of this lane's reserved slots
     unsigned long long lane_base;  // this lane's reserved slots
     uint32_t lane_left;
     uint32_t written;  // output slots this lane accounts for (work counter)
@@ -116,14 +116,14 @@ __device__ __forceinline__ void push(Stage &sg, uint2 c) {
         return;
     }
     if (sg.lane_left == 0) {
-        sg.lane_region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
+        sg.lane_shard = sg.shard;
         sg.lane_base = atomicAdd(sg.counts + sg.shard, (unsigned long long)kLaneChunk);
         sg.lane_left = kLaneChunk;
         sg.written += kLaneChunk;
     }
     const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left);
     sg.lane_left--;
-    if (at < sg.region_cap) sg.lane_region[at] = c;
+    if (at < sg.region_cap) sg.cands[(uint64_t)sg.lane_shard * sg.region_cap + at] = c;
 }
 
 // Copy the wave's staged candidates out with one atomic add (whole wave,
@@ -157,7 +157,9 @@ __device__ __forceinline__ void flush(Stage &sg, int lane) {
 __device__ __forceinline__ void pad_lane(Stage &sg) {
     for (uint32_t i = 0; i < sg.lane_left; i++) {
         const unsigned long long at = sg.lane_base + (kLaneChunk - sg.lane_left) + i;
-        if (at < sg.region_cap) sg.lane_region[at] = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+        if (at < sg.region_cap)
+            sg.cands[(uint64_t)sg.lane_shard * sg.region_cap + at] =
+                make_uint2(PN_CAND_NONE, PN_CAND_NONE);
     }
     sg.lane_left = 0;
 }
@@ -190,7 +192,7 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
 // items of at most kItem occurrences; shorter ones are walked by their lane.
 constexpr uint32_t kHeavy = 64;
 constexpr uint32_t kItem = 1024;
-constexpr uint32_t kWalk = 8;  // entries a lane loads at a time
+constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
 // strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
@@ -282,8 +284,8 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     }
 
     if (valid && !heavy) {
-        // eight entries loaded at a time: the walk waits on memory once per
-        // eight entries, not once per entry
+        // kWalk entries loaded at a time: the walk waits on memory once per
+        // kWalk entries, not once per entry
         for (uint32_t t = rg.a0; t < rg.a1; t += kWalk) {
             unsigned long long w[kWalk];
 #pragma unroll
@@ -350,11 +352,12 @@ __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q,
     ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
 }
 
+// (compiled for 8 waves per SIMD: more waves hide more of the walk's load
+// latency than the few registers this spills cost)
 template <typename TW>
-__global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIndexDev ix,
-                                               const unsigned long long *__restrict__ side,
-                                               const uint32_t *__restrict__ side_cls,
-                                               pn::FilterOut out) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_filter(
+    PnRefDev ref, pn::RefQDev P, PnIndexDev ix, const unsigned long long *__restrict__ side,
+    const uint32_t *__restrict__ side_cls, pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBuf];
     __shared__ uint32_t wcnt[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(kT) void k_filter(PnRefDev ref, pn::RefQDev P, PnIn
     __syncthreads();
     const uint32_t shard = blockIdx.x % pn::kShards;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             (blockIdx.x * kWaves + wave) % pn::kShards, nullptr, 0ull, 0u, 0u, (uint32_t)kWBuf};
+             (blockIdx.x * kWaves + wave) % pn::kShards, 0u, 0ull, 0u, 0u, (uint32_t)kWBuf};
     const int q = ix.q;
     const uint32_t gmask = (1u << (2 * q)) - 1u;
     unsigned long long seeds = 0, visited = 0, set_aside = 0;
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
     const uint32_t gw = blockIdx.x * kWaves + wave;  // this wave in the grid
     const uint32_t nw = gridDim.x * kWaves;
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             gw % pn::kShards, nullptr, 0ull, 0u, 0u, (uint32_t)kWBufHeavy};
+             gw % pn::kShards, 0u, 0ull, 0u, 0u, (uint32_t)kWBufHeavy};
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;

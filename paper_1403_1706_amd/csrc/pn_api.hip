@@ -546,7 +546,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_qgrams = c->hmisc[kStatT];
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
-    uint32_t *nq = nullptr, *flags = nullptr, *partials = nullptr, *lcs = nullptr;
+    uint32_t *nq = nullptr, *partials = nullptr, *lcs = nullptr;
+    uint8_t *flags = nullptr;
     uint16_t *rlen = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;

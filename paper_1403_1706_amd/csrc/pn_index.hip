@@ -85,7 +85,7 @@ template <typename TW, bool kCarry>
 __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            const unsigned long long *__restrict__ keys,
                                                            uint64_t T, unsigned long long *O,
-                                                           uint32_t *flags, TW *I,
+                                                           uint8_t *flags, TW *I,
                                                            const uint16_t *__restrict__ len) {
     const int sh = 2 * ix.q + 3;
     const int rsh = kCarry ? sh + 8 : sh;  // where (r << 8 | o) starts
@@ -221,7 +221,7 @@ void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long
 }
 
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint32_t *flags, void *I, const uint16_t *len,
+                              unsigned long long *O, uint8_t *flags, void *I, const uint16_t *len,
                               hipStream_t st) {
     if (!T) return;
     const unsigned blocks = grid_for(T, 256 * kPer);

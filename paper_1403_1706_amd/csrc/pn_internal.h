@@ -174,11 +174,11 @@ void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long
 // O, group-start flags and I (zeroed by the caller) from keys sorted by
 // their low 2q+3 bits
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint32_t *flags, void *I, const uint16_t *len,
+                              unsigned long long *O, uint8_t *flags, void *I, const uint16_t *len,
                               hipStream_t st);
 // S' from the group-start flags of the sorted occurrences: Sp[x] = position
 // of the x-th start, Sp[D] = T (partials: scan_partials_size(T) words)
-void launch_starts_to_sp(const uint32_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,
+void launch_starts_to_sp(const uint8_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,
                          hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
 

@@ -120,30 +120,81 @@ __global__ __launch_bounds__(256) void k_read_meta(const uint64_t *__restrict__ 
     }
 }
 
-// plane word m of read r and of its reverse complement (letter j of the
-// reverse complement is the complement, code ^ 3, of letter len-1-j)
-__global__ void k_read_planes(const uint32_t *__restrict__ packed,
-                              const uint64_t *__restrict__ offsets, uint32_t n_reads,
-                              uint2 *__restrict__ rplanes, uint2 *__restrict__ rplanes_rc) {
-    uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t r = (uint32_t)(gid / PN_READ_WORDS);
-    uint32_t m = (uint32_t)(gid % PN_READ_WORDS);
+// the odd (hi = true) or even bits of a 32-bit word packed into 16 bits,
+// in order: bit 2t+1 (or 2t) goes to bit t
+__device__ __forceinline__ uint32_t compress_bits(uint32_t x, bool hi) {
+    x = (hi ? x >> 1 : x) & 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0f0f0f0fu;
+    x = (x | (x >> 4)) & 0x00ff00ffu;
+    return (x | (x >> 8)) & 0x0000ffffu;
+}
+
+// Plane words of one read (a thread per read): word m holds letters
+// 32m .. 32m+31, letter b of the word in bit b (H: high code bit, L: low).
+// The forward words come from 64-bit windows of the packed text (32
+// letters, first letter in the top two bits): the odd bits give H and the
+// even bits L, highest first, so a bit reversal puts letter b at bit b.
+// Letter j of the reverse complement is the complement (both code bits
+// flipped) of forward letter len-1-j, so its words are the forward bit
+// vectors read backwards and inverted.  Bits past the read's end are 0.
+__global__ __launch_bounds__(256) void k_read_planes(const uint32_t *__restrict__ packed,
+                                                     const uint64_t *__restrict__ offsets,
+                                                     uint32_t n_reads, uint2 *__restrict__ rplanes,
+                                                     uint2 *__restrict__ rplanes_rc) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_reads) return;
-    uint64_t start = offsets[r];
-    uint64_t len = offsets[r + 1] - start;
-    uint32_t h = 0, l = 0, hr = 0, lr = 0;
-    for (uint32_t b = 0; b < 32; b++) {
-        uint64_t o = 32ull * m + b;
-        if (o >= len) break;
-        const uint32_t c = pn_base_at(packed, start + o);
-        h |= (c >> 1) << b;
-        l |= (c & 1u) << b;
-        const uint32_t cr = pn_base_at(packed, start + len - 1 - o) ^ 3u;
-        hr |= (cr >> 1) << b;
-        lr |= (cr & 1u) << b;
+    const uint64_t start = offsets[r];
+    const int len = (int)min(offsets[r + 1] - start, (uint64_t)PN_MAX_READ_LEN);
+    uint32_t H[PN_READ_WORDS], L[PN_READ_WORDS];
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) {
+        H[m] = L[m] = 0;
+        const int left = len - 32 * m;  // letters of this word inside the read
+        if (left > 0) {
+            const uint64_t t = start + 32ull * m;
+            const uint64_t wi = t >> 4;
+            const uint32_t sh = 2 * (uint32_t)(t & 15);
+            const uint32_t w0 = packed[wi], w1 = packed[wi + 1], w2 = packed[wi + 2];
+            const uint32_t hi = sh ? (w0 << sh) | (w1 >> (32 - sh)) : w0;  // letters 0-15
+            const uint32_t lo = sh ? (w1 << sh) | (w2 >> (32 - sh)) : w1;  // letters 16-31
+            const uint32_t keep = left >= 32 ? 0xffffffffu : (1u << left) - 1u;
+            H[m] = __builtin_bitreverse32((compress_bits(hi, true) << 16) | compress_bits(lo, true)) &
+                   keep;
+            L[m] = __builtin_bitreverse32((compress_bits(hi, false) << 16) | compress_bits(lo, false)) &
+                   keep;
+        }
     }
-    rplanes[gid] = make_uint2(h, l);
-    rplanes_rc[gid] = make_uint2(hr, lr);
+    uint2 *f = rplanes + (uint64_t)r * PN_READ_WORDS;
+    uint2 *rc = rplanes_rc + (uint64_t)r * PN_READ_WORDS;
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) f[m] = make_uint2(H[m], L[m]);
+    // reverse complement word m: forward bits len-1-32m-b for b = 0..31,
+    // i.e. forward bits [e-32, e) read downwards, e = len - 32m
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) {
+        const int e = len - 32 * m;
+        uint32_t h = 0, l = 0;
+        if (e > 0) {
+            // forward bits [e-32, e) as one word (bits below 0 are 0)
+            const int lo_bit = e - 32;
+            uint32_t vh, vl;
+            if (lo_bit >= 0) {
+                const int wlo = lo_bit >> 5, s5 = lo_bit & 31;
+                const uint32_t h0 = H[wlo], h1 = wlo + 1 < PN_READ_WORDS ? H[wlo + 1] : 0u;
+                const uint32_t l0 = L[wlo], l1 = wlo + 1 < PN_READ_WORDS ? L[wlo + 1] : 0u;
+                vh = s5 ? (h0 >> s5) | (h1 << (32 - s5)) : h0;
+                vl = s5 ? (l0 >> s5) | (l1 << (32 - s5)) : l0;
+            } else {
+                vh = H[0] << (-lo_bit);
+                vl = L[0] << (-lo_bit);
+            }
+            const uint32_t keep = e >= 32 ? 0xffffffffu : (1u << e) - 1u;
+            h = ~__builtin_bitreverse32(vh) & keep;
+            l = ~__builtin_bitreverse32(vl) & keep;
+        }
+        rc[m] = make_uint2(h, l);
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -188,8 +239,8 @@ void launch_read_planes(const uint32_t *packed, const uint64_t *offsets, uint32_
                         uint2 *rplanes, hipStream_t st) {
     uint64_t n = (uint64_t)n_reads * PN_READ_WORDS;
     if (!n) return;
-    hipLaunchKernelGGL(k_read_planes, dim3(grid_for(n, 256)), dim3(256), 0, st, packed, offsets,
-                       n_reads, rplanes, rplanes + n);
+    hipLaunchKernelGGL(k_read_planes, dim3(grid_for(n_reads, 256)), dim3(256), 0, st, packed,
+                       offsets, n_reads, rplanes, rplanes + n);
 }
 
 void launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {

@@ -16,6 +16,10 @@ struct LoadU32 {
     const uint32_t *p;
     __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
 };
+struct LoadU8 {
+    const uint8_t *p;
+    __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
+};
 template <typename TW>
 struct LoadPopc {
     const TW *I;
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Load load, uint32_t *out
 // every i with flags[i] = 1, Sp[number of flags before i] = i, and
 // Sp[number of flags] = n.  The scan's own down-sweep places them, so the
 // prefix sums are never stored.
-__global__ __launch_bounds__(kThreads) void k_scan_down_sp(const uint32_t *__restrict__ flags,
+__global__ __launch_bounds__(kThreads) void k_scan_down_sp(const uint8_t *__restrict__ flags,
                                                            uint64_t n,
                                                            const uint32_t *partials, uint64_t nb,
                                                            uint32_t *Sp) {
@@ -191,12 +195,12 @@ void launch_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *pa
     scan_impl(LoadU32{in}, out, n, partials, st);
 }
 
-void launch_starts_to_sp(const uint32_t *flags, uint64_t n, uint32_t *partials, uint32_t *Sp,
+void launch_starts_to_sp(const uint8_t *flags, uint64_t n, uint32_t *partials, uint32_t *Sp,
                          hipStream_t st) {
     uint64_t nb = (n + kTile - 1) / kTile;
     if (nb == 0) nb = 1;
-    const LoadU32 load{flags};
-    hipLaunchKernelGGL(k_scan_reduce<LoadU32>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, n,
+    const LoadU8 load{flags};
+    hipLaunchKernelGGL(k_scan_reduce<LoadU8>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, n,
                        partials);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, partials, nb);
     hipLaunchKernelGGL(k_scan_down_sp, dim3((unsigned)nb), dim3(kThreads), 0, st, flags, n,

@@ -47,31 +47,75 @@ __global__ void k_read_nq(PnIndexDev ix, uint32_t *nq, uint16_t *len) {
 // (next4 << (2q + 3)) | (class << 2q) | g.  Sorting looks at the low 2q
 // bits (the q-gram) only, so each slice keeps the order (read, offset).  One wave per read: lane l takes offsets l, l + 64, ..., so a
 // wave reads one stretch of the packed reads and writes one stretch of keys.
+// The keys of a read's q-gram occurrences, at the read's offset in the key
+// array (see the header).  A wave takes reads gw, gw + nw, ...; lane l
+// holds word l of the read's packed text (a read touches at most 18 words),
+// and every window a key needs is put together from two lanes' words, so a
+// read costs one coalesced load, issued one read ahead of its use.
 template <bool kCarry>
 __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                                                     const uint32_t *__restrict__ qoff,
                                                     unsigned long long *__restrict__ keys) {
-    const uint32_t r = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (r >= ix.n_reads) return;
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t off = ix.offsets[r];
-    const uint64_t n = ix.offsets[r + 1] - off;
-    if (n < (uint64_t)ix.q) return;
-    const uint32_t nq = (uint32_t)(n - ix.q + 1);
-    const int sh = 2 * ix.q + 3;
-    const uint64_t base = qoff[r];
-    for (uint32_t o = lane; o < nq; o += 64) {
-        uint32_t cls;
-        const uint32_t g = qgram_at(ix, off, o, cls);
-        unsigned long long key = ((unsigned long long)cls << (2 * ix.q)) | g;
-        if (kCarry) {
-            const uint32_t next4 = pn_window16(ix.packed, off + o + ix.q) >> 24;
-            key |= ((unsigned long long)((r << 8) | o) << (sh + 8)) |
-                   ((unsigned long long)next4 << sh);
-        } else {
-            key |= (unsigned long long)((r << 8) | o) << sh;
+    const uint32_t gw = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const uint32_t nw = (uint32_t)(((uint64_t)gridDim.x * blockDim.x) >> 6);
+    const int q = ix.q;
+    const int sh = 2 * q + 3;
+    struct Read {
+        uint64_t off, n, base;
+        uint32_t word;  // this lane's word of the read's packed text
+    };
+    auto fetch = [&](uint32_t r) {
+        Read d{0, 0, 0, 0u};
+        if (r < ix.n_reads) {
+            d.off = ix.offsets[r];
+            d.n = ix.offsets[r + 1] - d.off;
+            d.base = qoff[r];
+            // words of letters [off, off + n) and the one after them
+            const uint32_t words = (uint32_t)(((d.off & 15) + d.n + 15) >> 4) + 1;
+            if (lane < words) d.word = ix.packed[(d.off >> 4) + lane];
         }
-        keys[base + o] = key;
+        return d;
+    };
+    Read cur = fetch(gw);
+    for (uint32_t r = gw; r < ix.n_reads; r += nw) {
+        const Read nxt = fetch(r + nw);
+        if (cur.n >= (uint64_t)q) {
+            const uint32_t nq = (uint32_t)(cur.n - q + 1);
+            const uint64_t w0 = cur.off >> 4;
+            // 16 letters starting at letter t of the text, first in the top bits
+            auto window = [&](uint64_t t) {
+                const int wi = (int)((t >> 4) - w0);
+                const uint32_t hi = (uint32_t)__shfl((int)cur.word, wi);
+                const uint32_t lo = (uint32_t)__shfl((int)cur.word, wi + 1);
+                const uint32_t s2 = 2 * (uint32_t)(t & 15);
+                return s2 ? (hi << s2) | (lo >> (32 - s2)) : hi;
+            };
+            for (uint32_t o0 = 0; o0 < nq; o0 += 64) {
+                const uint32_t o = o0 + lane;
+                // every lane takes part in the shuffles; lanes past nq store nothing
+                const uint32_t wq = window(cur.off + (o ? o - 1 : 0));
+                const uint32_t w4 = window(cur.off + o + q);
+                uint32_t cls, g;
+                if (o == 0) {
+                    cls = PN_CLS_NONE;
+                    g = wq >> (32 - 2 * q);
+                } else {
+                    cls = wq >> 30;
+                    g = (wq << 2) >> (32 - 2 * q);
+                }
+                unsigned long long key = ((unsigned long long)cls << (2 * q)) | g;
+                if (kCarry) {
+                    const uint32_t next4 = w4 >> 24;
+                    key |= ((unsigned long long)((r << 8) | o) << (sh + 8)) |
+                           ((unsigned long long)next4 << sh);
+                } else {
+                    key |= (unsigned long long)((r << 8) | o) << sh;
+                }
+                if (o < nq) keys[cur.base + o] = key;
+            }
+        }
+        cur = nxt;
     }
 }
 
@@ -172,25 +216,93 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
 
 // S'[x] = position of the x-th group start; S'[D] = T
 
-// per read: number of low-complexity q-gram offsets and of maximal runs of
+// 256-bit vectors (PN_READ_WORDS words, bit b of word m = position 32m+b)
+struct Bits256 {
+    uint32_t w[PN_READ_WORDS];
+};
+// v >> s (towards position 0), 0 < s < 32
+__device__ __forceinline__ Bits256 bits_down(const Bits256 &v, int s) {
+    Bits256 o;
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++)
+        o.w[m] = (v.w[m] >> s) | (m + 1 < PN_READ_WORDS ? v.w[m + 1] << (32 - s) : 0u);
+    return o;
+}
+__device__ __forceinline__ void bits_and(Bits256 &a, const Bits256 &b) {
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) a.w[m] &= b.w[m];
+}
+// bits [0, n) set
+__device__ __forceinline__ Bits256 bits_prefix(int n) {
+    Bits256 o;
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) {
+        const int k = n - 32 * m;
+        o.w[m] = k >= 32 ? 0xffffffffu : k > 0 ? (1u << k) - 1u : 0u;
+    }
+    return o;
+}
+
+// Per read: number of low-complexity q-gram offsets and of maximal runs of
 // such offsets (both used by the map-time seed rules), and whether more of
 // them lie in the first half of the offsets than in the second (bit 31: a
-// hint for the direction of verification's first pass)
+// hint for the direction of verification's first pass).  Bit-parallel over
+// the read's planes: E[i] = (letter i == letter i+2); the q-gram at offset o
+// is low-complexity (period <= 2) exactly when E[o .. o+q-3] are all set.
 __global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ix.n_reads) return;
-    const uint64_t off = ix.offsets[r];
-    const uint64_t n = ix.offsets[r + 1] - off;
-    const uint64_t nq = n >= (uint64_t)ix.q ? n - ix.q + 1 : 0;
-    uint32_t cnt = 0, runs = 0, front = 0;
-    bool prev_lc = false;
-    for (uint64_t o = 0; o < nq; o++) {
-        const uint32_t g = pn_window16(ix.packed, off + o) >> (32 - 2 * ix.q);
-        const bool lc = pn_low_complexity(g, ix.q);
-        cnt += lc;
-        front += lc && 2 * o < nq;
-        runs += lc && !prev_lc;
-        prev_lc = lc;
+    const int n = (int)min(ix.offsets[r + 1] - ix.offsets[r], (uint64_t)PN_MAX_READ_LEN);
+    const int q = ix.q;
+    const int nq = n >= q ? n - q + 1 : 0;
+    if (q < 3 || nq == 0) {
+        lcinfo[r] = 0;
+        return;
+    }
+    Bits256 H, L;
+    const uint2 *rp = ix.rplanes + (uint64_t)r * PN_READ_WORDS;
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) {
+        const uint2 v = rp[m];
+        H.w[m] = v.x;
+        L.w[m] = v.y;
+    }
+    const Bits256 H2 = bits_down(H, 2), L2 = bits_down(L, 2);
+    Bits256 E = bits_prefix(n - 2);  // positions i with letter i+2 inside the read
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) E.w[m] &= ~(H.w[m] ^ H2.w[m]) & ~(L.w[m] ^ L2.w[m]);
+    // C[o] = AND of E[o .. o+len-1] for len = q-2, built by doubling
+    Bits256 C = E, X = E;  // X: runs of `span` ones
+    int span = 1, have = 1;
+    while (2 * span <= q - 2) {
+        Bits256 Y = bits_down(X, span);
+        bits_and(X, Y);
+        span *= 2;
+    }
+    C = X;
+    have = span;
+    while (have < q - 2) {
+        const int add = min(span, q - 2 - have);
+        // runs of `add` ones from E, shifted to start `have` positions later
+        Bits256 Z = E;
+        for (int t = 1; t < add; t++) {
+            Bits256 Y = bits_down(E, t);
+            bits_and(Z, Y);
+        }
+        Bits256 Zs = bits_down(Z, have);
+        bits_and(C, Zs);
+        have += add;
+    }
+    const Bits256 inside = bits_prefix(nq);
+    bits_and(C, inside);
+    const Bits256 front_mask = bits_prefix((nq + 1) / 2);
+    uint32_t cnt = 0, front = 0, runs = 0, carry = 0;
+#pragma unroll
+    for (int m = 0; m < PN_READ_WORDS; m++) {
+        cnt += __popc(C.w[m]);
+        front += __popc(C.w[m] & front_mask.w[m]);
+        runs += __popc(C.w[m] & ~((C.w[m] << 1) | carry));  // starts of runs
+        carry = C.w[m] >> 31;
     }
     lcinfo[r] = cnt | (runs << 16) | ((2 * front > cnt ? 1u : 0u) << 31);
 }
@@ -211,7 +323,8 @@ void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
                        hipStream_t st) {
     if (!ix.n_reads) return;
-    const uint64_t threads = (uint64_t)ix.n_reads * 64;  // a wave per read
+    // waves: enough to fill the chip several times, each taking many reads
+    const uint64_t threads = std::min<uint64_t>((uint64_t)ix.n_reads * 64, 65536ull * 64);
     if (index_key_carries(ix.q))
         hipLaunchKernelGGL(k_qgram_keys<true>, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix,
                            qoff, keys);

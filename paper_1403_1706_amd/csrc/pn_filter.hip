@@ -643,24 +643,34 @@ __device__ __forceinline__ unsigned long long stamp(unsigned long long v,
     return (v & ~0xffull) | rinfo[(uint32_t)(v >> 40) & (PN_MAX_READS - 1)];
 }
 
-// four entries per thread and step, in two 16-byte loads and stores (O is
-// 16-byte aligned), so that each thread has four gathers in flight
+// One pass per thread: kStampPer pairs of entries loaded (16 bytes each,
+// coalesced across the wave), then their reads' rule bytes gathered, then
+// the stores, so that no load waits behind a store of the same wave (O is
+// 16-byte aligned)
+constexpr int kStampPer = 8;
+
 __global__ __launch_bounds__(256) void k_stamp_rules(unsigned long long *O, uint64_t n,
                                                      const uint8_t *__restrict__ rinfo) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ulonglong2 *O2 = (ulonglong2 *)O;
-    const uint64_t n4 = n / 4;
-    for (uint64_t i = tid; i < n4; i += stride) {
-        ulonglong2 a = O2[2 * i], b = O2[2 * i + 1];
-        a.x = stamp(a.x, rinfo);
-        a.y = stamp(a.y, rinfo);
-        b.x = stamp(b.x, rinfo);
-        b.y = stamp(b.y, rinfo);
-        O2[2 * i] = a;
-        O2[2 * i + 1] = b;
+    const uint64_t n2 = n / 2;
+    const uint64_t base = (uint64_t)blockIdx.x * (256 * kStampPer) + threadIdx.x;
+    ulonglong2 v[kStampPer];
+#pragma unroll
+    for (int j = 0; j < kStampPer; j++) {
+        const uint64_t i = base + (uint64_t)j * 256;
+        v[j] = i < n2 ? O2[i] : make_ulonglong2(0ull, 0ull);
     }
-    if (tid < n - 4 * n4) O[4 * n4 + tid] = stamp(O[4 * n4 + tid], rinfo);
+#pragma unroll
+    for (int j = 0; j < kStampPer; j++) {
+        v[j].x = stamp(v[j].x, rinfo);
+        v[j].y = stamp(v[j].y, rinfo);
+    }
+#pragma unroll
+    for (int j = 0; j < kStampPer; j++) {
+        const uint64_t i = base + (uint64_t)j * 256;
+        if (i < n2) O2[i] = v[j];
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) O[n - 1] = stamp(O[n - 1], rinfo);
 }
 
 // occurrence counts of the 16 low-complexity q-grams (sizes of their O slices)
@@ -723,8 +733,7 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
 
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st) {
     if (!n) return;
-    uint64_t blocks = (n / 4 + 255) / 256 + 1;
-    if (blocks > 8192) blocks = 8192;
+    const uint64_t blocks = (n / 2 + 256 * kStampPer - 1) / (256 * kStampPer) + 1;
     hipLaunchKernelGGL(k_stamp_rules, dim3((unsigned)blocks), dim3(256), 0, st, O, n, rinfo);
 }
 

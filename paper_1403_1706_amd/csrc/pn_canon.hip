@@ -51,27 +51,63 @@ __global__ __launch_bounds__(256) void k_col_sums(const uint32_t *__restrict__ h
     colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
-// one block: colsum[g][d] -> digit base + groups below g
-__global__ __launch_bounds__(256) void k_col_top(uint32_t *colsum, uint32_t groups) {
-    // this digit's column, held in registers (groups <= kScanGroups)
-    constexpr int kPerThread = kScanGroups;
-    uint32_t col[kPerThread];
+// one block of 1024 threads: colsum[g][d] -> digit base + groups below g.
+// Thread (part, d) scans a quarter of digit d's column in registers; the
+// quarters' totals give their carries and the digit totals, whose exclusive
+// scan over the 256 digits is the digit base.
+constexpr int kTopParts = 4;
+
+__global__ __launch_bounds__(256 * kTopParts) void k_col_top(uint32_t *colsum, uint32_t groups) {
+    constexpr int kPer = kScanGroups / kTopParts;
+    __shared__ uint32_t part_sum[kTopParts][256];
+    __shared__ uint32_t wave_sum[4];
+    __shared__ uint32_t digit_base[256];
+    const uint32_t d = threadIdx.x & 255, part = threadIdx.x >> 8;
+    const uint32_t g0 = part * kPer;
+    uint32_t col[kPer];
     uint32_t acc = 0;
 #pragma unroll
-    for (int g = 0; g < kPerThread; g++) {
-        col[g] = g < (int)groups ? colsum[(uint64_t)g * 256 + threadIdx.x] : 0u;
-    }
+    for (int j = 0; j < kPer; j++)
+        col[j] = g0 + j < groups ? colsum[(uint64_t)(g0 + j) * 256 + d] : 0u;
 #pragma unroll
-    for (int g = 0; g < kPerThread; g++) {
-        const uint32_t c = col[g];
-        col[g] = acc;
+    for (int j = 0; j < kPer; j++) {
+        const uint32_t c = col[j];
+        col[j] = acc;
         acc += c;
     }
-    uint32_t tot;
-    const uint32_t base = pn_block_excl_scan(acc, &tot);  // digits below this one
+    part_sum[part][d] = acc;
+    __syncthreads();
+    // part 0's threads: the quarters' carries and the digit's total
+    uint32_t total = 0;
+    if (part == 0) {
 #pragma unroll
-    for (int g = 0; g < kPerThread; g++)
-        if (g < (int)groups) colsum[(uint64_t)g * 256 + threadIdx.x] = col[g] + base;
+        for (int p = 0; p < kTopParts; p++) {
+            const uint32_t v = part_sum[p][d];
+            part_sum[p][d] = total;
+            total += v;
+        }
+    }
+    // exclusive scan of the digit totals over the digits (part 0 is waves
+    // 0-3, 64 digits each; the other parts scan zeros)
+    const int lane = threadIdx.x & 63, wave = (int)(threadIdx.x >> 6);
+    uint32_t inc = total;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (part == 0 && lane == 63) wave_sum[wave] = inc;
+    __syncthreads();
+    if (part == 0) {
+        uint32_t before = 0;
+        for (int w = 0; w < wave; w++) before += wave_sum[w];
+        digit_base[d] = before + inc - total;
+    }
+    __syncthreads();
+    const uint32_t add = digit_base[d] + part_sum[part][d];
+#pragma unroll
+    for (int j = 0; j < kPer; j++)
+        if (g0 + j < groups) colsum[(uint64_t)(g0 + j) * 256 + d] = col[j] + add;
 }
 
 __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ hist,
@@ -281,7 +317,7 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
                            dmask, hist, nt);
         hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, colsum);
-        hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256), 0, st, colsum, groups);
+        hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256 * kTopParts), 0, st, colsum, groups);
         hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, (const uint32_t *)colsum, offs);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,

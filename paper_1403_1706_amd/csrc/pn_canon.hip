@@ -11,16 +11,22 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;
+// keys per thread in the radix kernels: 32 (tiles of 8192 keys: runs of
+// 32 keys per digit on average, written as longer bursts) for large sorts,
+// 16 for smaller ones, where more tiles keep more of the chip busy
+constexpr int kItemsLarge = 32, kItemsSmall = 16;
+constexpr uint64_t kLargeSort = 1ull << 24;  // keys from which the large tiles are used
+inline int radix_items(uint64_t n) { return n >= kLargeSort ? kItemsLarge : kItemsSmall; }
 
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
+template <int kItems>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long long *keys,
                                                          uint64_t n, int shift, uint32_t dmask,
                                                          uint32_t *hist, uint64_t n_tiles) {
+    constexpr int kTile = kThreads * kItems;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -130,12 +136,14 @@ __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ h
 // over the waves then places every key in digit order in LDS, and the tile
 // is written out so that consecutive threads write consecutive addresses of
 // one digit's run.
+template <int kItems>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
                                                             unsigned long long *out, uint64_t n,
                                                             int shift, uint32_t dmask,
                                                             const uint32_t *offs,
                                                             const uint32_t *hist,
                                                             uint64_t n_tiles) {
+    constexpr int kTile = kThreads * kItems;
     constexpr int kWaves = kThreads / 64;
     constexpr int kPerWave = kTile / kWaves;
     __shared__ unsigned long long tile[kTile];
@@ -290,7 +298,10 @@ __global__ void k_keys_to_cands(const unsigned long long *keys, uint64_t n, uint
 
 namespace pn {
 
-static uint64_t tiles_for(uint64_t n) { return (n + kTile - 1) / kTile; }
+static uint64_t tiles_for(uint64_t n) {
+    const uint64_t tile = (uint64_t)kThreads * radix_items(n);
+    return (n + tile - 1) / tile;
+}
 
 uint64_t radix_temp_size(uint64_t n) {
     uint64_t nt = tiles_for(n) ? tiles_for(n) : 1;
@@ -313,15 +324,23 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const int shift = 8 * p;
         // the last digit may be narrower: bits above `bits` do not take part
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kThreads), 0, st, src, n, shift,
-                           dmask, hist, nt);
+        if (radix_items(n) == kItemsLarge)
+            hipLaunchKernelGGL(k_radix_hist<kItemsLarge>, dim3((unsigned)nt), dim3(kThreads), 0, st,
+                               src, n, shift, dmask, hist, nt);
+        else
+            hipLaunchKernelGGL(k_radix_hist<kItemsSmall>, dim3((unsigned)nt), dim3(kThreads), 0, st,
+                               src, n, shift, dmask, hist, nt);
         hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, colsum);
         hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256 * kTopParts), 0, st, colsum, groups);
         hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, (const uint32_t *)colsum, offs);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kThreads), 0, st, src, dst, n,
-                           shift, dmask, offs, hist, nt);
+        if (radix_items(n) == kItemsLarge)
+            hipLaunchKernelGGL(k_radix_scatter<kItemsLarge>, dim3((unsigned)nt), dim3(kThreads), 0,
+                               st, src, dst, n, shift, dmask, offs, hist, nt);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<kItemsSmall>, dim3((unsigned)nt), dim3(kThreads), 0,
+                               st, src, dst, n, shift, dmask, offs, hist, nt);
         unsigned long long *t = src;
         src = dst;
         dst = t;

@@ -11,33 +11,54 @@
 namespace {
 
 constexpr int kThreads = 256;
-// keys per thread in the radix kernels: 32 (tiles of 8192 keys: runs of
-// 32 keys per digit on average, written as longer bursts) for large sorts,
-// 16 for smaller ones, where more tiles keep more of the chip busy
-constexpr int kItemsLarge = 32, kItemsSmall = 16;
+// Radix tiles: 16 keys per thread; blocks of 512 threads (tiles of 8192
+// keys: runs of 32 keys per digit on average, written as longer bursts) for
+// large sorts, of 256 threads for smaller ones, where more tiles keep more
+// of the chip busy
+constexpr int kRadixItems = 16;
+constexpr int kThrLarge = 512, kThrSmall = 256;
 constexpr uint64_t kLargeSort = 1ull << 24;  // keys from which the large tiles are used
-inline int radix_items(uint64_t n) { return n >= kLargeSort ? kItemsLarge : kItemsSmall; }
+inline int radix_threads(uint64_t n) { return n >= kLargeSort ? kThrLarge : kThrSmall; }
+
+// exclusive scan of one value per digit (threads 0-255) over the 256
+// digits; every thread of the block calls it (it synchronises the block)
+__device__ __forceinline__ uint32_t digit_excl_scan(uint32_t x) {
+    __shared__ uint32_t ws[4];
+    const int lane = threadIdx.x & 63, wave = (int)(threadIdx.x >> 6);
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (threadIdx.x < 256 && lane == 63) ws[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave && w < 4; w++) before += ws[w];
+    __syncthreads();
+    return before + inc - x;
+}
 
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
-template <int kItems>
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const unsigned long long *keys,
-                                                         uint64_t n, int shift, uint32_t dmask,
-                                                         uint32_t *hist, uint64_t n_tiles) {
-    constexpr int kTile = kThreads * kItems;
+template <int kThr>
+__global__ __launch_bounds__(kThr) void k_radix_hist(const unsigned long long *keys, uint64_t n,
+                                                     int shift, uint32_t dmask, uint32_t *hist,
+                                                     uint64_t n_tiles) {
+    constexpr int kTile = kThr * kRadixItems;
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
 #pragma unroll 4
-    for (int j = 0; j < kItems; j++) {
-        uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+    for (int j = 0; j < kRadixItems; j++) {
+        uint64_t i = base + (uint64_t)j * kThr + threadIdx.x;
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & dmask], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
 // Exclusive scan of the tile-major counts hist[b][d] in (digit, tile) order:
@@ -136,15 +157,15 @@ __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ h
 // over the waves then places every key in digit order in LDS, and the tile
 // is written out so that consecutive threads write consecutive addresses of
 // one digit's run.
-template <int kItems>
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long long *keys,
-                                                            unsigned long long *out, uint64_t n,
-                                                            int shift, uint32_t dmask,
-                                                            const uint32_t *offs,
-                                                            const uint32_t *hist,
-                                                            uint64_t n_tiles) {
-    constexpr int kTile = kThreads * kItems;
-    constexpr int kWaves = kThreads / 64;
+template <int kThr>
+__global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long *keys,
+                                                        unsigned long long *out, uint64_t n,
+                                                        int shift, uint32_t dmask,
+                                                        const uint32_t *offs,
+                                                        const uint32_t *hist, uint64_t n_tiles) {
+    constexpr int kItems = kRadixItems;
+    constexpr int kTile = kThr * kItems;
+    constexpr int kWaves = kThr / 64;
     constexpr int kPerWave = kTile / kWaves;
     __shared__ unsigned long long tile[kTile];
     __shared__ uint32_t local[256];        // start of each digit inside the tile
@@ -161,13 +182,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
         const uint32_t li = w0 + (uint32_t)j * 64 + lane;
         key[j] = li < tile_n ? keys[base + li] : 0ull;
     }
-#pragma unroll
-    for (int w = 0; w < kWaves; w++) wcnt[w][threadIdx.x] = 0;
+    for (int t = threadIdx.x; t < kWaves * 256; t += kThr) (&wcnt[0][0])[t] = 0;
     {
-        const uint32_t c = hist[(uint64_t)blockIdx.x * 256 + threadIdx.x];
-        goff[threadIdx.x] = offs[(uint64_t)blockIdx.x * 256 + threadIdx.x];
-        uint32_t tot;
-        local[threadIdx.x] = pn_block_excl_scan(c, &tot);  // (synchronises the block)
+        const bool dig = threadIdx.x < 256;
+        const uint32_t c = dig ? hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] : 0u;
+        if (dig) goff[threadIdx.x] = offs[(uint64_t)blockIdx.x * 256 + threadIdx.x];
+        const uint32_t ex = digit_excl_scan(c);  // (synchronises the block)
+        if (dig) local[threadIdx.x] = ex;
     }
     uint32_t slot[kItems];  // digit | rank inside the wave's run of that digit << 8
 #pragma unroll
@@ -191,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
     }
     __syncthreads();
     // per digit: the keys of the waves before each wave
-    {
+    if (threadIdx.x < 256) {
         uint32_t acc = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; w++) {
@@ -209,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const unsigned long 
     __syncthreads();
     // the tile in digit order: slot i belongs to digit d with local[d] <= i,
     // and goes to offs[d] + (i - local[d])
-    for (uint32_t i = threadIdx.x; i < tile_n; i += kThreads) {
+    for (uint32_t i = threadIdx.x; i < tile_n; i += kThr) {
         const unsigned long long k = tile[i];
         const uint32_t dg = (uint32_t)(k >> shift) & dmask;
         out[goff[dg] + (i - local[dg])] = k;
@@ -299,7 +320,7 @@ __global__ void k_keys_to_cands(const unsigned long long *keys, uint64_t n, uint
 namespace pn {
 
 static uint64_t tiles_for(uint64_t n) {
-    const uint64_t tile = (uint64_t)kThreads * radix_items(n);
+    const uint64_t tile = (uint64_t)radix_threads(n) * kRadixItems;
     return (n + tile - 1) / tile;
 }
 
@@ -324,22 +345,22 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const int shift = 8 * p;
         // the last digit may be narrower: bits above `bits` do not take part
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
-        if (radix_items(n) == kItemsLarge)
-            hipLaunchKernelGGL(k_radix_hist<kItemsLarge>, dim3((unsigned)nt), dim3(kThreads), 0, st,
+        if (radix_threads(n) == kThrLarge)
+            hipLaunchKernelGGL(k_radix_hist<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,
                                src, n, shift, dmask, hist, nt);
         else
-            hipLaunchKernelGGL(k_radix_hist<kItemsSmall>, dim3((unsigned)nt), dim3(kThreads), 0, st,
+            hipLaunchKernelGGL(k_radix_hist<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0, st,
                                src, n, shift, dmask, hist, nt);
         hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, colsum);
         hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256 * kTopParts), 0, st, colsum, groups);
         hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, (const uint32_t *)colsum, offs);
-        if (radix_items(n) == kItemsLarge)
-            hipLaunchKernelGGL(k_radix_scatter<kItemsLarge>, dim3((unsigned)nt), dim3(kThreads), 0,
+        if (radix_threads(n) == kThrLarge)
+            hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0,
                                st, src, dst, n, shift, dmask, offs, hist, nt);
         else
-            hipLaunchKernelGGL(k_radix_scatter<kItemsSmall>, dim3((unsigned)nt), dim3(kThreads), 0,
+            hipLaunchKernelGGL(k_radix_scatter<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0,
                                st, src, dst, n, shift, dmask, offs, hist, nt);
         unsigned long long *t = src;
         src = dst;

@@ -583,7 +583,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         const unsigned long long *sorted =
             pn::radix_sort_u64_any(keys, tmp, T, 2 * q, sort_temp, st);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
-        pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, rlen, st);  // step 1, O
+        pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
         pn::launch_starts_to_sp(flags, T, partials, x->Sp, st);  // steps 4-6
         stage_end(c, st, tok, 5 + 3 * ((2 * q + 7) / 8) + 3 + 3);

@@ -4,7 +4,9 @@
 // one sort, which needs no atomic per occurrence and leaves every slice of
 // O ordered:
 //   a. one 64-bit key per q-gram occurrence (read r, offset o): (r, o),
-//      the class of the letter before the q-gram and the q-gram g (k_qgram_keys)
+//      the class of the letter before the q-gram, the q-gram g and (q <= 12)
+//      the letters after it with their count, all that an O entry holds
+//      (k_qgram_keys)
 //   b. stable LSD radix sort on the 2q bits of g: occurrences grouped by g,
 //      inside a group in the order (r, o)                          (pn_canon.hip)
 //   c. O[i] from the i-th key; the first key of each g sets bit g of I
@@ -30,6 +32,38 @@ __device__ __forceinline__ uint32_t qgram_at(const PnIndexDev &ix, uint64_t off,
     uint32_t w = pn_window16(ix.packed, off + o - 1);  // letter o-1 then the q-gram
     cls = w >> 30;
     return (w << 2) >> (32 - 2 * ix.q);
+}
+
+// The (up to) four letters after a q-gram inside its read (first letter in
+// the top bits, missing letters 0) and how many there are, nav = 0..4, in 9
+// bits: nav = 4 takes the codes 0-255, nav = 3 the next 64, nav = 2 the next
+// 16, nav = 1 the next 4 and nav = 0 the code 340.
+__device__ __forceinline__ uint32_t after_code(uint32_t next4, uint32_t nav) {
+    switch (nav) {
+        case 4: return next4;
+        case 3: return 256u + (next4 >> 2);
+        case 2: return 320u + (next4 >> 4);
+        case 1: return 336u + (next4 >> 6);
+        default: return 340u;
+    }
+}
+__device__ __forceinline__ void after_decode(uint32_t c, uint32_t &next4, uint32_t &nav) {
+    if (c < 256u) {
+        next4 = c;
+        nav = 4;
+    } else if (c < 320u) {
+        next4 = (c - 256u) << 2;
+        nav = 3;
+    } else if (c < 336u) {
+        next4 = (c - 320u) << 4;
+        nav = 2;
+    } else if (c < 340u) {
+        next4 = (c - 336u) << 6;
+        nav = 1;
+    } else {
+        next4 = 0;
+        nav = 0;
+    }
 }
 
 // q-gram starts per read (n_r - q + 1, or 0) and read lengths (<= 256)
@@ -104,13 +138,19 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                     cls = wq >> 30;
                     g = (wq << 2) >> (32 - 2 * q);
                 }
-                unsigned long long key = ((unsigned long long)cls << (2 * q)) | g;
+                unsigned long long key;
                 if (kCarry) {
-                    const uint32_t next4 = w4 >> 24;
-                    key |= ((unsigned long long)((r << 8) | o) << (sh + 8)) |
-                           ((unsigned long long)next4 << sh);
+                    // the letter before as 2 bits (none exactly when o = 0)
+                    // and the letters after with their count as 9
+                    const uint32_t after = o < nq ? nq - 1 - o : 0u;  // n - q - o
+                    const uint32_t nav = after < 4u ? after : 4u;
+                    const uint32_t next4 = (w4 >> 24) & ((0xffu << (8 - 2 * nav)) & 0xffu);
+                    key = ((unsigned long long)((r << 8) | o) << (2 * q + 11)) |
+                          ((unsigned long long)after_code(next4, nav) << (2 * q + 2)) |
+                          ((unsigned long long)(cls & 3u) << (2 * q)) | g;
                 } else {
-                    key |= (unsigned long long)((r << 8) | o) << sh;
+                    key = ((unsigned long long)((r << 8) | o) << sh) |
+                          ((unsigned long long)cls << (2 * q)) | g;
                 }
                 if (o < nq) keys[cur.base + o] = key;
             }
@@ -129,15 +169,13 @@ template <typename TW, bool kCarry>
 __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            const unsigned long long *__restrict__ keys,
                                                            uint64_t T, unsigned long long *O,
-                                                           uint8_t *flags, TW *I,
-                                                           const uint16_t *__restrict__ len) {
-    const int sh = 2 * ix.q + 3;
-    const int rsh = kCarry ? sh + 8 : sh;  // where (r << 8 | o) starts
+                                                           uint8_t *flags, TW *I) {
+    const int rsh = kCarry ? 2 * ix.q + 11 : 2 * ix.q + 3;  // where (r << 8 | o) starts
     const unsigned long long gmask = (1ull << (2 * ix.q)) - 1ull;
     const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
     unsigned long long k[kPer], kl[kPer];
     uint64_t off[kPer], end[kPer];
-    uint32_t w[kPer];
+    uint32_t w[kPer], code[kPer];
     // every load before the first store (a wave's loads wait for its earlier
     // stores): the keys, and for lane 0 the key before its own
 #pragma unroll
@@ -147,15 +185,9 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         kl[j] = (threadIdx.x & 63) == 0 && i && i <= T ? keys[i - 1] : ~0ull;
     }
     if (kCarry) {
-        // the letters are in the key; only the read's length is looked up
+        // the letters after the q-gram and their count are in the key
 #pragma unroll
-        for (int j = 0; j < kPer; j++) {
-            const uint32_t r = (uint32_t)(k[j] >> rsh) >> 8;
-            const bool ok = i0 + (uint64_t)j * 256 < T;
-            off[j] = 0;
-            end[j] = ok ? len[r] : 0;
-            w[j] = (uint32_t)((k[j] >> sh) & 0xffu) << 24;
-        }
+        for (int j = 0; j < kPer; j++) code[j] = (uint32_t)(k[j] >> (2 * ix.q + 2)) & 511u;
     } else {
 #pragma unroll
         for (int j = 0; j < kPer; j++) {
@@ -177,9 +209,11 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         if (i0 + (uint64_t)j * 256 - (threadIdx.x & 63) >= T) break;  // the whole wave is past T
         const bool live = i < T;
         const uint32_t g = (uint32_t)(k[j] & gmask);
-        const uint32_t cls = (uint32_t)(k[j] >> (2 * ix.q)) & 7u;
         const uint32_t ro = (uint32_t)(k[j] >> rsh);
         const uint32_t r = ro >> 8, o = ro & 0xffu;
+        const uint32_t cls = kCarry ? (o == 0 ? (uint32_t)PN_CLS_NONE
+                                              : (uint32_t)(k[j] >> (2 * ix.q)) & 3u)
+                                    : (uint32_t)(k[j] >> (2 * ix.q)) & 7u;
         // the previous entry's key: the lane before, or memory for lane 0
         unsigned long long kp = __shfl_up(k[j], 1);
         if ((threadIdx.x & 63) == 0) kp = kl[j];
@@ -203,11 +237,15 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         if (last && bits) atomicOr(&I[word], bits);
         if (!live) continue;
         // the letters after the q-gram inside the read (at most four)
-        const uint32_t n = (uint32_t)(end[j] - off[j]);
-        const uint32_t after = n - o - (uint32_t)ix.q;
-        const uint32_t nav = after < 4u ? after : 4u;
-        uint32_t next4 = w[j] >> 24;
-        next4 &= (0xffu << (8 - 2 * nav)) & 0xffu;
+        uint32_t next4, nav;
+        if (kCarry) {
+            after_decode(code[j], next4, nav);
+        } else {
+            const uint32_t n = (uint32_t)(end[j] - off[j]);
+            const uint32_t after = n - o - (uint32_t)ix.q;
+            nav = after < 4u ? after : 4u;
+            next4 = (w[j] >> 24) & ((0xffu << (8 - 2 * nav)) & 0xffu);
+        }
         const uint32_t hi = (cls << 29) | (r << 8) | o;
         const uint32_t lo = (next4 << 24) | (nav << 21);
         O[i] = ((unsigned long long)hi << 32) | lo;
@@ -334,23 +372,22 @@ void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long
 }
 
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint8_t *flags, void *I, const uint16_t *len,
-                              hipStream_t st) {
+                              unsigned long long *O, uint8_t *flags, void *I, hipStream_t st) {
     if (!T) return;
     const unsigned blocks = grid_for(T, 256 * kPer);
     const bool c = index_key_carries(ix.q);
     if (ix.log2w == 6 && c)
         hipLaunchKernelGGL((k_index_from_sorted<unsigned long long, true>), dim3(blocks), dim3(256),
-                           0, st, ix, keys, T, O, flags, (unsigned long long *)I, len);
+                           0, st, ix, keys, T, O, flags, (unsigned long long *)I);
     else if (ix.log2w == 6)
         hipLaunchKernelGGL((k_index_from_sorted<unsigned long long, false>), dim3(blocks),
-                           dim3(256), 0, st, ix, keys, T, O, flags, (unsigned long long *)I, len);
+                           dim3(256), 0, st, ix, keys, T, O, flags, (unsigned long long *)I);
     else if (c)
         hipLaunchKernelGGL((k_index_from_sorted<uint32_t, true>), dim3(blocks), dim3(256), 0, st, ix,
-                           keys, T, O, flags, (uint32_t *)I, len);
+                           keys, T, O, flags, (uint32_t *)I);
     else
         hipLaunchKernelGGL((k_index_from_sorted<uint32_t, false>), dim3(blocks), dim3(256), 0, st,
-                           ix, keys, T, O, flags, (uint32_t *)I, len);
+                           ix, keys, T, O, flags, (uint32_t *)I);
 }
 
 

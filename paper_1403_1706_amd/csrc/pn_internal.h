@@ -166,16 +166,17 @@ uint64_t scan_partials_size(uint64_t n);
 
 // pn_index.hip (Algorithm 1)
 void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream_t st);
-// index keys hold the four letters after each q-gram when there is room
-// (2q + 3 sort bits + 8 letter bits + 29 bits of read and offset <= 64)
-inline bool index_key_carries(int q) { return 2 * q + 3 + 8 + 29 <= 64; }
+// index keys hold the four letters after each q-gram and their count when
+// there is room: 2q bits of q-gram, 2 of the letter before, 9 of the
+// letters after (with their count), 29 of read and offset <= 64
+// (otherwise: 2q + 3 bits, the letter before or "none", then read and offset)
+inline bool index_key_carries(int q) { return 2 * q + 2 + 9 + 29 <= 64; }
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
                        hipStream_t st);
 // O, group-start flags and I (zeroed by the caller) from keys sorted by
-// their low 2q+3 bits
+// their low 2q bits
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,
-                              unsigned long long *O, uint8_t *flags, void *I, const uint16_t *len,
-                              hipStream_t st);
+                              unsigned long long *O, uint8_t *flags, void *I, hipStream_t st);
 // S' from the group-start flags of the sorted occurrences: Sp[x] = position
 // of the x-th start, Sp[D] = T (partials: scan_partials_size(T) words)
 void launch_starts_to_sp(const uint8_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,

@@ -859,9 +859,13 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         pn::launch_gather_shards((const unsigned long long *)c->keys_tmp.p,
                                  (const unsigned long long *)&c->misc[kRecCounts], pn::kShards,
                                  c->rec_rcap, (unsigned long long *)c->keys.p, st);
+        // mapping: records need only be grouped by (read, strand, end), the
+        // finishing pass takes each group's smallest error count; the
+        // records pn_validate returns are sorted whole
+        const int lo = filter ? 5 : 0;
         pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
-                           got, bits, c->sort_temp.p, st);
-        stage_end(c, st, tok, 1 + 3 * ((bits + 7) / 8));
+                           got, bits, c->sort_temp.p, st, lo);
+        stage_end(c, st, tok, 1 + 5 * ((bits - lo + 7) / 8));
         return PN_OK;
     }
     return PN_ENOMEM;

@@ -247,15 +247,27 @@ __global__ void k_read_min(const unsigned long long *keys, uint64_t n, int ebits
     atomicMin(&minv[r], (uint32_t)(k & 31u));
 }
 
-// 1 for the first record of each (read, strand, end) run (smallest errors,
-// keys being sorted) that also passes the stratum filter
+// smallest error count of the (read, strand, end) run that starts at i (the
+// records of a run are adjacent, in no particular order of errors; a run
+// holds the few candidates that reached the same end)
+__device__ __forceinline__ uint32_t run_min_errors(const unsigned long long *keys, uint64_t n,
+                                                   uint64_t i) {
+    const unsigned long long k = keys[i];
+    uint32_t m = (uint32_t)(k & 31u);
+    for (uint64_t j = i + 1; j < n && (keys[j] >> 5) == (k >> 5); j++)
+        m = min(m, (uint32_t)(keys[j] & 31u));
+    return m;
+}
+
+// 1 for the first record of each (read, strand, end) run whose smallest
+// error count also passes the stratum filter
 __global__ void k_keep_flags(const unsigned long long *keys, uint64_t n, int ebits, int best,
                              const uint32_t *minv, uint32_t *flags) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     unsigned long long k = keys[i];
     uint32_t f = (i == 0) || ((keys[i - 1] >> 5) != (k >> 5));
-    if (best && f) f = (uint32_t)(k & 31u) == minv[(uint32_t)(k >> (6 + ebits))];
+    if (best && f) f = run_min_errors(keys, n, i) == minv[(uint32_t)(k >> (6 + ebits))];
     flags[i] = f;
 }
 
@@ -274,7 +286,7 @@ __global__ void k_write_hits(const unsigned long long *keys, uint64_t n, int ebi
     if (i >= n || !flags[i]) return;
     uint64_t p = pos[i];
     if (p >= capacity) return;
-    uint4 h = key_to_hit(keys[i], ebits);
+    uint4 h = key_to_hit((keys[i] & ~31ull) | run_min_errors(keys, n, i), ebits);
     out[3 * p + 0] = h.x;
     out[3 * p + 1] = h.y;
     out[3 * p + 2] = h.z;
@@ -331,7 +343,7 @@ uint64_t radix_temp_size(uint64_t n) {
 }
 
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
-                                       uint64_t n, int bits, void *temp, hipStream_t st) {
+                                       uint64_t n, int bits, void *temp, hipStream_t st, int lo) {
     if (n <= 1 || bits <= 0) return keys;
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
@@ -340,9 +352,9 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     const uint64_t per = (nt + kScanGroups - 1) / kScanGroups;  // tiles per group
     const uint32_t groups = (uint32_t)((nt + per - 1) / per);
     unsigned long long *src = keys, *dst = tmp;
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits - lo + 7) / 8;
     for (int p = 0; p < passes; p++) {
-        const int shift = 8 * p;
+        const int shift = lo + 8 * p;
         // the last digit may be narrower: bits above `bits` do not take part
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
         if (radix_threads(n) == kThrLarge)
@@ -370,8 +382,8 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
 }
 
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
-                    void *temp, hipStream_t st) {
-    unsigned long long *src = radix_sort_u64_any(keys, tmp, n, bits, temp, st);
+                    void *temp, hipStream_t st, int lo) {
+    unsigned long long *src = radix_sort_u64_any(keys, tmp, n, bits, temp, st, lo);
     if (src != keys)
         (void)hipMemcpyAsync(keys, src, n * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
                              st);

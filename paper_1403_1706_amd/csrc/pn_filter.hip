@@ -373,11 +373,19 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     // consecutive ones per round; every lane runs the same rounds so that
     // long slices can be shared by the wave
     const uint64_t i0 = (uint64_t)blockIdx.x * (kT * kPPT) + threadIdx.x;
+    // the next entry of P is loaded while this one is probed and walked
+    unsigned long long key_next = i0 < P.n ? P.keys[i0] : 0ull;
+    uint32_t c_next = i0 < P.n ? P.ctx[i0] : 0u;
     for (int jj = 0; jj < kPPT; jj++) {
         const uint64_t i = i0 + (uint64_t)jj * kT;
         const bool valid = i < P.n;
-        const unsigned long long key = valid ? P.keys[i] : 0ull;
-        const uint32_t c = valid ? P.ctx[i] : 0u;
+        const unsigned long long key = key_next;
+        const uint32_t c = c_next;
+        if (jj + 1 < kPPT) {
+            const uint64_t in = i + kT;
+            key_next = in < P.n ? P.keys[in] : 0ull;
+            c_next = in < P.n ? P.ctx[in] : 0u;
+        }
         const uint32_t g = (uint32_t)key & gmask;
         const unsigned long long ps = key >> (2 * q);
         const int64_t p = (int64_t)(ps >> 1);

@@ -272,12 +272,13 @@ void launch_gather_shards(const unsigned long long *src, const unsigned long lon
 
 // pn_canon.hip: sort + duplicate removal + strata + output
 uint64_t radix_temp_size(uint64_t n);  // bytes
-// stable sort by the low `bits` bits; the result is in the returned buffer
-// (keys or tmp)
+// stable sort by bits [lo, bits) of the keys; the result is in the
+// returned buffer (keys or tmp)
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
-                                       uint64_t n, int bits, void *temp, hipStream_t st);
+                                       uint64_t n, int bits, void *temp, hipStream_t st,
+                                       int lo = 0);
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
-                    void *temp, hipStream_t st);
+                    void *temp, hipStream_t st, int lo = 0);
 void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,
                         uint32_t n_reads, uint32_t *minv, uint32_t *flags, uint32_t *pos,
                         uint32_t *partials, void *out_hits, uint64_t capacity,

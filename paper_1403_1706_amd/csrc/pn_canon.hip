@@ -63,9 +63,9 @@ __global__ __launch_bounds__(kThr) void k_radix_hist(const unsigned long long *k
 
 // Exclusive scan of the tile-major counts hist[b][d] in (digit, tile) order:
 // offs[b][d] = sum of all counts of digits below d + counts of digit d in
-// tiles below b.  Three launches: column sums per group of tiles, one block
-// scanning those per digit (and the digit totals), then each group's
-// columns again with its carries.
+// tiles below b.  Three launches: column sums per group of tiles, a block
+// per digit scanning its column over the groups (and its total), then each
+// group's columns again with its carries and the digit base.
 constexpr int kScanGroups = 256;
 
 __global__ __launch_bounds__(256) void k_col_sums(const uint32_t *__restrict__ hist,
@@ -78,71 +78,27 @@ __global__ __launch_bounds__(256) void k_col_sums(const uint32_t *__restrict__ h
     colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
-// one block of 1024 threads: colsum[g][d] -> digit base + groups below g.
-// Thread (part, d) scans a quarter of digit d's column in registers; the
-// quarters' totals give their carries and the digit totals, whose exclusive
-// scan over the 256 digits is the digit base.
-constexpr int kTopParts = 4;
-
-__global__ __launch_bounds__(256 * kTopParts) void k_col_top(uint32_t *colsum, uint32_t groups) {
-    constexpr int kPer = kScanGroups / kTopParts;
-    __shared__ uint32_t part_sum[kTopParts][256];
-    __shared__ uint32_t wave_sum[4];
-    __shared__ uint32_t digit_base[256];
-    const uint32_t d = threadIdx.x & 255, part = threadIdx.x >> 8;
-    const uint32_t g0 = part * kPer;
-    uint32_t col[kPer];
-    uint32_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < kPer; j++)
-        col[j] = g0 + j < groups ? colsum[(uint64_t)(g0 + j) * 256 + d] : 0u;
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-        const uint32_t c = col[j];
-        col[j] = acc;
-        acc += c;
-    }
-    part_sum[part][d] = acc;
-    __syncthreads();
-    // part 0's threads: the quarters' carries and the digit's total
-    uint32_t total = 0;
-    if (part == 0) {
-#pragma unroll
-        for (int p = 0; p < kTopParts; p++) {
-            const uint32_t v = part_sum[p][d];
-            part_sum[p][d] = total;
-            total += v;
-        }
-    }
-    // exclusive scan of the digit totals over the digits (part 0 is waves
-    // 0-3, 64 digits each; the other parts scan zeros)
-    const int lane = threadIdx.x & 63, wave = (int)(threadIdx.x >> 6);
-    uint32_t inc = total;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(inc, o);
-        if (lane >= o) inc += y;
-    }
-    if (part == 0 && lane == 63) wave_sum[wave] = inc;
-    __syncthreads();
-    if (part == 0) {
-        uint32_t before = 0;
-        for (int w = 0; w < wave; w++) before += wave_sum[w];
-        digit_base[d] = before + inc - total;
-    }
-    __syncthreads();
-    const uint32_t add = digit_base[d] + part_sum[part][d];
-#pragma unroll
-    for (int j = 0; j < kPer; j++)
-        if (g0 + j < groups) colsum[(uint64_t)(g0 + j) * 256 + d] = col[j] + add;
+// a block per digit d, a thread per group: colsum[g][d] -> the column's
+// sum over groups below g, dtot[d] -> the column's total
+__global__ __launch_bounds__(256) void k_col_top(uint32_t *colsum, uint32_t groups,
+                                                 uint32_t *dtot) {
+    const uint32_t d = blockIdx.x, g = threadIdx.x;
+    const uint32_t v = g < groups ? colsum[(uint64_t)g * 256 + d] : 0u;
+    uint32_t tot;
+    const uint32_t ex = pn_block_excl_scan(v, &tot);
+    if (g < groups) colsum[(uint64_t)g * 256 + d] = ex;
+    if (g == 0) dtot[d] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ hist,
                                                   uint64_t n_tiles, uint64_t per,
                                                   const uint32_t *__restrict__ colsum,
+                                                  const uint32_t *__restrict__ dtot,
                                                   uint32_t *offs) {
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min(n_tiles, b0 + per);
-    uint32_t run = colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x];
+    uint32_t tot;
+    const uint32_t base = pn_block_excl_scan(dtot[threadIdx.x], &tot);  // digits below this one
+    uint32_t run = colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] + base;
 #pragma unroll 8
     for (uint64_t b = b0; b < b1; b++) {
         offs[b * 256 + threadIdx.x] = run;
@@ -339,7 +295,7 @@ static uint64_t tiles_for(uint64_t n) {
 uint64_t radix_temp_size(uint64_t n) {
     uint64_t nt = tiles_for(n) ? tiles_for(n) : 1;
     uint64_t hist = 256 * nt + 1;
-    return (2 * hist + 256 * (uint64_t)kScanGroups) * sizeof(uint32_t) + 256;
+    return (2 * hist + 256 * (uint64_t)kScanGroups + 256) * sizeof(uint32_t) + 256;
 }
 
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
@@ -349,6 +305,7 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     uint32_t *hist = (uint32_t *)temp;
     uint32_t *offs = hist + 256 * nt + 1;
     uint32_t *colsum = offs + 256 * nt + 1;
+    uint32_t *dtot = colsum + 256 * (uint64_t)kScanGroups;
     const uint64_t per = (nt + kScanGroups - 1) / kScanGroups;  // tiles per group
     const uint32_t groups = (uint32_t)((nt + per - 1) / per);
     unsigned long long *src = keys, *dst = tmp;
@@ -365,9 +322,9 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
                                src, n, shift, dmask, hist, nt);
         hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
                            per, colsum);
-        hipLaunchKernelGGL(k_col_top, dim3(1), dim3(256 * kTopParts), 0, st, colsum, groups);
+        hipLaunchKernelGGL(k_col_top, dim3(256), dim3(256), 0, st, colsum, groups, dtot);
         hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
-                           per, (const uint32_t *)colsum, offs);
+                           per, (const uint32_t *)colsum, (const uint32_t *)dtot, offs);
         if (radix_threads(n) == kThrLarge)
             hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0,
                                st, src, dst, n, shift, dmask, offs, hist, nt);

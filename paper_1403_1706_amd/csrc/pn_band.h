@@ -60,8 +60,10 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
     // step left it unchanged, i.e. moved a -1 difference out of the band's
     // top bit); Ck counts those rows plus k, so that R = i + k - Ck.
     int Ck = k;
+    uint2 rw_next = hd.rw0;  // the read's plane word for the next 32 rows, loaded a word ahead
     for (int m = 0;; m++) {
-        const uint2 rw = m == 0 ? hd.rw0 : rp[m];
+        const uint2 rw = rw_next;
+        if (32 * (m + 1) < len && 32 * (m + 1) < row_cap) rw_next = rp[m + 1];
 #pragma unroll
         for (int t = 0; t < 32; t++) {
             const int i = 32 * m + t + 1;  // row i compares read letter i-1

@@ -190,7 +190,7 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
 
 // Occurrence ranges longer than this are set aside for k_filter_heavy, in
 // items of at most kItem occurrences; shorter ones are walked by their lane.
-constexpr uint32_t kHeavy = 64;
+constexpr uint32_t kHeavy = 32;
 constexpr uint32_t kItem = 1024;
 constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 

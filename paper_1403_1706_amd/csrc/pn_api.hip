@@ -731,6 +731,7 @@ int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStrea
                      {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
                      (uint4 *)c->heavy.p,
                      {(unsigned long long *)&c->misc[kHeavyCounts], c->heavy_rcap},
+                     pn::filter_heavy_min(x->n_qgrams, x->q),
                      (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
     pn::launch_filter(ref_desc(ref), P, index_desc(x), (const unsigned long long *)c->side.p,

@@ -188,9 +188,9 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
                         (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
 }
 
-// Occurrence ranges longer than this are set aside for k_filter_heavy, in
-// items of at most kItem occurrences; shorter ones are walked by their lane.
-constexpr uint32_t kHeavy = 32;
+// Occurrence ranges longer than FilterOut::heavy_min are set aside for
+// k_filter_heavy, in items of at most kItem occurrences; shorter ones are
+// walked by their lane.
 constexpr uint32_t kItem = 1024;
 constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 
@@ -243,7 +243,7 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
                                               unsigned long long &set_aside) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
     // the longest ranges wait for k_filter_heavy (a block each)
-    const bool heavy = valid && len > kHeavy;
+    const bool heavy = valid && len > out.heavy_min;
     // a set-aside entry becomes one item per kItem occurrences (a wave walks
     // an item), so that no single item is long
     const uint32_t nitems = heavy ? (len + kItem - 1) / kItem : 0u;

@@ -201,10 +201,11 @@ constexpr int kLcPatterns = 16;  // period <= 2 q-grams: first two letters
 struct FilterOut {
     uint2 *cands;                 // (read | strand << 31, diagonal + PN_DBIAS), kShards regions
     Shards sh;                    // per-region append counters
-    // entries whose occurrence ranges are too long for one wave, set aside
-    // for a block each: 2 uint4 per item, kShards regions
+    // entries whose occurrence ranges are longer than heavy_min, set aside
+    // for k_filter_heavy: 2 uint4 per item, kShards regions
     uint4 *heavy;
     Shards hsh;
+    uint32_t heavy_min;
     // per region g (work counters of k_filter): stats[4g] = occurrence pairs
     // seen (sum of k_end - k_start), stats[4g+1] = index entries read (by
     // either kernel), stats[4g+2] = the part of those set aside for
@@ -238,6 +239,13 @@ void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys,
 // the occurrence lists k_filter set aside (FilterOut::heavy)
 void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,
                          hipStream_t st);
+// the longest occurrence list k_filter walks itself: 32 when the lists are
+// short on average (fewer than 16 entries per q-gram of the index: the long
+// ones are rare and are better walked by a whole wave), else 64 (where most
+// lists are long, a smaller bound would make nearly every list an item)
+inline uint32_t filter_heavy_min(uint64_t n_qgrams, int q) {
+    return n_qgrams < (16ull << (2 * q)) ? 32u : 64u;
+}
 void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
                    const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
                    hipStream_t st);

@@ -15,7 +15,7 @@ __host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo,
 // (lo = d - k); 1 <= len <= PN_MAX_READ_LEN; 0 <= k <= PN_MAX_K.  Calls
 // emit(end, value) for every end column of the last row with value <= k,
 // and returns the number of rows computed.  A candidate still alive after
-// row_cap rows (a multiple of 16, below len) stops there without emitting
+// row_cap rows (a multiple of 8, below len) stops there without emitting
 // and -row_cap is returned; the caller runs it again from row 0 without cap.
 // The first memory words a candidate needs: plane blocks blk .. blk+3 of
 // its stream and the read's first plane word.  Loading them is separate so
@@ -98,7 +98,7 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
             // the row minimum from below (R - popcount > k), written as one
             // accumulating bit count and a compare
             if (__builtin_popcount(VP & M2) + Ck < i) return i;
-            if (t == 15 && i == row_cap) return -i;  // a cap half way through a word
+            if ((t & 7) == 7 && t != 31 && i == row_cap) return -i;  // a cap inside a word
         }
         if (32 * (m + 1) >= row_cap) return -32 * (m + 1);
         // advance the stream by 32 positions

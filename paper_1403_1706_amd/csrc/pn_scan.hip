@@ -16,10 +16,6 @@ struct LoadU32 {
     const uint32_t *p;
     __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
 };
-struct LoadU8 {
-    const uint8_t *p;
-    __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
-};
 template <typename TW>
 struct LoadPopc {
     const TW *I;
@@ -124,35 +120,43 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(Load load, uint32_t *out
 
 // The group starts of a sorted q-gram list (Algorithm 1 steps 4-6): for
 // every i with flags[i] = 1, Sp[number of flags before i] = i, and
-// Sp[number of flags] = n.  The scan's own down-sweep places them, so the
-// prefix sums are never stored.
+// Sp[number of flags] = n.  The flags are bytes (0 or 1); a thread takes 16
+// consecutive ones in one 16-byte load, and counts them as the set bits of
+// its four words.  Tiles of kTile flags: per-tile counts, one block scanning
+// them, then each tile again with its carry placing its starts (the prefix
+// sums are never stored).
+__device__ __forceinline__ uint4 load_flags16(const uint8_t *__restrict__ flags, uint64_t n,
+                                              uint64_t first) {
+    if (first + 16 <= n) return *(const uint4 *)(flags + first);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (uint64_t j = first; j < n && j < first + 16; j++)
+        w[(j - first) >> 2] |= (uint32_t)flags[j] << (8 * ((j - first) & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_flags_reduce(const uint8_t *__restrict__ flags,
+                                                           uint64_t n, uint32_t *partials) {
+    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    const uint4 v = first < n ? load_flags16(flags, n, first) : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    uint32_t total;
+    block_excl_scan(c, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
 __global__ __launch_bounds__(kThreads) void k_scan_down_sp(const uint8_t *__restrict__ flags,
                                                            uint64_t n,
                                                            const uint32_t *partials, uint64_t nb,
                                                            uint32_t *Sp) {
-    __shared__ uint32_t tile[kTile + kTile / 32];
-    const uint64_t base = (uint64_t)blockIdx.x * kTile;
-#pragma unroll
-    for (int j = 0; j < kItems; j++) {
-        const int li = j * kThreads + threadIdx.x;
-        const uint64_t i = base + li;
-        tile[lds_idx(li)] = i < n ? flags[i] : 0u;
-    }
-    __syncthreads();
-    uint32_t v[kItems];
-    uint32_t s = 0;
-#pragma unroll
-    for (int j = 0; j < kItems; j++) {
-        v[j] = tile[lds_idx(threadIdx.x * kItems + j)];
-        s += v[j];
-    }
+    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    const uint4 v = first < n ? load_flags16(flags, n, first) : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
     uint32_t total;
-    uint32_t run = block_excl_scan(s, &total) + partials[blockIdx.x];
-    const uint64_t first = base + (uint64_t)threadIdx.x * kItems;
+    uint32_t run = block_excl_scan(c, &total) + partials[blockIdx.x];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < kItems; j++) {
-        if (v[j]) Sp[run] = (uint32_t)(first + j);
-        run += v[j];
+        if ((w[j >> 2] >> (8 * (j & 3))) & 1u) Sp[run++] = (uint32_t)(first + j);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) Sp[partials[nb]] = (uint32_t)n;
 }
@@ -199,8 +203,7 @@ void launch_starts_to_sp(const uint8_t *flags, uint64_t n, uint32_t *partials, u
                          hipStream_t st) {
     uint64_t nb = (n + kTile - 1) / kTile;
     if (nb == 0) nb = 1;
-    const LoadU8 load{flags};
-    hipLaunchKernelGGL(k_scan_reduce<LoadU8>, dim3((unsigned)nb), dim3(kThreads), 0, st, load, n,
+    hipLaunchKernelGGL(k_flags_reduce, dim3((unsigned)nb), dim3(kThreads), 0, st, flags, n,
                        partials);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, st, partials, nb);
     hipLaunchKernelGGL(k_scan_down_sp, dim3((unsigned)nb), dim3(kThreads), 0, st, flags, n,

@@ -287,9 +287,10 @@ int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
     unsigned long long *keys = nullptr, *tmp = nullptr;
     uint16_t *ctx = nullptr;
     void *temp = nullptr;
+    const bool packed = pn::refq_packs(r->L, q);
     hipError_t e = hipMalloc((void **)&keys, n * 8);
     if (e == hipSuccess) e = hipMalloc((void **)&tmp, n * 8);
-    if (e == hipSuccess) e = hipMalloc((void **)&ctx, n * 2);
+    if (e == hipSuccess && !packed) e = hipMalloc((void **)&ctx, n * 2);
     if (e == hipSuccess) e = hipMalloc(&temp, pn::radix_temp_size(n));
     if (e == hipSuccess) {
         const PnRefDev rd = ref_desc(r);

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_refq_keys(PnRefDev ref, int q,
 // there is one (bit 2), letters after it that exist, up to 4 (bits 3-5),
 // and those letters (bits 6-13, first letter highest)
 __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q,
-                                                  const unsigned long long *__restrict__ keys,
+                                                  unsigned long long *__restrict__ keys,
                                                   uint64_t n, uint16_t *__restrict__ ctx) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -349,12 +349,16 @@ __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q,
     }
     if (!has) prev = 0;
     N &= (0xffu << (8 - 2 * avail)) & 0xffu;
-    ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
+    if (ctx)
+        ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
+    else
+        keys[i] = (ps << (2 * q + 10)) | ((unsigned long long)N << (2 * q + 2)) |
+                  ((unsigned long long)prev << (2 * q)) | (keys[i] & ((1ull << (2 * q)) - 1ull));
 }
 
 // (compiled for 8 waves per SIMD: more waves hide more of the walk's load
 // latency than the few registers this spills cost)
-template <typename TW>
+template <typename TW, bool kPacked>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_filter(
     PnRefDev ref, pn::RefQDev P, PnIndexDev ix, const unsigned long long *__restrict__ side,
     const uint32_t *__restrict__ side_cls, pn::FilterOut out) {
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const uint64_t i0 = (uint64_t)blockIdx.x * (kT * kPPT) + threadIdx.x;
     // the next entry of P is loaded while this one is probed and walked
     unsigned long long key_next = i0 < P.n ? P.keys[i0] : 0ull;
-    uint32_t c_next = i0 < P.n ? P.ctx[i0] : 0u;
+    uint32_t c_next = !kPacked && i0 < P.n ? P.ctx[i0] : 0u;
     for (int jj = 0; jj < kPPT; jj++) {
         const uint64_t i = i0 + (uint64_t)jj * kT;
         const bool valid = i < P.n;
@@ -384,14 +388,26 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         if (jj + 1 < kPPT) {
             const uint64_t in = i + kT;
             key_next = in < P.n ? P.keys[in] : 0ull;
-            c_next = in < P.n ? P.ctx[in] : 0u;
+            if (!kPacked) c_next = in < P.n ? P.ctx[in] : 0u;
         }
         const uint32_t g = (uint32_t)key & gmask;
-        const unsigned long long ps = key >> (2 * q);
+        const unsigned long long ps = key >> (kPacked ? 2 * q + 10 : 2 * q);
         const int64_t p = (int64_t)(ps >> 1);
         const uint32_t s = (uint32_t)(ps & 1u);
-        const bool has = (c >> 2) & 1u;
-        const uint32_t prev = c & 3u, avail = (c >> 3) & 7u, N = (c >> 6) & 0xffu;
+        bool has;
+        uint32_t prev, avail, N;
+        if (kPacked) {
+            has = p >= 1;
+            prev = (uint32_t)(key >> (2 * q)) & 3u;
+            N = (uint32_t)(key >> (2 * q + 2)) & 0xffu;
+            const uint64_t after = ref.L - (uint64_t)q - (uint64_t)p;
+            avail = after < 4 ? (uint32_t)after : 4u;
+        } else {
+            has = (c >> 2) & 1u;
+            prev = c & 3u;
+            avail = (c >> 3) & 7u;
+            N = (c >> 6) & 0xffu;
+        }
         const bool lh = has && pn_low_complexity((prev << (2 * (q - 1))) | (g >> 2), q);
         Ranges r;
         if (valid) {
@@ -753,7 +769,7 @@ void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipS
                        q, keys);
 }
 
-void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys, uint64_t n,
+void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_refq_ctx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ref, q,
@@ -765,12 +781,19 @@ void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
                    hipStream_t st) {
     const uint64_t nb = (P.n + kFilterBlockPos - 1) / kFilterBlockPos;
     if (!nb || !ix.n_reads) return;
-    if (ix.log2w == 6)
-        hipLaunchKernelGGL(k_filter<unsigned long long>, dim3((unsigned)nb), dim3(kT), 0, st, ref,
-                           P, ix, side, side_cls, out);
+    const bool packed = P.ctx == nullptr;
+    if (ix.log2w == 6 && packed)
+        hipLaunchKernelGGL((k_filter<unsigned long long, true>), dim3((unsigned)nb), dim3(kT), 0,
+                           st, ref, P, ix, side, side_cls, out);
+    else if (ix.log2w == 6)
+        hipLaunchKernelGGL((k_filter<unsigned long long, false>), dim3((unsigned)nb), dim3(kT), 0,
+                           st, ref, P, ix, side, side_cls, out);
+    else if (packed)
+        hipLaunchKernelGGL((k_filter<uint32_t, true>), dim3((unsigned)nb), dim3(kT), 0, st, ref, P,
+                           ix, side, side_cls, out);
     else
-        hipLaunchKernelGGL(k_filter<uint32_t>, dim3((unsigned)nb), dim3(kT), 0, st, ref, P, ix,
-                           side, side_cls, out);
+        hipLaunchKernelGGL((k_filter<uint32_t, false>), dim3((unsigned)nb), dim3(kT), 0, st, ref, P,
+                           ix, side, side_cls, out);
 }
 
 void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,

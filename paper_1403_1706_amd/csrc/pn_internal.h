@@ -227,14 +227,27 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
                     hipStream_t st);
 // write each read's rule byte into the low byte of its O entries
 void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st);
-// the position set P of a reference for one q, sorted by q-gram
+// the position set P of a reference for one q, sorted by q-gram.  Two
+// layouts: keys ((p << 1 | strand) << 2q) | q-gram with a 16-bit context
+// each (ctx), or, when (p << 1 | strand) fits in 54 - 2q bits, one packed
+// word per entry and ctx == nullptr: (p << 1 | strand) << (2q + 10) | the
+// letters after (8 bits) << (2q + 2) | the letter before << 2q | q-gram.
+// In the packed form whether there is a letter before (p >= 1) and how many
+// letters follow (min(L - q - p, 4)) come from p, on both strands.
 struct RefQDev {
-    const unsigned long long *keys;  // ((p << 1 | strand) << 2q) | q-gram
-    const uint16_t *ctx;             // letters around each entry's q-gram
-    uint64_t n;                      // 2 (L - q + 1)
+    const unsigned long long *keys;
+    const uint16_t *ctx;
+    uint64_t n;  // 2 (L - q + 1)
 };
+inline bool refq_packs(uint64_t L, int q) {
+    int bits = 0;
+    for (uint64_t v = 2 * L; v > 1; v >>= 1) bits++;  // (p << 1 | strand) < 2L
+    return bits + 1 <= 54 - 2 * q;
+}
 void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipStream_t st);
-void launch_refq_ctx(const PnRefDev &ref, int q, const unsigned long long *keys, uint64_t n,
+// the contexts of the sorted keys: into ctx, or (ctx == nullptr) into the
+// keys themselves in the packed layout
+void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st);
 // the occurrence lists k_filter set aside (FilterOut::heavy)
 void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,

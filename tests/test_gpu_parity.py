@@ -233,6 +233,33 @@ def test_map_repeat_small(pn, sess):
     map_both(pn, sess, synth.make("repeat", scale=0.01))
 
 
+def test_position_set_layouts_agree(pn, sess):
+    """The reference's position set is packed into one word per entry when
+    (position, strand) fits beside the q-gram and its letters (at q = 12 up
+    to 2^29 bases, at q = 15 up to 2^23); a 10 Mbp reference at q = 15 takes
+    the two-array layout.  Both layouts must give the hits the lossless
+    filter gives at any admissible q (here q = 12, packed, also checked
+    against the oracle on a read sample)."""
+    w = synth.make("repeat", scale=0.1, n_reads=20000)
+    ref = sess.ref(w.ref)
+    say(f"layouts: L={len(w.ref)} n_reads={w.n_reads}")
+    hits = {}
+    for q in (12, 15):
+        idx = sess.index(w.reads, w.offsets, q)
+        hits[q] = pn.pn_map(sess.ctx, ref, idx, 5, 0)
+    assert len(hits[12]) > 1000
+    assert_hits_equal(hits[15], hits[12])
+    sample = np.arange(0, w.n_reads, 40)
+    sub = w.subset(sample)
+    o = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, 5, best=False)
+    g = fields(hits[12])
+    keep = np.isin(g[:, 0], sample)
+    remap = np.searchsorted(sample, g[keep, 0])
+    gs = g[keep].copy()
+    gs[:, 0] = remap
+    assert np.array_equal(gs, fields(o))
+
+
 def test_map_mixed_lengths(pn, sess):
     map_both(pn, sess, synth.make("mixed", scale=0.002))
 

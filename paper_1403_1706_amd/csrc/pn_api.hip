@@ -60,7 +60,7 @@ struct pn_ctx {
     // capacities per output region (pn::kShards regions; grow on demand)
     uint64_t cand_rcap = 1ull << 18;
     uint64_t rec_rcap = 1ull << 14;
-    uint64_t heavy_rcap = 1ull << 12;  // filter entries set aside for a block each
+    uint64_t heavy_rcap = 1ull << 12;  // per region: items of occurrence lists set aside
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -549,7 +549,6 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     const uint64_t T = x->n_qgrams, U = x->n_slots;
     uint32_t *nq = nullptr, *partials = nullptr, *lcs = nullptr;
     uint8_t *flags = nullptr;
-    uint16_t *rlen = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;
     s = dalloc_t(c, 2 * (uint64_t)n_reads * PN_READ_WORDS + 1, &x->rplanes);
@@ -560,7 +559,6 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &x->lcinfo);
     if (!s) s = dalloc_t(c, pn::kLcPatterns, &lcs);
     if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &nq);
-    if (!s) s = dalloc_t(c, (uint64_t)n_reads + 1, &rlen);
     if (!s) s = dalloc_t(c, T + 1, &keys);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
     if (!s) s = dalloc_t(c, T + 1, &flags);
@@ -578,7 +576,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         stage_end(c, st, tok, 2);
         tok = stage_begin(c, st, PN_STAGE_INDEX);
         // q-gram occurrences -> keys at their read's offset in O
-        pn::launch_read_nq(ix, nq, rlen, st);
+        pn::launch_read_nq(ix, nq, st);
         pn::launch_scan_u32(nq, nq, n_reads, partials, st);
         pn::launch_qgram_keys(ix, nq, keys, st);
         const unsigned long long *sorted =
@@ -603,7 +601,6 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         }
     }
     dfree(c, nq);
-    dfree(c, rlen);
     dfree(c, keys);
     dfree(c, tmp);
     dfree(c, flags);

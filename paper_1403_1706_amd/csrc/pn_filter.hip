@@ -4,8 +4,9 @@
 // the forward q-gram at u) and is sorted by q-gram, as the paper prepares
 // it with its reference index: neighbouring lanes then probe the same
 // parts of I, S, S' and O.  P is built once per reference and q
-// (k_refq_keys, a radix sort, k_refq_ctx), with a 16-bit context per entry:
-// the letter before the q-gram and up to four letters after it.  For every
+// (k_refq_keys, a radix sort, k_refq_ctx), with each entry's context: the
+// letter before the q-gram and up to four letters after it (packed into the
+// entry's word when there is room, else a 16-bit word beside it).  For every
 // entry the occurrences of its q-gram are O[k_start .. k_end) (INDEXPAIR);
 // each occurrence (read r, offset o) that passes the rules below becomes a
 // candidate (r, strand, diagonal d = p - o).
@@ -242,7 +243,7 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
                                               const pn::FilterOut &out,
                                               unsigned long long &set_aside) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
-    // the longest ranges wait for k_filter_heavy (a block each)
+    // the longest ranges wait for k_filter_heavy (a wave per item)
     const bool heavy = valid && len > out.heavy_min;
     // a set-aside entry becomes one item per kItem occurrences (a wave walks
     // an item), so that no single item is long

@@ -66,21 +66,20 @@ __device__ __forceinline__ void after_decode(uint32_t c, uint32_t &next4, uint32
     }
 }
 
-// q-gram starts per read (n_r - q + 1, or 0) and read lengths (<= 256)
-__global__ void k_read_nq(PnIndexDev ix, uint32_t *nq, uint16_t *len) {
+// q-gram starts per read (n_r - q + 1, or 0)
+__global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ix.n_reads) return;
     const uint64_t n = ix.offsets[r + 1] - ix.offsets[r];
     nq[r] = n >= (uint64_t)ix.q ? (uint32_t)(n - ix.q + 1) : 0u;
-    len[r] = (uint16_t)n;
 }
 
-// key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (class << 2q) | g;
-// with kCarry (q <= 12, where 8 bits are left) the four letters after the
-// q-gram sit between (r, o) and the class: ((r << 8 | o) << (2q + 11)) |
-// (next4 << (2q + 3)) | (class << 2q) | g.  Sorting looks at the low 2q
-// bits (the q-gram) only, so each slice keeps the order (read, offset).  One wave per read: lane l takes offsets l, l + 64, ..., so a
-// wave reads one stretch of the packed reads and writes one stretch of keys.
+// Key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (class << 2q) | g;
+// with kCarry (q <= 12) the key holds all an O entry needs:
+// ((r << 8 | o) << (2q + 11)) | (after_code(next4, nav) << (2q + 2)) |
+// (letter before << 2q) | g, the letter before being "none" exactly at
+// o = 0.  Sorting looks at the low 2q bits (the q-gram) only, so each slice
+// keeps the order (read, offset).
 // The keys of a read's q-gram occurrences, at the read's offset in the key
 // array (see the header).  A wave takes reads gw, gw + nw, ...; lane l
 // holds word l of the read's packed text (a read touches at most 18 words),
@@ -353,9 +352,9 @@ inline unsigned grid_for(uint64_t n, unsigned threads) {
 
 namespace pn {
 
-void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream_t st) {
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st) {
     if (!ix.n_reads) return;
-    hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq, len);
+    hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq);
 }
 
 void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,

@@ -165,7 +165,7 @@ void launch_scan_popc(const void *I, int log2w, uint32_t *out, uint64_t n, uint3
 uint64_t scan_partials_size(uint64_t n);
 
 // pn_index.hip (Algorithm 1)
-void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, uint16_t *len, hipStream_t st);
+void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st);
 // index keys hold the four letters after each q-gram and their count when
 // there is room: 2q bits of q-gram, 2 of the letter before, 9 of the
 // letters after (with their count), 29 of read and offset <= 64

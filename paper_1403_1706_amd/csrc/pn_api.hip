@@ -547,7 +547,10 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     x->n_qgrams = c->hmisc[kStatT];
     x->n_slots = std::min<uint64_t>(G, x->n_qgrams);
     const uint64_t T = x->n_qgrams, U = x->n_slots;
-    uint32_t *nq = nullptr, *partials = nullptr, *lcs = nullptr;
+    uint32_t *nq = nullptr, *partials = nullptr, *lcs = nullptr, *first_read = nullptr,
+             *hist0 = nullptr;
+    const uint64_t tile = pn::radix_tile_keys(T);
+    const uint64_t tiles = (T + tile - 1) / tile;
     uint8_t *flags = nullptr;
     unsigned long long *keys = nullptr, *tmp = nullptr;
     void *sort_temp = nullptr;
@@ -562,6 +565,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     if (!s) s = dalloc_t(c, T + 1, &keys);
     if (!s) s = dalloc_t(c, T + 1, &tmp);
     if (!s) s = dalloc_t(c, T + 1, &flags);
+    if (!s) s = dalloc_t(c, tiles + 1, &first_read);
+    if (!s) s = dalloc_t(c, 256 * tiles + 1, &hist0);
     if (!s) s = dalloc(c, pn::radix_temp_size(T), &sort_temp);
     if (!s)
         s = dalloc_t(c,
@@ -578,9 +583,9 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         // q-gram occurrences -> keys at their read's offset in O
         pn::launch_read_nq(ix, nq, st);
         pn::launch_scan_u32(nq, nq, n_reads, partials, st);
-        pn::launch_qgram_keys(ix, nq, keys, st);
+        pn::launch_qgram_keys(ix, nq, T, tile, first_read, keys, hist0, st);
         const unsigned long long *sorted =
-            pn::radix_sort_u64_any(keys, tmp, T, 2 * q, sort_temp, st);
+            pn::radix_sort_u64_any(keys, tmp, T, 2 * q, sort_temp, st, 0, hist0);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
         pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
@@ -604,6 +609,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
     dfree(c, keys);
     dfree(c, tmp);
     dfree(c, flags);
+    dfree(c, first_read);
+    dfree(c, hist0);
     dfree(c, sort_temp);
     dfree(c, partials);
     dfree(c, lcs);

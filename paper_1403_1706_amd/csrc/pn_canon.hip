@@ -287,8 +287,10 @@ __global__ void k_keys_to_cands(const unsigned long long *keys, uint64_t n, uint
 
 namespace pn {
 
+uint64_t radix_tile_keys(uint64_t n) { return (uint64_t)radix_threads(n) * kRadixItems; }
+
 static uint64_t tiles_for(uint64_t n) {
-    const uint64_t tile = (uint64_t)radix_threads(n) * kRadixItems;
+    const uint64_t tile = radix_tile_keys(n);
     return (n + tile - 1) / tile;
 }
 
@@ -299,7 +301,8 @@ uint64_t radix_temp_size(uint64_t n) {
 }
 
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
-                                       uint64_t n, int bits, void *temp, hipStream_t st, int lo) {
+                                       uint64_t n, int bits, void *temp, hipStream_t st, int lo,
+                                       const uint32_t *hist0) {
     if (n <= 1 || bits <= 0) return keys;
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
@@ -314,23 +317,25 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const int shift = lo + 8 * p;
         // the last digit may be narrower: bits above `bits` do not take part
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
-        if (radix_threads(n) == kThrLarge)
+        // the first pass may come with its histogram (made with the keys)
+        const bool given = p == 0 && hist0 != nullptr && lo == 0;
+        const uint32_t *hp = given ? hist0 : hist;
+        if (!given && radix_threads(n) == kThrLarge)
             hipLaunchKernelGGL(k_radix_hist<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,
                                src, n, shift, dmask, hist, nt);
-        else
+        else if (!given)
             hipLaunchKernelGGL(k_radix_hist<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0, st,
                                src, n, shift, dmask, hist, nt);
-        hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
-                           per, colsum);
+        hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, hp, nt, per, colsum);
         hipLaunchKernelGGL(k_col_top, dim3(256), dim3(256), 0, st, colsum, groups, dtot);
-        hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, (const uint32_t *)hist, nt,
-                           per, (const uint32_t *)colsum, (const uint32_t *)dtot, offs);
+        hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, hp, nt, per,
+                           (const uint32_t *)colsum, (const uint32_t *)dtot, offs);
         if (radix_threads(n) == kThrLarge)
             hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0,
-                               st, src, dst, n, shift, dmask, offs, hist, nt);
+                               st, src, dst, n, shift, dmask, offs, hp, nt);
         else
             hipLaunchKernelGGL(k_radix_scatter<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0,
-                               st, src, dst, n, shift, dmask, offs, hist, nt);
+                               st, src, dst, n, shift, dmask, offs, hp, nt);
         unsigned long long *t = src;
         src = dst;
         dst = t;

@@ -85,34 +85,61 @@ __global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
 // holds word l of the read's packed text (a read touches at most 18 words),
 // and every window a key needs is put together from two lanes' words, so a
 // read costs one coalesced load, issued one read ahead of its use.
+// for each tile of `tile` keys, the read its first key belongs to (a thread
+// per read: the tiles whose first key lies in the read's key range)
+__global__ void k_tile_first_read(const uint32_t *__restrict__ qoff, uint32_t n_reads,
+                                  uint64_t tile, uint32_t *first_read) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_reads) return;
+    const uint64_t a = qoff[r], e = qoff[r + 1];
+    for (uint64_t t = (a + tile - 1) / tile; t * tile < e; t++) first_read[t] = r;
+}
+
+// The keys of the q-gram occurrences, a block per tile of `tile` keys
+// (the radix sort's tiles): the block writes keys [b * tile, (b+1) * tile)
+// and counts their lowest 8 bits, the first digit of the sort, so that the
+// sort's first pass needs no histogram pass of its own (hist0[b][d]).  Wave
+// w takes the block's reads first + w, first + w + 4, ...; lane l holds word
+// l of a read's packed text (a read touches at most 18 words), and every
+// window a key needs is put together from two lanes' words, so a read costs
+// one coalesced load, issued one read ahead of its use.  A read that
+// straddles two tiles is taken by both blocks, each writing its own part.
 template <bool kCarry>
 __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                                                     const uint32_t *__restrict__ qoff,
-                                                    unsigned long long *__restrict__ keys) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t gw = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const uint32_t nw = (uint32_t)(((uint64_t)gridDim.x * blockDim.x) >> 6);
+                                                    const uint32_t *__restrict__ first_read,
+                                                    uint64_t T, uint64_t tile,
+                                                    unsigned long long *__restrict__ keys,
+                                                    uint32_t *__restrict__ hist0) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t K0 = (uint64_t)blockIdx.x * tile, K1 = min(T, K0 + tile);
+    const uint32_t first = first_read[blockIdx.x];
     const int q = ix.q;
     const int sh = 2 * q + 3;
     struct Read {
         uint64_t off, n, base;
         uint32_t word;  // this lane's word of the read's packed text
     };
+    // a read whose keys start before K1 (else n = 0 and base = K1)
     auto fetch = [&](uint32_t r) {
-        Read d{0, 0, 0, 0u};
+        Read d{0, 0, K1, 0u};
         if (r < ix.n_reads) {
-            d.off = ix.offsets[r];
-            d.n = ix.offsets[r + 1] - d.off;
             d.base = qoff[r];
-            // words of letters [off, off + n) and the one after them
-            const uint32_t words = (uint32_t)(((d.off & 15) + d.n + 15) >> 4) + 1;
-            if (lane < words) d.word = ix.packed[(d.off >> 4) + lane];
+            if (d.base < K1) {
+                d.off = ix.offsets[r];
+                d.n = ix.offsets[r + 1] - d.off;
+                const uint32_t words = (uint32_t)(((d.off & 15) + d.n + 15) >> 4) + 1;
+                if (lane < words) d.word = ix.packed[(d.off >> 4) + lane];
+            }
         }
         return d;
     };
-    Read cur = fetch(gw);
-    for (uint32_t r = gw; r < ix.n_reads; r += nw) {
-        const Read nxt = fetch(r + nw);
+    Read cur = fetch(first + wave);
+    for (uint32_t r = first + wave; cur.base < K1; r += 4) {
+        const Read nxt = fetch(r + 4);
         if (cur.n >= (uint64_t)q) {
             const uint32_t nq = (uint32_t)(cur.n - q + 1);
             const uint64_t w0 = cur.off >> 4;
@@ -126,7 +153,8 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
             };
             for (uint32_t o0 = 0; o0 < nq; o0 += 64) {
                 const uint32_t o = o0 + lane;
-                // every lane takes part in the shuffles; lanes past nq store nothing
+                // every lane takes part in the shuffles; lanes outside the
+                // read or the tile store nothing
                 const uint32_t wq = window(cur.off + (o ? o - 1 : 0));
                 const uint32_t w4 = window(cur.off + o + q);
                 uint32_t cls, g;
@@ -151,11 +179,17 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                     key = ((unsigned long long)((r << 8) | o) << sh) |
                           ((unsigned long long)cls << (2 * q)) | g;
                 }
-                if (o < nq) keys[cur.base + o] = key;
+                const uint64_t pos = cur.base + o;
+                if (o < nq && pos >= K0 && pos < K1) {
+                    keys[pos] = key;
+                    atomicAdd(&h[g & 255u], 1u);
+                }
             }
         }
         cur = nxt;
     }
+    __syncthreads();
+    hist0[(uint64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
 // O entries from the sorted keys, group starts, and the presence bitmap I.
@@ -357,17 +391,19 @@ void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st) {
     hipLaunchKernelGGL(k_read_nq, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, ix, nq);
 }
 
-void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
+void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, uint64_t T, uint64_t tile,
+                       uint32_t *first_read, unsigned long long *keys, uint32_t *hist0,
                        hipStream_t st) {
-    if (!ix.n_reads) return;
-    // waves: enough to fill the chip several times, each taking many reads
-    const uint64_t threads = std::min<uint64_t>((uint64_t)ix.n_reads * 64, 65536ull * 64);
+    if (!ix.n_reads || !T) return;
+    const uint64_t tiles = (T + tile - 1) / tile;
+    hipLaunchKernelGGL(k_tile_first_read, dim3(grid_for(ix.n_reads, 256)), dim3(256), 0, st, qoff,
+                       ix.n_reads, tile, first_read);
     if (index_key_carries(ix.q))
-        hipLaunchKernelGGL(k_qgram_keys<true>, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix,
-                           qoff, keys);
+        hipLaunchKernelGGL(k_qgram_keys<true>, dim3((unsigned)tiles), dim3(256), 0, st, ix, qoff,
+                           (const uint32_t *)first_read, T, tile, keys, hist0);
     else
-        hipLaunchKernelGGL(k_qgram_keys<false>, dim3(grid_for(threads, 256)), dim3(256), 0, st, ix,
-                           qoff, keys);
+        hipLaunchKernelGGL(k_qgram_keys<false>, dim3((unsigned)tiles), dim3(256), 0, st, ix, qoff,
+                           (const uint32_t *)first_read, T, tile, keys, hist0);
 }
 
 void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *keys, uint64_t T,

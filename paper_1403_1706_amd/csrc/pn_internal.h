@@ -171,7 +171,12 @@ void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st);
 // letters after (with their count), 29 of read and offset <= 64
 // (otherwise: 2q + 3 bits, the letter before or "none", then read and offset)
 inline bool index_key_carries(int q) { return 2 * q + 2 + 9 + 29 <= 64; }
-void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, unsigned long long *keys,
+// keys of all T occurrences (qoff: exclusive prefix of the reads' q-gram
+// counts, qoff[n_reads] = T), with hist0 (tile-major, 256 words per tile of
+// `tile` keys) the counts of their lowest 8 bits; first_read: one word per
+// tile (scratch)
+void launch_qgram_keys(const PnIndexDev &ix, const uint32_t *qoff, uint64_t T, uint64_t tile,
+                       uint32_t *first_read, unsigned long long *keys, uint32_t *hist0,
                        hipStream_t st);
 // O, group-start flags and I (zeroed by the caller) from keys sorted by
 // their low 2q bits
@@ -295,9 +300,12 @@ void launch_gather_shards(const unsigned long long *src, const unsigned long lon
 uint64_t radix_temp_size(uint64_t n);  // bytes
 // stable sort by bits [lo, bits) of the keys; the result is in the
 // returned buffer (keys or tmp)
+// (hist0: if given, the first pass's per-tile counts of the lowest 8 bits,
+// hist0[tile][digit] over tiles of radix_tile_keys(n) keys)
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
                                        uint64_t n, int bits, void *temp, hipStream_t st,
-                                       int lo = 0);
+                                       int lo = 0, const uint32_t *hist0 = nullptr);
+uint64_t radix_tile_keys(uint64_t n);
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
                     void *temp, hipStream_t st, int lo = 0);
 void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,

@@ -270,7 +270,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-            "(the path shards by reads with no exchange, see DESIGN.md)")
+            "(several GPUs would each map their own share of the reads against a "
+            "resident copy of the reference, with no exchange between them)")
         sys.exit(2)
 
     if args.batching:

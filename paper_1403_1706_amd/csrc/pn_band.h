@@ -36,7 +36,8 @@ __host__ __device__ __forceinline__ void pn_band_load(const uint4 *__restrict__ 
     h.rw0 = rp[0];
 }
 
-template <typename Emit>
+// kLast = false: the caller knows that len > row_cap, so no row is the last
+template <bool kLast = true, typename Emit>
 __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
                                                     const uint4 *__restrict__ pl,
                                                     const uint2 *__restrict__ rp, int len, int k,
@@ -84,7 +85,7 @@ __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
             HN <<= 1;
             VP = HN | ~(Xv | HP);
             VN = HP & Xv;
-            if (i == len) {
+            if (kLast && i == len) {
                 // last row: cell b holds R minus the differences to its right
                 int v = i + k - Ck;
                 for (int b = W - 1; b >= 0; b--) {

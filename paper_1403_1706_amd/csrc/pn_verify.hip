@@ -168,15 +168,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
         start(ref, ix, kglob, kpr, out.ebits, c_after, kFirst, nxt);
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
+        // first pass: a wave whose reads are all longer than the row cap
+        // never reaches a last row (wave-uniform)
+        const bool capped = kFirst && __all(!cur.ok || cur.len > kShortRows);
         if (cur.ok) {
             const unsigned long long head = cur.head;
             const bool tail = kFirst && cur.tail;
-            const int rw = pn_band_run(
-                cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
-                kFirst ? kShortRows : PN_MAX_READ_LEN, [&](uint32_t e, int v) {
-                    if (!tail)
-                        rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
-                });
+            auto emit = [&](uint32_t e, int v) {
+                if (!tail) rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
+            };
+            const int rw =
+                capped ? pn_band_run<false>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
+                                            kShortRows, emit)
+                       : pn_band_run(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
+                                     kFirst ? kShortRows : PN_MAX_READ_LEN, emit);
             // survivors (and tail checks that reached the read's first
             // letter) run again, forward, from row 0
             if (kFirst && (rw < 0 || (tail && rw == cur.len)))

@@ -36,79 +36,108 @@ __host__ __device__ __forceinline__ void pn_band_load(const uint4 *__restrict__ 
     h.rw0 = rp[0];
 }
 
-// kLast = false: the caller knows that len > row_cap, so no row is the last
+// The band's state between rows: the candidate's stream of plane words
+// (word m covers reference positions [lo + 32m, lo + 32m + 32); h0/l0/v0 the
+// current word, h1/l1/v1 the next), the row's differences VP/VN and the count
+// Ck of the right-most cell (see below).
+struct PnBandState {
+    uint32_t h0, l0, v0, h1, l1, v1;
+    uint32_t VP, VN;
+    int Ck;
+};
+
+// Rows 32m+1 .. 32m+32 (read plane word rw).  Returns 0 to go on with the
+// next word, else the value pn_band_run returns.  kLast = false: no row of
+// this word is the read's last (the caller knows len > 32m + 32).
+template <bool kLast, typename Emit>
+__host__ __device__ __forceinline__ int pn_band_word(PnBandState &s, uint2 rw, int m, int len,
+                                                     int k, int64_t lo, uint64_t L, int row_cap,
+                                                     Emit &emit) {
+    const int W = 2 * k + 1;
+    const uint32_t M = (1u << W) - 1u;
+    const uint32_t M2 = M & ~1u;
+    const uint32_t TOP = 1u << (W - 1);
+#pragma unroll
+    for (int t = 0; t < 32; t++) {
+        const int i = 32 * m + t + 1;  // row i compares read letter i-1
+        const uint32_t H = pn_funnel(s.h1, s.h0, t), Lw = pn_funnel(s.l1, s.l0, t),
+                       V = pn_funnel(s.v1, s.v0, t);
+        // all ones where read letter i-1 has a 1 bit (a sign-extended bit field)
+        const uint32_t xh = (uint32_t)((int32_t)(rw.x << (31 - t)) >> 31),
+                       xl = (uint32_t)((int32_t)(rw.y << (31 - t)) >> 31);
+        const uint32_t Eq = ~((H ^ xh) | (Lw ^ xl)) & V & M;
+        uint32_t VP = (s.VP >> 1) | TOP;  // previous row's differences, moved into this row's frame
+        uint32_t VN = s.VN >> 1;
+        const uint32_t Xv = Eq | VN;
+        const uint32_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
+        uint32_t HP = VN | ~(Xh | VP);
+        uint32_t HN = VP & Xh;
+        s.Ck += (int)((HN >> (W - 1)) & 1u);
+        HP = (HP << 1) | 1u;
+        HN <<= 1;
+        s.VP = VP = HN | ~(Xv | HP);
+        s.VN = VN = HP & Xv;
+        if (kLast && i == len) {
+            // last row: cell b holds R minus the differences to its right
+            int v = i + k - s.Ck;
+            for (int b = W - 1; b >= 0; b--) {
+                const int64_t c = (int64_t)len + lo + b;
+                if (c >= 1 && c <= (int64_t)L && v <= k) emit((uint32_t)(c - 1), v);
+                v -= (int)((VP >> b) & 1u) - (int)((VN >> b) & 1u);
+            }
+            return i;
+        }
+        // stop when the whole row is above k: R minus the +1 steps bounds
+        // the row minimum from below (R - popcount > k), written as one
+        // accumulating bit count and a compare
+        if (__builtin_popcount(VP & M2) + s.Ck < i) return i;
+        if ((t & 7) == 7 && t != 31 && i == row_cap) return -i;  // a cap inside a word
+    }
+    return 0;
+}
+
+// kLast = false: the caller knows that len > row_cap, so no row is the last.
+// no_end: no row below it is the read's last (a bound the caller may know
+// for a whole wave; words entirely below it skip the last-row test).
 template <bool kLast = true, typename Emit>
 __host__ __device__ __forceinline__ int pn_band_run(const PnBandHead &hd,
                                                     const uint4 *__restrict__ pl,
                                                     const uint2 *__restrict__ rp, int len, int k,
                                                     int64_t lo, uint64_t L, int row_cap,
-                                                    Emit &&emit) {
-    const int W = 2 * k + 1;
-    const uint32_t M = (1u << W) - 1u;
-    const uint32_t M2 = M & ~1u;
-    const uint32_t TOP = 1u << (W - 1);
-    // the candidate's own stream of plane words: stream word m covers
-    // reference positions [lo + 32m, lo + 32m + 32)
+                                                    Emit &&emit, int no_end = 0) {
     const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
     const uint64_t blk = tp >> 5;
     const uint32_t ph = (uint32_t)(tp & 31);
     const uint4 A = hd.A, B = hd.B;
     uint4 C = hd.C, Dn = hd.Dn;
-    uint32_t h0 = pn_funnel(B.x, A.x, ph), l0 = pn_funnel(B.y, A.y, ph), v0 = pn_funnel(B.z, A.z, ph);
-    uint32_t h1 = pn_funnel(C.x, B.x, ph), l1 = pn_funnel(C.y, B.y, ph), v1 = pn_funnel(C.z, B.z, ph);
-    uint32_t VP = 0, VN = 0;  // row 0: every band cell is 0 (free start)
+    PnBandState s;
+    s.h0 = pn_funnel(B.x, A.x, ph);
+    s.l0 = pn_funnel(B.y, A.y, ph);
+    s.v0 = pn_funnel(B.z, A.z, ph);
+    s.h1 = pn_funnel(C.x, B.x, ph);
+    s.l1 = pn_funnel(C.y, B.y, ph);
+    s.v1 = pn_funnel(C.z, B.z, ph);
+    s.VP = s.VN = 0;  // row 0: every band cell is 0 (free start)
     // The right-most band cell of row i holds R = i - (number of rows whose
     // step left it unchanged, i.e. moved a -1 difference out of the band's
     // top bit); Ck counts those rows plus k, so that R = i + k - Ck.
-    int Ck = k;
+    s.Ck = k;
     uint2 rw_next = hd.rw0;  // the read's plane word for the next 32 rows, loaded a word ahead
     for (int m = 0;; m++) {
         const uint2 rw = rw_next;
         if (32 * (m + 1) < len && 32 * (m + 1) < row_cap) rw_next = rp[m + 1];
-#pragma unroll
-        for (int t = 0; t < 32; t++) {
-            const int i = 32 * m + t + 1;  // row i compares read letter i-1
-            const uint32_t H = pn_funnel(h1, h0, t), Lw = pn_funnel(l1, l0, t),
-                           V = pn_funnel(v1, v0, t);
-            // all ones where read letter i-1 has a 1 bit (a sign-extended bit field)
-            const uint32_t xh = (uint32_t)((int32_t)(rw.x << (31 - t)) >> 31),
-                           xl = (uint32_t)((int32_t)(rw.y << (31 - t)) >> 31);
-            const uint32_t Eq = ~((H ^ xh) | (Lw ^ xl)) & V & M;
-            VP = (VP >> 1) | TOP;  // previous row's differences, moved into this row's frame
-            VN >>= 1;
-            const uint32_t Xv = Eq | VN;
-            const uint32_t Xh = (((Eq & VP) + VP) ^ VP) | Eq;
-            uint32_t HP = VN | ~(Xh | VP);
-            uint32_t HN = VP & Xh;
-            Ck += (int)((HN >> (W - 1)) & 1u);
-            HP = (HP << 1) | 1u;
-            HN <<= 1;
-            VP = HN | ~(Xv | HP);
-            VN = HP & Xv;
-            if (kLast && i == len) {
-                // last row: cell b holds R minus the differences to its right
-                int v = i + k - Ck;
-                for (int b = W - 1; b >= 0; b--) {
-                    const int64_t c = (int64_t)len + lo + b;
-                    if (c >= 1 && c <= (int64_t)L && v <= k) emit((uint32_t)(c - 1), v);
-                    v -= (int)((VP >> b) & 1u) - (int)((VN >> b) & 1u);
-                }
-                return i;
-            }
-            // stop when the whole row is above k: R minus the +1 steps bounds
-            // the row minimum from below (R - popcount > k), written as one
-            // accumulating bit count and a compare
-            if (__builtin_popcount(VP & M2) + Ck < i) return i;
-            if ((t & 7) == 7 && t != 31 && i == row_cap) return -i;  // a cap inside a word
-        }
+        const int r = !kLast || 32 * (m + 1) < no_end
+                          ? pn_band_word<false>(s, rw, m, len, k, lo, L, row_cap, emit)
+                          : pn_band_word<kLast>(s, rw, m, len, k, lo, L, row_cap, emit);
+        if (r) return r;
         if (32 * (m + 1) >= row_cap) return -32 * (m + 1);
         // advance the stream by 32 positions
-        h0 = h1;
-        l0 = l1;
-        v0 = v1;
-        h1 = pn_funnel(Dn.x, C.x, ph);
-        l1 = pn_funnel(Dn.y, C.y, ph);
-        v1 = pn_funnel(Dn.z, C.z, ph);
+        s.h0 = s.h1;
+        s.l0 = s.l1;
+        s.v0 = s.v1;
+        s.h1 = pn_funnel(Dn.x, C.x, ph);
+        s.l1 = pn_funnel(Dn.y, C.y, ph);
+        s.v1 = pn_funnel(Dn.z, C.z, ph);
         C = Dn;
         Dn = pl[blk + m + 4];
     }

@@ -169,8 +169,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
         // first pass: a wave whose reads are all longer than the row cap
-        // never reaches a last row (wave-uniform)
+        // never reaches a last row (wave-uniform); second pass: no row below
+        // the wave's shortest read is a last row
         const bool capped = kFirst && __all(!cur.ok || cur.len > kShortRows);
+        int no_end = 0;
+        if (!kFirst) {
+            no_end = cur.ok ? cur.len : PN_MAX_READ_LEN + 1;
+            for (int o = 32; o > 0; o >>= 1) no_end = min(no_end, __shfl_xor(no_end, o));
+            no_end = __builtin_amdgcn_readfirstlane(no_end);
+        }
         if (cur.ok) {
             const unsigned long long head = cur.head;
             const bool tail = kFirst && cur.tail;
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
                 capped ? pn_band_run<false>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
                                             kShortRows, emit)
                        : pn_band_run(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
-                                     kFirst ? kShortRows : PN_MAX_READ_LEN, emit);
+                                     kFirst ? kShortRows : PN_MAX_READ_LEN, emit, no_end);
             // survivors (and tail checks that reached the read's first
             // letter) run again, forward, from row 0
             if (kFirst && (rw < 0 || (tail && rw == cur.len)))

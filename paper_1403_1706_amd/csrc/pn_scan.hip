@@ -68,15 +68,29 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(Load load, uint64_t n,
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// one block: exclusive scan of partials[0..nb) in place, total to partials[nb]
+// one block: exclusive scan of partials[0..nb) in place, total to partials[nb];
+// each thread takes kTopItems consecutive values per round, so a round
+// covers 8192 tile sums (each thread reads and writes only its own)
+constexpr int kTopItems = 32;
+
 __global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t *partials, uint64_t nb) {
     uint32_t carry = 0;
-    for (uint64_t base = 0; base < nb; base += kThreads) {
-        uint64_t i = base + threadIdx.x;
-        uint32_t x = i < nb ? partials[i] : 0u;
+    for (uint64_t base = 0; base < nb; base += (uint64_t)kThreads * kTopItems) {
+        const uint64_t i0 = base + (uint64_t)threadIdx.x * kTopItems;
+        uint32_t x[kTopItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kTopItems; j++) {
+            x[j] = i0 + j < nb ? partials[i0 + j] : 0u;
+            s += x[j];
+        }
         uint32_t total;
-        uint32_t ex = block_excl_scan(x, &total);
-        if (i < nb) partials[i] = carry + ex;
+        uint32_t run = carry + block_excl_scan(s, &total);
+#pragma unroll
+        for (int j = 0; j < kTopItems; j++) {
+            if (i0 + j < nb) partials[i0 + j] = run;
+            run += x[j];
+        }
         carry += total;
     }
     if (threadIdx.x == 0) partials[nb] = carry;

@@ -125,6 +125,37 @@ def test_index_arrays_match_definition(pn, sess, wbits, case):
     assert np.all(ro[1:][same] > ro[:-1][same])
 
 
+def test_index_large_scans_by_definition(pn, sess):
+    # 400k reads of 100 bp, q = 12: 3.56e7 occurrences, more tile sums than
+    # one round of the scans' top level takes, so that the carries between
+    # rounds are exercised.  Checked by what holds at any size (Algorithm 1):
+    # S is the exclusive scan of popcount(I); S' cuts O into slices, one per
+    # present q-gram in increasing order, each holding that q-gram only.
+    w = synth.make("tiny", n_reads=400_000)
+    q = 12
+    say(f"index large q={q} reads={w.n_reads}")
+    idx = sess.index(w.reads, w.offsets, q, 64)
+    I, S, Sp, O = pn.pn_index_export(idx)
+    T = len(O)
+    assert T == w.n_reads * (100 - q + 1) and T > 8192 * 4096
+    pc = np.bitwise_count(I).astype(np.int64)
+    assert np.array_equal(S.astype(np.int64), np.concatenate([[0], np.cumsum(pc)]))
+    Sp = Sp.astype(np.int64)
+    assert Sp[0] == 0 and Sp[-1] == T and np.all(np.diff(Sp) > 0)
+    assert len(Sp) - 1 == int(pc.sum())
+    _, r, o = decode_O(O)
+    codes = oracle.encode(w.reads).astype(np.int64)
+    pos = w.offsets[r].astype(np.int64) + o
+    g = np.zeros(T, np.int64)
+    for t in range(q):
+        g = (g << 2) | codes[pos + t]
+    first = g[Sp[:-1]]
+    assert np.all(np.diff(first) > 0)
+    assert np.array_equal(g, np.repeat(first, np.diff(Sp)))
+    present = np.nonzero(np.unpackbits(I.view(np.uint8), bitorder="little"))[0]
+    assert np.array_equal(present, first)
+
+
 def test_index_w32_equals_w64(pn, sess):
     w = synth.make("tiny", n_reads=2000)
     a = pn.pn_index_export(sess.index(w.reads, w.offsets, 10, 32))

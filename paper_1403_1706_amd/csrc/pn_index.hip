@@ -181,7 +181,8 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                 }
                 const uint64_t pos = cur.base + o;
                 if (o < nq && pos >= K0 && pos < K1) {
-                    keys[pos] = key;
+                    // streamed out (read back only by the sort's first scatter)
+                    __builtin_nontemporal_store(key, &keys[pos]);
                     atomicAdd(&h[g & 255u], 1u);
                 }
             }

@@ -16,7 +16,7 @@ plain array arithmetic:
   the occurrences of the j'-th occurring q-gram of group i start in O).
 * :func:`qgroup_size_words` and the size ratios of the same section.
 
-Parity status: every function here is pinned by ``tests/test_oracle_*.py``
+Parity status: every function here is pinned by ``tests/test_oracle.py``
 against values that do not come from the oracle itself (hand-worked
 examples, brute force over all substrings, the q-gram lemma, closed forms).
 The agreement of hit sets with the paper's own printed results is

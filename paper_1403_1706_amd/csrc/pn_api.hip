@@ -1097,7 +1097,11 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
     uint8_t *dk = nullptr;
     if (k < 0 && x->n_reads) {
         PN_CHECK(dalloc_t(c, x->n_reads, &dk));
-        PN_TRY(hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st));
+        hipError_t e = hipMemcpyAsync(dk, kpr, x->n_reads, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            dfree(c, dk);
+            return map_err(e);
+        }
     }
     int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
     if (!s) s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));

@@ -7,6 +7,7 @@
 // exclusive scan in (digit, tile) order done column by column, and a stable
 // scatter that ranks equal digits inside each wave with ballots.
 #include "pn_internal.h"
+#include "pn_radix.h"
 
 namespace {
 
@@ -65,45 +66,63 @@ __global__ __launch_bounds__(kThr) void k_radix_hist(const unsigned long long *k
 // offs[b][d] = sum of all counts of digits below d + counts of digit d in
 // tiles below b.  Three launches: column sums per group of tiles, a block
 // per digit scanning its column over the groups (and its total), then each
-// group's columns again with its carries and the digit base.
-constexpr int kScanGroups = 256;
+// group's columns again with its carries and the digit base.  Sums and
+// offsets are 64-bit (pn_radix.h).
+
+// exclusive scan of one 64-bit value per thread over a 256-thread block;
+// *total = block sum.  Every thread of the block must call it.
+__device__ __forceinline__ pn_roff block_excl_scan64(pn_roff x, pn_roff *total) {
+    __shared__ pn_roff ws[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    pn_roff inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const pn_roff y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) ws[wave] = inc;
+    __syncthreads();
+    pn_roff before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        before += w < wave ? ws[w] : (pn_roff)0;
+        all += ws[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
 
 __global__ __launch_bounds__(256) void k_col_sums(const uint32_t *__restrict__ hist,
                                                   uint64_t n_tiles, uint64_t per,
-                                                  uint32_t *colsum) {
+                                                  pn_roff *colsum) {
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min(n_tiles, b0 + per);
-    uint32_t acc = 0;
-#pragma unroll 8
-    for (uint64_t b = b0; b < b1; b++) acc += hist[b * 256 + threadIdx.x];
-    colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
+    colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] =
+        pn_radix_col_sum(hist, b0, b1, threadIdx.x);
 }
 
 // a block per digit d, a thread per group: colsum[g][d] -> the column's
 // sum over groups below g, dtot[d] -> the column's total
-__global__ __launch_bounds__(256) void k_col_top(uint32_t *colsum, uint32_t groups,
-                                                 uint32_t *dtot) {
+__global__ __launch_bounds__(256) void k_col_top(pn_roff *colsum, uint32_t groups,
+                                                 pn_roff *dtot) {
     const uint32_t d = blockIdx.x, g = threadIdx.x;
-    const uint32_t v = g < groups ? colsum[(uint64_t)g * 256 + d] : 0u;
-    uint32_t tot;
-    const uint32_t ex = pn_block_excl_scan(v, &tot);
+    const pn_roff v = g < groups ? colsum[(uint64_t)g * 256 + d] : (pn_roff)0;
+    pn_roff tot;
+    const pn_roff ex = block_excl_scan64(v, &tot);
     if (g < groups) colsum[(uint64_t)g * 256 + d] = ex;
     if (g == 0) dtot[d] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ hist,
                                                   uint64_t n_tiles, uint64_t per,
-                                                  const uint32_t *__restrict__ colsum,
-                                                  const uint32_t *__restrict__ dtot,
-                                                  uint32_t *offs) {
+                                                  const pn_roff *__restrict__ colsum,
+                                                  const pn_roff *__restrict__ dtot,
+                                                  pn_roff *offs) {
     const uint64_t b0 = (uint64_t)blockIdx.x * per, b1 = min(n_tiles, b0 + per);
-    uint32_t tot;
-    const uint32_t base = pn_block_excl_scan(dtot[threadIdx.x], &tot);  // digits below this one
-    uint32_t run = colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] + base;
-#pragma unroll 8
-    for (uint64_t b = b0; b < b1; b++) {
-        offs[b * 256 + threadIdx.x] = run;
-        run += hist[b * 256 + threadIdx.x];
-    }
+    pn_roff tot;
+    const pn_roff base = block_excl_scan64(dtot[threadIdx.x], &tot);  // digits below this one
+    pn_radix_col_down(hist, b0, b1, threadIdx.x,
+                      colsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] + base, offs);
 }
 
 // Stable scatter of one tile.  Wave w owns the tile's keys
@@ -117,7 +136,7 @@ template <int kThr>
 __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long *keys,
                                                         unsigned long long *out, uint64_t n,
                                                         int shift, uint32_t dmask,
-                                                        const uint32_t *offs,
+                                                        const pn_roff *offs,
                                                         const uint32_t *hist, uint64_t n_tiles) {
     constexpr int kItems = kRadixItems;
     constexpr int kTile = kThr * kItems;
@@ -125,7 +144,7 @@ __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long
     constexpr int kPerWave = kTile / kWaves;
     __shared__ unsigned long long tile[kTile];
     __shared__ uint32_t local[256];        // start of each digit inside the tile
-    __shared__ uint32_t goff[256];         // start of each digit's run in the output
+    __shared__ pn_roff goff[256];          // start of each digit's run in the output
     __shared__ uint32_t wcnt[kWaves][256];  // per wave: keys of each digit (then: before it)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -294,10 +313,13 @@ static uint64_t tiles_for(uint64_t n) {
     return (n + tile - 1) / tile;
 }
 
+// temp: counts (u32, 256 per tile), offsets (64-bit, 256 per tile), column
+// sums (64-bit, 256 per group), digit totals (64-bit, 256)
 uint64_t radix_temp_size(uint64_t n) {
     uint64_t nt = tiles_for(n) ? tiles_for(n) : 1;
-    uint64_t hist = 256 * nt + 1;
-    return (2 * hist + 256 * (uint64_t)kScanGroups + 256) * sizeof(uint32_t) + 256;
+    uint64_t hist = 256 * nt + 2;
+    return hist * sizeof(uint32_t) +
+           (hist + 256 * (uint64_t)PN_RADIX_GROUPS + 256) * sizeof(pn_roff) + 256;
 }
 
 unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
@@ -306,10 +328,10 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     if (n <= 1 || bits <= 0) return keys;
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
-    uint32_t *offs = hist + 256 * nt + 1;
-    uint32_t *colsum = offs + 256 * nt + 1;
-    uint32_t *dtot = colsum + 256 * (uint64_t)kScanGroups;
-    const uint64_t per = (nt + kScanGroups - 1) / kScanGroups;  // tiles per group
+    pn_roff *offs = (pn_roff *)(hist + 256 * nt + 2);  // (8-byte aligned: temp is)
+    pn_roff *colsum = offs + 256 * nt + 2;
+    pn_roff *dtot = colsum + 256 * (uint64_t)PN_RADIX_GROUPS;
+    const uint64_t per = pn_radix_tiles_per_group(nt);  // tiles per group
     const uint32_t groups = (uint32_t)((nt + per - 1) / per);
     unsigned long long *src = keys, *dst = tmp;
     const int passes = (bits - lo + 7) / 8;
@@ -329,13 +351,13 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, hp, nt, per, colsum);
         hipLaunchKernelGGL(k_col_top, dim3(256), dim3(256), 0, st, colsum, groups, dtot);
         hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, hp, nt, per,
-                           (const uint32_t *)colsum, (const uint32_t *)dtot, offs);
+                           (const pn_roff *)colsum, (const pn_roff *)dtot, offs);
         if (radix_threads(n) == kThrLarge)
             hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0,
-                               st, src, dst, n, shift, dmask, offs, hp, nt);
+                               st, src, dst, n, shift, dmask, (const pn_roff *)offs, hp, nt);
         else
             hipLaunchKernelGGL(k_radix_scatter<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0,
-                               st, src, dst, n, shift, dmask, offs, hp, nt);
+                               st, src, dst, n, shift, dmask, (const pn_roff *)offs, hp, nt);
         unsigned long long *t = src;
         src = dst;
         dst = t;

@@ -347,3 +347,46 @@ def test_banded_equals_brute_band_including_overhangs():
         d = int(rng.integers(-n - k, L + 2))
         got = oracle.banded(oracle.encode(text), oracle.encode(x), d, k)
         assert sorted(got) == band_brute(text, x, d, k), (text, x, d, k)
+
+
+def test_lemma_ok_equals_brute_force_over_error_placements():
+    """lemma_ok(n, k, q) says every placement of at most k errors leaves a
+    read q-gram intact.  Checked against brute force over every set of k
+    substituted offsets (an edit of any kind touches at most q consecutive
+    q-grams, and substitutions at chosen offsets touch exactly those that
+    contain them, so they are the worst case)."""
+    from itertools import combinations
+    for n in range(1, 15):
+        for q in range(1, 6):
+            for k in range(0, 4):
+                windows = [set(range(o, o + q)) for o in range(n - q + 1)]
+                if not windows:
+                    killed = True  # a read shorter than q has no q-gram at all
+                else:
+                    killed = any(all(w & set(S) for w in windows)
+                                 for S in combinations(range(n), min(k, n)))
+                assert bool(oracle.lemma_ok([n], [k], q)[0]) == (not killed), (n, q, k)
+
+
+def test_lemma_boundary_one_letter_short():
+    """n = 71, q = 12, k = 5, so (k+1) q = n + 1: substitutions at offsets 11,
+    23, ..., 59 destroy every 12-gram of the read.  The full DP still finds
+    the occurrence with 5 errors, but filtration emits no candidate near its
+    diagonal: the lemma's condition is needed, and map_filtered refuses."""
+    rng = np.random.default_rng(6)
+    ref = rand_dna(rng, 3000)
+    p = 1200
+    x = bytearray(ref[p:p + 71])
+    for o in (11, 23, 35, 47, 59):
+        x[o] = ord({"A": "C", "C": "G", "G": "T", "T": "A"}[chr(x[o])])
+    x = bytes(x)
+    offs = np.array([0, 71], np.uint64)
+    assert not oracle.lemma_ok([71], [5], 12)[0]
+    assert oracle.lemma_ok([72], [5], 12)[0]
+    full = as_tuples(oracle.map_sellers(ref, x, offs, 5))
+    assert (0, p + 70, 0, 5) in full
+    r, s, d = oracle.candidates(ref, x, offs, 12)
+    near = (s == 0) & (np.abs(d - p) <= 5)
+    assert not near.any()
+    with pytest.raises(ValueError):
+        oracle.map_filtered(ref, x, offs, 12, 5)

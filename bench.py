@@ -113,8 +113,8 @@ def serving_run(pn, ref, ref_ascii, q, args):
 
     batched = dict(slots=2, max_batch_reads=1 << 20, hbm_budget=16 << 30)
     serial_cfg = dict(slots=1, max_batch_reads=1, hbm_budget=16 << 30)
-    srv_b = pn.pn_server_create(ref, q, **batched)
-    srv_s = pn.pn_server_create(ref, q, **serial_cfg)
+    srv_b = pn.pn_server_create(ctx, ref, q, **batched)
+    srv_s = pn.pn_server_create(ctx, ref, q, **serial_cfg)
     try:
         run(srv_b, None)  # warm-up: workspaces grow to their working size
         run(srv_s, None)

@@ -90,7 +90,9 @@ typedef struct {
 
 /* Sizes of a built q-group index (Section 2.2): |I| = n_groups words of w
  * bits, S has n_groups + 1 entries, S' has n_distinct + 1 entries (D = the
- * number of distinct q-grams present), O has n_qgrams = |T| entries. */
+ * number of distinct q-grams present), O has n_qgrams = |T| entries.
+ * after_sorted: 1 when each slice of O is ordered by the letters after its
+ * q-gram first (see pn_index_export). */
 typedef struct {
     uint64_t n_reads;
     uint64_t n_bases;
@@ -100,7 +102,7 @@ typedef struct {
     int32_t q;
     int32_t w;
     int32_t max_len;
-    int32_t reserved;
+    int32_t after_sorted;
 } pn_index_info;
 
 /* Human-readable name of a status code; never NULL. */
@@ -205,8 +207,13 @@ int pn_index_get_info(const pn_index *idx, pn_index_info *out);
  * letter before the q-gram in its read (4 when o == 0); the low 32 bits are
  * (next4 << 24) | (nav << 21): the nav = min(4, n_r - o - q) letters after
  * the q-gram, first letter in the top bits (unused letters 0).  Inside each
- * q-gram's slice of O, entries are in the order (r, o).  Any pointer may be
- * NULL to skip that array. */
+ * q-gram's slice of O, entries are in the order (r, o).  For q <= 12, when
+ * at least 1/128 of all occurrences fall into slices of more than 32 (reads
+ * from repeat families), the slices are first ordered by the letters after
+ * the q-gram (the code next4 when nav = 4, else 256 + the three letters,
+ * 320 + two, 336 + one, 340 for none; pn_index_info.after_sorted = 1), so
+ * that filtration can find the entries whose next letters agree with the
+ * text by binary search.  Any pointer may be NULL to skip that array. */
 int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint64_t *O);
 
 /* ---- mapping ----------------------------------------------------------- */
@@ -279,6 +286,30 @@ int pn_autotune(pn_ctx *ctx, const pn_ref *ref, const char *d_reads, const uint6
                 pn_mode mode, uint32_t sample_reads, pn_tune_result *results, int *n_results,
                 int *best_q, int *best_w);
 
+/* Map a read set of any size (host memory, reads of mixed lengths with
+ * per-read k_per_read[r]) against both strands of `ref`.  The reads are
+ * taken in input order in sub-batches that each fit one q-group index
+ * (at most 2^21 reads, and about 48 bytes per base of the device memory
+ * free at the call, halved): the paper buffers reads and indexes each
+ * buffer on the device (Section 3.1).  Each sub-batch is copied to the
+ * device, indexed (Algorithm 1) and mapped as pn_map does; its hits come
+ * back and are appended with read ids relative to the whole set, so the
+ * result is sorted by (read_id, strand, end_pos) and equals pn_map's on one
+ * index of all the reads (per read, the hits do not depend on the batch).
+ * q and w: with tune_cache == NULL, w = 64 and the largest q <= 12 that the
+ * q-gram lemma admits for every read ((k_r + 1) q <= n_r, Section 2.2).
+ * Otherwise tune_cache names a text file of lines "<key> <q> <w>", the key
+ * describing the reference length, read count (power of two), length and
+ * k ranges and mode: a line for this key is used; without one, pn_autotune
+ * picks (q, w) on a sample of the first sub-batch and a line is appended
+ * (a cache that cannot be written is not an error).  PN_EINVAL for a read
+ * shorter than 1 or longer than 256, k_r > 15 or decreasing offsets;
+ * PN_ELEMMA if no q >= 1 satisfies the lemma; the hit array is freed with
+ * pn_hits_free. */
+int pn_map_batched(pn_ctx *ctx, const pn_ref *ref, const char *reads, const uint64_t *offsets,
+                   uint32_t n_reads, const uint8_t *k_per_read, pn_mode mode,
+                   const char *tune_cache, pn_hit **hits, uint64_t *n_hits);
+
 /* ---- serving: continuous batching over a resident reference ------------ */
 
 /* A request loop around the mapping path (the paper's layered pipeline of
@@ -315,8 +346,11 @@ typedef struct {
     uint64_t hits;            /* delivered */
     uint64_t max_batch_reads; /* largest batch run */
 } pn_server_stats;
-/* `ref` stays owned by the caller and must outlive the server. */
-int pn_server_create(const pn_ref *ref, const pn_server_config *cfg, pn_server **out);
+/* The server runs on the device of `ctx` (which must be the reference's);
+ * each slot makes its own context there.  `ctx` and `ref` stay owned by
+ * the caller and must outlive the server. */
+int pn_server_create(pn_ctx *ctx, const pn_ref *ref, const pn_server_config *cfg,
+                     pn_server **out);
 /* Queue a request: reads[offsets[i] .. offsets[i+1]) for i < n_reads
  * (host memory, copied before return), error budget k >= 0 for all reads
  * or k < 0 and k_per_read[i] (host).  Checked here: letters ACGT (either
@@ -330,6 +364,12 @@ int pn_server_submit(pn_server *srv, const char *reads, const uint64_t *offsets,
  * once. */
 int pn_server_wait(pn_server *srv, uint64_t ticket, pn_hit **hits, uint64_t *n_hits,
                    double *latency_ms);
+/* Non-blocking pn_server_wait: PN_PENDING (1) while the request is queued
+ * or running (nothing is written); otherwise exactly what pn_server_wait
+ * returns, and the ticket is redeemed. */
+#define PN_PENDING 1
+int pn_poll(pn_server *srv, uint64_t ticket, pn_hit **hits, uint64_t *n_hits,
+            double *latency_ms);
 int pn_server_get_stats(pn_server *srv, pn_server_stats *out);
 /* Finishes every queued request, then stops the workers. */
 void pn_server_destroy(pn_server *srv);

@@ -3,8 +3,10 @@
 // path on one stream.  No call aborts or prints; HIP failures become status
 // codes.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 #include <map>
 #include <mutex>
 #include <new>
@@ -23,6 +25,11 @@ struct Buf {
     size_t cap = 0;
 };
 
+// an index orders its slices by the letters after the q-gram as well when
+// at least 1/kOrderNextShare of its occurrences lie in slices longer than
+// pn::kSubMin
+constexpr uint64_t kOrderNextShare = 128;
+
 enum MiscSlot {  // 64-bit words of the context's device scratch block
     kStatus = 0,
     kStatMaxLen = 1,
@@ -36,7 +43,9 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kLongCounts = kRecCounts + pn::kShards,
     kFilterStats = kLongCounts + pn::kShards,  // 4 x pn::kShards words
     kHeavyCounts = kFilterStats + 4 * pn::kShards,
-    kMiscWords = kHeavyCounts + pn::kShards
+    kLaxCount = kHeavyCounts + pn::kShards,
+    kLongEntries = kLaxCount + 1,
+    kMiscWords = kLongEntries + 1
 };
 
 struct PendingStage {
@@ -56,7 +65,8 @@ struct pn_ctx {
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
     Buf cands, longc, heavy, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
-        out_hits, out_best;
+        out_hits, out_best, lax, laxO;
+    bool sub_on = false;  // lax lists made for the current mapping call
     // capacities per output region (pn::kShards regions; grow on demand)
     uint64_t cand_rcap = 1ull << 18;
     uint64_t rec_rcap = 1ull << 14;
@@ -87,6 +97,7 @@ struct pn_index {
     uint32_t n_reads;
     uint64_t n_bases, n_qgrams, n_distinct, n_groups, n_slots;
     int q, w, max_len;
+    bool after_sorted = false;  // slices of O ordered by the letters after the q-gram first
     uint32_t *packed;
     uint64_t *offsets;
     uint2 *rplanes;
@@ -295,7 +306,8 @@ int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
     if (e == hipSuccess) {
         const PnRefDev rd = ref_desc(r);
         pn::launch_refq_keys(rd, q, keys, st);
-        unsigned long long *sorted = pn::radix_sort_u64_any(keys, tmp, n, 2 * q, temp, st);
+        unsigned long long *sorted = pn::radix_sort_u64_any(
+            keys, tmp, n, 2 * q + 2 * pn::refq_sort_letters(r->L, q), temp, st);
         if (sorted != keys) std::swap(keys, tmp);
         pn::launch_refq_ctx(rd, q, keys, n, ctx, st);
         e = hipStreamSynchronize(st);
@@ -330,6 +342,7 @@ PnIndexDev index_desc(const pn_index *x) {
     d.q = x->q;
     d.log2w = x->w == 64 ? 6 : 5;
     d.n_groups = x->n_groups;
+    d.after_sorted = x->after_sorted ? 1 : 0;
     return d;
 }
 
@@ -584,18 +597,26 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         pn::launch_read_nq(ix, nq, st);
         pn::launch_scan_u32(nq, nq, n_reads, partials, st);
         pn::launch_qgram_keys(ix, nq, T, tile, first_read, keys, hist0, st);
-        const unsigned long long *sorted =
-            pn::radix_sort_u64_any(keys, tmp, T, 2 * q, sort_temp, st, 0, hist0);
+        const int glo = pn::index_gram_lo(q);
+        unsigned long long *sorted =
+            pn::radix_sort_u64_any(keys, tmp, T, glo + 2 * q, sort_temp, st, glo, hist0);
         pn::launch_fill_u32((uint32_t *)x->I, x->n_groups * (w / 32), 0u, st);
         pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);  // step 1, O
         pn::launch_scan_popc(x->I, ix.log2w, x->S, x->n_groups, partials, st);  // steps 2-3
         pn::launch_starts_to_sp(flags, T, partials, x->Sp, st);  // steps 4-6
-        stage_end(c, st, tok, 5 + 3 * ((2 * q + 7) / 8) + 3 + 3);
+        // occurrences in long slices decide whether the slices are ordered
+        // by the letters after the q-gram as well
+        pn::launch_fill_u32((uint32_t *)&c->misc[kLongEntries], 2, 0u, st);
+        pn::launch_long_entries(ix, pn::kSubMin, (unsigned long long *)&c->misc[kLongEntries], st);
+        stage_end(c, st, tok, 7 + 3 * ((2 * q + 7) / 8) + 3 + 3);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
         e = hipMemcpyAsync(&n_distinct, x->S + x->n_groups, 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(x->lc_size, lcs, sizeof(x->lc_size), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&c->hmisc[kLongEntries], &c->misc[kLongEntries], 8,
+                               hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) s = map_err(e);
         if (!s) {
@@ -603,6 +624,22 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
             x->lc_total = 0;
             for (int i = 0; i < pn::kLcPatterns; i++) x->lc_total += x->lc_size[i];
             collect_stages(c);
+            // Repeat families in the reads give long slices whose entries
+            // differ in the letters that follow; ordering those letters too
+            // lets filtration visit only the entries that can pair with a
+            // text position (one more sort, worth it when a notable share of
+            // all occurrences lies in long slices)
+            if (glo && c->hmisc[kLongEntries] * kOrderNextShare >= T) {
+                tok = stage_begin(c, st, PN_STAGE_INDEX);
+                unsigned long long *other = sorted == keys ? tmp : keys;
+                sorted = pn::radix_sort_u64_any(sorted, other, T, glo + 2 * q, sort_temp, st, 0);
+                pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);
+                stage_end(c, st, tok, 5 * ((glo + 2 * q + 7) / 8) + 1);
+                x->after_sorted = true;
+                e = hipStreamSynchronize(st);
+                if (e != hipSuccess) s = map_err(e);
+                else collect_stages(c);
+            }
         }
     }
     dfree(c, nq);
@@ -665,6 +702,7 @@ int pn_index_get_info(const pn_index *x, pn_index_info *out) {
     i.q = x->q;
     i.w = x->w;
     i.max_len = x->max_len;
+    i.after_sorted = x->after_sorted ? 1 : 0;
     *out = i;
     return PN_OK;
 }
@@ -718,7 +756,18 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     if (x->n_reads)
         pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
                            meta + pn::kLcPatterns, meta + 7 * pn::kLcPatterns, st);
-    stage_end(c, st, tok, x->n_reads ? 7 : 3);
+    // lax lists: an index whose slices are ordered by the letters after the
+    // q-gram is searched in its long slices (see pn::Lists)
+    c->sub_on = x->after_sorted && x->n_reads && x->n_distinct;
+    if (c->sub_on) {
+        PN_CHECK(ensure(c, c->lax, (x->n_distinct + 1) * sizeof(uint2)));
+        PN_CHECK(ensure(c, c->laxO, std::max<uint64_t>(x->n_qgrams, 1) * 8));
+        pn::launch_fill_u32((uint32_t *)&c->misc[kLaxCount], 2, 0u, st);
+        pn::launch_lax_lists(ix, x->n_distinct, pn::kSubMin, (uint2 *)c->lax.p,
+                             (unsigned long long *)c->laxO.p,
+                             (unsigned long long *)&c->misc[kLaxCount], st);
+    }
+    stage_end(c, st, tok, (x->n_reads ? 7 : 3) + (c->sub_on ? 2 : 0));
     PN_CHECK(read_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];
     if (status & 2u) return PN_EINVAL;
@@ -726,12 +775,19 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     return PN_OK;
 }
 
-int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStream_t st) {
-    pn::RefQDev P;
-    PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
+pn::Lists lists_of(const pn_ctx *c) {
+    const uint32_t *meta = (const uint32_t *)c->side_meta.p;
+    return pn::Lists{(const unsigned long long *)c->side.p, meta + pn::kLcPatterns,
+                     (const unsigned long long *)c->laxO.p, (const uint2 *)c->lax.p, pn::kSubMin,
+                     c->sub_on ? 1 : 0};
+}
+
+// filtration of the entries [a, b) of the reference's position set P
+int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn::RefQDev &Pall,
+                       uint64_t a, uint64_t b, hipStream_t st) {
+    pn::RefQDev P{Pall.keys + a, Pall.ctx ? Pall.ctx + a : nullptr, b - a};
     PN_CHECK(ensure(c, c->heavy, pn::kShards * c->heavy_rcap * 2 * sizeof(uint4)));
     pn::launch_fill_u32((uint32_t *)&c->misc[kHeavyCounts], 2 * pn::kShards, 0u, st);
-    const uint32_t *meta = (const uint32_t *)c->side_meta.p;
     pn::FilterOut fo{(uint2 *)c->cands.p,
                      {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
                      (uint4 *)c->heavy.p,
@@ -739,11 +795,11 @@ int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, hipStrea
                      pn::filter_heavy_min(x->n_qgrams, x->q),
                      (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
-    pn::launch_filter(ref_desc(ref), P, index_desc(x), (const unsigned long long *)c->side.p,
-                      meta + pn::kLcPatterns, fo, st);
+    const pn::Lists ls = lists_of(c);
+    pn::launch_filter(ref_desc(ref), P, index_desc(x), ls, fo, st);
     stage_end(c, st, tok, 1);
     tok = stage_begin(c, st, PN_STAGE_FILTER_HEAVY);
-    pn::launch_filter_heavy(index_desc(x), (const unsigned long long *)c->side.p, fo, st);
+    pn::launch_filter_heavy(index_desc(x), ls, fo, st);
     stage_end(c, st, tok, 1);
     return PN_OK;
 }
@@ -757,14 +813,11 @@ void region_counts(const pn_ctx *c, int slot, uint32_t regions, uint64_t *mx, ui
     }
 }
 
-// after a filtration: did a heavy-item region overflow?  (then its capacity
-// grows and the caller runs the filtration again)
-bool heavy_overflow(pn_ctx *c) {
+// after a filtration: the largest heavy-item region count (items asked for)
+uint64_t heavy_max(const pn_ctx *c) {
     uint64_t mx, tot;
     region_counts(c, kHeavyCounts, pn::kShards, &mx, &tot);
-    if (mx <= c->heavy_rcap) return false;
-    c->heavy_rcap = mx + mx / 4;
-    return true;
+    return mx;
 }
 
 // occurrence pairs seen and index entries read by the last filtration
@@ -788,93 +841,155 @@ void zero_counts(pn_ctx *c, int slot, hipStream_t st) {
     pn::launch_fill_u32((uint32_t *)&c->misc[slot], 2 * pn::kShards, 0u, st);
 }
 
-// validation of the candidates `in` (both passes), records into the
-// sharded c->keys_tmp; grows the record regions and runs again on overflow.
-// Leaves the records, gathered and sorted, in c->keys and their count in
-// *n_rec.  With `filter`, each attempt also runs filtration first (its
-// candidate regions may overflow too).
+// Candidate and hand-off buffers of one filtration stay below these sizes
+// (per region: kShards regions each); a part of the position set whose
+// output would not fit is split in two and each half is run on its own.
+constexpr uint64_t kMaxCandRegion = (1ull << 28) / pn::kShards;   // 2 GiB of candidates
+constexpr uint64_t kMaxHeavyRegion = (1ull << 26) / pn::kShards;  // 2 GiB of items
+
+// grow-only buffer whose first `keep` bytes survive the growth
+int ensure_keep(pn_ctx *c, Buf &b, size_t bytes, size_t keep, hipStream_t st) {
+    if (b.cap >= bytes && b.p) return PN_OK;
+    size_t want = std::max(bytes + bytes / 4, (size_t)4096);
+    void *p = nullptr;
+    PN_CHECK(dalloc(c, want, &p));
+    if (keep && b.p) {
+        hipError_t e = hipMemcpyAsync(p, b.p, keep, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) {
+            dfree(c, p);
+            return map_err(e);
+        }
+    }
+    dfree(c, b.p);
+    b.p = p;
+    b.cap = want;
+    return PN_OK;
+}
+
+// Validation (both passes) of candidates, records into the sharded
+// c->keys_tmp.  With `filter`, the candidates come from filtration of the
+// reference's position set, part by part: each part is filtered (and its
+// candidate counts checked: a buffer that overflowed is grown, or the part
+// split when its output would pass the bounds above, and the part filtered
+// again), verified (records that overflowed: grown, verified again) and its
+// records gathered into c->keys before the next part, so that candidate
+// buffers stay bounded however many candidates the whole reference yields.
+// Without `filter`, the n_in candidates already in c->cands are verified.
+// Leaves all records, sorted, in c->keys and their count in *n_rec.
+constexpr uint64_t kFirstPart = 1ull << 30;  // position-set entries filtered at once at first
+
 int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
                     bool filter, uint64_t n_in, hipStream_t st, uint64_t *n_rec) {
     const int ebits = key_ebits(ref->L);
     c->rec_rcap = std::max<uint64_t>(c->rec_rcap, (16ull * x->n_reads) / pn::kShards + 4096);
-    for (int attempt = 0; attempt < 8; attempt++) {
-        const uint32_t regions = filter ? pn::kShards : 1;
+    pn::RefQDev P{nullptr, nullptr, 0};
+    if (filter) PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
+    const uint32_t regions = filter ? pn::kShards : 1;
+    const uint64_t end = filter ? P.n : (n_in ? 1 : 0);
+    uint64_t a = 0, part = std::min<uint64_t>(std::max<uint64_t>(end, 1), kFirstPart), total = 0;
+    int attempts = 0;
+    while (a < end) {
+        if (++attempts > 64) return PN_ENOMEM;
+        const uint64_t b = filter ? std::min(end, a + part) : end;
+        uint64_t cand_total = filter ? 0 : n_in;
         const uint64_t in_rcap = filter ? c->cand_rcap : std::max<uint64_t>(n_in, 1);
         PN_CHECK(ensure(c, c->cands, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->longc, regions * in_rcap * sizeof(uint2)));
-        PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
-        pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
-        pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
-        zero_counts(c, kRecCounts, st);
-        zero_counts(c, kLongCounts, st);
+        zero_counts(c, kCandCounts, st);
+        FilterWork fw;
         if (filter) {
-            zero_counts(c, kCandCounts, st);
-            PN_CHECK(launch_filter_into(c, ref, x, st));
+            pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
+            PN_CHECK(launch_filter_into(c, ref, x, P, a, b, st));
+            PN_CHECK(read_misc(c, st));
+            uint64_t cand_max;
+            region_counts(c, kCandCounts, regions, &cand_max, &cand_total);
+            const uint64_t hmax = heavy_max(c);
+            bool again = false;
+            if ((cand_max > kMaxCandRegion || hmax > kMaxHeavyRegion) && b - a > 1) {
+                part = std::max<uint64_t>(1, (b - a) / 2);
+                again = true;
+            } else {
+                if (cand_max > c->cand_rcap) {
+                    c->cand_rcap = cand_max + cand_max / 4;
+                    again = true;
+                }
+                if (hmax > c->heavy_rcap) {
+                    c->heavy_rcap = hmax + hmax / 4;
+                    again = true;
+                }
+            }
+            if (again) continue;
+            fw = filter_stats(c);
+            // parts that came out small may grow again
+            if (cand_max < kMaxCandRegion / 4 && hmax < kMaxHeavyRegion / 4 && part < kFirstPart)
+                part *= 2;
         } else {
-            zero_counts(c, kCandCounts, st);
             pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n_in, st);
         }
-        pn::VerifyIn in{(const uint2 *)c->cands.p, (const unsigned long long *)&c->misc[kCandCounts],
-                        regions, in_rcap};
-        pn::VerifyOut vo{(unsigned long long *)c->keys_tmp.p,
-                         {(unsigned long long *)&c->misc[kRecCounts], c->rec_rcap},
-                         (unsigned long long *)&c->misc[kVerifyRows], ebits};
-        int tok = stage_begin(c, st, PN_STAGE_VERIFY);
-        pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, (uint2 *)c->longc.p,
-                          (unsigned long long *)&c->misc[kLongCounts], true, st);
-        stage_end(c, st, tok, 1);
-        vo.rows = (unsigned long long *)&c->misc[kVerifyRowsLong];
-        tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
-        pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, (uint2 *)c->longc.p,
-                          (unsigned long long *)&c->misc[kLongCounts], false, st);
-        stage_end(c, st, tok, 1);
-        PN_CHECK(read_misc(c, st));
-        uint64_t cand_max, cand_total, rec_max, got;
-        region_counts(c, kCandCounts, regions, &cand_max, &cand_total);
-        region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
-        // an output that overflowed is grown (every one at once) and the
-        // attempt runs again
-        bool again = false;
-        if (filter && cand_max > c->cand_rcap) {
-            c->cand_rcap = cand_max + cand_max / 4;
-            again = true;
-        }
-        if (filter && heavy_overflow(c)) again = true;
-        if (rec_max > c->rec_rcap) {
+        uint64_t got = 0;
+        for (int vattempt = 0;; vattempt++) {
+            if (vattempt >= 8) return PN_ENOMEM;
+            PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
+            pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
+            zero_counts(c, kRecCounts, st);
+            zero_counts(c, kLongCounts, st);
+            pn::VerifyIn in{(const uint2 *)c->cands.p,
+                            (const unsigned long long *)&c->misc[kCandCounts], regions, in_rcap};
+            pn::VerifyOut vo{(unsigned long long *)c->keys_tmp.p,
+                             {(unsigned long long *)&c->misc[kRecCounts], c->rec_rcap},
+                             (unsigned long long *)&c->misc[kVerifyRows], ebits};
+            int tok = stage_begin(c, st, PN_STAGE_VERIFY);
+            pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
+                              (uint2 *)c->longc.p, (unsigned long long *)&c->misc[kLongCounts],
+                              true, st);
+            stage_end(c, st, tok, 1);
+            vo.rows = (unsigned long long *)&c->misc[kVerifyRowsLong];
+            tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
+            pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
+                              (uint2 *)c->longc.p, (unsigned long long *)&c->misc[kLongCounts],
+                              false, st);
+            stage_end(c, st, tok, 1);
+            PN_CHECK(read_misc(c, st));
+            uint64_t rec_max;
+            region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
+            if (rec_max <= c->rec_rcap) break;
             c->rec_rcap = rec_max + rec_max / 4;
-            again = true;
         }
-        if (again) continue;
-        *n_rec = got;
         if (filter) {
-            const FilterWork f = filter_stats(c);
-            c->stats.n_seeds += f.seeds;
-            c->stats.n_visited += f.visited;
+            c->stats.n_seeds += fw.seeds;
+            c->stats.n_visited += fw.visited;
             c->stats.n_candidates += cand_total;
-            c->stats.n_visited_heavy += f.set_aside;
-            c->stats.n_heavy_items += f.items;
-            c->stats.n_candidates_heavy += cand_total - std::min(cand_total, f.written);
+            c->stats.n_visited_heavy += fw.set_aside;
+            c->stats.n_heavy_items += fw.items;
+            c->stats.n_candidates_heavy += cand_total - std::min(cand_total, fw.written);
         }
         c->stats.verify_rows += c->hmisc[kVerifyRows] + c->hmisc[kVerifyRowsLong];
         c->stats.verify_rows_long += c->hmisc[kVerifyRowsLong];
         c->stats.n_records += got;
-        const int bits = 6 + ebits + key_rbits(x->n_reads);
-        PN_CHECK(ensure(c, c->keys, std::max<uint64_t>(got, 1) * 8));
-        PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(got)));
-        tok = stage_begin(c, st, PN_STAGE_SORT);
+        PN_CHECK(ensure_keep(c, c->keys, std::max<uint64_t>(total + got, 1) * 8, total * 8, st));
+        const int tok = stage_begin(c, st, PN_STAGE_SORT);
         pn::launch_gather_shards((const unsigned long long *)c->keys_tmp.p,
                                  (const unsigned long long *)&c->misc[kRecCounts], pn::kShards,
-                                 c->rec_rcap, (unsigned long long *)c->keys.p, st);
-        // mapping: records need only be grouped by (read, strand, end), the
-        // finishing pass takes each group's smallest error count; the
-        // records pn_validate returns are sorted whole
-        const int lo = filter ? 5 : 0;
-        pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
-                           got, bits, c->sort_temp.p, st, lo);
-        stage_end(c, st, tok, 1 + 5 * ((bits - lo + 7) / 8));
-        return PN_OK;
+                                 c->rec_rcap, (unsigned long long *)c->keys.p + total, st);
+        stage_end(c, st, tok, 1);
+        total += got;
+        a = b;
+        attempts = 0;
     }
-    return PN_ENOMEM;
+    *n_rec = total;
+    const int bits = 6 + ebits + key_rbits(x->n_reads);
+    PN_CHECK(ensure_keep(c, c->keys, std::max<uint64_t>(total, 1) * 8, total * 8, st));
+    PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(total, 1) * 8));
+    PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(total)));
+    const int tok = stage_begin(c, st, PN_STAGE_SORT);
+    // mapping: records need only be grouped by (read, strand, end), the
+    // finishing pass takes each group's smallest error count; the records
+    // pn_validate returns are sorted whole
+    const int lo = filter ? 5 : 0;
+    pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, total,
+                       bits, c->sort_temp.p, st, lo);
+    stage_end(c, st, tok, 5 * ((bits - lo + 7) / 8));
+    return PN_OK;
 }
 
 // filtration + validation; leaves the sorted record keys in c->keys and
@@ -1008,6 +1123,159 @@ int pn_map(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t
 
 void pn_hits_free(pn_hit *h) { std::free(h); }
 
+// ---- batching: a read set of any size in memory-sized sub-batches -----------
+
+namespace {
+
+// q and w from the cache file, or -1
+void tune_cache_lookup(const char *path, const std::string &key, int *q, int *w) {
+    *q = *w = -1;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[400];
+        int a = 0, b = 0;
+        if (std::sscanf(line, "%399s %d %d", k, &a, &b) == 3 && key == k) {
+            *q = a;
+            *w = b;
+        }
+    }
+    std::fclose(f);
+}
+
+void tune_cache_store(const char *path, const std::string &key, int q, int w) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;  // an unwritable cache only costs a new tuning next time
+    std::fprintf(f, "%s %d %d\n", key.c_str(), q, w);
+    std::fclose(f);
+}
+
+}  // namespace
+
+int pn_map_batched(pn_ctx *c, const pn_ref *ref, const char *reads, const uint64_t *offsets,
+                   uint32_t n_reads, const uint8_t *k_per_read, pn_mode mode,
+                   const char *tune_cache, pn_hit **hits, uint64_t *n_hits) {
+    if (!c || !ref || !hits || !n_hits || (n_reads && (!offsets || !k_per_read)))
+        return PN_EINVAL;
+    if (mode != PN_ALL_HITS && mode != PN_BEST_STRATUM) return PN_EINVAL;
+    if (ref->ctx->device != c->device) return PN_EINVAL;
+    uint32_t len_lo = PN_MAX_READ_LEN, len_hi = 0, k_lo = 255, k_hi = 0;
+    int q_lemma = 12;  // largest q the lemma admits for every read, at most 12
+    for (uint32_t r = 0; r < n_reads; r++) {
+        if (offsets[r + 1] < offsets[r]) return PN_EINVAL;
+        const uint64_t n = offsets[r + 1] - offsets[r];
+        const uint32_t k = k_per_read[r];
+        if (n < 1 || n > PN_MAX_READ_LEN || k > PN_MAX_K) return PN_EINVAL;
+        len_lo = std::min<uint32_t>(len_lo, (uint32_t)n);
+        len_hi = std::max<uint32_t>(len_hi, (uint32_t)n);
+        k_lo = std::min(k_lo, k);
+        k_hi = std::max(k_hi, k);
+        q_lemma = std::min<int>(q_lemma, (int)(n / (k + 1)));
+    }
+    if (n_reads && q_lemma < 1) return PN_ELEMMA;
+    if (reads == nullptr && n_reads && offsets[n_reads] > offsets[0]) return PN_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    // sub-batches: at most PN_MAX_READS reads (one index) and a share of the
+    // free device memory (about 48 bytes per base while an index is built
+    // and mapped)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        free_b = 8ull << 30;
+    }
+    const uint64_t max_bases = std::max<uint64_t>(std::min<uint64_t>(free_b / 2 / 48, (1ull << 31)),
+                                                  PN_MAX_READ_LEN);
+    std::vector<uint32_t> cut{0};
+    for (uint32_t r = 0; r < n_reads;) {
+        const uint32_t r0 = r;
+        while (r < n_reads && r - r0 < PN_MAX_READS &&
+               offsets[r + 1] - offsets[r0] <= max_bases)
+            r++;
+        cut.push_back(r);
+    }
+    std::vector<pn_hit> out;
+    int q = q_lemma, w = 64;
+    bool tuned = tune_cache == nullptr;
+    std::string key;
+    if (!tuned) {
+        char buf[400];
+        int lg = 0;
+        while ((1ull << (lg + 1)) <= (uint64_t)std::max<uint32_t>(n_reads, 1)) lg++;
+        std::snprintf(buf, sizeof(buf), "L=%llu;reads=2^%d;len=%u-%u;k=%u-%u;mode=%d",
+                      (unsigned long long)ref->L, lg, len_lo, len_hi, k_lo, k_hi, (int)mode);
+        key = buf;
+        int cq = -1, cw = -1;
+        tune_cache_lookup(tune_cache, key, &cq, &cw);
+        if (cq >= 1 && cq <= q_lemma && (cw == 32 || cw == 64)) {
+            q = cq;
+            w = cw;
+            tuned = true;
+        }
+    }
+    int s = PN_OK;
+    for (size_t b = 0; b + 1 < cut.size() && !s; b++) {
+        const uint32_t r0 = cut[b], r1 = cut[b + 1], m = r1 - r0;
+        const uint64_t base = offsets[r0], nb = offsets[r1] - base;
+        std::vector<uint64_t> offs(m + 1);
+        for (uint32_t i = 0; i <= m; i++) offs[i] = offsets[r0 + i] - base;
+        char *dr = nullptr;
+        uint64_t *doff = nullptr;
+        uint8_t *dk = nullptr;
+        pn_index *x = nullptr;
+        s = dalloc_t(c, nb + 1, &dr);
+        if (!s) s = dalloc_t(c, (uint64_t)m + 1, &doff);
+        if (!s) s = dalloc_t(c, (uint64_t)m + 1, &dk);
+        if (!s && nb) s = map_err(hipMemcpyAsync(dr, reads + base, nb, hipMemcpyHostToDevice, st));
+        if (!s)
+            s = map_err(hipMemcpyAsync(doff, offs.data(), ((uint64_t)m + 1) * 8,
+                                       hipMemcpyHostToDevice, st));
+        if (!s) s = map_err(hipMemcpyAsync(dk, k_per_read + r0, m, hipMemcpyHostToDevice, st));
+        if (!s && !tuned) {
+            // the autotuner times each admitted (q, w) on a sample of this
+            // first sub-batch and predicts the whole batch
+            pn_tune_result res[6];
+            int nres = 0, bq = 0, bw = 0;
+            s = pn_autotune(c, ref, dr, doff, m, nb, -1, dk, mode, std::min<uint32_t>(m, 1u << 16),
+                            res, &nres, &bq, &bw);
+            if (!s) {
+                q = bq;
+                w = bw;
+                tuned = true;
+                tune_cache_store(tune_cache, key, q, w);
+            }
+        }
+        if (!s) s = pn_index_build_dev(c, dr, doff, m, nb, q, w, st, &x);
+        uint64_t n_rec = 0, n_out = 0;
+        if (!s) s = map_records(c, ref, x, -1, dk, st, &n_rec);
+        if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
+        if (!s)
+            s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->out_hits.p,
+                       c->out_hits.cap / sizeof(pn_hit), st, &n_out);
+        if (!s && n_out) {
+            const size_t at = out.size();
+            out.resize(at + n_out);
+            s = map_err(hipMemcpyAsync(out.data() + at, c->out_hits.p, n_out * sizeof(pn_hit),
+                                       hipMemcpyDeviceToHost, st));
+            if (!s) s = map_err(hipStreamSynchronize(st));
+            for (size_t i = at; !s && i < out.size(); i++) out[i].read_id += r0;
+        }
+        (void)hipStreamSynchronize(st);
+        if (x) pn_index_free(x);
+        dfree(c, dr);
+        dfree(c, doff);
+        dfree(c, dk);
+    }
+    if (s) return s;
+    pn_hit *h = (pn_hit *)std::malloc(std::max<size_t>(out.size(), 1) * sizeof(pn_hit));
+    if (!h) return PN_ENOMEM;
+    if (!out.empty()) std::memcpy(h, out.data(), out.size() * sizeof(pn_hit));
+    *hits = h;
+    *n_hits = out.size();
+    return PN_OK;
+}
+
 int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t *kpr,
               pn_candidate **cands, uint64_t *n_cands, uint64_t *n_seeds) {
     PN_CHECK(check_map_args(c, ref, x, k, kpr, PN_ALL_HITS));
@@ -1024,20 +1292,24 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         }
     }
     int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
+    pn::RefQDev P{nullptr, nullptr, 0};
+    if (!s) s = ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P);
     uint64_t n = 0;
+    // (the whole position set at once: this call returns every candidate)
     for (int attempt = 0; !s && attempt < 8; attempt++) {
         s = ensure(c, c->cands, pn::kShards * c->cand_rcap * sizeof(uint2));
         if (s) break;
         pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
         zero_counts(c, kCandCounts, st);
-        s = launch_filter_into(c, ref, x, st);
+        s = launch_filter_into(c, ref, x, P, 0, P.n, st);
         if (!s) s = read_misc(c, st);
         if (s) break;
         uint64_t mx;
         region_counts(c, kCandCounts, pn::kShards, &mx, &n);
-        const bool hov = heavy_overflow(c);
-        if (mx <= c->cand_rcap && !hov) break;
+        const uint64_t hmax = heavy_max(c);
+        if (mx <= c->cand_rcap && hmax <= c->heavy_rcap) break;
         if (mx > c->cand_rcap) c->cand_rcap = mx + mx / 4;
+        if (hmax > c->heavy_rcap) c->heavy_rcap = hmax + hmax / 4;
         n = 0;
     }
     uint64_t seeds = 0;

@@ -339,8 +339,9 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const int shift = lo + 8 * p;
         // the last digit may be narrower: bits above `bits` do not take part
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
-        // the first pass may come with its histogram (made with the keys)
-        const bool given = p == 0 && hist0 != nullptr && lo == 0;
+        // the first pass may come with its histogram (made with the keys:
+        // the counts of the digit at bit lo)
+        const bool given = p == 0 && hist0 != nullptr;
         const uint32_t *hp = given ? hist0 : hist;
         if (!given && radix_threads(n) == kThrLarge)
             hipLaunchKernelGGL(k_radix_hist<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,

@@ -48,6 +48,8 @@
 // 64 at a time; slots it does not use are filled with PN_CAND_NONE, which
 // verification skips.  Slots are counted even past a region's capacity so
 // that the host can grow the buffer and run again.
+#include <algorithm>
+
 #include "pn_internal.h"
 
 namespace {
@@ -168,17 +170,22 @@ __device__ __forceinline__ void pad_lane(Stage &sg) {
 // one (position, strand): INDEXPAIR and the rules of the header comment
 // One occurrence.  The read's rule bits (keep flag, required extra run) were
 // stamped into the entry's low byte for this mapping call (k_stamp_rules).
+// With `strict`, entries of reads that need fewer than four letters past the
+// q-gram are skipped: the sub-range they were found in holds only the
+// entries whose four letters agree with the text, and such entries are
+// visited through the slice's lax list instead (see probe).
 __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uint32_t s,
                                       bool has_prev, uint32_t prev, bool lh, uint32_t N,
-                                      uint32_t avail, Stage &sg) {
+                                      uint32_t avail, bool strict, Stage &sg) {
     const uint32_t hi = (uint32_t)(v >> 32);
     const uint32_t cls = hi >> 29;
     const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
     const uint32_t o = hi & 0xffu;
     const uint32_t info = (uint32_t)v & 0xffu;
     const bool keep = (info >> 7) & 1u;
-    if (has_prev && cls == prev && (keep || !lh)) return;  // rule 1
     const uint32_t need = info & 7u;                         // rule 3
+    if (strict && need < 4u) return;
+    if (has_prev && cls == prev && (keep || !lh)) return;  // rule 1
     if (need) {
         const uint32_t nav = (uint32_t)(v >> 21) & 7u;
         const uint32_t next4 = (uint32_t)(v >> 24) & 0xffu;
@@ -196,18 +203,53 @@ constexpr uint32_t kItem = 1024;
 constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
-// strand): [a0, a1) and [b0, b1) of `src` (the rules' class cut applies to
-// the low-complexity side lists).  Returns k_end - k_start.
+// strand): [a0, a1) of srcA and [b0, b1) of srcB (the rules' class cut
+// applies to the low-complexity side lists).  Returns k_end - k_start.
+// List ids (for the hand-off items): 0 = O, 1 = side lists, 2 = lax lists.
 struct Ranges {
-    gu64 *src;
+    gu64 *srcA, *srcB;
     uint32_t a0, a1, b0, b1;
+    uint32_t idA, idB;
+    bool strictA;
 };
 
-template <typename TW>
-__device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned long long *side,
-                                          const uint32_t *side_cls, uint32_t g, bool has_prev,
-                                          uint32_t prev, Ranges &rg) {
-    rg.src = (gu64 *)ix.O;
+// the 9-bit code of an O entry's letters after the q-gram (the order of a
+// slice when the index is sorted by them; see pn_index.hip)
+__device__ __forceinline__ uint32_t entry_after_code(unsigned long long v) {
+    const uint32_t lo = (uint32_t)v;
+    const uint32_t next4 = lo >> 24, nav = (lo >> 21) & 7u;
+    switch (nav) {
+        case 4: return next4;
+        case 3: return 256u + (next4 >> 2);
+        case 2: return 320u + (next4 >> 4);
+        case 1: return 336u + (next4 >> 6);
+        default: return 340u;
+    }
+}
+
+// first position in O[lo, hi) whose code is >= target (codes ascend)
+__device__ __forceinline__ uint32_t code_lower_bound(gu64 *O, uint32_t lo, uint32_t hi,
+                                                     uint32_t target) {
+    uint32_t n = hi - lo;
+    while (n > 0) {
+        const uint32_t half = n >> 1;
+        if (entry_after_code(O[lo + half]) < target) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo;
+}
+
+template <typename TW, bool kSub>
+__device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const pn::Lists &ls, uint32_t g,
+                                          bool has_prev, uint32_t prev, uint32_t N,
+                                          uint32_t avail, Ranges &rg) {
+    rg.srcA = rg.srcB = (gu64 *)ix.O;
+    rg.idA = rg.idB = 0;
+    rg.strictA = false;
     rg.a0 = rg.a1 = rg.b0 = rg.b1 = 0;
     const TW *I = (const TW *)ix.I;
     const uint32_t wmask = (1u << ix.log2w) - 1;
@@ -220,12 +262,30 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
     if (pn_low_complexity(g, ix.q)) {
         // rule 2: only reads that keep these seeds, listed by preceding
         // letter; for those reads rule 1 drops the class equal to `prev`
-        const uint32_t *cb = side_cls + (g >> (2 * ix.q - 4)) * 6;
-        rg.src = (gu64 *)side;
+        const uint32_t *cb = ls.side_cls + (g >> (2 * ix.q - 4)) * 6;
+        rg.srcA = rg.srcB = (gu64 *)ls.side;
+        rg.idA = rg.idB = 1;
         rg.a0 = cb[0];
         rg.b1 = cb[5];
         rg.a1 = has_prev ? cb[prev] : rg.b1;
         rg.b0 = has_prev ? cb[prev + 1] : rg.b1;
+    } else if (kSub && ke - ks > ls.sub_min) {
+        // A long slice, ordered by the letters after the q-gram: a read that
+        // needs four of them (rule 3) can only pair here with the entries
+        // whose four letters are the text's, found by binary search; the
+        // entries of the other reads of this slice are in its lax list.
+        if (avail == 4u) {
+            rg.a0 = code_lower_bound((gu64 *)ix.O, ks, ke, N);
+            rg.a1 = code_lower_bound((gu64 *)ix.O, rg.a0, ke, N + 1u);
+        } else {
+            rg.a0 = rg.a1 = ks;
+        }
+        rg.strictA = true;
+        const uint2 lx = ls.lax[x];
+        rg.srcB = (gu64 *)ls.laxO;
+        rg.idB = 2;
+        rg.b0 = lx.x;
+        rg.b1 = lx.x + lx.y;
     } else {
         rg.a0 = ks;
         rg.a1 = ke;
@@ -236,10 +296,10 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const unsigned l
 
 // visit one (position, strand): short ranges by this lane, long ones set
 // aside for k_filter_heavy (every lane of the wave calls this together)
+template <bool kSub>
 __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint32_t s,
                                               bool has_prev, uint32_t prev, bool lh, uint32_t N,
                                               uint32_t avail, bool valid, Stage &sg,
-                                              const unsigned long long *side,
                                               const pn::FilterOut &out,
                                               unsigned long long &set_aside) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
@@ -263,11 +323,14 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
         first = __shfl(first, 0);
         if (heavy) {
             set_aside += len;
-            // position (33 bits), strand, letters and which list
+            // position (32 bits in the item, the rest here), strand, letters
+            // and which lists
+            // (without sub-ranges both ranges lie in one list, O or the side lists)
+            const uint32_t idA = kSub ? rg.idA : rg.idA, idB = kSub ? rg.idB : rg.idA;
             const uint32_t fl = (has_prev ? 1u : 0u) | (lh ? 2u : 0u) | (prev << 2) |
-                                (avail << 4) | (N << 8) | (s << 16) |
-                                ((gu64 *)side == rg.src ? 1u << 17 : 0u) |
-                                ((uint32_t)((uint64_t)p >> 32) << 18);
+                                (avail << 4) | (N << 8) | (s << 16) | (idA << 17) |
+                                (idB << 19) | (kSub && rg.strictA ? 1u << 21 : 0u) |
+                                ((uint32_t)((uint64_t)p >> 32) << 22);
             const uint32_t la = rg.a1 - rg.a0;
             unsigned long long at = first + (incl - nitems);
             for (uint32_t c = 0; c < nitems; c++, at++) {
@@ -290,79 +353,104 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
         for (uint32_t t = rg.a0; t < rg.a1; t += kWalk) {
             unsigned long long w[kWalk];
 #pragma unroll
-            for (uint32_t u = 0; u < kWalk; u++) w[u] = t + u < rg.a1 ? rg.src[t + u] : 0ull;
+            for (uint32_t u = 0; u < kWalk; u++) w[u] = t + u < rg.a1 ? rg.srcA[t + u] : 0ull;
 #pragma unroll
             for (uint32_t u = 0; u < kWalk; u++)
-                if (t + u < rg.a1) visit(w[u], p, s, has_prev, prev, lh, N, avail, sg);
+                if (t + u < rg.a1)
+                    visit(w[u], p, s, has_prev, prev, lh, N, avail, kSub && rg.strictA, sg);
         }
-        for (uint32_t t = rg.b0; t < rg.b1; t++) visit(rg.src[t], p, s, has_prev, prev, lh, N, avail, sg);
+        gu64 *srcB = kSub ? rg.srcB : rg.srcA;
+        for (uint32_t t = rg.b0; t < rg.b1; t++)
+            visit(srcB[t], p, s, has_prev, prev, lh, N, avail, false, sg);
     }
     return valid ? len : 0u;  // entries read for this lane's (position, strand)
 }
 
+// The context of the q-gram at forward position u on strand s, from the
+// 64-bit window X of the packed reference that starts at base u - 5 - t0
+// (the q-gram's first base is base t0 + 5 of X): the letter before the
+// q-gram on that strand (0 when there is none), whether there is one, how
+// many letters follow it (up to 4) and those letters, first letter in the
+// top bits, missing ones 0.  Strand 1 reads the forward text backwards and
+// complemented: T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i]).
+__device__ __forceinline__ void refq_context(uint64_t X, int t0, uint64_t L, int q, uint64_t u,
+                                             uint32_t s, uint32_t &has, uint32_t &prev,
+                                             uint32_t &N, uint32_t &avail) {
+    const uint64_t after = L - u - q;  // forward letters after the q-gram
+    if (!s) {
+        has = u >= 1;
+        prev = base_rel(X, t0 + 4);
+        N = (uint32_t)((X << (2 * (t0 + 5 + q))) >> 56);
+        avail = after < 4 ? (uint32_t)after : 4u;
+    } else {
+        has = after >= 1;
+        prev = 3u - base_rel(X, t0 + 5 + q);
+        const uint32_t F = (uint32_t)((X << (2 * t0)) >> 54) & 0xffu;  // R[u-4..u-1]
+        N = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) | (F >> 6)) ^ 0xffu;
+        avail = u < 4 ? (uint32_t)u : 4u;
+    }
+    if (!has) prev = 0;
+    N &= (0xffu << (8 - 2 * avail)) & 0xffu;
+}
+
 // P's keys, one per forward position u: strand 0 at u, strand 1 at L-q-u;
-// key = ((p << 1 | strand) << 2q) | q-gram
-__global__ __launch_bounds__(256) void k_refq_keys(PnRefDev ref, int q,
+// key = ((p << 1 | strand) << (2q + 2a)) | (q-gram << 2a) | the first a
+// letters after the q-gram (a = refq_sort_letters), so that sorting the low
+// 2q + 2a bits orders P by q-gram and then by the letters that follow
+__global__ __launch_bounds__(256) void k_refq_keys(PnRefDev ref, int q, int a,
                                                    unsigned long long *__restrict__ keys) {
     const uint64_t L = ref.L;
     const uint64_t npos = L - q + 1;
     const uint64_t u0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kPPT;
     if (u0 >= npos) return;
     const uint64_t X = window32(ref.packed, (int64_t)u0 - 5);
-    const int sh = 2 * q;
+    const int sh = 2 * q + 2 * a;
     for (int jj = 0; jj < kPPT && u0 + jj < npos; jj++) {
         const uint64_t u = u0 + jj;
         const uint32_t g0 = (uint32_t)((X << (2 * (jj + 5))) >> (64 - 2 * q));
-        keys[u] = ((unsigned long long)(u << 1) << sh) | g0;
+        uint32_t has, prev, N0, N1, avail;
+        refq_context(X, jj, L, q, u, 0u, has, prev, N0, avail);
+        refq_context(X, jj, L, q, u, 1u, has, prev, N1, avail);
+        keys[u] = ((unsigned long long)(u << 1) << sh) | ((unsigned long long)g0 << (2 * a)) |
+                  (N0 >> (8 - 2 * a));
         keys[npos + u] = ((unsigned long long)(((L - q - u) << 1) | 1u) << sh) |
-                         pn_revcomp_code(g0, q);
+                         ((unsigned long long)pn_revcomp_code(g0, q) << (2 * a)) |
+                         (N1 >> (8 - 2 * a));
     }
 }
 
 // context of a sorted entry: letter before the q-gram (bits 0-1), whether
 // there is one (bit 2), letters after it that exist, up to 4 (bits 3-5),
 // and those letters (bits 6-13, first letter highest)
-__global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q,
+__global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q, int a,
                                                   unsigned long long *__restrict__ keys,
                                                   uint64_t n, uint16_t *__restrict__ ctx) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t L = ref.L;
-    const unsigned long long ps = keys[i] >> (2 * q);
+    const unsigned long long key = keys[i];
+    const unsigned long long ps = key >> (2 * q + 2 * a);
+    const uint32_t g = (uint32_t)(key >> (2 * a)) & ((1u << (2 * q)) - 1u);
     const uint64_t p = ps >> 1;
     const uint32_t s = (uint32_t)(ps & 1u);
     const uint64_t u = s ? L - q - p : p;  // forward position of the q-gram
     const uint64_t X = window32(ref.packed, (int64_t)u - 5);
-    const uint64_t after = L - u - q;  // forward letters after the q-gram
     uint32_t has, prev, N, avail;
-    if (!s) {
-        has = u >= 1;
-        prev = base_rel(X, 4);
-        N = (uint32_t)((X << (2 * (5 + q))) >> 56);
-        avail = after < 4 ? (uint32_t)after : 4u;
-    } else {
-        // T1[p-1] = comp(R[u+q]), T1[p+q+i] = comp(R[u-1-i])
-        has = after >= 1;
-        prev = 3u - base_rel(X, 5 + q);
-        const uint32_t F = (uint32_t)(X >> 54) & 0xffu;  // R[u-4..u-1]
-        N = (((F & 3u) << 6) | (((F >> 2) & 3u) << 4) | (((F >> 4) & 3u) << 2) | (F >> 6)) ^ 0xffu;
-        avail = u < 4 ? (uint32_t)u : 4u;
-    }
-    if (!has) prev = 0;
-    N &= (0xffu << (8 - 2 * avail)) & 0xffu;
-    if (ctx)
+    refq_context(X, 0, L, q, u, s, has, prev, N, avail);
+    if (ctx) {
+        keys[i] = (ps << (2 * q)) | g;
         ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
-    else
+    } else {
         keys[i] = (ps << (2 * q + 10)) | ((unsigned long long)N << (2 * q + 2)) |
-                  ((unsigned long long)prev << (2 * q)) | (keys[i] & ((1ull << (2 * q)) - 1ull));
+                  ((unsigned long long)prev << (2 * q)) | g;
+    }
 }
 
 // (compiled for 8 waves per SIMD: more waves hide more of the walk's load
 // latency than the few registers this spills cost)
-template <typename TW, bool kPacked>
+template <typename TW, bool kPacked, bool kSub>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_filter(
-    PnRefDev ref, pn::RefQDev P, PnIndexDev ix, const unsigned long long *__restrict__ side,
-    const uint32_t *__restrict__ side_cls, pn::FilterOut out) {
+    PnRefDev ref, pn::RefQDev P, PnIndexDev ix, pn::Lists ls, pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBuf];
     __shared__ uint32_t wcnt[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -412,12 +500,14 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const bool lh = has && pn_low_complexity((prev << (2 * (q - 1))) | (g >> 2), q);
         Ranges r;
         if (valid) {
-            seeds += probe<TW>(ix, side, side_cls, g, has, prev, r);
+            seeds += probe<TW, kSub>(ix, ls, g, has, prev, N, avail, r);
         } else {
-            r.src = (gu64 *)ix.O;
+            r.srcA = r.srcB = (gu64 *)ix.O;
+            r.idA = r.idB = 0;
+            r.strictA = false;
             r.a0 = r.a1 = r.b0 = r.b1 = 0;
         }
-        visited += visit_all(r, p, s, has, prev, lh, N, avail, valid, sg, side, out, set_aside);
+        visited += visit_all<kSub>(r, p, s, has, prev, lh, N, avail, valid, sg, out, set_aside);
         // the wave is converged here: empty the stage before it can overflow
         if (*sg.cnt >= kWBuf / 2) flush(sg, lane);
     }
@@ -442,8 +532,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // walks each in wave-uniform steps of 64 occurrences (the same rules, the
 // same staging; a step adds at most 64 candidates, so flushing once 64 or
 // fewer slots are free keeps the stage from overflowing).
-__global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
-                                                     const unsigned long long *__restrict__ side,
+__global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls,
                                                      pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBufHeavy];
     __shared__ uint32_t wcnt[kWaves];
@@ -471,8 +560,11 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
             n1 = items[2 * (it + step) + 1];
         }
         const uint32_t fl = h0.y;
-        const int64_t p = (int64_t)(((uint64_t)(fl >> 18) << 32) | h0.x);
-        gu64 *src = (fl >> 17) & 1u ? (gu64 *)side : (gu64 *)ix.O;
+        const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | h0.x);
+        const uint32_t idA = (fl >> 17) & 3u, idB = (fl >> 19) & 3u;
+        gu64 *srcA = idA == 1u ? (gu64 *)ls.side : (gu64 *)ix.O;
+        gu64 *srcB = idB == 1u ? (gu64 *)ls.side : idB == 2u ? (gu64 *)ls.laxO : (gu64 *)ix.O;
+        const bool strictA = (fl >> 21) & 1u;
         const bool has = fl & 1u, lh = (fl >> 1) & 1u;
         const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
         const uint32_t s = (fl >> 16) & 1u;
@@ -483,13 +575,12 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix,
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t k = base + 64 * u + (uint32_t)lane;
-                const uint32_t t = k < la ? h0.z + k : h1.x + (k - la);
-                v[u] = k < total ? src[t] : 0ull;
+                v[u] = k < total ? (k < la ? srcA[h0.z + k] : srcB[h1.x + (k - la)]) : 0ull;
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                if (base + 64 * u + (uint32_t)lane < total)
-                    visit(v[u], p, s, has, prev, lh, N, avail, sg);
+                const uint32_t k = base + 64 * u + (uint32_t)lane;
+                if (k < total) visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < la, sg);
                 if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
             }
         }
@@ -718,6 +809,52 @@ __global__ void k_lc_sizes(PnIndexDev ix, uint32_t *sizes) {
     sizes[id] = m;
 }
 
+// Lax lists (per mapping call, after the rule bytes are stamped): for every
+// slice of O longer than min_len, its entries whose read needs fewer than
+// four letters past the q-gram (rule 3), in slice order, appended to laxO;
+// lax[x] = {start, count} for such a slot x (other slots are not written).
+// A lane looks at one slot; the wave then takes the long slots one by one,
+// counts their lax entries with ballots, reserves room with one atomic add
+// and writes them.
+__global__ __launch_bounds__(kT) void k_lax_lists(PnIndexDev ix, uint64_t n_slots,
+                                                  uint32_t min_len, uint2 *__restrict__ lax,
+                                                  unsigned long long *__restrict__ laxO,
+                                                  unsigned long long *count) {
+    const uint32_t lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const uint64_t gw = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+    gu64 *O = (gu64 *)ix.O;
+    for (uint64_t base = gw * 64; base < n_slots; base += nw * 64) {
+        const uint64_t x = base + lane;
+        const uint32_t ks = x < n_slots ? ix.Sp[x] : 0u;
+        const uint32_t ke = x < n_slots ? ix.Sp[x + 1] : 0u;
+        unsigned long long todo = __ballot(ke - ks > min_len);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const uint32_t a = __shfl(ks, l), b = __shfl(ke, l);
+            uint32_t n = 0;
+            for (uint32_t t = a; t < b; t += 64) {
+                const bool f = t + lane < b && (((uint32_t)O[t + lane] & 7u) < 4u);
+                n += (uint32_t)__popcll(__ballot(f));
+            }
+            unsigned long long at = 0;
+            if (lane == 0 && n) at = atomicAdd(count, (unsigned long long)n);
+            at = __shfl(at, 0);
+            uint32_t w = 0;
+            for (uint32_t t = a; t < b && w < n; t += 64) {
+                const unsigned long long v = t + lane < b ? O[t + lane] : 0ull;
+                const bool f = t + lane < b && (((uint32_t)v & 7u) < 4u);
+                const unsigned long long m = __ballot(f);
+                if (f) laxO[at + w + (uint32_t)__popcll(m & lt)] = v;
+                w += (uint32_t)__popcll(m);
+            }
+            if (lane == (uint32_t)l) lax[x] = make_uint2((uint32_t)at, n);
+        }
+    }
+}
+
 }  // namespace
 
 namespace pn {
@@ -767,40 +904,53 @@ void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipS
     const uint64_t npos = ref.L - q + 1;
     const uint64_t threads = (npos + kPPT - 1) / kPPT;
     hipLaunchKernelGGL(k_refq_keys, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ref,
-                       q, keys);
+                       q, refq_sort_letters(ref.L, q), keys);
 }
 
 void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_refq_ctx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ref, q,
-                       keys, n, ctx);
+                       refq_sort_letters(ref.L, q), keys, n, ctx);
 }
 
-void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
-                   const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
-                   hipStream_t st) {
+template <typename TW, bool kPacked, bool kSub>
+static void filter_variant(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
+                           const Lists &ls, FilterOut out, uint64_t nb, hipStream_t st) {
+    hipLaunchKernelGGL((k_filter<TW, kPacked, kSub>), dim3((unsigned)nb), dim3(kT), 0, st, ref, P,
+                       ix, ls, out);
+}
+
+template <typename TW>
+static void filter_variant_tw(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
+                              const Lists &ls, FilterOut out, uint64_t nb, hipStream_t st) {
+    const bool packed = P.ctx == nullptr;
+    if (packed && ls.sub_on) filter_variant<TW, true, true>(ref, P, ix, ls, out, nb, st);
+    else if (packed) filter_variant<TW, true, false>(ref, P, ix, ls, out, nb, st);
+    else if (ls.sub_on) filter_variant<TW, false, true>(ref, P, ix, ls, out, nb, st);
+    else filter_variant<TW, false, false>(ref, P, ix, ls, out, nb, st);
+}
+
+void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix, const Lists &ls,
+                   FilterOut out, hipStream_t st) {
     const uint64_t nb = (P.n + kFilterBlockPos - 1) / kFilterBlockPos;
     if (!nb || !ix.n_reads) return;
-    const bool packed = P.ctx == nullptr;
-    if (ix.log2w == 6 && packed)
-        hipLaunchKernelGGL((k_filter<unsigned long long, true>), dim3((unsigned)nb), dim3(kT), 0,
-                           st, ref, P, ix, side, side_cls, out);
-    else if (ix.log2w == 6)
-        hipLaunchKernelGGL((k_filter<unsigned long long, false>), dim3((unsigned)nb), dim3(kT), 0,
-                           st, ref, P, ix, side, side_cls, out);
-    else if (packed)
-        hipLaunchKernelGGL((k_filter<uint32_t, true>), dim3((unsigned)nb), dim3(kT), 0, st, ref, P,
-                           ix, side, side_cls, out);
-    else
-        hipLaunchKernelGGL((k_filter<uint32_t, false>), dim3((unsigned)nb), dim3(kT), 0, st, ref, P,
-                           ix, side, side_cls, out);
+    if (ix.log2w == 6) filter_variant_tw<unsigned long long>(ref, P, ix, ls, out, nb, st);
+    else filter_variant_tw<uint32_t>(ref, P, ix, ls, out, nb, st);
 }
 
-void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,
-                         hipStream_t st) {
+void launch_filter_heavy(const PnIndexDev &ix, const Lists &ls, FilterOut out, hipStream_t st) {
     if (!ix.n_reads) return;
-    hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), 0, st, ix, side, out);
+    hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), 0, st, ix, ls, out);
+}
+
+void launch_lax_lists(const PnIndexDev &ix, uint64_t n_slots, uint32_t min_len, uint2 *lax,
+                      unsigned long long *laxO, unsigned long long *count, hipStream_t st) {
+    if (!n_slots || !ix.n_reads) return;
+    const uint64_t waves = (n_slots + 63) / 64;
+    const unsigned blocks = (unsigned)std::min<uint64_t>((waves + kWaves - 1) / kWaves, 8192);
+    hipLaunchKernelGGL(k_lax_lists, dim3(blocks), dim3(kT), 0, st, ix, n_slots, min_len, lax, laxO,
+                       count);
 }
 
 }  // namespace pn

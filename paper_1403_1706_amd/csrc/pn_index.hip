@@ -7,8 +7,10 @@
 //      the class of the letter before the q-gram, the q-gram g and (q <= 12)
 //      the letters after it with their count, all that an O entry holds
 //      (k_qgram_keys)
-//   b. stable LSD radix sort on the 2q bits of g: occurrences grouped by g,
-//      inside a group in the order (r, o)                          (pn_canon.hip)
+//   b. stable LSD radix sort on g: occurrences grouped by g, inside a group
+//      in the order (r, o); when (q <= 12) many occurrences fall into long
+//      slices, sorted again on g and the letters after it, which orders
+//      each slice by those letters first                         (pn_canon.hip)
 //   c. O[i] from the i-th key; the first key of each g sets bit g of I
 //      (Algorithm 1 step 1) and marks a group start               (k_index_from_sorted)
 //   d. S = exclusive scan of popcount(I[i]) (steps 2-3); the rank of each
@@ -76,10 +78,12 @@ __global__ void k_read_nq(PnIndexDev ix, uint32_t *nq) {
 
 // Key of occurrence (r, o): ((r << 8 | o) << (2q + 3)) | (class << 2q) | g;
 // with kCarry (q <= 12) the key holds all an O entry needs:
-// ((r << 8 | o) << (2q + 11)) | (after_code(next4, nav) << (2q + 2)) |
-// (letter before << 2q) | g, the letter before being "none" exactly at
-// o = 0.  Sorting looks at the low 2q bits (the q-gram) only, so each slice
-// keeps the order (read, offset).
+// ((r << 8 | o) << (2q + 11)) | (letter before << (2q + 9)) | (g << 9) |
+// after_code(next4, nav), the letter before being "none" exactly at o = 0.
+// Sorting looks at the q-gram's bits, so each slice keeps the order (read,
+// offset); with kCarry an index may be sorted again by the low 2q + 9 bits
+// (the q-gram, then the letters after it), ordering each slice by those
+// letters first.
 // The keys of a read's q-gram occurrences, at the read's offset in the key
 // array (see the header).  A wave takes reads gw, gw + nw, ...; lane l
 // holds word l of the read's packed text (a read touches at most 18 words),
@@ -173,8 +177,8 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                     const uint32_t nav = after < 4u ? after : 4u;
                     const uint32_t next4 = (w4 >> 24) & ((0xffu << (8 - 2 * nav)) & 0xffu);
                     key = ((unsigned long long)((r << 8) | o) << (2 * q + 11)) |
-                          ((unsigned long long)after_code(next4, nav) << (2 * q + 2)) |
-                          ((unsigned long long)(cls & 3u) << (2 * q)) | g;
+                          ((unsigned long long)(cls & 3u) << (2 * q + 9)) |
+                          ((unsigned long long)g << 9) | after_code(next4, nav);
                 } else {
                     key = ((unsigned long long)((r << 8) | o) << sh) |
                           ((unsigned long long)cls << (2 * q)) | g;
@@ -183,7 +187,8 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                 if (o < nq && pos >= K0 && pos < K1) {
                     // streamed out (read back only by the sort's first scatter)
                     __builtin_nontemporal_store(key, &keys[pos]);
-                    atomicAdd(&h[g & 255u], 1u);
+                    // the first digit the sort looks at: the q-gram's low 8 bits
+                    atomicAdd(&h[(uint32_t)(key >> (kCarry ? 9 : 0)) & 255u], 1u);
                 }
             }
         }
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
                                                            uint64_t T, unsigned long long *O,
                                                            uint8_t *flags, TW *I) {
     const int rsh = kCarry ? 2 * ix.q + 11 : 2 * ix.q + 3;  // where (r << 8 | o) starts
+    const int gsh = kCarry ? 9 : 0;                            // where the q-gram starts
     const unsigned long long gmask = (1ull << (2 * ix.q)) - 1ull;
     const uint64_t i0 = (uint64_t)blockIdx.x * (256 * kPer) + threadIdx.x;
     unsigned long long k[kPer], kl[kPer];
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
     if (kCarry) {
         // the letters after the q-gram and their count are in the key
 #pragma unroll
-        for (int j = 0; j < kPer; j++) code[j] = (uint32_t)(k[j] >> (2 * ix.q + 2)) & 511u;
+        for (int j = 0; j < kPer; j++) code[j] = (uint32_t)k[j] & 511u;
     } else {
 #pragma unroll
         for (int j = 0; j < kPer; j++) {
@@ -242,16 +248,16 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
         const uint64_t i = i0 + (uint64_t)j * 256;
         if (i0 + (uint64_t)j * 256 - (threadIdx.x & 63) >= T) break;  // the whole wave is past T
         const bool live = i < T;
-        const uint32_t g = (uint32_t)(k[j] & gmask);
+        const uint32_t g = (uint32_t)((k[j] >> gsh) & gmask);
         const uint32_t ro = (uint32_t)(k[j] >> rsh);
         const uint32_t r = ro >> 8, o = ro & 0xffu;
         const uint32_t cls = kCarry ? (o == 0 ? (uint32_t)PN_CLS_NONE
-                                              : (uint32_t)(k[j] >> (2 * ix.q)) & 3u)
+                                              : (uint32_t)(k[j] >> (2 * ix.q + 9)) & 3u)
                                     : (uint32_t)(k[j] >> (2 * ix.q)) & 7u;
         // the previous entry's key: the lane before, or memory for lane 0
         unsigned long long kp = __shfl_up(k[j], 1);
         if ((threadIdx.x & 63) == 0) kp = kl[j];
-        const bool start = i == 0 || (uint32_t)(kp & gmask) != g;
+        const bool start = i == 0 || (uint32_t)((kp >> gsh) & gmask) != g;
         if (live) flags[i] = start;
         // I: lanes holding one word of I are contiguous (keys are sorted);
         // their bits are ORed across the run and the run's last lane alone
@@ -379,6 +385,22 @@ __global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo
     lcinfo[r] = cnt | (runs << 16) | ((2 * front > cnt ? 1u : 0u) << 31);
 }
 
+// occurrences in slices longer than min_len (D = S[n_groups] slots)
+__global__ __launch_bounds__(256) void k_long_entries(const uint32_t *__restrict__ S,
+                                                      uint64_t n_groups,
+                                                      const uint32_t *__restrict__ Sp,
+                                                      uint32_t min_len, unsigned long long *out) {
+    const uint64_t D = S[n_groups];
+    unsigned long long acc = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < D;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t len = Sp[x + 1] - Sp[x];
+        if (len > min_len) acc += len;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -426,6 +448,12 @@ void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *ke
                            ix, keys, T, O, flags, (uint32_t *)I);
 }
 
+
+void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long long *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_long_entries, dim3(1024), dim3(256), 0, st, ix.S, ix.n_groups, ix.Sp,
+                       min_len, out);
+}
 
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st) {
     if (!ix.n_reads) return;

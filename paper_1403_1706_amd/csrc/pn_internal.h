@@ -65,6 +65,7 @@ struct PnIndexDev {
     int q;
     int log2w;
     uint64_t n_groups;
+    int after_sorted;  // each slice of O ordered by the letters after the q-gram first
 };
 
 // ---------------------------------------------------------------------------
@@ -171,6 +172,12 @@ void launch_read_nq(const PnIndexDev &ix, uint32_t *nq, hipStream_t st);
 // letters after (with their count), 29 of read and offset <= 64
 // (otherwise: 2q + 3 bits, the letter before or "none", then read and offset)
 inline bool index_key_carries(int q) { return 2 * q + 2 + 9 + 29 <= 64; }
+// bits [index_gram_lo(q), index_gram_lo(q) + 2q) of an index key hold the
+// q-gram; when the key carries the letters after it, they are the 9 bits
+// below (an index sorted by all 2q + 9 low bits has each slice of O ordered
+// by those letters, which lets filtration find the entries whose next
+// letters agree with the text by binary search)
+inline int index_gram_lo(int q) { return index_key_carries(q) ? 9 : 0; }
 // keys of all T occurrences (qoff: exclusive prefix of the reads' q-gram
 // counts, qoff[n_reads] = T), with hist0 (tile-major, 256 words per tile of
 // `tile` keys) the counts of their lowest 8 bits; first_read: one word per
@@ -187,6 +194,9 @@ void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *ke
 void launch_starts_to_sp(const uint8_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,
                          hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
+// the number of occurrences in slices of O longer than min_len, added to *out
+void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long long *out,
+                         hipStream_t st);
 
 // Append-only output split into kShards regions of `region_cap` entries,
 // each with its own counter: a thread block appends to region
@@ -249,14 +259,46 @@ inline bool refq_packs(uint64_t L, int q) {
     for (uint64_t v = 2 * L; v > 1; v >>= 1) bits++;  // (p << 1 | strand) < 2L
     return bits + 1 <= 54 - 2 * q;
 }
+// letters after the q-gram that P's sort keys carry (up to 4, as many as
+// fit beside (p << 1 | strand) and the q-gram in 64 bits): P is ordered by
+// q-gram and then by them
+inline int refq_sort_letters(uint64_t L, int q) {
+    int bits = 0;
+    for (uint64_t v = 2 * L; v > 1; v >>= 1) bits++;
+    const int a = (64 - 2 * q - (bits + 1)) / 2;
+    return a < 0 ? 0 : (a > 4 ? 4 : a);
+}
 void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipStream_t st);
 // the contexts of the sorted keys: into ctx, or (ctx == nullptr) into the
 // keys themselves in the packed layout
 void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st);
+// Lists of O entries made per mapping call, read by filtration:
+//  * side lists: the occurrences of the 16 low-complexity q-grams from reads
+//    that keep them (rule 2), grouped by the letter before, with their
+//    class bounds side_cls (6 per q-gram);
+//  * lax lists (when sub_on: the index orders each slice by the letters
+//    after the q-gram): for each slice longer than sub_min, its entries
+//    whose read needs fewer than four letters past the q-gram (rule 3),
+//    at laxO[lax[x].x .. lax[x].x + lax[x].y) for slot x.  Filtration then
+//    visits, in such a slice, only the binary-searched entries whose four
+//    letters equal the text's, plus the slice's lax list.
+struct Lists {
+    const unsigned long long *side;
+    const uint32_t *side_cls;
+    const unsigned long long *laxO;
+    const uint2 *lax;
+    uint32_t sub_min;
+    int sub_on;
+};
+// slices longer than this are searched rather than walked whole
+constexpr uint32_t kSubMin = 32;
 // the occurrence lists k_filter set aside (FilterOut::heavy)
-void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, FilterOut out,
-                         hipStream_t st);
+void launch_filter_heavy(const PnIndexDev &ix, const Lists &ls, FilterOut out, hipStream_t st);
+// the lax lists of the slots [0, n_slots) (count: one zeroed word, receives
+// the number of entries written to laxO, which needs room for all of O)
+void launch_lax_lists(const PnIndexDev &ix, uint64_t n_slots, uint32_t min_len, uint2 *lax,
+                      unsigned long long *laxO, unsigned long long *count, hipStream_t st);
 // the longest occurrence list k_filter walks itself: 32 when the lists are
 // short on average (fewer than 16 entries per q-gram of the index: the long
 // ones are rare and are better walked by a whole wave), else 64 (where most
@@ -264,9 +306,8 @@ void launch_filter_heavy(const PnIndexDev &ix, const unsigned long long *side, F
 inline uint32_t filter_heavy_min(uint64_t n_qgrams, int q) {
     return n_qgrams < (16ull << (2 * q)) ? 32u : 64u;
 }
-void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix,
-                   const unsigned long long *side, const uint32_t *side_cls, FilterOut out,
-                   hipStream_t st);
+void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix, const Lists &ls,
+                   FilterOut out, hipStream_t st);
 
 // pn_verify.hip (Section 3.3)
 struct VerifyIn {

@@ -258,8 +258,10 @@ void free_slot(Slot *sl) {
 
 extern "C" {
 
-int pn_server_create(const pn_ref *ref, const pn_server_config *cfg, pn_server **out) {
-    if (!ref || !cfg || !out) return PN_EINVAL;
+int pn_server_create(pn_ctx *ctx, const pn_ref *ref, const pn_server_config *cfg,
+                     pn_server **out) {
+    if (!ctx || !ref || !cfg || !out) return PN_EINVAL;
+    if (pnrt::ctx_device(ctx) != pnrt::ref_device(ref)) return PN_EINVAL;
     if (cfg->q < 1 || cfg->q > 15 || (cfg->w != 32 && cfg->w != 64) || cfg->slots < 1 ||
         cfg->slots > 8 || cfg->max_batch_reads < 1 || cfg->max_batch_reads > PN_MAX_READS ||
         cfg->hbm_budget == 0)
@@ -355,18 +357,10 @@ int pn_server_submit(pn_server *s, const char *reads, const uint64_t *offsets, u
     return PN_OK;
 }
 
-int pn_server_wait(pn_server *s, uint64_t ticket, pn_hit **hits, uint64_t *n_hits,
-                   double *latency_ms) {
-    if (!s || !hits || !n_hits) return PN_EINVAL;
-    Request *r = nullptr;
-    {
-        std::unique_lock<std::mutex> lk(s->mu);
-        auto it = s->reqs.find(ticket);
-        if (it == s->reqs.end()) return PN_EINVAL;
-        r = it->second;
-        s->cv_done.wait(lk, [&] { return r->done; });
-        s->reqs.erase(it);
-    }
+namespace {
+
+// hand a finished request's hits to the caller and delete it
+int redeem(Request *r, pn_hit **hits, uint64_t *n_hits, double *latency_ms) {
     const int rc = r->status;
     if (latency_ms) *latency_ms = r->t_done - r->t_submit;
     *hits = nullptr;
@@ -383,6 +377,37 @@ int pn_server_wait(pn_server *s, uint64_t ticket, pn_hit **hits, uint64_t *n_hit
     }
     delete r;
     return rc;
+}
+
+}  // namespace
+
+int pn_server_wait(pn_server *s, uint64_t ticket, pn_hit **hits, uint64_t *n_hits,
+                   double *latency_ms) {
+    if (!s || !hits || !n_hits) return PN_EINVAL;
+    Request *r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return PN_EINVAL;
+        r = it->second;
+        s->cv_done.wait(lk, [&] { return r->done; });
+        s->reqs.erase(it);
+    }
+    return redeem(r, hits, n_hits, latency_ms);
+}
+
+int pn_poll(pn_server *s, uint64_t ticket, pn_hit **hits, uint64_t *n_hits, double *latency_ms) {
+    if (!s || !hits || !n_hits) return PN_EINVAL;
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return PN_EINVAL;
+        if (!it->second->done) return PN_PENDING;
+        r = it->second;
+        s->reqs.erase(it);
+    }
+    return redeem(r, hits, n_hits, latency_ms);
 }
 
 int pn_server_get_stats(pn_server *s, pn_server_stats *out) {

@@ -30,6 +30,7 @@ PN_EDEVICE = -4
 PN_ELEMMA = -5
 PN_ETRUNC = -6
 PN_EBUDGET = -7
+PN_PENDING = 1
 
 PN_ALL_HITS = 0
 PN_BEST_STRATUM = 1
@@ -44,7 +45,7 @@ class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_reads", ctypes.c_uint64), ("n_bases", ctypes.c_uint64),
                 ("n_qgrams", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
                 ("n_groups", ctypes.c_uint64), ("q", ctypes.c_int32), ("w", ctypes.c_int32),
-                ("max_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_len", ctypes.c_int32), ("after_sorted", ctypes.c_int32)]
 
 
 STAGES = ["ingest", "index", "filter_heavy", "filter_emit", "verify", "sort", "finish", "rules",
@@ -121,13 +122,16 @@ _sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_
 _sig("pn_hits_free", None, [_P])
 _sig("pn_filter", _int, [_P, _P, _P, _int, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
 _sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
-_sig("pn_server_create", _int, [_P, ctypes.POINTER(_ServerConfig), _PP])
+_sig("pn_server_create", _int, [_P, _P, ctypes.POINTER(_ServerConfig), _PP])
 _sig("pn_server_submit", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _P, _int,
                                 ctypes.POINTER(_u64)])
 _sig("pn_server_wait", _int, [_P, _u64, _PP, ctypes.POINTER(_u64),
                               ctypes.POINTER(ctypes.c_double)])
+_sig("pn_poll", _int, [_P, _u64, _PP, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
 _sig("pn_server_get_stats", _int, [_P, ctypes.POINTER(_ServerStats)])
 _sig("pn_server_destroy", None, [_P])
+_sig("pn_map_batched", _int, [_P, _P, ctypes.c_char_p, _P, _u32, _P, _int, ctypes.c_char_p, _PP,
+                              ctypes.POINTER(_u64)])
 _sig("pn_autotune", _int, [_P, _P, _P, _P, _u32, _u64, _int, _P, _int, _u32,
                            ctypes.POINTER(_TuneResult), ctypes.POINTER(_int), ctypes.POINTER(_int),
                            ctypes.POINTER(_int)])
@@ -137,8 +141,8 @@ EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
             "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
-            "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_server_get_stats",
-            "pn_server_destroy", "pn_autotune"]
+            "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_poll",
+            "pn_server_get_stats", "pn_server_destroy", "pn_autotune", "pn_map_batched"]
 
 
 def _check(st: int, where: str):
@@ -255,7 +259,7 @@ def pn_index_free(idx) -> None:
 def pn_index_get_info(idx) -> dict:
     info = _IndexInfo()
     _check(_lib.pn_index_get_info(idx, ctypes.byref(info)), "pn_index_get_info")
-    return {f: getattr(info, f) for f, _ in _IndexInfo._fields_ if f != "reserved"}
+    return {f: getattr(info, f) for f, _ in _IndexInfo._fields_}
 
 
 def pn_index_export(idx):
@@ -372,11 +376,12 @@ class Session:
         self.close()
 
 
-def pn_server_create(ref, q: int, w: int = 64, hbm_budget: int = 16 << 30,
+def pn_server_create(ctx, ref, q: int, w: int = 64, hbm_budget: int = 16 << 30,
                      max_batch_reads: int = 1 << 20, slots: int = 2):
     cfg = _ServerConfig(q, w, hbm_budget, max_batch_reads, slots)
     h = ctypes.c_void_p()
-    _check(_lib.pn_server_create(ref, ctypes.byref(cfg), ctypes.byref(h)), "pn_server_create")
+    _check(_lib.pn_server_create(ctx, ref, ctypes.byref(cfg), ctypes.byref(h)),
+           "pn_server_create")
     return h
 
 
@@ -400,6 +405,34 @@ def pn_server_wait(srv, ticket: int):
     _check(_lib.pn_server_wait(srv, ticket, ctypes.byref(hp), ctypes.byref(n), ctypes.byref(lat)),
            "pn_server_wait")
     return _take_hits(hp, n.value, HIT_DTYPE), lat.value
+
+
+def pn_poll(srv, ticket: int):
+    """None while the request is pending, else (hits, latency_ms)."""
+    hp = ctypes.c_void_p()
+    n = _u64()
+    lat = ctypes.c_double()
+    st = _lib.pn_poll(srv, ticket, ctypes.byref(hp), ctypes.byref(n), ctypes.byref(lat))
+    if st == PN_PENDING:
+        return None
+    _check(st, "pn_poll")
+    return _take_hits(hp, n.value, HIT_DTYPE), lat.value
+
+
+def pn_map_batched(ctx, ref, reads: bytes, offsets, k, mode: int = PN_ALL_HITS,
+                   tune_cache: str | None = None) -> np.ndarray:
+    """k: int for all reads, or a uint8 array of per-read k (host)."""
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n_reads = len(offs) - 1
+    karr = np.full(n_reads, int(k), np.uint8) if np.isscalar(k) else \
+        np.ascontiguousarray(k, dtype=np.uint8)
+    assert len(karr) == n_reads
+    hp = ctypes.c_void_p()
+    n = _u64()
+    _check(_lib.pn_map_batched(ctx, ref, reads, _ptr(offs), n_reads, _ptr(karr), mode,
+                               None if tune_cache is None else tune_cache.encode(),
+                               ctypes.byref(hp), ctypes.byref(n)), "pn_map_batched")
+    return _take_hits(hp, n.value, HIT_DTYPE)
 
 
 def pn_server_get_stats(srv) -> dict:

@@ -206,7 +206,8 @@ def _simulate_from_windows(src: np.ndarray, lengths: np.ndarray, eps: np.ndarray
         dele = (u >= p_ins[todo]) & (u < p_err[todo])
         consume = ~ins
         emit = ~dele
-        src_idx = np.cumsum(consume, axis=1) - consume  # source base looked at in this step
+        consumed_total = np.cumsum(consume, axis=1, dtype=np.int32)
+        src_idx = consumed_total - consume  # source base looked at in this step
         src_idx = np.minimum(src_idx, M - 1)
         base = np.take_along_axis(src[todo], src_idx, axis=1).copy()
         nsub = int(sub.sum())
@@ -215,9 +216,8 @@ def _simulate_from_windows(src: np.ndarray, lengths: np.ndarray, eps: np.ndarray
         nins = int(ins.sum())
         if nins:
             base[ins] = rng.integers(0, 4, nins, dtype=np.uint8)
-        opos = np.cumsum(emit, axis=1) - 1
+        opos = np.cumsum(emit, axis=1, dtype=np.int32) - 1
         # rows whose walk ran past the source window or emitted too little: redraw
-        consumed_total = np.cumsum(consume, axis=1)
         need = lengths[todo][:, None]
         reached = (opos == need - 1) & emit
         first = np.where(reached.any(axis=1), reached.argmax(axis=1), M)
@@ -282,15 +282,117 @@ def repeat_reference(length: int, rng: np.random.Generator) -> np.ndarray:
     return ref
 
 
-def human_reference(length: int, rng: np.random.Generator) -> np.ndarray:
-    ref = iid_reference(length, rng, gc=0.41)
-    add_repeat_families(ref, rng, [(300, 0.15), (6000, 0.30)], 0.10, 0.20)
+# --- the human-shaped preset, drawn in parallel ------------------------------
+#
+# 3 Gbp and 10 M reads are too much for one thread, so this preset draws its
+# parts from independent streams (children of one SeedSequence: a stream per
+# reference chunk, per batch of repeat copies and per chunk of reads) on a
+# pool of threads (numpy releases the GIL in its bulk draws and ufuncs).  The
+# result depends on the seed only, not on the number of threads: repeat
+# copies are written into the reference in batch order.
+
+_HUMAN_CHUNK = 1 << 26  # reference bases per stream
+_HUMAN_READ_CHUNK = 1 << 17  # reads per stream
+
+
+def _pool_threads(threads: int | None) -> int:
+    import os
+    return max(1, min(16, threads or os.cpu_count() or 1))
+
+
+def _map_threads(fn, items, threads: int):
+    if threads <= 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
+
+
+def human_reference(length: int, seed: int, threads: int | None = None) -> np.ndarray:
+    """GC-41 % i.i.d. background, then two interspersed repeat families (one
+    random GC-41 % consensus each: 300 bp covering 15 %, 6 kbp covering 30 %),
+    diverged full-length copies at a per-copy rate U[10 %, 20 %] of 90/5/5
+    sub/ins/del edits, random positions and orientations."""
+    threads = _pool_threads(threads)
+    root = np.random.SeedSequence(seed)
+    s_bg, s_fam = root.spawn(2)
+    ref = np.empty(length, dtype=np.uint8)
+    starts = list(range(0, length, _HUMAN_CHUNK))
+    bg_seeds = s_bg.spawn(len(starts))
+    # P(A) = P(T) = 0.295, P(C) = P(G) = 0.205 from a 16-bit draw
+    cut = np.array([19333, 19333 + 13435, 19333 + 2 * 13435], dtype=np.uint16)
+
+    def background(i):
+        a = starts[i]
+        e = min(length, a + _HUMAN_CHUNK)
+        g = np.random.Generator(np.random.PCG64(bg_seeds[i]))
+        u = g.integers(0, 1 << 16, e - a, dtype=np.uint16)
+        ref[a:e] = np.searchsorted(cut, u, side="right").astype(np.uint8)
+
+    _map_threads(background, range(len(starts)), threads)
+    fam_seeds = s_fam.spawn(2)
+    for (cons_len, frac), fseed in zip([(300, 0.15), (6000, 0.30)], fam_seeds):
+        s_cons, s_batches = fseed.spawn(2)
+        u = np.random.Generator(np.random.PCG64(s_cons)).integers(0, 1 << 16, cons_len,
+                                                                  dtype=np.uint16)
+        cons = np.searchsorted(cut, u, side="right").astype(np.uint8)
+        n_copies = int(frac * length / cons_len)
+        if n_copies == 0 or length < cons_len:
+            continue
+        batch = max(1, min(n_copies, (1 << 24) // cons_len))
+        bounds = [(a, min(n_copies, a + batch)) for a in range(0, n_copies, batch)]
+        b_seeds = s_batches.spawn(len(bounds))
+        margin = 16 + int(cons_len * 0.20 * 0.3)
+
+        def copies_of(i):
+            b = bounds[i][1] - bounds[i][0]
+            g = np.random.Generator(np.random.PCG64(b_seeds[i]))
+            rates = g.uniform(0.10, 0.20, b)
+            src = np.empty((b, cons_len + margin), dtype=np.uint8)
+            src[:, :cons_len] = cons
+            src[:, cons_len:] = g.integers(0, 4, (b, margin), dtype=np.uint8)
+            cp = _simulate_from_windows(src, np.full(b, cons_len), rates, g)
+            flip = g.random(b) < 0.5
+            cp[flip] = 3 - cp[flip, ::-1]
+            pos = g.integers(0, length - cons_len + 1, b)
+            return pos, cp
+
+        # draw a few batches at a time in parallel, write them in order
+        for w0 in range(0, len(bounds), threads):
+            done = _map_threads(copies_of, range(w0, min(len(bounds), w0 + threads)), threads)
+            for pos, cp in done:
+                idx = pos[:, None] + np.arange(cons_len)[None, :]
+                ref[idx.ravel()] = cp.ravel()
     return ref
 
 
-def make(name: str, scale: float = 1.0, n_reads: int | None = None, seed_offset: int = 0) -> Workload:
+def human_reads(ref: np.ndarray, n_reads: int, seed: int, threads: int | None = None):
+    """n_reads x 100 bp at 3 % error, uniform over both strands, drawn a
+    chunk per stream; returns what simulate_reads returns."""
+    threads = _pool_threads(threads)
+    starts = list(range(0, n_reads, _HUMAN_READ_CHUNK))
+    seeds = np.random.SeedSequence(seed).spawn(len(starts))
+
+    def chunk(i):
+        m = min(n_reads, starts[i] + _HUMAN_READ_CHUNK) - starts[i]
+        g = np.random.Generator(np.random.PCG64(seeds[i]))
+        return simulate_reads(ref, np.full(m, 100, dtype=np.int64), 0.03, g)
+
+    parts = _map_threads(chunk, range(len(starts)), threads)
+    offsets = np.zeros(n_reads + 1, dtype=np.uint64)
+    offsets[1:] = 100 * np.arange(1, n_reads + 1, dtype=np.uint64)
+    reads = b"".join(p[0] for p in parts)
+    strands = np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, np.uint8)
+    rstarts = np.concatenate([p[3] for p in parts]) if parts else np.zeros(0, np.int64)
+    return reads, offsets, strands, rstarts
+
+
+def make(name: str, scale: float = 1.0, n_reads: int | None = None, seed_offset: int = 0,
+         threads: int | None = None) -> Workload:
     """Build a preset workload.  ``scale`` shrinks reference length and read
-    count together; ``n_reads`` overrides the read count."""
+    count together; ``n_reads`` overrides the read count; ``threads`` bounds
+    the pool that draws the human-shaped preset (its output does not depend
+    on it)."""
     i = PRESET_NUMBER[name]
     ref_rng = np.random.Generator(np.random.PCG64(1000 * i + 1 + seed_offset))
     read_rng = np.random.Generator(np.random.PCG64(1000 * i + 2 + seed_offset))
@@ -314,10 +416,13 @@ def make(name: str, scale: float = 1.0, n_reads: int | None = None, seed_offset:
             lengths = read_rng.integers(50, 251, n_reads or N).astype(np.int64)
             kr = k_ceil_fraction(lengths)
     elif name == "human":
-        L, N, eps, q = int(3_000_000_000 * scale), int(10_000_000 * scale), 0.03, 12
-        ref = human_reference(L, ref_rng)
-        lengths = np.full(n_reads or N, 100, dtype=np.int64)
-        kr = np.full(len(lengths), 5, dtype=np.uint8)
+        L, N = int(3_000_000_000 * scale), int(10_000_000 * scale)
+        ref = human_reference(L, 1000 * i + 1 + seed_offset, threads)
+        reads, offsets, strands, starts = human_reads(ref, n_reads or N,
+                                                      1000 * i + 2 + seed_offset, threads)
+        n = len(offsets) - 1
+        return Workload(name, _ascii(ref), reads, offsets, 12, np.full(n, 5, dtype=np.uint8),
+                        {"scale": scale, "eps": 0.03, "L": len(ref)}, strands, starts)
     else:
         raise ValueError(f"unknown preset {name!r}")
     reads, offsets, strands, starts = simulate_reads(ref, lengths, eps, read_rng)

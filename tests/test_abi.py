@@ -70,3 +70,14 @@ def test_struct_layouts(pn):
     assert pn.HIT_DTYPE.itemsize == 12
     assert pn.CAND_DTYPE.itemsize == 16
     assert ctypes.sizeof(pn._IndexInfo) == 56
+
+
+def test_new_entry_points_check_arguments(pn):
+    lib = pn._lib
+    hp, n = ctypes.c_void_p(), ctypes.c_uint64()
+    assert lib.pn_map_batched(None, None, None, None, 0, None, 0, None, ctypes.byref(hp),
+                              ctypes.byref(n)) == pn.PN_EINVAL
+    assert lib.pn_poll(None, 1, ctypes.byref(hp), ctypes.byref(n), None) == pn.PN_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.pn_server_create(None, None, None, ctypes.byref(out)) == pn.PN_EINVAL
+    assert pn.PN_PENDING == 1

@@ -75,3 +75,51 @@ def test_autotune_respects_lemma_and_keeps_hits(pn):
         assert q in (10, 11) and wb in (32, 64)
         hits = pn.pn_map(s.ctx, ref, s.index(w.reads, w.offsets, q, wb), k)
         assert_same(hits, oracle.map_filtered(w.ref, w.reads, w.offsets, 10, k))
+
+
+def test_map_batched_equals_oracle_with_tune_cache(pn, tmp_path):
+    """pn_map_batched on host reads of mixed lengths with per-read k: equal
+    to the oracle in both modes; with a tune cache the first call tunes and
+    stores (q, w), the second reads them back, and the hits do not change."""
+    w = synth.make("mixed", scale=0.002)
+    cache = str(tmp_path / "tune.txt")
+    with pn.Session(0) as s:
+        ref = s.ref(w.ref)
+        for mode in (0, 1):
+            exp = oracle.map_filtered(w.ref, w.reads, w.offsets, 12, w.k_per_read, best=bool(mode))
+            assert_same(pn.pn_map_batched(s.ctx, ref, w.reads, w.offsets, w.k_per_read, mode), exp)
+            a = pn.pn_map_batched(s.ctx, ref, w.reads, w.offsets, w.k_per_read, mode, cache)
+            lines = open(cache).read().splitlines()
+            b = pn.pn_map_batched(s.ctx, ref, w.reads, w.offsets, w.k_per_read, mode, cache)
+            assert open(cache).read().splitlines() == lines  # read back, not tuned again
+            say(f"tune cache: {lines}")
+            assert_same(a, exp)
+            assert_same(b, exp)
+
+
+def test_map_batched_over_one_index(pn):
+    """More reads than one index holds (2^21): pn_map_batched splits them
+    into sub-batches; each part equals pn_map of its own index, and a sample
+    equals the oracle."""
+    w = synth.make("tiny", scale=0.2, n_reads=(1 << 21) + 3000)  # 200 kbp reference
+    split = 1 << 21
+    with pn.Session(0) as s:
+        ref = s.ref(w.ref)
+        say(f"pn_map_batched over {w.n_reads} reads")
+        got = pn.pn_map_batched(s.ctx, ref, w.reads, w.offsets, w.k_per_read, 0)
+        key = (got["read_id"].astype(np.int64) << 33) | (got["strand"].astype(np.int64) << 32) | \
+            got["end_pos"].astype(np.int64)
+        assert np.all(np.diff(key) > 0)
+        # the second sub-batch, indexed on its own
+        sub = w.subset(np.arange(split, w.n_reads))
+        part = pn.pn_map(s.ctx, ref, s.index(sub.reads, sub.offsets, 10), 5, 0)
+        part["read_id"] += np.uint32(split)
+        assert_same(got[got["read_id"] >= split], part)
+        rng = np.random.default_rng(7)
+        sample = np.sort(np.concatenate([rng.choice(split, 500, replace=False),
+                                         split + rng.choice(w.n_reads - split, 500, replace=False)]))
+        sub = w.subset(sample)
+        orc = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 10, 5)
+        mine = got[np.isin(got["read_id"], sample)].copy()
+        mine["read_id"] = np.searchsorted(sample, mine["read_id"])
+        assert_same(mine, orc)

@@ -1,0 +1,140 @@
+"""Parity at the full sizes the benchmark runs, in its launch path.
+
+The oracle cannot map a million reads inside a GPU job, so its results for
+the whole workload were computed once on the CPU by
+tests/golden/make_repeat_digest.py (oracle and seeded generator only) and
+stored as digests: hit counts and SHA-256 of the canonical 12-byte records,
+per mode and per chunk of reads.  Here the GPU maps the same workload as
+bench.py does (one index over every read, pn_map_dev) and must reproduce
+those digests exactly.  On a mismatch the first differing chunk is mapped by
+the oracle again and compared read by read, so that the failure names the
+reads.
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_1706_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pn():
+    from paper_1403_1706_amd import peanut
+    return peanut
+
+
+def canonical(h):
+    out = np.zeros(len(h), dtype=oracle.HIT_DTYPE)
+    for f in ("read_id", "end_pos", "strand", "errors"):
+        out[f] = h[f]
+    return out[np.lexsort((out["end_pos"], out["strand"], out["read_id"]))]
+
+
+def sha(b):
+    return hashlib.sha256(b).hexdigest()
+
+
+def fields(h):
+    return np.stack([h["read_id"].astype(np.int64), h["strand"].astype(np.int64),
+                     h["end_pos"].astype(np.int64), h["errors"].astype(np.int64)], axis=1)
+
+
+def map_all_reads(pn, w, modes):
+    """One index over every read and pn_map_dev, as bench.py times it."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    with pn.Session(0) as s:
+        ref = s.ref(w.ref)
+        d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+        d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+        d_k = torch.from_numpy(np.ascontiguousarray(w.k_per_read)).to(dev)
+        torch.cuda.synchronize()
+        idx = pn.pn_index_build_dev(s.ctx, d_reads, d_offs, w.q, 64)
+        try:
+            buf = torch.zeros(12 * 60_000_000, dtype=torch.uint8, device=dev)
+            for mode in modes:
+                say(f"{w.name}: map all {w.n_reads} reads, mode={mode}")
+                n = pn.pn_map_dev(s.ctx, ref, idx, 0, buf, mode, d_k=d_k)
+                out[mode] = np.frombuffer(buf[:n * 12].cpu().numpy().tobytes(),
+                                          dtype=pn.HIT_DTYPE).copy()
+        finally:
+            pn.pn_index_free(idx)
+    return out
+
+
+def diff_chunk(w, got, mode, first, count):
+    """The oracle on one chunk of reads, compared read by read."""
+    ids = np.arange(first, first + count)
+    sub = w.subset(ids)
+    orc = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, w.q, sub.k_per_read,
+                              best=bool(mode)).copy()
+    orc["read_id"] += np.uint32(first)
+    mine = got[(got["read_id"] >= first) & (got["read_id"] < first + count)]
+    a = {tuple(r) for r in fields(mine)}
+    b = {tuple(r) for r in fields(orc)}
+    lost, extra = sorted(b - a), sorted(a - b)
+    return (f"mode {mode}, reads {first}..{first + count - 1}: {len(lost)} oracle hits missing "
+            f"(first {lost[:5]}), {len(extra)} extra (first {extra[:5]})")
+
+
+def test_repeat_workload_all_reads_equal_oracle_digest(pn):
+    path = os.path.join(GOLDEN, "repeat_digest.json")
+    dg = json.load(open(path))
+    say("generating the 100 Mbp / 1 M read workload")
+    w = synth.make("repeat")
+    assert w.n_reads == dg["n_reads"] and w.q == dg["q"]
+    got = map_all_reads(pn, w, (0, 1))
+    for mode, name in ((0, "all"), (1, "best")):
+        h = canonical(got[mode])
+        want = dg[name]
+        counts = np.bincount(h["read_id"].astype(np.int64), minlength=w.n_reads).astype("<u4")
+        ok = (len(h) == want["n_hits"] and sha(h.tobytes()) == want["sha256"]
+              and sha(counts.tobytes()) == want["per_read_counts_sha256"])
+        say(f"mode={name}: {len(h)} hits (oracle {want['n_hits']}), digest match: {ok}")
+        if not ok:
+            for ch in want["chunks"]:
+                a, n = ch["first_read"], ch["n_reads"]
+                part = h[(h["read_id"] >= a) & (h["read_id"] < a + n)]
+                if len(part) != ch["n_hits"] or sha(part.tobytes()) != ch["sha256"]:
+                    pytest.fail(diff_chunk(w, h, mode, a, min(n, 2000)))
+            pytest.fail(f"mode {name}: per-chunk digests agree but the whole does not")
+
+
+def test_mixed_batch_sample_equals_oracle_digest(pn):
+    path = os.path.join(GOLDEN, "mixed_sample_digest.json")
+    dg = json.load(open(path))
+    say("generating the mixed-length workload (2 M reads of 50-250 bp)")
+    w = synth.make("mixed")
+    assert w.n_reads == dg["n_reads"]
+    rng = np.random.Generator(np.random.PCG64(dg["sample_seed"]))
+    ids = np.sort(rng.choice(w.n_reads, size=dg["sample_size"], replace=False))
+    w.q = dg["q"]
+    got = map_all_reads(pn, w, (0, 1))
+    for mode, name in ((0, "all"), (1, "best")):
+        h = got[mode]
+        mine = canonical(h[np.isin(h["read_id"], ids)])
+        want = dg[name]
+        say(f"mode={name}: {len(h)} hits in all, {len(mine)} on the sample "
+            f"(oracle {want['n_hits']})")
+        assert len(mine) == want["n_hits"] and sha(mine.tobytes()) == want["sha256"], \
+            diff_chunk(w.subset(ids), canonical(_renumber(mine, ids)), mode, 0, 2000)
+
+
+def _renumber(h, ids):
+    out = h.copy()
+    out["read_id"] = np.searchsorted(ids, out["read_id"])
+    return out

@@ -119,10 +119,17 @@ def test_index_arrays_match_definition(pn, sess, wbits, case):
         next4 |= letter.astype(np.int64) << (6 - 2 * t)
     assert np.array_equal((lo >> 24) & 0xff, next4)
     assert np.all((lo & ((1 << 21) - 1)) == 0)
-    # inside a slice entries are in the order (read, offset)
+    # inside a slice: for q <= 12 ordered by the letters after the q-gram
+    # (their 9-bit code: all four letters 0-255, else 256 + three, 320 +
+    # two, 336 + one, 340 none), then by (read, offset); else by (read, offset)
+    n4 = (lo >> 24) & 0xff
+    code = np.select([nav == 4, nav == 3, nav == 2, nav == 1],
+                     [n4, 256 + (n4 >> 2), 320 + (n4 >> 4), 336 + (n4 >> 6)], 340)
+    if not pn.pn_index_get_info(idx)["after_sorted"]:
+        code = np.zeros_like(code)
     same = bucket[1:] == bucket[:-1]
-    ro = r * 256 + o
-    assert np.all(ro[1:][same] > ro[:-1][same])
+    order = (code << 40) | (r << 8) | o
+    assert np.all(order[1:][same] > order[:-1][same])
 
 
 def test_index_large_scans_by_definition(pn, sess):
@@ -409,44 +416,6 @@ def test_repeat_runs_are_identical(pn, sess):
     assert a.tobytes() == b.tobytes()
 
 
-# ---------------------------------------------------------------------------
-# full size: 100 Mbp repeat reference, 1 M reads, the benchmark's launch path
-
-
-def test_full_size_repeat_sampled(pn, sess):
-    import torch
-    say("generating the 100 Mbp / 1 M read workload")
-    w = synth.make("repeat")
-    ref = sess.ref(w.ref)
-    dev = torch.device("cuda:0")
-    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
-    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(12345)
-    sample = np.sort(rng.choice(w.n_reads, 1000, replace=False))
-    sub = w.subset(sample)
-    idx = pn.pn_index_build_dev(sess.ctx, d_reads, d_offs, 12, 64)
-    try:
-        out = torch.zeros(12 * 40_000_000, dtype=torch.uint8, device=dev)
-        for mode in (0, 1):
-            say(f"full-size map mode={mode}")
-            n = pn.pn_map_dev(sess.ctx, ref, idx, 5, out, mode)
-            got = np.frombuffer(out[:n * 12].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
-            keep = np.isin(got["read_id"], sample)
-            mine = got[keep].copy()
-            mine["read_id"] = np.searchsorted(sample, mine["read_id"])
-            say(f"oracle on {len(sample)} sampled reads")
-            orc = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, 5, best=bool(mode))
-            assert_hits_equal(mine, orc)
-            # properties at full size: sorted, unique, errors within budget
-            key = (got["read_id"].astype(np.int64) << 33) | (got["strand"].astype(np.int64) << 32) | \
-                got["end_pos"].astype(np.int64)
-            assert np.all(np.diff(key) > 0) and got["errors"].max() <= 5
-            say(f"mode={mode}: {n} hits, {len(np.unique(got['read_id']))} reads mapped")
-    finally:
-        pn.pn_index_free(idx)
-
-
 def test_low_complexity_reads_equal_definition(pn, sess):
     """Reads dominated by homopolymers and dinucleotide repeats, with errors,
     against a reference full of such runs: the seed rules (low-complexity
@@ -510,3 +479,41 @@ def test_repeat_family_in_both_orientations(pn, sess):
     w = synth.Workload("family", synth.ALPHABET[ref].tobytes(), r1 + r2, offsets, 12,
                        np.full(700, 5, dtype=np.uint8))
     map_both(pn, sess, w)
+
+
+def test_repeat_family_reads_order_slices_by_next_letters(pn, sess):
+    """Reads from interspersed repeat families (the human-shaped generator,
+    9 Mbp, 100k reads) put many occurrences into long slices, so the index
+    orders each slice by the letters after the q-gram and filtration
+    searches the long ones (pn::Lists).  The hits equal those of q = 13,
+    whose index is never ordered that way, and the oracle on a sample."""
+    w = synth.make("human", scale=0.003, n_reads=100_000)
+    say(f"human-shaped L={len(w.ref)} reads={w.n_reads}")
+    ref = sess.ref(w.ref)
+    i12 = sess.index(w.reads, w.offsets, 12)
+    i13 = sess.index(w.reads, w.offsets, 13)
+    assert pn.pn_index_get_info(i12)["after_sorted"] == 1
+    assert pn.pn_index_get_info(i13)["after_sorted"] == 0
+    I, S, Sp, O = pn.pn_index_export(i12)
+    lo = (O & np.uint64(0xffffffff)).astype(np.int64)
+    nav, n4 = (lo >> 21) & 7, (lo >> 24) & 0xff
+    code = np.select([nav == 4, nav == 3, nav == 2, nav == 1],
+                     [n4, 256 + (n4 >> 2), 320 + (n4 >> 4), 336 + (n4 >> 6)], 340)
+    _, r, o = decode_O(O)
+    bucket = np.repeat(np.arange(len(Sp) - 1), np.diff(Sp.astype(np.int64)))
+    same = bucket[1:] == bucket[:-1]
+    order = (code << 40) | (r << 8) | o
+    assert np.all(order[1:][same] > order[:-1][same])
+    rng = np.random.default_rng(31)
+    sample = np.sort(rng.choice(w.n_reads, 3000, replace=False))
+    sub = w.subset(sample)
+    for mode in (0, 1):
+        a = pn.pn_map(sess.ctx, ref, i12, 5, mode)
+        b = pn.pn_map(sess.ctx, ref, i13, 5, mode)
+        assert_hits_equal(a, b)
+        mine = a[np.isin(a["read_id"], sample)].copy()
+        mine["read_id"] = np.searchsorted(sample, mine["read_id"])
+        assert_hits_equal(mine, oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, 5,
+                                                    best=bool(mode)))
+    st = pn.pn_ctx_get_stats(sess.ctx)
+    say(f"seeds {st['n_seeds']} visited {st['n_visited']} candidates {st['n_candidates']}")

@@ -53,8 +53,8 @@ def alone(pn, sess, ref, r, q):
     return pn.pn_map(sess.ctx, ref, idx, r["k_per_read"], int(r["best"]))
 
 
-def serve(pn, ref, reqs, q, **cfg):
-    srv = pn.pn_server_create(ref, q, **cfg)
+def serve(pn, ctx, ref, reqs, q, **cfg):
+    srv = pn.pn_server_create(ctx, ref, q, **cfg)
     try:
         tickets = [pn.pn_server_submit(srv, r["reads"], r["offsets"], r["k_per_read"], int(r["best"]))
                    for r in reqs]
@@ -69,7 +69,7 @@ def test_batched_results_equal_alone(pn, env):
     w, sess, ref, reqs = env
     q = 10
     say(f"serving {len(reqs)} requests, {sum(len(r['offsets']) - 1 for r in reqs)} reads, 2 slots")
-    out, stats = serve(pn, ref, reqs, q, slots=2, max_batch_reads=8000)
+    out, stats = serve(pn, sess.ctx, ref, reqs, q, slots=2, max_batch_reads=8000)
     say(f"stats {stats}")
     assert stats["requests"] == len(reqs)
     assert stats["batches"] < len(reqs)  # requests were merged
@@ -87,11 +87,11 @@ def test_serial_and_budget_limited_equal_batched(pn, env):
     w, sess, ref, reqs = env
     q = 10
     sub = reqs[:6]
-    serial, st1 = serve(pn, ref, sub, q, slots=1, max_batch_reads=1)
+    serial, st1 = serve(pn, sess.ctx, ref, sub, q, slots=1, max_batch_reads=1)
     assert st1["batches"] == len(sub)
     # a budget that holds about one request's working set at a time
     biggest = max(12 * int(r["offsets"][-1]) + 4096 * (len(r["offsets"]) - 1) for r in sub)
-    tight, st2 = serve(pn, ref, sub, q, slots=2, hbm_budget=biggest + (16 << 20) + 1)
+    tight, st2 = serve(pn, sess.ctx, ref, sub, q, slots=2, hbm_budget=biggest + (16 << 20) + 1)
     assert st2["requests"] == len(sub)
     for (a, _), (b, _) in zip(serial, tight):
         assert_same(a, b)
@@ -99,7 +99,7 @@ def test_serial_and_budget_limited_equal_batched(pn, env):
 
 def test_submit_checks(pn, env):
     w, sess, ref, reqs = env
-    srv = pn.pn_server_create(ref, 10, slots=1, hbm_budget=64 << 20)
+    srv = pn.pn_server_create(sess.ctx, ref, 10, slots=1, hbm_budget=64 << 20)
     try:
         reads = b"ACGT" * 25
         offs = np.array([0, 100], dtype=np.uint64)
@@ -125,5 +125,44 @@ def test_submit_checks(pn, env):
         assert (hits["read_id"] == 0).all()
         with pytest.raises(pn.PnError):
             pn.pn_server_wait(srv, t)  # redeemed
+    finally:
+        pn.pn_server_destroy(srv)
+
+
+def test_poll_is_non_blocking_and_equals_alone(pn, env):
+    """pn_poll returns PN_PENDING until a request is done, then its hits,
+    which equal the request mapped alone (continuous batching: requests
+    submitted while others run are merged into later batches)."""
+    import time
+    w, sess, ref, reqs = env
+    q = 10
+    srv = pn.pn_server_create(sess.ctx, ref, q, slots=2, max_batch_reads=6000)
+    try:
+        tickets = [pn.pn_server_submit(srv, r["reads"], r["offsets"], r["k_per_read"],
+                                       int(r["best"])) for r in reqs]
+        first = pn.pn_poll(srv, tickets[-1])  # the last request cannot be done yet, or is
+        got = {}
+        if first is not None:
+            got[len(reqs) - 1] = first
+        pending_seen = first is None
+        t0 = time.time()
+        while len(got) < len(reqs):
+            assert time.time() - t0 < 120, "requests did not finish"
+            for i, t in enumerate(tickets):
+                if i in got:
+                    continue
+                res = pn.pn_poll(srv, t)
+                if res is None:
+                    pending_seen = True
+                else:
+                    got[i] = res
+            time.sleep(0.001)
+        assert pending_seen
+        for i, r in enumerate(reqs):
+            hits, lat = got[i]
+            assert lat >= 0
+            assert_same(hits, alone(pn, sess, ref, r, q))
+        with pytest.raises(pn.PnError):
+            pn.pn_poll(srv, tickets[0])  # redeemed
     finally:
         pn.pn_server_destroy(srv)

@@ -26,8 +26,12 @@ OPS_PER_ROW = 22
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
+SUB_BATCH = 1 << 21  # reads per index (the read field of an O entry has 21 bits)
 
 WORKLOADS = {
+    "human": "3 Gbp reference (GC 41%, 45% interspersed repeat copies of a 300 bp and a 6 kbp "
+             "family at 10-20% divergence), both strands (6 Gbp scanned), 10 M reads x 100 bp "
+             "at 3% error, q=12, k=5, reads indexed in sub-batches of 2^21",
     "repeat": "100 Mbp reference with 5% segmental copies and 0.5% homopolymer runs, "
               "1 M reads x 100 bp at 4% error, both strands, q=12, k=5",
     "tiny": "1 Mbp i.i.d. reference, 10,000 reads x 100 bp at 2% error, q=10, k=5",
@@ -255,11 +259,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="repeat", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="human", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-pcie", action="store_true")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--mode", default="all", choices=["all", "best"])
     ap.add_argument("--w", type=int, default=64)
-    ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="reads the CPU oracle maps (default: 200 for human, else 10000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
@@ -296,45 +302,93 @@ def main():
     log(f"workload {args.workload}: L={len(w.ref)} reads={w.n_reads} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
-    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
     uniform_k = len(set(w.k_per_read.tolist())) == 1
-    d_k = None if uniform_k else torch.from_numpy(w.k_per_read.copy()).to(dev)
     k = int(w.k_per_read[0]) if uniform_k else -1
     mode = pn.PN_ALL_HITS if args.mode == "all" else pn.PN_BEST_STRATUM
+    # sub-batches of at most 2^21 reads (one index holds that many), staged
+    # on the device before timing; a step maps one sub-batch against the
+    # whole reference, and the steps take the sub-batches in turn
+    parts = []
+    for a in range(0, w.n_reads, SUB_BATCH):
+        b = min(w.n_reads, a + SUB_BATCH)
+        lo, hi = int(w.offsets[a]), int(w.offsets[b])
+        d_o = torch.from_numpy((w.offsets[a:b + 1] - lo).astype(np.int64)).to(dev)
+        d_kk = None if uniform_k else torch.from_numpy(w.k_per_read[a:b].copy()).to(dev)
+        parts.append((a, b, d_reads[lo:hi], d_o, d_kk))
     torch.cuda.synchronize()
 
     ctx = pn.pn_ctx_create(0)
+    t0 = time.time()
     ref = pn.pn_ref_load(ctx, w.ref)
     pn.pn_ref_prepare(ref, w.q)  # reference-side precompute, outside the timed region
-    out = torch.empty(12 * max(1 << 20, 64 * w.n_reads), dtype=torch.uint8, device=dev)
+    log(f"reference loaded and prepared ({time.time() - t0:.1f}s)")
+    out = torch.empty(12 * max(1 << 20, 64 * min(w.n_reads, SUB_BATCH)), dtype=torch.uint8,
+                      device=dev)
     pn.pn_ctx_set_timing(ctx, True)
     n_hits = 0
+    last_part = 0
 
-    def step():
-        nonlocal n_hits
-        idx = pn.pn_index_build_dev(ctx, d_reads, d_offs, w.q, args.w)
+    def step(i, m=mode):
+        nonlocal n_hits, last_part
+        a, b, d_r, d_o, d_kk = parts[i % len(parts)]
+        idx = pn.pn_index_build_dev(ctx, d_r, d_o, w.q, args.w)
         try:
-            n_hits = pn.pn_map_dev(ctx, ref, idx, k, out, mode, d_k=d_k)
+            n_hits = pn.pn_map_dev(ctx, ref, idx, k, out, m, d_k=d_kk)
         finally:
             pn.pn_index_free(idx)
+        last_part = i % len(parts)
+        return b - a
 
     for i in range(args.warmup):
-        step()
+        step(i)
         log(f"warmup {i + 1}/{args.warmup} done")
     pn.pn_ctx_get_stats(ctx, reset=True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    done_reads = 0
     for i in range(args.steps):
-        step()
+        done_reads += step(i)
+        if len(parts) > 1:
+            log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t_end = time.perf_counter()
     st = pn.pn_ctx_get_stats(ctx)
     ms_per_step = (t_end - t_start) * 1000.0 / args.steps
-    reads_per_s = w.n_reads / (ms_per_step / 1000.0)
-    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:.3e} reads/s, hits {n_hits}")
-
+    reads_per_s = done_reads / (t_end - t_start)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {reads_per_s:.3e} reads/s, "
+        f"hits {n_hits} (last step)")
+    step_reads = done_reads / args.steps
     hits = np.frombuffer(out[:12 * n_hits].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
-    mapped = len(np.unique(hits["read_id"])) / max(1, w.n_reads)
+    pa, pb = parts[last_part][0], parts[last_part][1]
+    mapped = len(np.unique(hits["read_id"])) / max(1, pb - pa)
+    pn.pn_ctx_set_timing(ctx, False)
+
+    # the other mode, timed over fewer steps (the same filtration and
+    # verification; only the last pass differs)
+    other = pn.PN_BEST_STRATUM if mode == pn.PN_ALL_HITS else pn.PN_ALL_HITS
+    k2 = max(1, args.steps // 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2 = sum(step(i, other) for i in range(k2))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    other_mode = {"mode": "best" if other == pn.PN_BEST_STRATUM else "all", "steps": k2,
+                  "ms_per_step": (t1 - t0) * 1000.0 / k2, "reads_per_s": r2 / (t1 - t0)}
+    log(f"{other_mode['mode']} mode: {other_mode['ms_per_step']:.2f} ms/step, "
+        f"{other_mode['reads_per_s']:.3e} reads/s")
+
+    # PCIe-inclusive: every read from host memory through pn_map_batched
+    # (sub-batches copied in, indexed, mapped, hits copied back), once
+    pcie = None
+    if not args.no_pcie:
+        t0 = time.perf_counter()
+        hb = pn.pn_map_batched(ctx, ref, w.reads, w.offsets, w.k_per_read, mode)
+        t1 = time.perf_counter()
+        pcie = {"reads_per_s": w.n_reads / (t1 - t0), "seconds": t1 - t0, "hits": int(len(hb)),
+                "path": "pn_map_batched: host reads in, sorted hits back on the host"}
+        log(f"PCIe-inclusive (pn_map_batched, all {w.n_reads} reads): "
+            f"{pcie['reads_per_s']:.3e} reads/s")
+        del hb
 
     K = args.steps
     stage_ms = {s: st["ms"][s] / K for s in pn.STAGES}
@@ -369,7 +423,10 @@ def main():
             ent, cand = st["n_visited_heavy"] / K, st["n_candidates_heavy"] / K
             nbytes = ent * 4 + cand * 8
         else:
-            probe_bytes = 2 * (1 / 16 + args.w / 8 + 4 + 8)
+            # per scanned position: 1/8 byte of packed reference (two bits
+            # per forward position, shared by the two strands), I word, S
+            # entry, S' pair
+            probe_bytes = 2 * (1 / 8 + args.w / 8 + 4 + 8)
             nbytes = n_pos * probe_bytes + ent * 4 + cand * 8
         achieved = nbytes / max(1.0, launches[dominant]) / (per_launch_ms / 1000.0)
         wkey = f"{args.workload}:{args.scale}:{args.w}"
@@ -378,6 +435,8 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK_BPS / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_BPS,
                 "traffic": None if tb is None else tb / (per_launch_ms / 1000.0) / 1e9,
+                "counter_frac": None if tb is None else
+                tb / (per_launch_ms / 1000.0) / HBM_PEAK_BPS,
                 "traffic_gb_per_launch": None if tb is None else tb / 1e9,
                 "algorithmic_gb_per_launch": nbytes / max(1.0, launches[dominant]) / 1e9,
                 "kernel": kernel, "avg_launch_ms": per_launch_ms}
@@ -386,7 +445,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(2024)
-        m = min(args.cpu_sample, w.n_reads)
+        m = min(args.cpu_sample or (200 if args.workload == "human" else 10000), w.n_reads)
         sample = np.sort(rng.choice(w.n_reads, m, replace=False))
         sub = w.subset(sample)
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -422,7 +481,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload] + (f" (scale {args.scale})" if args.scale != 1 else ""),
                    "mode": args.mode, "q": w.q, "w": args.w, "n_reads": w.n_reads,
-                   "ref_len": len(w.ref)},
+                   "ref_len": len(w.ref), "sub_batch_reads": min(w.n_reads, SUB_BATCH),
+                   "reads_per_step": step_reads},
+        "other_mode": other_mode,
+        "pcie_inclusive": pcie,
         "roofline": roof,
         "cpu_baseline": cpu,
         "latency_ms": None if serving is None else {"p50": serving["p50_ms"],

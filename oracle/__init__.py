@@ -72,6 +72,8 @@ def _load():
     lib.orc_map_filtered.argtypes = [P, u64, P, P, u32, i32, P, i32, i32, P, P]
     lib.orc_map_sellers.restype = i32
     lib.orc_map_sellers.argtypes = [P, u64, P, P, u32, P, i32, i32, P, P]
+    lib.orc_align.restype = i32
+    lib.orc_align.argtypes = [P, u64, P, u32, u64, i32, P, P, P]
     lib.orc_free.restype = None
     lib.orc_free.argtypes = [P]
     _lib = lib
@@ -290,3 +292,24 @@ def best_stratum(hits: np.ndarray) -> np.ndarray:
             minv[r] = v
     keep = np.array([v == minv[r] for r, v in zip(hits["read_id"], hits["errors"])], dtype=bool)
     return hits[keep]
+
+
+OPS = "=XID"
+
+
+def align(text_codes: np.ndarray, read_codes: np.ndarray, end: int, span_max: int):
+    """Start and alignment of a hit ending at text position `end` (codes of
+    the strand's text and of the read): (start, errors, ops string over
+    '=', 'X', 'I', 'D', first op first).  Text spans up to span_max letters
+    are considered (a hit with e errors spans at most n + e letters)."""
+    lib = _load()
+    t = np.ascontiguousarray(text_codes, dtype=np.uint8)
+    x = np.ascontiguousarray(read_codes, dtype=np.uint8)
+    ops = np.empty(len(x) + span_max + 1, dtype=np.uint8)
+    st = ctypes.c_int64()
+    er = ctypes.c_int32()
+    m = lib.orc_align(_ptr(t), len(t), _ptr(x), len(x), int(end), int(span_max),
+                      ctypes.byref(st), ctypes.byref(er), _ptr(ops))
+    if m < 0:
+        raise ValueError("orc_align failed")
+    return int(st.value), int(er.value), "".join(OPS[o] for o in ops[:m])

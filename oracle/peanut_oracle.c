@@ -47,6 +47,22 @@
  *    the read prefix of length i and any reference substring ending at j),
  *    reporting every (r, s, e = j-1, E[n][j]) with E[n][j] <= k_r.
  *
+ *  - orc_align: the start and the alignment of one hit (Section 3.3 runs
+ *    the verification backwards from a hit's end to find where it starts;
+ *    the actual alignment is made in postprocessing, Section 3.4).  For a
+ *    read x of length n ending at text position e, the read reversed is
+ *    aligned to the text read backwards from e with the same unit costs:
+ *    F[i][j] = edit distance of the last i read letters and the j text
+ *    letters ending at e (F[0][j] = j, F[i][0] = i, no free start).  The
+ *    hit's error count is the least F[n][j]; the start is e + 1 - j for the
+ *    smallest such j (the latest start, the shortest text span).  The
+ *    alignment is read off from (n, j) back to (0, 0), which walks the read
+ *    from its first letter on; of the predecessors whose value explains the
+ *    cell, the diagonal one (a match '=' or a substitution 'X') is taken
+ *    first, then the one above (a read letter not in the text, 'I'), then
+ *    the one to the left (a text letter not in the read, 'D').  That rule
+ *    makes the alignment unique.
+ *
  * Hit records are 12-byte structs (read_id u32, end_pos u32, strand u8,
  * errors u8, 2 padding bytes), sorted by (read_id, strand, end_pos).
  */
@@ -594,6 +610,65 @@ int orc_map_sellers(const uint8_t *ref, uint64_t L, const uint8_t *codes, const 
     int st = finish_hits(keys, total, n_reads, best, out, n_out);
     free(keys);
     return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* start and alignment of one hit, by the full matrix of the reversed read  */
+
+/* ops: 0 '=' (match), 1 'X' (substitution), 2 'I' (read letter not in the
+ * text), 3 'D' (text letter not in the read), first op first.  Returns the
+ * number of ops (<= n + span), with *start and *errors; -1 if span_max < 0
+ * or memory runs out.  Text columns considered: j = 0 .. min(e + 1,
+ * span_max). */
+int orc_align(const uint8_t *text, uint64_t L, const uint8_t *x, uint32_t n, uint64_t e,
+              int span_max, int64_t *start, int32_t *errors, uint8_t *ops) {
+    if (span_max < 0 || e >= L) return -1;
+    const int J = (uint64_t)span_max < e + 1 ? span_max : (int)(e + 1);
+    const int W = J + 1;
+    int *F = (int *)malloc(sizeof(int) * (size_t)(n + 1) * (size_t)W);
+    if (!F) return -1;
+#define ORC_F(i, j) F[(size_t)(i) * (size_t)W + (size_t)(j)]
+    for (int j = 0; j <= J; j++) ORC_F(0, j) = j;
+    for (uint32_t i = 1; i <= n; i++) {
+        const uint8_t xi = x[n - i]; /* the i-th letter from the read's end */
+        ORC_F(i, 0) = (int)i;
+        for (int j = 1; j <= J; j++) {
+            const uint8_t tj = text[e + 1 - (uint64_t)j]; /* the j-th letter back from e */
+            int v = ORC_F(i - 1, j - 1) + (xi != tj);
+            if (ORC_F(i - 1, j) + 1 < v) v = ORC_F(i - 1, j) + 1;
+            if (ORC_F(i, j - 1) + 1 < v) v = ORC_F(i, j - 1) + 1;
+            ORC_F(i, j) = v;
+        }
+    }
+    int best = 0;
+    for (int j = 1; j <= J; j++)
+        if (ORC_F(n, j) < ORC_F(n, best)) best = j;
+    *errors = ORC_F(n, best);
+    *start = (int64_t)e + 1 - best;
+    int m = 0;
+    int i = (int)n, j = best;
+    while (i > 0 || j > 0) {
+        const int v = ORC_F(i, j);
+        if (i > 0 && j > 0) {
+            const int sub = x[n - (uint32_t)i] != text[e + 1 - (uint64_t)j];
+            if (ORC_F(i - 1, j - 1) + sub == v) {
+                ops[m++] = (uint8_t)sub;
+                i--;
+                j--;
+                continue;
+            }
+        }
+        if (i > 0 && ORC_F(i - 1, j) + 1 == v) {
+            ops[m++] = 2;
+            i--;
+            continue;
+        }
+        ops[m++] = 3;
+        j--;
+    }
+#undef ORC_F
+    free(F);
+    return m;
 }
 
 void orc_free(void *p) { free(p); }

@@ -48,6 +48,16 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kMiscWords = kLongEntries + 1
 };
 
+// the mapping path's grow-only buffers and output-region capacities
+// (pn::kShards regions each; they grow on demand)
+struct Workspace {
+    Buf cands, longc, heavy, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side,
+        side_meta, out_hits, out_best, lax, laxO;
+    uint64_t cand_rcap = 1ull << 18;
+    uint64_t rec_rcap = 1ull << 14;
+    uint64_t heavy_rcap = 1ull << 12;  // per region: items of occurrence lists set aside
+};
+
 struct PendingStage {
     int stage;
     hipEvent_t a, b;
@@ -64,13 +74,8 @@ struct pn_ctx {
     uint64_t *misc = nullptr;             // device scratch words (MiscSlot)
     uint64_t *hmisc = nullptr;            // pinned host mirror
     // grow-only workspace of the mapping path
-    Buf cands, longc, heavy, keys, keys_tmp, sort_temp, flags, pos, partials, minv, rinfo, side, side_meta,
-        out_hits, out_best, lax, laxO;
+    Workspace ws;
     bool sub_on = false;  // lax lists made for the current mapping call
-    // capacities per output region (pn::kShards regions; grow on demand)
-    uint64_t cand_rcap = 1ull << 18;
-    uint64_t rec_rcap = 1ull << 14;
-    uint64_t heavy_rcap = 1ull << 12;  // per region: items of occurrence lists set aside
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -734,9 +739,9 @@ int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 // per-read seed rules (with the k / lemma check) and the low-complexity side
 // lists; synchronises once to report a bad k or a lemma violation
 int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, hipStream_t st) {
-    PN_CHECK(ensure(c, c->rinfo, (uint64_t)x->n_reads + 1));
-    PN_CHECK(ensure(c, c->side, std::max<uint64_t>(x->lc_total, 1) * 8));
-    PN_CHECK(ensure(c, c->side_meta, 17 * pn::kLcPatterns * 4));
+    PN_CHECK(ensure(c, c->ws.rinfo, (uint64_t)x->n_reads + 1));
+    PN_CHECK(ensure(c, c->ws.side, std::max<uint64_t>(x->lc_total, 1) * 8));
+    PN_CHECK(ensure(c, c->ws.side_meta, 17 * pn::kLcPatterns * 4));
     uint32_t starts[pn::kLcPatterns];
     uint64_t at = 0;
     for (int i = 0; i < pn::kLcPatterns; i++) {
@@ -744,27 +749,27 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
         at += x->lc_size[i];
     }
     zero_misc(c, st);
-    PN_TRY(hipMemcpyAsync(c->side_meta.p, starts, sizeof(starts), hipMemcpyHostToDevice, st));
+    PN_TRY(hipMemcpyAsync(c->ws.side_meta.p, starts, sizeof(starts), hipMemcpyHostToDevice, st));
     PnIndexDev ix = index_desc(x);
     const int tok = stage_begin(c, st, PN_STAGE_RULES);
-    pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->rinfo.p, (uint32_t *)&c->misc[kStatus],
+    pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->ws.rinfo.p, (uint32_t *)&c->misc[kStatus],
                           st);
-    pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->rinfo.p, st);
+    pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->ws.rinfo.p, st);
     // 16 region starts, 16 x 6 class bounds, then scratch for the side lists
-    uint32_t *meta = (uint32_t *)c->side_meta.p;
+    uint32_t *meta = (uint32_t *)c->ws.side_meta.p;
     pn::launch_fill_u32(meta + pn::kLcPatterns, 6 * pn::kLcPatterns, 0u, st);
     if (x->n_reads)
-        pn::launch_lc_side(ix, (const uint8_t *)c->rinfo.p, (unsigned long long *)c->side.p, meta,
+        pn::launch_lc_side(ix, (const uint8_t *)c->ws.rinfo.p, (unsigned long long *)c->ws.side.p, meta,
                            meta + pn::kLcPatterns, meta + 7 * pn::kLcPatterns, st);
     // lax lists: an index whose slices are ordered by the letters after the
     // q-gram is searched in its long slices (see pn::Lists)
     c->sub_on = x->after_sorted && x->n_reads && x->n_distinct;
     if (c->sub_on) {
-        PN_CHECK(ensure(c, c->lax, (x->n_distinct + 1) * sizeof(uint2)));
-        PN_CHECK(ensure(c, c->laxO, std::max<uint64_t>(x->n_qgrams, 1) * 8));
+        PN_CHECK(ensure(c, c->ws.lax, (x->n_distinct + 1) * sizeof(uint2)));
+        PN_CHECK(ensure(c, c->ws.laxO, std::max<uint64_t>(x->n_qgrams, 1) * 8));
         pn::launch_fill_u32((uint32_t *)&c->misc[kLaxCount], 2, 0u, st);
-        pn::launch_lax_lists(ix, x->n_distinct, pn::kSubMin, (uint2 *)c->lax.p,
-                             (unsigned long long *)c->laxO.p,
+        pn::launch_lax_lists(ix, x->n_distinct, pn::kSubMin, (uint2 *)c->ws.lax.p,
+                             (unsigned long long *)c->ws.laxO.p,
                              (unsigned long long *)&c->misc[kLaxCount], st);
     }
     stage_end(c, st, tok, (x->n_reads ? 7 : 3) + (c->sub_on ? 2 : 0));
@@ -776,9 +781,9 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
 }
 
 pn::Lists lists_of(const pn_ctx *c) {
-    const uint32_t *meta = (const uint32_t *)c->side_meta.p;
-    return pn::Lists{(const unsigned long long *)c->side.p, meta + pn::kLcPatterns,
-                     (const unsigned long long *)c->laxO.p, (const uint2 *)c->lax.p, pn::kSubMin,
+    const uint32_t *meta = (const uint32_t *)c->ws.side_meta.p;
+    return pn::Lists{(const unsigned long long *)c->ws.side.p, meta + pn::kLcPatterns,
+                     (const unsigned long long *)c->ws.laxO.p, (const uint2 *)c->ws.lax.p, pn::kSubMin,
                      c->sub_on ? 1 : 0};
 }
 
@@ -786,12 +791,12 @@ pn::Lists lists_of(const pn_ctx *c) {
 int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn::RefQDev &Pall,
                        uint64_t a, uint64_t b, hipStream_t st) {
     pn::RefQDev P{Pall.keys + a, Pall.ctx ? Pall.ctx + a : nullptr, b - a};
-    PN_CHECK(ensure(c, c->heavy, pn::kShards * c->heavy_rcap * 2 * sizeof(uint4)));
+    PN_CHECK(ensure(c, c->ws.heavy, pn::kShards * c->ws.heavy_rcap * 2 * sizeof(uint4)));
     pn::launch_fill_u32((uint32_t *)&c->misc[kHeavyCounts], 2 * pn::kShards, 0u, st);
-    pn::FilterOut fo{(uint2 *)c->cands.p,
-                     {(unsigned long long *)&c->misc[kCandCounts], c->cand_rcap},
-                     (uint4 *)c->heavy.p,
-                     {(unsigned long long *)&c->misc[kHeavyCounts], c->heavy_rcap},
+    pn::FilterOut fo{(uint2 *)c->ws.cands.p,
+                     {(unsigned long long *)&c->misc[kCandCounts], c->ws.cand_rcap},
+                     (uint4 *)c->ws.heavy.p,
+                     {(unsigned long long *)&c->misc[kHeavyCounts], c->ws.heavy_rcap},
                      pn::filter_heavy_min(x->n_qgrams, x->q),
                      (unsigned long long *)&c->misc[kFilterStats]};
     int tok = stage_begin(c, st, PN_STAGE_FILTER_EMIT);
@@ -867,21 +872,21 @@ int ensure_keep(pn_ctx *c, Buf &b, size_t bytes, size_t keep, hipStream_t st) {
 }
 
 // Validation (both passes) of candidates, records into the sharded
-// c->keys_tmp.  With `filter`, the candidates come from filtration of the
+// c->ws.keys_tmp.  With `filter`, the candidates come from filtration of the
 // reference's position set, part by part: each part is filtered (and its
 // candidate counts checked: a buffer that overflowed is grown, or the part
 // split when its output would pass the bounds above, and the part filtered
 // again), verified (records that overflowed: grown, verified again) and its
-// records gathered into c->keys before the next part, so that candidate
+// records gathered into c->ws.keys before the next part, so that candidate
 // buffers stay bounded however many candidates the whole reference yields.
-// Without `filter`, the n_in candidates already in c->cands are verified.
-// Leaves all records, sorted, in c->keys and their count in *n_rec.
+// Without `filter`, the n_in candidates already in c->ws.cands are verified.
+// Leaves all records, sorted, in c->ws.keys and their count in *n_rec.
 constexpr uint64_t kFirstPart = 1ull << 30;  // position-set entries filtered at once at first
 
 int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
                     bool filter, uint64_t n_in, hipStream_t st, uint64_t *n_rec) {
     const int ebits = key_ebits(ref->L);
-    c->rec_rcap = std::max<uint64_t>(c->rec_rcap, (16ull * x->n_reads) / pn::kShards + 4096);
+    c->ws.rec_rcap = std::max<uint64_t>(c->ws.rec_rcap, (16ull * x->n_reads) / pn::kShards + 4096);
     pn::RefQDev P{nullptr, nullptr, 0};
     if (filter) PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
     const uint32_t regions = filter ? pn::kShards : 1;
@@ -892,9 +897,9 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         if (++attempts > 64) return PN_ENOMEM;
         const uint64_t b = filter ? std::min(end, a + part) : end;
         uint64_t cand_total = filter ? 0 : n_in;
-        const uint64_t in_rcap = filter ? c->cand_rcap : std::max<uint64_t>(n_in, 1);
-        PN_CHECK(ensure(c, c->cands, regions * in_rcap * sizeof(uint2)));
-        PN_CHECK(ensure(c, c->longc, regions * in_rcap * sizeof(uint2)));
+        const uint64_t in_rcap = filter ? c->ws.cand_rcap : std::max<uint64_t>(n_in, 1);
+        PN_CHECK(ensure(c, c->ws.cands, regions * in_rcap * sizeof(uint2)));
+        PN_CHECK(ensure(c, c->ws.longc, regions * in_rcap * sizeof(uint2)));
         zero_counts(c, kCandCounts, st);
         FilterWork fw;
         if (filter) {
@@ -909,12 +914,12 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
                 part = std::max<uint64_t>(1, (b - a) / 2);
                 again = true;
             } else {
-                if (cand_max > c->cand_rcap) {
-                    c->cand_rcap = cand_max + cand_max / 4;
+                if (cand_max > c->ws.cand_rcap) {
+                    c->ws.cand_rcap = cand_max + cand_max / 4;
                     again = true;
                 }
-                if (hmax > c->heavy_rcap) {
-                    c->heavy_rcap = hmax + hmax / 4;
+                if (hmax > c->ws.heavy_rcap) {
+                    c->ws.heavy_rcap = hmax + hmax / 4;
                     again = true;
                 }
             }
@@ -929,31 +934,31 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         uint64_t got = 0;
         for (int vattempt = 0;; vattempt++) {
             if (vattempt >= 8) return PN_ENOMEM;
-            PN_CHECK(ensure(c, c->keys_tmp, pn::kShards * c->rec_rcap * 8));
+            PN_CHECK(ensure(c, c->ws.keys_tmp, pn::kShards * c->ws.rec_rcap * 8));
             pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
             zero_counts(c, kRecCounts, st);
             zero_counts(c, kLongCounts, st);
-            pn::VerifyIn in{(const uint2 *)c->cands.p,
+            pn::VerifyIn in{(const uint2 *)c->ws.cands.p,
                             (const unsigned long long *)&c->misc[kCandCounts], regions, in_rcap};
-            pn::VerifyOut vo{(unsigned long long *)c->keys_tmp.p,
-                             {(unsigned long long *)&c->misc[kRecCounts], c->rec_rcap},
+            pn::VerifyOut vo{(unsigned long long *)c->ws.keys_tmp.p,
+                             {(unsigned long long *)&c->misc[kRecCounts], c->ws.rec_rcap},
                              (unsigned long long *)&c->misc[kVerifyRows], ebits};
             int tok = stage_begin(c, st, PN_STAGE_VERIFY);
             pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
-                              (uint2 *)c->longc.p, (unsigned long long *)&c->misc[kLongCounts],
+                              (uint2 *)c->ws.longc.p, (unsigned long long *)&c->misc[kLongCounts],
                               true, st);
             stage_end(c, st, tok, 1);
             vo.rows = (unsigned long long *)&c->misc[kVerifyRowsLong];
             tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
             pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
-                              (uint2 *)c->longc.p, (unsigned long long *)&c->misc[kLongCounts],
+                              (uint2 *)c->ws.longc.p, (unsigned long long *)&c->misc[kLongCounts],
                               false, st);
             stage_end(c, st, tok, 1);
             PN_CHECK(read_misc(c, st));
             uint64_t rec_max;
             region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
-            if (rec_max <= c->rec_rcap) break;
-            c->rec_rcap = rec_max + rec_max / 4;
+            if (rec_max <= c->ws.rec_rcap) break;
+            c->ws.rec_rcap = rec_max + rec_max / 4;
         }
         if (filter) {
             c->stats.n_seeds += fw.seeds;
@@ -966,11 +971,11 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         c->stats.verify_rows += c->hmisc[kVerifyRows] + c->hmisc[kVerifyRowsLong];
         c->stats.verify_rows_long += c->hmisc[kVerifyRowsLong];
         c->stats.n_records += got;
-        PN_CHECK(ensure_keep(c, c->keys, std::max<uint64_t>(total + got, 1) * 8, total * 8, st));
+        PN_CHECK(ensure_keep(c, c->ws.keys, std::max<uint64_t>(total + got, 1) * 8, total * 8, st));
         const int tok = stage_begin(c, st, PN_STAGE_SORT);
-        pn::launch_gather_shards((const unsigned long long *)c->keys_tmp.p,
+        pn::launch_gather_shards((const unsigned long long *)c->ws.keys_tmp.p,
                                  (const unsigned long long *)&c->misc[kRecCounts], pn::kShards,
-                                 c->rec_rcap, (unsigned long long *)c->keys.p + total, st);
+                                 c->ws.rec_rcap, (unsigned long long *)c->ws.keys.p + total, st);
         stage_end(c, st, tok, 1);
         total += got;
         a = b;
@@ -978,21 +983,21 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
     }
     *n_rec = total;
     const int bits = 6 + ebits + key_rbits(x->n_reads);
-    PN_CHECK(ensure_keep(c, c->keys, std::max<uint64_t>(total, 1) * 8, total * 8, st));
-    PN_CHECK(ensure(c, c->keys_tmp, std::max<uint64_t>(total, 1) * 8));
-    PN_CHECK(ensure(c, c->sort_temp, pn::radix_temp_size(total)));
+    PN_CHECK(ensure_keep(c, c->ws.keys, std::max<uint64_t>(total, 1) * 8, total * 8, st));
+    PN_CHECK(ensure(c, c->ws.keys_tmp, std::max<uint64_t>(total, 1) * 8));
+    PN_CHECK(ensure(c, c->ws.sort_temp, pn::radix_temp_size(total)));
     const int tok = stage_begin(c, st, PN_STAGE_SORT);
     // mapping: records need only be grouped by (read, strand, end), the
     // finishing pass takes each group's smallest error count; the records
     // pn_validate returns are sorted whole
     const int lo = filter ? 5 : 0;
-    pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p, total,
-                       bits, c->sort_temp.p, st, lo);
+    pn::radix_sort_u64((unsigned long long *)c->ws.keys.p, (unsigned long long *)c->ws.keys_tmp.p, total,
+                       bits, c->ws.sort_temp.p, st, lo);
     stage_end(c, st, tok, 5 * ((bits - lo + 7) / 8));
     return PN_OK;
 }
 
-// filtration + validation; leaves the sorted record keys in c->keys and
+// filtration + validation; leaves the sorted record keys in c->ws.keys and
 // their count in *n_rec
 int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
                 hipStream_t st, uint64_t *n_rec) {
@@ -1004,14 +1009,14 @@ int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, cons
 int finish(pn_ctx *c, const pn_ref *ref, const pn_index *x, uint64_t n_rec, int best, void *d_out,
            uint64_t cap, hipStream_t st, uint64_t *n_out) {
     const int ebits = key_ebits(ref->L);
-    PN_CHECK(ensure(c, c->flags, (n_rec + 1) * 4));
-    PN_CHECK(ensure(c, c->pos, (n_rec + 1) * 4));
-    PN_CHECK(ensure(c, c->partials, pn::scan_partials_size(n_rec + 1) * 4));
-    PN_CHECK(ensure(c, c->minv, ((uint64_t)x->n_reads + 1) * 4));
+    PN_CHECK(ensure(c, c->ws.flags, (n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->ws.pos, (n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->ws.partials, pn::scan_partials_size(n_rec + 1) * 4));
+    PN_CHECK(ensure(c, c->ws.minv, ((uint64_t)x->n_reads + 1) * 4));
     int tok = stage_begin(c, st, PN_STAGE_FINISH);
-    pn::launch_finish_hits((const unsigned long long *)c->keys.p, n_rec, ebits, best, x->n_reads,
-                           (uint32_t *)c->minv.p, (uint32_t *)c->flags.p, (uint32_t *)c->pos.p,
-                           (uint32_t *)c->partials.p, d_out, cap,
+    pn::launch_finish_hits((const unsigned long long *)c->ws.keys.p, n_rec, ebits, best, x->n_reads,
+                           (uint32_t *)c->ws.minv.p, (uint32_t *)c->ws.flags.p, (uint32_t *)c->ws.pos.p,
+                           (uint32_t *)c->ws.partials.p, d_out, cap,
                            (unsigned long long *)&c->misc[kOutCount], st);
     stage_end(c, st, tok, best ? 7 : 5);
     PN_CHECK(read_misc(c, st));
@@ -1048,14 +1053,14 @@ int map_to_workspace(pn_ctx *c, const pn_ref *ref, const pn_index *x, const uint
     const uint64_t cap = std::max<uint64_t>(n_rec, 1);
     *n_all = *n_best = 0;
     if (want_all) {
-        PN_CHECK(ensure(c, c->out_hits, cap * sizeof(pn_hit)));
-        PN_CHECK(finish(c, ref, x, n_rec, 0, c->out_hits.p, cap, st, n_all));
-        *d_all = (const pn_hit *)c->out_hits.p;
+        PN_CHECK(ensure(c, c->ws.out_hits, cap * sizeof(pn_hit)));
+        PN_CHECK(finish(c, ref, x, n_rec, 0, c->ws.out_hits.p, cap, st, n_all));
+        *d_all = (const pn_hit *)c->ws.out_hits.p;
     }
     if (want_best) {
-        PN_CHECK(ensure(c, c->out_best, cap * sizeof(pn_hit)));
-        PN_CHECK(finish(c, ref, x, n_rec, 1, c->out_best.p, cap, st, n_best));
-        *d_best = (const pn_hit *)c->out_best.p;
+        PN_CHECK(ensure(c, c->ws.out_best, cap * sizeof(pn_hit)));
+        PN_CHECK(finish(c, ref, x, n_rec, 1, c->ws.out_best.p, cap, st, n_best));
+        *d_best = (const pn_hit *)c->ws.out_best.p;
     }
     return PN_OK;
 }
@@ -1095,17 +1100,17 @@ int pn_map(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint8_t
     uint64_t n_rec = 0, n_out = 0;
     int s = map_records(c, ref, x, k < 0 ? -1 : k, dk, st, &n_rec);
     // the output can hold at most one hit per record
-    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
+    if (!s) s = ensure(c, c->ws.out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
     if (!s)
-        s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->out_hits.p,
-                   c->out_hits.cap / sizeof(pn_hit), st, &n_out);
+        s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->ws.out_hits.p,
+                   c->ws.out_hits.cap / sizeof(pn_hit), st, &n_out);
     pn_hit *h = nullptr;
     if (!s) {
         h = (pn_hit *)std::malloc(std::max<uint64_t>(n_out, 1) * sizeof(pn_hit));
         if (!h) s = PN_ENOMEM;
     }
     if (!s && n_out) {
-        hipError_t e = hipMemcpyAsync(h, c->out_hits.p, n_out * sizeof(pn_hit),
+        hipError_t e = hipMemcpyAsync(h, c->ws.out_hits.p, n_out * sizeof(pn_hit),
                                       hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         s = map_err(e);
@@ -1249,14 +1254,14 @@ int pn_map_batched(pn_ctx *c, const pn_ref *ref, const char *reads, const uint64
         if (!s) s = pn_index_build_dev(c, dr, doff, m, nb, q, w, st, &x);
         uint64_t n_rec = 0, n_out = 0;
         if (!s) s = map_records(c, ref, x, -1, dk, st, &n_rec);
-        if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
+        if (!s) s = ensure(c, c->ws.out_hits, std::max<uint64_t>(n_rec, 1) * sizeof(pn_hit));
         if (!s)
-            s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->out_hits.p,
-                       c->out_hits.cap / sizeof(pn_hit), st, &n_out);
+            s = finish(c, ref, x, n_rec, mode == PN_BEST_STRATUM, c->ws.out_hits.p,
+                       c->ws.out_hits.cap / sizeof(pn_hit), st, &n_out);
         if (!s && n_out) {
             const size_t at = out.size();
             out.resize(at + n_out);
-            s = map_err(hipMemcpyAsync(out.data() + at, c->out_hits.p, n_out * sizeof(pn_hit),
+            s = map_err(hipMemcpyAsync(out.data() + at, c->ws.out_hits.p, n_out * sizeof(pn_hit),
                                        hipMemcpyDeviceToHost, st));
             if (!s) s = map_err(hipStreamSynchronize(st));
             for (size_t i = at; !s && i < out.size(); i++) out[i].read_id += r0;
@@ -1297,7 +1302,7 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
     uint64_t n = 0;
     // (the whole position set at once: this call returns every candidate)
     for (int attempt = 0; !s && attempt < 8; attempt++) {
-        s = ensure(c, c->cands, pn::kShards * c->cand_rcap * sizeof(uint2));
+        s = ensure(c, c->ws.cands, pn::kShards * c->ws.cand_rcap * sizeof(uint2));
         if (s) break;
         pn::launch_fill_u32((uint32_t *)&c->misc[kFilterStats], 8 * pn::kShards, 0u, st);
         zero_counts(c, kCandCounts, st);
@@ -1307,35 +1312,35 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
         uint64_t mx;
         region_counts(c, kCandCounts, pn::kShards, &mx, &n);
         const uint64_t hmax = heavy_max(c);
-        if (mx <= c->cand_rcap && hmax <= c->heavy_rcap) break;
-        if (mx > c->cand_rcap) c->cand_rcap = mx + mx / 4;
-        if (hmax > c->heavy_rcap) c->heavy_rcap = hmax + hmax / 4;
+        if (mx <= c->ws.cand_rcap && hmax <= c->ws.heavy_rcap) break;
+        if (mx > c->ws.cand_rcap) c->ws.cand_rcap = mx + mx / 4;
+        if (hmax > c->ws.heavy_rcap) c->ws.heavy_rcap = hmax + hmax / 4;
         n = 0;
     }
     uint64_t seeds = 0;
     if (!s) seeds = filter_stats(c).seeds;
-    if (!s) s = ensure(c, c->keys, std::max<uint64_t>(n, 1) * 8);
-    if (!s) s = ensure(c, c->keys_tmp, std::max<uint64_t>(n, 1) * 8);
-    if (!s) s = ensure(c, c->sort_temp, pn::radix_temp_size(n));
-    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
+    if (!s) s = ensure(c, c->ws.keys, std::max<uint64_t>(n, 1) * 8);
+    if (!s) s = ensure(c, c->ws.keys_tmp, std::max<uint64_t>(n, 1) * 8);
+    if (!s) s = ensure(c, c->ws.sort_temp, pn::radix_temp_size(n));
+    if (!s) s = ensure(c, c->ws.out_hits, std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
     pn_candidate *h = nullptr;
     if (!s) {
         if (n) {
-            pn::launch_gather_shards((const unsigned long long *)c->cands.p,
+            pn::launch_gather_shards((const unsigned long long *)c->ws.cands.p,
                                      (const unsigned long long *)&c->misc[kCandCounts],
-                                     pn::kShards, c->cand_rcap,
-                                     (unsigned long long *)c->keys_tmp.p, st);
-            pn::launch_cand_keys((const uint2 *)c->keys_tmp.p, n, (unsigned long long *)c->keys.p,
+                                     pn::kShards, c->ws.cand_rcap,
+                                     (unsigned long long *)c->ws.keys_tmp.p, st);
+            pn::launch_cand_keys((const uint2 *)c->ws.keys_tmp.p, n, (unsigned long long *)c->ws.keys.p,
                                  st);
-            pn::radix_sort_u64((unsigned long long *)c->keys.p, (unsigned long long *)c->keys_tmp.p,
-                               n, 33 + key_rbits(x->n_reads), c->sort_temp.p, st);
-            pn::launch_keys_to_cands((const unsigned long long *)c->keys.p, n, c->out_hits.p, st);
+            pn::radix_sort_u64((unsigned long long *)c->ws.keys.p, (unsigned long long *)c->ws.keys_tmp.p,
+                               n, 33 + key_rbits(x->n_reads), c->ws.sort_temp.p, st);
+            pn::launch_keys_to_cands((const unsigned long long *)c->ws.keys.p, n, c->ws.out_hits.p, st);
         }
         h = (pn_candidate *)std::malloc(std::max<uint64_t>(n, 1) * sizeof(pn_candidate));
         if (!h) s = PN_ENOMEM;
     }
     if (!s && n)
-        s = map_err(hipMemcpyAsync(h, c->out_hits.p, n * sizeof(pn_candidate),
+        s = map_err(hipMemcpyAsync(h, c->ws.out_hits.p, n * sizeof(pn_candidate),
                                    hipMemcpyDeviceToHost, st));
     if (!s) s = map_err(hipStreamSynchronize(st));
     dfree(c, dk);
@@ -1376,23 +1381,23 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
         }
     }
     int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
-    if (!s) s = ensure(c, c->cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
+    if (!s) s = ensure(c, c->ws.cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
     if (!s && n)
-        s = map_err(hipMemcpyAsync(c->cands.p, host.data(), n * sizeof(uint2),
+        s = map_err(hipMemcpyAsync(c->ws.cands.p, host.data(), n * sizeof(uint2),
                                    hipMemcpyHostToDevice, st));
     uint64_t got = 0;
     const int ebits = key_ebits(ref->L);
     if (!s) s = validate_sorted(c, ref, x, k < 0 ? -1 : k, dk, false, n, st, &got);
-    if (!s) s = ensure(c, c->out_hits, std::max<uint64_t>(got, 1) * sizeof(pn_hit));
+    if (!s) s = ensure(c, c->ws.out_hits, std::max<uint64_t>(got, 1) * sizeof(pn_hit));
     pn_hit *h = nullptr;
     if (!s) {
-        pn::launch_records_to_hits((const unsigned long long *)c->keys.p, got, ebits, c->out_hits.p,
+        pn::launch_records_to_hits((const unsigned long long *)c->ws.keys.p, got, ebits, c->ws.out_hits.p,
                                    st);
         h = (pn_hit *)std::malloc(std::max<uint64_t>(got, 1) * sizeof(pn_hit));
         if (!h) s = PN_ENOMEM;
     }
     if (!s && got)
-        s = map_err(hipMemcpyAsync(h, c->out_hits.p, got * sizeof(pn_hit), hipMemcpyDeviceToHost,
+        s = map_err(hipMemcpyAsync(h, c->ws.out_hits.p, got * sizeof(pn_hit), hipMemcpyDeviceToHost,
                                    st));
     if (!s) s = map_err(hipStreamSynchronize(st));
     dfree(c, dk);

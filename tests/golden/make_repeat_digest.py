@@ -3,7 +3,7 @@
 Calls only the CPU oracle (``oracle/``) and the seeded input generator
 (``paper_1403_1706_amd/synth.py``).  Nothing here comes from the HIP path.
 
-Two fixtures:
+Three fixtures:
 
 ``repeat_digest.json``
     The 100 Mbp repeat reference with 1,000,000 reads x 100 bp (4 % error),
@@ -17,6 +17,13 @@ Two fixtures:
     the same two figures per chunk of reads, so that a mismatch can be
     narrowed to a chunk and diffed read by read.
 
+``human_sample_digest.json``
+    The human-shaped workload (3 Gbp, GC 41 %, interspersed repeat families,
+    10,000,000 reads x 100 bp at 3 % error, q = 12, k = 5): 2,000 reads drawn
+    with a seeded generator, mapped by the oracle (in chunks of reads), hits
+    renumbered to the full read set's ids; hit counts and SHA-256 of the
+    records in both modes.
+
 ``mixed_sample_digest.json``
     The mixed-length workload (2,000,000 reads of 50..250 bp, 3 % error,
     k_r = ceil(0.05 n_r)) on the same reference: 50,000 reads drawn with a
@@ -25,7 +32,7 @@ Two fixtures:
     read ids.  Stored: the sampled ids' seed and count, hit counts and
     SHA-256 of the records in both modes.
 
-Usage: ``python tests/golden/make_repeat_digest.py [repeat|mixed] [threads]``.
+Usage: ``python tests/golden/make_repeat_digest.py [repeat|mixed|human] [threads]``.
 """
 from __future__ import annotations
 
@@ -48,6 +55,9 @@ from paper_1403_1706_amd import synth  # noqa: E402
 CHUNK = 25_000
 MIXED_SAMPLE = 50_000
 MIXED_SEED = 3_050
+HUMAN_SAMPLE = 2_000
+HUMAN_SEED = 4_050
+HUMAN_CHUNK = 250
 
 
 def canonical(hits: np.ndarray) -> np.ndarray:
@@ -141,7 +151,48 @@ def mixed(threads: int) -> None:
         f.write("\n")
 
 
+def human_sample_ids(n_reads: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(HUMAN_SEED))
+    return np.sort(rng.choice(n_reads, size=HUMAN_SAMPLE, replace=False))
+
+
+def human(threads: int) -> None:
+    t0 = time.time()
+    w = synth.make("human", threads=threads or None)
+    print(f"human workload: L={len(w.ref)} reads={w.n_reads} ({time.time() - t0:.0f} s)",
+          flush=True)
+    ids = human_sample_ids(w.n_reads)
+    parts = []
+    for a in range(0, len(ids), HUMAN_CHUNK):
+        sel = ids[a:a + HUMAN_CHUNK]
+        sub = w.subset(sel)
+        h = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, sub.k_per_read,
+                                nthreads=threads).copy()
+        h["read_id"] = sel[h["read_id"]].astype(np.uint32)
+        parts.append(h)
+        print(f"sample reads {a + len(sel)}/{len(ids)}: {len(h)} hits, "
+              f"{time.time() - t0:.0f} s", flush=True)
+    h = np.concatenate(parts)
+    out = {
+        "_source": "oracle.map_filtered on a seeded sample of the human-shaped workload "
+                   "(synth.make('human')), written by tests/golden/make_repeat_digest.py; "
+                   "Section 3.3 result definition, Section 3.4 strata",
+        "workload": "human-shaped: 3 Gbp reference (GC 41 %, 300 bp and 6 kbp repeat families "
+                    "covering 15 % and 30 %, 10-20 % divergence), 10,000,000 reads x 100 bp, "
+                    "3 % error, q = 12, k = 5",
+        "n_reads": int(w.n_reads), "sample_seed": HUMAN_SEED, "sample_size": HUMAN_SAMPLE,
+        "q": 12, "k": 5,
+        "ref_sha256": sha(w.ref), "reads_sha256": sha(w.reads),
+    }
+    for mode, x in (("all", h), ("best", oracle.best_stratum(h))):
+        d = canonical(x)
+        out[mode] = {"n_hits": int(len(d)), "sha256": sha(d.tobytes())}
+    with open(os.path.join(HERE, "human_sample_digest.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "repeat"
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    {"repeat": repeat, "mixed": mixed}[which](threads)
+    {"repeat": repeat, "mixed": mixed, "human": human}[which](threads)

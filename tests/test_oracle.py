@@ -390,3 +390,114 @@ def test_lemma_boundary_one_letter_short():
     assert not near.any()
     with pytest.raises(ValueError):
         oracle.map_filtered(ref, x, offs, 12, 5)
+
+
+# ---------------------------------------------------------------------------
+# start and alignment of a hit (Section 3.3 backward pass, Section 3.4)
+
+
+def _edit(a, b):
+    """Textbook global unit-cost edit distance (Levenshtein), plain loops."""
+    prev = list(range(len(b) + 1))
+    for i in range(1, len(a) + 1):
+        cur = [i] + [0] * len(b)
+        for j in range(1, len(b) + 1):
+            cur[j] = min(prev[j - 1] + (a[i - 1] != b[j - 1]), prev[j] + 1, cur[j - 1] + 1)
+        prev = cur
+    return prev[-1]
+
+
+def _all_alignments(x, t):
+    """Every edit transcript turning t into x (ops '=', 'X', 'I', 'D')."""
+    out = []
+
+    def rec(i, j, ops):
+        if i == len(x) and j == len(t):
+            out.append(ops)
+            return
+        if i < len(x) and j < len(t):
+            rec(i + 1, j + 1, ops + ("=" if x[i] == t[j] else "X"))
+        if i < len(x):
+            rec(i + 1, j, ops + "I")
+        if j < len(t):
+            rec(i, j + 1, ops + "D")
+    rec(0, 0, "")
+    return out
+
+
+def _apply(ops, t):
+    """The read an alignment produces from text t (checks '=' and 'X')."""
+    out, j = [], 0
+    for o in ops:
+        if o in "=X":
+            out.append(None if o == "X" else t[j])
+            j += 1
+        elif o == "I":
+            out.append(None)
+        else:
+            j += 1
+    return out, j
+
+
+def test_align_golden_hand_worked():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "align_examples.json")))
+    for c in g["cases"]:
+        t, x = oracle.encode(c["text"].encode()), oracle.encode(c["read"].encode())
+        assert oracle.align(t, x, c["end"], len(x) + 4) == (c["start"], c["errors"], c["ops"]), c
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_align_equals_brute_force(seed):
+    """Errors = the least edit distance over every start (textbook DP); the
+    start is the latest such start; the alignment is a transcript of that
+    cost turning the text span into the read, and the first of all such
+    transcripts in the order (= or X) < I < D, by enumeration."""
+    rng = np.random.default_rng(100 + seed)
+    rank = {"=": 0, "X": 0, "I": 1, "D": 2}
+    for trial in range(150):
+        L = int(rng.integers(8, 14))
+        t = rng.integers(0, 4, L).astype(np.uint8)
+        n = int(rng.integers(1, 6))
+        b0 = int(rng.integers(0, L - n + 1))
+        x = t[b0:b0 + n].copy()
+        for _ in range(int(rng.integers(0, 3))):
+            kind = rng.integers(0, 3)
+            p = int(rng.integers(0, len(x)))
+            if kind == 0:
+                x[p] = (x[p] + rng.integers(1, 4)) % 4
+            elif kind == 1 and len(x) > 1:
+                x = np.delete(x, p)
+            else:
+                x = np.insert(x, p, rng.integers(0, 4))
+        e = int(rng.integers(len(x) - 1, L)) if len(x) <= L else L - 1
+        e = max(e, 0)
+        span_max = len(x) + 3
+        start, err, ops = oracle.align(t, x, e, span_max)
+        spans = [(b, _edit(list(x), list(t[b:e + 1]))) for b in range(max(0, e + 1 - span_max), e + 2)]
+        best = min(d for _, d in spans)
+        assert err == best
+        assert start == max(b for b, d in spans if d == best)
+        span = list(t[start:e + 1])
+        produced, used = _apply(ops, span)
+        assert used == len(span) and len(produced) == len(x)
+        assert all(p is None or p == xi for p, xi in zip(produced, x))
+        assert sum(o != "=" for o in ops) == err
+        assert all((o == "=") == (xi == span[j]) for o, xi, j in _diag_pairs(ops, x))
+        cands = [a for a in _all_alignments(list(x), span) if sum(o != "=" for o in a) == err]
+        assert ops == min(cands, key=lambda a: [rank[o] for o in a])
+
+
+def _diag_pairs(ops, x):
+    """(op, read letter, text index) of the diagonal steps of an alignment."""
+    i = j = 0
+    for o in ops:
+        if o in "=X":
+            yield o, x[i], j
+            i += 1
+            j += 1
+        elif o == "I":
+            i += 1
+        else:
+            j += 1

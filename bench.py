@@ -63,7 +63,7 @@ def counter_traffic(kernel, workload):
     return None
 
 
-def serving_run(pn, ref, ref_ascii, q, args):
+def serving_run(pn, ctx, ref, ref_ascii, q, args):
     """Requests shaped like the serving workload (1k-200k reads log-uniform,
     75-250 bp, 2-5 % error, all hits or best stratum, Poisson arrivals)
     against the resident reference.  Serial capacity first (one request per
@@ -461,7 +461,7 @@ def main():
 
     serving = None
     if not args.no_serve:
-        serving = serving_run(pn, ref, w.ref, w.q, args)
+        serving = serving_run(pn, ctx, ref, w.ref, w.q, args)
 
     pn.pn_ref_free(ref)
     pn.pn_ctx_destroy(ctx)

@@ -261,6 +261,28 @@ int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_ca
                 uint64_t n_cands, int k, const uint8_t *k_per_read, pn_hit **records,
                 uint64_t *n_records);
 
+/* pn_validate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same candidates, k and records as pn_validate, but device arrays in and
+ * out, ordered on `stream` (NULL: the context's stream): d_cands holds
+ * n_cands pn_candidate entries, d_k_per_read (k < 0) one byte per read of
+ * idx, and the records, sorted, go to d_records (room for `capacity`);
+ * *n_records (host) receives their count.  The call synchronises the stream
+ * and allocates nothing: its working memory is one fixed 37 MiB device array
+ * per device, set up by pn_ctx_create and held until the process ends.
+ * Limits: n_cands <= 65536 and at most 2^20 records (and 32768 in each of
+ * the 64 output regions that blocks of 256 candidates append to in turn);
+ * beyond them PN_EINVAL.  PN_ETRUNC with *n_records = the required count
+ * when capacity is too small.  PN_EINVAL for a candidate with read_id >=
+ * n_reads, strand > 1 or a diagonal outside [-256, L]; PN_EINVAL /
+ * PN_ELEMMA for k as pn_map.  Every call on one device shares its array and
+ * leaves its contents behind: calls that overlap on one device (on two
+ * streams or threads) race and must be serialised by the caller. */
+int pn_validate_noalloc(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx,
+                        const pn_candidate *d_cands, uint64_t n_cands, int k,
+                        const uint8_t *d_k_per_read, pn_hit *d_records, uint64_t capacity,
+                        uint64_t *n_records, void *stream);
+
 /* ---- batching: parameter choice ----------------------------------------- */
 
 /* Pick q in {10, 11, 12} and group width w in {32, 64} for a read batch

@@ -66,6 +66,8 @@ struct PendingStage {
 
 }  // namespace
 
+int pnrt_noalloc_setup(int device);  // once per device (pn_ctx_create)
+
 struct pn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -398,11 +400,14 @@ int pn_ctx_create(int device, pn_ctx **out) {
     hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc((void **)&c->misc, kMiscWords * sizeof(uint64_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hmisc, kMiscWords * sizeof(uint64_t), 0);
-    if (e != hipSuccess) {
+    // the device array of pn_validate_noalloc: its address on this device
+    const int s = e == hipSuccess ? pnrt_noalloc_setup(device) : map_err(e);
+    if (s) {
+        if (c->hmisc) (void)hipHostFree(c->hmisc);
         if (c->misc) (void)hipFree(c->misc);
         if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
-        return map_err(e);
+        return s;
     }
     *out = c;
     return PN_OK;
@@ -1407,6 +1412,133 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
     }
     *records = h;
     *n_records = got;
+    return PN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// validation without allocation: a fixed device array per device
+
+namespace {
+
+// Limits of pn_validate_noalloc and the layout of its array (byte offsets,
+// each a multiple of 256).
+constexpr uint64_t kNaMaxCands = 1ull << 16;
+constexpr uint64_t kNaRegionCap = 1ull << 15;  // records per output region
+constexpr uint64_t kNaMaxRecords = 1ull << 20;
+constexpr uint64_t kNaTempBytes = 2ull << 20;  // radix sort counts and offsets
+constexpr uint64_t kNaRinfo = 0;
+constexpr uint64_t kNaCands = kNaRinfo + (((uint64_t)PN_MAX_READS + 1 + 255) & ~255ull);
+constexpr uint64_t kNaLong = kNaCands + kNaMaxCands * 8;
+constexpr uint64_t kNaRegions = kNaLong + kNaMaxCands * 8;
+constexpr uint64_t kNaKeys = kNaRegions + pn::kShards * kNaRegionCap * 8;
+constexpr uint64_t kNaTmp = kNaKeys + kNaMaxRecords * 8;
+constexpr uint64_t kNaTemp = kNaTmp + kNaMaxRecords * 8;
+constexpr uint64_t kNaBytes = kNaTemp + kNaTempBytes;  // 37 MiB
+constexpr int kNaMaxDevices = 64;
+
+// Its device copy (one per device, at a device address that the host
+// learns from hipGetSymbolAddress; host code never passes the name itself).
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[kNaMaxDevices] = {};
+
+// Once per device, with that device current: the array's device address.
+int noalloc_setup(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return PN_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (g_na_ptr[device]) return PN_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return PN_EDEVICE;
+    }
+    g_na_ptr[device] = (unsigned char *)p;
+    return PN_OK;
+}
+
+unsigned char *noalloc_ptr(int device) {
+    if (device < 0 || device >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    return g_na_ptr[device];
+}
+
+// the context's misc words back to the host (no stage bookkeeping)
+int na_sync_misc(pn_ctx *c, hipStream_t st) {
+    PN_TRY(hipMemcpyAsync(c->hmisc, c->misc, kMiscWords * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                          st));
+    PN_TRY(hipStreamSynchronize(st));
+    return PN_OK;
+}
+
+}  // namespace
+
+int pnrt_noalloc_setup(int device) { return noalloc_setup(device); }
+
+extern "C" {
+
+int pn_validate_noalloc(pn_ctx *c, const pn_ref *ref, const pn_index *x,
+                        const pn_candidate *d_cands, uint64_t n, int k,
+                        const uint8_t *d_k_per_read, pn_hit *d_records, uint64_t capacity,
+                        uint64_t *n_records, void *stream) {
+    PN_CHECK(check_map_args(c, ref, x, k, d_k_per_read, PN_ALL_HITS));
+    if (!n_records || (n && !d_cands) || (capacity && !d_records) || n > kNaMaxCands)
+        return PN_EINVAL;
+    DeviceGuard g(c->device);
+    unsigned char *base = noalloc_ptr(c->device);
+    if (!base) return PN_EDEVICE;
+    hipStream_t st = pick_stream(c, stream);
+    const int kglob = k < 0 ? -1 : k;
+    uint2 *cands = (uint2 *)(base + kNaCands);
+    uint2 *longc = (uint2 *)(base + kNaLong);
+    unsigned long long *regions = (unsigned long long *)(base + kNaRegions);
+    unsigned long long *keys = (unsigned long long *)(base + kNaKeys);
+    unsigned long long *tmp = (unsigned long long *)(base + kNaTmp);
+    const PnIndexDev ix = index_desc(x);
+    // k and the lemma per read (as the mapping checks them), the candidates
+    // converted and range-checked
+    zero_misc(c, st);
+    pn::launch_read_rules(ix, kglob, d_k_per_read, base + kNaRinfo, (uint32_t *)&c->misc[kStatus],
+                          st);
+    pn::launch_cands_in(d_cands, n, x->n_reads, ref->L, cands, (uint32_t *)&c->misc[kStatus], st);
+    pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n, st);
+    PN_CHECK(na_sync_misc(c, st));
+    const uint32_t status = (uint32_t)c->hmisc[kStatus];
+    if (status & (2u | 8u)) return PN_EINVAL;
+    if (status & 4u) return PN_ELEMMA;
+    // both verification passes, records into the array's regions
+    const int ebits = key_ebits(ref->L);
+    const uint64_t in_cap = std::max<uint64_t>(n, 1);
+    pn::VerifyIn in{cands, (const unsigned long long *)&c->misc[kCandCounts], 1, in_cap};
+    pn::VerifyOut vo{regions, {(unsigned long long *)&c->misc[kRecCounts], kNaRegionCap},
+                     (unsigned long long *)&c->misc[kVerifyRows], ebits};
+    if (n) {
+        pn::launch_verify(ref_desc(ref), ix, in, kglob, d_k_per_read, vo, longc,
+                          (unsigned long long *)&c->misc[kLongCounts], true, st);
+        pn::launch_verify(ref_desc(ref), ix, in, kglob, d_k_per_read, vo, longc,
+                          (unsigned long long *)&c->misc[kLongCounts], false, st);
+    }
+    PN_CHECK(na_sync_misc(c, st));
+    uint64_t rmax = 0, total = 0;
+    region_counts(c, kRecCounts, pn::kShards, &rmax, &total);
+    if (rmax > kNaRegionCap || total > kNaMaxRecords) return PN_EINVAL;
+    if (total > capacity) {
+        *n_records = total;
+        return PN_ETRUNC;
+    }
+    if (pn::radix_temp_size(total) > kNaTempBytes) return PN_EINVAL;
+    if (total) {
+        pn::launch_gather_shards(regions, (const unsigned long long *)&c->misc[kRecCounts],
+                                 pn::kShards, kNaRegionCap, keys, st);
+        unsigned long long *sorted = pn::radix_sort_u64_any(
+            keys, tmp, total, 6 + ebits + key_rbits(x->n_reads), base + kNaTemp, st);
+        pn::launch_records_to_hits(sorted, total, ebits, d_records, st);
+    }
+    PN_TRY(hipStreamSynchronize(st));
+    *n_records = total;
     return PN_OK;
 }
 

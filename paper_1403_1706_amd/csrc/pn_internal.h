@@ -331,6 +331,11 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
                    const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
                    bool first, hipStream_t st);
 
+// candidates in the C ABI's 16-byte layout (device) to verification words;
+// out-of-range ones become padding and set bit 3 of *status
+void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,
+                     uint32_t *status, hipStream_t st);
+
 // pn_scan.hip: concatenate the regions of a sharded list (8-byte entries)
 // into dst; counts past region_cap are clipped
 void launch_gather_shards(const unsigned long long *src, const unsigned long long *counts,

@@ -205,6 +205,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
     if (lane == 0 && rows) atomicAdd(out.rows, rows);
 }
 
+// Candidates in the C ABI's layout (16 bytes: read id u32, strand u8, three
+// reserved bytes, diagonal i64) to the verification's (read | strand << 31,
+// diagonal + PN_DBIAS) words.  A candidate whose read, strand or diagonal is
+// out of range becomes a padding slot and sets bit 3 of *status.
+__global__ __launch_bounds__(256) void k_cands_in(const uint4 *__restrict__ in, uint64_t n,
+                                                  uint32_t n_reads, uint64_t L,
+                                                  uint2 *__restrict__ out, uint32_t *status) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 v = in[i];
+    const uint32_t strand = v.y & 0xffu;
+    const int64_t d = (int64_t)(((uint64_t)v.w << 32) | v.z);
+    const bool ok = v.x < n_reads && strand <= 1u && d >= -(int64_t)PN_MAX_READ_LEN &&
+                    d <= (int64_t)L;
+    if (!ok) atomicOr(status, 8u);
+    out[i] = ok ? make_uint2(v.x | (strand << 31), (uint32_t)(d + (int64_t)PN_DBIAS))
+                : make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+}
+
 }  // namespace
 
 namespace pn {
@@ -226,6 +245,13 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
         hipLaunchKernelGGL(k_verify<false>, grid, dim3(kThreads), 0, st, ref, ix, in2, kglob, kpr,
                            out, longc, n_long);
     }
+}
+
+void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,
+                     uint32_t *status, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_cands_in, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (const uint4 *)in, n, n_reads, L, out, status);
 }
 
 }  // namespace pn

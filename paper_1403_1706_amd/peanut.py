@@ -122,6 +122,8 @@ _sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_
 _sig("pn_hits_free", None, [_P])
 _sig("pn_filter", _int, [_P, _P, _P, _int, _P, _PP, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
 _sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
+_sig("pn_validate_noalloc", _int, [_P, _P, _P, _P, _u64, _int, _P, _P, _u64,
+                                   ctypes.POINTER(_u64), _P])
 _sig("pn_server_create", _int, [_P, _P, ctypes.POINTER(_ServerConfig), _PP])
 _sig("pn_server_submit", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _P, _int,
                                 ctypes.POINTER(_u64)])
@@ -141,6 +143,7 @@ EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
             "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
+            "pn_validate_noalloc",
             "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_poll",
             "pn_server_get_stats", "pn_server_destroy", "pn_autotune", "pn_map_batched"]
 
@@ -332,6 +335,28 @@ def pn_validate(ctx, ref, idx, cands: np.ndarray, k) -> np.ndarray:
                             None if karr is None else _ptr(karr), ctypes.byref(hp),
                             ctypes.byref(n)), "pn_validate")
     return _take_hits(hp, n.value, HIT_DTYPE)
+
+
+def pn_validate_noalloc(ctx, ref, idx, d_cands, n_cands: int, k, d_out, stream=None,
+                        d_k=None) -> int:
+    """pn_validate on device arrays with no device allocation: d_cands is a
+    torch tensor holding n_cands CAND_DTYPE entries (16 bytes each), d_out
+    receives the sorted records (room for d_out bytes // 12).  Returns the
+    record count; raises PnError(PN_ETRUNC) with .required if d_out is too
+    small."""
+    cap = d_out.numel() * d_out.element_size() // HIT_DTYPE.itemsize
+    n = _u64()
+    kg = -1 if d_k is not None else int(k)
+    st = _lib.pn_validate_noalloc(ctx, ref, idx, ctypes.c_void_p(d_cands.data_ptr()), n_cands, kg,
+                                  None if d_k is None else ctypes.c_void_p(d_k.data_ptr()),
+                                  ctypes.c_void_p(d_out.data_ptr()), cap, ctypes.byref(n),
+                                  _stream_ptr(stream))
+    if st == PN_ETRUNC:
+        e = PnError(st, "pn_validate_noalloc")
+        e.required = n.value
+        raise e
+    _check(st, "pn_validate_noalloc")
+    return n.value
 
 
 def make_candidates(read_id, strand, diagonal) -> np.ndarray:

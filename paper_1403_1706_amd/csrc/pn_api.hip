@@ -1013,6 +1013,8 @@ int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, cons
 // duplicate removal + strata + output of the sorted records
 int finish(pn_ctx *c, const pn_ref *ref, const pn_index *x, uint64_t n_rec, int best, void *d_out,
            uint64_t cap, hipStream_t st, uint64_t *n_out) {
+    // (hit positions are 32-bit prefix sums over the records)
+    if (n_rec >= 0xffffffffull) return PN_ENOMEM;
     const int ebits = key_ebits(ref->L);
     PN_CHECK(ensure(c, c->ws.flags, (n_rec + 1) * 4));
     PN_CHECK(ensure(c, c->ws.pos, (n_rec + 1) * 4));

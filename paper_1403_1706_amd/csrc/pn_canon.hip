@@ -215,11 +215,12 @@ __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long
 // smallest error count per read (over all records; duplicates do not matter)
 __global__ void k_read_min(const unsigned long long *keys, uint64_t n, int ebits,
                            uint32_t *minv) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    unsigned long long k = keys[i];
-    uint32_t r = (uint32_t)(k >> (6 + ebits));
-    atomicMin(&minv[r], (uint32_t)(k & 31u));
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        unsigned long long k = keys[i];
+        uint32_t r = (uint32_t)(k >> (6 + ebits));
+        atomicMin(&minv[r], (uint32_t)(k & 31u));
+    }
 }
 
 // smallest error count of the (read, strand, end) run that starts at i (the
@@ -238,12 +239,13 @@ __device__ __forceinline__ uint32_t run_min_errors(const unsigned long long *key
 // error count also passes the stratum filter
 __global__ void k_keep_flags(const unsigned long long *keys, uint64_t n, int ebits, int best,
                              const uint32_t *minv, uint32_t *flags) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    unsigned long long k = keys[i];
-    uint32_t f = (i == 0) || ((keys[i - 1] >> 5) != (k >> 5));
-    if (best && f) f = run_min_errors(keys, n, i) == minv[(uint32_t)(k >> (6 + ebits))];
-    flags[i] = f;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        unsigned long long k = keys[i];
+        uint32_t f = (i == 0) || ((keys[i - 1] >> 5) != (k >> 5));
+        if (best && f) f = run_min_errors(keys, n, i) == minv[(uint32_t)(k >> (6 + ebits))];
+        flags[i] = f;
+    }
 }
 
 __device__ __forceinline__ uint4 key_to_hit(unsigned long long k, int ebits) {
@@ -257,14 +259,16 @@ __device__ __forceinline__ uint4 key_to_hit(unsigned long long k, int ebits) {
 __global__ void k_write_hits(const unsigned long long *keys, uint64_t n, int ebits,
                              const uint32_t *flags, const uint32_t *pos, uint32_t *out,
                              uint64_t capacity) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !flags[i]) return;
-    uint64_t p = pos[i];
-    if (p >= capacity) return;
-    uint4 h = key_to_hit((keys[i] & ~31ull) | run_min_errors(keys, n, i), ebits);
-    out[3 * p + 0] = h.x;
-    out[3 * p + 1] = h.y;
-    out[3 * p + 2] = h.z;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!flags[i]) continue;
+        uint64_t p = pos[i];
+        if (p >= capacity) continue;
+        uint4 h = key_to_hit((keys[i] & ~31ull) | run_min_errors(keys, n, i), ebits);
+        out[3 * p + 0] = h.x;
+        out[3 * p + 1] = h.y;
+        out[3 * p + 2] = h.z;
+    }
 }
 
 __global__ void k_total(const uint32_t *pos, uint64_t n, unsigned long long *n_out) {
@@ -273,33 +277,36 @@ __global__ void k_total(const uint32_t *pos, uint64_t n, unsigned long long *n_o
 
 __global__ void k_records_to_hits(const unsigned long long *keys, uint64_t n, int ebits,
                                   uint32_t *out) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint4 h = key_to_hit(keys[i], ebits);
-    out[3 * i + 0] = h.x;
-    out[3 * i + 1] = h.y;
-    out[3 * i + 2] = h.z;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint4 h = key_to_hit(keys[i], ebits);
+        out[3 * i + 0] = h.x;
+        out[3 * i + 1] = h.y;
+        out[3 * i + 2] = h.z;
+    }
 }
 
 // candidate (read | strand << 31, diagonal + bias) -> sortable key
 __global__ void k_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint2 v = c[i];
-    const uint32_t r = v.x == PN_CAND_NONE ? 0x7fffffffu : v.x & PN_CAND_READ;
-    keys[i] = ((unsigned long long)r << 33) | ((unsigned long long)(v.x >> 31) << 32) | v.y;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint2 v = c[i];
+        const uint32_t r = v.x == PN_CAND_NONE ? 0x7fffffffu : v.x & PN_CAND_READ;
+        keys[i] = ((unsigned long long)r << 33) | ((unsigned long long)(v.x >> 31) << 32) | v.y;
+    }
 }
 
 // sorted candidate key -> pn_candidate {u32 read, u8 strand, pad[3], i64 diag}
 __global__ void k_keys_to_cands(const unsigned long long *keys, uint64_t n, uint32_t *out) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    unsigned long long k = keys[i];
-    long long d = (long long)(k & 0xffffffffull) - (long long)PN_DBIAS;
-    out[4 * i + 0] = (uint32_t)(k >> 33);
-    out[4 * i + 1] = (uint32_t)((k >> 32) & 1u);
-    out[4 * i + 2] = (uint32_t)((unsigned long long)d & 0xffffffffull);
-    out[4 * i + 3] = (uint32_t)((unsigned long long)d >> 32);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        unsigned long long k = keys[i];
+        long long d = (long long)(k & 0xffffffffull) - (long long)PN_DBIAS;
+        out[4 * i + 0] = (uint32_t)(k >> 33);
+        out[4 * i + 1] = (uint32_t)((k >> 32) & 1u);
+        out[4 * i + 2] = (uint32_t)((unsigned long long)d & 0xffffffffull);
+        out[4 * i + 3] = (uint32_t)((unsigned long long)d >> 32);
+    }
 }
 
 }  // namespace
@@ -381,15 +388,15 @@ void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits,
     if (best) {
         launch_fill_u32(minv, n_reads, 0xffffffffu, st);
         if (n)
-            hipLaunchKernelGGL(k_read_min, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+            hipLaunchKernelGGL(k_read_min, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, sorted, n,
                                ebits, minv);
     }
     if (n)
-        hipLaunchKernelGGL(k_keep_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+        hipLaunchKernelGGL(k_keep_flags, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, sorted, n,
                            ebits, best, (const uint32_t *)minv, flags);
     launch_scan_u32(flags, pos, n, partials, st);
     if (n)
-        hipLaunchKernelGGL(k_write_hits, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+        hipLaunchKernelGGL(k_write_hits, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, sorted, n,
                            ebits, (const uint32_t *)flags, (const uint32_t *)pos,
                            (uint32_t *)out_hits, capacity);
     hipLaunchKernelGGL(k_total, dim3(1), dim3(1), 0, st, (const uint32_t *)pos, n, n_out);
@@ -398,18 +405,18 @@ void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits,
 void launch_records_to_hits(const unsigned long long *sorted, uint64_t n, int ebits, void *out,
                             hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_records_to_hits, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n,
+    hipLaunchKernelGGL(k_records_to_hits, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, sorted, n,
                        ebits, (uint32_t *)out);
 }
 
 void launch_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_cand_keys, dim3(grid_for(n, 256)), dim3(256), 0, st, c, n, keys);
+    hipLaunchKernelGGL(k_cand_keys, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, c, n, keys);
 }
 
 void launch_keys_to_cands(const unsigned long long *keys, uint64_t n, void *out, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_keys_to_cands, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, n,
+    hipLaunchKernelGGL(k_keys_to_cands, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, keys, n,
                        (uint32_t *)out);
 }
 

@@ -425,24 +425,25 @@ __global__ __launch_bounds__(256) void k_refq_keys(PnRefDev ref, int q, int a,
 __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q, int a,
                                                   unsigned long long *__restrict__ keys,
                                                   uint64_t n, uint16_t *__restrict__ ctx) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const uint64_t L = ref.L;
-    const unsigned long long key = keys[i];
-    const unsigned long long ps = key >> (2 * q + 2 * a);
-    const uint32_t g = (uint32_t)(key >> (2 * a)) & ((1u << (2 * q)) - 1u);
-    const uint64_t p = ps >> 1;
-    const uint32_t s = (uint32_t)(ps & 1u);
-    const uint64_t u = s ? L - q - p : p;  // forward position of the q-gram
-    const uint64_t X = window32(ref.packed, (int64_t)u - 5);
-    uint32_t has, prev, N, avail;
-    refq_context(X, 0, L, q, u, s, has, prev, N, avail);
-    if (ctx) {
-        keys[i] = (ps << (2 * q)) | g;
-        ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
-    } else {
-        keys[i] = (ps << (2 * q + 10)) | ((unsigned long long)N << (2 * q + 2)) |
-                  ((unsigned long long)prev << (2 * q)) | g;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long key = keys[i];
+        const unsigned long long ps = key >> (2 * q + 2 * a);
+        const uint32_t g = (uint32_t)(key >> (2 * a)) & ((1u << (2 * q)) - 1u);
+        const uint64_t p = ps >> 1;
+        const uint32_t s = (uint32_t)(ps & 1u);
+        const uint64_t u = s ? L - q - p : p;  // forward position of the q-gram
+        const uint64_t X = window32(ref.packed, (int64_t)u - 5);
+        uint32_t has, prev, N, avail;
+        refq_context(X, 0, L, q, u, s, has, prev, N, avail);
+        if (ctx) {
+            keys[i] = (ps << (2 * q)) | g;
+            ctx[i] = (uint16_t)(prev | (has << 2) | (avail << 3) | (N << 6));
+        } else {
+            keys[i] = (ps << (2 * q + 10)) | ((unsigned long long)N << (2 * q + 2)) |
+                      ((unsigned long long)prev << (2 * q)) | g;
+        }
     }
 }
 
@@ -910,7 +911,7 @@ void launch_refq_keys(const PnRefDev &ref, int q, unsigned long long *keys, hipS
 void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint64_t n,
                      uint16_t *ctx, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_refq_ctx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ref, q,
+    hipLaunchKernelGGL(k_refq_ctx, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, ref, q,
                        refq_sort_letters(ref.L, q), keys, n, ctx);
 }
 

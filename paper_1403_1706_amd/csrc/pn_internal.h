@@ -40,6 +40,16 @@
 #define PN_CAND_TAIL 0x40000000u
 #define PN_CAND_READ 0x3fffffffu
 
+// Blocks for a kernel that walks n elements with a grid-stride loop.  A
+// dispatch covers fewer than 2^32 work-items (the packet's grid size is a
+// 32-bit count), so one thread per element cannot cover the position set
+// of a reference past 2^31 bases (both strands); the grid is capped well
+// below that and every thread takes several elements.
+inline unsigned pn_stride_blocks(uint64_t n, unsigned threads) {
+    const uint64_t b = (n + threads - 1) / threads;
+    return (unsigned)(b < (1ull << 20) ? (b ? b : 1) : (1ull << 20));
+}
+
 // ---------------------------------------------------------------------------
 // descriptors passed by value to kernels
 

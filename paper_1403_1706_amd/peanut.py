@@ -169,7 +169,9 @@ def _take_hits(ptr, n: int, dtype) -> np.ndarray:
     try:
         if n == 0:
             return np.zeros(0, dtype=dtype)
-        return np.frombuffer(ctypes.string_at(ptr, n * dtype.itemsize), dtype=dtype).copy()
+        # (a copy through a byte view: ctypes.string_at takes a C int size)
+        raw = (ctypes.c_uint8 * (n * dtype.itemsize)).from_address(ptr.value)
+        return np.frombuffer(raw, dtype=dtype).copy()
     finally:
         _lib.pn_hits_free(ptr)
 

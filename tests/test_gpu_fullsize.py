@@ -138,3 +138,89 @@ def _renumber(h, ids):
     out = h.copy()
     out["read_id"] = np.searchsorted(ids, out["read_id"])
     return out
+
+
+def test_human_workload_sample_equals_oracle_digest(pn):
+    """The human-shaped workload (3 Gbp, 10 M reads) mapped as bench.py maps
+    it (sub-batches of 2^21 reads, one index each, against the whole
+    reference): the hits of a seeded 2,000-read sample equal the oracle's."""
+    import torch
+    path = os.path.join(GOLDEN, "human_sample_digest.json")
+    dg = json.load(open(path))
+    say("generating the 3 Gbp / 10 M read workload")
+    w = synth.make("human")
+    assert w.n_reads == dg["n_reads"]
+    assert sha(w.ref) == dg["ref_sha256"] and sha(w.reads) == dg["reads_sha256"]
+    rng = np.random.Generator(np.random.PCG64(dg["sample_seed"]))
+    ids = np.sort(rng.choice(w.n_reads, size=dg["sample_size"], replace=False))
+    dev = torch.device("cuda:0")
+    sub_batch = 1 << 21
+    got = {0: [], 1: []}
+    with pn.Session(0) as s:
+        ref = s.ref(w.ref)
+        buf = torch.empty(12 * 64 * sub_batch, dtype=torch.uint8, device=dev)
+        for a in range(0, w.n_reads, sub_batch):
+            b = min(w.n_reads, a + sub_batch)
+            lo, hi = int(w.offsets[a]), int(w.offsets[b])
+            d_r = torch.frombuffer(bytearray(w.reads[lo:hi]), dtype=torch.uint8).to(dev)
+            d_o = torch.from_numpy((w.offsets[a:b + 1] - lo).astype(np.int64)).to(dev)
+            idx = pn.pn_index_build_dev(s.ctx, d_r, d_o, 12, 64)
+            try:
+                for mode in (0, 1):
+                    say(f"human: reads {a}..{b - 1}, mode={mode}")
+                    n = pn.pn_map_dev(s.ctx, ref, idx, 5, buf, mode)
+                    h = np.frombuffer(buf[:n * 12].cpu().numpy().tobytes(),
+                                      dtype=pn.HIT_DTYPE).copy()
+                    h["read_id"] += np.uint32(a)
+                    got[mode].append(h[np.isin(h["read_id"], ids)])
+            finally:
+                pn.pn_index_free(idx)
+    for mode, name in ((0, "all"), (1, "best")):
+        mine = canonical(np.concatenate(got[mode]))
+        want = dg[name]
+        say(f"mode={name}: {len(mine)} hits on the sample (oracle {want['n_hits']})")
+        if len(mine) != want["n_hits"] or sha(mine.tobytes()) != want["sha256"]:
+            sub = w.subset(ids[:200])
+            orc = oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, sub.k_per_read,
+                                      best=bool(mode)).copy()
+            orc["read_id"] = ids[:200][orc["read_id"]]
+            m200 = mine[np.isin(mine["read_id"], ids[:200])]
+            a_ = {tuple(r) for r in fields(m200)}
+            b_ = {tuple(r) for r in fields(orc)}
+            pytest.fail(f"mode {name}: first 200 sampled reads: {len(b_ - a_)} oracle hits "
+                        f"missing (first {sorted(b_ - a_)[:5]}), {len(a_ - b_)} extra")
+
+
+def test_position_set_past_2_pow_32_entries(pn):
+    """A 2.25 Gbp reference has 4.5e9 position-set entries (both strands),
+    more than one dispatch can give a thread each (its grid size is a 32-bit
+    count of work-items).  Error-free reads drawn from seeded positions on
+    both strands, mapped with k = 0: each must be found exactly where it was
+    drawn (its exact match is a hit with 0 errors by the definition of
+    Section 3.3), whatever q-gram it starts with."""
+    L = 2_250_000_000
+    say(f"generating a {L}-base human-shaped reference")
+    ref = synth.human_reference(L, 4001, 16)
+    rng = np.random.Generator(np.random.PCG64(4_002))
+    n = 4000
+    start = rng.integers(0, L - 100, n)
+    strand = np.repeat(np.array([0, 1], dtype=np.uint8), n // 2)
+    win = ref[start[:, None] + np.arange(100)[None, :]]
+    win[strand == 1] = 3 - win[strand == 1, ::-1]
+    reads = synth.ALPHABET[win.ravel()].tobytes()
+    offsets = (100 * np.arange(n + 1)).astype(np.uint64)
+    # the exact hit: strand 0 ends at start + 99; strand 1 (the reverse
+    # complement's coordinates) at L - 1 - start
+    end = np.where(strand == 0, start + 99, L - 1 - start).astype(np.int64)
+    with pn.Session(0) as s:
+        r = s.ref(synth.ALPHABET[ref].tobytes())
+        del ref
+        idx = s.index(reads, offsets, 12)
+        say("mapping 4000 error-free reads with k = 0")
+        h = pn.pn_map(s.ctx, r, idx, 0, pn.PN_ALL_HITS)
+    got = {(int(a), int(b), int(c)) for a, b, c in zip(h["read_id"], h["strand"], h["end_pos"])}
+    missing = [i for i in range(n) if (i, int(strand[i]), int(end[i])) not in got]
+    first_letter = win[:, 0]
+    assert not missing, (f"{len(missing)} of {n} error-free reads not found; by first letter "
+                         f"{np.bincount(first_letter[missing], minlength=4).tolist()}")
+    assert (h["errors"] == 0).all()

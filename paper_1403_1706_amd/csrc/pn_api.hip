@@ -636,15 +636,16 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
             collect_stages(c);
             // Repeat families in the reads give long slices whose entries
             // differ in the letters that follow; ordering those letters too
-            // lets filtration visit only the entries that can pair with a
-            // text position (one more sort, worth it when a notable share of
-            // all occurrences lies in long slices)
+            // (and, inside one set of letters, the piece starts last) lets
+            // filtration visit only the entries that can pair with a text
+            // position (one more sort, worth it when a notable share of all
+            // occurrences lies in long slices)
             if (glo && c->hmisc[kLongEntries] * kOrderNextShare >= T) {
                 tok = stage_begin(c, st, PN_STAGE_INDEX);
                 unsigned long long *other = sorted == keys ? tmp : keys;
-                sorted = pn::radix_sort_u64_any(sorted, other, T, glo + 2 * q, sort_temp, st, 0);
+                sorted = pn::radix_sort_index_slices(sorted, other, T, q, sort_temp, st);
                 pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);
-                stage_end(c, st, tok, 5 * ((glo + 2 * q + 7) / 8) + 1);
+                stage_end(c, st, tok, 5 * (1 + (2 * q + 9) / 8) + 1);
                 x->after_sorted = true;
                 e = hipStreamSynchronize(st);
                 if (e != hipSuccess) s = map_err(e);

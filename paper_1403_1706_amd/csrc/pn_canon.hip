@@ -44,9 +44,28 @@ inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
 
+// The digit a radix pass sorts by: bits [shift, shift + width) of the key,
+// or (osh > 0) the first pass of an index whose slices are ordered by the
+// letters after the q-gram (see pn::radix_sort_index_slices): the key's 7
+// lowest bits above a piece-start flag.
+struct RadixDigit {
+    int shift;
+    uint32_t dmask;
+    int osh;       // where the read offset (8 bits) starts in an index key, or 0
+    uint32_t ell;  // piece length
+    __device__ __forceinline__ uint32_t operator()(unsigned long long k) const {
+        if (osh) {
+            const uint32_t o = (uint32_t)(k >> osh) & 0xffu;
+            const uint32_t piece = ((uint32_t)k & 511u) < 256u && o % ell == 0u;
+            return (((uint32_t)k & 127u) << 1) | piece;
+        }
+        return (uint32_t)(k >> shift) & dmask;
+    }
+};
+
 template <int kThr>
 __global__ __launch_bounds__(kThr) void k_radix_hist(const unsigned long long *keys, uint64_t n,
-                                                     int shift, uint32_t dmask, uint32_t *hist,
+                                                     RadixDigit digit, uint32_t *hist,
                                                      uint64_t n_tiles) {
     constexpr int kTile = kThr * kRadixItems;
     __shared__ uint32_t h[256];
@@ -56,7 +75,7 @@ __global__ __launch_bounds__(kThr) void k_radix_hist(const unsigned long long *k
 #pragma unroll 4
     for (int j = 0; j < kRadixItems; j++) {
         uint64_t i = base + (uint64_t)j * kThr + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & dmask], 1u);
+        if (i < n) atomicAdd(&h[digit(keys[i])], 1u);
     }
     __syncthreads();
     if (threadIdx.x < 256) hist[(uint64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
@@ -135,7 +154,7 @@ __global__ __launch_bounds__(256) void k_col_down(const uint32_t *__restrict__ h
 template <int kThr>
 __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long *keys,
                                                         unsigned long long *out, uint64_t n,
-                                                        int shift, uint32_t dmask,
+                                                        RadixDigit digit,
                                                         const pn_roff *offs,
                                                         const uint32_t *hist, uint64_t n_tiles) {
     constexpr int kItems = kRadixItems;
@@ -170,7 +189,7 @@ __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long
     for (int j = 0; j < kItems; j++) {
         const uint32_t li = w0 + (uint32_t)j * 64 + lane;
         const bool valid = li < tile_n;
-        const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
+        const uint32_t dg = digit(key[j]);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -207,7 +226,7 @@ __global__ __launch_bounds__(kThr) void k_radix_scatter(const unsigned long long
     // and goes to offs[d] + (i - local[d])
     for (uint32_t i = threadIdx.x; i < tile_n; i += kThr) {
         const unsigned long long k = tile[i];
-        const uint32_t dg = (uint32_t)(k >> shift) & dmask;
+        const uint32_t dg = digit(k);
         out[goff[dg] + (i - local[dg])] = k;
     }
 }
@@ -329,10 +348,10 @@ uint64_t radix_temp_size(uint64_t n) {
            (hist + 256 * (uint64_t)PN_RADIX_GROUPS + 256) * sizeof(pn_roff) + 256;
 }
 
-unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
-                                       uint64_t n, int bits, void *temp, hipStream_t st, int lo,
-                                       const uint32_t *hist0) {
-    if (n <= 1 || bits <= 0) return keys;
+// one stable pass src -> dst by `digit` (hist_given: its per-tile counts, if
+// already made)
+static void radix_pass(const unsigned long long *src, unsigned long long *dst, uint64_t n,
+                       RadixDigit digit, const uint32_t *hist_given, void *temp, hipStream_t st) {
     const uint64_t nt = tiles_for(n);
     uint32_t *hist = (uint32_t *)temp;
     pn_roff *offs = (pn_roff *)(hist + 256 * nt + 2);  // (8-byte aligned: temp is)
@@ -340,6 +359,29 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
     pn_roff *dtot = colsum + 256 * (uint64_t)PN_RADIX_GROUPS;
     const uint64_t per = pn_radix_tiles_per_group(nt);  // tiles per group
     const uint32_t groups = (uint32_t)((nt + per - 1) / per);
+    const uint32_t *hp = hist_given ? hist_given : hist;
+    if (!hist_given && radix_threads(n) == kThrLarge)
+        hipLaunchKernelGGL(k_radix_hist<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,
+                           src, n, digit, hist, nt);
+    else if (!hist_given)
+        hipLaunchKernelGGL(k_radix_hist<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0, st,
+                           src, n, digit, hist, nt);
+    hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, hp, nt, per, colsum);
+    hipLaunchKernelGGL(k_col_top, dim3(256), dim3(256), 0, st, colsum, groups, dtot);
+    hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, hp, nt, per,
+                       (const pn_roff *)colsum, (const pn_roff *)dtot, offs);
+    if (radix_threads(n) == kThrLarge)
+        hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,
+                           src, dst, n, digit, (const pn_roff *)offs, hp, nt);
+    else
+        hipLaunchKernelGGL(k_radix_scatter<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0, st,
+                           src, dst, n, digit, (const pn_roff *)offs, hp, nt);
+}
+
+unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long long *tmp,
+                                       uint64_t n, int bits, void *temp, hipStream_t st, int lo,
+                                       const uint32_t *hist0) {
+    if (n <= 1 || bits <= 0) return keys;
     unsigned long long *src = keys, *dst = tmp;
     const int passes = (bits - lo + 7) / 8;
     for (int p = 0; p < passes; p++) {
@@ -348,29 +390,26 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
         const uint32_t dmask = bits - shift >= 8 ? 255u : (1u << (bits - shift)) - 1u;
         // the first pass may come with its histogram (made with the keys:
         // the counts of the digit at bit lo)
-        const bool given = p == 0 && hist0 != nullptr;
-        const uint32_t *hp = given ? hist0 : hist;
-        if (!given && radix_threads(n) == kThrLarge)
-            hipLaunchKernelGGL(k_radix_hist<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0, st,
-                               src, n, shift, dmask, hist, nt);
-        else if (!given)
-            hipLaunchKernelGGL(k_radix_hist<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0, st,
-                               src, n, shift, dmask, hist, nt);
-        hipLaunchKernelGGL(k_col_sums, dim3(groups), dim3(256), 0, st, hp, nt, per, colsum);
-        hipLaunchKernelGGL(k_col_top, dim3(256), dim3(256), 0, st, colsum, groups, dtot);
-        hipLaunchKernelGGL(k_col_down, dim3(groups), dim3(256), 0, st, hp, nt, per,
-                           (const pn_roff *)colsum, (const pn_roff *)dtot, offs);
-        if (radix_threads(n) == kThrLarge)
-            hipLaunchKernelGGL(k_radix_scatter<kThrLarge>, dim3((unsigned)nt), dim3(kThrLarge), 0,
-                               st, src, dst, n, shift, dmask, (const pn_roff *)offs, hp, nt);
-        else
-            hipLaunchKernelGGL(k_radix_scatter<kThrSmall>, dim3((unsigned)nt), dim3(kThrSmall), 0,
-                               st, src, dst, n, shift, dmask, (const pn_roff *)offs, hp, nt);
+        radix_pass(src, dst, n, RadixDigit{shift, dmask, 0, 1u}, p == 0 ? hist0 : nullptr, temp,
+                   st);
         unsigned long long *t = src;
         src = dst;
         dst = t;
     }
     return src;
+}
+
+// An index key (q <= 12: read and offset, letter before, q-gram, 9-bit code
+// of the letters after) sorted by (q-gram, code, piece start): each slice
+// ordered by the letters after its q-gram, and inside one code the entries
+// that start a piece (read offset a multiple of q + 4, four letters after
+// it) last.  The first pass takes the code's low 7 bits above the piece
+// flag, the others bits 7 .. 2q + 9 of the key.
+unsigned long long *radix_sort_index_slices(unsigned long long *keys, unsigned long long *tmp,
+                                            uint64_t n, int q, void *temp, hipStream_t st) {
+    if (n <= 1) return keys;
+    radix_pass(keys, tmp, n, RadixDigit{0, 0u, 2 * q + 11, (uint32_t)q + 4u}, nullptr, temp, st);
+    return radix_sort_u64_any(tmp, keys, n, 2 * q + 9, temp, st, 7);
 }
 
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,

@@ -182,9 +182,18 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
     const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
     const uint32_t o = hi & 0xffu;
     const uint32_t info = (uint32_t)v & 0xffu;
+    if ((info >> 3) & 1u) {
+        // piece mode: a piece start whose q-gram and four letters after it
+        // equal the text's
+        if (!((v >> 20) & 1u) || avail < 4u || ((uint32_t)(v >> 24) & 0xffu) != N) return;
+        push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+        return;
+    }
+    // (a searched range of an ordered slice serves reads in piece mode only;
+    // the slice's entries of the other reads are in its lax list)
+    if (strict) return;
     const bool keep = (info >> 7) & 1u;
     const uint32_t need = info & 7u;                         // rule 3
-    if (strict && need < 4u) return;
     if (has_prev && cls == prev && (keep || !lh)) return;  // rule 1
     if (need) {
         const uint32_t nav = (uint32_t)(v >> 21) & 7u;
@@ -213,21 +222,24 @@ struct Ranges {
     bool strictA;
 };
 
-// the 9-bit code of an O entry's letters after the q-gram (the order of a
-// slice when the index is sorted by them; see pn_index.hip)
+// the order of an O entry inside a slice of an ordered index (see
+// pn_index.hip): twice the 9-bit code of its letters after the q-gram, plus
+// one for a piece start
 __device__ __forceinline__ uint32_t entry_after_code(unsigned long long v) {
     const uint32_t lo = (uint32_t)v;
-    const uint32_t next4 = lo >> 24, nav = (lo >> 21) & 7u;
+    const uint32_t next4 = lo >> 24, nav = (lo >> 21) & 7u, piece = (lo >> 20) & 1u;
+    uint32_t c;
     switch (nav) {
-        case 4: return next4;
-        case 3: return 256u + (next4 >> 2);
-        case 2: return 320u + (next4 >> 4);
-        case 1: return 336u + (next4 >> 6);
-        default: return 340u;
+        case 4: c = next4; break;
+        case 3: c = 256u + (next4 >> 2); break;
+        case 2: c = 320u + (next4 >> 4); break;
+        case 1: c = 336u + (next4 >> 6); break;
+        default: c = 340u;
     }
+    return 2u * c + piece;
 }
 
-// first position in O[lo, hi) whose code is >= target (codes ascend)
+// first position in O[lo, hi) whose order value is >= target (they ascend)
 __device__ __forceinline__ uint32_t code_lower_bound(gu64 *O, uint32_t lo, uint32_t hi,
                                                      uint32_t target) {
     uint32_t n = hi - lo;
@@ -274,9 +286,11 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const pn::Lists 
         // needs four of them (rule 3) can only pair here with the entries
         // whose four letters are the text's, found by binary search; the
         // entries of the other reads of this slice are in its lax list.
+        // (the piece starts among them: the entries of reads in piece mode
+        // that can pair here; the other reads' entries are in the lax list)
         if (avail == 4u) {
-            rg.a0 = code_lower_bound((gu64 *)ix.O, ks, ke, N);
-            rg.a1 = code_lower_bound((gu64 *)ix.O, rg.a0, ke, N + 1u);
+            rg.a0 = code_lower_bound((gu64 *)ix.O, ks, ke, 2u * N + 1u);
+            rg.a1 = code_lower_bound((gu64 *)ix.O, rg.a0, ke, 2u * N + 2u);
         } else {
             rg.a0 = rg.a1 = ks;
         }
@@ -599,32 +613,51 @@ __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a
 __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict__ kpr,
                              uint8_t *__restrict__ rinfo, uint32_t *status) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= ix.n_reads) return;
-    const uint32_t n = (uint32_t)(ix.offsets[r + 1] - ix.offsets[r]);
-    const uint32_t k = kglob >= 0 ? (uint32_t)kglob : kpr[r];
-    const uint32_t q = (uint32_t)ix.q;
-    uint32_t bad = 0;
-    if (k > PN_MAX_K) bad |= 2u;
-    if ((k + 1) * q > n) bad |= 4u;
-    if (bad) {
-        atomicOr(status, bad);
-        rinfo[r] = 0;
-        return;
+    if (r < ix.n_reads) {
+        const uint64_t off = ix.offsets[r];
+        const uint32_t n = (uint32_t)(ix.offsets[r + 1] - off);
+        const uint32_t k = kglob >= 0 ? (uint32_t)kglob : kpr[r];
+        const uint32_t q = (uint32_t)ix.q;
+        uint32_t bad = 0;
+        if (k > PN_MAX_K) bad |= 2u;
+        if ((k + 1) * q > n) bad |= 4u;
+        // Piece mode (an index whose long slices are ordered with the piece
+        // starts apart): the read's disjoint windows of q + 4 letters at
+        // offsets 0, q + 4, 2 (q + 4), ...  An edit falls into one window at
+        // most, so an alignment with at most k errors leaves a window
+        // untouched when k + 1 of them can be looked up: an exact match of
+        // the window's q-gram and the four letters after it, found by
+        // filtration at its piece start.  Windows whose q-gram is
+        // low-complexity are not looked up (rule 2) and do not count.
+        uint32_t pieces = 0;
+        if (!bad && ix.after_sorted) {
+            const uint32_t ell = q + 4;
+            for (uint32_t o = 0; o + ell <= n; o += ell)
+                pieces += !pn_low_complexity(pn_window16(ix.packed, off + o) >> (32 - 2 * q), q);
+        }
+        if (bad) {
+            atomicOr(status, bad);
+            rinfo[r] = 0;
+        } else if (pieces >= k + 1) {
+            // (its entries are in no lax list and no side list)
+            rinfo[r] = (uint8_t)((1u << 3) | 4u);
+        } else {
+            const uint32_t nq = n - q + 1;
+            const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = (ix.lcinfo[r] >> 16) & 0x7fffu;
+            const uint32_t front = ix.lcinfo[r] >> 31;
+            const uint32_t Q = nq - lc;  // offsets whose q-gram is not low-complexity
+            uint32_t keep, run;
+            if (Q >= k * q + 1) {
+                keep = 0;
+                run = q - 1 + ceil_div(Q - k * q, k + 1 + runs);
+            } else {
+                keep = 1;
+                run = ceil_div(n - k, k + 1);
+            }
+            const uint32_t need = run > q ? min(run - q, 4u) : 0u;
+            rinfo[r] = (uint8_t)((keep << 7) | (front << 6) | need);
+        }
     }
-    const uint32_t nq = n - q + 1;
-    const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = (ix.lcinfo[r] >> 16) & 0x7fffu;
-    const uint32_t front = ix.lcinfo[r] >> 31;
-    const uint32_t Q = nq - lc;  // offsets whose q-gram is not low-complexity
-    uint32_t keep, run;
-    if (Q >= k * q + 1) {
-        keep = 0;
-        run = q - 1 + ceil_div(Q - k * q, k + 1 + runs);
-    } else {
-        keep = 1;
-        run = ceil_div(n - k, k + 1);
-    }
-    const uint32_t need = run > q ? min(run - q, 4u) : 0u;
-    rinfo[r] = (uint8_t)((keep << 7) | (front << 6) | need);
 }
 
 // side lists: for each of the 16 low-complexity q-grams (first two letters
@@ -811,8 +844,9 @@ __global__ void k_lc_sizes(PnIndexDev ix, uint32_t *sizes) {
 }
 
 // Lax lists (per mapping call, after the rule bytes are stamped): for every
-// slice of O longer than min_len, its entries whose read needs fewer than
-// four letters past the q-gram (rule 3), in slice order, appended to laxO;
+// slice of O longer than min_len, its entries whose read is not in piece
+// mode (the searched ranges hold piece starts only), in slice order,
+// appended to laxO;
 // lax[x] = {start, count} for such a slot x (other slots are not written).
 // A lane looks at one slot; the wave then takes the long slots one by one,
 // counts their lax entries with ballots, reserves room with one atomic add
@@ -837,7 +871,7 @@ __global__ __launch_bounds__(kT) void k_lax_lists(PnIndexDev ix, uint64_t n_slot
             const uint32_t a = __shfl(ks, l), b = __shfl(ke, l);
             uint32_t n = 0;
             for (uint32_t t = a; t < b; t += 64) {
-                const bool f = t + lane < b && (((uint32_t)O[t + lane] & 7u) < 4u);
+                const bool f = t + lane < b && !(((uint32_t)O[t + lane] >> 3) & 1u);
                 n += (uint32_t)__popcll(__ballot(f));
             }
             unsigned long long at = 0;
@@ -846,7 +880,7 @@ __global__ __launch_bounds__(kT) void k_lax_lists(PnIndexDev ix, uint64_t n_slot
             uint32_t w = 0;
             for (uint32_t t = a; t < b && w < n; t += 64) {
                 const unsigned long long v = t + lane < b ? O[t + lane] : 0ull;
-                const bool f = t + lane < b && (((uint32_t)v & 7u) < 4u);
+                const bool f = t + lane < b && !(((uint32_t)v >> 3) & 1u);
                 const unsigned long long m = __ballot(f);
                 if (f) laxO[at + w + (uint32_t)__popcll(m & lt)] = v;
                 w += (uint32_t)__popcll(m);

@@ -286,8 +286,12 @@ __global__ __launch_bounds__(256) void k_index_from_sorted(PnIndexDev ix,
             nav = after < 4u ? after : 4u;
             next4 = (w[j] >> 24) & ((0xffu << (8 - 2 * nav)) & 0xffu);
         }
+        // a piece start: the read offset is a multiple of q + 4 and the four
+        // letters after the q-gram lie in the read (the q-gram and those
+        // letters form one of the read's disjoint pieces of q + 4 letters)
+        const uint32_t piece = nav == 4u && o % (uint32_t)(ix.q + 4) == 0u;
         const uint32_t hi = (cls << 29) | (r << 8) | o;
-        const uint32_t lo = (next4 << 24) | (nav << 21);
+        const uint32_t lo = (next4 << 24) | (nav << 21) | (piece << 20);
         O[i] = ((unsigned long long)hi << 32) | lo;
     }
 }

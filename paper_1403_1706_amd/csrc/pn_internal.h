@@ -12,9 +12,11 @@
 //  * read planes: per read, PN_READ_WORDS uint2 {H, L} words (LSB-first).
 //  * O entry (64 bits): high word (cls << 29) | (read << 8) | offset, cls =
 //    code of the letter before the q-gram in its read or 4 at offset 0; low
-//    word (next4 << 24) | (nav << 21) | rule byte: the (up to) four read
-//    letters after the q-gram, first letter in the top bits, how many exist
-//    (0..4), and in the low byte the read's seed-rule bits of the current
+//    word (next4 << 24) | (nav << 21) | (piece << 20) | rule byte: the (up
+//    to) four read letters after the q-gram, first letter in the top bits,
+//    how many exist (0..4), whether the entry starts a piece (offset a
+//    multiple of q + 4 and nav = 4: the read's disjoint windows of q + 4
+//    letters), and in the low byte the read's seed-rule bits of the current
 //    mapping call (written by launch_stamp_rules).
 //  * low-complexity q-grams: period <= 2 (homopolymers and dinucleotide
 //    repeats), see pn_low_complexity.
@@ -239,7 +241,9 @@ struct FilterOut {
 };
 // per read: bit 7 = keeps its low-complexity seeds, bit 6 = its
 // low-complexity offsets lie mostly in its first half (candidates get
-// PN_CAND_TAIL), bits 0-2 = extra letters of exact run required beyond q (0..4)
+// PN_CAND_TAIL), bit 3 = piece mode (its candidates come from exact pieces
+// only), bits 0-2 = extra letters of exact run required beyond q (0..4).
+// Status: bit 2 some k_r too large, bit 4 the lemma fails for some read.
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
                        uint32_t *status, hipStream_t st);
 // sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)
@@ -288,11 +292,11 @@ void launch_refq_ctx(const PnRefDev &ref, int q, unsigned long long *keys, uint6
 //    that keep them (rule 2), grouped by the letter before, with their
 //    class bounds side_cls (6 per q-gram);
 //  * lax lists (when sub_on: the index orders each slice by the letters
-//    after the q-gram): for each slice longer than sub_min, its entries
-//    whose read needs fewer than four letters past the q-gram (rule 3),
-//    at laxO[lax[x].x .. lax[x].x + lax[x].y) for slot x.  Filtration then
-//    visits, in such a slice, only the binary-searched entries whose four
-//    letters equal the text's, plus the slice's lax list.
+//    after the q-gram, piece starts last among equal letters): for each
+//    slice longer than sub_min, its entries whose read is not in piece
+//    mode, at laxO[lax[x].x .. lax[x].x + lax[x].y) for slot x.  Filtration
+//    then visits, in such a slice, only the binary-searched piece starts
+//    whose four letters equal the text's, plus the slice's lax list.
 struct Lists {
     const unsigned long long *side;
     const uint32_t *side_cls;
@@ -362,6 +366,10 @@ unsigned long long *radix_sort_u64_any(unsigned long long *keys, unsigned long l
                                        uint64_t n, int bits, void *temp, hipStream_t st,
                                        int lo = 0, const uint32_t *hist0 = nullptr);
 uint64_t radix_tile_keys(uint64_t n);
+// index keys that carry the letters after the q-gram (q <= 12), sorted by
+// (q-gram, letters-after code, piece start); result in keys or tmp
+unsigned long long *radix_sort_index_slices(unsigned long long *keys, unsigned long long *tmp,
+                                            uint64_t n, int q, void *temp, hipStream_t st);
 void radix_sort_u64(unsigned long long *keys, unsigned long long *tmp, uint64_t n, int bits,
                     void *temp, hipStream_t st, int lo = 0);
 void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits, int best,

@@ -118,17 +118,23 @@ def test_index_arrays_match_definition(pn, sess, wbits, case):
         letter = np.where(t < nav, codes[np.minimum(start + t, len(codes) - 1)], 0)
         next4 |= letter.astype(np.int64) << (6 - 2 * t)
     assert np.array_equal((lo >> 24) & 0xff, next4)
-    assert np.all((lo & ((1 << 21) - 1)) == 0)
+    # bit 20: the entry starts one of the read's disjoint pieces of q + 4
+    # letters (offset a multiple of q + 4, four letters after the q-gram)
+    piece = ((nav == 4) & (o % (q + 4) == 0)).astype(np.int64)
+    assert np.array_equal((lo >> 20) & 1, piece)
+    assert np.all((lo & ((1 << 20) - 1)) == 0)
     # inside a slice: for q <= 12 ordered by the letters after the q-gram
     # (their 9-bit code: all four letters 0-255, else 256 + three, 320 +
-    # two, 336 + one, 340 none), then by (read, offset); else by (read, offset)
+    # two, 336 + one, 340 none), then piece starts last, then by (read,
+    # offset); else by (read, offset)
     n4 = (lo >> 24) & 0xff
     code = np.select([nav == 4, nav == 3, nav == 2, nav == 1],
                      [n4, 256 + (n4 >> 2), 320 + (n4 >> 4), 336 + (n4 >> 6)], 340)
     if not pn.pn_index_get_info(idx)["after_sorted"]:
         code = np.zeros_like(code)
+        piece = np.zeros_like(piece)
     same = bucket[1:] == bucket[:-1]
-    order = (code << 40) | (r << 8) | o
+    order = (code << 41) | (piece << 40) | (r << 8) | o
     assert np.all(order[1:][same] > order[:-1][same])
 
 
@@ -500,9 +506,11 @@ def test_repeat_family_reads_order_slices_by_next_letters(pn, sess):
     code = np.select([nav == 4, nav == 3, nav == 2, nav == 1],
                      [n4, 256 + (n4 >> 2), 320 + (n4 >> 4), 336 + (n4 >> 6)], 340)
     _, r, o = decode_O(O)
+    piece = ((nav == 4) & (o % 16 == 0)).astype(np.int64)
+    assert np.array_equal((lo >> 20) & 1, piece)
     bucket = np.repeat(np.arange(len(Sp) - 1), np.diff(Sp.astype(np.int64)))
     same = bucket[1:] == bucket[:-1]
-    order = (code << 40) | (r << 8) | o
+    order = (code << 41) | (piece << 40) | (r << 8) | o
     assert np.all(order[1:][same] > order[:-1][same])
     rng = np.random.default_rng(31)
     sample = np.sort(rng.choice(w.n_reads, 3000, replace=False))
@@ -515,5 +523,14 @@ def test_repeat_family_reads_order_slices_by_next_letters(pn, sess):
         mine["read_id"] = np.searchsorted(sample, mine["read_id"])
         assert_hits_equal(mine, oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, 5,
                                                     best=bool(mode)))
+    # per-read k of 5 and 6: with six pieces of 16 letters, k = 5 reads take
+    # piece mode and k = 6 reads the run rules, in one mapping call
+    kr = np.where(rng.random(w.n_reads) < 0.5, 5, 6).astype(np.uint8)
+    a = pn.pn_map(sess.ctx, ref, i12, kr, 0)
+    b = pn.pn_map(sess.ctx, ref, i13, kr, 0)
+    assert_hits_equal(a, b)
+    mine = a[np.isin(a["read_id"], sample)].copy()
+    mine["read_id"] = np.searchsorted(sample, mine["read_id"])
+    assert_hits_equal(mine, oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, kr[sample]))
     st = pn.pn_ctx_get_stats(sess.ctx)
     say(f"seeds {st['n_seeds']} visited {st['n_visited']} candidates {st['n_candidates']}")

@@ -186,7 +186,11 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
         // piece mode: a piece start whose q-gram and four letters after it
         // equal the text's
         if (!((v >> 20) & 1u) || avail < 4u || ((uint32_t)(v >> 24) & 0xffu) != N) return;
-        push(sg, make_uint2(r | (s << 31), (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+        // a window in the read's first half: verification's first pass
+        // checks the read's last rows, away from the exact window
+        const bool tail = o < 16u * ((info >> 4) & 7u);
+        push(sg, make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
+                            (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
         return;
     }
     // (a searched range of an ordered slice serves reads in piece mode only;
@@ -639,8 +643,11 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
             atomicOr(status, bad);
             rinfo[r] = 0;
         } else if (pieces >= k + 1) {
-            // (its entries are in no lax list and no side list)
-            rinfo[r] = (uint8_t)((1u << 3) | 4u);
+            // (its entries are in no lax list and no side list); bits 4-6:
+            // windows starting below 16 times this lie in the read's first
+            // half (their centre before the read's)
+            const uint32_t half = (n - (q + 4)) / 2;
+            rinfo[r] = (uint8_t)((1u << 3) | (min((half + 15) / 16, 7u) << 4) | 4u);
         } else {
             const uint32_t nq = n - q + 1;
             const uint32_t lc = ix.lcinfo[r] & 0xffffu, runs = (ix.lcinfo[r] >> 16) & 0x7fffu;

@@ -242,7 +242,9 @@ struct FilterOut {
 // per read: bit 7 = keeps its low-complexity seeds, bit 6 = its
 // low-complexity offsets lie mostly in its first half (candidates get
 // PN_CAND_TAIL), bit 3 = piece mode (its candidates come from exact pieces
-// only), bits 0-2 = extra letters of exact run required beyond q (0..4).
+// only; then bits 4-6 = t, windows at offsets below 16 t lie in its first
+// half and their candidates get PN_CAND_TAIL), bits 0-2 = extra letters of
+// exact run required beyond q (0..4).
 // Status: bit 2 some k_r too large, bit 4 the lemma fails for some read.
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
                        uint32_t *status, hipStream_t st);

@@ -20,9 +20,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 32-bit integer operations of one band row of the verification recurrence:
-# match word (4), bit-vector step (13), band shift (3), right-edge value (2)
-OPS_PER_ROW = 22
+# VALU instructions of one band row of the verification recurrence, counted
+# in the compiled kernels' unrolled row loops (gfx950 assembly of this
+# build: 981 for the 32 rows of a read word in the second pass, 472 for the
+# 16 rows of the first pass): text window and read letter (5), match word
+# (2-3), bit-vector step (about 13), band shift and right-edge count (5),
+# the cut-off test (3)
+OPS_PER_ROW = 30
+# VALU instructions per read letter of the count filter (k_count's unrolled
+# piece loop, band inside the reference: two text-plane shifts, two read-bit
+# extracts, the match word and its accumulation)
+OPS_PER_LETTER = 8.5
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
@@ -397,14 +405,18 @@ def main():
     # per step; these stages each time exactly one kernel (the index stage is
     # a chain of ~20 short kernels, none of them close)
     kernel_of = {"filter_emit": "k_filter", "verify": "k_verify", "verify_long": "k_verify_long",
-                 "filter_heavy": "k_filter_heavy"}
+                 "count": "k_count", "filter_heavy": "k_filter_heavy"}
     dominant = max(kernel_of, key=lambda s: stage_ms[s])
     kernel = kernel_of[dominant]
     per_launch_ms = stage_ms[dominant] / max(1.0, launches[dominant])
     n_pos = max(0, len(w.ref) - w.q + 1)
-    if dominant in ("verify", "verify_long"):
-        rows = st["verify_rows_long"] if dominant == "verify_long" else st["verify_rows"] - st["verify_rows_long"]
-        work = rows / K * OPS_PER_ROW
+    if dominant in ("verify", "verify_long", "count"):
+        if dominant == "count":
+            work = st["count_letters"] / K * OPS_PER_LETTER
+        else:
+            rows = st["verify_rows_long"] if dominant == "verify_long" else \
+                st["verify_rows"] - st["verify_rows_long"]
+            work = rows / K * OPS_PER_ROW
         achieved = work / max(1.0, launches[dominant]) / (per_launch_ms / 1000.0)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
@@ -495,6 +507,7 @@ def main():
         "stage_ms": stage_ms,
         "counters_per_step": {c: st[c] / K for c in ("n_seeds", "n_visited", "n_candidates",
                                                         "verify_rows", "verify_rows_long",
+                                                        "count_letters",
                                                         "n_visited_heavy", "n_heavy_items",
                                                         "n_candidates_heavy", "n_records",
                                                         "n_hits")},

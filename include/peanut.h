@@ -138,7 +138,10 @@ enum {
     PN_STAGE_RULES = 7,        /* per-read seed rules, low-complexity side lists */
     PN_STAGE_VERIFY_LONG = 8,  /* validation, second pass: the candidates still open
                                   after the first pass's rows (one kernel) */
-    PN_N_STAGES = 10           /* stage 9 is reserved */
+    PN_STAGE_COUNT = 9,        /* indexes of reads from repeat families: the count filter
+                                  (q-gram lemma on disjoint 8-letter pieces of the read)
+                                  in place of the first pass (one kernel) */
+    PN_N_STAGES = 10
 };
 typedef struct {
     double ms[PN_N_STAGES];
@@ -153,6 +156,7 @@ typedef struct {
     uint64_t n_visited_heavy;    /* the part of n_visited read by FILTER_HEAVY */
     uint64_t n_heavy_items;      /* work items (32 bytes each) handed to FILTER_HEAVY */
     uint64_t n_candidates_heavy; /* the part of n_candidates written by FILTER_HEAVY */
+    uint64_t count_letters;      /* read letters the count filter looked at */
 } pn_stats;
 int pn_ctx_set_timing(pn_ctx *ctx, int enable);
 int pn_ctx_get_stats(pn_ctx *ctx, pn_stats *out, int reset);

@@ -38,6 +38,7 @@ enum MiscSlot {  // 64-bit words of the context's device scratch block
     kOutCount = 6,
     kVerifyRows = 8,
     kVerifyRowsLong = 9,
+    kCountLetters = 10,
     kCandCounts = 16,                        // pn::kShards words each
     kRecCounts = kCandCounts + pn::kShards,
     kLongCounts = kRecCounts + pn::kShards,
@@ -906,6 +907,9 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         const uint64_t in_rcap = filter ? c->ws.cand_rcap : std::max<uint64_t>(n_in, 1);
         PN_CHECK(ensure(c, c->ws.cands, regions * in_rcap * sizeof(uint2)));
         PN_CHECK(ensure(c, c->ws.longc, regions * in_rcap * sizeof(uint2)));
+        // the count filter before the band pass when the reads come from
+        // repeat families (below)
+        const bool count_first = filter && x->after_sorted;
         zero_counts(c, kCandCounts, st);
         FilterWork fw;
         if (filter) {
@@ -941,7 +945,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         for (int vattempt = 0;; vattempt++) {
             if (vattempt >= 8) return PN_ENOMEM;
             PN_CHECK(ensure(c, c->ws.keys_tmp, pn::kShards * c->ws.rec_rcap * 8));
-            pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 4, 0u, st);
+            pn::launch_fill_u32((uint32_t *)&c->misc[kVerifyRows], 6, 0u, st);
             zero_counts(c, kRecCounts, st);
             zero_counts(c, kLongCounts, st);
             pn::VerifyIn in{(const uint2 *)c->ws.cands.p,
@@ -949,15 +953,27 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
             pn::VerifyOut vo{(unsigned long long *)c->ws.keys_tmp.p,
                              {(unsigned long long *)&c->misc[kRecCounts], c->ws.rec_rcap},
                              (unsigned long long *)&c->misc[kVerifyRows], ebits};
-            int tok = stage_begin(c, st, PN_STAGE_VERIFY);
-            pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
-                              (uint2 *)c->ws.longc.p, (unsigned long long *)&c->misc[kLongCounts],
-                              true, st);
-            stage_end(c, st, tok, 1);
+            uint2 *last_in = (uint2 *)c->ws.longc.p;
+            unsigned long long *last_n = (unsigned long long *)&c->misc[kLongCounts];
+            if (count_first) {
+                // Reads from repeat families: most candidates pair a read with
+                // another copy of its family, diverged far beyond k but sharing
+                // an exact window; the count filter drops them for a few
+                // operations per letter, and the band pass takes the rest
+                // from row 0.
+                const int tok = stage_begin(c, st, PN_STAGE_COUNT);
+                pn::launch_count(ref_desc(ref), index_desc(x), in, kglob, d_k, last_in, last_n,
+                                 (unsigned long long *)&c->misc[kCountLetters], st);
+                stage_end(c, st, tok, 1);
+            } else {
+                const int tok = stage_begin(c, st, PN_STAGE_VERIFY);
+                pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, last_in, last_n,
+                                  true, st);
+                stage_end(c, st, tok, 1);
+            }
             vo.rows = (unsigned long long *)&c->misc[kVerifyRowsLong];
-            tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
-            pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo,
-                              (uint2 *)c->ws.longc.p, (unsigned long long *)&c->misc[kLongCounts],
+            const int tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
+            pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, last_in, last_n,
                               false, st);
             stage_end(c, st, tok, 1);
             PN_CHECK(read_misc(c, st));
@@ -976,6 +992,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
         }
         c->stats.verify_rows += c->hmisc[kVerifyRows] + c->hmisc[kVerifyRowsLong];
         c->stats.verify_rows_long += c->hmisc[kVerifyRowsLong];
+        c->stats.count_letters += c->hmisc[kCountLetters];
         c->stats.n_records += got;
         PN_CHECK(ensure_keep(c, c->ws.keys, std::max<uint64_t>(total + got, 1) * 8, total * 8, st));
         const int tok = stage_begin(c, st, PN_STAGE_SORT);

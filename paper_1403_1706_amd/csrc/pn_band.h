@@ -153,3 +153,70 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
     pn_band_load(pl, rp, lo, hd);
     return pn_band_run(hd, pl, rp, len, k, lo, L, row_cap, emit);
 }
+
+// Count filter (the q-gram lemma of Section 2.2, with the read cut into its
+// m = floor(n / 8) disjoint pieces of 8 letters): an edit falls into one
+// piece at most (a deletion between two pieces breaks neither), so an
+// alignment with at most k errors leaves at least m - k pieces exact, each
+// on one diagonal of the alignment; every cell of an alignment through the
+// candidate's diagonal d lies within k diagonals of d, so those pieces
+// match the text exactly on diagonals of the band [d - k, d + k].  A piece
+// is exact on band diagonal b when bit b of the match words of its 8
+// letters (the band's Eq, one row per letter) is set in all of them.  The
+// candidate is dropped as soon as the pieces found plus those unchecked
+// fall below m - k, and kept once m - k are found.  kInside: every band
+// position of the wave's candidates lies in [0, L) (no validity plane).
+constexpr int kPnPiece = 8;
+
+template <bool kInside>
+__host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, const uint4 *__restrict__ pl,
+                                             const uint2 *__restrict__ rp, int len, int k,
+                                             int64_t lo, int &letters) {
+    const int m = len / kPnPiece;
+    const int need = m - k;
+    letters = 0;
+    if (need <= 0) return true;
+    const uint32_t M = (1u << (2 * k + 1)) - 1u;
+    const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
+    const uint64_t blk = tp >> 5;
+    const uint32_t ph = (uint32_t)(tp & 31);
+    uint4 C = hd.C, Dn = hd.Dn;
+    uint32_t h0 = pn_funnel(hd.B.x, hd.A.x, ph), l0 = pn_funnel(hd.B.y, hd.A.y, ph),
+             v0 = pn_funnel(hd.B.z, hd.A.z, ph);
+    uint32_t h1 = pn_funnel(C.x, hd.B.x, ph), l1 = pn_funnel(C.y, hd.B.y, ph),
+             v1 = pn_funnel(C.z, hd.B.z, ph);
+    uint2 rw = hd.rw0;
+    int found = 0, checked = 0;
+    for (int w = 0;; w++) {
+        const uint2 rwn = 32 * (w + 1) < kPnPiece * m ? rp[w + 1] : rw;
+#pragma unroll
+        for (int pc = 0; pc < 4; pc++) {
+            uint32_t acc = M;
+#pragma unroll
+            for (int u = 0; u < kPnPiece; u++) {
+                const int t = kPnPiece * pc + u;  // read letter 32 w + t
+                const uint32_t H = pn_funnel(h1, h0, t), Lw = pn_funnel(l1, l0, t);
+                const uint32_t xh = (uint32_t)((int32_t)(rw.x << (31 - t)) >> 31),
+                               xl = (uint32_t)((int32_t)(rw.y << (31 - t)) >> 31);
+                uint32_t eq = ~((H ^ xh) | (Lw ^ xl));
+                if (!kInside) eq &= pn_funnel(v1, v0, t);
+                acc &= eq;
+            }
+            letters += kPnPiece;
+            found += acc != 0u;
+            checked++;
+            if (found >= need) return true;
+            if (found + (m - checked) < need) return false;
+        }
+        // the next 32 letters: advance the text stream by 32 positions
+        h0 = h1;
+        l0 = l1;
+        v0 = v1;
+        h1 = pn_funnel(Dn.x, C.x, ph);
+        l1 = pn_funnel(Dn.y, C.y, ph);
+        v1 = pn_funnel(Dn.z, C.z, ph);
+        C = Dn;
+        Dn = pl[blk + w + 4];
+        rw = rwn;
+    }
+}

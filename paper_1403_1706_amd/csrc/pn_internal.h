@@ -347,6 +347,13 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
                    const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
                    bool first, hipStream_t st);
 
+// The count filter (pn_verify.hip): each candidate of `in` whose band holds
+// at least floor(n/8) - k exact pieces of 8 read letters (the q-gram lemma
+// on disjoint pieces; Section 2.2) goes to surv (in's shape, counters n_surv
+// zeroed by the caller) for the band pass; *letters += read letters looked at.
+void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                  const uint8_t *kpr, uint2 *surv, unsigned long long *n_surv,
+                  unsigned long long *letters, hipStream_t st);
 // candidates in the C ABI's 16-byte layout (device) to verification words;
 // out-of-range ones become padding and set bit 3 of *status
 void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,

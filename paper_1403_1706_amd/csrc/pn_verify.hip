@@ -126,15 +126,17 @@ __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix,
 }
 
 // Block b reads input region b % in.regions; its records go to output
-// region b % kShards and (first pass) its survivors to long region
+// region b % kShards and (capped passes) its survivors to long region
 // b % in.regions, which can hold every candidate of that input region.
-template <bool kFirst>
+// kFirst: the first pass (16 rows, tail checks); kCapped: the pass stops
+// each candidate after `cap` rows and hands the survivors on.
+template <bool kFirst, bool kCapped>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst ? kFirstWaves : 1))) void k_verify(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
                                                      int kglob, const uint8_t *__restrict__ kpr,
                                                      pn::VerifyOut out, uint2 *longc,
-                                                     unsigned long long *n_long) {
+                                                     unsigned long long *n_long, int cap) {
     __shared__ unsigned long long s_rec[kWaves][kStage];
-    __shared__ unsigned long long s_long[kFirst ? kWaves : 1][kFirst ? kStage : 1];
+    __shared__ unsigned long long s_long[kCapped ? kWaves : 1][kCapped ? kStage : 1];
     __shared__ uint32_t s_cnt[kWaves][2];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
     const uint32_t rout = blockIdx.x % pn::kShards;
     Stage rec{s_rec[wv], &s_cnt[wv][0], out.records + (uint64_t)rout * out.sh.region_cap,
               out.sh.counts + rout, out.sh.region_cap};
-    Stage lng{s_long[kFirst ? wv : 0], &s_cnt[wv][1],
+    Stage lng{s_long[kCapped ? wv : 0], &s_cnt[wv][1],
               (unsigned long long *)longc + (uint64_t)rin * in.region_cap, n_long + rin,
               in.region_cap};
 
@@ -168,10 +170,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
         start(ref, ix, kglob, kpr, out.ebits, c_after, kFirst, nxt);
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
-        // first pass: a wave whose reads are all longer than the row cap
-        // never reaches a last row (wave-uniform); second pass: no row below
-        // the wave's shortest read is a last row
-        const bool capped = kFirst && __all(!cur.ok || cur.len > kShortRows);
+        // capped passes: a wave whose reads are all longer than the row cap
+        // never reaches a last row (wave-uniform); later passes: no row
+        // below the wave's shortest read is a last row
+        const int row_cap = kFirst ? kShortRows : kCapped ? cap : PN_MAX_READ_LEN;
+        const bool capped = kCapped && __all(!cur.ok || cur.len > row_cap);
         int no_end = 0;
         if (!kFirst) {
             no_end = cur.ok ? cur.len : PN_MAX_READ_LEN + 1;
@@ -186,23 +189,74 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
             };
             const int rw =
                 capped ? pn_band_run<false>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
-                                            kShortRows, emit)
+                                            row_cap, emit)
                        : pn_band_run(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, ref.L,
-                                     kFirst ? kShortRows : PN_MAX_READ_LEN, emit, no_end);
+                                     row_cap, emit, no_end);
             // survivors (and tail checks that reached the read's first
             // letter) run again, forward, from row 0
-            if (kFirst && (rw < 0 || (tail && rw == cur.len)))
+            if (kCapped && (rw < 0 || (kFirst && tail && rw == cur.len)))
                 lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
             rows += (unsigned long long)(rw < 0 ? -rw : rw);
         }
         cur = nxt;
         if (*rec.cnt >= kStage / 2) rec.flush(lane);
-        if (kFirst && *lng.cnt >= kStage / 2) lng.flush(lane);
+        if (kCapped && *lng.cnt >= kStage / 2) lng.flush(lane);
     }
     rec.flush(lane);
-    if (kFirst) lng.flush(lane);
+    if (kCapped) lng.flush(lane);
     for (int o = 32; o > 0; o >>= 1) rows += __shfl_xor(rows, o);
     if (lane == 0 && rows) atomicAdd(out.rows, rows);
+}
+
+// The count filter over a candidate list: candidates that may hold a hit
+// go to the survivor list (longc, one region per input region), which the
+// band pass then runs from row 0 to the end.
+__global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
+                                                    int kglob, const uint8_t *__restrict__ kpr,
+                                                    uint2 *longc, unsigned long long *n_long,
+                                                    unsigned long long *letters_out) {
+    __shared__ unsigned long long s_long[kWaves][kStage];
+    __shared__ uint32_t s_cnt[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) s_cnt[wv] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t rin = blockIdx.x % in.regions;
+    Stage lng{s_long[wv], &s_cnt[wv], (unsigned long long *)longc + (uint64_t)rin * in.region_cap,
+              n_long + rin, in.region_cap};
+    const uint2 *cands = in.cands + (uint64_t)rin * in.region_cap;
+    const uint64_t n = min((uint64_t)in.counts[rin], in.region_cap);
+    const uint64_t per = gridDim.x / in.regions;
+    const uint64_t stride = per * kThreads;
+    const uint2 none = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    unsigned long long letters = 0;
+    uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64;
+    uint2 c_next = base + lane < n ? cands[base + lane] : none;
+    uint2 c_after = base + stride + lane < n ? cands[base + stride + lane] : none;
+    Cand cur;
+    start(ref, ix, kglob, kpr, 0, c_next, false, cur);
+    for (; base < n; base += stride) {
+        Cand nxt;
+        start(ref, ix, kglob, kpr, 0, c_after, false, nxt);
+        const uint64_t ci2 = base + 2 * stride + lane;
+        c_after = ci2 < n ? cands[ci2] : none;
+        // (wave-uniform) every band position inside the reference
+        const bool inside =
+            __all(!cur.ok || (cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L));
+        if (cur.ok) {
+            int lt = 0;
+            const bool keep =
+                inside ? pn_count_pieces<true>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, lt)
+                       : pn_count_pieces<false>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, lt);
+            if (keep) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
+            letters += (unsigned long long)lt;
+        }
+        cur = nxt;
+        if (*lng.cnt >= kStage / 2) lng.flush(lane);
+    }
+    lng.flush(lane);
+    for (int o = 32; o > 0; o >>= 1) letters += __shfl_xor(letters, o);
+    if (lane == 0 && letters) atomicAdd(letters_out, letters);
 }
 
 // Candidates in the C ABI's layout (16 bytes: read id u32, strand u8, three
@@ -238,13 +292,24 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
     if (per > max_per) per = max_per;
     const dim3 grid((unsigned)(per * in.regions));
     if (first) {
-        hipLaunchKernelGGL(k_verify<true>, grid, dim3(kThreads), 0, st, ref, ix, in, kglob, kpr,
-                           out, longc, n_long);
+        hipLaunchKernelGGL((k_verify<true, true>), grid, dim3(kThreads), 0, st, ref, ix, in, kglob,
+                           kpr, out, longc, n_long, kShortRows);
     } else {
         VerifyIn in2{longc, n_long, in.regions, in.region_cap};
-        hipLaunchKernelGGL(k_verify<false>, grid, dim3(kThreads), 0, st, ref, ix, in2, kglob, kpr,
-                           out, longc, n_long);
+        hipLaunchKernelGGL((k_verify<false, false>), grid, dim3(kThreads), 0, st, ref, ix, in2,
+                           kglob, kpr, out, longc, n_long, PN_MAX_READ_LEN);
     }
+}
+
+void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                  const uint8_t *kpr, uint2 *surv, unsigned long long *n_surv,
+                  unsigned long long *letters, hipStream_t st) {
+    if (!in.region_cap || !in.regions) return;
+    uint64_t per = (in.region_cap + kThreads - 1) / kThreads;
+    const uint64_t max_per = std::max<uint64_t>(8192 / in.regions, 1);
+    if (per > max_per) per = max_per;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)(per * in.regions)), dim3(kThreads), 0, st, ref,
+                       ix, in, kglob, kpr, surv, n_surv, letters);
 }
 
 void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,

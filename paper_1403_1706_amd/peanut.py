@@ -49,7 +49,7 @@ class _IndexInfo(ctypes.Structure):
 
 
 STAGES = ["ingest", "index", "filter_heavy", "filter_emit", "verify", "sort", "finish", "rules",
-          "verify_long"]
+          "verify_long", "count"]
 
 
 class _Stats(ctypes.Structure):
@@ -58,7 +58,8 @@ class _Stats(ctypes.Structure):
                 ("verify_rows", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
                 ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64),
                 ("verify_rows_long", ctypes.c_uint64), ("n_visited_heavy", ctypes.c_uint64),
-                ("n_heavy_items", ctypes.c_uint64), ("n_candidates_heavy", ctypes.c_uint64)]
+                ("n_heavy_items", ctypes.c_uint64), ("n_candidates_heavy", ctypes.c_uint64),
+                ("count_letters", ctypes.c_uint64)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -206,7 +207,8 @@ def pn_ctx_get_stats(ctx, reset: bool = False) -> dict:
     out = {"ms": {n: st.ms[i] for i, n in enumerate(STAGES)},
            "launches": {n: int(st.launches[i]) for i, n in enumerate(STAGES)}}
     for f in ("n_seeds", "n_candidates", "verify_rows", "n_records", "n_hits", "n_visited",
-              "verify_rows_long", "n_visited_heavy", "n_heavy_items", "n_candidates_heavy"):
+              "verify_rows_long", "n_visited_heavy", "n_heavy_items", "n_candidates_heavy",
+              "count_letters"):
         out[f] = int(getattr(st, f))
     return out
 

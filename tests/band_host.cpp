@@ -70,3 +70,19 @@ extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, i
     }
     return m;
 }
+
+// The count filter's per-candidate code (pn_count_pieces) on the host:
+// 1 when the candidate is kept for the band pass, 0 when dropped.
+extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, int n, int64_t d,
+                          int k) {
+    if (n < 1 || n > PN_MAX_READ_LEN || k < 0 || k > PN_MAX_K) return -1;
+    const std::vector<uint4> pl = text_planes(text, L, false);
+    const std::vector<uint2> rp = read_planes(read, n, false);
+    PnBandHead hd;
+    pn_band_load(pl.data(), rp.data(), d - k, hd);
+    int letters = 0;
+    const bool inside = d - k >= 0 && d - k + n + 2 * k < (int64_t)L;
+    const bool keep = inside ? pn_count_pieces<true>(hd, pl.data(), rp.data(), n, k, d - k, letters)
+                             : pn_count_pieces<false>(hd, pl.data(), rp.data(), n, k, d - k, letters);
+    return keep ? 1 : 0;
+}

@@ -110,3 +110,67 @@ def test_tail_check_is_lossless(band, seed):
             assert got == exp, (L, n, k, d)
             kept_with_hits += bool(exp)
     assert dropped > 50 and kept_with_hits > 50
+
+
+@pytest.fixture(scope="module")
+def count(band):
+    lib = ctypes.CDLL(LIB)
+    lib.count_host.restype = ctypes.c_int
+    lib.count_host.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
+                               ctypes.c_int64, ctypes.c_int]
+
+    def run(text, read, d, k):
+        text = np.ascontiguousarray(text, np.uint8)
+        read = np.ascontiguousarray(read, np.uint8)
+        r = lib.count_host(text.ctypes.data, len(text), read.ctypes.data, len(read), int(d), int(k))
+        assert r in (0, 1)
+        return bool(r)
+    return run
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_count_filter_is_lossless(count, seed):
+    """The count filter keeps a candidate only when its band holds at least
+    floor(n/8) - k exact 8-letter pieces of the read (the q-gram lemma on
+    disjoint pieces).  Every candidate whose band has a hit by the oracle's
+    cell-by-cell band DP must be kept; copies diverged well beyond k (a
+    repeat family's other members) and random candidates must mostly go."""
+    rng = np.random.default_rng(200 + seed)
+    kept_hits = dropped_far = far = 0
+    for trial in range(500):
+        L = int(rng.integers(150, 700))
+        text = rng.integers(0, 4, L).astype(np.uint8)
+        n = int(rng.integers(16, 257))
+        k = int(rng.integers(0, min(16, n // 8)))
+        p = int(rng.integers(-10, max(1, L - n + 10)))
+        x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
+                     np.uint8)
+        kind = rng.random()
+        if kind < 0.5:  # a few edits: substitutions, insertions, deletions
+            for _ in range(int(rng.integers(0, k + 3))):
+                j = int(rng.integers(0, len(x)))
+                e = rng.random()
+                if e < 0.8:
+                    x[j] = rng.integers(0, 4)
+                elif e < 0.9:
+                    x = np.concatenate([x[:j], rng.integers(0, 4, 1).astype(np.uint8), x[j:]])[:n]
+                else:
+                    x = np.concatenate([x[:j], x[j + 1:], rng.integers(0, 4, 1).astype(np.uint8)])
+        elif kind < 0.8:  # a diverged copy: 25 % substitutions, a 16-letter exact window kept
+            keep0 = int(rng.integers(0, n - 15))
+            sub = rng.random(n) < 0.25
+            sub[keep0:keep0 + 16] = False
+            x[sub] = (x[sub] + rng.integers(1, 4, int(sub.sum()))) % 4
+        else:
+            x = rng.integers(0, 4, n).astype(np.uint8)
+        d = max(p + int(rng.integers(-2, 3)), -256)
+        has_hit = bool(oracle.banded(text, x, d, k))
+        kept = count(text, x, d, k)
+        if has_hit:
+            assert kept, (L, n, k, d)
+            kept_hits += 1
+        elif kind >= 0.5 and n // 8 - k >= 4:
+            far += 1
+            dropped_far += not kept
+    assert kept_hits > 100
+    assert far > 50 and dropped_far > 0.9 * far

@@ -27,7 +27,7 @@ struct Buf {
 
 // an index orders its slices by the letters after the q-gram as well when
 // at least 1/kOrderNextShare of its occurrences lie in slices longer than
-// pn::kSubMin
+// pn::kLongSlice
 constexpr uint64_t kOrderNextShare = 128;
 
 enum MiscSlot {  // 64-bit words of the context's device scratch block
@@ -618,7 +618,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         // occurrences in long slices decide whether the slices are ordered
         // by the letters after the q-gram as well
         pn::launch_fill_u32((uint32_t *)&c->misc[kLongEntries], 2, 0u, st);
-        pn::launch_long_entries(ix, pn::kSubMin, (unsigned long long *)&c->misc[kLongEntries], st);
+        pn::launch_long_entries(ix, pn::kLongSlice, (unsigned long long *)&c->misc[kLongEntries],
+                                st);
         stage_end(c, st, tok, 7 + 3 * ((2 * q + 7) / 8) + 3 + 3);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
@@ -775,7 +776,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
         PN_CHECK(ensure(c, c->ws.lax, (x->n_distinct + 1) * sizeof(uint2)));
         PN_CHECK(ensure(c, c->ws.laxO, std::max<uint64_t>(x->n_qgrams, 1) * 8));
         pn::launch_fill_u32((uint32_t *)&c->misc[kLaxCount], 2, 0u, st);
-        pn::launch_lax_lists(ix, x->n_distinct, pn::kSubMin, (uint2 *)c->ws.lax.p,
+        pn::launch_lax_lists(ix, x->n_distinct, pn::kSearchMin, (uint2 *)c->ws.lax.p,
                              (unsigned long long *)c->ws.laxO.p,
                              (unsigned long long *)&c->misc[kLaxCount], st);
     }
@@ -790,7 +791,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
 pn::Lists lists_of(const pn_ctx *c) {
     const uint32_t *meta = (const uint32_t *)c->ws.side_meta.p;
     return pn::Lists{(const unsigned long long *)c->ws.side.p, meta + pn::kLcPatterns,
-                     (const unsigned long long *)c->ws.laxO.p, (const uint2 *)c->ws.lax.p, pn::kSubMin,
+                     (const unsigned long long *)c->ws.laxO.p, (const uint2 *)c->ws.lax.p, pn::kSearchMin,
                      c->sub_on ? 1 : 0};
 }
 

@@ -307,8 +307,12 @@ struct Lists {
     uint32_t sub_min;
     int sub_on;
 };
-// slices longer than this are searched rather than walked whole
-constexpr uint32_t kSubMin = 32;
+// an index orders its slices when a notable share of its occurrences lie in
+// slices longer than kLongSlice (reads from repeat families); filtration
+// then searches every slice of it longer than kSearchMin (and the lax lists
+// cover those slices)
+constexpr uint32_t kLongSlice = 32;
+constexpr uint32_t kSearchMin = 0;
 // the occurrence lists k_filter set aside (FilterOut::heavy)
 void launch_filter_heavy(const PnIndexDev &ix, const Lists &ls, FilterOut out, hipStream_t st);
 // the lax lists of the slots [0, n_slots) (count: one zeroed word, receives

@@ -277,6 +277,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="mixed-length batch with autotuned q/w vs per-length launches")
     ap.add_argument("--copy-kernel", action="store_true",
@@ -398,6 +399,37 @@ def main():
             f"{pcie['reads_per_s']:.3e} reads/s")
         del hb
 
+    # start positions and alignments (pn_align) of one sub-batch's hits, on
+    # the index of that sub-batch: host hits in, starts, error counts and
+    # operations back on the host
+    align = None
+    if not args.no_align:
+        a, b, d_r, d_o, d_kk = parts[0]
+        idx = pn.pn_index_build_dev(ctx, d_r, d_o, w.q, args.w)
+        try:
+            nh = pn.pn_map_dev(ctx, ref, idx, k, out, pn.PN_ALL_HITS, d_k=d_kk)
+            hh = np.frombuffer(out[:12 * nh].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE).copy()
+            lens = np.diff(w.offsets[a:b + 1]).astype(np.int64)
+            pn.pn_ctx_get_stats(ctx, reset=True)
+            pn.pn_ctx_set_timing(ctx, True)
+            t0 = time.perf_counter()
+            _, er, _, _ = pn.pn_align(ctx, ref, idx, hh, int(lens.max()) + 16)
+            t1 = time.perf_counter()
+            sa = pn.pn_ctx_get_stats(ctx, reset=True)
+            pn.pn_ctx_set_timing(ctx, False)
+        finally:
+            pn.pn_index_free(idx)
+        assert np.array_equal(er, hh["errors"])
+        cells = float((lens[hh["read_id"]] * (2 * hh["errors"].astype(np.int64) + 1)).sum())
+        kms = sa["ms"]["align"]
+        align = {"hits": int(nh), "seconds": t1 - t0, "hits_per_s": nh / (t1 - t0),
+                 "kernel_ms": kms, "launches": int(sa["launches"]["align"]),
+                 "kernel_hits_per_s": nh / max(kms, 1e-9) * 1000.0,
+                 "band_cells_per_s": cells / max(kms, 1e-9) * 1000.0,
+                 "path": "pn_align over the hits of one sub-batch (all-hits mode)"}
+        log(f"align: {nh} hits in {t1 - t0:.3f} s ({kms:.2f} ms in kernels)")
+        del hh
+
     K = args.steps
     stage_ms = {s: st["ms"][s] / K for s in pn.STAGES}
     launches = {s: st["launches"][s] / K for s in pn.STAGES}
@@ -502,6 +534,7 @@ def main():
         "latency_ms": None if serving is None else {"p50": serving["p50_ms"],
                                                      "p99": serving["p99_ms"]},
         "serving": serving,
+        "align": align,
         "hits": n_hits,
         "mapped_fraction": mapped,
         "stage_ms": stage_ms,

@@ -139,9 +139,10 @@ enum {
     PN_STAGE_VERIFY_LONG = 8,  /* validation, second pass: the candidates still open
                                   after the first pass's rows (one kernel) */
     PN_STAGE_COUNT = 9,        /* indexes of reads from repeat families: the count filter
-                                  (q-gram lemma on disjoint 8-letter pieces of the read)
+                                  (q-gram lemma on disjoint 4-letter pieces of the read)
                                   in place of the first pass (one kernel) */
-    PN_N_STAGES = 10
+    PN_STAGE_ALIGN = 10,       /* pn_align: start positions and alignments of hits */
+    PN_N_STAGES = 11
 };
 typedef struct {
     double ms[PN_N_STAGES];
@@ -264,6 +265,35 @@ int pn_filter(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, int k,
 int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_candidate *cands,
                 uint64_t n_cands, int k, const uint8_t *k_per_read, pn_hit **records,
                 uint64_t *n_records);
+
+/* Start position and alignment of hits (Section 3.3 runs the verification
+ * backwards from a hit's end to find its start; Section 3.4 makes the
+ * alignment in postprocessing).  hits: n_hits records as pn_map returns
+ * them, against `ref` and the reads of `idx` (read_id < n_reads, strand 0
+ * or 1, end_pos < L, errors <= PN_MAX_K: the hit's exact error count).  For
+ * each hit h, in host arrays of n_hits entries:
+ *   starts[h]  first aligned text position, in the strand's own
+ *              coordinates (the hit covers [start, end_pos]); of all
+ *              starts whose alignment has the hit's error count, the
+ *              latest one (the shortest text span);
+ *   errors[h]  the alignment's edit distance, equal to the hit's; 255 when
+ *              no alignment with the given error count ends at end_pos
+ *              (start 0, no ops);
+ *   ops        (may be NULL) row h of ops_stride bytes: the operations from
+ *              the read's first letter on, 0 '=' match, 1 'X' substitution,
+ *              2 'I' read letter not in the text, 3 'D' text letter not in
+ *              the read; among equally good alignments the one that, walking
+ *              back from the read's first letter, takes a diagonal step
+ *              first, then 'I', then 'D'.  At most n + errors operations;
+ *              a longer row is cut at ops_stride;
+ *   n_ops[h]   (may be NULL: then ops is not written) the number of
+ *              operations.
+ * The caller owns every array.  PN_EINVAL for a record outside those
+ * bounds or a NULL starts / errors with n_hits > 0; PN_ENOMEM when the
+ * device work space cannot be had. */
+int pn_align(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_hit *hits,
+             uint64_t n_hits, uint32_t *starts, uint8_t *errors, uint8_t *ops,
+             uint32_t ops_stride, uint16_t *n_ops);
 
 /* pn_validate for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.

@@ -113,6 +113,8 @@ struct pn_index {
     uint32_t *S, *Sp;
     unsigned long long *O;
     uint32_t *lcinfo;
+    uint32_t *tab_id = nullptr, *tabs = nullptr;  // slice tables (ordered index)
+    uint32_t n_tabs = 0;
     uint32_t lc_size[pn::kLcPatterns];  // slice sizes of the low-complexity q-grams
     uint64_t lc_total;
 };
@@ -345,6 +347,8 @@ PnIndexDev index_desc(const pn_index *x) {
     d.Sp = x->Sp;
     d.O = x->O;
     d.lcinfo = x->lcinfo;
+    d.tab_id = x->tab_id;
+    d.tabs = x->tabs;
     d.n_reads = x->n_reads;
     d.max_len = (uint32_t)x->max_len;
     d.q = x->q;
@@ -364,6 +368,8 @@ void free_index_arrays(pn_index *x) {
     dfree(c, x->Sp);
     dfree(c, x->O);
     dfree(c, x->lcinfo);
+    dfree(c, x->tab_id);
+    dfree(c, x->tabs);
 }
 
 }  // namespace
@@ -649,9 +655,35 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
                 pn::launch_index_from_sorted(ix, sorted, T, x->O, flags, x->I, st);
                 stage_end(c, st, tok, 5 * (1 + (2 * q + 9) / 8) + 1);
                 x->after_sorted = true;
-                e = hipStreamSynchronize(st);
-                if (e != hipSuccess) s = map_err(e);
-                else collect_stages(c);
+                // a table per long slice: where each set of letters after the
+                // q-gram starts (filtration's searches become two loads)
+                const uint64_t D = x->n_distinct;
+                uint32_t *tflags = nullptr, *tnum = nullptr;
+                s = dalloc_t(c, D + 1, &tnum);
+                if (!s) s = dalloc_t(c, D + 1, &tflags);
+                if (!s) {
+                    pn::launch_tab_flags(x->Sp, D, pn::kTabMin, tflags, st);
+                    pn::launch_scan_u32(tflags, tnum, D, partials, st);
+                    uint32_t nt = 0;
+                    e = hipMemcpyAsync(&nt, tnum + D, 4, hipMemcpyDeviceToHost, st);
+                    if (e == hipSuccess) e = hipStreamSynchronize(st);
+                    s = map_err(e);
+                    if (!s) {
+                        x->n_tabs = nt;
+                        s = dalloc_t(c, D + 1, &x->tab_id);
+                        if (!s) s = dalloc_t(c, (uint64_t)nt * pn::kTabWidth + 1, &x->tabs);
+                        if (!s) {
+                            // (the flags' buffer then takes the list of table slots)
+                            pn::launch_tab_build(x->O, x->Sp, D, pn::kTabMin, tnum, nt, x->tab_id,
+                                                 tflags, x->tabs, st);
+                            e = hipStreamSynchronize(st);
+                            s = map_err(e);
+                        }
+                    }
+                }
+                dfree(c, tnum);
+                dfree(c, tflags);
+                if (!s) collect_stages(c);
             }
         }
     }
@@ -1434,6 +1466,81 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
     *records = h;
     *n_records = got;
     return PN_OK;
+}
+
+int pn_align(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_hit *hits, uint64_t n,
+             uint32_t *starts, uint8_t *errors, uint8_t *ops, uint32_t stride, uint16_t *n_ops) {
+    if (!c || !ref || !x || ref->ctx->device != c->device || x->ctx != c) return PN_EINVAL;
+    if (n && (!hits || !starts || !errors)) return PN_EINVAL;
+    for (uint64_t h = 0; h < n; h++) {
+        const pn_hit &t = hits[h];
+        if (t.read_id >= x->n_reads || t.strand > 1 || t.end_pos >= ref->L || t.errors > PN_MAX_K)
+            return PN_EINVAL;
+    }
+    if (!n) return PN_OK;
+    static_assert(sizeof(pn_hit) == 12, "hit records are three words");
+    const bool want_ops = n_ops != nullptr;
+    const uint32_t ost = want_ops && ops ? stride : 0;
+    // chunks whose op-code rows fit 512 MiB
+    const uint64_t rows = (uint64_t)std::max(x->max_len, 1);
+    const uint64_t chunk = std::min<uint64_t>(n, std::max<uint64_t>(64, (512ull << 20) / (rows * 8)));
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    uint32_t *dh = nullptr, *dperm = nullptr, *dstart = nullptr;
+    unsigned long long *bp = nullptr;
+    uint8_t *derr = nullptr, *dops = nullptr;
+    uint16_t *dnops = nullptr;
+    int s = dalloc_t(c, chunk * 3, &dh);
+    if (!s) s = dalloc_t(c, chunk, &dperm);
+    if (!s) s = dalloc_t(c, chunk * rows, &bp);
+    if (!s) s = dalloc_t(c, chunk, &dstart);
+    if (!s) s = dalloc_t(c, chunk, &derr);
+    if (!s && ost) s = dalloc_t(c, chunk * ost, &dops);
+    if (!s && want_ops) s = dalloc_t(c, chunk, &dnops);
+    std::vector<uint32_t> perm(chunk);
+    const PnRefDev rd = ref_desc(ref);
+    const PnIndexDev xd = index_desc(x);
+    for (uint64_t c0 = 0; !s && c0 < n; c0 += chunk) {
+        const uint64_t m = std::min(chunk, n - c0);
+        // the chunk's hits grouped by error count (one launch per count)
+        uint32_t cnt[PN_MAX_K + 1] = {}, off[PN_MAX_K + 2] = {};
+        for (uint64_t h = 0; h < m; h++) cnt[hits[c0 + h].errors]++;
+        for (int v = 0; v <= PN_MAX_K; v++) off[v + 1] = off[v] + cnt[v];
+        uint32_t at[PN_MAX_K + 1];
+        for (int v = 0; v <= PN_MAX_K; v++) at[v] = off[v];
+        for (uint64_t h = 0; h < m; h++) perm[at[hits[c0 + h].errors]++] = (uint32_t)h;
+        s = map_err(hipMemcpyAsync(dh, hits + c0, m * sizeof(pn_hit), hipMemcpyHostToDevice, st));
+        if (!s)
+            s = map_err(hipMemcpyAsync(dperm, perm.data(), m * 4, hipMemcpyHostToDevice, st));
+        const int tok = s ? -1 : stage_begin(c, st, PN_STAGE_ALIGN);
+        int launches = 0;
+        for (int v = 0; !s && v <= PN_MAX_K; v++) {
+            if (!cnt[v]) continue;
+            pn::launch_align(rd, xd, v, dh, dperm + off[v], cnt[v], bp, dstart, derr, dops, ost,
+                             dnops, st);
+            launches++;
+        }
+        stage_end(c, st, tok, launches);
+        if (!s) s = map_err(hipGetLastError());
+        if (!s)
+            s = map_err(hipMemcpyAsync(starts + c0, dstart, m * 4, hipMemcpyDeviceToHost, st));
+        if (!s) s = map_err(hipMemcpyAsync(errors + c0, derr, m, hipMemcpyDeviceToHost, st));
+        if (!s && ost)
+            s = map_err(hipMemcpyAsync(ops + c0 * ost, dops, m * ost, hipMemcpyDeviceToHost, st));
+        if (!s && want_ops)
+            s = map_err(hipMemcpyAsync(n_ops + c0, dnops, m * 2, hipMemcpyDeviceToHost, st));
+        if (!s) s = map_err(hipStreamSynchronize(st));
+        if (!s) collect_stages(c);
+    }
+    if (s) (void)hipStreamSynchronize(st);
+    dfree(c, dh);
+    dfree(c, dperm);
+    dfree(c, bp);
+    dfree(c, dstart);
+    dfree(c, derr);
+    dfree(c, dops);
+    dfree(c, dnops);
+    return s;
 }
 
 }  // extern "C"

@@ -155,18 +155,23 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
 }
 
 // Count filter (the q-gram lemma of Section 2.2, with the read cut into its
-// m = floor(n / 8) disjoint pieces of 8 letters): an edit falls into one
+// m = floor(n / 4) disjoint pieces of 4 letters): an edit falls into one
 // piece at most (a deletion between two pieces breaks neither), so an
 // alignment with at most k errors leaves at least m - k pieces exact, each
 // on one diagonal of the alignment; every cell of an alignment through the
 // candidate's diagonal d lies within k diagonals of d, so those pieces
 // match the text exactly on diagonals of the band [d - k, d + k].  A piece
-// is exact on band diagonal b when bit b of the match words of its 8
-// letters (the band's Eq, one row per letter) is set in all of them.  The
+// is exact on band diagonal b when bit b of the match words of its letters
+// (the band's Eq, one row per letter) is set in all of them.  The
 // candidate is dropped as soon as the pieces found plus those unchecked
-// fall below m - k, and kept once m - k are found.  kInside: every band
-// position of the wave's candidates lies in [0, L) (no validity plane).
-constexpr int kPnPiece = 8;
+// fall below m - k, and kept once m - k are found.  Short pieces decide
+// sooner against a diverged copy (a 4-letter piece of a copy at 72 %
+// identity is exact a quarter of the time, an 8-letter one a fourteenth:
+// six failures come after fewer letters) while a chance match on one of
+// the band's 2k + 1 diagonals stays rare (2k + 1 in 256).  kInside: every
+// band position of the wave's candidates lies in [0, L) (no validity
+// plane).
+constexpr int kPnPiece = 4;
 
 template <bool kInside>
 __host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, const uint4 *__restrict__ pl,
@@ -190,7 +195,7 @@ __host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, c
     for (int w = 0;; w++) {
         const uint2 rwn = 32 * (w + 1) < kPnPiece * m ? rp[w + 1] : rw;
 #pragma unroll
-        for (int pc = 0; pc < 4; pc++) {
+        for (int pc = 0; pc < 32 / kPnPiece; pc++) {
             uint32_t acc = M;
 #pragma unroll
             for (int u = 0; u < kPnPiece; u++) {

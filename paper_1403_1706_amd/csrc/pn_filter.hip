@@ -213,6 +213,7 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
 // k_filter_heavy, in items of at most kItem occurrences; shorter ones are
 // walked by their lane.
 constexpr uint32_t kItem = 1024;
+constexpr uint32_t kStrictHeavy = 4;
 constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
@@ -293,8 +294,16 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const pn::Lists 
         // (the piece starts among them: the entries of reads in piece mode
         // that can pair here; the other reads' entries are in the lax list)
         if (avail == 4u) {
-            rg.a0 = code_lower_bound((gu64 *)ix.O, ks, ke, 2u * N + 1u);
-            rg.a1 = code_lower_bound((gu64 *)ix.O, rg.a0, ke, 2u * N + 2u);
+            const uint32_t tid = ix.tab_id[x];
+            if (tid != 0xffffffffu) {
+                // a long slice: its table
+                const uint32_t *T = ix.tabs + (uint64_t)tid * pn::kTabWidth;
+                rg.a0 = ks + T[2u * N + 1u];
+                rg.a1 = ks + T[2u * N + 2u];
+            } else {
+                rg.a0 = code_lower_bound((gu64 *)ix.O, ks, ke, 2u * N + 1u);
+                rg.a1 = code_lower_bound((gu64 *)ix.O, rg.a0, ke, 2u * N + 2u);
+            }
         } else {
             rg.a0 = rg.a1 = ks;
         }
@@ -321,8 +330,10 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
                                               const pn::FilterOut &out,
                                               unsigned long long &set_aside) {
     const uint32_t len = (rg.a1 - rg.a0) + (rg.b1 - rg.b0);
-    // the longest ranges wait for k_filter_heavy (a wave per item)
-    const bool heavy = valid && len > out.heavy_min;
+    // the longest ranges wait for k_filter_heavy (a wave per item); a
+    // searched range of an ordered slice is nearly all candidates, so a lane
+    // keeps fewer of them (its wave waits for its longest lane)
+    const bool heavy = valid && len > (kSub && rg.strictA ? kStrictHeavy : out.heavy_min);
     // a set-aside entry becomes one item per kItem occurrences (a wave walks
     // an item), so that no single item is long
     const uint32_t nitems = heavy ? (len + kItem - 1) / kItem : 0u;

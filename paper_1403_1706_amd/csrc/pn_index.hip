@@ -19,6 +19,8 @@
 // Each O entry also carries the letter before its q-gram and the (up to)
 // four letters after it, which the filter compares with the reference
 // without touching the reads.
+#include <algorithm>
+
 #include "pn_internal.h"
 
 namespace {
@@ -405,6 +407,85 @@ __global__ __launch_bounds__(256) void k_long_entries(const uint32_t *__restrict
     if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
 }
 
+// Slice tables of an ordered index.  Inside a slice the entries are
+// ordered by v = 2 x (9-bit code of the letters after the q-gram) + piece
+// start, so for a text position whose four next letters are N the entries
+// filtration takes lie at [lb(2N + 1), lb(2N + 2)), lb(t) = the first entry
+// whose v is t or more.  For a slice longer than min_len the table holds
+// lb(t) - (slice start) for t = 0 .. pn::kTabWidth - 1, two loads instead of
+// a binary search over the slice.
+
+__device__ __forceinline__ uint32_t order_value(unsigned long long v) {
+    const uint32_t lo = (uint32_t)v;
+    return 2u * after_code(lo >> 24, (lo >> 21) & 7u) + ((lo >> 20) & 1u);
+}
+
+// flags[x] = 1 for a slot whose slice is longer than min_len
+__global__ void k_tab_flags(const uint32_t *__restrict__ Sp, uint64_t D, uint32_t min_len,
+                            uint32_t *__restrict__ flags) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < D; x += stride)
+        flags[x] = Sp[x + 1] - Sp[x] > min_len ? 1u : 0u;
+}
+
+// tab_id[x] = the table's number (num: exclusive scan of the flags) or ~0;
+// list[number] = x
+__global__ void k_tab_ids(const uint32_t *__restrict__ Sp, uint64_t D, uint32_t min_len,
+                          const uint32_t *__restrict__ num, uint32_t *__restrict__ tab_id,
+                          uint32_t *__restrict__ list) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < D; x += stride) {
+        const bool lng = Sp[x + 1] - Sp[x] > min_len;
+        tab_id[x] = lng ? num[x] : 0xffffffffu;
+        if (lng) list[num[x]] = (uint32_t)x;
+    }
+}
+
+// a block per table: counts of each v below kTabWidth, then their prefix
+__global__ __launch_bounds__(256) void k_tab_fill(const unsigned long long *__restrict__ O,
+                                                  const uint32_t *__restrict__ Sp,
+                                                  const uint32_t *__restrict__ list,
+                                                  uint32_t n_tabs, uint32_t *__restrict__ tabs) {
+    constexpr uint32_t W = pn::kTabWidth;
+    __shared__ uint32_t h[W + 1];
+    for (uint32_t t = blockIdx.x; t < n_tabs; t += gridDim.x) {
+        for (uint32_t b = threadIdx.x; b <= W; b += 256) h[b] = 0;
+        __syncthreads();
+        const uint32_t x = list[t];
+        const uint32_t ks = Sp[x], ke = Sp[x + 1];
+        for (uint32_t i = ks + threadIdx.x; i < ke; i += 256) {
+            const uint32_t v = order_value(O[i]);
+            if (v + 1 < W) atomicAdd(&h[v + 1], 1u);  // counted into lb(v + 1) onwards
+        }
+        __syncthreads();
+        // inclusive prefix over h[0 .. W-1] by the first wave: h[t] = #(v < t)
+        if (threadIdx.x < 64) {
+            const uint32_t lane = threadIdx.x;
+            constexpr uint32_t per = (W + 63) / 64;
+            uint32_t sum = 0;
+            for (uint32_t j = 0; j < per; j++) {
+                const uint32_t b = lane * per + j;
+                if (b < W) sum += h[b];
+            }
+            uint32_t incl = sum;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o);
+                if ((int)lane >= o) incl += y;
+            }
+            uint32_t run = incl - sum;
+            uint32_t *T = tabs + (uint64_t)t * W;
+            for (uint32_t j = 0; j < per; j++) {
+                const uint32_t b = lane * per + j;
+                if (b < W) {
+                    run += h[b];
+                    T[b] = run;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 inline unsigned grid_for(uint64_t n, unsigned threads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -457,6 +538,24 @@ void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long l
                          hipStream_t st) {
     hipLaunchKernelGGL(k_long_entries, dim3(1024), dim3(256), 0, st, ix.S, ix.n_groups, ix.Sp,
                        min_len, out);
+}
+
+void launch_tab_flags(const uint32_t *Sp, uint64_t D, uint32_t min_len, uint32_t *flags,
+                      hipStream_t st) {
+    if (!D) return;
+    hipLaunchKernelGGL(k_tab_flags, dim3(pn_stride_blocks(D, 256)), dim3(256), 0, st, Sp, D,
+                       min_len, flags);
+}
+
+void launch_tab_build(const unsigned long long *O, const uint32_t *Sp, uint64_t D,
+                      uint32_t min_len, const uint32_t *num, uint32_t n_tabs, uint32_t *tab_id,
+                      uint32_t *list, uint32_t *tabs, hipStream_t st) {
+    if (!D) return;
+    hipLaunchKernelGGL(k_tab_ids, dim3(pn_stride_blocks(D, 256)), dim3(256), 0, st, Sp, D,
+                       min_len, num, tab_id, list);
+    if (n_tabs)
+        hipLaunchKernelGGL(k_tab_fill, dim3(std::min<uint32_t>(n_tabs, 65536u)), dim3(256), 0, st,
+                           O, Sp, (const uint32_t *)list, n_tabs, tabs);
 }
 
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st) {

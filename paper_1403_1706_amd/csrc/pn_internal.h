@@ -72,6 +72,8 @@ struct PnIndexDev {
     const uint32_t *Sp;       // n_distinct + 1
     const unsigned long long *O;  // n_qgrams 64-bit entries
     const uint32_t *lcinfo;   // per read: low-complexity offsets | (intervals << 16)
+    const uint32_t *tab_id;   // ordered index: per slot, its slice table or ~0 (or null)
+    const uint32_t *tabs;     // slice tables, pn::kTabWidth words each
     uint32_t n_reads;
     uint32_t max_len;
     int q;
@@ -206,6 +208,19 @@ void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *ke
 void launch_starts_to_sp(const uint8_t *flags, uint64_t T, uint32_t *partials, uint32_t *Sp,
                          hipStream_t st);
 void launch_read_lc(const PnIndexDev &ix, uint32_t *lcinfo, hipStream_t st);
+// slice tables of an ordered index (pn_index.hip): for a slot x whose slice
+// is longer than kTabMin, tabs[tab_id[x] * kTabWidth + t] = (first entry of
+// the slice whose order value 2 code + piece is t or more) - slice start
+constexpr uint32_t kTabWidth = 513;  // t = 0 .. 512: every 2N + 1 and 2N + 2, N < 256
+constexpr uint32_t kTabMin = 128;
+// flags[x] = slice of slot x longer than min_len (D slots)
+void launch_tab_flags(const uint32_t *Sp, uint64_t D, uint32_t min_len, uint32_t *flags,
+                      hipStream_t st);
+// num: exclusive scan of those flags; writes tab_id (D words), list (n_tabs
+// words: the slot of each table) and the n_tabs tables
+void launch_tab_build(const unsigned long long *O, const uint32_t *Sp, uint64_t D,
+                      uint32_t min_len, const uint32_t *num, uint32_t n_tabs, uint32_t *tab_id,
+                      uint32_t *list, uint32_t *tabs, hipStream_t st);
 // the number of occurrences in slices of O longer than min_len, added to *out
 void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long long *out,
                          hipStream_t st);
@@ -352,7 +367,7 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
                    bool first, hipStream_t st);
 
 // The count filter (pn_verify.hip): each candidate of `in` whose band holds
-// at least floor(n/8) - k exact pieces of 8 read letters (the q-gram lemma
+// at least floor(n/4) - k exact pieces of 4 read letters (the q-gram lemma
 // on disjoint pieces; Section 2.2) goes to surv (in's shape, counters n_surv
 // zeroed by the caller) for the band pass; *letters += read letters looked at.
 void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
@@ -389,6 +404,12 @@ void launch_finish_hits(const unsigned long long *sorted, uint64_t n, int ebits,
                         uint32_t n_reads, uint32_t *minv, uint32_t *flags, uint32_t *pos,
                         uint32_t *partials, void *out_hits, uint64_t capacity,
                         unsigned long long *n_out, hipStream_t st);
+// start and alignment of the hits of error count v (pn_align.hip): hw the
+// chunk's hit records, perm the chunk-local indices of the cnt hits, bp
+// cnt * (longest read) words of work space
+void launch_align(const PnRefDev &ref, const PnIndexDev &ix, int v, const uint32_t *hw,
+                  const uint32_t *perm, uint32_t cnt, unsigned long long *bp, uint32_t *starts,
+                  uint8_t *errs, uint8_t *ops, uint32_t stride, uint16_t *n_ops, hipStream_t st);
 void launch_records_to_hits(const unsigned long long *sorted, uint64_t n, int ebits, void *out,
                             hipStream_t st);
 void launch_cand_keys(const uint2 *c, uint64_t n, unsigned long long *keys, hipStream_t st);

@@ -49,11 +49,12 @@ class _IndexInfo(ctypes.Structure):
 
 
 STAGES = ["ingest", "index", "filter_heavy", "filter_emit", "verify", "sort", "finish", "rules",
-          "verify_long", "count"]
+          "verify_long", "count", "align"]
 
 
 class _Stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_uint64 * 10),
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)),
+                ("launches", ctypes.c_uint64 * len(STAGES)),
                 ("n_seeds", ctypes.c_uint64), ("n_candidates", ctypes.c_uint64),
                 ("verify_rows", ctypes.c_uint64), ("n_records", ctypes.c_uint64),
                 ("n_hits", ctypes.c_uint64), ("n_visited", ctypes.c_uint64),
@@ -125,6 +126,7 @@ _sig("pn_filter", _int, [_P, _P, _P, _int, _P, _PP, ctypes.POINTER(_u64), ctypes
 _sig("pn_validate", _int, [_P, _P, _P, _P, _u64, _int, _P, _PP, ctypes.POINTER(_u64)])
 _sig("pn_validate_noalloc", _int, [_P, _P, _P, _P, _u64, _int, _P, _P, _u64,
                                    ctypes.POINTER(_u64), _P])
+_sig("pn_align", _int, [_P, _P, _P, _P, _u64, _P, _P, _P, _u32, _P])
 _sig("pn_server_create", _int, [_P, _P, ctypes.POINTER(_ServerConfig), _PP])
 _sig("pn_server_submit", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _P, _int,
                                 ctypes.POINTER(_u64)])
@@ -144,7 +146,7 @@ EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
             "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
-            "pn_validate_noalloc",
+            "pn_validate_noalloc", "pn_align",
             "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_poll",
             "pn_server_get_stats", "pn_server_destroy", "pn_autotune", "pn_map_batched"]
 
@@ -361,6 +363,31 @@ def pn_validate_noalloc(ctx, ref, idx, d_cands, n_cands: int, k, d_out, stream=N
         raise e
     _check(st, "pn_validate_noalloc")
     return n.value
+
+
+OPS = "=XID"
+
+
+def pn_align(ctx, ref, idx, hits: np.ndarray, ops_stride: int = 0):
+    """Start positions and alignments of hits (HIT_DTYPE records as pn_map
+    returns them).  Returns (starts u32, errors u8, ops u8 [n, ops_stride],
+    n_ops u16); with ops_stride 0 only starts and errors are computed and
+    ops / n_ops are None.  Op codes index OPS ('=', 'X', 'I', 'D'), read's
+    first letter first."""
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    n = len(hits)
+    starts = np.zeros(n, dtype=np.uint32)
+    errors = np.zeros(n, dtype=np.uint8)
+    ops = np.zeros((n, ops_stride), dtype=np.uint8) if ops_stride else None
+    n_ops = np.zeros(n, dtype=np.uint16) if ops_stride else None
+    _check(_lib.pn_align(ctx, ref, idx, _ptr(hits), n, _ptr(starts), _ptr(errors),
+                         None if ops is None else _ptr(ops), int(ops_stride),
+                         None if n_ops is None else _ptr(n_ops)), "pn_align")
+    return starts, errors, ops, n_ops
+
+
+def ops_string(row: np.ndarray, m: int) -> str:
+    return "".join(OPS[o] for o in row[:m])
 
 
 def make_candidates(read_id, strand, diagonal) -> np.ndarray:

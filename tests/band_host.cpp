@@ -5,7 +5,7 @@
 #include <cstdint>
 #include <vector>
 
-#include "../paper_1403_1706_amd/csrc/pn_band.h"
+#include "../paper_1403_1706_amd/csrc/pn_align.h"
 
 namespace {
 
@@ -85,4 +85,32 @@ extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, 
     const bool keep = inside ? pn_count_pieces<true>(hd, pl.data(), rp.data(), n, k, d - k, letters)
                              : pn_count_pieces<false>(hd, pl.data(), rp.data(), n, k, d - k, letters);
     return keep ? 1 : 0;
+}
+
+// The alignment code (pn_align_one) on the host for one hit on `text` (the
+// strand's own letters) ending at e with v errors: the other strand's planes
+// are those of the text's reverse complement, the read's are those of its
+// reverse complement.  Returns the number of ops, with *start and *err.
+template <int K>
+static int align_k(const std::vector<uint4> &pl, const std::vector<uint2> &rp, int n, uint64_t e,
+                   uint64_t L, uint32_t *start, uint8_t *err, uint8_t *ops, uint32_t stride) {
+    std::vector<unsigned long long> bp((size_t)n + 1);
+    return pn_align_one<K>(pl.data(), rp.data(), n, (int64_t)e, L, bp.data(), 1, true, ops, stride,
+                           start, err);
+}
+
+extern "C" int align_host(const uint8_t *text, uint64_t L, const uint8_t *read, int n, uint64_t e,
+                          int v, uint32_t *start, uint8_t *err, uint8_t *ops, uint32_t stride) {
+    if (n < 1 || n > PN_MAX_READ_LEN || v < 0 || v > PN_MAX_K || e >= L) return -1;
+    const std::vector<uint4> pl = text_planes(text, L, true);
+    const std::vector<uint2> rp = read_planes(read, n, true);
+    switch (v) {
+#define ALIGN_CASE(k) \
+    case k: return align_k<k>(pl, rp, n, e, L, start, err, ops, stride);
+        ALIGN_CASE(0) ALIGN_CASE(1) ALIGN_CASE(2) ALIGN_CASE(3) ALIGN_CASE(4) ALIGN_CASE(5)
+        ALIGN_CASE(6) ALIGN_CASE(7) ALIGN_CASE(8) ALIGN_CASE(9) ALIGN_CASE(10) ALIGN_CASE(11)
+        ALIGN_CASE(12) ALIGN_CASE(13) ALIGN_CASE(14) ALIGN_CASE(15)
+#undef ALIGN_CASE
+    }
+    return -1;
 }

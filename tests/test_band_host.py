@@ -131,7 +131,7 @@ def count(band):
 @pytest.mark.parametrize("seed", range(3))
 def test_count_filter_is_lossless(count, seed):
     """The count filter keeps a candidate only when its band holds at least
-    floor(n/8) - k exact 8-letter pieces of the read (the q-gram lemma on
+    floor(n/4) - k exact 4-letter pieces of the read (the q-gram lemma on
     disjoint pieces).  Every candidate whose band has a hit by the oracle's
     cell-by-cell band DP must be kept; copies diverged well beyond k (a
     repeat family's other members) and random candidates must mostly go."""
@@ -141,7 +141,7 @@ def test_count_filter_is_lossless(count, seed):
         L = int(rng.integers(150, 700))
         text = rng.integers(0, 4, L).astype(np.uint8)
         n = int(rng.integers(16, 257))
-        k = int(rng.integers(0, min(16, n // 8)))
+        k = int(rng.integers(0, min(16, n // 4)))
         p = int(rng.integers(-10, max(1, L - n + 10)))
         x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
                      np.uint8)
@@ -169,8 +169,73 @@ def test_count_filter_is_lossless(count, seed):
         if has_hit:
             assert kept, (L, n, k, d)
             kept_hits += 1
-        elif kind >= 0.5 and n // 8 - k >= 4:
+        elif kind >= 0.5 and n // 4 - k >= 8:
             far += 1
             dropped_far += not kept
     assert kept_hits > 100
     assert far > 50 and dropped_far > 0.9 * far
+
+
+@pytest.fixture(scope="module")
+def align(band):
+    lib = ctypes.CDLL(LIB)
+    lib.align_host.restype = ctypes.c_int
+    lib.align_host.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int,
+                               ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_uint32]
+
+    def run(text, read, e, v):
+        text = np.ascontiguousarray(text, np.uint8)
+        read = np.ascontiguousarray(read, np.uint8)
+        st = ctypes.c_uint32()
+        er = ctypes.c_uint8()
+        ops = np.zeros(len(read) + 32, np.uint8)
+        m = lib.align_host(text.ctypes.data, len(text), read.ctypes.data, len(read), int(e), int(v),
+                           ctypes.byref(st), ctypes.byref(er), ops.ctypes.data, len(ops))
+        assert m >= 0
+        return st.value, er.value, "".join("=XID"[o] for o in ops[:m])
+    return run
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_align_code_equals_oracle(align, seed):
+    """The alignment code (the reversed read against the text read
+    backwards, in a band of the hit's error count, as the other strand's
+    planes against the read's reverse complement) gives the oracle's start,
+    error count and operations for every hit, also with a wider band than
+    the error count needs; a band narrower than the error count finds
+    nothing."""
+    rng = np.random.default_rng(300 + seed)
+    checked = with_indels = 0
+    for trial in range(400):
+        L = int(rng.integers(60, 600))
+        text = rng.integers(0, 4, L).astype(np.uint8)
+        if rng.random() < 0.3:  # homopolymer runs: many equally good alignments
+            a = int(rng.integers(0, L - 30))
+            text[a:a + int(rng.integers(8, 30))] = rng.integers(0, 4)
+        n = int(rng.integers(8, 257))
+        p = int(rng.integers(-5, max(1, L - n + 5)))
+        x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
+                     np.uint8)
+        for _ in range(int(rng.integers(0, 8))):
+            j = int(rng.integers(0, len(x)))
+            r = rng.random()
+            if r < 0.6:
+                x[j] = rng.integers(0, 4)
+            elif r < 0.8:
+                x = np.concatenate([x[:j], rng.integers(0, 4, 1).astype(np.uint8), x[j:]])
+            elif len(x) > 8:
+                x = np.concatenate([x[:j], x[j + 1:]])
+        x = x[:256]
+        e = int(np.clip(p + len(x) - 1 + int(rng.integers(-3, 4)), 0, L - 1))
+        start, err, ops = oracle.align(text, x, e, len(x) + 15)
+        if err > 15:
+            continue
+        assert align(text, x, e, err) == (start, err, ops), (L, len(x), e, err)
+        wider = int(rng.integers(err, 16))
+        assert align(text, x, e, wider) == (start, err, ops), (L, len(x), e, err, wider)
+        if err > 0:
+            assert align(text, x, e, err - 1)[1] == 0xff
+        checked += 1
+        with_indels += ("I" in ops) or ("D" in ops)
+    assert checked > 250 and with_indels > 50

@@ -143,7 +143,8 @@ def _renumber(h, ids):
 def test_human_workload_sample_equals_oracle_digest(pn):
     """The human-shaped workload (3 Gbp, 10 M reads) mapped as bench.py maps
     it (sub-batches of 2^21 reads, one index each, against the whole
-    reference): the hits of a seeded 2,000-read sample equal the oracle's."""
+    reference): the hits of a seeded 2,000-read sample equal the oracle's,
+    and so do the start positions and alignments of those hits."""
     import torch
     path = os.path.join(GOLDEN, "human_sample_digest.json")
     dg = json.load(open(path))
@@ -156,6 +157,7 @@ def test_human_workload_sample_equals_oracle_digest(pn):
     dev = torch.device("cuda:0")
     sub_batch = 1 << 21
     got = {0: [], 1: []}
+    aligned = []
     with pn.Session(0) as s:
         ref = s.ref(w.ref)
         buf = torch.empty(12 * 64 * sub_batch, dtype=torch.uint8, device=dev)
@@ -171,8 +173,14 @@ def test_human_workload_sample_equals_oracle_digest(pn):
                     n = pn.pn_map_dev(s.ctx, ref, idx, 5, buf, mode)
                     h = np.frombuffer(buf[:n * 12].cpu().numpy().tobytes(),
                                       dtype=pn.HIT_DTYPE).copy()
+                    sel = np.isin(h["read_id"].astype(np.int64) + a, ids)
+                    if mode == 0 and sel.any():
+                        # the sampled reads' hits aligned against this index
+                        st, er, ops, nops = pn.pn_align(s.ctx, ref, idx, h[sel], 272)
+                        aligned.append((h[sel]["read_id"].astype(np.int64) + a,
+                                        h[sel], st, er, ops, nops))
                     h["read_id"] += np.uint32(a)
-                    got[mode].append(h[np.isin(h["read_id"], ids)])
+                    got[mode].append(h[sel])
             finally:
                 pn.pn_index_free(idx)
     for mode, name in ((0, "all"), (1, "best")):
@@ -189,6 +197,24 @@ def test_human_workload_sample_equals_oracle_digest(pn):
             b_ = {tuple(r) for r in fields(orc)}
             pytest.fail(f"mode {name}: first 200 sampled reads: {len(b_ - a_)} oracle hits "
                         f"missing (first {sorted(b_ - a_)[:5]}), {len(a_ - b_)} extra")
+    # start positions and alignments of the sample's hits (at most 3,000 of
+    # them) equal the oracle's on the whole 3 Gbp strands
+    say("aligning the sample's hits with the oracle")
+    text = [oracle.encode(w.ref)]
+    text.append(oracle.reverse_complement(text[0]))
+    checked = 0
+    for gid, hh, st, er, ops, nops in aligned:
+        for t in range(len(hh)):
+            if checked >= 3000:
+                break
+            r, e, sd = int(gid[t]), int(hh[t]["end_pos"]), int(hh[t]["strand"])
+            x = oracle.encode(w.reads[int(w.offsets[r]):int(w.offsets[r + 1])])
+            want = oracle.align(text[sd], x, e, len(x) + 15)
+            mine_t = (int(st[t]), int(er[t]), pn.ops_string(ops[t], int(nops[t])))
+            assert mine_t == want, f"read {r} strand {sd} end {e}"
+            checked += 1
+    say(f"{checked} alignments equal the oracle's")
+    assert checked >= min(3000, dg["all"]["n_hits"])
 
 
 def test_position_set_past_2_pow_32_entries(pn):

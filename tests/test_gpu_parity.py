@@ -385,6 +385,72 @@ def test_error_statuses(pn, sess):
     assert len(pn.pn_map(sess.ctx, ref, idx, 5, 0)) > 0
 
 
+# ---------------------------------------------------------------------------
+# start positions and alignments of hits (Section 3.3 backward pass, 3.4)
+
+
+def check_alignments(pn, sess, ref_bytes, reads, offsets, refh, idx, hits, k_max=15):
+    """pn_align on `hits` against oracle.align on the strand's text, hit by
+    hit: start, error count and operations identical; returns the number of
+    hits checked."""
+    stride = int(np.diff(offsets).max()) + 16
+    starts, errs, ops, n_ops = pn.pn_align(sess.ctx, refh, idx, hits, stride)
+    text = [oracle.encode(ref_bytes)]
+    text.append(oracle.reverse_complement(text[0]))
+    for h in range(len(hits)):
+        r, e, s, v = (int(hits[h][f]) for f in ("read_id", "end_pos", "strand", "errors"))
+        x = oracle.encode(reads[int(offsets[r]):int(offsets[r + 1])])
+        want = oracle.align(text[s], x, e, len(x) + k_max)
+        got = (int(starts[h]), int(errs[h]), pn.ops_string(ops[h], int(n_ops[h])))
+        assert got == want, f"hit {h} (read {r}, strand {s}, end {e}, errors {v})"
+        assert want[1] == v
+    return len(hits)
+
+
+def test_align_matches_oracle(pn, sess):
+    """Mixed read lengths and per-read k, both strands, and the edge cases
+    (reads hanging off either end of the reference, homopolymer runs with
+    many equally good alignments): every hit's start, error count and
+    operations equal the oracle's; a starts-only call gives the same starts."""
+    w = synth.make("mixed", scale=0.002)
+    refh = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, w.q)
+    hits = pn.pn_map(sess.ctx, refh, idx, w.k_per_read, 0)
+    say(f"align: {len(hits)} hits of {w.n_reads} reads")
+    assert len(hits) > 500
+    assert check_alignments(pn, sess, w.ref, w.reads, w.offsets, refh, idx, hits) == len(hits)
+    st0, er0, _, _ = pn.pn_align(sess.ctx, refh, idx, hits, 0)
+    st1, er1, _, _ = pn.pn_align(sess.ctx, refh, idx, hits, 300)
+    assert np.array_equal(st0, st1) and np.array_equal(er0, er1)
+    # edge cases: reads at and beyond the ends, runs, strand 1
+    rng = np.random.default_rng(43)
+    refc = rng.integers(0, 4, 5000).astype(np.uint8)
+    refc[2500:2540] = 2
+    ref = synth.ALPHABET[refc].tobytes()
+    comp = bytes.maketrans(b"ACGT", b"TGCA")
+    reads = [b"TTG" + ref[:97], ref[-95:] + b"GAT", ref[:100], ref[-100:], ref[2480:2580],
+             ref[2490:2520] + b"C" + ref[2520:2590], ref[700:800].translate(comp)[::-1],
+             ref[1200:1250] + ref[1251:1300], b"G" * 80]
+    buf = b"".join(reads)
+    offs = np.zeros(len(reads) + 1, np.uint64)
+    np.cumsum([len(x) for x in reads], out=offs[1:])
+    refe = sess.ref(ref)
+    idx2 = sess.index(buf, offs, 10)
+    h2 = pn.pn_map(sess.ctx, refe, idx2, 6, 0)
+    assert set(h2["strand"].tolist()) == {0, 1}
+    assert check_alignments(pn, sess, ref, buf, offs, refe, idx2, h2) == len(h2)
+    # an error count below the true one: no alignment, reported as 255
+    low = h2[h2["errors"] > 0].copy()
+    low["errors"] -= 1
+    _, er, _, n = pn.pn_align(sess.ctx, refe, idx2, low, 200)
+    assert (er == 255).all() and (n == 0).all()
+    assert len(pn.pn_align(sess.ctx, refe, idx2, h2[:0], 8)[0]) == 0
+    bad = h2[:1].copy()
+    bad["end_pos"] = len(ref)
+    with pytest.raises(pn.PnError):
+        pn.pn_align(sess.ctx, refe, idx2, bad, 8)
+
+
 def test_device_entry_points_and_truncation(pn, sess):
     import torch
     w = synth.make("tiny", scale=0.05)

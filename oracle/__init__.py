@@ -65,11 +65,11 @@ def _load():
     lib.orc_qgram_index.restype = i32
     lib.orc_qgram_index.argtypes = [P, P, u32, i32, P, P, P]
     lib.orc_candidates.restype = i32
-    lib.orc_candidates.argtypes = [P, u64, P, P, u32, i32, i32, P, P, P, P]
+    lib.orc_candidates.argtypes = [P, u64, P, P, u32, i32, u32, i32, P, P, P, P]
     lib.orc_banded.restype = i32
     lib.orc_banded.argtypes = [P, u64, P, u32, ctypes.c_int64, i32, P, P]
     lib.orc_map_filtered.restype = i32
-    lib.orc_map_filtered.argtypes = [P, u64, P, P, u32, i32, P, i32, i32, P, P]
+    lib.orc_map_filtered.argtypes = [P, u64, P, P, u32, i32, P, i32, u32, i32, P, P]
     lib.orc_map_sellers.restype = i32
     lib.orc_map_sellers.argtypes = [P, u64, P, P, u32, P, i32, i32, P, P]
     lib.orc_align.restype = i32
@@ -183,9 +183,11 @@ def conventional_size_words(q: int, T: int) -> int:
 # filtration, validation, mapping
 
 
-def candidates(ref: bytes, reads: bytes, offsets, q: int, nthreads: int = 0):
+def candidates(ref: bytes, reads: bytes, offsets, q: int, nthreads: int = 0, mask: int = 0):
     """All (read, strand, diagonal) filtration hits, duplicates included,
-    sorted.  Returns (read u32, strand u8, diag i64)."""
+    sorted.  Returns (read u32, strand u8, diag i64).  mask > 0: repeat
+    masking, positions whose q-gram occurs more than `mask` times on the two
+    strands together emit nothing."""
     lib = _load()
     rc = np.ascontiguousarray(encode(ref))
     codes = np.ascontiguousarray(encode(reads))
@@ -193,7 +195,7 @@ def candidates(ref: bytes, reads: bytes, offsets, q: int, nthreads: int = 0):
     pr, ps, pd = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
     n = ctypes.c_uint64()
     st = lib.orc_candidates(_ptr(rc), len(rc), _ptr(codes), _ptr(offsets), len(offsets) - 1, q,
-                            nthreads, ctypes.byref(pr), ctypes.byref(ps), ctypes.byref(pd),
+                            int(mask), nthreads, ctypes.byref(pr), ctypes.byref(ps), ctypes.byref(pd),
                             ctypes.byref(n))
     if st:
         raise RuntimeError(f"orc_candidates failed: {st}")
@@ -241,9 +243,11 @@ def _k_array(k, n_reads: int) -> np.ndarray:
 
 
 def map_filtered(ref: bytes, reads: bytes, offsets, q: int, k, best: bool = False,
-                 nthreads: int = 0) -> np.ndarray:
+                 nthreads: int = 0, mask: int = 0) -> np.ndarray:
     """Every hit with at most k_r errors (or the best stratum) through the
-    method's steps with a conventional index.  Requires (k_r+1) q <= n_r."""
+    method's steps with a conventional index.  Requires (k_r+1) q <= n_r.
+    mask > 0: repeat masking (as in `candidates`); the hits are then those
+    of the remaining candidates' bands."""
     lib = _load()
     rc = np.ascontiguousarray(encode(ref))
     codes = np.ascontiguousarray(encode(reads))
@@ -253,7 +257,7 @@ def map_filtered(ref: bytes, reads: bytes, offsets, q: int, k, best: bool = Fals
     ph = ctypes.c_void_p()
     nh = ctypes.c_uint64()
     st = lib.orc_map_filtered(_ptr(rc), len(rc), _ptr(codes), _ptr(offsets), n, q, _ptr(karr),
-                              int(best), nthreads, ctypes.byref(ph), ctypes.byref(nh))
+                              int(best), int(mask), nthreads, ctypes.byref(ph), ctypes.byref(nh))
     if st == -3:
         raise ValueError("q-gram lemma violated: (k_r + 1) * q > n_r for some read")
     if st:

@@ -26,6 +26,10 @@
  *    conventional index: for both strands s and every reference position p
  *    in [0, L-q], look up the bucket of the q-gram at p and emit, for every
  *    occurrence (r, o), the hit diagonal d = p - o (the putative read start).
+ *    With repeat masking (max_occ > 0; Section 3.2 leaves exceedingly
+ *    frequent q-grams out of P, without fixing "frequent"), positions whose
+ *    q-gram occurs more than max_occ times on the two strands together
+ *    emit nothing.
  *
  *  - orc_banded: validation of one candidate (Section 3.3): the semiglobal
  *    edit-distance matrix E (unit costs) restricted to the diagonal band
@@ -217,9 +221,52 @@ typedef struct {
     int q;
     const uint64_t *A;
     const uint32_t *P_read, *P_off;
+    const uint64_t *masked; /* ascending q-gram codes left out of P */
+    uint64_t n_masked;
     u64vec *out; /* one per thread */
     int failed;
 } cand_job;
+
+static int is_masked(const cand_job *j, uint64_t g) {
+    uint64_t lo = 0, hi = j->n_masked;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (j->masked[mid] < g)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < j->n_masked && j->masked[lo] == g;
+}
+
+/* Repeat masking (Section 3.2 leaves exceedingly frequent q-grams out of
+ * P): the q-grams occurring more than max_occ times among the positions of
+ * both strands, ascending.  The counts come from sorting the codes of all
+ * 2 (L - q + 1) positions and measuring each run of equal codes. */
+static int masked_qgrams(const uint8_t *ref, const uint8_t *rc, uint64_t L, int q,
+                         uint32_t max_occ, uint64_t **out, uint64_t *n_out) {
+    *out = NULL;
+    *n_out = 0;
+    if (L < (uint64_t)q) return 0;
+    const uint64_t npos = L - (uint64_t)q + 1;
+    uint64_t *codes = (uint64_t *)malloc(sizeof(uint64_t) * 2 * npos);
+    if (!codes) return -2;
+    for (uint64_t p = 0; p < npos; p++) {
+        codes[p] = qgram_code(ref + p, q);
+        codes[npos + p] = qgram_code(rc + p, q);
+    }
+    qsort(codes, 2 * npos, sizeof(uint64_t), cmp_u64);
+    uint64_t m = 0;
+    for (uint64_t a = 0; a < 2 * npos;) {
+        uint64_t b = a;
+        while (b < 2 * npos && codes[b] == codes[a]) b++;
+        if (b - a > (uint64_t)max_occ) codes[m++] = codes[a];
+        a = b;
+    }
+    *out = codes;
+    *n_out = m;
+    return 0;
+}
 
 /* candidate key: read (31 bits) | strand (1 bit) | diagonal + bias (32 bits) */
 static uint64_t cand_key(uint32_t r, int s, int64_t d) {
@@ -235,6 +282,7 @@ static void cand_range(void *arg, int tid, uint64_t lo, uint64_t hi) {
         int s = (int)(x / npos);
         uint64_t p = x % npos;
         uint64_t g = qgram_code(j->text[s] + p, j->q);
+        if (j->n_masked && is_masked(j, g)) continue;
         for (uint64_t k = j->A[g]; k < j->A[g + 1]; k++) {
             int64_t d = (int64_t)p - (int64_t)j->P_off[k];
             if (vec_push(out, cand_key(j->P_read[k], s, d))) {
@@ -245,14 +293,23 @@ static void cand_range(void *arg, int tid, uint64_t lo, uint64_t hi) {
     }
 }
 
+/* max_occ > 0: positions whose q-gram occurs more than max_occ times on
+ * the two strands together emit nothing (repeat masking) */
 static int collect_candidates(const uint8_t *ref, const uint8_t *rc, uint64_t L, int q,
                               const uint64_t *A, const uint32_t *P_read, const uint32_t *P_off,
-                              int nthreads, uint64_t **keys, uint64_t *n_keys) {
+                              uint32_t max_occ, int nthreads, uint64_t **keys, uint64_t *n_keys) {
     *keys = NULL;
     *n_keys = 0;
     if (L < (uint64_t)q) return 0;
     nthreads = orc_threads(nthreads);
     cand_job j;
+    j.masked = NULL;
+    j.n_masked = 0;
+    if (max_occ > 0) {
+        uint64_t *mk = NULL;
+        if (masked_qgrams(ref, rc, L, q, max_occ, &mk, &j.n_masked)) return -2;
+        j.masked = mk;
+    }
     j.text[0] = ref;
     j.text[1] = rc;
     j.L = L;
@@ -262,8 +319,12 @@ static int collect_candidates(const uint8_t *ref, const uint8_t *rc, uint64_t L,
     j.P_off = P_off;
     j.failed = 0;
     j.out = (u64vec *)calloc((size_t)nthreads, sizeof(u64vec));
-    if (!j.out) return -2;
+    if (!j.out) {
+        free((void *)j.masked);
+        return -2;
+    }
     parallel_for(nthreads, 2 * (L - (uint64_t)q + 1), cand_range, &j);
+    free((void *)j.masked);
     size_t total = 0;
     for (int t = 0; t < nthreads; t++) total += j.out[t].n;
     uint64_t *all = (uint64_t *)malloc(sizeof(uint64_t) * (total ? total : 1));
@@ -288,8 +349,9 @@ static int collect_candidates(const uint8_t *ref, const uint8_t *rc, uint64_t L,
  * q-gram occurrence pair (so duplicates are kept).  Output arrays are
  * malloc'ed; free with orc_free. */
 int orc_candidates(const uint8_t *ref, uint64_t L, const uint8_t *codes, const uint64_t *offsets,
-                   uint32_t n_reads, int q, int nthreads, uint32_t **out_read, uint8_t **out_strand,
-                   int64_t **out_diag, uint64_t *n_out) {
+                   uint32_t n_reads, int q, uint32_t mask_max_occ, int nthreads,
+                   uint32_t **out_read, uint8_t **out_strand, int64_t **out_diag,
+                   uint64_t *n_out) {
     const uint64_t G = 1ULL << (2 * q);
     uint64_t T = orc_qgram_count(offsets, n_reads, q);
     uint64_t *A = (uint64_t *)malloc(sizeof(uint64_t) * (G + 1));
@@ -298,7 +360,7 @@ int orc_candidates(const uint8_t *ref, uint64_t L, const uint8_t *codes, const u
     uint8_t *rc = reverse_complement(ref, L);
     int st = (A && Pr && Po && rc) ? orc_qgram_index(codes, offsets, n_reads, q, A, Pr, Po) : -2;
     uint64_t *keys = NULL, n = 0;
-    if (!st) st = collect_candidates(ref, rc, L, q, A, Pr, Po, nthreads, &keys, &n);
+    if (!st) st = collect_candidates(ref, rc, L, q, A, Pr, Po, mask_max_occ, nthreads, &keys, &n);
     free(A);
     free(Pr);
     free(Po);
@@ -454,8 +516,8 @@ static void verify_range(void *arg, int tid, uint64_t lo, uint64_t hi) {
 /* Filtration + validation with the conventional index.  Requires
  * (k_r + 1) * q <= n_r for every read (q-gram lemma, Section 2.2). */
 int orc_map_filtered(const uint8_t *ref, uint64_t L, const uint8_t *codes, const uint64_t *offsets,
-                     uint32_t n_reads, int q, const uint8_t *k_per_read, int best, int nthreads,
-                     orc_hit **out, uint64_t *n_out) {
+                     uint32_t n_reads, int q, const uint8_t *k_per_read, int best,
+                     uint32_t mask_max_occ, int nthreads, orc_hit **out, uint64_t *n_out) {
     *out = NULL;
     *n_out = 0;
     for (uint32_t r = 0; r < n_reads; r++) {
@@ -471,7 +533,8 @@ int orc_map_filtered(const uint8_t *ref, uint64_t L, const uint8_t *codes, const
     uint8_t *rc = reverse_complement(ref, L);
     int st = (A && Pr && Po && rc) ? orc_qgram_index(codes, offsets, n_reads, q, A, Pr, Po) : -2;
     uint64_t *cands = NULL, nc = 0;
-    if (!st) st = collect_candidates(ref, rc, L, q, A, Pr, Po, nthreads, &cands, &nc);
+    if (!st)
+        st = collect_candidates(ref, rc, L, q, A, Pr, Po, mask_max_occ, nthreads, &cands, &nc);
     free(A);
     free(Pr);
     free(Po);

@@ -501,3 +501,87 @@ def _diag_pairs(ops, x):
             i += 1
         else:
             j += 1
+
+
+# ---------------------------------------------------------------------------
+# repeat masking of P (Section 3.2): an optional threshold on q-gram counts
+
+
+def _masked_cands_brute(ref: bytes, reads: list, q: int, mask: int):
+    """(read, strand, diagonal) of every occurrence pair whose reference
+    q-gram occurs at most `mask` times on the two strands together
+    (mask 0: no masking), by enumeration over strings."""
+    texts = [ref, revcomp_str(ref)]
+    cnt = Counter(t[p:p + q] for t in texts for p in range(len(t) - q + 1))
+    out = []
+    for r, x in enumerate(reads):
+        for s, t in enumerate(texts):
+            for p in range(len(t) - q + 1):
+                g = t[p:p + q]
+                if mask and cnt[g] > mask:
+                    continue
+                for o in range(len(x) - q + 1):
+                    if x[o:o + q] == g:
+                        out.append((r, s, p - o))
+    return sorted(out)
+
+
+def _repeat_case(rng, L=400, unit=40, copies=5, n_reads=12, n=36):
+    """A random reference with one segment copied several times (some
+    copies mutated), reads from repeat copies and from unique sequence."""
+    ref = bytearray(rand_dna(rng, L))
+    seg = bytes(ref[:unit])
+    for c in range(copies):
+        a = int(rng.integers(unit, L - unit))
+        cp = bytearray(seg)
+        if c % 2:
+            cp[int(rng.integers(0, unit))] = b"ACGT"[int(rng.integers(0, 4))]
+        ref[a:a + unit] = cp
+    ref = bytes(ref)
+    reads = []
+    for i in range(n_reads):
+        a = int(rng.integers(0, L - n))
+        x = bytearray(ref[a:a + n])
+        if rng.random() < 0.5:
+            x[int(rng.integers(0, n))] = b"ACGT"[int(rng.integers(0, 4))]
+        reads.append(bytes(x) if rng.random() < 0.7 else revcomp_str(bytes(x)))
+    return ref, reads
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_masked_candidates_equal_enumeration(seed):
+    rng = np.random.default_rng(500 + seed)
+    ref, reads = _repeat_case(rng)
+    buf, offs = pack(reads)
+    q = 6
+    for mask in (0, 1, 2, 3, 5, 8, 10 ** 6):
+        r, s, d = oracle.candidates(ref, buf, offs, q, mask=mask)
+        got = sorted(zip(r.tolist(), s.tolist(), d.tolist()))
+        assert got == _masked_cands_brute(ref, reads, q, mask), mask
+
+
+def test_masked_map_equals_bands_of_unmasked_candidates():
+    """Masked mapping = the band DP (written out over the whole matrix) of
+    every remaining candidate diagonal, the smallest value per (read,
+    strand, end); a threshold at or above every count changes nothing, and
+    masking only removes hits or raises their error counts."""
+    rng = np.random.default_rng(601)
+    q, k = 6, 2
+    for trial in range(6):
+        ref, reads = _repeat_case(rng, L=300, unit=30, copies=4, n_reads=8, n=24)
+        buf, offs = pack(reads)
+        texts = [ref, revcomp_str(ref)]
+        full = as_tuples(oracle.map_filtered(ref, buf, offs, q, k))
+        assert as_tuples(oracle.map_filtered(ref, buf, offs, q, k, mask=10 ** 6)) == full
+        for mask in (2, 4):
+            best = {}
+            for r, s, d in set(_masked_cands_brute(ref, reads, q, mask)):
+                for e, v in band_brute(texts[s], reads[r], d, k):
+                    key = (r, e, s)
+                    best[key] = min(best.get(key, 99), v)
+            want = sorted(((r, e, s, v) for (r, e, s), v in best.items()),
+                          key=lambda h: (h[0], h[2], h[1]))
+            got = as_tuples(oracle.map_filtered(ref, buf, offs, q, k, mask=mask))
+            assert got == want, (trial, mask)
+            fd = {(r, e, s): v for r, e, s, v in full}
+            assert all((r, e, s) in fd and v >= fd[(r, e, s)] for r, e, s, v in got)

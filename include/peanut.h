@@ -185,6 +185,19 @@ uint64_t pn_ref_length(const pn_ref *ref);
  * from several threads. */
 int pn_ref_prepare(pn_ref *ref, int q);
 
+/* Repeat masking (Section 3.2: exceedingly frequent q-grams are left out of
+ * the position set; the paper does not fix "frequent"): after this call,
+ * filtration with q-gram length q skips every position whose q-gram occurs
+ * more than max_occ times on the two strands together (so a q-gram and its
+ * reverse complement are masked together); max_occ = 0 turns masking off
+ * again.  Mapping a masked reference is no longer lossless: the hits are
+ * those of the remaining candidates' bands (the per-read seed rules that
+ * rely on every position being present are switched off), a subset of the
+ * unmasked hits whose error counts may be larger.  The mask (4^q bits) is
+ * owned by the reference.  Not to be called while a mapping with this
+ * reference and q runs.  PN_EINVAL for q outside 1..15. */
+int pn_ref_mask(pn_ref *ref, int q, uint32_t max_occ);
+
 /* ---- q-group index over a read batch (Algorithm 1) --------------------- */
 
 /* Build the q-group index (I, S, S', O) of all q-grams of the reads

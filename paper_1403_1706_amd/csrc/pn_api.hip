@@ -98,6 +98,8 @@ struct pn_ref {
     unsigned long long *pkeys[16] = {};
     uint16_t *pctx[16] = {};
     uint64_t pn[16] = {};
+    // repeat masking per q: 4^q bits, set for the q-grams left out (null: off)
+    uint32_t *pmask[16] = {};
 };
 
 struct pn_index {
@@ -302,7 +304,7 @@ int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
     std::lock_guard<std::mutex> lk(r->prep_mu);
     const uint64_t n = r->L >= (uint64_t)q ? 2 * (r->L - q + 1) : 0;
     if (r->pkeys[q] || n == 0) {
-        *out = pn::RefQDev{r->pkeys[q], r->pctx[q], r->pkeys[q] ? r->pn[q] : 0};
+        *out = pn::RefQDev{r->pkeys[q], r->pctx[q], r->pkeys[q] ? r->pn[q] : 0, r->pmask[q]};
         return PN_OK;
     }
     unsigned long long *keys = nullptr, *tmp = nullptr;
@@ -332,7 +334,7 @@ int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
     r->pkeys[q] = keys;
     r->pctx[q] = ctx;
     r->pn[q] = n;
-    *out = pn::RefQDev{keys, ctx, n};
+    *out = pn::RefQDev{keys, ctx, n, nullptr};
     return PN_OK;
 }
 
@@ -513,8 +515,36 @@ void pn_ref_free(pn_ref *r) {
     for (int q = 0; q < 16; q++) {
         if (r->pkeys[q]) (void)hipFree(r->pkeys[q]);
         if (r->pctx[q]) (void)hipFree(r->pctx[q]);
+        if (r->pmask[q]) (void)hipFree(r->pmask[q]);
     }
     delete r;
+}
+
+int pn_ref_mask(pn_ref *r, int q, uint32_t max_occ) {
+    if (!r || q < 1 || q > 15) return PN_EINVAL;
+    DeviceGuard g(r->ctx->device);
+    hipStream_t st = r->ctx->stream;
+    pn::RefQDev P;
+    PN_CHECK(ref_prepare(r, q, st, &P));
+    std::lock_guard<std::mutex> lk(r->prep_mu);
+    if (r->pmask[q]) {
+        PN_TRY(hipStreamSynchronize(st));
+        (void)hipFree(r->pmask[q]);
+        r->pmask[q] = nullptr;
+    }
+    if (!max_occ || !P.n) return PN_OK;
+    const uint64_t words = ((1ull << (2 * q)) + 31) / 32;
+    uint32_t *bits = nullptr;
+    PN_TRY(hipMalloc((void **)&bits, words * 4));
+    pn::launch_fill_u32(bits, words, 0u, st);
+    pn::launch_mask_runs(P, q, max_occ, bits, st);
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(bits);
+        return map_err(e);
+    }
+    r->pmask[q] = bits;
+    return PN_OK;
 }
 
 int pn_ref_prepare(pn_ref *r, int q) {
@@ -778,7 +808,9 @@ int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 
 // per-read seed rules (with the k / lemma check) and the low-complexity side
 // lists; synchronises once to report a bad k or a lemma violation
-int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, hipStream_t st) {
+// plain: the position set is masked (every read gets the plain rule byte)
+int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, bool plain,
+                  hipStream_t st) {
     PN_CHECK(ensure(c, c->ws.rinfo, (uint64_t)x->n_reads + 1));
     PN_CHECK(ensure(c, c->ws.side, std::max<uint64_t>(x->lc_total, 1) * 8));
     PN_CHECK(ensure(c, c->ws.side_meta, 17 * pn::kLcPatterns * 4));
@@ -793,7 +825,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, h
     PnIndexDev ix = index_desc(x);
     const int tok = stage_begin(c, st, PN_STAGE_RULES);
     pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->ws.rinfo.p, (uint32_t *)&c->misc[kStatus],
-                          st);
+                          plain, st);
     pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->ws.rinfo.p, st);
     // 16 region starts, 16 x 6 class bounds, then scratch for the side lists
     uint32_t *meta = (uint32_t *)c->ws.side_meta.p;
@@ -830,7 +862,7 @@ pn::Lists lists_of(const pn_ctx *c) {
 // filtration of the entries [a, b) of the reference's position set P
 int launch_filter_into(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn::RefQDev &Pall,
                        uint64_t a, uint64_t b, hipStream_t st) {
-    pn::RefQDev P{Pall.keys + a, Pall.ctx ? Pall.ctx + a : nullptr, b - a};
+    pn::RefQDev P{Pall.keys + a, Pall.ctx ? Pall.ctx + a : nullptr, b - a, Pall.mask};
     PN_CHECK(ensure(c, c->ws.heavy, pn::kShards * c->ws.heavy_rcap * 2 * sizeof(uint4)));
     pn::launch_fill_u32((uint32_t *)&c->misc[kHeavyCounts], 2 * pn::kShards, 0u, st);
     pn::FilterOut fo{(uint2 *)c->ws.cands.p,
@@ -927,7 +959,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
                     bool filter, uint64_t n_in, hipStream_t st, uint64_t *n_rec) {
     const int ebits = key_ebits(ref->L);
     c->ws.rec_rcap = std::max<uint64_t>(c->ws.rec_rcap, (16ull * x->n_reads) / pn::kShards + 4096);
-    pn::RefQDev P{nullptr, nullptr, 0};
+    pn::RefQDev P{nullptr, nullptr, 0, nullptr};
     if (filter) PN_CHECK(ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P));
     const uint32_t regions = filter ? pn::kShards : 1;
     const uint64_t end = filter ? P.n : (n_in ? 1 : 0);
@@ -1057,7 +1089,7 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
 // their count in *n_rec
 int map_records(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, const uint8_t *d_k,
                 hipStream_t st, uint64_t *n_rec) {
-    PN_CHECK(prepare_rules(c, x, kglob, d_k, st));
+    PN_CHECK(prepare_rules(c, x, kglob, d_k, ref->pmask[x->q] != nullptr, st));
     return validate_sorted(c, ref, x, kglob, d_k, true, 0, st, n_rec);
 }
 
@@ -1354,8 +1386,8 @@ int pn_filter(pn_ctx *c, const pn_ref *ref, const pn_index *x, int k, const uint
             return map_err(e);
         }
     }
-    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
-    pn::RefQDev P{nullptr, nullptr, 0};
+    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, ref->pmask[x->q] != nullptr, st);
+    pn::RefQDev P{nullptr, nullptr, 0, nullptr};
     if (!s) s = ref_prepare(const_cast<pn_ref *>(ref), x->q, st, &P);
     uint64_t n = 0;
     // (the whole position set at once: this call returns every candidate)
@@ -1438,7 +1470,7 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
             return map_err(e);
         }
     }
-    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, st);
+    int s = prepare_rules(c, x, k < 0 ? -1 : k, dk, false, st);
     if (!s) s = ensure(c, c->ws.cands, std::max<uint64_t>(n, 1) * sizeof(uint2));
     if (!s && n)
         s = map_err(hipMemcpyAsync(c->ws.cands.p, host.data(), n * sizeof(uint2),
@@ -1630,7 +1662,7 @@ int pn_validate_noalloc(pn_ctx *c, const pn_ref *ref, const pn_index *x,
     // converted and range-checked
     zero_misc(c, st);
     pn::launch_read_rules(ix, kglob, d_k_per_read, base + kNaRinfo, (uint32_t *)&c->misc[kStatus],
-                          st);
+                          false, st);
     pn::launch_cands_in(d_cands, n, x->n_reads, ref->L, cands, (uint32_t *)&c->misc[kStatus], st);
     pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n, st);
     PN_CHECK(na_sync_misc(c, st));

@@ -476,6 +476,30 @@ __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q, int a,
     }
 }
 
+// Repeat masking (Section 3.2 leaves exceedingly frequent q-grams out of
+// P): bit g of `bits` is set when q-gram g has more than max_occ entries in
+// P, i.e. occurrences on the two strands together.  P is ordered by q-gram,
+// so these form one run; its first entry finds the run's end by binary
+// search.
+__global__ __launch_bounds__(256) void k_mask_runs(pn::RefQDev P, int q, uint32_t max_occ,
+                                                   uint32_t *__restrict__ bits) {
+    const uint64_t gmask = (1ull << (2 * q)) - 1ull;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
+        const uint64_t g = P.keys[i] & gmask;
+        if (i > 0 && (P.keys[i - 1] & gmask) == g) continue;
+        uint64_t lo = i + 1, hi = P.n;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if ((P.keys[mid] & gmask) <= g)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo - i > (uint64_t)max_occ) atomicOr(&bits[g >> 5], 1u << (uint32_t)(g & 31));
+    }
+}
+
 // (compiled for 8 waves per SIMD: more waves hide more of the walk's load
 // latency than the few registers this spills cost)
 template <typename TW, bool kPacked, bool kSub>
@@ -501,7 +525,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     uint32_t c_next = !kPacked && i0 < P.n ? P.ctx[i0] : 0u;
     for (int jj = 0; jj < kPPT; jj++) {
         const uint64_t i = i0 + (uint64_t)jj * kT;
-        const bool valid = i < P.n;
+        bool valid = i < P.n;
         const unsigned long long key = key_next;
         const uint32_t c = c_next;
         if (jj + 1 < kPPT) {
@@ -526,6 +550,13 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
             prev = c & 3u;
             avail = (c >> 3) & 7u;
             N = (c >> 6) & 0xffu;
+        }
+        if (P.mask) {
+            // a masked q-gram emits nothing; rule 1 may drop a pair only
+            // when the pair to its left is not masked
+            if ((P.mask[g >> 5] >> (g & 31)) & 1u) valid = false;
+            const uint32_t gl = (prev << (2 * (q - 1))) | (g >> 2);
+            if ((P.mask[gl >> 5] >> (gl & 31)) & 1u) has = false;
         }
         const bool lh = has && pn_low_complexity((prev << (2 * (q - 1))) | (g >> 2), q);
         Ranges r;
@@ -626,7 +657,7 @@ __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a
 
 // status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
 __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict__ kpr,
-                             uint8_t *__restrict__ rinfo, uint32_t *status) {
+                             uint8_t *__restrict__ rinfo, uint32_t *status, int plain) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < ix.n_reads) {
         const uint64_t off = ix.offsets[r];
@@ -645,7 +676,7 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
         // filtration at its piece start.  Windows whose q-gram is
         // low-complexity are not looked up (rule 2) and do not count.
         uint32_t pieces = 0;
-        if (!bad && ix.after_sorted) {
+        if (!bad && !plain && ix.after_sorted) {
             const uint32_t ell = q + 4;
             for (uint32_t o = 0; o + ell <= n; o += ell)
                 pieces += !pn_low_complexity(pn_window16(ix.packed, off + o) >> (32 - 2 * q), q);
@@ -653,6 +684,8 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
         if (bad) {
             atomicOr(status, bad);
             rinfo[r] = 0;
+        } else if (plain) {
+            rinfo[r] = 0x80u;
         } else if (pieces >= k + 1) {
             // (its entries are in no lax list and no side list); bits 4-6:
             // windows starting below 16 times this lie in the read's first
@@ -921,10 +954,16 @@ void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st) {
 
 
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
-                       uint32_t *status, hipStream_t st) {
+                       uint32_t *status, bool plain, hipStream_t st) {
     if (!ix.n_reads) return;
     hipLaunchKernelGGL(k_read_rules, dim3((ix.n_reads + 255) / 256), dim3(256), 0, st, ix, kglob,
-                       kpr, rinfo, status);
+                       kpr, rinfo, status, plain ? 1 : 0);
+}
+
+void launch_mask_runs(const RefQDev &P, int q, uint32_t max_occ, uint32_t *bits, hipStream_t st) {
+    if (!P.n) return;
+    hipLaunchKernelGGL(k_mask_runs, dim3(pn_stride_blocks(P.n, 256)), dim3(256), 0, st, P, q,
+                       max_occ, bits);
 }
 
 void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long long *side,

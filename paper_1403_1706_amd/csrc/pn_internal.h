@@ -261,8 +261,11 @@ struct FilterOut {
 // half and their candidates get PN_CAND_TAIL), bits 0-2 = extra letters of
 // exact run required beyond q (0..4).
 // Status: bit 2 some k_r too large, bit 4 the lemma fails for some read.
+// plain: every read gets rule byte 0x80 (keeps its low-complexity seeds, no
+// exact run required, no piece mode), for filtration of a masked position
+// set, where a pair may be the only one left of its alignment
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
-                       uint32_t *status, hipStream_t st);
+                       uint32_t *status, bool plain, hipStream_t st);
 // sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)
 void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st);
 // low-complexity occurrence lists restricted to reads that keep them
@@ -284,7 +287,13 @@ struct RefQDev {
     const unsigned long long *keys;
     const uint16_t *ctx;
     uint64_t n;  // 2 (L - q + 1)
+    // repeat masking: bit g set = q-gram g is left out of filtration (null:
+    // no masking)
+    const uint32_t *mask;
 };
+// repeat masking: bit g of `bits` (4^q bits, zeroed by the caller) set for
+// every q-gram with more than max_occ entries in P
+void launch_mask_runs(const RefQDev &P, int q, uint32_t max_occ, uint32_t *bits, hipStream_t st);
 inline bool refq_packs(uint64_t L, int q) {
     int bits = 0;
     for (uint64_t v = 2 * L; v > 1; v >>= 1) bits++;  // (p << 1 | strand) < 2L

@@ -114,6 +114,7 @@ _sig("pn_ref_load_dev", _int, [_P, _P, _u64, _P, _PP])
 _sig("pn_ref_free", None, [_P])
 _sig("pn_ref_length", _u64, [_P])
 _sig("pn_ref_prepare", _int, [_P, _int])
+_sig("pn_ref_mask", _int, [_P, _int, _u32])
 _sig("pn_index_build", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _int, _PP])
 _sig("pn_index_build_dev", _int, [_P, _P, _P, _u32, _u64, _int, _int, _P, _PP])
 _sig("pn_index_free", None, [_P])
@@ -143,7 +144,8 @@ _sig("pn_autotune", _int, [_P, _P, _P, _P, _u32, _u64, _int, _P, _int, _u32,
 
 EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ctx_set_timing", "pn_ctx_get_stats", "pn_ref_load",
-            "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_index_build",
+            "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_ref_mask",
+            "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
             "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
             "pn_validate_noalloc", "pn_align",
@@ -217,6 +219,10 @@ def pn_ctx_get_stats(ctx, reset: bool = False) -> dict:
 
 def pn_ref_prepare(ref, q: int) -> None:
     _check(_lib.pn_ref_prepare(ref, q), "pn_ref_prepare")
+
+
+def pn_ref_mask(ref, q: int, max_occ: int) -> None:
+    _check(_lib.pn_ref_mask(ref, q, int(max_occ)), "pn_ref_mask")
 
 
 def pn_ref_load(ctx, seq: bytes):

@@ -386,6 +386,56 @@ def test_error_statuses(pn, sess):
 
 
 # ---------------------------------------------------------------------------
+# repeat masking of the position set (Section 3.2)
+
+
+@pytest.mark.parametrize("case", ["repeat", "human-ordered"])
+def test_repeat_masking_equals_masked_oracle(pn, sess, case):
+    """With the q-grams of more than m occurrences (both strands together)
+    left out of P, filtration's occurrence-pair count equals the masked
+    oracle's and its candidates are among the oracle's, and the hits of both
+    modes equal the masked oracle's (on a seeded read sample for the larger
+    case, whose index orders its long slices); m = 0 restores the unmasked
+    hits."""
+    if case == "repeat":
+        w = synth.make("repeat", scale=0.01)
+        sample = np.arange(w.n_reads)
+    else:
+        w = synth.make("human", scale=0.003, n_reads=100_000)
+        sample = np.sort(np.random.default_rng(37).choice(w.n_reads, 2000, replace=False))
+    k = w.k_per_read if case == "repeat" else 5
+    sub = w.subset(sample)
+    ksub = k if np.isscalar(k) else k[sample]
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, 12)
+    if case != "repeat":
+        assert pn.pn_index_get_info(idx)["after_sorted"] == 1
+    plain = {mode: pn.pn_map(sess.ctx, ref, idx, k, mode) for mode in (0, 1)}
+    changed = False
+    for m in ((1, 2, 16) if case == "repeat" else (3, 16, 200)):
+        say(f"mask {case}: m={m}")
+        pn.pn_ref_mask(ref, 12, m)
+        if case == "repeat":
+            c, n_seeds = pn.pn_filter(sess.ctx, ref, idx, k)
+            r0, s0, d0 = oracle.candidates(w.ref, w.reads, w.offsets, 12, mask=m)
+            assert n_seeds == len(r0)
+            assert np.all(np.isin(cand_set(c["read_id"], c["strand"], c["diagonal"]),
+                                  cand_set(r0, s0, d0)))
+        for mode in (0, 1):
+            g = pn.pn_map(sess.ctx, ref, idx, k, mode)
+            changed |= len(g) != len(plain[mode]) or not np.array_equal(fields(g),
+                                                                       fields(plain[mode]))
+            mine = g[np.isin(g["read_id"], sample)].copy()
+            mine["read_id"] = np.searchsorted(sample, mine["read_id"])
+            assert_hits_equal(mine, oracle.map_filtered(sub.ref, sub.reads, sub.offsets, 12, ksub,
+                                                        best=bool(mode), mask=m))
+    assert changed
+    pn.pn_ref_mask(ref, 12, 0)
+    for mode in (0, 1):
+        assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, k, mode), plain[mode])
+
+
+# ---------------------------------------------------------------------------
 # start positions and alignments of hits (Section 3.3 backward pass, 3.4)
 
 

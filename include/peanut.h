@@ -38,7 +38,9 @@
  *  - Sequences are ASCII A, C, G, T in either case; anything else is
  *    PN_EALPHABET.  Base codes are A=0, C=1, G=2, T=3 (Section 2.2).
  *  - Limits: reference length L < 2^32 - 2^16; reads per index < 2^21;
- *    read length <= 256; 1 <= q <= 15; w in {32, 64}; 0 <= k_r <= 15.
+ *    read length <= 256; 1 <= q <= 16 (q = 16 with a reference of at most
+ *    2^31 - 1 letters: a position-set key holds the position beside the
+ *    32-bit q-gram); w in {32, 64}; 0 <= k_r <= 15.
  */
 #ifndef PEANUT_H
 #define PEANUT_H
@@ -103,6 +105,7 @@ typedef struct {
     int32_t w;
     int32_t max_len;
     int32_t after_sorted;
+    int32_t s_sample; /* 1: S holds every group start; 2: every second (pn_index_sample_s) */
 } pn_index_info;
 
 /* Human-readable name of a status code; never NULL. */
@@ -195,7 +198,7 @@ int pn_ref_prepare(pn_ref *ref, int q);
  * rely on every position being present are switched off), a subset of the
  * unmasked hits whose error counts may be larger.  The mask (4^q bits) is
  * owned by the reference.  Not to be called while a mapping with this
- * reference and q runs.  PN_EINVAL for q outside 1..15. */
+ * reference and q runs.  PN_EINVAL for q outside 1..16. */
 int pn_ref_mask(pn_ref *ref, int q, uint32_t max_occ);
 
 /* ---- q-group index over a read batch (Algorithm 1) --------------------- */
@@ -217,9 +220,17 @@ int pn_index_build_dev(pn_ctx *ctx, const char *d_reads, const uint64_t *d_offse
 void pn_index_free(pn_index *idx);
 int pn_index_get_info(const pn_index *idx, pn_index_info *out);
 
+/* Sampling S (Section 2.2): keep only the even entries S[0], S[2], ..., S[2 t]
+ * (t = n_groups / 2) and free the full array, halving S's memory; a lookup
+ * in an odd group adds the population count of the group before it.  The
+ * hits of every later mapping are unchanged.  Idempotent.  pn_index_export
+ * then writes n_groups / 2 + 1 words of S. */
+int pn_index_sample_s(pn_index *idx);
+
 /* Copy the index arrays to host buffers sized from pn_index_get_info:
  * I: n_groups words of w bits (uint32 for w = 32, uint64 for w = 64);
- * S: n_groups + 1 uint32; S': n_distinct + 1 uint32; O: n_qgrams uint64.
+ * S: n_groups + 1 uint32 (sampled: n_groups / 2 + 1); S': n_distinct + 1
+ * uint32; O: n_qgrams uint64.
  * An O entry holds one occurrence (read r, offset o) of its q-gram: the high
  * 32 bits are (cls << 29) | (r << 8) | o, where cls is the code of the
  * letter before the q-gram in its read (4 when o == 0); the low 32 bits are
@@ -402,7 +413,7 @@ int pn_map_batched(pn_ctx *ctx, const pn_ref *ref, const char *reads, const uint
  * serial one-request-at-a-time mapping is slots = 1, max_batch_reads = 1. */
 typedef struct pn_server pn_server;
 typedef struct {
-    int q;                    /* q-gram length of every batch index, 1..15 */
+    int q;                    /* q-gram length of every batch index, 1..16 */
     int w;                    /* group width, 32 or 64 */
     uint64_t hbm_budget;      /* bytes of estimated working sets in flight */
     uint32_t max_batch_reads; /* reads merged into one batch, 1..2^21 */

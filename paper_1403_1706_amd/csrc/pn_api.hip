@@ -95,11 +95,11 @@ struct pn_ref {
     // position sets sorted by q-gram, built on first use per q (any context
     // on the device may map against the reference: guarded by prep_mu)
     std::mutex prep_mu;
-    unsigned long long *pkeys[16] = {};
-    uint16_t *pctx[16] = {};
-    uint64_t pn[16] = {};
+    unsigned long long *pkeys[PN_MAX_Q + 1] = {};
+    uint16_t *pctx[PN_MAX_Q + 1] = {};
+    uint64_t pn[PN_MAX_Q + 1] = {};
     // repeat masking per q: 4^q bits, set for the q-grams left out (null: off)
-    uint32_t *pmask[16] = {};
+    uint32_t *pmask[PN_MAX_Q + 1] = {};
 };
 
 struct pn_index {
@@ -117,6 +117,7 @@ struct pn_index {
     uint32_t *lcinfo;
     uint32_t *tab_id = nullptr, *tabs = nullptr;  // slice tables (ordered index)
     uint32_t n_tabs = 0;
+    bool s_half = false;  // S sampled at even groups
     uint32_t lc_size[pn::kLcPatterns];  // slice sizes of the low-complexity q-grams
     uint64_t lc_total;
 };
@@ -303,6 +304,8 @@ PnRefDev ref_desc(const pn_ref *r) {
 int ref_prepare(pn_ref *r, int q, hipStream_t st, pn::RefQDev *out) {
     std::lock_guard<std::mutex> lk(r->prep_mu);
     const uint64_t n = r->L >= (uint64_t)q ? 2 * (r->L - q + 1) : 0;
+    // a key holds (position << 1 | strand) beside the q-gram's 2q bits
+    if (bitlen(2 * r->L) + 2 * q > 64) return PN_EINVAL;
     if (r->pkeys[q] || n == 0) {
         *out = pn::RefQDev{r->pkeys[q], r->pctx[q], r->pkeys[q] ? r->pn[q] : 0, r->pmask[q]};
         return PN_OK;
@@ -357,6 +360,7 @@ PnIndexDev index_desc(const pn_index *x) {
     d.log2w = x->w == 64 ? 6 : 5;
     d.n_groups = x->n_groups;
     d.after_sorted = x->after_sorted ? 1 : 0;
+    d.s_half = x->s_half ? 1 : 0;
     return d;
 }
 
@@ -512,7 +516,7 @@ void pn_ref_free(pn_ref *r) {
     dfree(c, r->packed_base);
     dfree(c, r->planes0);
     dfree(c, r->planes1);
-    for (int q = 0; q < 16; q++) {
+    for (int q = 0; q <= PN_MAX_Q; q++) {
         if (r->pkeys[q]) (void)hipFree(r->pkeys[q]);
         if (r->pctx[q]) (void)hipFree(r->pctx[q]);
         if (r->pmask[q]) (void)hipFree(r->pmask[q]);
@@ -521,7 +525,7 @@ void pn_ref_free(pn_ref *r) {
 }
 
 int pn_ref_mask(pn_ref *r, int q, uint32_t max_occ) {
-    if (!r || q < 1 || q > 15) return PN_EINVAL;
+    if (!r || q < 1 || q > PN_MAX_Q) return PN_EINVAL;
     DeviceGuard g(r->ctx->device);
     hipStream_t st = r->ctx->stream;
     pn::RefQDev P;
@@ -548,7 +552,7 @@ int pn_ref_mask(pn_ref *r, int q, uint32_t max_occ) {
 }
 
 int pn_ref_prepare(pn_ref *r, int q) {
-    if (!r || q < 1 || q > 15) return PN_EINVAL;
+    if (!r || q < 1 || q > PN_MAX_Q) return PN_EINVAL;
     DeviceGuard g(r->ctx->device);
     pn::RefQDev P;
     return ref_prepare(r, q, r->ctx->stream, &P);
@@ -562,7 +566,7 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
                        uint32_t n_reads, uint64_t n_bases, int q, int w, void *stream,
                        pn_index **out) {
     if (!c || !out || (n_reads && !d_offsets) || (n_bases && !d_reads)) return PN_EINVAL;
-    if (q < 1 || q > 15 || (w != 32 && w != 64) || n_reads > PN_MAX_READS ||
+    if (q < 1 || q > PN_MAX_Q || (w != 32 && w != 64) || n_reads > PN_MAX_READS ||
         n_bases >= (1ull << 32))
         return PN_EINVAL;
     DeviceGuard g(c->device);
@@ -654,8 +658,8 @@ int pn_index_build_dev(pn_ctx *c, const char *d_reads, const uint64_t *d_offsets
         // occurrences in long slices decide whether the slices are ordered
         // by the letters after the q-gram as well
         pn::launch_fill_u32((uint32_t *)&c->misc[kLongEntries], 2, 0u, st);
-        pn::launch_long_entries(ix, pn::kLongSlice, (unsigned long long *)&c->misc[kLongEntries],
-                                st);
+        pn::launch_long_entries(x->S + x->n_groups, x->Sp, pn::kLongSlice,
+                                (unsigned long long *)&c->misc[kLongEntries], st);
         stage_end(c, st, tok, 7 + 3 * ((2 * q + 7) / 8) + 3 + 3);
         pn::launch_lc_sizes(ix, lcs, st);
         uint32_t n_distinct = 0;
@@ -778,7 +782,28 @@ int pn_index_get_info(const pn_index *x, pn_index_info *out) {
     i.w = x->w;
     i.max_len = x->max_len;
     i.after_sorted = x->after_sorted ? 1 : 0;
+    i.s_sample = x->s_half ? 2 : 1;
     *out = i;
+    return PN_OK;
+}
+
+int pn_index_sample_s(pn_index *x) {
+    if (!x) return PN_EINVAL;
+    if (x->s_half) return PN_OK;
+    pn_ctx *c = x->ctx;
+    DeviceGuard g(c->device);
+    hipStream_t st = c->stream;
+    uint32_t *half = nullptr;
+    PN_CHECK(dalloc_t(c, x->n_groups / 2 + 1, &half));
+    pn::launch_sample_s(x->S, x->n_groups, half, st);
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        dfree(c, half);
+        return map_err(e);
+    }
+    dfree(c, x->S);
+    x->S = half;
+    x->s_half = true;
     return PN_OK;
 }
 
@@ -788,7 +813,8 @@ int pn_index_export(const pn_index *x, void *I, uint32_t *S, uint32_t *Sp, uint6
     DeviceGuard g(c->device);
     hipStream_t st = c->stream;
     if (I) PN_TRY(hipMemcpyAsync(I, x->I, x->n_groups * (x->w / 8), hipMemcpyDeviceToHost, st));
-    if (S) PN_TRY(hipMemcpyAsync(S, x->S, (x->n_groups + 1) * 4, hipMemcpyDeviceToHost, st));
+    const uint64_t ns = x->s_half ? x->n_groups / 2 + 1 : x->n_groups + 1;
+    if (S) PN_TRY(hipMemcpyAsync(S, x->S, ns * 4, hipMemcpyDeviceToHost, st));
     if (Sp) PN_TRY(hipMemcpyAsync(Sp, x->Sp, (x->n_distinct + 1) * 4, hipMemcpyDeviceToHost, st));
     if (O && x->n_qgrams)
         PN_TRY(hipMemcpyAsync(O, x->O, x->n_qgrams * 8, hipMemcpyDeviceToHost, st));

@@ -274,7 +274,7 @@ __device__ __forceinline__ uint32_t probe(const PnIndexDev &ix, const pn::Lists 
     const TW word = I[i];
     if (!((word >> j) & 1)) return 0;
     const uint32_t jp = (uint32_t)pn_popc<TW>(word & (((TW)1 << j) - 1));  // GROUPRANK
-    const uint32_t x = ix.S[i] + jp;
+    const uint32_t x = pn_group_start<TW>(ix, I, i) + jp;
     const uint32_t ks = ix.Sp[x], ke = ix.Sp[x + 1];
     if (pn_low_complexity(g, ix.q)) {
         // rule 2: only reads that keep these seeds, listed by preceding
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void k_refq_ctx(PnRefDev ref, int q, int a,
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const unsigned long long key = keys[i];
         const unsigned long long ps = key >> (2 * q + 2 * a);
-        const uint32_t g = (uint32_t)(key >> (2 * a)) & ((1u << (2 * q)) - 1u);
+        const uint32_t g = (uint32_t)((key >> (2 * a)) & ((1ull << (2 * q)) - 1ull));
         const uint64_t p = ps >> 1;
         const uint32_t s = (uint32_t)(ps & 1u);
         const uint64_t u = s ? L - q - p : p;  // forward position of the q-gram
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
              (blockIdx.x * kWaves + wave) % pn::kShards, 0u, 0ull, 0u, 0u, (uint32_t)kWBuf};
     const int q = ix.q;
-    const uint32_t gmask = (1u << (2 * q)) - 1u;
+    const uint32_t gmask = (uint32_t)((1ull << (2 * q)) - 1ull);
     unsigned long long seeds = 0, visited = 0, set_aside = 0;
     // the block takes kT * kPPT consecutive entries of P, a wave 64
     // consecutive ones per round; every lane runs the same rounds so that
@@ -735,7 +735,8 @@ __device__ __forceinline__ void lc_slices(const PnIndexDev &ix, uint32_t *s_ks, 
         const TW word = I[gi];
         uint32_t ks = 0, ke = 0;
         if ((word >> gj) & 1) {
-            const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
+            const uint32_t slot =
+                pn_group_start<TW>(ix, I, gi) + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
             ks = ix.Sp[slot];
             ke = ix.Sp[slot + 1];
         }
@@ -888,7 +889,8 @@ __global__ void k_lc_sizes(PnIndexDev ix, uint32_t *sizes) {
     const TW word = I[gi];
     uint32_t m = 0;
     if ((word >> gj) & 1) {
-        const uint32_t slot = ix.S[gi] + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
+        const uint32_t slot =
+            pn_group_start<TW>(ix, I, gi) + (uint32_t)pn_popc<TW>(word & (((TW)1 << gj) - 1));
         m = ix.Sp[slot + 1] - ix.Sp[slot];
     }
     sizes[id] = m;

@@ -25,19 +25,6 @@
 
 namespace {
 
-// q-gram code at read offset o (first base most significant) and the class
-// of the letter before it (its code, or PN_CLS_NONE at o == 0)
-__device__ __forceinline__ uint32_t qgram_at(const PnIndexDev &ix, uint64_t off, uint32_t o,
-                                             uint32_t &cls) {
-    if (o == 0) {
-        cls = PN_CLS_NONE;
-        return pn_window16(ix.packed, off) >> (32 - 2 * ix.q);
-    }
-    uint32_t w = pn_window16(ix.packed, off + o - 1);  // letter o-1 then the q-gram
-    cls = w >> 30;
-    return (w << 2) >> (32 - 2 * ix.q);
-}
-
 // The (up to) four letters after a q-gram inside its read (first letter in
 // the top bits, missing letters 0) and how many there are, nav = 0..4, in 9
 // bits: nav = 4 takes the codes 0-255, nav = 3 the next 64, nav = 2 the next
@@ -164,7 +151,11 @@ __global__ __launch_bounds__(256) void k_qgram_keys(PnIndexDev ix,
                 const uint32_t wq = window(cur.off + (o ? o - 1 : 0));
                 const uint32_t w4 = window(cur.off + o + q);
                 uint32_t cls, g;
-                if (o == 0) {
+                if (q == 16) {
+                    // the q-gram fills a whole 16-letter window
+                    g = window(cur.off + o);
+                    cls = o == 0 ? PN_CLS_NONE : wq >> 30;
+                } else if (o == 0) {
                     cls = PN_CLS_NONE;
                     g = wq >> (32 - 2 * q);
                 } else {
@@ -391,12 +382,11 @@ __global__ __launch_bounds__(256) void k_read_lc(PnIndexDev ix, uint32_t *lcinfo
     lcinfo[r] = cnt | (runs << 16) | ((2 * front > cnt ? 1u : 0u) << 31);
 }
 
-// occurrences in slices longer than min_len (D = S[n_groups] slots)
-__global__ __launch_bounds__(256) void k_long_entries(const uint32_t *__restrict__ S,
-                                                      uint64_t n_groups,
+// occurrences in slices longer than min_len (*Dp slots)
+__global__ __launch_bounds__(256) void k_long_entries(const uint32_t *__restrict__ Dp,
                                                       const uint32_t *__restrict__ Sp,
                                                       uint32_t min_len, unsigned long long *out) {
-    const uint64_t D = S[n_groups];
+    const uint64_t D = *Dp;
     unsigned long long acc = 0;
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < D;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -534,10 +524,23 @@ void launch_index_from_sorted(const PnIndexDev &ix, const unsigned long long *ke
 }
 
 
-void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long long *out,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_long_entries, dim3(1024), dim3(256), 0, st, ix.S, ix.n_groups, ix.Sp,
-                       min_len, out);
+void launch_long_entries(const uint32_t *D, const uint32_t *Sp, uint32_t min_len,
+                         unsigned long long *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_long_entries, dim3(1024), dim3(256), 0, st, D, Sp, min_len, out);
+}
+
+// the even entries of S (a sampled S): out[t] = S[2 t], t <= n_groups / 2
+__global__ void k_sample_s(const uint32_t *__restrict__ S, uint64_t n_half,
+                           uint32_t *__restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_half; t += stride)
+        out[t] = S[2 * t];
+}
+
+void launch_sample_s(const uint32_t *S, uint64_t n_groups, uint32_t *out, hipStream_t st) {
+    const uint64_t n_half = n_groups / 2 + 1;
+    hipLaunchKernelGGL(k_sample_s, dim3(pn_stride_blocks(n_half, 256)), dim3(256), 0, st, S,
+                       n_half, out);
 }
 
 void launch_tab_flags(const uint32_t *Sp, uint64_t D, uint32_t min_len, uint32_t *flags,

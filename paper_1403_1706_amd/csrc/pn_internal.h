@@ -29,6 +29,7 @@
 #define PN_READ_WORDS (PN_MAX_READ_LEN / 32)
 #define PN_MAX_READS (1u << 21)
 #define PN_MAX_K 15
+#define PN_MAX_Q 16  // a q-gram code fills at most one 32-bit word
 #define PN_PAD_BLOCKS 16
 #define PN_PAD_POS (32 * PN_PAD_BLOCKS)
 #define PN_DBIAS 65536u
@@ -68,7 +69,7 @@ struct PnIndexDev {
     const uint2 *rplanes;     // n_reads * PN_READ_WORDS
     const uint2 *rplanes_rc;  // the same for each read's reverse complement
     const void *I;            // n_groups words of w bits
-    const uint32_t *S;        // n_groups + 1
+    const uint32_t *S;        // n_groups + 1 (s_half: every second one, S[0], S[2], ...)
     const uint32_t *Sp;       // n_distinct + 1
     const unsigned long long *O;  // n_qgrams 64-bit entries
     const uint32_t *lcinfo;   // per read: low-complexity offsets | (intervals << 16)
@@ -80,6 +81,7 @@ struct PnIndexDev {
     int log2w;
     uint64_t n_groups;
     int after_sorted;  // each slice of O ordered by the letters after the q-gram first
+    int s_half;        // S sampled at even groups (pn_group_start)
 };
 
 // ---------------------------------------------------------------------------
@@ -126,6 +128,16 @@ template <>
 __device__ __forceinline__ int pn_popc<uint32_t>(uint32_t x) { return __popc(x); }
 template <>
 __device__ __forceinline__ int pn_popc<uint64_t>(uint64_t x) { return __popcll(x); }
+
+// S[i], the number of occurring q-grams in the groups before i.  A sampled
+// S (Section 2.2, "Sampling S") keeps the even entries only; an odd one is
+// the even one before it plus the population count of that group's word.
+template <typename TW>
+__device__ __forceinline__ uint32_t pn_group_start(const PnIndexDev &ix, const TW *I, uint32_t i) {
+    if (!ix.s_half) return ix.S[i];
+    const uint32_t v = ix.S[i >> 1];
+    return (i & 1u) ? v + (uint32_t)pn_popc<TW>(I[i - 1]) : v;
+}
 template <>
 __device__ __forceinline__ int pn_popc<unsigned long long>(unsigned long long x) {
     return __popcll(x);
@@ -221,9 +233,12 @@ void launch_tab_flags(const uint32_t *Sp, uint64_t D, uint32_t min_len, uint32_t
 void launch_tab_build(const unsigned long long *O, const uint32_t *Sp, uint64_t D,
                       uint32_t min_len, const uint32_t *num, uint32_t n_tabs, uint32_t *tab_id,
                       uint32_t *list, uint32_t *tabs, hipStream_t st);
-// the number of occurrences in slices of O longer than min_len, added to *out
-void launch_long_entries(const PnIndexDev &ix, uint32_t min_len, unsigned long long *out,
-                         hipStream_t st);
+// the number of occurrences in slices of O longer than min_len, added to
+// *out (D: device word holding the number of slices)
+void launch_long_entries(const uint32_t *D, const uint32_t *Sp, uint32_t min_len,
+                         unsigned long long *out, hipStream_t st);
+// a sampled S from the full one: out[t] = S[2 t] for t = 0 .. n_groups / 2
+void launch_sample_s(const uint32_t *S, uint64_t n_groups, uint32_t *out, hipStream_t st);
 
 // Append-only output split into kShards regions of `region_cap` entries,
 // each with its own counter: a thread block appends to region

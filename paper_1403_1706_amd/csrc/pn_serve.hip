@@ -262,7 +262,7 @@ int pn_server_create(pn_ctx *ctx, const pn_ref *ref, const pn_server_config *cfg
                      pn_server **out) {
     if (!ctx || !ref || !cfg || !out) return PN_EINVAL;
     if (pnrt::ctx_device(ctx) != pnrt::ref_device(ref)) return PN_EINVAL;
-    if (cfg->q < 1 || cfg->q > 15 || (cfg->w != 32 && cfg->w != 64) || cfg->slots < 1 ||
+    if (cfg->q < 1 || cfg->q > PN_MAX_Q || (cfg->w != 32 && cfg->w != 64) || cfg->slots < 1 ||
         cfg->slots > 8 || cfg->max_batch_reads < 1 || cfg->max_batch_reads > PN_MAX_READS ||
         cfg->hbm_budget == 0)
         return PN_EINVAL;

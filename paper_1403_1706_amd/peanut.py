@@ -45,7 +45,8 @@ class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_reads", ctypes.c_uint64), ("n_bases", ctypes.c_uint64),
                 ("n_qgrams", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
                 ("n_groups", ctypes.c_uint64), ("q", ctypes.c_int32), ("w", ctypes.c_int32),
-                ("max_len", ctypes.c_int32), ("after_sorted", ctypes.c_int32)]
+                ("max_len", ctypes.c_int32), ("after_sorted", ctypes.c_int32),
+                ("s_sample", ctypes.c_int32)]
 
 
 STAGES = ["ingest", "index", "filter_heavy", "filter_emit", "verify", "sort", "finish", "rules",
@@ -119,6 +120,7 @@ _sig("pn_index_build", _int, [_P, ctypes.c_char_p, _P, _u32, _int, _int, _PP])
 _sig("pn_index_build_dev", _int, [_P, _P, _P, _u32, _u64, _int, _int, _P, _PP])
 _sig("pn_index_free", None, [_P])
 _sig("pn_index_get_info", _int, [_P, ctypes.POINTER(_IndexInfo)])
+_sig("pn_index_sample_s", _int, [_P])
 _sig("pn_index_export", _int, [_P, _P, _P, _P, _P])
 _sig("pn_map", _int, [_P, _P, _P, _int, _P, _int, _PP, ctypes.POINTER(_u64)])
 _sig("pn_map_dev", _int, [_P, _P, _P, _int, _P, _int, _P, _u64, ctypes.POINTER(_u64), _P])
@@ -147,6 +149,7 @@ EXPORTED = ["pn_strerror", "pn_ctx_create", "pn_ctx_destroy", "pn_ctx_stream",
             "pn_ref_load_dev", "pn_ref_free", "pn_ref_length", "pn_ref_prepare", "pn_ref_mask",
             "pn_index_build",
             "pn_index_build_dev", "pn_index_free", "pn_index_get_info", "pn_index_export",
+            "pn_index_sample_s",
             "pn_map", "pn_map_dev", "pn_hits_free", "pn_filter", "pn_validate",
             "pn_validate_noalloc", "pn_align",
             "pn_server_create", "pn_server_submit", "pn_server_wait", "pn_poll",
@@ -277,11 +280,15 @@ def pn_index_get_info(idx) -> dict:
     return {f: getattr(info, f) for f, _ in _IndexInfo._fields_}
 
 
+def pn_index_sample_s(idx) -> None:
+    _check(_lib.pn_index_sample_s(idx), "pn_index_sample_s")
+
+
 def pn_index_export(idx):
     """(I, S, S', O) as numpy arrays."""
     info = pn_index_get_info(idx)
     I = np.empty(info["n_groups"], dtype=np.uint64 if info["w"] == 64 else np.uint32)
-    S = np.empty(info["n_groups"] + 1, dtype=np.uint32)
+    S = np.empty(info["n_groups"] // info["s_sample"] + 1, dtype=np.uint32)
     Sp = np.empty(info["n_distinct"] + 1, dtype=np.uint32)
     O = np.empty(max(info["n_qgrams"], 1), dtype=np.uint64)
     _check(_lib.pn_index_export(idx, _ptr(I), _ptr(S), _ptr(Sp), _ptr(O)), "pn_index_export")

@@ -69,7 +69,7 @@ def test_no_device_gives_device_error(pn):
 def test_struct_layouts(pn):
     assert pn.HIT_DTYPE.itemsize == 12
     assert pn.CAND_DTYPE.itemsize == 16
-    assert ctypes.sizeof(pn._IndexInfo) == 56
+    assert ctypes.sizeof(pn._IndexInfo) == 64
 
 
 def test_new_entry_points_check_arguments(pn):
@@ -81,3 +81,6 @@ def test_new_entry_points_check_arguments(pn):
     out = ctypes.c_void_p()
     assert lib.pn_server_create(None, None, None, ctypes.byref(out)) == pn.PN_EINVAL
     assert pn.PN_PENDING == 1
+    assert lib.pn_ref_mask(None, 12, 5) == pn.PN_EINVAL
+    assert lib.pn_index_sample_s(None) == pn.PN_EINVAL
+    assert lib.pn_align(None, None, None, None, 0, None, None, None, 0, None) == pn.PN_EINVAL

@@ -169,6 +169,46 @@ def test_index_large_scans_by_definition(pn, sess):
     assert np.array_equal(present, first)
 
 
+@pytest.mark.parametrize("wbits", [32, 64])
+def test_index_q16_by_definition(pn, sess, wbits):
+    """q = 16 (a q-gram fills a 32-bit word; 4^16 bits of I, Section 2.2's
+    regime where the q-group index saves the most), checked by what holds
+    at any size: S is the exclusive scan of popcount(I) (also once
+    sampled), S' cuts O into one slice per present q-gram in increasing
+    order, each holding that q-gram only (recomputed from the reads), the
+    present q-grams are I's set bits, and O lists every occurrence once."""
+    w = synth.make("tiny", n_reads=20_000)
+    q = 16
+    idx = sess.index(w.reads, w.offsets, q, wbits)
+    info = pn.pn_index_get_info(idx)
+    assert info["n_groups"] == (1 << 32) // wbits
+    I, S, Sp, O = pn.pn_index_export(idx)
+    T = len(O)
+    assert T == w.n_reads * (100 - q + 1)
+    pc = np.bitwise_count(I).astype(np.int64)
+    full = np.concatenate([[0], np.cumsum(pc)])
+    assert np.array_equal(S.astype(np.int64), full)
+    Sp = Sp.astype(np.int64)
+    assert Sp[0] == 0 and Sp[-1] == T and np.all(np.diff(Sp) > 0)
+    assert len(Sp) - 1 == int(pc.sum())
+    _, r, o = decode_O(O)
+    assert len(np.unique(r * 256 + o)) == T
+    codes = oracle.encode(w.reads).astype(np.int64)
+    pos = w.offsets[r].astype(np.int64) + o
+    g = np.zeros(T, np.int64)
+    for t in range(q):
+        g = (g << 2) | codes[pos + t]
+    first = g[Sp[:-1]]
+    assert np.all(np.diff(first) > 0)
+    assert np.array_equal(g, np.repeat(first, np.diff(Sp)))
+    nz = np.nonzero(I)[0]
+    bits = np.unpackbits(I[nz].view(np.uint8).reshape(len(nz), -1), axis=1, bitorder="little")
+    wi, bj = np.nonzero(bits)
+    assert np.array_equal(nz[wi].astype(np.int64) * wbits + bj, first)
+    pn.pn_index_sample_s(idx)
+    assert np.array_equal(pn.pn_index_export(idx)[1].astype(np.int64), full[::2])
+
+
 def test_index_w32_equals_w64(pn, sess):
     w = synth.make("tiny", n_reads=2000)
     a = pn.pn_index_export(sess.index(w.reads, w.offsets, 10, 32))
@@ -267,7 +307,7 @@ def test_map_tiny_w32_and_q_invariance(pn, sess):
     base = map_both(pn, sess, w, k=5, q=10, modes=(0,), wbits=32)
     # q = 6 makes the index average over 16 occurrences per q-gram, so the
     # filter hands only lists over 64 entries to its second kernel (else 32)
-    for q in (6, 7, 8, 9, 11, 13, 15):
+    for q in (6, 7, 8, 9, 11, 13, 15, 16):
         idx = sess.index(w.reads, w.offsets, q)
         ref = sess.ref(w.ref)
         assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, 5, 0), base)
@@ -383,6 +423,41 @@ def test_error_statuses(pn, sess):
     assert e.value.status == pn.PN_EINVAL
     # the context still works after errors
     assert len(pn.pn_map(sess.ctx, ref, idx, 5, 0)) > 0
+
+
+# ---------------------------------------------------------------------------
+# sampled S (Section 2.2)
+
+
+@pytest.mark.parametrize("case", ["mixed-q12-w32", "tiny-q15-w64", "human-ordered"])
+def test_sampled_s_keeps_index_and_hits(pn, sess, case):
+    """After pn_index_sample_s the index keeps S's even entries only (equal
+    to the full S at those groups) and reports s_sample = 2; every group's
+    start is still found (odd groups add one population count), so the
+    hits of both modes are unchanged, on a plain and on an ordered index."""
+    if case != "human-ordered":
+        w = synth.make(case.split("-")[0], scale=0.002 if case.startswith("mixed") else 0.1)
+        q = int(case.split("-")[1][1:])
+        wb = int(case.split("-")[2][1:])
+        k = w.k_per_read
+    else:
+        w = synth.make("human", scale=0.003, n_reads=100_000)
+        q, wb, k = 12, 64, 5
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, q, wb)
+    if case == "human-ordered":
+        assert pn.pn_index_get_info(idx)["after_sorted"] == 1
+    I, S, Sp, O = pn.pn_index_export(idx)
+    before = [pn.pn_map(sess.ctx, ref, idx, k, mode) for mode in (0, 1)]
+    pn.pn_index_sample_s(idx)
+    pn.pn_index_sample_s(idx)  # idempotent
+    info = pn.pn_index_get_info(idx)
+    assert info["s_sample"] == 2
+    I2, S2, Sp2, O2 = pn.pn_index_export(idx)
+    assert len(S2) == info["n_groups"] // 2 + 1
+    assert np.array_equal(S2, S[::2]) and np.array_equal(I2, I) and np.array_equal(Sp2, Sp)
+    for mode in (0, 1):
+        assert_hits_equal(pn.pn_map(sess.ctx, ref, idx, k, mode), before[mode])
 
 
 # ---------------------------------------------------------------------------

@@ -27,10 +27,13 @@ sys.path.insert(0, ROOT)
 # (2-3), bit-vector step (about 13), band shift and right-edge count (5),
 # the cut-off test (3)
 OPS_PER_ROW = 30
-# VALU instructions per read letter of the count filter (k_count's unrolled
-# piece loop, band inside the reference: two text-plane shifts, two read-bit
-# extracts, the match word and its accumulation)
-OPS_PER_LETTER = 8.5
+# VALU instructions of the count filter per 32-letter read word and band
+# diagonal (k_count's loops, band inside the reference, in the compiled
+# kernel's assembly): per diagonal two text-plane shifts, the match word
+# (3), the piece reduction (4) and the loop test; per word the text stream,
+# the read word, the piece count and the exits
+OPS_PER_WORD = 34
+OPS_PER_DIAGONAL = 10
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
 HBM_PEAK_BPS = 8.0e12
@@ -71,6 +74,64 @@ def counter_traffic(kernel, workload):
     return None
 
 
+def large_q_run(pn, steps):
+    """The q-group index in the sparse regime of Section 2.2: 10^8 read
+    letters (1 M reads x 100 bp against the 100 Mbp repeat reference), where
+    4^16 = 42.95 x the read text.  Mapping steps (index build + map, all
+    hits, k = 5) timed at q = 12, at q = 16 and at q = 16 with S sampled,
+    with each index's sizes beside a conventional q-gram index's
+    ((4^q + 1) bucket starts + one position per occurrence, 4 bytes each)."""
+    import numpy as np
+    import torch
+    from paper_1403_1706_amd import synth
+    w = synth.make("repeat")
+    dev = torch.device("cuda:0")
+    d_r = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_o = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    ctx = pn.pn_ctx_create(0)
+    ref = pn.pn_ref_load(ctx, w.ref)
+    out = torch.empty(12 * 16 * w.n_reads, dtype=torch.uint8, device=dev)
+    res = {"workload": WORKLOADS["repeat"].replace("q=12, ", ""), "steps": steps, "w": 64}
+    hits = set()
+    for q, sample in ((12, False), (16, False), (16, True)):
+        pn.pn_ref_prepare(ref, q)
+
+        def step():
+            idx = pn.pn_index_build_dev(ctx, d_r, d_o, q, 64)
+            try:
+                if sample:
+                    pn.pn_index_sample_s(idx)
+                info = pn.pn_index_get_info(idx)
+                n = pn.pn_map_dev(ctx, ref, idx, 5, out, pn.PN_ALL_HITS)
+            finally:
+                pn.pn_index_free(idx)
+            return n, info
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            n, info = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hits.add(n)
+        T = info["n_qgrams"]
+        qgroup = info["n_groups"] * 8 + (info["n_groups"] // info["s_sample"] + 1) * 4 + \
+            (info["n_distinct"] + 1) * 4
+        conv = ((1 << (2 * q)) + 1) * 4
+        key = f"q{q}" + ("_sampled_s" if sample else "")
+        res[key] = {"ms_per_step": (t1 - t0) * 1000.0 / steps,
+                    "reads_per_s": w.n_reads * steps / (t1 - t0), "hits": int(n),
+                    "I_S_Sp_bytes": qgroup, "O_entries": T,
+                    "conventional_bucket_bytes": conv,
+                    "size_ratio_4_byte_positions": (qgroup + 4 * T) / (conv + 4 * T)}
+        log(f"large q: {key}: {res[key]['ms_per_step']:.2f} ms/step, "
+            f"index ratio {res[key]['size_ratio_4_byte_positions']:.3f}")
+    res["same_hits"] = len(hits) == 1
+    pn.pn_ref_free(ref)
+    pn.pn_ctx_destroy(ctx)
+    return res
+
+
 def serving_run(pn, ctx, ref, ref_ascii, q, args):
     """Requests shaped like the serving workload (1k-200k reads log-uniform,
     75-250 bp, 2-5 % error, all hits or best stratum, Poisson arrivals)
@@ -88,7 +149,8 @@ def serving_run(pn, ctx, ref, ref_ascii, q, args):
     log(f"serving: {len(reqs)} requests, {n_reads} reads ({time.time() - t0:.1f}s to generate)")
     unit_arrivals = np.array([r["arrival"] for r in reqs])
 
-    def run(srv, rate):
+    def run(srv, rate, reqs=reqs):
+        n_reads = sum(len(r["offsets"]) - 1 for r in reqs)
         before = pn.pn_server_get_stats(srv)
         tickets = [None] * len(reqs)
         t_sub = [0.0] * len(reqs)
@@ -128,8 +190,10 @@ def serving_run(pn, ctx, ref, ref_ascii, q, args):
     srv_b = pn.pn_server_create(ctx, ref, q, **batched)
     srv_s = pn.pn_server_create(ctx, ref, q, **serial_cfg)
     try:
-        run(srv_b, None)  # warm-up: workspaces grow to their working size
-        run(srv_s, None)
+        # warm-up on the largest requests: workspaces grow to their working size
+        big = sorted(reqs, key=lambda r: -len(r["offsets"]))[:8]
+        run(srv_b, None, big)
+        run(srv_s, None, big)
         serial = run(srv_s, None)
         cap = len(reqs) / serial["wall_s"]  # requests/s, one at a time
         log(f"serving: serial {serial['reads_per_s']:.3e} reads/s ({cap:.1f} requests/s)")
@@ -275,9 +339,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="reads the CPU oracle maps (default: 200 for human, else 10000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-align", action="store_true")
+    ap.add_argument("--no-large-q", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="mixed-length batch with autotuned q/w vs per-length launches")
     ap.add_argument("--copy-kernel", action="store_true",
@@ -444,7 +509,9 @@ def main():
     n_pos = max(0, len(w.ref) - w.q + 1)
     if dominant in ("verify", "verify_long", "count"):
         if dominant == "count":
-            work = st["count_letters"] / K * OPS_PER_LETTER
+            # (the workload's k is uniform: 2k + 1 diagonals per word)
+            words = st["count_letters"] / 32.0 / K
+            work = words * (OPS_PER_WORD + OPS_PER_DIAGONAL * (2 * int(w.k_per_read[0]) + 1))
         else:
             rows = st["verify_rows_long"] if dominant == "verify_long" else \
                 st["verify_rows"] - st["verify_rows_long"]
@@ -503,6 +570,10 @@ def main():
                "seconds": c1 - c0}
         log(f"cpu baseline: {cpu['value']:.1f} reads/s")
 
+    large_q = None
+    if not args.no_large_q:
+        large_q = large_q_run(pn, args.steps)
+
     serving = None
     if not args.no_serve:
         serving = serving_run(pn, ctx, ref, w.ref, w.q, args)
@@ -535,6 +606,7 @@ def main():
                                                      "p99": serving["p99_ms"]},
         "serving": serving,
         "align": align,
+        "large_q": large_q,
         "hits": n_hits,
         "mapped_fraction": mapped,
         "stage_ms": stage_ms,

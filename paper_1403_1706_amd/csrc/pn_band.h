@@ -5,9 +5,13 @@
 
 #include "pn_internal.h"
 
-// bits [sh, sh+32) of the 64-bit value hi:lo
+// bits [sh, sh+32) of the 64-bit value hi:lo (0 <= sh < 32)
 __host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+#else
     return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+#endif
 }
 
 // Verify one candidate.  `pl`: the strand's padded bit planes; `rp`: the
@@ -160,17 +164,24 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
 // alignment with at most k errors leaves at least m - k pieces exact, each
 // on one diagonal of the alignment; every cell of an alignment through the
 // candidate's diagonal d lies within k diagonals of d, so those pieces
-// match the text exactly on diagonals of the band [d - k, d + k].  A piece
-// is exact on band diagonal b when bit b of the match words of its letters
-// (the band's Eq, one row per letter) is set in all of them.  The
-// candidate is dropped as soon as the pieces found plus those unchecked
-// fall below m - k, and kept once m - k are found.  Short pieces decide
-// sooner against a diverged copy (a 4-letter piece of a copy at 72 %
-// identity is exact a quarter of the time, an 8-letter one a fourteenth:
-// six failures come after fewer letters) while a chance match on one of
-// the band's 2k + 1 diagonals stays rare (2k + 1 in 256).  kInside: every
-// band position of the wave's candidates lies in [0, L) (no validity
-// plane).
+// match the text exactly on diagonals of the band [d - k, d + k].
+//
+// The read is taken 32 letters (8 pieces) at a time and the band one
+// diagonal at a time: on diagonal b the match bits of all 32 letters are
+// one word, ~((H_b ^ xH) | (L_b ^ xL)) with H_b, L_b the text planes from
+// position lo + 32 w + b, and a piece is exact there when its 4 bits are
+// all set (two shift-and steps leave that at the piece's first bit).  OR
+// over the 2k + 1 diagonals and a population count give the pieces of the
+// word found somewhere in the band: about 8 operations per diagonal for 32
+// letters, against 8 per letter row by row.  The candidate is dropped as
+// soon as the pieces found plus those unchecked fall below m - k, and kept
+// once m - k are found (decisions at word ends; the outcome is the same as
+// piece by piece).  Short pieces decide sooner against a diverged copy (a
+// 4-letter piece of a copy at 72 % identity is exact a quarter of the
+// time) while a chance match on one of the band's 2k + 1 diagonals stays
+// rare (2k + 1 in 256).  kInside: every band position of the wave's
+// candidates lies in [0, L) (no validity plane).  `letters`: 32 per word
+// examined (the letters one diagonal-major step covers).
 constexpr int kPnPiece = 4;
 
 template <bool kInside>
@@ -181,45 +192,43 @@ __host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, c
     const int need = m - k;
     letters = 0;
     if (need <= 0) return true;
-    const uint32_t M = (1u << (2 * k + 1)) - 1u;
+    const int W = 2 * k + 1;
     const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
     const uint64_t blk = tp >> 5;
     const uint32_t ph = (uint32_t)(tp & 31);
-    uint4 C = hd.C, Dn = hd.Dn;
-    uint32_t h0 = pn_funnel(hd.B.x, hd.A.x, ph), l0 = pn_funnel(hd.B.y, hd.A.y, ph),
-             v0 = pn_funnel(hd.B.z, hd.A.z, ph);
-    uint32_t h1 = pn_funnel(C.x, hd.B.x, ph), l1 = pn_funnel(C.y, hd.B.y, ph),
-             v1 = pn_funnel(C.z, hd.B.z, ph);
+    uint4 A = hd.A, B = hd.B, C = hd.C, Dn = hd.Dn;
     uint2 rw = hd.rw0;
-    int found = 0, checked = 0;
+    int found = 0;
     for (int w = 0;; w++) {
-        const uint2 rwn = 32 * (w + 1) < kPnPiece * m ? rp[w + 1] : rw;
-#pragma unroll
-        for (int pc = 0; pc < 32 / kPnPiece; pc++) {
-            uint32_t acc = M;
-#pragma unroll
-            for (int u = 0; u < kPnPiece; u++) {
-                const int t = kPnPiece * pc + u;  // read letter 32 w + t
-                const uint32_t H = pn_funnel(h1, h0, t), Lw = pn_funnel(l1, l0, t);
-                const uint32_t xh = (uint32_t)((int32_t)(rw.x << (31 - t)) >> 31),
-                               xl = (uint32_t)((int32_t)(rw.y << (31 - t)) >> 31);
-                uint32_t eq = ~((H ^ xh) | (Lw ^ xl));
-                if (!kInside) eq &= pn_funnel(v1, v0, t);
-                acc &= eq;
-            }
-            letters += kPnPiece;
-            found += acc != 0u;
-            checked++;
-            if (found >= need) return true;
-            if (found + (m - checked) < need) return false;
+        const int left = m - 8 * w;  // pieces from this word on
+        const uint2 rwn = left > 8 ? rp[w + 1] : rw;
+        // the 64 text letters from lo + 32 w
+        const uint32_t h0 = pn_funnel(B.x, A.x, ph), h1 = pn_funnel(C.x, B.x, ph);
+        const uint32_t l0 = pn_funnel(B.y, A.y, ph), l1 = pn_funnel(C.y, B.y, ph);
+        uint32_t v0 = 0, v1 = 0;
+        if (!kInside) {
+            v0 = pn_funnel(B.z, A.z, ph);
+            v1 = pn_funnel(C.z, B.z, ph);
         }
+        uint32_t F = 0;
+        for (int b = 0; b < W; b++) {
+            const uint32_t H = pn_funnel(h1, h0, (uint32_t)b), Lw = pn_funnel(l1, l0, (uint32_t)b);
+            uint32_t eq = ~((H ^ rw.x) | (Lw ^ rw.y));
+            if (!kInside) eq &= pn_funnel(v1, v0, (uint32_t)b);
+            const uint32_t y = eq & (eq >> 1);
+            F |= y & (y >> 2);
+        }
+        const uint32_t firsts =
+            left >= 8 ? 0x11111111u : (0x11111111u & ((1u << (4 * left)) - 1u));
+        found += __builtin_popcount(F & firsts);
+        const int now = left < 8 ? left : 8;
+        letters += 32;
+        const int unchecked = left - now;
+        if (found >= need) return true;
+        if (found + unchecked < need) return false;
         // the next 32 letters: advance the text stream by 32 positions
-        h0 = h1;
-        l0 = l1;
-        v0 = v1;
-        h1 = pn_funnel(Dn.x, C.x, ph);
-        l1 = pn_funnel(Dn.y, C.y, ph);
-        v1 = pn_funnel(Dn.z, C.z, ph);
+        A = B;
+        B = C;
         C = Dn;
         Dn = pl[blk + w + 4];
         rw = rwn;

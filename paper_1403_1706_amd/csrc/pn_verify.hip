@@ -211,6 +211,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
 // The count filter over a candidate list: candidates that may hold a hit
 // go to the survivor list (longc, one region per input region), which the
 // band pass then runs from row 0 to the end.
+// A count-filter candidate ready to run: the first three plane blocks and
+// the read's first word (the fourth block is loaded when it starts), fewer
+// registers than a verification candidate so that more waves fit.
+struct CountCand {
+    uint2 c;
+    int len, k;  // k < 0: nothing to do
+    int64_t lo;
+    uint4 A, B, C;
+    uint2 rw0;
+};
+
+__device__ __forceinline__ const uint4 *count_planes(const PnRefDev &ref, uint2 c) {
+    return (c.x >> 31) ? ref.planes[1] : ref.planes[0];
+}
+
+__device__ __forceinline__ void count_start(const PnRefDev &ref, const PnIndexDev &ix, int kglob,
+                                            const uint8_t *__restrict__ kpr, uint2 c,
+                                            CountCand &x) {
+    x.c = c;
+    x.k = -1;
+    if (c.x == PN_CAND_NONE) return;
+    const uint32_t r = c.x & PN_CAND_READ;
+    const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
+    const int k = kglob >= 0 ? kglob : (int)kpr[r];
+    if (k > PN_MAX_K || len < 1 || len > PN_MAX_READ_LEN) return;
+    x.len = len;
+    x.k = k;
+    x.lo = (int64_t)c.y - (int64_t)PN_DBIAS - k;
+    const uint4 *pl = count_planes(ref, c);
+    const uint64_t blk = (uint64_t)(x.lo + PN_PAD_POS) >> 5;
+    x.A = pl[blk];
+    x.B = pl[blk + 1];
+    x.C = pl[blk + 2];
+    x.rw0 = ix.rplanes[(uint64_t)r * PN_READ_WORDS];
+}
+
 __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
                                                     int kglob, const uint8_t *__restrict__ kpr,
                                                     uint2 *longc, unsigned long long *n_long,
@@ -233,21 +269,30 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
     uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64;
     uint2 c_next = base + lane < n ? cands[base + lane] : none;
     uint2 c_after = base + stride + lane < n ? cands[base + stride + lane] : none;
-    Cand cur;
-    start(ref, ix, kglob, kpr, 0, c_next, false, cur);
+    CountCand cur;
+    count_start(ref, ix, kglob, kpr, c_next, cur);
     for (; base < n; base += stride) {
-        Cand nxt;
-        start(ref, ix, kglob, kpr, 0, c_after, false, nxt);
+        CountCand nxt;
+        count_start(ref, ix, kglob, kpr, c_after, nxt);
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
+        const bool ok = cur.k >= 0;
         // (wave-uniform) every band position inside the reference
         const bool inside =
-            __all(!cur.ok || (cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L));
-        if (cur.ok) {
+            __all(!ok || (cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L));
+        if (ok) {
+            const uint4 *pl = count_planes(ref, cur.c);
+            const uint2 *rp = ix.rplanes + (uint64_t)(cur.c.x & PN_CAND_READ) * PN_READ_WORDS;
+            PnBandHead hd;
+            hd.A = cur.A;
+            hd.B = cur.B;
+            hd.C = cur.C;
+            hd.Dn = pl[((uint64_t)(cur.lo + PN_PAD_POS) >> 5) + 3];
+            hd.rw0 = cur.rw0;
             int lt = 0;
             const bool keep =
-                inside ? pn_count_pieces<true>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, lt)
-                       : pn_count_pieces<false>(cur.hd, cur.pl, cur.rp, cur.len, cur.k, cur.lo, lt);
+                inside ? pn_count_pieces<true>(hd, pl, rp, cur.len, cur.k, cur.lo, lt)
+                       : pn_count_pieces<false>(hd, pl, rp, cur.len, cur.k, cur.lo, lt);
             if (keep) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
             letters += (unsigned long long)lt;
         }

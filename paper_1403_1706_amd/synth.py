@@ -467,18 +467,28 @@ def letters_to_index(seq: bytes) -> np.ndarray:
 
 
 def serving_requests(rng: np.random.Generator, ref: np.ndarray, n_requests: int,
-                     min_reads: int = 1000, max_reads: int = 200_000):
+                     min_reads: int = 1000, max_reads: int = 200_000,
+                     threads: int | None = None):
     """Request stream: reads per request log-uniform in [min_reads, max_reads],
     lengths uniform 75..250, error rate U[2 %, 5 %] per request, mode all or
-    best with probability 1/2, Poisson arrivals (unit rate; scale by 1/lambda)."""
-    out = []
+    best with probability 1/2, Poisson arrivals (unit rate; scale by 1/lambda).
+    Each request's reads come from a child stream of `rng`, drawn on a thread
+    pool (the result does not depend on the thread count)."""
+    params = []
     t = 0.0
     for _ in range(n_requests):
         nr = int(math.floor(math.exp(rng.uniform(math.log(min_reads), math.log(max_reads)))))
-        lengths = rng.integers(75, 251, nr).astype(np.int64)
         eps = float(rng.uniform(0.02, 0.05))
-        reads, offsets, strands, starts = simulate_reads(ref, lengths, eps, rng)
         t += float(rng.exponential(1.0))
-        out.append({"arrival": t, "reads": reads, "offsets": offsets,
-                    "k_per_read": k_ceil_fraction(lengths), "best": bool(rng.random() < 0.5)})
-    return out
+        best = bool(rng.random() < 0.5)
+        params.append((nr, eps, t, best))
+    children = rng.spawn(n_requests)
+
+    def one(i):
+        nr, eps, t, best = params[i]
+        g = children[i]
+        lengths = g.integers(75, 251, nr).astype(np.int64)
+        reads, offsets, strands, starts = simulate_reads(ref, lengths, eps, g)
+        return {"arrival": t, "reads": reads, "offsets": offsets,
+                "k_per_read": k_ceil_fraction(lengths), "best": best}
+    return _map_threads(one, range(n_requests), _pool_threads(threads))

@@ -419,7 +419,10 @@ def test_error_statuses(pn, sess):
         sess.index(b"A" * 300, np.array([0, 300], np.uint64), 10)
     assert e.value.status == pn.PN_EINVAL
     with pytest.raises(pn.PnError) as e:
-        sess.index(w.reads, w.offsets, 16)
+        sess.index(w.reads, w.offsets, 17)  # a q-gram code must fit 32 bits
+    assert e.value.status == pn.PN_EINVAL
+    with pytest.raises(pn.PnError) as e:
+        pn.pn_ref_mask(ref, 17, 5)
     assert e.value.status == pn.PN_EINVAL
     # the context still works after errors
     assert len(pn.pn_map(sess.ctx, ref, idx, 5, 0)) > 0

@@ -517,8 +517,14 @@ def main():
                 st["verify_rows"] - st["verify_rows_long"]
             work = rows / K * OPS_PER_ROW
         achieved = work / max(1.0, launches[dominant]) / (per_launch_ms / 1000.0)
+        tb = counter_traffic(kernel, f"{args.workload}:{args.scale}:{args.w}")
+        # traffic: the kernel's HBM bytes per launch from the counters, over
+        # the same launch time (GB/s)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / ALU_PEAK_OPS, "traffic": None,
+                "unit": "TOP/s", "frac": achieved / ALU_PEAK_OPS,
+                "traffic": None if tb is None else tb / (per_launch_ms / 1000.0) / 1e9,
+                "traffic_unit": "GB/s",
+                "traffic_gb_per_launch": None if tb is None else tb / 1e9,
                 "kernel": kernel, "avg_launch_ms": per_launch_ms}
     else:
         # the method's minimum traffic, per scanned position (2 per forward

@@ -242,7 +242,11 @@ int pn_index_sample_s(pn_index *idx);
  * the q-gram (the code next4 when nav = 4, else 256 + the three letters,
  * 320 + two, 336 + one, 340 for none; pn_index_info.after_sorted = 1), so
  * that filtration can find the entries whose next letters agree with the
- * text by binary search.  Any pointer may be NULL to skip that array. */
+ * text by binary search; bit 20 marks a piece start (offset a multiple of
+ * q + 4 with four letters after the q-gram).  Each mapping call writes its
+ * per-read seed-rule byte into bits 0-7 and the read's length - 1 into bits
+ * 8-15 (both 0 in a freshly built index).  Any pointer may be NULL to skip
+ * that array. */
 int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime, uint64_t *O);
 
 /* ---- mapping ----------------------------------------------------------- */

@@ -837,7 +837,10 @@ int key_rbits(uint32_t n) { return std::max(1, bitlen(n ? n - 1 : 0)); }
 // plain: the position set is masked (every read gets the plain rule byte)
 int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, bool plain,
                   hipStream_t st) {
-    PN_CHECK(ensure(c, c->ws.rinfo, (uint64_t)x->n_reads + 1));
+    // the rule bytes, then (256-byte aligned) the stamp words
+    const uint64_t rinfo_bytes = ((uint64_t)x->n_reads + 1 + 255) & ~255ull;
+    PN_CHECK(ensure(c, c->ws.rinfo, rinfo_bytes + 2 * ((uint64_t)x->n_reads + 1)));
+    uint16_t *rstamp = (uint16_t *)((uint8_t *)c->ws.rinfo.p + rinfo_bytes);
     PN_CHECK(ensure(c, c->ws.side, std::max<uint64_t>(x->lc_total, 1) * 8));
     PN_CHECK(ensure(c, c->ws.side_meta, 17 * pn::kLcPatterns * 4));
     uint32_t starts[pn::kLcPatterns];
@@ -850,9 +853,9 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, b
     PN_TRY(hipMemcpyAsync(c->ws.side_meta.p, starts, sizeof(starts), hipMemcpyHostToDevice, st));
     PnIndexDev ix = index_desc(x);
     const int tok = stage_begin(c, st, PN_STAGE_RULES);
-    pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->ws.rinfo.p, (uint32_t *)&c->misc[kStatus],
-                          plain, st);
-    pn::launch_stamp_rules(x->O, x->n_qgrams, (const uint8_t *)c->ws.rinfo.p, st);
+    pn::launch_read_rules(ix, kglob, d_k, (uint8_t *)c->ws.rinfo.p, rstamp,
+                          (uint32_t *)&c->misc[kStatus], plain, st);
+    pn::launch_stamp_rules(x->O, x->n_qgrams, rstamp, st);
     // 16 region starts, 16 x 6 class bounds, then scratch for the side lists
     uint32_t *meta = (uint32_t *)c->ws.side_meta.p;
     pn::launch_fill_u32(meta + pn::kLcPatterns, 6 * pn::kLcPatterns, 0u, st);
@@ -1501,6 +1504,7 @@ int pn_validate(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_candid
     if (!s && n)
         s = map_err(hipMemcpyAsync(c->ws.cands.p, host.data(), n * sizeof(uint2),
                                    hipMemcpyHostToDevice, st));
+    if (!s) pn::launch_cands_len((uint2 *)c->ws.cands.p, n, x->offsets, st);
     uint64_t got = 0;
     const int ebits = key_ebits(ref->L);
     if (!s) s = validate_sorted(c, ref, x, k < 0 ? -1 : k, dk, false, n, st, &got);
@@ -1687,9 +1691,10 @@ int pn_validate_noalloc(pn_ctx *c, const pn_ref *ref, const pn_index *x,
     // k and the lemma per read (as the mapping checks them), the candidates
     // converted and range-checked
     zero_misc(c, st);
-    pn::launch_read_rules(ix, kglob, d_k_per_read, base + kNaRinfo, (uint32_t *)&c->misc[kStatus],
-                          false, st);
-    pn::launch_cands_in(d_cands, n, x->n_reads, ref->L, cands, (uint32_t *)&c->misc[kStatus], st);
+    pn::launch_read_rules(ix, kglob, d_k_per_read, base + kNaRinfo, nullptr,
+                          (uint32_t *)&c->misc[kStatus], false, st);
+    pn::launch_cands_in(d_cands, n, x->n_reads, ref->L, x->offsets, cands,
+                        (uint32_t *)&c->misc[kStatus], st);
     pn::launch_fill_u32((uint32_t *)&c->misc[kCandCounts], 1, (uint32_t)n, st);
     PN_CHECK(na_sync_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];

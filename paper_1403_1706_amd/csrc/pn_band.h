@@ -234,3 +234,49 @@ __host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, c
         rw = rwn;
     }
 }
+
+// The same count for a band that lies inside the reference, from the H and
+// L words of the plane blocks only (V is all ones there): `hl` is the
+// planes read as uint2 (block i's H, L at hl[2 i]), A..Dn the blocks
+// blk .. blk + 3 of the candidate's stream.
+__host__ __device__ __forceinline__ bool pn_count_pieces_hl(uint2 A, uint2 B, uint2 C, uint2 Dn,
+                                                            uint2 rw0,
+                                                            const uint2 *__restrict__ hl,
+                                                            const uint2 *__restrict__ rp, int len,
+                                                            int k, int64_t lo, int &letters) {
+    const int m = len / kPnPiece;
+    const int need = m - k;
+    letters = 0;
+    if (need <= 0) return true;
+    const int W = 2 * k + 1;
+    const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
+    const uint64_t blk = tp >> 5;
+    const uint32_t ph = (uint32_t)(tp & 31);
+    uint2 rw = rw0;
+    int found = 0;
+    for (int w = 0;; w++) {
+        const int left = m - 8 * w;
+        const uint2 rwn = left > 8 ? rp[w + 1] : rw;
+        const uint32_t h0 = pn_funnel(B.x, A.x, ph), h1 = pn_funnel(C.x, B.x, ph);
+        const uint32_t l0 = pn_funnel(B.y, A.y, ph), l1 = pn_funnel(C.y, B.y, ph);
+        uint32_t F = 0;
+        for (int b = 0; b < W; b++) {
+            const uint32_t H = pn_funnel(h1, h0, (uint32_t)b), Lw = pn_funnel(l1, l0, (uint32_t)b);
+            const uint32_t eq = ~((H ^ rw.x) | (Lw ^ rw.y));
+            const uint32_t y = eq & (eq >> 1);
+            F |= y & (y >> 2);
+        }
+        const uint32_t firsts =
+            left >= 8 ? 0x11111111u : (0x11111111u & ((1u << (4 * left)) - 1u));
+        found += __builtin_popcount(F & firsts);
+        const int now = left < 8 ? left : 8;
+        letters += 32;
+        if (found >= need) return true;
+        if (found + (left - now) < need) return false;
+        A = B;
+        B = C;
+        C = Dn;
+        Dn = hl[2 * (blk + w + 4)];
+        rw = rwn;
+    }
+}

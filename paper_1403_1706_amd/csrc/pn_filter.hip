@@ -179,9 +179,11 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
                                       uint32_t avail, bool strict, Stage &sg) {
     const uint32_t hi = (uint32_t)(v >> 32);
     const uint32_t cls = hi >> 29;
-    const uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
+    uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
     const uint32_t o = hi & 0xffu;
     const uint32_t info = (uint32_t)v & 0xffu;
+    // the read's length - 1, stamped beside the rule byte, into the candidate
+    r |= ((uint32_t)v & 0xff00u) << (PN_CAND_LEN_SHIFT - 8);
     if ((info >> 3) & 1u) {
         // piece mode: a piece start whose q-gram and four letters after it
         // equal the text's
@@ -500,10 +502,11 @@ __global__ __launch_bounds__(256) void k_mask_runs(pn::RefQDev P, int q, uint32_
     }
 }
 
-// (compiled for 8 waves per SIMD: more waves hide more of the walk's load
-// latency than the few registers this spills cost)
+// (compiled for 7 waves per SIMD: more waves hide more of the walk's load
+// latency than the few registers this spills cost; 8 waves spill more than
+// they gain, 6 need no spill but hide less)
 template <typename TW, bool kPacked, bool kSub>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8))) void k_filter(
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(7))) void k_filter(
     PnRefDev ref, pn::RefQDev P, PnIndexDev ix, pn::Lists ls, pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBuf];
     __shared__ uint32_t wcnt[kWaves];
@@ -657,7 +660,8 @@ __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a
 
 // status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
 __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict__ kpr,
-                             uint8_t *__restrict__ rinfo, uint32_t *status, int plain) {
+                             uint8_t *__restrict__ rinfo, uint16_t *__restrict__ rstamp,
+                             uint32_t *status, int plain) {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < ix.n_reads) {
         const uint64_t off = ix.offsets[r];
@@ -708,6 +712,9 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
             const uint32_t need = run > q ? min(run - q, 4u) : 0u;
             rinfo[r] = (uint8_t)((keep << 7) | (front << 6) | need);
         }
+        // the word stamped into the read's O entries: the rule byte and the
+        // read's length - 1 (filtration hands it on in the candidate)
+        if (rstamp) rstamp[r] = (uint16_t)(rinfo[r] | (((n - 1u) & 0xffu) << 8));
     }
 }
 
@@ -841,8 +848,8 @@ __global__ __launch_bounds__(256) void k_lc_scatter(PnIndexDev ix, const uint8_t
 // copy each read's rule bits (keep flag << 7 | required extra run) into the
 // low byte of its O entries, so that the filter reads them with the entry
 __device__ __forceinline__ unsigned long long stamp(unsigned long long v,
-                                                    const uint8_t *__restrict__ rinfo) {
-    return (v & ~0xffull) | rinfo[(uint32_t)(v >> 40) & (PN_MAX_READS - 1)];
+                                                    const uint16_t *__restrict__ rstamp) {
+    return (v & ~0xffffull) | rstamp[(uint32_t)(v >> 40) & (PN_MAX_READS - 1)];
 }
 
 // One pass per thread: kStampPer pairs of entries loaded (16 bytes each,
@@ -852,7 +859,7 @@ __device__ __forceinline__ unsigned long long stamp(unsigned long long v,
 constexpr int kStampPer = 8;
 
 __global__ __launch_bounds__(256) void k_stamp_rules(unsigned long long *O, uint64_t n,
-                                                     const uint8_t *__restrict__ rinfo) {
+                                                     const uint16_t *__restrict__ rinfo) {
     ulonglong2 *O2 = (ulonglong2 *)O;
     const uint64_t n2 = n / 2;
     const uint64_t base = (uint64_t)blockIdx.x * (256 * kStampPer) + threadIdx.x;
@@ -956,10 +963,10 @@ void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st) {
 
 
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
-                       uint32_t *status, bool plain, hipStream_t st) {
+                       uint16_t *rstamp, uint32_t *status, bool plain, hipStream_t st) {
     if (!ix.n_reads) return;
     hipLaunchKernelGGL(k_read_rules, dim3((ix.n_reads + 255) / 256), dim3(256), 0, st, ix, kglob,
-                       kpr, rinfo, status, plain ? 1 : 0);
+                       kpr, rinfo, rstamp, status, plain ? 1 : 0);
 }
 
 void launch_mask_runs(const RefQDev &P, int q, uint32_t max_occ, uint32_t *bits, hipStream_t st) {
@@ -987,7 +994,7 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
         hipLaunchKernelGGL(k_lc_scatter<uint32_t>, grid, block, 0, st, ix, rinfo, side, cursors);
 }
 
-void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st) {
+void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint16_t *rinfo, hipStream_t st) {
     if (!n) return;
     const uint64_t blocks = (n / 2 + 256 * kStampPer - 1) / (256 * kStampPer) + 1;
     hipLaunchKernelGGL(k_stamp_rules, dim3((unsigned)blocks), dim3(256), 0, st, O, n, rinfo);

@@ -35,13 +35,19 @@
 #define PN_DBIAS 65536u
 #define PN_CLS_NONE 4u
 #define PN_CAND_NONE 0xffffffffu  // padding slot in the candidate array
-// Candidate word x: read id (bits 0-20) | PN_CAND_TAIL | strand << 31.
-// PN_CAND_TAIL asks verification's first pass to check the read's last rows
-// instead of its first ones (set for reads whose low-complexity q-grams lie
-// mostly in their first half, whose first rows would match along a repeat
-// run); either check only drops a candidate without a hit.
+// Candidate word x: read id (bits 0-20) | (read length - 1) << 21 (bits
+// 21-28) | PN_CAND_TAIL | strand << 31.  PN_CAND_TAIL asks verification's
+// first pass to check the read's last rows instead of its first ones (set
+// for reads whose low-complexity q-grams lie mostly in their first half,
+// whose first rows would match along a repeat run); either check only
+// drops a candidate without a hit.  The length travels in the candidate so
+// that verification need not gather the read's offsets.
 #define PN_CAND_TAIL 0x40000000u
-#define PN_CAND_READ 0x3fffffffu
+#define PN_CAND_READ 0x001fffffu
+#define PN_CAND_LEN_SHIFT 21
+__host__ __device__ inline int pn_cand_len(uint32_t x) {
+    return (int)((x >> PN_CAND_LEN_SHIFT) & 0xffu) + 1;
+}
 
 // Blocks for a kernel that walks n elements with a grid-stride loop.  A
 // dispatch covers fewer than 2^32 work-items (the packet's grid size is a
@@ -233,6 +239,10 @@ void launch_tab_flags(const uint32_t *Sp, uint64_t D, uint32_t min_len, uint32_t
 void launch_tab_build(const unsigned long long *O, const uint32_t *Sp, uint64_t D,
                       uint32_t min_len, const uint32_t *num, uint32_t n_tabs, uint32_t *tab_id,
                       uint32_t *list, uint32_t *tabs, hipStream_t st);
+// read lengths into candidate words made without them (pn_validate's
+// host candidates); a read of length 0 or over PN_MAX_READ_LEN makes the
+// candidate a padding slot
+void launch_cands_len(uint2 *cands, uint64_t n, const uint64_t *offsets, hipStream_t st);
 // the number of occurrences in slices of O longer than min_len, added to
 // *out (D: device word holding the number of slices)
 void launch_long_entries(const uint32_t *D, const uint32_t *Sp, uint32_t min_len,
@@ -279,8 +289,10 @@ struct FilterOut {
 // plain: every read gets rule byte 0x80 (keeps its low-complexity seeds, no
 // exact run required, no piece mode), for filtration of a masked position
 // set, where a pair may be the only one left of its alignment
+// rstamp (may be null): per read the rule byte | (length - 1) << 8, the
+// word k_stamp_rules writes into the low 16 bits of the read's O entries
 void launch_read_rules(const PnIndexDev &ix, int kglob, const uint8_t *kpr, uint8_t *rinfo,
-                       uint32_t *status, bool plain, hipStream_t st);
+                       uint16_t *rstamp, uint32_t *status, bool plain, hipStream_t st);
 // sizes of the 16 low-complexity q-grams' O slices (for sizing side lists)
 void launch_lc_sizes(const PnIndexDev &ix, uint32_t *sizes, hipStream_t st);
 // low-complexity occurrence lists restricted to reads that keep them
@@ -290,7 +302,7 @@ void launch_lc_side(const PnIndexDev &ix, const uint8_t *rinfo, unsigned long lo
                     const uint32_t *region, uint32_t *side_cls, uint32_t *scratch,
                     hipStream_t st);
 // write each read's rule byte into the low byte of its O entries
-void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint8_t *rinfo, hipStream_t st);
+void launch_stamp_rules(unsigned long long *O, uint64_t n, const uint16_t *rstamp, hipStream_t st);
 // the position set P of a reference for one q, sorted by q-gram.  Two
 // layouts: keys ((p << 1 | strand) << 2q) | q-gram with a 16-bit context
 // each (ctx), or, when (p << 1 | strand) fits in 54 - 2q bits, one packed
@@ -399,7 +411,9 @@ void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kg
                   unsigned long long *letters, hipStream_t st);
 // candidates in the C ABI's 16-byte layout (device) to verification words;
 // out-of-range ones become padding and set bit 3 of *status
-void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,
+// (the read lengths from `offsets` go into the candidate words)
+void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L,
+                     const uint64_t *offsets, uint2 *out,
                      uint32_t *status, hipStream_t st);
 
 // pn_scan.hip: concatenate the regions of a sharded list (8-byte entries)

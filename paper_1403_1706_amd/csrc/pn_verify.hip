@@ -107,7 +107,7 @@ __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix,
     const uint32_t r = c.x & PN_CAND_READ;
     const uint32_t s = c.x >> 31;
     x.tail = first && (c.x & PN_CAND_TAIL);
-    x.len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
+    x.len = pn_cand_len(c.x);
     x.k = kglob >= 0 ? kglob : (int)kpr[r];
     if (x.k > PN_MAX_K || x.len < 1 || x.len > PN_MAX_READ_LEN) return;
     x.ok = true;
@@ -211,14 +211,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
 // The count filter over a candidate list: candidates that may hold a hit
 // go to the survivor list (longc, one region per input region), which the
 // band pass then runs from row 0 to the end.
-// A count-filter candidate ready to run: the first three plane blocks and
-// the read's first word (the fourth block is loaded when it starts), fewer
-// registers than a verification candidate so that more waves fit.
+// A count-filter candidate ready to run: the H and L words of its first
+// four plane blocks and the read's first word (the validity words are
+// loaded only for a wave whose bands leave the reference), fewer registers
+// than a verification candidate so that more waves fit.
 struct CountCand {
     uint2 c;
     int len, k;  // k < 0: nothing to do
     int64_t lo;
-    uint4 A, B, C;
+    uint2 A, B, C, Dn;
     uint2 rw0;
 };
 
@@ -233,17 +234,18 @@ __device__ __forceinline__ void count_start(const PnRefDev &ref, const PnIndexDe
     x.k = -1;
     if (c.x == PN_CAND_NONE) return;
     const uint32_t r = c.x & PN_CAND_READ;
-    const int len = (int)(ix.offsets[r + 1] - ix.offsets[r]);
+    const int len = pn_cand_len(c.x);
     const int k = kglob >= 0 ? kglob : (int)kpr[r];
     if (k > PN_MAX_K || len < 1 || len > PN_MAX_READ_LEN) return;
     x.len = len;
     x.k = k;
     x.lo = (int64_t)c.y - (int64_t)PN_DBIAS - k;
-    const uint4 *pl = count_planes(ref, c);
+    const uint2 *hl = (const uint2 *)count_planes(ref, c);
     const uint64_t blk = (uint64_t)(x.lo + PN_PAD_POS) >> 5;
-    x.A = pl[blk];
-    x.B = pl[blk + 1];
-    x.C = pl[blk + 2];
+    x.A = hl[2 * blk];
+    x.B = hl[2 * (blk + 1)];
+    x.C = hl[2 * (blk + 2)];
+    x.Dn = hl[2 * (blk + 3)];
     x.rw0 = ix.rplanes[(uint64_t)r * PN_READ_WORDS];
 }
 
@@ -277,22 +279,18 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
         const uint64_t ci2 = base + 2 * stride + lane;
         c_after = ci2 < n ? cands[ci2] : none;
         const bool ok = cur.k >= 0;
-        // (wave-uniform) every band position inside the reference
-        const bool inside =
-            __all(!ok || (cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L));
         if (ok) {
-            const uint4 *pl = count_planes(ref, cur.c);
-            const uint2 *rp = ix.rplanes + (uint64_t)(cur.c.x & PN_CAND_READ) * PN_READ_WORDS;
-            PnBandHead hd;
-            hd.A = cur.A;
-            hd.B = cur.B;
-            hd.C = cur.C;
-            hd.Dn = pl[((uint64_t)(cur.lo + PN_PAD_POS) >> 5) + 3];
-            hd.rw0 = cur.rw0;
+            // a band that leaves the reference (a read at either end) is
+            // kept without counting: the band pass settles it
+            const bool inside = cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L;
             int lt = 0;
-            const bool keep =
-                inside ? pn_count_pieces<true>(hd, pl, rp, cur.len, cur.k, cur.lo, lt)
-                       : pn_count_pieces<false>(hd, pl, rp, cur.len, cur.k, cur.lo, lt);
+            bool keep = true;
+            if (inside) {
+                const uint2 *hl = (const uint2 *)count_planes(ref, cur.c);
+                const uint2 *rp = ix.rplanes + (uint64_t)(cur.c.x & PN_CAND_READ) * PN_READ_WORDS;
+                keep = pn_count_pieces_hl(cur.A, cur.B, cur.C, cur.Dn, cur.rw0, hl, rp, cur.len,
+                                          cur.k, cur.lo, lt);
+            }
             if (keep) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
             letters += (unsigned long long)lt;
         }
@@ -308,8 +306,16 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
 // reserved bytes, diagonal i64) to the verification's (read | strand << 31,
 // diagonal + PN_DBIAS) words.  A candidate whose read, strand or diagonal is
 // out of range becomes a padding slot and sets bit 3 of *status.
+// the length field of a candidate word for read r (false: no verifiable read)
+__device__ __forceinline__ bool cand_len_bits(const uint64_t *offsets, uint32_t r, uint32_t &bits) {
+    const uint64_t len = offsets[r + 1] - offsets[r];
+    bits = (uint32_t)((len - 1) & 0xffu) << PN_CAND_LEN_SHIFT;
+    return len >= 1 && len <= PN_MAX_READ_LEN;
+}
+
 __global__ __launch_bounds__(256) void k_cands_in(const uint4 *__restrict__ in, uint64_t n,
                                                   uint32_t n_reads, uint64_t L,
+                                                  const uint64_t *__restrict__ offsets,
                                                   uint2 *__restrict__ out, uint32_t *status) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -319,8 +325,23 @@ __global__ __launch_bounds__(256) void k_cands_in(const uint4 *__restrict__ in, 
     const bool ok = v.x < n_reads && strand <= 1u && d >= -(int64_t)PN_MAX_READ_LEN &&
                     d <= (int64_t)L;
     if (!ok) atomicOr(status, 8u);
-    out[i] = ok ? make_uint2(v.x | (strand << 31), (uint32_t)(d + (int64_t)PN_DBIAS))
-                : make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    uint32_t lb = 0;
+    const bool has_len = ok && cand_len_bits(offsets, v.x, lb);
+    out[i] = has_len ? make_uint2(v.x | lb | (strand << 31), (uint32_t)(d + (int64_t)PN_DBIAS))
+                     : make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+}
+
+__global__ __launch_bounds__(256) void k_cands_len(uint2 *__restrict__ c, uint64_t n,
+                                                   const uint64_t *__restrict__ offsets) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint2 v = c[i];
+        if (v.x == PN_CAND_NONE) continue;
+        uint32_t lb = 0;
+        c[i] = cand_len_bits(offsets, v.x & PN_CAND_READ, lb)
+                   ? make_uint2(v.x | lb, v.y)
+                   : make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    }
 }
 
 }  // namespace
@@ -357,11 +378,17 @@ void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kg
                        ix, in, kglob, kpr, surv, n_surv, letters);
 }
 
-void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L, uint2 *out,
-                     uint32_t *status, hipStream_t st) {
+void launch_cands_in(const void *in, uint64_t n, uint32_t n_reads, uint64_t L,
+                     const uint64_t *offsets, uint2 *out, uint32_t *status, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_cands_in, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       (const uint4 *)in, n, n_reads, L, out, status);
+                       (const uint4 *)in, n, n_reads, L, offsets, out, status);
+}
+
+void launch_cands_len(uint2 *cands, uint64_t n, const uint64_t *offsets, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_cands_len, dim3(pn_stride_blocks(n, 256)), dim3(256), 0, st, cands, n,
+                       offsets);
 }
 
 }  // namespace pn

@@ -84,6 +84,15 @@ extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, 
     const bool inside = d - k >= 0 && d - k + n + 2 * k < (int64_t)L;
     const bool keep = inside ? pn_count_pieces<true>(hd, pl.data(), rp.data(), n, k, d - k, letters)
                              : pn_count_pieces<false>(hd, pl.data(), rp.data(), n, k, d - k, letters);
+    if (inside) {
+        // the H/L-only form the kernel runs for bands inside the reference
+        const uint2 *hl = (const uint2 *)pl.data();
+        const uint64_t blk = (uint64_t)(d - k + PN_PAD_POS) >> 5;
+        int l2 = 0;
+        const bool k2 = pn_count_pieces_hl(hl[2 * blk], hl[2 * (blk + 1)], hl[2 * (blk + 2)],
+                                           hl[2 * (blk + 3)], rp[0], hl, rp.data(), n, k, d - k, l2);
+        if (k2 != keep || l2 != letters) return -2;
+    }
     return keep ? 1 : 0;
 }
 

@@ -123,7 +123,7 @@ def count(band):
         text = np.ascontiguousarray(text, np.uint8)
         read = np.ascontiguousarray(read, np.uint8)
         r = lib.count_host(text.ctypes.data, len(text), read.ctypes.data, len(read), int(d), int(k))
-        assert r in (0, 1)
+        assert r in (0, 1)  # (-2: the H/L-only form disagreed with the full one)
         return bool(r)
     return run
 

@@ -591,15 +591,23 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(7))) void k_
     if (lane == 0 && written) atomicAdd(stats + 3, written);
 }
 
-// The ranges set aside by k_filter, a wave per item: wave v of the grid
-// takes items v, v + (waves per region), ... of heavy region v % kShards and
-// walks each in wave-uniform steps of 64 occurrences (the same rules, the
-// same staging; a step adds at most 64 candidates, so flushing once 64 or
-// fewer slots are free keeps the stage from overflowing).
+// The ranges set aside by k_filter, 64 items per wave at a time: each lane
+// loads one item, a wave-wide prefix sum lays their entries end to end, and
+// the wave walks that sequence 64 entries per step, four steps' loads first
+// (an item is mostly a few dozen entries: one item per wave left most lanes
+// idle).  Lane e of a step finds its item from the count of items that start
+// at or before the step's first entry (a ballot) plus the starts inside the
+// step before it (a 64-bit mask built with one LDS atomic OR per start).
+// The same rules, the same staging; a step adds at most 64 candidates, so
+// flushing once 64 or fewer slots are free keeps the stage from
+// overflowing.
 __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls,
                                                      pn::FilterOut out) {
     __shared__ uint2 wbuf[kWaves][kWBufHeavy];
     __shared__ uint32_t wcnt[kWaves];
+    __shared__ uint4 s_item[kWaves][64][2];
+    __shared__ uint32_t s_pre[kWaves][64];
+    __shared__ unsigned long long s_mask[kWaves][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
@@ -610,44 +618,86 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
-    const uint64_t step = nw / pn::kShards;
-    uint64_t it = gw / pn::kShards;
-    uint4 n0 = make_uint4(0u, 0u, 0u, 0u), n1 = n0;  // the next item, loaded ahead
-    if (it < n) {
-        n0 = items[2 * it];
-        n1 = items[2 * it + 1];
-    }
-    for (; it < n; it += step) {
-        const uint4 h0 = n0, h1 = n1;
-        if (it + step < n) {
-            n0 = items[2 * (it + step)];
-            n1 = items[2 * (it + step) + 1];
+    const uint64_t step = (uint64_t)(nw / pn::kShards) * 64;
+    for (uint64_t ib = (uint64_t)(gw / pn::kShards) * 64; ib < n; ib += step) {
+        // this lane's item and the wave's exclusive prefix of their sizes
+        const uint64_t my = ib + (uint64_t)lane;
+        uint4 h0 = make_uint4(0u, 0u, 0u, 0u), h1 = h0;
+        if (my < n) {
+            h0 = items[2 * my];
+            h1 = items[2 * my + 1];
         }
-        const uint32_t fl = h0.y;
-        const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | h0.x);
-        const uint32_t idA = (fl >> 17) & 3u, idB = (fl >> 19) & 3u;
-        gu64 *srcA = idA == 1u ? (gu64 *)ls.side : (gu64 *)ix.O;
-        gu64 *srcB = idB == 1u ? (gu64 *)ls.side : idB == 2u ? (gu64 *)ls.laxO : (gu64 *)ix.O;
-        const bool strictA = (fl >> 21) & 1u;
-        const bool has = fl & 1u, lh = (fl >> 1) & 1u;
-        const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
-        const uint32_t s = (fl >> 16) & 1u;
-        const uint32_t la = h0.w - h0.z, total = la + (h1.y - h1.x);
-        // four steps of 64 occurrences: every load first, then the visits
+        const uint32_t tot = my < n ? (h0.w - h0.z) + (h1.y - h1.x) : 0u;
+        uint32_t incl = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const uint32_t start = incl - tot;
+        const uint32_t total = __shfl(incl, 63);
+        s_item[wave][lane][0] = h0;
+        s_item[wave][lane][1] = h1;
+        s_pre[wave][lane] = start;
+        __builtin_amdgcn_wave_barrier();
         for (uint32_t base = 0; base < total; base += 256) {
+            // for each of the four steps: which items start inside it
+            if (lane < 4) s_mask[wave][lane] = 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (tot > 0 && start > base && start < base + 256) {
+                const uint32_t rel = start - base;
+                atomicOr(&s_mask[wave][rel >> 6], 1ull << (rel & 63));
+            }
+            __builtin_amdgcn_wave_barrier();
             unsigned long long v[4];
+            uint32_t jj[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const uint32_t k = base + 64 * u + (uint32_t)lane;
-                v[u] = k < total ? (k < la ? srcA[h0.z + k] : srcB[h1.x + (k - la)]) : 0ull;
+                const uint32_t t0 = base + 64u * (uint32_t)u;
+                const uint32_t e = t0 + (uint32_t)lane;
+                // items starting at or before the step's first entry: a
+                // prefix of the lanes (sizes are positive up to the last item)
+                const uint32_t before =
+                    (uint32_t)__popcll(__ballot(tot > 0 && start <= t0));
+                const unsigned long long m = s_mask[wave][u];
+                const uint32_t j = before - 1u +
+                                   (uint32_t)__popcll(m & ((2ull << lane) - 1ull) & ~1ull);
+                jj[u] = j;
+                v[u] = 0ull;
+                if (e < total) {
+                    const uint4 a0 = s_item[wave][j][0], a1 = s_item[wave][j][1];
+                    const uint32_t k = e - s_pre[wave][j];
+                    const uint32_t la = a0.w - a0.z;
+                    const uint32_t fl = a0.y;
+                    const uint32_t idA = (fl >> 17) & 3u, idB = (fl >> 19) & 3u;
+                    gu64 *srcA = idA == 1u ? (gu64 *)ls.side : (gu64 *)ix.O;
+                    gu64 *srcB = idB == 1u ? (gu64 *)ls.side
+                                 : idB == 2u ? (gu64 *)ls.laxO
+                                             : (gu64 *)ix.O;
+                    v[u] = k < la ? srcA[a0.z + k] : srcB[a1.x + (k - la)];
+                }
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const uint32_t k = base + 64 * u + (uint32_t)lane;
-                if (k < total) visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < la, sg);
+                const uint32_t e = base + 64u * (uint32_t)u + (uint32_t)lane;
+                if (e < total) {
+                    const uint32_t j = jj[u];
+                    const uint4 a0 = s_item[wave][j][0];
+                    const uint32_t k = e - s_pre[wave][j];
+                    const uint32_t fl = a0.y;
+                    const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | a0.x);
+                    const bool strictA = (fl >> 21) & 1u;
+                    const bool has = fl & 1u, lh = (fl >> 1) & 1u;
+                    const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u,
+                                   N = (fl >> 8) & 0xffu;
+                    const uint32_t s = (fl >> 16) & 1u;
+                    visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < a0.w - a0.z, sg);
+                }
                 if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
             }
+            __builtin_amdgcn_wave_barrier();
         }
+        __builtin_amdgcn_wave_barrier();
     }
     pad_lane(sg);
     flush(sg, lane);

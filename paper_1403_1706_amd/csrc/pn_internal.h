@@ -361,9 +361,10 @@ struct Lists {
 // an index orders its slices when a notable share of its occurrences lie in
 // slices longer than kLongSlice (reads from repeat families); filtration
 // then searches every slice of it longer than kSearchMin (and the lax lists
-// cover those slices)
+// cover those slices); shorter slices are walked whole (16: two binary
+// searches cost more than walking a slice that short)
 constexpr uint32_t kLongSlice = 32;
-constexpr uint32_t kSearchMin = 0;
+constexpr uint32_t kSearchMin = 16;
 // the occurrence lists k_filter set aside (FilterOut::heavy)
 void launch_filter_heavy(const PnIndexDev &ix, const Lists &ls, FilterOut out, hipStream_t st);
 // the lax lists of the slots [0, n_slots) (count: one zeroed word, receives

@@ -216,6 +216,7 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
 // walked by their lane.
 constexpr uint32_t kItem = 1024;
 constexpr uint32_t kStrictHeavy = 4;
+constexpr uint32_t kLongItem = 128;  // k_filter_heavy walks items this long one at a time
 constexpr uint32_t kWalk = 4;  // entries a lane loads at a time
 
 // INDEXPAIR(g) and the occurrence ranges to visit for one (position,
@@ -339,15 +340,16 @@ __device__ __forceinline__ uint32_t visit_all(const Ranges &rg, int64_t p, uint3
     // a set-aside entry becomes one item per kItem occurrences (a wave walks
     // an item), so that no single item is long
     const uint32_t nitems = heavy ? (len + kItem - 1) / kItem : 0u;
-    uint32_t incl = nitems;  // inclusive prefix over the wave
     const int hl = threadIdx.x & 63;
+    // (most positions hand nothing on: the prefix is skipped then)
+    if (__ballot(heavy)) {
+        uint32_t incl = nitems;  // inclusive prefix over the wave
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d);
-        if (hl >= d) incl += y;
-    }
-    const uint32_t wtotal = __shfl(incl, 63);
-    if (wtotal) {
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d);
+            if (hl >= d) incl += y;
+        }
+        const uint32_t wtotal = __shfl(incl, 63);
         const uint32_t region = (blockIdx.x * kWaves + (threadIdx.x >> 6)) % pn::kShards;
         unsigned long long first = 0;
         if (hl == 0) first = atomicAdd(out.hsh.counts + region, (unsigned long long)wtotal);
@@ -591,7 +593,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(7))) void k_
     if (lane == 0 && written) atomicAdd(stats + 3, written);
 }
 
-// The ranges set aside by k_filter, 64 items per wave at a time: each lane
+// The ranges set aside by k_filter, each wave an even share of its region's
+// items, 64 of them at a time: each lane
 // loads one item, a wave-wide prefix sum lays their entries end to end, and
 // the wave walks that sequence 64 entries per step, four steps' loads first
 // (an item is mostly a few dozen entries: one item per wave left most lanes
@@ -608,6 +611,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
     __shared__ uint4 s_item[kWaves][64][2];
     __shared__ uint32_t s_pre[kWaves][64];
     __shared__ unsigned long long s_mask[kWaves][4];
+    __shared__ uint8_t s_owner[kWaves][256];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (threadIdx.x < kWaves) wcnt[threadIdx.x] = 0;
     __syncthreads();
@@ -618,16 +622,57 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
-    const uint64_t step = (uint64_t)(nw / pn::kShards) * 64;
-    for (uint64_t ib = (uint64_t)(gw / pn::kShards) * 64; ib < n; ib += step) {
+    // the region's items split evenly over its waves, 64 at a time
+    const uint64_t wpr = nw / pn::kShards;
+    const uint64_t chunk = (n + wpr - 1) / wpr;
+    const uint64_t i_lo = (uint64_t)(gw / pn::kShards) * chunk;
+    const uint64_t i_hi = min(n, i_lo + chunk);
+    for (uint64_t ib = i_lo; ib < i_hi; ib += 64) {
         // this lane's item and the wave's exclusive prefix of their sizes
         const uint64_t my = ib + (uint64_t)lane;
         uint4 h0 = make_uint4(0u, 0u, 0u, 0u), h1 = h0;
-        if (my < n) {
+        if (my < i_hi) {
             h0 = items[2 * my];
             h1 = items[2 * my + 1];
         }
-        const uint32_t tot = my < n ? (h0.w - h0.z) + (h1.y - h1.x) : 0u;
+        const uint32_t size = my < i_hi ? (h0.w - h0.z) + (h1.y - h1.x) : 0u;
+        // long items: walked one at a time by the whole wave, as they fill
+        // its lanes anyway
+        unsigned long long longs = __ballot(size >= kLongItem);
+        while (longs) {
+            const int j = __ffsll((long long)longs) - 1;
+            longs &= longs - 1;
+            const uint4 a0 = make_uint4(__shfl(h0.x, j), __shfl(h0.y, j), __shfl(h0.z, j),
+                                        __shfl(h0.w, j));
+            const uint32_t b0 = __shfl(h1.x, j), b1 = __shfl(h1.y, j);
+            const uint32_t fl = a0.y;
+            const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | a0.x);
+            const uint32_t idA = (fl >> 17) & 3u, idB = (fl >> 19) & 3u;
+            gu64 *srcA = idA == 1u ? (gu64 *)ls.side : (gu64 *)ix.O;
+            gu64 *srcB = idB == 1u ? (gu64 *)ls.side : idB == 2u ? (gu64 *)ls.laxO : (gu64 *)ix.O;
+            const bool strictA = (fl >> 21) & 1u;
+            const bool has = fl & 1u, lh = (fl >> 1) & 1u;
+            const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u, N = (fl >> 8) & 0xffu;
+            const uint32_t s = (fl >> 16) & 1u;
+            const uint32_t la = a0.w - a0.z, total = la + (b1 - b0);
+            for (uint32_t base = 0; base < total; base += 256) {
+                unsigned long long v[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t k = base + 64 * u + (uint32_t)lane;
+                    v[u] = k < total ? (k < la ? srcA[a0.z + k] : srcB[b0 + (k - la)]) : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t k = base + 64 * u + (uint32_t)lane;
+                    if (k < total)
+                        visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < la, sg);
+                    if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
+                }
+            }
+        }
+        // the short ones laid end to end
+        const uint32_t tot = size < kLongItem ? size : 0u;
         uint32_t incl = tot;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -636,6 +681,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
         }
         const uint32_t start = incl - tot;
         const uint32_t total = __shfl(incl, 63);
+        if (total == 0) continue;
         s_item[wave][lane][0] = h0;
         s_item[wave][lane][1] = h1;
         s_pre[wave][lane] = start;
@@ -647,23 +693,31 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
             if (tot > 0 && start > base && start < base + 256) {
                 const uint32_t rel = start - base;
                 atomicOr(&s_mask[wave][rel >> 6], 1ull << (rel & 63));
+                s_owner[wave][rel] = (uint8_t)lane;
             }
             __builtin_amdgcn_wave_barrier();
             unsigned long long v[4];
-            uint32_t jj[4];
+            uint32_t px[4], pf[4];
+            bool st[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t t0 = base + 64u * (uint32_t)u;
                 const uint32_t e = t0 + (uint32_t)lane;
-                // items starting at or before the step's first entry: a
-                // prefix of the lanes (sizes are positive up to the last item)
-                const uint32_t before =
-                    (uint32_t)__popcll(__ballot(tot > 0 && start <= t0));
-                const unsigned long long m = s_mask[wave][u];
-                const uint32_t j = before - 1u +
-                                   (uint32_t)__popcll(m & ((2ull << lane) - 1ull) & ~1ull);
-                jj[u] = j;
+                // the item of entry e: the last (non-empty) item starting at
+                // or before it; the one holding t0 is the highest lane whose
+                // item starts at or before t0, later starts inside the step
+                // are marked in the mask with their lanes in s_owner
+                const unsigned long long at0 = __ballot(tot > 0 && start <= t0);
+                const uint32_t j0 = 63u - (uint32_t)__clzll(at0 | 1ull);
+                const unsigned long long mm =
+                    s_mask[wave][u] & ((2ull << lane) - 1ull) & ~1ull;
+                const uint32_t j =
+                    mm ? (uint32_t)s_owner[wave][64u * (uint32_t)u +
+                                                 (63u - (uint32_t)__clzll(mm))]
+                       : j0;
                 v[u] = 0ull;
+                px[u] = pf[u] = 0u;
+                st[u] = false;
                 if (e < total) {
                     const uint4 a0 = s_item[wave][j][0], a1 = s_item[wave][j][1];
                     const uint32_t k = e - s_pre[wave][j];
@@ -675,23 +729,22 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
                                  : idB == 2u ? (gu64 *)ls.laxO
                                              : (gu64 *)ix.O;
                     v[u] = k < la ? srcA[a0.z + k] : srcB[a1.x + (k - la)];
+                    px[u] = a0.x;
+                    pf[u] = fl;
+                    st[u] = ((fl >> 21) & 1u) && k < la;
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t e = base + 64u * (uint32_t)u + (uint32_t)lane;
                 if (e < total) {
-                    const uint32_t j = jj[u];
-                    const uint4 a0 = s_item[wave][j][0];
-                    const uint32_t k = e - s_pre[wave][j];
-                    const uint32_t fl = a0.y;
-                    const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | a0.x);
-                    const bool strictA = (fl >> 21) & 1u;
+                    const uint32_t fl = pf[u];
+                    const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | px[u]);
                     const bool has = fl & 1u, lh = (fl >> 1) & 1u;
                     const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u,
                                    N = (fl >> 8) & 0xffu;
                     const uint32_t s = (fl >> 16) & 1u;
-                    visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < a0.w - a0.z, sg);
+                    visit(v[u], p, s, has, prev, lh, N, avail, st[u], sg);
                 }
                 if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
             }

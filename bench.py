@@ -132,6 +132,68 @@ def large_q_run(pn, steps):
     return res
 
 
+def batching_leg(pn, steps):
+    """Batching (a mixed-length read set mapped as one batch) against plain
+    fixed-size batches in arrival order: 2 M reads of 50-250 bp (k =
+    ceil(5% n)) against the 100 Mbp repeat reference, one index and one
+    mapping for the whole set versus 16 batches of 2^17 reads, each indexed
+    and mapped on its own (every mapping scans the whole position set)."""
+    import numpy as np
+    import torch
+    from paper_1403_1706_amd import synth
+    w = synth.make("mixed")
+    dev = torch.device("cuda:0")
+    ctx = pn.pn_ctx_create(0)
+    ref = pn.pn_ref_load(ctx, w.ref)
+    q, wbits = 12, 64
+    pn.pn_ref_prepare(ref, q)
+    d_reads = torch.frombuffer(bytearray(w.reads), dtype=torch.uint8).to(dev)
+    d_offs = torch.from_numpy(w.offsets.astype(np.int64)).to(dev)
+    d_k = torch.from_numpy(w.k_per_read.copy()).to(dev)
+    out = torch.empty(12 * 16 * w.n_reads, dtype=torch.uint8, device=dev)
+    parts = []
+    size = 1 << 17
+    for a in range(0, w.n_reads, size):
+        b = min(w.n_reads, a + size)
+        lo, hi = int(w.offsets[a]), int(w.offsets[b])
+        parts.append((d_reads[lo:hi], torch.from_numpy((w.offsets[a:b + 1] - lo).astype(np.int64)).to(dev),
+                      d_k[a:b]))
+
+    def one(dr, do, dk, o):
+        idx = pn.pn_index_build_dev(ctx, dr, do, q, wbits)
+        try:
+            return pn.pn_map_dev(ctx, ref, idx, -1, o, pn.PN_ALL_HITS, d_k=dk)
+        finally:
+            pn.pn_index_free(idx)
+
+    def batched():
+        return one(d_reads, d_offs, d_k, out)
+
+    def plain():
+        return sum(one(dr, do, dk, out) for dr, do, dk in parts)
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            n = fn()
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) * 1000.0 / steps, int(n))
+    pn.pn_ref_free(ref)
+    pn.pn_ctx_destroy(ctx)
+    out_line = {"workload": WORKLOADS["mixed"], "q": q, "w": wbits, "steps": steps,
+                "batched_ms": res["batched"][0], "batched_reads_per_s": w.n_reads / res["batched"][0] * 1e3,
+                "plain_batches": len(parts), "plain_batch_reads": size,
+                "plain_ms": res["plain"][0], "plain_reads_per_s": w.n_reads / res["plain"][0] * 1e3,
+                "speedup": res["plain"][0] / res["batched"][0],
+                "same_hit_count": res["batched"][1] == res["plain"][1]}
+    log(f"batching: one batch {res['batched'][0]:.1f} ms, {len(parts)} batches of {size} "
+        f"{res['plain'][0]:.1f} ms ({out_line['speedup']:.2f}x)")
+    return out_line
+
+
 def serving_run(pn, ctx, ref, ref_ascii, q, args):
     """Requests shaped like the serving workload (1k-200k reads log-uniform,
     75-250 bp, 2-5 % error, all hits or best stratum, Poisson arrivals)
@@ -343,6 +405,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--no-large-q", action="store_true")
+    ap.add_argument("--no-batching-leg", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="mixed-length batch with autotuned q/w vs per-length launches")
     ap.add_argument("--copy-kernel", action="store_true",
@@ -580,6 +643,10 @@ def main():
     if not args.no_large_q:
         large_q = large_q_run(pn, args.steps)
 
+    batching = None
+    if not args.no_batching_leg:
+        batching = batching_leg(pn, max(1, min(args.steps, 3)))
+
     serving = None
     if not args.no_serve:
         serving = serving_run(pn, ctx, ref, w.ref, w.q, args)
@@ -613,6 +680,7 @@ def main():
         "serving": serving,
         "align": align,
         "large_q": large_q,
+        "batching": batching,
         "hits": n_hits,
         "mapped_fraction": mapped,
         "stage_ms": stage_ms,

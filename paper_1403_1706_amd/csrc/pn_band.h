@@ -235,6 +235,29 @@ __host__ __device__ __forceinline__ bool pn_count_pieces(const PnBandHead &hd, c
     }
 }
 
+// The pieces of one 32-letter read word (plane words rw) found on some
+// diagonal of the band, at each piece's first bit, for a band inside the
+// reference: A, B, C are the H and L words of the word's plane blocks
+// (letters from lo + 32 w on, phase ph inside block A), W = 2k + 1.
+__host__ __device__ __forceinline__ uint32_t pn_count_word_hl(uint2 A, uint2 B, uint2 C, uint2 rw,
+                                                              uint32_t ph, int W) {
+    const uint32_t h0 = pn_funnel(B.x, A.x, ph), h1 = pn_funnel(C.x, B.x, ph);
+    const uint32_t l0 = pn_funnel(B.y, A.y, ph), l1 = pn_funnel(C.y, B.y, ph);
+    uint32_t F = 0;
+    for (int b = 0; b < W; b++) {
+        const uint32_t H = pn_funnel(h1, h0, (uint32_t)b), Lw = pn_funnel(l1, l0, (uint32_t)b);
+        const uint32_t eq = ~((H ^ rw.x) | (Lw ^ rw.y));
+        const uint32_t y = eq & (eq >> 1);
+        F |= y & (y >> 2);
+    }
+    return F;
+}
+
+// the first bits of the pieces of a word that has `left` pieces from it on
+__host__ __device__ __forceinline__ uint32_t pn_piece_firsts(int left) {
+    return left >= 8 ? 0x11111111u : (0x11111111u & ((1u << (4 * left)) - 1u));
+}
+
 // The same count for a band that lies inside the reference, from the H and
 // L words of the plane blocks only (V is all ones there): `hl` is the
 // planes read as uint2 (block i's H, L at hl[2 i]), A..Dn the blocks
@@ -257,18 +280,8 @@ __host__ __device__ __forceinline__ bool pn_count_pieces_hl(uint2 A, uint2 B, ui
     for (int w = 0;; w++) {
         const int left = m - 8 * w;
         const uint2 rwn = left > 8 ? rp[w + 1] : rw;
-        const uint32_t h0 = pn_funnel(B.x, A.x, ph), h1 = pn_funnel(C.x, B.x, ph);
-        const uint32_t l0 = pn_funnel(B.y, A.y, ph), l1 = pn_funnel(C.y, B.y, ph);
-        uint32_t F = 0;
-        for (int b = 0; b < W; b++) {
-            const uint32_t H = pn_funnel(h1, h0, (uint32_t)b), Lw = pn_funnel(l1, l0, (uint32_t)b);
-            const uint32_t eq = ~((H ^ rw.x) | (Lw ^ rw.y));
-            const uint32_t y = eq & (eq >> 1);
-            F |= y & (y >> 2);
-        }
-        const uint32_t firsts =
-            left >= 8 ? 0x11111111u : (0x11111111u & ((1u << (4 * left)) - 1u));
-        found += __builtin_popcount(F & firsts);
+        const uint32_t F = pn_count_word_hl(A, B, C, rw, ph, W);
+        found += __builtin_popcount(F & pn_piece_firsts(left));
         const int now = left < 8 ? left : 8;
         letters += 32;
         if (found >= need) return true;

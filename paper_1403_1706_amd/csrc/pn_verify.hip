@@ -249,6 +249,13 @@ __device__ __forceinline__ void count_start(const PnRefDev &ref, const PnIndexDe
     x.rw0 = ix.rplanes[(uint64_t)r * PN_READ_WORDS];
 }
 
+// The count filter, one read word per lane and step: a lane whose candidate
+// is decided takes its next one at the following step instead of waiting
+// for the wave's slowest candidate.  Each lane keeps a candidate in
+// progress, the next one with its first memory words already loaded, and
+// the candidate word after that (two steps of prefetch, so that its loads
+// have a step to land).  A wave takes an even share of its region's
+// candidates and hands them out from a wave-wide cursor.
 __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix, pn::VerifyIn in,
                                                     int kglob, const uint8_t *__restrict__ kpr,
                                                     uint2 *longc, unsigned long long *n_long,
@@ -264,37 +271,100 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
               n_long + rin, in.region_cap};
     const uint2 *cands = in.cands + (uint64_t)rin * in.region_cap;
     const uint64_t n = min((uint64_t)in.counts[rin], in.region_cap);
-    const uint64_t per = gridDim.x / in.regions;
-    const uint64_t stride = per * kThreads;
-    const uint2 none = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    const uint64_t wpr = (uint64_t)(gridDim.x / in.regions) * kWaves;  // waves of this region
+    const uint64_t wr = (uint64_t)(blockIdx.x / in.regions) * kWaves + (uint64_t)wv;
+    const uint64_t chunk = (n + wpr - 1) / wpr;
+    const uint64_t hi = min(n, wr * chunk + chunk);
+    uint64_t cursor = min(n, wr * chunk);  // (wave-uniform) next candidate to hand out
     unsigned long long letters = 0;
-    uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64;
-    uint2 c_next = base + lane < n ? cands[base + lane] : none;
-    uint2 c_after = base + stride + lane < n ? cands[base + stride + lane] : none;
-    CountCand cur;
-    count_start(ref, ix, kglob, kpr, c_next, cur);
-    for (; base < n; base += stride) {
-        CountCand nxt;
-        count_start(ref, ix, kglob, kpr, c_after, nxt);
-        const uint64_t ci2 = base + 2 * stride + lane;
-        c_after = ci2 < n ? cands[ci2] : none;
-        const bool ok = cur.k >= 0;
-        if (ok) {
-            // a band that leaves the reference (a read at either end) is
-            // kept without counting: the band pass settles it
-            const bool inside = cur.lo >= 0 && cur.lo + cur.len + 2 * cur.k < (int64_t)ref.L;
-            int lt = 0;
-            bool keep = true;
-            if (inside) {
-                const uint2 *hl = (const uint2 *)count_planes(ref, cur.c);
-                const uint2 *rp = ix.rplanes + (uint64_t)(cur.c.x & PN_CAND_READ) * PN_READ_WORDS;
-                keep = pn_count_pieces_hl(cur.A, cur.B, cur.C, cur.Dn, cur.rw0, hl, rp, cur.len,
-                                          cur.k, cur.lo, lt);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // the candidate word after the next candidate
+    bool has_cw = false;
+    uint2 cw = make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+    // the next candidate, its first words loaded
+    bool has_nxt = false;
+    CountCand nxt;
+    nxt.k = -1;
+    // the candidate in progress
+    bool has_cur = false;
+    uint2 c = make_uint2(0u, 0u);
+    uint2 A = c, B = c, C = c, Dn = c, rw = c;
+    uint64_t blk = 0;
+    uint32_t ph = 0;
+    int W = 1, need = 0, found = 0, left = 0, w = 0;
+    for (;;) {
+        // 1. a lane without a candidate in progress takes the next one
+        if (!has_cur && has_nxt) {
+            has_nxt = false;
+            if (nxt.k >= 0) {
+                const int m = nxt.len / kPnPiece;
+                const bool inside =
+                    nxt.lo >= 0 && nxt.lo + nxt.len + 2 * nxt.k < (int64_t)ref.L;
+                if (m - nxt.k <= 0 || !inside) {
+                    // nothing to count (too short to drop any, or a band that
+                    // crosses a reference end): the band pass settles it
+                    lng.push(((unsigned long long)nxt.c.y << 32) | nxt.c.x);
+                } else {
+                    has_cur = true;
+                    c = nxt.c;
+                    A = nxt.A;
+                    B = nxt.B;
+                    C = nxt.C;
+                    Dn = nxt.Dn;
+                    rw = nxt.rw0;
+                    const uint64_t tp = (uint64_t)(nxt.lo + PN_PAD_POS);
+                    blk = tp >> 5;
+                    ph = (uint32_t)(tp & 31);
+                    W = 2 * nxt.k + 1;
+                    need = m - nxt.k;
+                    left = m;
+                    found = 0;
+                    w = 0;
+                }
             }
-            if (keep) lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
-            letters += (unsigned long long)lt;
         }
-        cur = nxt;
+        // 2. a lane without a next candidate starts one from its candidate
+        //    word, and lanes without a candidate word take new ones
+        if (!has_nxt && has_cw) {
+            count_start(ref, ix, kglob, kpr, cw, nxt);
+            has_nxt = true;
+            has_cw = false;
+        }
+        const bool want = !has_cw && cursor < hi;
+        const unsigned long long wm = __ballot(want);
+        if (want) {
+            const uint64_t idx = cursor + (uint64_t)__popcll(wm & below);
+            if (idx < hi) {
+                cw = cands[idx];
+                has_cw = true;
+            }
+        }
+        cursor = min(hi, cursor + (uint64_t)__popcll(wm));
+        if (!__any(has_cur || has_nxt || has_cw)) break;
+        // 3. one read word of the candidate in progress
+        if (has_cur) {
+            const uint32_t F = pn_count_word_hl(A, B, C, rw, ph, W);
+            found += __popc(F & pn_piece_firsts(left));
+            const int now = left < 8 ? left : 8;
+            letters += 32;
+            if (found >= need) {
+                lng.push(((unsigned long long)c.y << 32) | c.x);
+                has_cur = false;
+            } else if (found + (left - now) < need) {
+                has_cur = false;
+            } else {
+                // the next word: its read plane word and one more text block
+                const uint2 *hl = (const uint2 *)count_planes(ref, c);
+                const uint2 *rp = ix.rplanes + (uint64_t)(c.x & PN_CAND_READ) * PN_READ_WORDS;
+                rw = rp[w + 1];
+                A = B;
+                B = C;
+                C = Dn;
+                Dn = hl[2 * (blk + (uint64_t)w + 4)];
+                left -= 8;
+                w++;
+            }
+        }
         if (*lng.cnt >= kStage / 2) lng.flush(lane);
     }
     lng.flush(lane);

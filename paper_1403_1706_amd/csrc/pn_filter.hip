@@ -58,9 +58,14 @@ constexpr int kT = pn::kFilterThreads;
 constexpr int kPPT = pn::kFilterPPT;
 constexpr int kWaves = kT / 64;
 constexpr int kWBuf = 256;        // staged candidates per wave (k_filter)
-constexpr int kWBufHeavy = 512;   // the same in k_filter_heavy, which flushes at
-                                  // kWBufHeavy - 64: fewer, longer flushes (each
-                                  // one's stores hold up the wave's next loads)
+// staged candidates per wave in k_filter_heavy, which flushes once 64 or
+// fewer slots are free: fewer, longer flushes (each one's stores and its
+// output-slot atomic hold up the wave).  An ordered index (reads from
+// repeat families: billions of candidates) takes 1024, which beat 512
+// although it halves the blocks per CU (1536 did not); otherwise 512,
+// which keeps more waves for the long lists of a plain index.
+constexpr int kWBufHeavy = 512;
+constexpr int kWBufHeavyOrdered = 1024;
 
 // 64 bits of packed reference starting at signed base position B (base B+t
 // in bits 63-2t .. 62-2t); packed[-1] and 3 words past the end are readable
@@ -606,7 +611,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(7))) void k_
 // overflowing.
 __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls,
                                                      pn::FilterOut out) {
-    __shared__ uint2 wbuf[kWaves][kWBufHeavy];
+    extern __shared__ uint2 wbuf_dyn[];  // kWaves stages of `cap` entries
+    const uint32_t cap = ix.after_sorted ? kWBufHeavyOrdered : kWBufHeavy;
     __shared__ uint32_t wcnt[kWaves];
     __shared__ uint4 s_item[kWaves][64][2];
     __shared__ uint32_t s_pre[kWaves][64];
@@ -617,8 +623,8 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
     __syncthreads();
     const uint32_t gw = blockIdx.x * kWaves + wave;  // this wave in the grid
     const uint32_t nw = gridDim.x * kWaves;
-    Stage sg{(lds_u64 *)wbuf[wave], &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
-             gw % pn::kShards, 0u, 0ull, 0u, 0u, (uint32_t)kWBufHeavy};
+    Stage sg{(lds_u64 *)(wbuf_dyn + (uint64_t)wave * cap), &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
+             gw % pn::kShards, 0u, 0ull, 0u, 0u, cap};
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
@@ -667,7 +673,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
                     const uint32_t k = base + 64 * u + (uint32_t)lane;
                     if (k < total)
                         visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < la, sg);
-                    if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
+                    if (*sg.cnt >= cap - 64) flush(sg, lane);
                 }
             }
         }
@@ -746,7 +752,7 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
                     const uint32_t s = (fl >> 16) & 1u;
                     visit(v[u], p, s, has, prev, lh, N, avail, st[u], sg);
                 }
-                if (*sg.cnt >= kWBufHeavy - 64) flush(sg, lane);
+                if (*sg.cnt >= cap - 64) flush(sg, lane);
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -1145,7 +1151,9 @@ void launch_filter(const PnRefDev &ref, const RefQDev &P, const PnIndexDev &ix, 
 
 void launch_filter_heavy(const PnIndexDev &ix, const Lists &ls, FilterOut out, hipStream_t st) {
     if (!ix.n_reads) return;
-    hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), 0, st, ix, ls, out);
+    const size_t lds = (size_t)kWaves * (ix.after_sorted ? kWBufHeavyOrdered : kWBufHeavy) *
+                       sizeof(uint2);
+    hipLaunchKernelGGL(k_filter_heavy, dim3(128 * pn::kShards), dim3(kT), lds, st, ix, ls, out);
 }
 
 void launch_lax_lists(const PnIndexDev &ix, uint64_t n_slots, uint32_t min_len, uint2 *lax,

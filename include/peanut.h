@@ -40,7 +40,9 @@
  *  - Limits: reference length L < 2^32 - 2^16; reads per index < 2^21;
  *    read length <= 256; 1 <= q <= 16 (q = 16 with a reference of at most
  *    2^31 - 1 letters: a position-set key holds the position beside the
- *    32-bit q-gram); w in {32, 64}; 0 <= k_r <= 15.
+ *    32-bit q-gram); w in {32, 64}; 0 <= k_r <= 31 (a band of 2 k_r + 1 <= 63
+ *    diagonals around a candidate's diagonal, Section 3.3; bands of up to
+ *    31 diagonals run in 32-bit words, wider ones in a 64-bit pass).
  */
 #ifndef PEANUT_H
 #define PEANUT_H
@@ -254,7 +256,7 @@ int pn_index_export(const pn_index *idx, void *I, uint32_t *S, uint32_t *S_prime
 /* Map the indexed reads against both strands of `ref`.  k >= 0 applies to
  * every read; k < 0 takes k_per_read[r] (host array for pn_map, device
  * array for pn_map_dev).  Hits are sorted by (read_id, strand, end_pos).
- * PN_ELEMMA if some read has (k_r + 1) * q > n_r; PN_EINVAL if k_r > 15.
+ * PN_ELEMMA if some read has (k_r + 1) * q > n_r; PN_EINVAL if k_r > 31.
  * pn_map returns a library-allocated host array (free with pn_hits_free).
  * pn_map_dev writes at most `capacity` hits to device `d_hits`, stores the
  * total in *n_hits (host) and returns PN_ETRUNC if it exceeded capacity. */
@@ -298,7 +300,7 @@ int pn_validate(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_ca
  * backwards from a hit's end to find its start; Section 3.4 makes the
  * alignment in postprocessing).  hits: n_hits records as pn_map returns
  * them, against `ref` and the reads of `idx` (read_id < n_reads, strand 0
- * or 1, end_pos < L, errors <= PN_MAX_K: the hit's exact error count).  For
+ * or 1, end_pos < L, errors <= 31: the hit's exact error count).  For
  * each hit h, in host arrays of n_hits entries:
  *   starts[h]  first aligned text position, in the strand's own
  *              coordinates (the hit covers [start, end_pos]); of all
@@ -387,7 +389,7 @@ int pn_autotune(pn_ctx *ctx, const pn_ref *ref, const char *d_reads, const uint6
  * k ranges and mode: a line for this key is used; without one, pn_autotune
  * picks (q, w) on a sample of the first sub-batch and a line is appended
  * (a cache that cannot be written is not an error).  PN_EINVAL for a read
- * shorter than 1 or longer than 256, k_r > 15 or decreasing offsets;
+ * shorter than 1 or longer than 256, k_r > 31 or decreasing offsets;
  * PN_ELEMMA if no q >= 1 satisfies the lemma; the hit array is freed with
  * pn_hits_free. */
 int pn_map_batched(pn_ctx *ctx, const pn_ref *ref, const char *reads, const uint64_t *offsets,
@@ -438,7 +440,7 @@ int pn_server_create(pn_ctx *ctx, const pn_ref *ref, const pn_server_config *cfg
 /* Queue a request: reads[offsets[i] .. offsets[i+1]) for i < n_reads
  * (host memory, copied before return), error budget k >= 0 for all reads
  * or k < 0 and k_per_read[i] (host).  Checked here: letters ACGT (either
- * case), 1 <= n_r <= 256, k_r <= 15, (k_r + 1) q <= n_r; PN_EALPHABET /
+ * case), 1 <= n_r <= 256, k_r <= 31, (k_r + 1) q <= n_r; PN_EALPHABET /
  * PN_EINVAL / PN_ELEMMA / PN_EBUDGET.  *ticket identifies the request. */
 int pn_server_submit(pn_server *srv, const char *reads, const uint64_t *offsets, uint32_t n_reads,
                      int k, const uint8_t *k_per_read, pn_mode mode, uint64_t *ticket);

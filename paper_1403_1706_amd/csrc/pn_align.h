@@ -33,11 +33,14 @@
 
 // One hit, error count K, read length n (its reverse complement's plane
 // words rp), end e on a strand whose other strand's planes are pl (text
-// length L).  bp[(i - 1) * bstride] receives row i's op codes (2 bits per
-// band cell: 0 '=', 1 'X', 2 'I', 3 'D').  Writes *start and *err (0xff and
+// length L).  Row i's op codes (2 bits per band cell: 0 '=', 1 'X', 2 'I',
+// 3 'D'; cell b in bits 2 (b mod 32) of word b / 32) go to
+// bp[((i - 1) * NW + b / 32) * bstride], NW = pn_align_row_words(K).  Writes *start and *err (0xff and
 // start 0 when no alignment of K errors ends at e) and, with want_ops, the
 // operations into o (at most stride of them; o may be null) and returns
 // their number (0 without want_ops).
+__host__ __device__ constexpr int pn_align_row_words(int K) { return (2 * (2 * K + 1) + 63) / 64; }
+
 template <int K>
 __host__ __device__ inline int pn_align_one(const uint4 *pl, const uint2 *rp, int n, int64_t e,
                                             uint64_t L, unsigned long long *bp, uint64_t bstride,
@@ -45,6 +48,7 @@ __host__ __device__ inline int pn_align_one(const uint4 *pl, const uint2 *rp, in
                                             uint32_t *start, uint8_t *err) {
     constexpr int W = 2 * K + 1;
     constexpr int C = K + 1;  // saturation value
+    constexpr int NW = pn_align_row_words(K);
     // other-strand position of cell (i, b): p0 + i + b
     const int64_t p0 = (int64_t)L - 2 - e - K;
     int Fp[W], F[W];
@@ -55,13 +59,22 @@ __host__ __device__ inline int pn_align_one(const uint4 *pl, const uint2 *rp, in
         const uint64_t blk = tp >> 5;
         const uint32_t ph = (uint32_t)(tp & 31);
         const uint4 A = pl[blk], B = pl[blk + 1];
-        const uint32_t H = pn_funnel(B.x, A.x, ph), Lw = pn_funnel(B.y, A.y, ph),
-                       V = pn_funnel(B.z, A.z, ph);
+        // the W text letters of the row (a second word for W > 32)
+        uint64_t H = pn_funnel(B.x, A.x, ph), Lw = pn_funnel(B.y, A.y, ph),
+                 V = pn_funnel(B.z, A.z, ph);
+        if (W > 32) {
+            const uint4 Cb = pl[blk + 2];
+            H |= (uint64_t)pn_funnel(Cb.x, B.x, ph) << 32;
+            Lw |= (uint64_t)pn_funnel(Cb.y, B.y, ph) << 32;
+            V |= (uint64_t)pn_funnel(Cb.z, B.z, ph) << 32;
+        }
         const uint2 rw = rp[(i - 1) >> 5];
         const uint32_t sh = (uint32_t)((i - 1) & 31);
-        const uint32_t xh = 0u - ((rw.x >> sh) & 1u), xl = 0u - ((rw.y >> sh) & 1u);
-        const uint32_t eq = ~((H ^ xh) | (Lw ^ xl)) & V;
-        unsigned long long row = 0;
+        const uint64_t xh = 0ull - ((rw.x >> sh) & 1u), xl = 0ull - ((rw.y >> sh) & 1u);
+        const uint64_t eq = ~((H ^ xh) | (Lw ^ xl)) & V;
+        unsigned long long row[NW];
+#pragma unroll
+        for (int q = 0; q < NW; q++) row[q] = 0;
 #pragma unroll
         for (int b = 0; b < W; b++) {
             const int j = i - K + b;
@@ -82,9 +95,10 @@ __host__ __device__ inline int pn_align_one(const uint4 *pl, const uint2 *rp, in
                 val = m < C ? m : C;
             }
             F[b] = val;
-            row |= (unsigned long long)op << (2 * b);
+            row[b >> 5] |= (unsigned long long)op << (2 * (b & 31));
         }
-        bp[(uint64_t)(i - 1) * bstride] = row;
+#pragma unroll
+        for (int q = 0; q < NW; q++) bp[((uint64_t)(i - 1) * NW + q) * bstride] = row[q];
 #pragma unroll
         for (int b = 0; b < W; b++) Fp[b] = F[b];
     }
@@ -109,7 +123,10 @@ __host__ __device__ inline int pn_align_one(const uint4 *pl, const uint2 *rp, in
     // the walk from (n, best) back to (0, 0)
     int i = n, b = best, m = 0;
     while (i > 0 || i - K + b > 0) {
-        const int op = i == 0 ? 3 : (int)((bp[(uint64_t)(i - 1) * bstride] >> (2 * b)) & 3u);
+        const int op =
+            i == 0 ? 3
+                   : (int)((bp[((uint64_t)(i - 1) * NW + (b >> 5)) * bstride] >> (2 * (b & 31))) &
+                           3u);
         if (o && (uint32_t)m < stride) o[m] = (uint8_t)op;
         m++;
         if (op <= 1) {

@@ -8,7 +8,8 @@ constexpr int kAlignThreads = 64;
 
 // The launch covers the hits of one error count K.  hw: the chunk's hit
 // records (3 words each: read, end, strand | errors << 8); perm: the
-// chunk-local indices of this launch's hits; bp: cnt words per read row.
+// chunk-local indices of this launch's hits; bp: cnt words per op-code word
+// of a row (pn_align_row_words(K) of them per row).
 template <int K>
 __global__ __launch_bounds__(kAlignThreads) void k_align(PnRefDev ref, PnIndexDev ix,
                                                          const uint32_t *__restrict__ hw,
@@ -50,7 +51,7 @@ void launch_k(const PnRefDev &ref, const PnIndexDev &ix, const uint32_t *hw, con
 
 namespace pn {
 
-static_assert(PN_MAX_K == 15, "one instance per error count 0 .. PN_MAX_K");
+static_assert(PN_MAX_K == 31, "one instance per error count 0 .. PN_MAX_K");
 
 void launch_align(const PnRefDev &ref, const PnIndexDev &ix, int v, const uint32_t *hw,
                   const uint32_t *perm, uint32_t cnt, unsigned long long *bp, uint32_t *starts,
@@ -63,6 +64,10 @@ void launch_align(const PnRefDev &ref, const PnIndexDev &ix, int v, const uint32
         PN_ALIGN_CASE(4) PN_ALIGN_CASE(5) PN_ALIGN_CASE(6) PN_ALIGN_CASE(7)
         PN_ALIGN_CASE(8) PN_ALIGN_CASE(9) PN_ALIGN_CASE(10) PN_ALIGN_CASE(11)
         PN_ALIGN_CASE(12) PN_ALIGN_CASE(13) PN_ALIGN_CASE(14) PN_ALIGN_CASE(15)
+        PN_ALIGN_CASE(16) PN_ALIGN_CASE(17) PN_ALIGN_CASE(18) PN_ALIGN_CASE(19)
+        PN_ALIGN_CASE(20) PN_ALIGN_CASE(21) PN_ALIGN_CASE(22) PN_ALIGN_CASE(23)
+        PN_ALIGN_CASE(24) PN_ALIGN_CASE(25) PN_ALIGN_CASE(26) PN_ALIGN_CASE(27)
+        PN_ALIGN_CASE(28) PN_ALIGN_CASE(29) PN_ALIGN_CASE(30) PN_ALIGN_CASE(31)
 #undef PN_ALIGN_CASE
         default: break;
     }

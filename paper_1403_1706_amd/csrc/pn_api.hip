@@ -79,6 +79,7 @@ struct pn_ctx {
     // grow-only workspace of the mapping path
     Workspace ws;
     bool sub_on = false;  // lax lists made for the current mapping call
+    bool wide_k = false;  // some read of the current mapping call has k > PN_BAND_K
     // stage timing and counters
     bool timing = false;
     pn_stats stats{};
@@ -876,6 +877,7 @@ int prepare_rules(pn_ctx *c, const pn_index *x, int kglob, const uint8_t *d_k, b
     stage_end(c, st, tok, (x->n_reads ? 7 : 3) + (c->sub_on ? 2 : 0));
     PN_CHECK(read_misc(c, st));
     const uint32_t status = (uint32_t)c->hmisc[kStatus];
+    c->wide_k = (status & 16u) != 0;
     if (status & 2u) return PN_EINVAL;
     if (status & 4u) return PN_ELEMMA;
     return PN_OK;
@@ -1069,7 +1071,13 @@ int validate_sorted(pn_ctx *c, const pn_ref *ref, const pn_index *x, int kglob, 
             const int tok = stage_begin(c, st, PN_STAGE_VERIFY_LONG);
             pn::launch_verify(ref_desc(ref), index_desc(x), in, kglob, d_k, vo, last_in, last_n,
                               false, st);
-            stage_end(c, st, tok, 1);
+            // reads with k > PN_BAND_K: their candidates are all in the
+            // survivor list
+            if (c->wide_k)
+                pn::launch_verify_wide(ref_desc(ref), index_desc(x),
+                                       pn::VerifyIn{last_in, last_n, in.regions, in.region_cap},
+                                       kglob, d_k, vo, st);
+            stage_end(c, st, tok, c->wide_k ? 2 : 1);
             PN_CHECK(read_misc(c, st));
             uint64_t rec_max;
             region_counts(c, kRecCounts, pn::kShards, &rec_max, &got);
@@ -1543,8 +1551,12 @@ int pn_align(pn_ctx *c, const pn_ref *ref, const pn_index *x, const pn_hit *hits
     static_assert(sizeof(pn_hit) == 12, "hit records are three words");
     const bool want_ops = n_ops != nullptr;
     const uint32_t ost = want_ops && ops ? stride : 0;
-    // chunks whose op-code rows fit 512 MiB
-    const uint64_t rows = (uint64_t)std::max(x->max_len, 1);
+    // chunks whose op-code rows fit 512 MiB (two words per row for bands of
+    // more than 32 diagonals)
+    uint32_t vmax = 0;
+    for (uint64_t h = 0; h < n; h++) vmax = std::max<uint32_t>(vmax, hits[h].errors);
+    const uint64_t rows =
+        (uint64_t)std::max(x->max_len, 1) * (vmax > PN_BAND_K ? 2ull : 1ull);
     const uint64_t chunk = std::min<uint64_t>(n, std::max<uint64_t>(64, (512ull << 20) / (rows * 8)));
     DeviceGuard g(c->device);
     hipStream_t st = c->stream;
@@ -1711,6 +1723,11 @@ int pn_validate_noalloc(pn_ctx *c, const pn_ref *ref, const pn_index *x,
                           (unsigned long long *)&c->misc[kLongCounts], true, st);
         pn::launch_verify(ref_desc(ref), ix, in, kglob, d_k_per_read, vo, longc,
                           (unsigned long long *)&c->misc[kLongCounts], false, st);
+        if (status & 16u)
+            pn::launch_verify_wide(ref_desc(ref), ix,
+                                   pn::VerifyIn{longc, (const unsigned long long *)&c->misc[kLongCounts],
+                                                1, in_cap},
+                                   kglob, d_k_per_read, vo, st);
     }
     PN_CHECK(na_sync_misc(c, st));
     uint64_t rmax = 0, total = 0;

@@ -16,7 +16,7 @@ __host__ __device__ __forceinline__ uint32_t pn_funnel(uint32_t hi, uint32_t lo,
 
 // Verify one candidate.  `pl`: the strand's padded bit planes; `rp`: the
 // read's PN_READ_WORDS plane words; the band covers diagonals [lo, lo + 2k]
-// (lo = d - k); 1 <= len <= PN_MAX_READ_LEN; 0 <= k <= PN_MAX_K.  Calls
+// (lo = d - k); 1 <= len <= PN_MAX_READ_LEN; 0 <= k <= PN_BAND_K.  Calls
 // emit(end, value) for every end column of the last row with value <= k,
 // and returns the number of rows computed.  A candidate still alive after
 // row_cap rows (a multiple of 8, below len) stops there without emitting
@@ -156,6 +156,77 @@ __host__ __device__ __forceinline__ int pn_band_verify(const uint4 *__restrict__
     PnBandHead hd;
     pn_band_load(pl, rp, lo, hd);
     return pn_band_run(hd, pl, rp, len, k, lo, L, row_cap, emit);
+}
+
+// The same recurrence for PN_BAND_K < k <= PN_MAX_K: the band's 2k + 1 <= 63
+// diagonals in one 64-bit word, row by row from row 0 to the end (no cap,
+// no tail check).  Row i compares read letter i - 1 with the text from
+// position lo + i - 1 on; the four plane blocks the window needs advance by
+// one block every 32 rows.  Calls emit(end, value) like pn_band_run and returns
+// the number of rows computed.
+template <typename Emit>
+__host__ __device__ inline int pn_band_verify_wide(const uint4 *__restrict__ pl,
+                                                   const uint2 *__restrict__ rp, int len, int k,
+                                                   int64_t lo, uint64_t L, Emit &&emit) {
+    const int W = 2 * k + 1;
+    const uint64_t M = (1ull << W) - 1ull;
+    const uint64_t M2 = M & ~1ull;
+    const uint64_t TOP = 1ull << (W - 1);
+    const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
+    uint64_t blk = tp >> 5;
+    const uint32_t ph = (uint32_t)(tp & 31);
+    uint4 A = pl[blk], B = pl[blk + 1], C = pl[blk + 2], D = pl[blk + 3];
+    uint64_t VP = 0, VN = 0;  // row 0: every band cell is 0 (free start)
+    int Ck = k;               // as in pn_band_run: R = i + k - Ck
+    uint2 rw = rp[0];
+    for (int i = 1; i <= len; i++) {
+        const uint32_t t = (uint32_t)(i - 1) & 31u;  // (ph + i - 1) - 32 * (blocks advanced)
+        const uint32_t sh = ph + t;
+        // bits [sh, sh + 64) of the blocks A .. D (sh < 63)
+        const uint32_t s0 = sh & 31u;
+        const bool up = sh >= 32;
+        const uint4 a0 = up ? B : A, a1 = up ? C : B, a2 = up ? D : C;
+        const uint32_t a0x = a0.x, a1x = a1.x, a2x = a2.x;
+        const uint32_t a0y = a0.y, a1y = a1.y, a2y = a2.y;
+        const uint32_t a0z = a0.z, a1z = a1.z, a2z = a2.z;
+        const uint64_t H = (uint64_t)pn_funnel(a1x, a0x, s0) | ((uint64_t)pn_funnel(a2x, a1x, s0) << 32);
+        const uint64_t Lw = (uint64_t)pn_funnel(a1y, a0y, s0) | ((uint64_t)pn_funnel(a2y, a1y, s0) << 32);
+        const uint64_t V = (uint64_t)pn_funnel(a1z, a0z, s0) | ((uint64_t)pn_funnel(a2z, a1z, s0) << 32);
+        const uint64_t xh = 0ull - (uint64_t)((rw.x >> t) & 1u);
+        const uint64_t xl = 0ull - (uint64_t)((rw.y >> t) & 1u);
+        const uint64_t Eq = ~((H ^ xh) | (Lw ^ xl)) & V & M;
+        uint64_t vp = (VP >> 1) | TOP;
+        uint64_t vn = VN >> 1;
+        const uint64_t Xv = Eq | vn;
+        const uint64_t Xh = (((Eq & vp) + vp) ^ vp) | Eq;
+        uint64_t HP = vn | ~(Xh | vp);
+        uint64_t HN = vp & Xh;
+        Ck += (int)((HN >> (W - 1)) & 1ull);
+        HP = (HP << 1) | 1ull;
+        HN <<= 1;
+        VP = HN | ~(Xv | HP);
+        VN = HP & Xv;
+        if (i == len) {
+            int v = i + k - Ck;
+            for (int b = W - 1; b >= 0; b--) {
+                const int64_t c = (int64_t)len + lo + b;
+                if (c >= 1 && c <= (int64_t)L && v <= k) emit((uint32_t)(c - 1), v);
+                v -= (int)((VP >> b) & 1ull) - (int)((VN >> b) & 1ull);
+            }
+            return i;
+        }
+        if (__builtin_popcountll(VP & M2) + Ck < i) return i;
+        if (t == 31) {
+            // the next 32 rows: the next read word, the window one block on
+            rw = rp[i >> 5];
+            blk++;
+            A = B;
+            B = C;
+            C = D;
+            D = pl[blk + 3];
+        }
+    }
+    return len;
 }
 
 // Count filter (the q-gram lemma of Section 2.2, with the read cut into its

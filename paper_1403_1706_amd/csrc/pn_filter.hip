@@ -767,7 +767,8 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
 
 __device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
-// status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r
+// status bit 2: some k_r > PN_MAX_K; bit 4: some read violates (k_r+1) q <= n_r;
+// bit 16 (no error): some k_r > PN_BAND_K (the 64-bit band pass is needed)
 __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict__ kpr,
                              uint8_t *__restrict__ rinfo, uint16_t *__restrict__ rstamp,
                              uint32_t *status, int plain) {
@@ -794,6 +795,7 @@ __global__ void k_read_rules(PnIndexDev ix, int kglob, const uint8_t *__restrict
             for (uint32_t o = 0; o + ell <= n; o += ell)
                 pieces += !pn_low_complexity(pn_window16(ix.packed, off + o) >> (32 - 2 * q), q);
         }
+        if (!bad && k > PN_BAND_K) atomicOr(status, 16u);
         if (bad) {
             atomicOr(status, bad);
             rinfo[r] = 0;

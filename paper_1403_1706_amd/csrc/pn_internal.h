@@ -28,7 +28,8 @@
 #define PN_MAX_READ_LEN 256
 #define PN_READ_WORDS (PN_MAX_READ_LEN / 32)
 #define PN_MAX_READS (1u << 21)
-#define PN_MAX_K 15
+#define PN_MAX_K 31   // 2k + 1 <= 63 band diagonals
+#define PN_BAND_K 15  // largest k whose band fits one 32-bit word (the fast passes)
 #define PN_MAX_Q 16  // a q-gram code fills at most one 32-bit word
 #define PN_PAD_BLOCKS 16
 #define PN_PAD_POS (32 * PN_PAD_BLOCKS)
@@ -401,10 +402,16 @@ struct VerifyOut {
 // alive from row 0 to the end.  `longc` (in.regions regions of
 // in.region_cap entries) and its counters `n_long` (in.regions words, zeroed
 // by the caller) hold the second pass's candidates.  `first` picks the pass;
-// the second pass reads `longc` and ignores in.cands.
+// the second pass reads `longc` and ignores in.cands.  Candidates of reads
+// with k > PN_BAND_K skip both passes: the first (and the count filter) puts
+// them into `longc` as they are, for launch_verify_wide.
 void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
                    const uint8_t *kpr, VerifyOut out, uint2 *longc, unsigned long long *n_long,
                    bool first, hipStream_t st);
+// The 64-bit band pass over `in` (the survivor list: longc and n_long) for
+// the candidates of reads with PN_BAND_K < k <= PN_MAX_K; records into out.
+void launch_verify_wide(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                        const uint8_t *kpr, VerifyOut out, hipStream_t st);
 
 // The count filter (pn_verify.hip): each candidate of `in` whose band holds
 // at least floor(n/4) - k exact pieces of 4 read letters (the q-gram lemma

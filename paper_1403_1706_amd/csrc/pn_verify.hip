@@ -1,6 +1,7 @@
 // Validation (Section 3.3): banded bit-parallel semiglobal edit distance,
 // one candidate per lane, the band of W = 2k+1 diagonals [d-k, d+k] held in
-// one 32-bit word (k <= 15).
+// one 32-bit word (k <= 15); reads with 15 < k <= 31 take a third pass with
+// the band in one 64-bit word (k_verify_wide).
 //
 // The band is processed row by row (one read letter per step).  Bit b of
 // row i stands for column c = i + (d-k) + b, so the same bit index is the
@@ -84,6 +85,7 @@ struct Stage {
 struct Cand {
     uint2 c;
     bool ok;
+    bool wide;  // k > PN_BAND_K: left to the 64-bit band pass
     bool tail;  // first pass: check the read's last rows (reverse complement band)
     int len, k;
     int64_t lo;  // reference position of the band's first diagonal
@@ -103,6 +105,7 @@ __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix,
                                       bool first, Cand &x) {
     x.c = c;
     x.ok = false;
+    x.wide = false;
     if (c.x == PN_CAND_NONE) return;  // padding slot
     const uint32_t r = c.x & PN_CAND_READ;
     const uint32_t s = c.x >> 31;
@@ -110,6 +113,10 @@ __device__ __forceinline__ void start(const PnRefDev &ref, const PnIndexDev &ix,
     x.len = pn_cand_len(c.x);
     x.k = kglob >= 0 ? kglob : (int)kpr[r];
     if (x.k > PN_MAX_K || x.len < 1 || x.len > PN_MAX_READ_LEN) return;
+    if (x.k > PN_BAND_K) {
+        x.wide = true;
+        return;
+    }
     x.ok = true;
     const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
     if (x.tail) {
@@ -197,6 +204,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
             if (kCapped && (rw < 0 || (kFirst && tail && rw == cur.len)))
                 lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
             rows += (unsigned long long)(rw < 0 ? -rw : rw);
+        } else if (kCapped && cur.wide) {
+            lng.push(((unsigned long long)cur.c.y << 32) | cur.c.x);
         }
         cur = nxt;
         if (*rec.cnt >= kStage / 2) rec.flush(lane);
@@ -204,6 +213,57 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kFirst
     }
     rec.flush(lane);
     if (kCapped) lng.flush(lane);
+    for (int o = 32; o > 0; o >>= 1) rows += __shfl_xor(rows, o);
+    if (lane == 0 && rows) atomicAdd(out.rows, rows);
+}
+
+// The band pass for reads with PN_BAND_K < k <= PN_MAX_K, over the survivor
+// list of the first pass (or of the count filter), which holds every such
+// candidate: the band of up to 63 diagonals in one 64-bit word, row 0 to
+// the end, one candidate per lane.  Such reads are rare (long reads with a
+// small q), so the pass has no pipelining of its own.
+__global__ __launch_bounds__(kThreads) void k_verify_wide(PnRefDev ref, PnIndexDev ix,
+                                                          pn::VerifyIn in, int kglob,
+                                                          const uint8_t *__restrict__ kpr,
+                                                          pn::VerifyOut out) {
+    __shared__ unsigned long long s_rec[kWaves][kStage];
+    __shared__ uint32_t s_cnt[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    if (lane == 0) s_cnt[wv] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t rin = blockIdx.x % in.regions;
+    const uint32_t rout = blockIdx.x % pn::kShards;
+    Stage rec{s_rec[wv], &s_cnt[wv], out.records + (uint64_t)rout * out.sh.region_cap,
+              out.sh.counts + rout, out.sh.region_cap};
+    const uint2 *cands = in.cands + (uint64_t)rin * in.region_cap;
+    const uint64_t n = min((uint64_t)in.counts[rin], in.region_cap);
+    const uint64_t stride = (uint64_t)(gridDim.x / in.regions) * kThreads;
+    unsigned long long rows = 0;
+    // the loop bound is wave-uniform, so the wave is converged at the flushes
+    for (uint64_t base = (blockIdx.x / in.regions) * kThreads + (uint64_t)wv * 64; base < n;
+         base += stride) {
+        const uint64_t ci = base + lane;
+        const uint2 c = ci < n ? cands[ci] : make_uint2(PN_CAND_NONE, PN_CAND_NONE);
+        if (c.x != PN_CAND_NONE) {
+            const uint32_t r = c.x & PN_CAND_READ;
+            const uint32_t s = c.x >> 31;
+            const int len = pn_cand_len(c.x);
+            const int k = kglob >= 0 ? kglob : (int)kpr[r];
+            if (k > PN_BAND_K && k <= PN_MAX_K && len >= 1 && len <= PN_MAX_READ_LEN) {
+                const int64_t d = (int64_t)c.y - (int64_t)PN_DBIAS;
+                const unsigned long long head = (((unsigned long long)r << 1) | s) << out.ebits;
+                auto emit = [&](uint32_t e, int v) {
+                    rec.push(((head | (unsigned long long)e) << 5) | (unsigned long long)v);
+                };
+                rows += (unsigned long long)pn_band_verify_wide(
+                    s ? ref.planes[1] : ref.planes[0], ix.rplanes + (uint64_t)r * PN_READ_WORDS,
+                    len, k, d - k, ref.L, emit);
+            }
+        }
+        if (*rec.cnt >= kStage / 2) rec.flush(lane);
+    }
+    rec.flush(lane);
     for (int o = 32; o > 0; o >>= 1) rows += __shfl_xor(rows, o);
     if (lane == 0 && rows) atomicAdd(out.rows, rows);
 }
@@ -300,9 +360,10 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
                 const int m = nxt.len / kPnPiece;
                 const bool inside =
                     nxt.lo >= 0 && nxt.lo + nxt.len + 2 * nxt.k < (int64_t)ref.L;
-                if (m - nxt.k <= 0 || !inside) {
-                    // nothing to count (too short to drop any, or a band that
-                    // crosses a reference end): the band pass settles it
+                if (m - nxt.k <= 0 || !inside || nxt.k > PN_BAND_K) {
+                    // nothing to count (too short to drop any, a band that
+                    // crosses a reference end, or one wider than the 32
+                    // diagonals a text word covers): the band pass settles it
                     lng.push(((unsigned long long)nxt.c.y << 32) | nxt.c.x);
                 } else {
                     has_cur = true;
@@ -435,6 +496,16 @@ void launch_verify(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int k
         hipLaunchKernelGGL((k_verify<false, false>), grid, dim3(kThreads), 0, st, ref, ix, in2,
                            kglob, kpr, out, longc, n_long, PN_MAX_READ_LEN);
     }
+}
+
+void launch_verify_wide(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,
+                        const uint8_t *kpr, VerifyOut out, hipStream_t st) {
+    if (!in.region_cap || !in.regions) return;
+    uint64_t per = (in.region_cap + kThreads - 1) / kThreads;
+    const uint64_t max_per = std::max<uint64_t>(8192 / in.regions, 1);
+    if (per > max_per) per = max_per;
+    hipLaunchKernelGGL(k_verify_wide, dim3((unsigned)(per * in.regions)), dim3(kThreads), 0, st,
+                       ref, ix, in, kglob, kpr, out);
 }
 
 void launch_count(const PnRefDev &ref, const PnIndexDev &ix, VerifyIn in, int kglob,

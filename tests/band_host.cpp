@@ -54,6 +54,11 @@ extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, i
         out_v[m] = v;
         m++;
     };
+    if (k > PN_BAND_K) {
+        // the 64-bit band pass: from row 0 to the end, no first pass
+        pn_band_verify_wide(pl.data(), rp.data(), n, k, d - k, L, emit);
+        return m;
+    }
     if (tail) {
         const std::vector<uint4> plr = text_planes(text, L, true);
         const std::vector<uint2> rpr = read_planes(read, n, true);
@@ -76,6 +81,7 @@ extern "C" int band_host(const uint8_t *text, uint64_t L, const uint8_t *read, i
 extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, int n, int64_t d,
                           int k) {
     if (n < 1 || n > PN_MAX_READ_LEN || k < 0 || k > PN_MAX_K) return -1;
+    if (k > PN_BAND_K) return 1;  // the kernel hands such bands to the band pass uncounted
     const std::vector<uint4> pl = text_planes(text, L, false);
     const std::vector<uint2> rp = read_planes(read, n, false);
     PnBandHead hd;
@@ -103,7 +109,7 @@ extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, 
 template <int K>
 static int align_k(const std::vector<uint4> &pl, const std::vector<uint2> &rp, int n, uint64_t e,
                    uint64_t L, uint32_t *start, uint8_t *err, uint8_t *ops, uint32_t stride) {
-    std::vector<unsigned long long> bp((size_t)n + 1);
+    std::vector<unsigned long long> bp(((size_t)n + 1) * pn_align_row_words(K));
     return pn_align_one<K>(pl.data(), rp.data(), n, (int64_t)e, L, bp.data(), 1, true, ops, stride,
                            start, err);
 }
@@ -118,7 +124,10 @@ extern "C" int align_host(const uint8_t *text, uint64_t L, const uint8_t *read, 
     case k: return align_k<k>(pl, rp, n, e, L, start, err, ops, stride);
         ALIGN_CASE(0) ALIGN_CASE(1) ALIGN_CASE(2) ALIGN_CASE(3) ALIGN_CASE(4) ALIGN_CASE(5)
         ALIGN_CASE(6) ALIGN_CASE(7) ALIGN_CASE(8) ALIGN_CASE(9) ALIGN_CASE(10) ALIGN_CASE(11)
-        ALIGN_CASE(12) ALIGN_CASE(13) ALIGN_CASE(14) ALIGN_CASE(15)
+        ALIGN_CASE(12) ALIGN_CASE(13) ALIGN_CASE(14) ALIGN_CASE(15) ALIGN_CASE(16) ALIGN_CASE(17)
+        ALIGN_CASE(18) ALIGN_CASE(19) ALIGN_CASE(20) ALIGN_CASE(21) ALIGN_CASE(22) ALIGN_CASE(23)
+        ALIGN_CASE(24) ALIGN_CASE(25) ALIGN_CASE(26) ALIGN_CASE(27) ALIGN_CASE(28) ALIGN_CASE(29)
+        ALIGN_CASE(30) ALIGN_CASE(31)
 #undef ALIGN_CASE
     }
     return -1;

@@ -47,7 +47,8 @@ def test_band_code_equals_scalar_band_dp(band, seed):
         L = int(rng.integers(40, 700))
         text = rng.integers(0, 4, L).astype(np.uint8)
         n = int(rng.integers(12, 257))
-        k = int(rng.integers(0, 16))
+        # k <= 15: the 32-bit band passes; 15 < k <= 31: the 64-bit band pass
+        k = int(rng.integers(0, 32))
         if rng.random() < 0.7:
             p = int(rng.integers(-20, L))
             x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
@@ -206,7 +207,7 @@ def test_align_code_equals_oracle(align, seed):
     the error count needs; a band narrower than the error count finds
     nothing."""
     rng = np.random.default_rng(300 + seed)
-    checked = with_indels = 0
+    checked = with_indels = wide = 0
     for trial in range(400):
         L = int(rng.integers(60, 600))
         text = rng.integers(0, 4, L).astype(np.uint8)
@@ -217,7 +218,9 @@ def test_align_code_equals_oracle(align, seed):
         p = int(rng.integers(-5, max(1, L - n + 5)))
         x = np.array([text[j] if 0 <= j < L else rng.integers(0, 4) for j in range(p, p + n)],
                      np.uint8)
-        for _ in range(int(rng.integers(0, 8))):
+        # up to 7 edits, or (a third of the hits) up to 30: error counts
+        # beyond 15 take two op-code words per row
+        for _ in range(int(rng.integers(0, 8 if rng.random() < 0.67 else 31))):
             j = int(rng.integers(0, len(x)))
             r = rng.random()
             if r < 0.6:
@@ -228,14 +231,15 @@ def test_align_code_equals_oracle(align, seed):
                 x = np.concatenate([x[:j], x[j + 1:]])
         x = x[:256]
         e = int(np.clip(p + len(x) - 1 + int(rng.integers(-3, 4)), 0, L - 1))
-        start, err, ops = oracle.align(text, x, e, len(x) + 15)
-        if err > 15:
+        start, err, ops = oracle.align(text, x, e, len(x) + 31)
+        if err > 31:
             continue
         assert align(text, x, e, err) == (start, err, ops), (L, len(x), e, err)
-        wider = int(rng.integers(err, 16))
+        wider = int(rng.integers(err, 32))
         assert align(text, x, e, wider) == (start, err, ops), (L, len(x), e, err, wider)
         if err > 0:
             assert align(text, x, e, err - 1)[1] == 0xff
         checked += 1
         with_indels += ("I" in ops) or ("D" in ops)
-    assert checked > 250 and with_indels > 50
+        wide += err > 15
+    assert checked > 250 and with_indels > 50 and wide > 20

@@ -397,6 +397,85 @@ def test_empty_and_tiny_batches(pn, sess):
                       oracle.map_filtered(w.ref, one.reads, one.offsets, 10, 5))
 
 
+# ---------------------------------------------------------------------------
+# error bounds above 15: 2k + 1 up to 63 band diagonals (the 64-bit band pass)
+
+
+def wide_k_case(seed, L, n_reads, len_lo, len_hi, eps, q):
+    """Reads of len_lo..len_hi letters at error rate eps, two thirds of them
+    with the largest k the q-gram lemma admits at this q (at most 31), the
+    rest with ceil(5 % n): both band widths in one batch."""
+    rng = np.random.default_rng(seed)
+    w = synth.random_case(rng, L, n_reads, len_lo, len_hi, eps, q, repeats=True)
+    n = w.lengths
+    wide = rng.random(w.n_reads) < 0.67
+    w.k_per_read = np.where(wide, np.minimum(31, n // q - 1),
+                            synth.k_ceil_fraction(n)).astype(np.uint8)
+    assert ((w.k_per_read.astype(np.int64) + 1) * q <= n).all()
+    return w
+
+
+@pytest.mark.parametrize("case", ["plain-q8", "ordered-q11"])
+def test_wide_k_map_equals_oracle(pn, sess, case):
+    """Per-read k up to 31 (long reads, small q) mixed with k <= 15 in one
+    batch: ALL and BEST hits equal the oracle's, with hits of more than 15
+    errors among them.  The second case's reads pile up on a 5 kbp
+    reference, so the index is the ordered one and the count filter runs
+    (it hands bands wider than 32 diagonals to the band pass uncounted)."""
+    if case == "plain-q8":
+        w = wide_k_case(61, 200_000, 1_000, 150, 256, 0.07, 8)
+    else:
+        w = wide_k_case(62, 5_000, 6_000, 200, 256, 0.05, 11)
+    idx = sess.index(w.reads, w.offsets, w.q)
+    info = pn.pn_index_get_info(idx)
+    assert bool(info["after_sorted"]) == (case == "ordered-q11")
+    g = map_both(pn, sess, w)
+    say(f"{case}: {len(g)} best-stratum hits, k up to {int(w.k_per_read.max())}")
+    refh = sess.ref(w.ref)
+    hits = pn.pn_map(sess.ctx, refh, idx, w.k_per_read, 0)
+    assert (hits["errors"] > 15).sum() > 20
+    # starts and alignments of the hits above 15 errors (two op-code words per row)
+    sel = hits[hits["errors"] > 15][:400]
+    assert check_alignments(pn, sess, w.ref, w.reads, w.offsets, refh, idx, sel, 31) == len(sel)
+
+
+def test_wide_k_validate_equals_band_dp(pn, sess):
+    """pn_validate with k up to 31 on the oracle's candidates plus bands
+    over both reference ends equals the oracle's band DP, candidate by
+    candidate; pn_validate_noalloc gives the same records."""
+    import torch
+    w = wide_k_case(63, 60_000, 200, 150, 256, 0.07, 8)
+    ref = sess.ref(w.ref)
+    idx = sess.index(w.reads, w.offsets, w.q)
+    r0, s0, d0 = oracle.candidates(w.ref, w.reads, w.offsets, w.q)
+    rng = np.random.default_rng(64)
+    pick = rng.choice(len(r0), size=min(3000, len(r0)), replace=False)
+    L = len(w.ref)
+    er = rng.integers(0, w.n_reads, 40)
+    ed = np.concatenate([rng.integers(-256, 5, 20), rng.integers(L - 260, L + 1, 20)])
+    cands = np.concatenate([pn.make_candidates(r0[pick], s0[pick], d0[pick]),
+                            pn.make_candidates(er, rng.integers(0, 2, 40), ed)])
+    got = pn.pn_validate(sess.ctx, ref, idx, cands, w.k_per_read)
+    texts = [oracle.encode(w.ref), oracle.reverse_complement(oracle.encode(w.ref))]
+    codes = oracle.encode(w.reads)
+    expect = []
+    for c in cands:
+        r, s, d = int(c["read_id"]), int(c["strand"]), int(c["diagonal"])
+        x = codes[int(w.offsets[r]):int(w.offsets[r + 1])]
+        for e, v in oracle.banded(texts[s], x, d, int(w.k_per_read[r])):
+            expect.append((r, s, e, v))
+    expect.sort()
+    assert [tuple(t) for t in fields(got).tolist()] == expect
+    assert sum(v > 15 for *_, v in expect) > 20
+    dev = torch.device("cuda:0")
+    d_c = torch.from_numpy(np.ascontiguousarray(cands).view(np.uint8).copy()).to(dev)
+    out = torch.empty(12 * (len(got) + 64), dtype=torch.uint8, device=dev)
+    d_k = torch.from_numpy(w.k_per_read.copy()).to(dev)
+    n = pn.pn_validate_noalloc(sess.ctx, ref, idx, d_c, len(cands), -1, out, d_k=d_k)
+    na = np.frombuffer(out[:12 * n].cpu().numpy().tobytes(), dtype=pn.HIT_DTYPE)
+    assert np.array_equal(fields(na), fields(got))
+
+
 def test_error_statuses(pn, sess):
     w = synth.make("tiny", scale=0.01)
     ref = sess.ref(w.ref)
@@ -405,7 +484,7 @@ def test_error_statuses(pn, sess):
         pn.pn_map(sess.ctx, ref, idx, 10, 0)  # (10+1)*10 > 100
     assert e.value.status == pn.PN_ELEMMA
     with pytest.raises(pn.PnError) as e:
-        pn.pn_map(sess.ctx, ref, idx, 16, 0)
+        pn.pn_map(sess.ctx, ref, idx, 32, 0)  # above the 63-diagonal band
     assert e.value.status == pn.PN_EINVAL
     bad = bytearray(w.reads)
     bad[50] = ord("N")
@@ -521,7 +600,7 @@ def check_alignments(pn, sess, ref_bytes, reads, offsets, refh, idx, hits, k_max
     """pn_align on `hits` against oracle.align on the strand's text, hit by
     hit: start, error count and operations identical; returns the number of
     hits checked."""
-    stride = int(np.diff(offsets).max()) + 16
+    stride = int(np.diff(offsets).max()) + k_max + 1  # at most n + k operations
     starts, errs, ops, n_ops = pn.pn_align(sess.ctx, refh, idx, hits, stride)
     text = [oracle.encode(ref_bytes)]
     text.append(oracle.reverse_complement(text[0]))

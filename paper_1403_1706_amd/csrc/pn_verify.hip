@@ -404,7 +404,10 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
         if (!__any(has_cur || has_nxt || has_cw)) break;
         // 3. one read word of the candidate in progress
         if (has_cur) {
-            const uint32_t F = pn_count_word_hl(A, B, C, rw, ph, W);
+            // (with one k for every read the diagonal loop's bound is
+            // wave-uniform: scalar loop control)
+            const uint32_t F = kglob >= 0 ? pn_count_word_hl(A, B, C, rw, ph, 2 * kglob + 1)
+                                          : pn_count_word_hl(A, B, C, rw, ph, W);
             found += __popc(F & pn_piece_firsts(left));
             const int now = left < 8 ? left : 8;
             letters += 32;

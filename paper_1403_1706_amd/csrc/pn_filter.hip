@@ -179,9 +179,12 @@ __device__ __forceinline__ void pad_lane(Stage &sg) {
 // q-gram are skipped: the sub-range they were found in holds only the
 // entries whose four letters agree with the text, and such entries are
 // visited through the slice's lax list instead (see probe).
-__device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uint32_t s,
-                                      bool has_prev, uint32_t prev, bool lh, uint32_t N,
-                                      uint32_t avail, bool strict, Stage &sg) {
+// visit_rules decides and hands the candidate to take(c) at the point where
+// it is formed (the callers below append it or keep it).
+template <typename Take>
+__device__ __forceinline__ void visit_rules(const unsigned long long v, int64_t p, uint32_t s,
+                                            bool has_prev, uint32_t prev, bool lh, uint32_t N,
+                                            uint32_t avail, bool strict, Take &&take) {
     const uint32_t hi = (uint32_t)(v >> 32);
     const uint32_t cls = hi >> 29;
     uint32_t r = (hi >> 8) & (PN_MAX_READS - 1);
@@ -196,8 +199,8 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
         // a window in the read's first half: verification's first pass
         // checks the read's last rows, away from the exact window
         const bool tail = o < 16u * ((info >> 4) & 7u);
-        push(sg, make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
-                            (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+        take(make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
+                        (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
         return;
     }
     // (a searched range of an ordered slice serves reads in piece mode only;
@@ -212,8 +215,59 @@ __device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uin
         if (nav < need || avail < need || ((next4 ^ N) >> (8 - 2 * need)) != 0u) return;
     }
     const uint32_t tail = (info >> 6) & 1u;  // the read's first rows are mostly a repeat run
-    push(sg, make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
-                        (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+    take(make_uint2(r | (tail ? PN_CAND_TAIL : 0u) | (s << 31),
+                    (uint32_t)((int64_t)PN_DBIAS + p - (int64_t)o)));
+}
+
+// the candidate appended to the stage where it is formed
+__device__ __forceinline__ void visit(const unsigned long long v, int64_t p, uint32_t s,
+                                      bool has_prev, uint32_t prev, bool lh, uint32_t N,
+                                      uint32_t avail, bool strict, Stage &sg) {
+    visit_rules(v, p, s, has_prev, prev, lh, N, avail, strict, [&](uint2 c) { push(sg, c); });
+}
+
+// the candidate kept in c (false: none)
+__device__ __forceinline__ bool visit_cand(const unsigned long long v, int64_t p, uint32_t s,
+                                           bool has_prev, uint32_t prev, bool lh, uint32_t N,
+                                           uint32_t avail, bool strict, uint2 &c) {
+    bool got = false;
+    visit_rules(v, p, s, has_prev, prev, lh, N, avail, strict, [&](uint2 x) {
+        c = x;
+        got = true;
+    });
+    return got;
+}
+
+// Converged wave (every lane calls it): appends the lanes' candidates (has)
+// to the wave's stage at its count n, a wave-uniform register (no LDS
+// counter, no atomics); the caller keeps n + 64 <= the stage's size.
+__device__ __forceinline__ void stage_put(const Stage &sg, uint32_t &n, bool has, uint2 c,
+                                          int lane) {
+    const unsigned long long m = __ballot(has);
+    if (has) sg.buf[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = pack_cand(c);
+    n += (uint32_t)__popcll(m);
+}
+
+// flush for a stage whose count is the register n (whole wave, converged)
+__device__ __forceinline__ void flush_n(Stage &sg, int lane, uint32_t &n) {
+    __builtin_amdgcn_wave_barrier();
+    if (n) {
+        uint2 *region = sg.cands + (uint64_t)sg.shard * sg.region_cap;
+        unsigned long long base = 0;
+        if (lane == 0) {
+            base = atomicAdd(sg.counts + sg.shard, (unsigned long long)n);
+            sg.written += n;
+        }
+        base = __shfl(base, 0);
+        for (uint32_t i = lane; i < n; i += 64) {
+            const unsigned long long v = sg.buf[i];
+            if (base + i < sg.region_cap)
+                region[base + i] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+        }
+        sg.shard = (sg.shard + 1) % pn::kShards;
+    }
+    __builtin_amdgcn_wave_barrier();
+    n = 0;
 }
 
 // Occurrence ranges longer than FilterOut::heavy_min are set aside for
@@ -625,6 +679,9 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
     const uint32_t nw = gridDim.x * kWaves;
     Stage sg{(lds_u64 *)(wbuf_dyn + (uint64_t)wave * cap), &wcnt[wave], out.cands, out.sh.counts, out.sh.region_cap,
              gw % pn::kShards, 0u, 0ull, 0u, 0u, cap};
+    // candidates in the wave's stage (wave-uniform: every lane takes part in
+    // each stage_put, so the stage never needs the LDS counter)
+    uint32_t staged = 0;
     const uint32_t region = gw % pn::kShards;
     const uint64_t n = min((uint64_t)out.hsh.counts[region], out.hsh.region_cap);
     const uint4 *items = out.heavy + 2 * (uint64_t)region * out.hsh.region_cap;
@@ -671,9 +728,12 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const uint32_t k = base + 64 * u + (uint32_t)lane;
-                    if (k < total)
-                        visit(v[u], p, s, has, prev, lh, N, avail, strictA && k < la, sg);
-                    if (*sg.cnt >= cap - 64) flush(sg, lane);
+                    uint2 c = make_uint2(0u, 0u);
+                    const bool e = k < total &&
+                                   visit_cand(v[u], p, s, has, prev, lh, N, avail,
+                                              strictA && k < la, c);
+                    stage_put(sg, staged, e, c, lane);
+                    if (staged > cap - 64) flush_n(sg, lane, staged);
                 }
             }
         }
@@ -743,6 +803,8 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t e = base + 64u * (uint32_t)u + (uint32_t)lane;
+                uint2 c = make_uint2(0u, 0u);
+                bool got = false;
                 if (e < total) {
                     const uint32_t fl = pf[u];
                     const int64_t p = (int64_t)(((uint64_t)(fl >> 22) << 32) | px[u]);
@@ -750,16 +812,16 @@ __global__ __launch_bounds__(kT) void k_filter_heavy(PnIndexDev ix, pn::Lists ls
                     const uint32_t prev = (fl >> 2) & 3u, avail = (fl >> 4) & 7u,
                                    N = (fl >> 8) & 0xffu;
                     const uint32_t s = (fl >> 16) & 1u;
-                    visit(v[u], p, s, has, prev, lh, N, avail, st[u], sg);
+                    got = visit_cand(v[u], p, s, has, prev, lh, N, avail, st[u], c);
                 }
-                if (*sg.cnt >= cap - 64) flush(sg, lane);
+                stage_put(sg, staged, got, c, lane);
+                if (staged > cap - 64) flush_n(sg, lane, staged);
             }
             __builtin_amdgcn_wave_barrier();
         }
         __builtin_amdgcn_wave_barrier();
     }
-    pad_lane(sg);
-    flush(sg, lane);
+    flush_n(sg, lane, staged);
 }
 
 // ---------------------------------------------------------------------------

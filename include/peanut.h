@@ -325,8 +325,9 @@ int pn_align(pn_ctx *ctx, const pn_ref *ref, const pn_index *idx, const pn_hit *
              uint64_t n_hits, uint32_t *starts, uint8_t *errors, uint8_t *ops,
              uint32_t ops_stride, uint16_t *n_ops);
 
-/* pn_validate for callers that cannot allocate device memory: code under
- * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+/* pn_validate for callers that cannot allocate device memory: tight serving
+ * loops and harnesses that forbid hipMalloc.  (It reads counts back and
+ * synchronises, so it cannot itself be recorded into a HIP graph.)
  * Same candidates, k and records as pn_validate, but device arrays in and
  * out, ordered on `stream` (NULL: the context's stream): d_cands holds
  * n_cands pn_candidate entries, d_k_per_read (k < 0) one byte per read of

@@ -61,11 +61,12 @@ constexpr int kWBuf = 256;        // staged candidates per wave (k_filter)
 // staged candidates per wave in k_filter_heavy, which flushes once 64 or
 // fewer slots are free: fewer, longer flushes (each one's stores and its
 // output-slot atomic hold up the wave).  An ordered index (reads from
-// repeat families: billions of candidates) takes 1024, which beat 512
-// although it halves the blocks per CU (1536 did not); otherwise 512,
-// which keeps more waves for the long lists of a plain index.
+// repeat families: billions of candidates) takes 896, the largest stage
+// with which four blocks fit a CU's 160 KB of LDS (measured against 512,
+// 640, 768 and 1024, which leaves room for three); otherwise 512, which
+// keeps more waves for the long lists of a plain index.
 constexpr int kWBufHeavy = 512;
-constexpr int kWBufHeavyOrdered = 1024;
+constexpr int kWBufHeavyOrdered = 896;
 
 // 64 bits of packed reference starting at signed base position B (base B+t
 // in bits 63-2t .. 62-2t); packed[-1] and 3 words past the end are readable

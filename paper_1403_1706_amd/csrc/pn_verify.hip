@@ -278,6 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_verify_wide(PnRefDev ref, PnIndexD
 struct CountCand {
     uint2 c;
     int len, k;  // k < 0: nothing to do
+    int w0;      // the first read word counted (see count_start)
     int64_t lo;
     uint2 A, B, C, Dn;
     uint2 rw0;
@@ -300,13 +301,21 @@ __device__ __forceinline__ void count_start(const PnRefDev &ref, const PnIndexDe
     x.len = len;
     x.k = k;
     x.lo = (int64_t)c.y - (int64_t)PN_DBIAS - k;
+    // A candidate whose exact window lies in the read's first half
+    // (PN_CAND_TAIL) is counted from its last whole read word backwards:
+    // the words far from the window decide sooner, and a word that holds
+    // the window always shows its pieces.  The pieces past the last whole
+    // word are then never counted but taken as found (a keep, never a drop,
+    // rests on them), so the count stays lossless.
+    const int wf = (len / kPnPiece) / 8;  // whole read words (8 pieces each)
+    x.w0 = (c.x & PN_CAND_TAIL) && wf >= 2 ? wf - 1 : 0;
     const uint2 *hl = (const uint2 *)count_planes(ref, c);
-    const uint64_t blk = (uint64_t)(x.lo + PN_PAD_POS) >> 5;
+    const uint64_t blk = ((uint64_t)(x.lo + PN_PAD_POS) >> 5) + (uint64_t)x.w0;
     x.A = hl[2 * blk];
     x.B = hl[2 * (blk + 1)];
     x.C = hl[2 * (blk + 2)];
     x.Dn = hl[2 * (blk + 3)];
-    x.rw0 = ix.rplanes[(uint64_t)r * PN_READ_WORDS];
+    x.rw0 = ix.rplanes[(uint64_t)r * PN_READ_WORDS + x.w0];
 }
 
 // The count filter, one read word per lane and step: a lane whose candidate
@@ -352,6 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
     uint64_t blk = 0;
     uint32_t ph = 0;
     int W = 1, need = 0, found = 0, left = 0, w = 0;
+    bool rev = false;  // counting backwards (from word w0 down to 0)
     for (;;) {
         // 1. a lane without a candidate in progress takes the next one
         if (!has_cur && has_nxt) {
@@ -380,7 +390,8 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
                     need = m - nxt.k;
                     left = m;
                     found = 0;
-                    w = 0;
+                    w = nxt.w0;
+                    rev = nxt.w0 > 0;
                 }
             }
         }
@@ -408,25 +419,36 @@ __global__ __launch_bounds__(kThreads) void k_count(PnRefDev ref, PnIndexDev ix,
             // wave-uniform: scalar loop control)
             const uint32_t F = kglob >= 0 ? pn_count_word_hl(A, B, C, rw, ph, 2 * kglob + 1)
                                           : pn_count_word_hl(A, B, C, rw, ph, W);
-            found += __popc(F & pn_piece_firsts(left));
-            const int now = left < 8 ? left : 8;
+            // (a backward count takes whole words only)
+            found += __popc(F & pn_piece_firsts(rev ? 8 : left));
+            const int now = rev || left >= 8 ? 8 : left;
             letters += 32;
-            if (found >= need) {
+            if (found >= need || (rev && w == 0 && found + (left - now) >= need)) {
                 lng.push(((unsigned long long)c.y << 32) | c.x);
                 has_cur = false;
             } else if (found + (left - now) < need) {
                 has_cur = false;
             } else {
-                // the next word: its read plane word and one more text block
+                // the next word (the one after, or before when counting
+                // backwards): its read plane word and one more text block
                 const uint2 *hl = (const uint2 *)count_planes(ref, c);
                 const uint2 *rp = ix.rplanes + (uint64_t)(c.x & PN_CAND_READ) * PN_READ_WORDS;
-                rw = rp[w + 1];
-                A = B;
-                B = C;
-                C = Dn;
-                Dn = hl[2 * (blk + (uint64_t)w + 4)];
+                const int wn = rev ? w - 1 : w + 1;
+                rw = rp[wn];
+                const uint2 nb = hl[2 * (blk + (uint64_t)(rev ? wn : wn + 3))];
+                if (rev) {
+                    Dn = C;
+                    C = B;
+                    B = A;
+                    A = nb;
+                } else {
+                    A = B;
+                    B = C;
+                    C = Dn;
+                    Dn = nb;
+                }
                 left -= 8;
-                w++;
+                w = wn;
             }
         }
         if (*lng.cnt >= kStage / 2) lng.flush(lane);

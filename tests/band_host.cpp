@@ -102,6 +102,39 @@ extern "C" int count_host(const uint8_t *text, uint64_t L, const uint8_t *read, 
     return keep ? 1 : 0;
 }
 
+// The count filter's backward order on the host, from the per-word code
+// the kernel runs (pn_count_word_hl): the whole read words from the last
+// one down to the first, the pieces past the last whole word taken as
+// found; for a band inside the reference.  1: kept, 0: dropped, -1: bad
+// arguments, -3: outside the reference or fewer than two whole words (the
+// kernel counts those forwards).  *words: read words examined.
+extern "C" int count_host_backward(const uint8_t *text, uint64_t L, const uint8_t *read, int n,
+                                   int64_t d, int k, int *words) {
+    if (n < 1 || n > PN_MAX_READ_LEN || k < 0 || k > PN_BAND_K) return -1;
+    const int m = n / kPnPiece, wf = m / 8, need = m - k;
+    const int64_t lo = d - k;
+    if (wf < 2 || !(lo >= 0 && lo + n + 2 * k < (int64_t)L)) return -3;
+    *words = 0;
+    if (need <= 0) return 1;
+    const std::vector<uint4> pl = text_planes(text, L, false);
+    const std::vector<uint2> rp = read_planes(read, n, false);
+    const uint2 *hl = (const uint2 *)pl.data();
+    const uint64_t tp = (uint64_t)(lo + PN_PAD_POS);
+    const uint64_t blk = tp >> 5;
+    const uint32_t ph = (uint32_t)(tp & 31);
+    int found = 0, left = m;
+    for (int w = wf - 1; w >= 0; w--) {
+        const uint32_t F = pn_count_word_hl(hl[2 * (blk + w)], hl[2 * (blk + w + 1)],
+                                            hl[2 * (blk + w + 2)], rp[w], ph, 2 * k + 1);
+        found += __builtin_popcount(F & pn_piece_firsts(8));
+        left -= 8;
+        (*words)++;
+        if (found >= need) return 1;
+        if (found + left < need) return 0;
+    }
+    return 1;  // the pieces past the last whole word could make up the rest
+}
+
 // The alignment code (pn_align_one) on the host for one hit on `text` (the
 // strand's own letters) ending at e with v errors: the other strand's planes
 // are those of the text's reverse complement, the read's are those of its

@@ -177,6 +177,61 @@ def test_count_filter_is_lossless(count, seed):
     assert far > 50 and dropped_far > 0.9 * far
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_backward_count_is_lossless(band, seed):
+    """The count filter counts a candidate whose exact window lies in the
+    read's first half from its last whole read word backwards, taking the
+    pieces past that word as found.  Every candidate with a hit in its band
+    (by the oracle's band DP) must still be kept, and diverged copies must
+    still mostly go."""
+    lib = ctypes.CDLL(LIB)
+    lib.count_host_backward.restype = ctypes.c_int
+    lib.count_host_backward.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.c_void_p]
+    rng = np.random.default_rng(400 + seed)
+    kept_hits = far = dropped_far = 0
+    words = ctypes.c_int()
+    for trial in range(600):
+        L = int(rng.integers(400, 900))
+        text = rng.integers(0, 4, L).astype(np.uint8)
+        n = int(rng.integers(64, 257))
+        k = int(rng.integers(0, min(16, n // 4)))
+        p = int(rng.integers(k + 1, L - n - 2 * k - 2))
+        x = text[p:p + n].copy()
+        kind = rng.random()
+        if kind < 0.5:  # a few edits
+            for _ in range(int(rng.integers(0, k + 3))):
+                j = int(rng.integers(0, n))
+                e = rng.random()
+                if e < 0.8:
+                    x[j] = rng.integers(0, 4)
+                elif e < 0.9:
+                    x = np.concatenate([x[:j], rng.integers(0, 4, 1).astype(np.uint8), x[j:]])[:n]
+                else:
+                    x = np.concatenate([x[:j], x[j + 1:], rng.integers(0, 4, 1).astype(np.uint8)])
+        else:  # a diverged copy keeping a 16-letter window in the read's first half
+            keep0 = 4 * int(rng.integers(0, max(1, (n // 2 - 16) // 4)))
+            sub = rng.random(n) < 0.25
+            sub[keep0:keep0 + 16] = False
+            x[sub] = (x[sub] + rng.integers(1, 4, int(sub.sum()))) % 4
+        d = p + int(rng.integers(-1, 2))
+        x = np.ascontiguousarray(x, np.uint8)
+        r = lib.count_host_backward(np.ascontiguousarray(text).ctypes.data, L, x.ctypes.data, n, d,
+                                    k, ctypes.byref(words))
+        if r == -3:
+            continue
+        assert r in (0, 1)
+        if oracle.banded(text, x, d, k):
+            assert r == 1, (L, n, k, d)
+            kept_hits += 1
+        elif kind >= 0.5 and n // 4 - k >= 12:
+            far += 1
+            dropped_far += r == 0
+    assert kept_hits > 100
+    assert far > 50 and dropped_far > 0.9 * far
+
+
 @pytest.fixture(scope="module")
 def align(band):
     lib = ctypes.CDLL(LIB)
